@@ -1,0 +1,122 @@
+"""Positivity safeguard for the zone polynomials (a reading: the paper is
+silent on positivity).
+
+Component-wise WENO of the conserved variables (Sec. II.1, VII) can put
+negative density or pressure at the predictor and facial nodes next to strong
+blasts (the Sedov-type overpressure workload does so within two steps), which
+makes the fluxes and wave speeds meaningless.  The safeguard is the scaling
+limiter of Zhang & Shu (J. Comput. Phys. 229, 2010): every non-constant mode
+of a zone is multiplied by one factor theta in [0, 1], the largest for which
+density and pressure stay above eps times their zone-average values at every
+point of the zone's check set.  The zone average is untouched, so the scheme
+stays conservative, and theta = 1 (no change at all) wherever the polynomial
+is already positive there, so smooth solutions and every other pin are
+unaffected.
+
+Check set: all predictor nodes (eq. 31/37/46, or A.1), the facial nodes of all
+six sides (D.1/D.6/D.11) and the six face barycentres (eq. 54).  Applied
+twice: to the spatial modes before the predictor (at the spatial positions of
+the check set) and to all modes after it (at the space-time points).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+"""
+
+import numpy as np
+
+from .basis import N_SPATIAL, evaluate
+from .faces import FACE_NODES, zone_point
+from .predictor import NODES_MODAL, NODES_NODAL_2
+
+EPS_REL = 1.0e-8
+
+
+def check_points(order, form):
+    """Space-time points of the check set, in a fixed order."""
+    pts = list(NODES_NODAL_2 if form == 'nodal' else NODES_MODAL[order])
+    for d in range(3):
+        for s in (-1, 1):
+            for (t1, t2, tau) in FACE_NODES[order]:
+                pts.append(zone_point(d, s, t1, t2, tau))
+            pts.append(zone_point(d, s, 0.0, 0.0, 0.5))
+    return [tuple(float(c) for c in p) for p in pts]
+
+
+def _pressure_like(u, gamma):
+    """(gamma-1)(E - m^2 / 2 rho) of an Euler state."""
+    m2 = u[1] ** 2 + u[2] ** 2 + u[3] ** 2
+    return (gamma - 1.0) * (u[4] - 0.5 * m2 / u[0])
+
+
+def _pressure_root(ubar, du, eps_p, gamma):
+    """Smallest t in (0, 1] with pressure(ubar + t du) = eps_p.
+
+    rho(t) (E(t) - e) - |m(t)|^2 / 2 is the quadratic a t^2 + b t + c with
+    e = eps_p / (gamma - 1); c > 0 at t = 0 and the value at t = 1 is < 0.
+    """
+    e = eps_p / (gamma - 1.0)
+    r0, m0, E0 = ubar[0], ubar[1:4], ubar[4]
+    dr, dm, dE = du[0], du[1:4], du[4]
+    a = dr * dE - 0.5 * (dm * dm).sum(axis=0)
+    b = r0 * dE + dr * (E0 - e) - (m0 * dm).sum(axis=0)
+    c = r0 * (E0 - e) - 0.5 * (m0 * m0).sum(axis=0)
+    with np.errstate(all='ignore'):
+        disc = np.sqrt(np.maximum(b * b - 4.0 * a * c, 0.0))
+        qq = -0.5 * (b + np.where(b >= 0.0, disc, -disc))
+        t1 = qq / a
+        t2 = c / qq
+        lin = -c / b
+    big = 2.0
+    t1 = np.where(np.isfinite(t1) & (t1 >= 0.0), t1, big)
+    t2 = np.where(np.isfinite(t2) & (t2 >= 0.0), t2, big)
+    t = np.minimum(t1, t2)
+    t = np.where(a == 0.0, lin, t)
+    return np.clip(t, 0.0, 1.0)
+
+
+def scale_factor(ubar, values, gamma):
+    """theta in [0, 1] of one zone polynomial given its point values."""
+    rho_eps = EPS_REL * ubar[0]
+    p_bar = _pressure_like(ubar, gamma)
+    p_eps = EPS_REL * p_bar
+    theta = np.ones_like(ubar[0])
+    for u in values:
+        with np.errstate(divide='ignore', invalid='ignore'):
+            t = np.where(u[0] < rho_eps, (ubar[0] - rho_eps) / (ubar[0] - u[0]), 1.0)
+        theta = np.minimum(theta, t)
+    theta_rho = theta
+    for u in values:
+        v = ubar + theta_rho * (u - ubar)
+        p = _pressure_like(v, gamma)
+        t = np.where(p < p_eps,
+                     theta_rho * _pressure_root(ubar, v - ubar, p_eps, gamma), theta_rho)
+        theta = np.minimum(theta, t)
+    return theta
+
+
+def limit_spatial(what, order, form, gamma):
+    """Scale w_2..w_{L_S} so the spatial polynomial is positive at the
+    spatial positions of the check set."""
+    # evaluate the spatial part only (tau = 0)
+    pts = sorted(set((p[0], p[1], p[2], 0.0) for p in check_points(order, form)))
+    vals = [evaluate(_as_spacetime(what, order), order, p) for p in pts]
+    theta = scale_factor(what[0], vals, gamma)
+    out = what.copy()
+    out[1:] = out[1:] * theta
+    return out
+
+
+def _as_spacetime(what, order):
+    from .basis import N_SPACETIME
+    uh = np.zeros((N_SPACETIME[order],) + what.shape[1:])
+    uh[:N_SPATIAL[order]] = what
+    return uh
+
+
+def limit_spacetime(uhat, order, form, gamma):
+    """Scale every mode but the zone average so the space-time polynomial is
+    positive at every point of the check set."""
+    vals = [evaluate(uhat, order, p) for p in check_points(order, form)]
+    theta = scale_factor(uhat[0], vals, gamma)
+    out = uhat.copy()
+    out[1:] = out[1:] * theta
+    return out

@@ -1,0 +1,293 @@
+"""ADER-CG space-time predictor (Sec. IV modal, Appendix A nodal).
+
+Starting from the spatial modes w_1..w_{L_S} of a zone, the evolutionary modes
+u_{L_S+1}..u_L of eq. (14)-(16) are found by M-1 Picard iterations (Sec. IV.2):
+each iteration evaluates the current space-time polynomial at the predictor
+nodes, evaluates the scaled fluxes f = dt F/dx, g = dt G/dy, h = dt H/dz at
+those nodes (eq. 5), forms the flux modes the evolution equations need with the
+paper's nodal-to-modal rules, and applies the evolution equations.  The initial
+guess has all evolutionary modes zero (eq. 10-12 taken as eq. 14-16 at tau=0).
+
+The oracle evaluates the polynomial at every node by direct summation over the
+basis (the plain definition of eq. 32, 38-39, 47-48), recomputes every node on
+every iteration (the paper reuses the tau=0 ones, which are identical), and
+drops the source terms (S = 0 for every system handled here).
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+"""
+
+import numpy as np
+
+from .basis import N_SPATIAL, N_SPACETIME, evaluate
+from .physics import flux
+
+H = 0.5
+T3 = 1.0 / 3.0
+T23 = 2.0 / 3.0
+
+# Eq. (31): the seven second-order nodes (xi, eta, zeta, tau).
+NODES_MODAL_2 = [(H, 0, 0, 0), (-H, 0, 0, 0), (0, H, 0, 0), (0, -H, 0, 0),
+                 (0, 0, H, 0), (0, 0, -H, 0), (0, 0, 0, 1)]
+
+# Eq. (37): the twenty third-order nodes.
+NODES_MODAL_3 = [(0, 0, 0, 0),
+                 (H, H, 0, 0), (H, -H, 0, 0), (H, 0, H, 0), (H, 0, -H, 0),
+                 (-H, H, 0, 0), (-H, -H, 0, 0), (-H, 0, H, 0), (-H, 0, -H, 0),
+                 (0, H, H, 0), (0, -H, H, 0), (0, H, -H, 0), (0, -H, -H, 0),
+                 (H, 0, 0, H), (-H, 0, 0, H), (0, H, 0, H), (0, -H, 0, H),
+                 (0, 0, H, H), (0, 0, -H, H), (0, 0, 0, 1)]
+
+# Eq. (46): the forty-two fourth-order nodes.
+Q4 = 0.25
+NODES_MODAL_4 = [(0, 0, 0, 0), (H, 0, 0, 0), (Q4, 0, 0, 0), (-Q4, 0, 0, 0), (-H, 0, 0, 0),
+                 (0, H, 0, 0), (0, Q4, 0, 0), (0, -Q4, 0, 0), (0, -H, 0, 0),
+                 (0, 0, H, 0), (0, 0, Q4, 0), (0, 0, -Q4, 0), (0, 0, -H, 0),
+                 (H, H, H, 0), (H, -H, H, 0), (H, H, -H, 0), (H, -H, -H, 0),
+                 (-H, H, H, 0), (-H, -H, H, 0), (-H, H, -H, 0), (-H, -H, -H, 0),
+                 (0, 0, 0, T3), (H, H, 0, T3), (H, -H, 0, T3), (H, 0, H, T3), (H, 0, -H, T3),
+                 (-H, H, 0, T3), (-H, -H, 0, T3), (-H, 0, H, T3), (-H, 0, -H, T3),
+                 (0, H, H, T3), (0, -H, H, T3), (0, H, -H, T3), (0, -H, -H, T3),
+                 (0, 0, 0, T23), (H, 0, 0, T23), (-H, 0, 0, T23), (0, H, 0, T23),
+                 (0, -H, 0, T23), (0, 0, H, T23), (0, 0, -H, T23), (0, 0, 0, 1)]
+
+# Eq. (A.1): the five nodes of the second-order nodal formulation.
+NODES_NODAL_2 = [(0, 0, 0, 0), (H, 0, 0, 0), (0, H, 0, 0), (0, 0, H, 0), (0, 0, 0, 1)]
+
+NODES_MODAL = {2: NODES_MODAL_2, 3: NODES_MODAL_3, 4: NODES_MODAL_4}
+
+
+def _one_based(values):
+    """Index nodal values 1..N as the paper does."""
+    return [None] + list(values)
+
+
+# ---------------------------------------------------------------------------
+# Nodal-to-modal flux rules (the modes each evolution equation needs)
+# ---------------------------------------------------------------------------
+
+def flux_modes_2(f, g, h):
+    """Eq. (33)."""
+    return {'f2': f[1] - f[2], 'g3': g[3] - g[4], 'h4': h[5] - h[6]}
+
+
+def flux_modes_3(f, g, h):
+    """Eq. (40) (x-flux), (41) (y-flux), (42) (z-flux)."""
+    r = {}
+    q1 = f[2] + f[3] + f[4] + f[5]
+    q2 = f[6] + f[7] + f[8] + f[9]
+    q3 = f[10] + f[11] + f[12] + f[13]
+    r['f2'] = 0.25 * (q1 - q2)
+    r['f5'] = 0.5 * (q1 + q2 - q3) - 2.0 * f[1]
+    r['f8'] = f[2] - f[3] - f[6] + f[7]
+    r['f10'] = f[4] - f[5] - f[8] + f[9]
+    r['f13'] = 2.0 * (f[14] - f[15] - r['f2'])
+
+    q4 = g[2] + g[6] + g[10] + g[12]
+    q5 = g[3] + g[7] + g[11] + g[13]
+    q6 = g[4] + g[5] + g[8] + g[9]
+    r['g3'] = 0.25 * (q4 - q5)
+    r['g6'] = 0.5 * (q4 + q5 - q6) - 2.0 * g[1]
+    r['g8'] = g[2] - g[3] - g[6] + g[7]
+    r['g9'] = g[10] - g[11] - g[12] + g[13]
+    r['g14'] = 2.0 * (g[16] - g[17] - r['g3'])
+
+    q7 = h[4] + h[8] + h[10] + h[11]
+    q8 = h[5] + h[9] + h[12] + h[13]
+    q9 = h[2] + h[3] + h[6] + h[7]
+    r['h4'] = 0.25 * (q7 - q8)
+    r['h7'] = 0.5 * (q7 + q8 - q9) - 2.0 * h[1]
+    r['h9'] = h[10] - h[11] - h[12] + h[13]
+    r['h10'] = h[4] - h[5] - h[8] + h[9]
+    r['h15'] = 2.0 * (h[18] - h[19] - r['h4'])
+    return r
+
+
+def _corner_sums(f):
+    """The temporaries q1..q9 shared by eq. (49), (50) and (51)."""
+    q = {}
+    q[1] = f[14] + f[15] + f[16] + f[17]
+    q[2] = f[18] + f[19] + f[20] + f[21]
+    q[3] = f[14] + f[16] + f[18] + f[20]
+    q[4] = f[15] + f[17] + f[19] + f[21]
+    q[5] = f[14] + f[15] + f[18] + f[19]
+    q[6] = f[16] + f[17] + f[20] + f[21]
+    q[7] = f[23] + f[24] - f[25] - f[26] - f[27] - f[28] + f[29] + f[30]
+    q[8] = f[23] + f[27] - f[24] - f[28] - f[31] - f[33] + f[32] + f[34]
+    q[9] = f[25] + f[29] - f[26] - f[30] - f[31] - f[32] + f[33] + f[34]
+    return q
+
+
+def _mixed_modes(f, q):
+    """Modes 14..20 in eq. (49)-(51): the same formulas for f, g and h."""
+    r = {}
+    r[20] = f[14] - f[15] - f[16] + f[17] - f[18] + f[19] + f[20] - f[21]
+    r[14] = q[8] + 0.5 * (q[3] - q[4]) - 2.0 * (f[6] - f[9])
+    r[15] = q[9] + 0.5 * (q[5] - q[6]) - 2.0 * (f[10] - f[13])
+    r[16] = q[7] + 0.5 * (q[1] - q[2]) - 2.0 * (f[2] - f[5])
+    r[17] = -2.0 * q[9] + r[15]
+    r[18] = -2.0 * q[7] + r[16]
+    r[19] = -2.0 * q[8] + r[14]
+    return r
+
+
+def flux_modes_4(f, g, h):
+    """Eq. (49) (x-flux), (50) (y-flux), (51) (z-flux)."""
+    r = {}
+    # ---- x-flux, eq. (49)
+    q = _corner_sums(f)
+    q10 = f[23] + f[24] + f[25] + f[26] - f[27] - f[28] - f[29] - f[30]
+    r['f5'] = 2.0 * (f[2] - 2.0 * f[1] + f[5])
+    r['f8'] = 0.5 * (f[14] - f[15] + f[16] - f[17] - f[18] + f[19] - f[20] + f[21])
+    r['f10'] = 0.5 * (f[14] + f[15] - f[16] - f[17] - f[18] - f[19] + f[20] + f[21])
+    r['f11'] = 16.0 * (f[2] - 2.0 * f[3] + 2.0 * f[4] - f[5]) / 3.0
+    r['f2'] = 2.0 * (f[2] - f[5]) / 3.0 - 0.1 * r['f11'] + (q[1] - q[2]) / 12.0
+    mx = _mixed_modes(f, q)
+    for k in (14, 15, 16, 18, 20):
+        r['f%d' % k] = mx[k]
+    r['f27'] = 1.125 * (q[1] - q[2]) + 4.5 * (f[36] - f[37]) - 2.25 * q10
+    r['f24'] = (3.0 * (f[36] - f[37]) - 0.75 * q10 + 0.375 * (mx[16] + mx[18])
+                - r['f27'])
+    r['f30'] = 3.0 * (f[36] - 2.0 * f[35] + f[37]) - 1.5 * r['f5']
+    r['f33'] = 3.0 * (f[23] - f[27] - f[24] + f[28]) - 3.0 * r['f8']
+    r['f35'] = 3.0 * (f[25] - f[29] - f[26] + f[30]) - 3.0 * r['f10']
+
+    # ---- y-flux, eq. (50)
+    q = _corner_sums(g)
+    q11 = g[23] - g[24] + g[27] - g[28] + g[31] - g[32] + g[33] - g[34]
+    r['g6'] = 2.0 * (g[6] - 2.0 * g[1] + g[9])
+    r['g8'] = 0.5 * (g[14] - g[15] + g[16] - g[17] - g[18] + g[19] - g[20] + g[21])
+    r['g9'] = 0.5 * (g[14] - g[15] - g[16] + g[17] + g[18] - g[19] - g[20] + g[21])
+    r['g12'] = 16.0 * (g[6] - 2.0 * g[7] + 2.0 * g[8] - g[9]) / 3.0
+    r['g3'] = 2.0 * (g[6] - g[9]) / 3.0 - 0.1 * r['g12'] + (q[3] - q[4]) / 12.0
+    my = _mixed_modes(g, q)
+    for k in (14, 16, 17, 19, 20):
+        r['g%d' % k] = my[k]
+    r['g28'] = 1.125 * (q[3] - q[4]) + 4.5 * (g[38] - g[39]) - 2.25 * q11
+    r['g25'] = (3.0 * (g[38] - g[39]) - 0.75 * q11 + 0.375 * (my[14] + my[19])
+                - r['g28'])
+    r['g31'] = 3.0 * (g[38] - 2.0 * g[35] + g[39]) - 1.5 * r['g6']
+    r['g33'] = 3.0 * (g[23] - g[27] - g[24] + g[28]) - 3.0 * r['g8']
+    r['g34'] = 3.0 * (g[31] - g[32] - g[33] + g[34]) - 3.0 * r['g9']
+
+    # ---- z-flux, eq. (51)
+    q = _corner_sums(h)
+    q12 = h[25] - h[26] + h[29] - h[30] + h[31] + h[32] - h[33] - h[34]
+    r['h7'] = 2.0 * (h[10] - 2.0 * h[1] + h[13])
+    r['h9'] = 0.5 * (h[14] - h[15] - h[16] + h[17] + h[18] - h[19] - h[20] + h[21])
+    r['h10'] = 0.5 * (h[14] + h[15] - h[16] - h[17] - h[18] - h[19] + h[20] + h[21])
+    r['h13'] = 16.0 * (h[10] - 2.0 * h[11] + 2.0 * h[12] - h[13]) / 3.0
+    r['h4'] = 2.0 * (h[10] - h[13]) / 3.0 - 0.1 * r['h13'] + (q[5] - q[6]) / 12.0
+    mz = _mixed_modes(h, q)
+    for k in (15, 17, 18, 19, 20):
+        r['h%d' % k] = mz[k]
+    r['h29'] = 1.125 * (q[5] - q[6]) + 4.5 * (h[40] - h[41]) - 2.25 * q12
+    r['h26'] = (3.0 * (h[40] - h[41]) - 0.75 * q12 + 0.375 * (mz[15] + mz[17])
+                - r['h29'])
+    r['h32'] = 3.0 * (h[40] - 2.0 * h[35] + h[41]) - 1.5 * r['h7']
+    r['h34'] = 3.0 * (h[31] - h[32] - h[33] + h[34]) - 3.0 * r['h9']
+    r['h35'] = 3.0 * (h[25] - h[26] - h[29] + h[30]) - 3.0 * r['h10']
+    return r
+
+
+# ---------------------------------------------------------------------------
+# Evolution equations (source terms dropped: S = 0)
+# ---------------------------------------------------------------------------
+
+def evolve_2(r):
+    """Eq. (30): returns [u_5]."""
+    return [-r['f2'] - r['g3'] - r['h4']]
+
+
+def evolve_3(r):
+    """Eq. (36): returns [u_11 .. u_15]."""
+    return [
+        -r['f2'] - r['g3'] - r['h4'],
+        -0.5 * r['f13'] - 0.5 * r['g14'] - 0.5 * r['h15'],
+        -2.0 * r['f5'] - r['g8'] - r['h10'],
+        -r['f8'] - 2.0 * r['g6'] - r['h9'],
+        -r['f10'] - r['g9'] - 2.0 * r['h7'],
+    ]
+
+
+def evolve_4(r):
+    """Eq. (45): returns [u_21 .. u_35]."""
+    return [
+        -r['f11'] / 10.0 - r['f2'] - r['g12'] / 10.0 - r['g3'] - r['h13'] / 10.0 - r['h4'],
+        -r['f24'] / 2.0 - r['g25'] / 2.0 - r['h26'] / 2.0,
+        -r['f27'] / 3.0 - r['g28'] / 3.0 - r['h29'] / 3.0,
+        -2.0 * r['f5'] - r['g8'] - r['h10'],
+        -r['f8'] - 2.0 * r['g6'] - r['h9'],
+        -r['f10'] - r['g9'] - 2.0 * r['h7'],
+        -r['f30'] - r['g33'] / 2.0 - r['h35'] / 2.0,
+        -r['f33'] / 2.0 - r['g31'] - r['h34'] / 2.0,
+        -r['f35'] / 2.0 - r['g34'] / 2.0 - r['h32'],
+        -3.0 * r['f11'] - r['g14'] - r['h15'],
+        -r['f16'] - 3.0 * r['g12'] - r['h17'],
+        -r['f18'] - r['g19'] - 3.0 * r['h13'],
+        -2.0 * r['f14'] - 2.0 * r['g16'] - r['h20'],
+        -r['f20'] - 2.0 * r['g17'] - 2.0 * r['h19'],
+        -2.0 * r['f15'] - r['g20'] - 2.0 * r['h18'],
+    ]
+
+
+FLUX_MODES = {2: flux_modes_2, 3: flux_modes_3, 4: flux_modes_4}
+EVOLVE = {2: evolve_2, 3: evolve_3, 4: evolve_4}
+
+
+def _scaled_fluxes(ubar, dt, dx, gamma):
+    fbar = _one_based([dt / dx[0] * flux(u, 0, gamma) for u in ubar[1:]])
+    gbar = _one_based([dt / dx[1] * flux(u, 1, gamma) for u in ubar[1:]])
+    hbar = _one_based([dt / dx[2] * flux(u, 2, gamma) for u in ubar[1:]])
+    return fbar, gbar, hbar
+
+
+def predict_modal(what, order, dt, dx, gamma, flux_fn=None):
+    """Modal ADER-CG of Sec. IV.1-IV.3: spatial modes -> all L modes.
+
+    ``what``: (L_S, nv, ...).  ``dx`` = (dx, dy, dz).  ``flux_fn(u, axis)``
+    overrides the physical flux (used by the pins with linear fluxes).
+    Returns uhat of shape (L, nv, ...).
+    """
+    ls, L = N_SPATIAL[order], N_SPACETIME[order]
+    uhat = np.zeros((L,) + what.shape[1:])
+    uhat[:ls] = what
+    nodes = NODES_MODAL[order]
+    for _ in range(order - 1):
+        ubar = _one_based([evaluate(uhat, order, x) for x in nodes])
+        if flux_fn is None:
+            fbar, gbar, hbar = _scaled_fluxes(ubar, dt, dx, gamma)
+        else:
+            fbar = _one_based([dt / dx[0] * flux_fn(u, 0) for u in ubar[1:]])
+            gbar = _one_based([dt / dx[1] * flux_fn(u, 1) for u in ubar[1:]])
+            hbar = _one_based([dt / dx[2] * flux_fn(u, 2) for u in ubar[1:]])
+        modes = FLUX_MODES[order](fbar, gbar, hbar)
+        uhat[ls:] = np.stack(EVOLVE[order](modes))
+    return uhat
+
+
+def predict_nodal_2(what, dt, dx, gamma, flux_fn=None):
+    """Nodal ADER-CG at second order, Appendix A.
+
+    Nodal values at the first four nodes of (A.1) by (A.5); one iteration of
+    the evolution equation (A.4) gives the fifth nodal value; (A.6) returns
+    the fifth mode.  (A.4) as printed subtracts h_3; the Galerkin derivation
+    with the nodal basis (A.2) gives h_4 (the z-node), which is used here.
+    """
+    ubar = _one_based([
+        what[0],
+        what[0] + 0.5 * what[1],
+        what[0] + 0.5 * what[2],
+        what[0] + 0.5 * what[3],
+    ])
+    if flux_fn is None:
+        fn = lambda u, a: flux(u, a, gamma)  # noqa: E731
+    else:
+        fn = flux_fn
+    f1, f2 = dt / dx[0] * fn(ubar[1], 0), dt / dx[0] * fn(ubar[2], 0)
+    g1, g3 = dt / dx[1] * fn(ubar[1], 1), dt / dx[1] * fn(ubar[3], 1)
+    h1, h4 = dt / dx[2] * fn(ubar[1], 2), dt / dx[2] * fn(ubar[4], 2)
+    u5 = ubar[1] - 2.0 * (f2 - f1) - 2.0 * (g3 - g1) - 2.0 * (h4 - h1)
+    uhat = np.zeros((5,) + what.shape[1:])
+    uhat[:4] = what
+    uhat[4] = u5 - ubar[1]
+    return uhat

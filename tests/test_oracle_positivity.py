@@ -1,0 +1,56 @@
+"""Pins of the positivity safeguard (a reading; see oracle/positivity.py)."""
+
+import numpy as np
+import pytest
+
+from oracle import basis, positivity
+from oracle.physics import primitives
+
+
+def _zone_poly(order, rng, amp):
+    ls = basis.N_SPATIAL[order]
+    w = np.zeros((ls, 5, 1))
+    w[0, :, 0] = [1.0, 0.3, -0.2, 0.1, 2.0]
+    w[1:, :, 0] = amp * rng.normal(size=(ls - 1, 5))
+    return w
+
+
+def _check_values(w, order, form):
+    uh = np.zeros((basis.N_SPACETIME[order],) + w.shape[1:])
+    uh[:w.shape[0]] = w
+    return [basis.evaluate(uh, order, p) for p in positivity.check_points(order, form)]
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_limiter_inactive_on_positive_polynomials(order):
+    rng = np.random.default_rng(order)
+    w = _zone_poly(order, rng, 0.01)
+    out = positivity.limit_spatial(w, order, 'modal', 1.4)
+    assert np.array_equal(out, w)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_limiter_restores_positivity_tightly(order):
+    rng = np.random.default_rng(10 + order)
+    hits = 0
+    for _ in range(20):
+        w = _zone_poly(order, rng, 1.5)
+        out = positivity.limit_spatial(w, order, 'modal', 1.4)
+        assert np.array_equal(out[0], w[0])                 # zone average kept
+        ratio = out[1:] / np.where(w[1:] == 0, 1, w[1:])
+        theta = ratio.ravel()[np.argmax(np.abs(w[1:]).ravel())]
+        assert np.allclose(out[1:], theta * w[1:], rtol=1e-13, atol=0)
+        vals = [v for v in _check_values(out, order, 'modal')]
+        rho = np.array([v[0, 0] for v in vals])
+        p = np.array([primitives(v, 1.4)[2][0] for v in vals])
+        p_bar = primitives(w[0], 1.4)[2][0]
+        eps_r = positivity.EPS_REL * w[0, 0, 0]
+        eps_p = positivity.EPS_REL * p_bar
+        assert rho.min() >= eps_r * (1 - 1e-6)
+        assert p.min() >= eps_p * (1 - 1e-4) - 1e-14
+        if theta < 1.0:
+            hits += 1
+            # the largest admissible theta: one check point sits on a bound
+            tight = min(rho.min() / eps_r, p.min() / eps_p)
+            assert abs(tight - 1.0) < 1e-3
+    assert hits > 5

@@ -1,0 +1,181 @@
+"""Pins of the oracle's basis, nodal-to-modal flux rules, evolution equations
+and predictor (Sec. II.1-II.2, Sec. IV, App. A) against facts the paper and
+the mathematics fix."""
+
+import numpy as np
+import pytest
+import sympy as sp
+
+from oracle import basis
+from oracle import predictor as pr
+from tests import indep
+
+
+@pytest.mark.parametrize("a", [0, 1, 2, 3])
+def test_basis_is_monic_legendre(a):
+    # eq. (9): P_a is the Legendre polynomial rescaled to [-1/2, 1/2], monic
+    x = np.linspace(-0.5, 0.5, 17)
+    assert np.allclose(basis.P(a, x), indep.P(a, x), rtol=0, atol=1e-15)
+
+
+def test_basis_orthogonal_zero_mean():
+    x, w = indep.gauss(8, -0.5, 0.5)
+    G = np.array([[np.dot(w, basis.P(a, x) * basis.P(b, x)) for b in range(4)] for a in range(4)])
+    assert np.allclose(G - np.diag(np.diag(G)), 0.0, atol=1e-16)
+    assert np.allclose(np.diag(G), [1.0, 1.0 / 12, 1.0 / 180, 1.0 / 2800], rtol=1e-14)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_mode_order_matches_paper(order):
+    # eq. (10)-(16)
+    assert basis.spacetime_modes(order) == indep.st_modes(order)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_node_sets_are_mirror_symmetric(order):
+    nodes = {tuple(float(c) for c in n) for n in pr.NODES_MODAL[order]}
+    assert len(nodes) == {2: 7, 3: 20, 4: 42}[order]
+    for axis in range(3):
+        for n in nodes:
+            m = list(n)
+            m[axis] = -m[axis]
+            assert tuple(m) in nodes
+
+
+def _rule_exactness(order, seed):
+    """Apply the oracle's rule to nodal values of random polynomials in the
+    space-time span; every mode it returns must come out exactly."""
+    rng = np.random.default_rng(seed)
+    L = basis.N_SPACETIME[order]
+    cf, cg, ch = rng.normal(size=(3, L))
+    nodes = pr.NODES_MODAL[order]
+    fv = [None] + [indep.st_value(cf, order, n) for n in nodes]
+    gv = [None] + [indep.st_value(cg, order, n) for n in nodes]
+    hv = [None] + [indep.st_value(ch, order, n) for n in nodes]
+    modes = pr.FLUX_MODES[order](fv, gv, hv)
+    ref = {'f': cf, 'g': cg, 'h': ch}
+    for key, val in modes.items():
+        k = int(key[1:])
+        assert abs(val - ref[key[0]][k - 1]) < 1e-12, (order, key, val, ref[key[0]][k - 1])
+    return modes
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_flux_rules_exact_on_span(order):
+    # eq. (33), (40)-(42), (49)-(51)
+    for seed in range(3):
+        _rule_exactness(order, seed)
+
+
+def _galerkin_matrices(order):
+    """Exact Galerkin operators of the space-time predictor.
+
+    For every evolutionary test function phi_k:
+      int phi_k (d_tau u + d_xi f + d_eta g + d_zeta h) = 0
+    over [-1/2,1/2]^3 x [0,1], with u, f, g, h in the full space-time span.
+    Returns (E, Kf, Kg, Kh) with u_evol = E_f f + E_g g + E_h h (rationals).
+    """
+    x, t = sp.symbols('x t')
+    Pp = [sp.Integer(1), x, x ** 2 - sp.Rational(1, 12), x ** 3 - sp.Rational(3, 20) * x]
+
+    def i_pp(a, b):
+        return sp.integrate(Pp[a] * Pp[b], (x, -sp.Rational(1, 2), sp.Rational(1, 2)))
+
+    def i_pdp(a, b):
+        return sp.integrate(Pp[a] * sp.diff(Pp[b], x), (x, -sp.Rational(1, 2), sp.Rational(1, 2)))
+
+    def i_tt(d, e):
+        return sp.integrate(t ** d * t ** e, (t, 0, 1))
+
+    def i_tdt(d, e):
+        return sp.integrate(t ** d * sp.diff(t ** e, t), (t, 0, 1))
+
+    modes = indep.st_modes(order)
+    ls = basis.N_SPATIAL[order]
+    evol = list(range(ls, len(modes)))
+    L = len(modes)
+    Mt = sp.zeros(len(evol), len(evol))
+    K = [sp.zeros(len(evol), L) for _ in range(3)]
+    for r, k in enumerate(evol):
+        ak = modes[k]
+        for c, m in enumerate(evol):
+            am = modes[m]
+            Mt[r, c] = (i_pp(ak[0], am[0]) * i_pp(ak[1], am[1]) * i_pp(ak[2], am[2])
+                        * i_tdt(ak[3], am[3]))
+        for m in range(L):
+            am = modes[m]
+            for axis in range(3):
+                f = [i_pp(ak[i], am[i]) for i in range(3)]
+                f[axis] = i_pdp(ak[axis], am[axis])
+                K[axis][r, m] = f[0] * f[1] * f[2] * i_tt(ak[3], am[3])
+    Minv = Mt.inv()
+    return [-(Minv * Kd) for Kd in K]
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_evolution_equations_match_galerkin(order):
+    # eq. (30), (36), (45) against the Galerkin weak form derived here
+    E = [np.array(e.tolist(), dtype=np.float64) for e in _galerkin_matrices(order)]
+    rng = np.random.default_rng(7)
+    L = basis.N_SPACETIME[order]
+    for _ in range(3):
+        fv, gv, hv = rng.normal(size=(3, L))
+        ref = E[0] @ fv + E[1] @ gv + E[2] @ hv
+        r = {}
+        for name, vec in (('f', fv), ('g', gv), ('h', hv)):
+            for k in range(1, L + 1):
+                r['%s%d' % (name, k)] = vec[k - 1]
+        got = np.array(pr.EVOLVE[order](r))
+        assert np.allclose(got, ref, rtol=0, atol=1e-13), (got, ref)
+
+
+def test_nodal_A4_reading():
+    # (A.4) derived from the nodal basis (A.2): the z-difference uses node 4
+    x, y, z, t = sp.symbols('x y z t')
+    Pn = [1 - 2 * x - 2 * y - 2 * z - t, 2 * x, 2 * y, 2 * z, t]
+    nodes = [(0, 0, 0, 0), (sp.Rational(1, 2), 0, 0, 0), (0, sp.Rational(1, 2), 0, 0),
+             (0, 0, sp.Rational(1, 2), 0), (0, 0, 0, 1)]
+    for i, p in enumerate(Pn):
+        for j, n in enumerate(nodes):
+            assert p.subs({x: n[0], y: n[1], z: n[2], t: n[3]}) == (1 if i == j else 0)
+    ub = sp.symbols('u1:6')
+    hb = sp.symbols('h1:6')
+    u = sum(ub[i] * Pn[i] for i in range(5))
+    hz = sum(hb[i] * Pn[i] for i in range(5))
+    box = [(x, -sp.Rational(1, 2), sp.Rational(1, 2)), (y, -sp.Rational(1, 2), sp.Rational(1, 2)),
+           (z, -sp.Rational(1, 2), sp.Rational(1, 2)), (t, 0, 1)]
+    eq = sp.integrate(Pn[4] * (sp.diff(u, t) + sp.diff(hz, z)), *box)
+    sol = sp.solve(eq, ub[4])[0]
+    assert sp.simplify(sol - (ub[0] - 2 * (hb[3] - hb[0]))) == 0
+
+
+def _linear_flux(adv):
+    return lambda u, axis: adv[axis] * u
+
+
+def _spatial_value(what, order, point):
+    ls = basis.N_SPATIAL[order]
+    c = np.zeros(basis.N_SPACETIME[order])
+    c[:ls] = what
+    return indep.st_value(c, order, (point[0], point[1], point[2], 0.0))
+
+
+@pytest.mark.parametrize("order,form", [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')])
+def test_predictor_exact_for_linear_advection(order, form):
+    # constant-coefficient linear flux on data of degree <= M-1: the
+    # space-time polynomial must be w(x - c tau) after M-1 iterations
+    rng = np.random.default_rng(11 + order)
+    ls = basis.N_SPATIAL[order]
+    what = rng.normal(size=(ls, 1))
+    adv = np.array([0.7, -1.3, 0.4])
+    dt, dx = 0.05, (0.1, 0.2, 0.125)
+    c = adv * dt / np.array(dx)
+    if form == 'nodal':
+        uhat = pr.predict_nodal_2(what, dt, dx, 1.4, flux_fn=_linear_flux(adv))
+    else:
+        uhat = pr.predict_modal(what, order, dt, dx, 1.4, flux_fn=_linear_flux(adv))
+    for p in rng.uniform(-0.5, 0.5, size=(10, 4)):
+        tau = p[3] + 0.5
+        got = indep.st_value(uhat[:, 0], order, (p[0], p[1], p[2], tau))
+        ref = _spatial_value(what[:, 0], order, p[:3] - c * tau)
+        assert abs(got - ref) < 1e-13

@@ -1,0 +1,175 @@
+"""Whole-step pins of the oracle (Sec. II, VI, VIII.3): constant states,
+conservation, exact translation, design order and mirror symmetry."""
+
+import os
+
+import numpy as np
+import pytest
+
+from oracle import OracleConfig, compute_dt, step, step_block
+from oracle.physics import conserved, primitives
+
+GOLDEN = os.path.join(os.path.dirname(__file__), 'golden')
+
+CONFIGS = [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')]
+
+
+@pytest.mark.parametrize("order,form", CONFIGS)
+@pytest.mark.parametrize("solver", ["hll", "linearized"])
+def test_constant_state_is_preserved_bitwise(order, form, solver):
+    cfg = OracleConfig(order=order, form=form, riemann=solver)
+    U = np.zeros((5, 5, 6, 7))
+    U[:] = np.array([1.3, 0.2, -0.1, 0.3, 2.5])[:, None, None, None]
+    assert np.array_equal(step(U, 0.01, cfg), U)
+
+
+def _random_smooth_state(n, seed, gamma=1.4):
+    rng = np.random.default_rng(seed)
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing='ij')
+    def field(amp):
+        out = 0.0
+        for _ in range(3):
+            k = rng.integers(-2, 3, size=3)
+            out = out + amp * np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + rng.uniform(0, 6.3))
+        return out
+    rho = 1.0 + field(0.1)
+    v = np.stack([field(0.2) for _ in range(3)])
+    P = 1.0 + field(0.1)
+    return conserved(rho, v, P, None, gamma)
+
+
+@pytest.mark.parametrize("order,form", CONFIGS)
+@pytest.mark.parametrize("solver", ["hll", "linearized"])
+def test_conservation_to_roundoff(order, form, solver):
+    cfg = OracleConfig(order=order, form=form, riemann=solver)
+    U = _random_smooth_state(8, 1)
+    dt = compute_dt(U, cfg, 0.3)
+    Un = step(U, dt, cfg)
+    tot0, tot1 = U.sum(axis=(1, 2, 3)), Un.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(U).sum(axis=(1, 2, 3)))
+    assert not np.allclose(Un, U)
+
+
+@pytest.mark.parametrize("order,form", CONFIGS)
+@pytest.mark.parametrize("solver", ["hll", "linearized"])
+def test_exact_translation_at_unit_courant(order, form, solver):
+    # supersonic flow along x with uniform v and P: the x-faces upwind
+    # exactly, the predictor is exact for the resulting linear advection, and
+    # at u dt / dx = 1 the density must shift by exactly one zone.  With HLL
+    # the transverse faces add dissipation, so the HLL case varies rho along
+    # x only; the linearized solver upwinds the contact on every face, so its
+    # case varies rho in all three directions.
+    rng = np.random.default_rng(order)
+    n = (6, 5, 8)
+    if solver == 'hll':
+        rho = np.broadcast_to(rng.uniform(0.8, 1.2, size=(1, 1, n[2])), n).copy()
+    else:
+        rho = rng.uniform(0.8, 1.2, size=n)
+    u = 4.0
+    v = np.zeros((3,) + n)
+    v[0] = u
+    U = conserved(rho, v, np.full(n, 0.01), None, 1.4)
+    cfg = OracleConfig(order=order, form=form, riemann=solver)
+    dt = (1.0 / n[2]) / u
+    Un = step(U, dt, cfg)
+    assert np.allclose(Un[0], np.roll(rho, 1, axis=2), rtol=0, atol=1e-9)
+
+
+def _density_wave(n, t, gamma=1.4):
+    """rho = 1 + 0.2 sin(2 pi (x + y + z - 3t)), v = (1, 1, 1), P = 1, with
+    exact zone averages (sinc factors)."""
+    x = (np.arange(n) + 0.5) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing='ij')
+    h = 1.0 / n
+    s = (np.sin(np.pi * h) / (np.pi * h)) ** 3
+    rho = 1.0 + 0.2 * s * np.sin(2 * np.pi * (X + Y + Z - 3.0 * t))
+    U = np.zeros((5,) + rho.shape)
+    U[0] = rho
+    U[1:4] = rho
+    U[4] = 1.0 / (gamma - 1.0) + 1.5 * rho
+    return U
+
+
+def _run(U, cfg, T, cfl=0.3):
+    t = 0.0
+    while t < T - 1e-14:
+        dt = min(compute_dt(U, cfg, cfl), T - t)
+        U = step(U, dt, cfg)
+        t += dt
+    return U
+
+
+def _read_golden_rates():
+    rates = {}
+    with open(os.path.join(GOLDEN, 'table_iv_density_wave.txt')) as fh:
+        for line in fh:
+            if line.startswith('#') or not line.strip():
+                continue
+            order, n, l1, rate = line.split()
+            if rate != '-':
+                rates.setdefault(int(order), []).append(float(rate))
+    return rates
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("order,sizes,T", [(2, (16, 32), 0.02), (3, (8, 16), 0.05), (4, (8, 16), 0.05)])
+def test_design_order_density_wave(order, sizes, T):
+    # Table IV demonstrates L1 rates near the design order on a smooth
+    # diagonal density wave; the oracle must reach its design order too
+    paper = _read_golden_rates()[order]
+    assert min(paper) > order - 0.5
+    cfg = OracleConfig(order=order, form='modal', riemann='hll')
+    errs = []
+    for n in sizes:
+        U = _run(_density_wave(n, 0.0), cfg, T)
+        errs.append(np.abs(U[0] - _density_wave(n, T)[0]).mean())
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > order - 0.6, (errs, rate)
+
+
+def _blast(n, gamma=1.4):
+    x = (np.arange(n) + 0.5) / n - 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing='ij')
+    r = np.sqrt(X ** 2 + Y ** 2 + Z ** 2)
+    P = np.where(r < 0.2, 10.0, 0.1)
+    return conserved(np.ones_like(r), np.zeros((3,) + r.shape), P, None, gamma)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_modal_blast_is_mirror_symmetric(order):
+    # Sec. VIII.3: with the modal formulation, oppositely directed velocities
+    # stay equal in magnitude to round-off
+    cfg = OracleConfig(order=order, form='modal', riemann='hll')
+    U = _blast(10)
+    for _ in range(4):
+        U = step(U, compute_dt(U, cfg, 0.3), cfg)
+    rho, v, P, _ = primitives(U, 1.4)
+    scale = np.abs(v).max()
+    assert scale > 0.1
+    assert np.abs(v[0] + v[0][:, :, ::-1]).max() < 1e-12 * scale
+    assert np.abs(v[1] + v[1][:, ::-1, :]).max() < 1e-12 * scale
+    assert np.abs(v[2] + v[2][::-1, :, :]).max() < 1e-12 * scale
+    assert np.abs(rho - rho[::-1, ::-1, ::-1]).max() < 1e-12
+
+
+def test_nodal_blast_is_not_mirror_symmetric():
+    # Sec. VIII.3: the asymmetric nodes of App. A break the mirror symmetry
+    cfg = OracleConfig(order=2, form='nodal', riemann='hll')
+    U = _blast(10)
+    for _ in range(4):
+        U = step(U, compute_dt(U, cfg, 0.3), cfg)
+    _, v, _, _ = primitives(U, 1.4)
+    assert np.abs(v[0] + v[0][:, :, ::-1]).max() > 1e-8 * np.abs(v).max()
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_step_block_equals_full_step(order):
+    cfg = OracleConfig(order=order, riemann='linearized')
+    U = _random_smooth_state(9, 5)
+    dt = compute_dt(U, cfg, 0.3)
+    full = step(U, dt, cfg)
+    blk = step_block(U, dt, cfg, (7, 1, 4), (3, 2, 4))
+    iz = np.arange(7, 10) % 9
+    ref = full[:, iz][:, :, 1:3][:, :, :, 4:8]
+    assert np.array_equal(blk, ref)
