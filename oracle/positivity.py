@@ -13,10 +13,15 @@ stays conservative, and theta = 1 (no change at all) wherever the polynomial
 is already positive there, so smooth solutions and every other pin are
 unaffected.
 
-Check set: all predictor nodes (eq. 31/37/46, or A.1), the facial nodes of all
-six sides (D.1/D.6/D.11) and the six face barycentres (eq. 54).  Applied
-twice: to the spatial modes before the predictor (at the spatial positions of
-the check set) and to all modes after it (at the space-time points).
+Check sets.  Before the predictor the spatial modes are checked at the
+spatial positions of every predictor node (eq. 31/37/46, or A.1) and of every
+facial node that enters a face average; after the predictor all modes are
+checked at those facial nodes of the six sides and at the six face
+barycentres (eq. 54), the points where the step evaluates the space-time
+polynomial.  The facial nodes entering the face average of (D.5)/(D.10)/(D.15)
+composed with (D.4)/(D.9)/(D.14) are nodes 1-4 of (D.1), nodes 1 and 6-10 of
+(D.6) and nodes 1, 2, 5, 6, 9, 14-19 and 24 of (D.11); the others carry zero
+weight.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 """
@@ -30,15 +35,29 @@ from .predictor import NODES_MODAL, NODES_NODAL_2
 EPS_REL = 1.0e-8
 
 
-def check_points(order, form):
-    """Space-time points of the check set, in a fixed order."""
-    pts = list(NODES_NODAL_2 if form == 'nodal' else NODES_MODAL[order])
+# 1-based facial nodes with a nonzero weight in the face average
+FACE_AVERAGE_NODES = {2: [1, 2, 3, 4], 3: [1, 6, 7, 8, 9, 10],
+                      4: [1, 2, 5, 6, 9, 14, 15, 16, 17, 18, 19, 24]}
+
+
+def facial_check_points(order):
+    """Space-time points of the facial check set, six sides, fixed order."""
+    pts = []
     for d in range(3):
         for s in (-1, 1):
-            for (t1, t2, tau) in FACE_NODES[order]:
+            for j in FACE_AVERAGE_NODES[order]:
+                t1, t2, tau = FACE_NODES[order][j - 1]
                 pts.append(zone_point(d, s, t1, t2, tau))
             pts.append(zone_point(d, s, 0.0, 0.0, 0.5))
     return [tuple(float(c) for c in p) for p in pts]
+
+
+def spatial_check_points(order, form):
+    """Distinct spatial positions of the predictor nodes and of the facial
+    check points (tau set to 0)."""
+    pts = list(NODES_NODAL_2 if form == 'nodal' else NODES_MODAL[order])
+    pts += facial_check_points(order)
+    return sorted(set((float(p[0]), float(p[1]), float(p[2]), 0.0) for p in pts))
 
 
 def _pressure_like(u, gamma):
@@ -96,8 +115,7 @@ def scale_factor(ubar, values, gamma):
 def limit_spatial(what, order, form, gamma):
     """Scale w_2..w_{L_S} so the spatial polynomial is positive at the
     spatial positions of the check set."""
-    # evaluate the spatial part only (tau = 0)
-    pts = sorted(set((p[0], p[1], p[2], 0.0) for p in check_points(order, form)))
+    pts = spatial_check_points(order, form)
     vals = [evaluate(_as_spacetime(what, order), order, p) for p in pts]
     theta = scale_factor(what[0], vals, gamma)
     out = what.copy()
@@ -114,8 +132,8 @@ def _as_spacetime(what, order):
 
 def limit_spacetime(uhat, order, form, gamma):
     """Scale every mode but the zone average so the space-time polynomial is
-    positive at every point of the check set."""
-    vals = [evaluate(uhat, order, p) for p in check_points(order, form)]
+    positive at the facial check points."""
+    vals = [evaluate(uhat, order, p) for p in facial_check_points(order)]
     theta = scale_factor(uhat[0], vals, gamma)
     out = uhat.copy()
     out[1:] = out[1:] * theta

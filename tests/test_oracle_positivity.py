@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from oracle import basis, positivity
+from oracle import basis, faces, positivity
 from oracle.physics import primitives
 
 
@@ -18,7 +18,21 @@ def _zone_poly(order, rng, amp):
 def _check_values(w, order, form):
     uh = np.zeros((basis.N_SPACETIME[order],) + w.shape[1:])
     uh[:w.shape[0]] = w
-    return [basis.evaluate(uh, order, p) for p in positivity.check_points(order, form)]
+    return [basis.evaluate(uh, order, p) for p in positivity.spatial_check_points(order, form)]
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_face_average_nodes_are_the_weighted_ones(order):
+    # compose (D.4)/(D.9)/(D.14) with the exact face integral: exactly the
+    # listed facial nodes carry a nonzero weight
+    n = len(faces.FACE_NODES[order])
+    weights = []
+    for j in range(n):
+        unit = [None] + [1.0 if k == j else 0.0 for k in range(n)]
+        weights.append(faces.face_average_of_modes(faces.FACE_RULE[order](unit), order))
+    nz = [j + 1 for j, w in enumerate(weights) if abs(w) > 1e-14]
+    assert nz == positivity.FACE_AVERAGE_NODES[order]
+    assert abs(sum(weights) - 1.0) < 1e-14
 
 
 @pytest.mark.parametrize("order", [2, 3, 4])
