@@ -1,0 +1,123 @@
+/*
+ * ader.h -- C ABI of the MI355X ADER-CG step library (libader_hip.so).
+ *
+ * One ADER-CG time step on a periodic 3D Cartesian mesh, after Balsara,
+ * Meyer, Dumbser, Du & Xu, "Efficient Implementation of ADER Schemes for
+ * Euler and Magnetohydrodynamical Flows on Structured Meshes" (arXiv
+ * 1006.2146): reconstruction (Sec. II.1), the ADER-CG space-time predictor
+ * (Sec. II.2, IV; App. A), space-time averaged Riemann fluxes at the faces
+ * (Sec. II.3, V; App. D) and the one-step update of eq. (6).
+ *
+ * Conventions
+ *  - State layout: SoA double U[5][nz][ny][nx], x fastest; components
+ *    (rho, rho vx, rho vy, rho vz, E) with E = rho v^2/2 + P/(gamma-1)
+ *    (eq. 3 with B = 0), zone averages.  Zone (i,j,k) covers
+ *    [i dx, (i+1) dx] x [j dy, (j+1) dy] x [k dz, (k+1) dz], dx = lx/nx, ...
+ *  - Every call is ordered on the HIP stream given to ader_create (NULL =
+ *    the default stream).  Calls that return data to the host synchronise
+ *    that stream; ader_step and ader_step_cfl do not.
+ *  - Errors: every int-returning call returns ADER_OK (0) or a negative
+ *    ADER_E* code; nothing throws across the ABI.  A context is not
+ *    thread-safe.
+ *  - Ownership: the library copies host arrays passed to it; device buffers
+ *    it allocates are freed by ader_destroy.  A device state bound with
+ *    ader_bind_device_state stays owned by the caller and must outlive the
+ *    context (or the next bind).
+ */
+#ifndef ADER_H
+#define ADER_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ader_ctx ader_ctx;
+
+enum {
+  ADER_OK = 0,
+  ADER_EINVAL = -1,        /* bad argument (size, order, gamma, dt, ...) */
+  ADER_EUNSUPPORTED = -2,  /* valid but not built (e.g. nodal at order 3) */
+  ADER_ENOMEM = -3,        /* device allocation failed */
+  ADER_EDEVICE = -4,       /* a HIP call failed */
+  ADER_ESTATE = -5,        /* state has rho <= 0, P <= 0 or a non-finite value */
+  ADER_ESEQ = -6           /* call out of sequence (e.g. step before set_state) */
+};
+
+enum { ADER_EULER = 0 };                       /* eq. (3) with B = 0 */
+enum { ADER_HLL = 0, ADER_LINEARIZED = 1 };     /* eq. (17)/(56); Sec. II.3 */
+enum { ADER_MODAL = 0, ADER_NODAL = 1 };        /* Sec. IV; App. A (order 2) */
+enum { ADER_FP64 = 0, ADER_MIXED = 1 };         /* all-FP64, or FP32 bulk with FP64
+                                                   update and dt */
+
+typedef struct {
+  int nx, ny, nz;        /* zones per axis, each >= 1 */
+  double lx, ly, lz;     /* periodic box lengths, each > 0 */
+} ader_mesh;
+
+/* Create a context on HIP device `device` with `stream` (a hipStream_t, or
+ * NULL).  Defaults: gamma 1.4, order 3 modal, HLL, FP64.  Allocates the
+ * state and the work buffers of the largest order.  Returns ADER_EINVAL for
+ * a bad mesh or system, ADER_ENOMEM / ADER_EDEVICE on HIP failures. */
+int ader_create(const ader_mesh* mesh, int system, int device, void* stream,
+                ader_ctx** out);
+
+/* Ratio of specific heats, gamma > 1 (eq. 3). */
+int ader_set_gamma(ader_ctx* ctx, double gamma);
+
+/* order in {2, 3, 4}; form ADER_MODAL (Sec. IV) or ADER_NODAL (App. A,
+ * order 2 only: ADER_EUNSUPPORTED otherwise).  At order 2 the
+ * reconstruction is minmod-limited linear; at 3 and 4 it is centred WENO. */
+int ader_set_order(ader_ctx* ctx, int order, int form);
+
+/* ADER_HLL or ADER_LINEARIZED. */
+int ader_set_riemann(ader_ctx* ctx, int riemann);
+
+/* ADER_FP64 or ADER_MIXED. */
+int ader_set_precision(ader_ctx* ctx, int precision);
+
+/* Copy a host state U[5][nz][ny][nx] (conserved zone averages) to the
+ * device.  Returns ADER_ESTATE (and keeps the old state) if any zone has
+ * rho <= 0, P <= 0 or a non-finite component. */
+int ader_set_state(ader_ctx* ctx, const double* U);
+
+/* Use a caller-owned device buffer of 5*nx*ny*nz doubles as the state
+ * (zero copy, e.g. a torch tensor's data pointer).  The library reads and
+ * updates it in place on the context's stream. */
+int ader_bind_device_state(ader_ctx* ctx, void* dU);
+
+/* Copy the state to the host array U[5][nz][ny][nx] (synchronises). */
+int ader_get_state(ader_ctx* ctx, double* U);
+
+/* dt = cfl / max over zones of sum_d (|v_d| + c) / dx_d (c = sound speed),
+ * computed on the device into the context's dt slot.  If dt_out is not
+ * NULL the value is copied back (synchronises) and ADER_ESTATE is returned
+ * if a zone is unphysical.  cfl > 0. */
+int ader_compute_dt(ader_ctx* ctx, double cfl, double* dt_out);
+
+/* One ADER-CG step of size dt > 0 (finite).  Asynchronous. */
+int ader_step(ader_ctx* ctx, double dt);
+
+/* dt by CFL on the device, then one step with it; no host round trip. */
+int ader_step_cfl(ader_ctx* ctx, double cfl);
+
+/* The dt of the latest ader_compute_dt / ader_step_cfl / ader_step
+ * (synchronises). */
+int ader_get_dt(ader_ctx* ctx, double* dt_out);
+
+/* Wait for all queued work; returns ADER_ESTATE if a dt evaluation since
+ * the last check met an unphysical zone, ADER_EDEVICE on a HIP error. */
+int ader_synchronize(ader_ctx* ctx);
+
+/* Bytes of device memory the context holds (state + work buffers). */
+int ader_device_bytes(ader_ctx* ctx, double* bytes_out);
+
+/* Static description of an error code. */
+const char* ader_strerror(int code);
+
+/* Free the context and its device buffers (NULL is a no-op). */
+void ader_destroy(ader_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADER_H */

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of libader_hip.so (include/ader.h), same names as the
+C ABI.  Argument marshalling only: every step of the path runs in the HIP
+kernels.  Raises if the library is missing; there is no CPU fallback."""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libader_hip.so")
+
+ADER_OK = 0
+ADER_EINVAL = -1
+ADER_EUNSUPPORTED = -2
+ADER_ENOMEM = -3
+ADER_EDEVICE = -4
+ADER_ESTATE = -5
+ADER_ESEQ = -6
+
+ADER_EULER = 0
+ADER_HLL, ADER_LINEARIZED = 0, 1
+ADER_MODAL, ADER_NODAL = 0, 1
+ADER_FP64, ADER_MIXED = 0, 1
+
+# every symbol include/ader.h declares
+EXPORTS = [
+    "ader_create", "ader_set_gamma", "ader_set_order", "ader_set_riemann",
+    "ader_set_precision", "ader_set_state", "ader_bind_device_state",
+    "ader_get_state", "ader_compute_dt", "ader_step", "ader_step_cfl",
+    "ader_get_dt", "ader_synchronize", "ader_device_bytes", "ader_strerror",
+    "ader_destroy",
+]
+
+
+class ader_mesh(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class AderError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, strerror(code), code))
+
+
+_lib = None
+
+
+def load():
+    """Load libader_hip.so (raises FileNotFoundError if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(
+            "libader_hip.so is not built; run `python -m paper_1006_2146_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.c_double
+    I = ctypes.c_int
+    DP = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "ader_create": ([ctypes.POINTER(ader_mesh), I, I, P, ctypes.POINTER(P)], I),
+        "ader_set_gamma": ([P, D], I),
+        "ader_set_order": ([P, I, I], I),
+        "ader_set_riemann": ([P, I], I),
+        "ader_set_precision": ([P, I], I),
+        "ader_set_state": ([P, DP], I),
+        "ader_bind_device_state": ([P, P], I),
+        "ader_get_state": ([P, DP], I),
+        "ader_compute_dt": ([P, D, DP], I),
+        "ader_step": ([P, D], I),
+        "ader_step_cfl": ([P, D], I),
+        "ader_get_dt": ([P, DP], I),
+        "ader_synchronize": ([P], I),
+        "ader_device_bytes": ([P, DP], I),
+        "ader_strerror": ([I], ctypes.c_char_p),
+        "ader_destroy": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(code):
+    return load().ader_strerror(code).decode()
+
+
+def _check(rc, where):
+    if rc != ADER_OK:
+        raise AderError(rc, where)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --- one Python function per C entry point -----------------------------------
+
+def ader_create(nx, ny, nz, lx=1.0, ly=1.0, lz=1.0, system=ADER_EULER, device=0, stream=None):
+    lib = load()
+    mesh = ader_mesh(nx, ny, nz, lx, ly, lz)
+    out = ctypes.c_void_p()
+    rc = lib.ader_create(ctypes.byref(mesh), system, device,
+                         ctypes.c_void_p(stream) if stream else None, ctypes.byref(out))
+    _check(rc, "ader_create")
+    return out
+
+
+def ader_set_gamma(ctx, gamma):
+    _check(load().ader_set_gamma(ctx, gamma), "ader_set_gamma")
+
+
+def ader_set_order(ctx, order, form=ADER_MODAL):
+    _check(load().ader_set_order(ctx, order, form), "ader_set_order")
+
+
+def ader_set_riemann(ctx, riemann):
+    _check(load().ader_set_riemann(ctx, riemann), "ader_set_riemann")
+
+
+def ader_set_precision(ctx, precision):
+    _check(load().ader_set_precision(ctx, precision), "ader_set_precision")
+
+
+def ader_set_state(ctx, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    _check(load().ader_set_state(ctx, _dptr(U)), "ader_set_state")
+
+
+def ader_bind_device_state(ctx, device_ptr):
+    _check(load().ader_bind_device_state(ctx, ctypes.c_void_p(device_ptr)),
+           "ader_bind_device_state")
+
+
+def ader_get_state(ctx, shape):
+    U = np.empty(shape, dtype=np.float64)
+    _check(load().ader_get_state(ctx, _dptr(U)), "ader_get_state")
+    return U
+
+
+def ader_compute_dt(ctx, cfl, want_host=True):
+    if not want_host:
+        _check(load().ader_compute_dt(ctx, cfl, None), "ader_compute_dt")
+        return None
+    dt = ctypes.c_double()
+    _check(load().ader_compute_dt(ctx, cfl, ctypes.byref(dt)), "ader_compute_dt")
+    return dt.value
+
+
+def ader_step(ctx, dt):
+    _check(load().ader_step(ctx, dt), "ader_step")
+
+
+def ader_step_cfl(ctx, cfl):
+    _check(load().ader_step_cfl(ctx, cfl), "ader_step_cfl")
+
+
+def ader_get_dt(ctx):
+    dt = ctypes.c_double()
+    _check(load().ader_get_dt(ctx, ctypes.byref(dt)), "ader_get_dt")
+    return dt.value
+
+
+def ader_synchronize(ctx):
+    _check(load().ader_synchronize(ctx), "ader_synchronize")
+
+
+def ader_device_bytes(ctx):
+    b = ctypes.c_double()
+    _check(load().ader_device_bytes(ctx, ctypes.byref(b)), "ader_device_bytes")
+    return b.value
+
+
+def ader_destroy(ctx):
+    if ctx:
+        load().ader_destroy(ctx)
+
+
+class Solver:
+    """Convenience owner of one context (still marshalling only)."""
+
+    def __init__(self, shape, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3,
+                 form=ADER_MODAL, riemann=ADER_HLL, precision=ADER_FP64,
+                 device=0, stream=None):
+        nz, ny, nx = shape
+        self.shape = (5, nz, ny, nx)
+        self.ctx = ader_create(nx, ny, nz, *lengths, device=device, stream=stream)
+        try:
+            ader_set_gamma(self.ctx, gamma)
+            ader_set_order(self.ctx, order, form)
+            ader_set_riemann(self.ctx, riemann)
+            ader_set_precision(self.ctx, precision)
+        except Exception:
+            self.close()
+            raise
+
+    def set_state(self, U):
+        ader_set_state(self.ctx, U)
+
+    def get_state(self):
+        return ader_get_state(self.ctx, self.shape)
+
+    def compute_dt(self, cfl):
+        return ader_compute_dt(self.ctx, cfl)
+
+    def step(self, dt):
+        ader_step(self.ctx, dt)
+
+    def step_cfl(self, cfl):
+        ader_step_cfl(self.ctx, cfl)
+
+    def dt(self):
+        return ader_get_dt(self.ctx)
+
+    def synchronize(self):
+        ader_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            ader_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

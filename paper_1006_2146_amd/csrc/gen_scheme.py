@@ -1,0 +1,581 @@
+#!/usr/bin/env python3
+"""Generate ``generated/ader_scheme.h``: straight-line device code for the
+per-zone pieces of the ADER-CG step at orders 2-4.
+
+Run once after editing this file (``python gen_scheme.py``); the output is
+committed and compiled by ``build.py``.  Everything is derived here in exact
+rational arithmetic (``fractions.Fraction``) from the paper's definitions:
+
+* basis: Hermite P0..P3 (eq. 9) and tau^d (eq. 13), mode orders eq. (10)-(16);
+* predictor nodes: eq. (31), (37), (46) (modal) and (A.1) (nodal);
+* nodal-to-modal flux rules (33), (40)-(42), (49)-(51) composed with the
+  evolution equations (30), (36), (45): every evolutionary mode becomes a
+  weighted sum of the scaled nodal fluxes f = dt F/dx, g, h; the nodal
+  second-order update (A.4) (z-term read as h4 - h1) and (A.6) likewise;
+* facial nodes (D.1)/(D.6)/(D.11) with the rules (D.4)/(D.9)/(D.14) composed
+  with the face integrals (D.5)/(D.10)/(D.15): the face average of the
+  normal flux is a weighted sum of facial nodal fluxes (nodes of zero weight
+  are dropped);
+* barycentre states (eq. 54) and face averages of u (eq. 55) as weighted sums
+  of modes;
+* centred WENO candidate matrices and smoothness forms.
+
+A mode value at a point is the sum over modes with nonzero basis value only,
+so the emitted code carries no multiplications by zero.
+"""
+
+import os
+from fractions import Fraction as Fr
+
+HALF = Fr(1, 2)
+QTR = Fr(1, 4)
+THIRD = Fr(1, 3)
+
+# ---------------------------------------------------------------- basis ----
+
+
+def P(a, x):
+    x = Fr(x)
+    return [Fr(1), x, x * x - Fr(1, 12), x ** 3 - Fr(3, 20) * x][a]
+
+
+def mode_list(order):
+    """Space-time modes (a, b, c, d) in the order of eq. (14)-(16)."""
+    words = {
+        2: "1 x y z t",
+        3: "1 x y z xx yy zz xy yz xz t tt xt yt zt",
+        4: ("1 x y z xx yy zz xy yz xz xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz "
+            "t tt ttt xt yt zt xtt ytt ztt xxt yyt zzt xyt yzt xzt"),
+    }[order]
+    out = []
+    for w in words.split():
+        if w == "1":
+            out.append((0, 0, 0, 0))
+        else:
+            out.append((w.count('x'), w.count('y'), w.count('z'), w.count('t')))
+    return out
+
+
+LS = {2: 4, 3: 10, 4: 20}
+
+
+def phi(mode, pt):
+    a, b, c, d = mode
+    return P(a, pt[0]) * P(b, pt[1]) * P(c, pt[2]) * Fr(pt[3]) ** d
+
+
+def point_row(order, pt):
+    return [phi(m, pt) for m in mode_list(order)]
+
+
+# ------------------------------------------------------- predictor nodes ----
+
+def pred_nodes(order, form):
+    h, q, t1, t2 = HALF, QTR, THIRD, 2 * THIRD
+    if form == 'nodal':
+        return [(0, 0, 0, 0), (h, 0, 0, 0), (0, h, 0, 0), (0, 0, h, 0), (0, 0, 0, 1)]
+    if order == 2:
+        return [(h, 0, 0, 0), (-h, 0, 0, 0), (0, h, 0, 0), (0, -h, 0, 0),
+                (0, 0, h, 0), (0, 0, -h, 0), (0, 0, 0, 1)]
+    if order == 3:
+        return [(0, 0, 0, 0),
+                (h, h, 0, 0), (h, -h, 0, 0), (h, 0, h, 0), (h, 0, -h, 0),
+                (-h, h, 0, 0), (-h, -h, 0, 0), (-h, 0, h, 0), (-h, 0, -h, 0),
+                (0, h, h, 0), (0, -h, h, 0), (0, h, -h, 0), (0, -h, -h, 0),
+                (h, 0, 0, h), (-h, 0, 0, h), (0, h, 0, h), (0, -h, 0, h),
+                (0, 0, h, h), (0, 0, -h, h), (0, 0, 0, 1)]
+    return [(0, 0, 0, 0), (h, 0, 0, 0), (q, 0, 0, 0), (-q, 0, 0, 0), (-h, 0, 0, 0),
+            (0, h, 0, 0), (0, q, 0, 0), (0, -q, 0, 0), (0, -h, 0, 0),
+            (0, 0, h, 0), (0, 0, q, 0), (0, 0, -q, 0), (0, 0, -h, 0),
+            (h, h, h, 0), (h, -h, h, 0), (h, h, -h, 0), (h, -h, -h, 0),
+            (-h, h, h, 0), (-h, -h, h, 0), (-h, h, -h, 0), (-h, -h, -h, 0),
+            (0, 0, 0, t1), (h, h, 0, t1), (h, -h, 0, t1), (h, 0, h, t1), (h, 0, -h, t1),
+            (-h, h, 0, t1), (-h, -h, 0, t1), (-h, 0, h, t1), (-h, 0, -h, t1),
+            (0, h, h, t1), (0, -h, h, t1), (0, h, -h, t1), (0, -h, -h, t1),
+            (0, 0, 0, t2), (h, 0, 0, t2), (-h, 0, 0, t2), (0, h, 0, t2),
+            (0, -h, 0, t2), (0, 0, h, t2), (0, 0, -h, t2), (0, 0, 0, 1)]
+
+
+# --------------------------------------------- symbolic linear combinations --
+
+class Lin(dict):
+    """A linear combination of named unknowns with rational coefficients."""
+
+    def __add__(self, o):
+        r = Lin(self)
+        for k, v in o.items():
+            r[k] = r.get(k, 0) + v
+        return Lin({k: v for k, v in r.items() if v != 0})
+
+    def __neg__(self):
+        return Lin({k: -v for k, v in self.items()})
+
+    def __sub__(self, o):
+        return self + (-o)
+
+    def __mul__(self, c):
+        return Lin({k: v * Fr(c) for k, v in self.items() if v * Fr(c) != 0})
+
+    __rmul__ = __mul__
+
+    def __truediv__(self, c):
+        return self * (Fr(1) / Fr(c))
+
+
+def unknowns(prefix, n):
+    return [None] + [Lin({(prefix, j): Fr(1)}) for j in range(1, n + 1)]
+
+
+def S(*xs):
+    out = Lin()
+    for x in xs:
+        out = out + x
+    return out
+
+
+def rules_o2(f, g, h):
+    # eq. (33) and the evolution equation (30)
+    return [-(f[1] - f[2]) - (g[3] - g[4]) - (h[5] - h[6])]
+
+
+def rules_o3(f, g, h):
+    # eq. (40), (41), (42) then (36)
+    q1, q2, q3 = S(f[2], f[3], f[4], f[5]), S(f[6], f[7], f[8], f[9]), S(f[10], f[11], f[12], f[13])
+    F2 = (q1 - q2) * QTR
+    F5 = (q1 + q2 - q3) * HALF - f[1] * 2
+    F8 = f[2] - f[3] - f[6] + f[7]
+    F10 = f[4] - f[5] - f[8] + f[9]
+    F13 = (f[14] - f[15] - F2) * 2
+    q4, q5, q6 = S(g[2], g[6], g[10], g[12]), S(g[3], g[7], g[11], g[13]), S(g[4], g[5], g[8], g[9])
+    G3 = (q4 - q5) * QTR
+    G6 = (q4 + q5 - q6) * HALF - g[1] * 2
+    G8 = g[2] - g[3] - g[6] + g[7]
+    G9 = g[10] - g[11] - g[12] + g[13]
+    G14 = (g[16] - g[17] - G3) * 2
+    q7, q8, q9 = S(h[4], h[8], h[10], h[11]), S(h[5], h[9], h[12], h[13]), S(h[2], h[3], h[6], h[7])
+    H4 = (q7 - q8) * QTR
+    H7 = (q7 + q8 - q9) * HALF - h[1] * 2
+    H9 = h[10] - h[11] - h[12] + h[13]
+    H10 = h[4] - h[5] - h[8] + h[9]
+    H15 = (h[18] - h[19] - H4) * 2
+    return [
+        -F2 - G3 - H4,
+        -(F13 + G14 + H15) * HALF,
+        -F5 * 2 - G8 - H10,
+        -F8 - G6 * 2 - H9,
+        -F10 - G9 - H7 * 2,
+    ]
+
+
+def _o4_common(f):
+    q = [None] * 10
+    q[1] = S(f[14], f[15], f[16], f[17])
+    q[2] = S(f[18], f[19], f[20], f[21])
+    q[3] = S(f[14], f[16], f[18], f[20])
+    q[4] = S(f[15], f[17], f[19], f[21])
+    q[5] = S(f[14], f[15], f[18], f[19])
+    q[6] = S(f[16], f[17], f[20], f[21])
+    q[7] = f[23] + f[24] - f[25] - f[26] - f[27] - f[28] + f[29] + f[30]
+    q[8] = f[23] + f[27] - f[24] - f[28] - f[31] - f[33] + f[32] + f[34]
+    q[9] = f[25] + f[29] - f[26] - f[30] - f[31] - f[32] + f[33] + f[34]
+    m = {}
+    m[20] = f[14] - f[15] - f[16] + f[17] - f[18] + f[19] + f[20] - f[21]
+    m[14] = q[8] + (q[3] - q[4]) * HALF - (f[6] - f[9]) * 2
+    m[15] = q[9] + (q[5] - q[6]) * HALF - (f[10] - f[13]) * 2
+    m[16] = q[7] + (q[1] - q[2]) * HALF - (f[2] - f[5]) * 2
+    m[17] = m[15] - q[9] * 2
+    m[18] = m[16] - q[7] * 2
+    m[19] = m[14] - q[8] * 2
+    return q, m
+
+
+def rules_o4(f, g, h):
+    # eq. (49), (50), (51) then (45)
+    q, F = _o4_common(f)
+    q10 = f[23] + f[24] + f[25] + f[26] - f[27] - f[28] - f[29] - f[30]
+    F[5] = (f[2] - f[1] * 2 + f[5]) * 2
+    F[8] = (f[14] - f[15] + f[16] - f[17] - f[18] + f[19] - f[20] + f[21]) * HALF
+    F[10] = (f[14] + f[15] - f[16] - f[17] - f[18] - f[19] + f[20] + f[21]) * HALF
+    F[11] = (f[2] - f[3] * 2 + f[4] * 2 - f[5]) * Fr(16, 3)
+    F[2] = (f[2] - f[5]) * Fr(2, 3) - F[11] * Fr(1, 10) + (q[1] - q[2]) / 12
+    F[27] = (q[1] - q[2]) * Fr(9, 8) + (f[36] - f[37]) * Fr(9, 2) - q10 * Fr(9, 4)
+    F[24] = (f[36] - f[37]) * 3 - q10 * Fr(3, 4) + (F[16] + F[18]) * Fr(3, 8) - F[27]
+    F[30] = (f[36] - f[35] * 2 + f[37]) * 3 - F[5] * Fr(3, 2)
+    F[33] = (f[23] - f[27] - f[24] + f[28]) * 3 - F[8] * 3
+    F[35] = (f[25] - f[29] - f[26] + f[30]) * 3 - F[10] * 3
+
+    q, G = _o4_common(g)
+    q11 = g[23] - g[24] + g[27] - g[28] + g[31] - g[32] + g[33] - g[34]
+    G[6] = (g[6] - g[1] * 2 + g[9]) * 2
+    G[8] = (g[14] - g[15] + g[16] - g[17] - g[18] + g[19] - g[20] + g[21]) * HALF
+    G[9] = (g[14] - g[15] - g[16] + g[17] + g[18] - g[19] - g[20] + g[21]) * HALF
+    G[12] = (g[6] - g[7] * 2 + g[8] * 2 - g[9]) * Fr(16, 3)
+    G[3] = (g[6] - g[9]) * Fr(2, 3) - G[12] * Fr(1, 10) + (q[3] - q[4]) / 12
+    G[28] = (q[3] - q[4]) * Fr(9, 8) + (g[38] - g[39]) * Fr(9, 2) - q11 * Fr(9, 4)
+    G[25] = (g[38] - g[39]) * 3 - q11 * Fr(3, 4) + (G[14] + G[19]) * Fr(3, 8) - G[28]
+    G[31] = (g[38] - g[35] * 2 + g[39]) * 3 - G[6] * Fr(3, 2)
+    G[33] = (g[23] - g[27] - g[24] + g[28]) * 3 - G[8] * 3
+    G[34] = (g[31] - g[32] - g[33] + g[34]) * 3 - G[9] * 3
+
+    q, H = _o4_common(h)
+    q12 = h[25] - h[26] + h[29] - h[30] + h[31] + h[32] - h[33] - h[34]
+    H[7] = (h[10] - h[1] * 2 + h[13]) * 2
+    H[9] = (h[14] - h[15] - h[16] + h[17] + h[18] - h[19] - h[20] + h[21]) * HALF
+    H[10] = (h[14] + h[15] - h[16] - h[17] - h[18] - h[19] + h[20] + h[21]) * HALF
+    H[13] = (h[10] - h[11] * 2 + h[12] * 2 - h[13]) * Fr(16, 3)
+    H[4] = (h[10] - h[13]) * Fr(2, 3) - H[13] * Fr(1, 10) + (q[5] - q[6]) / 12
+    H[29] = (q[5] - q[6]) * Fr(9, 8) + (h[40] - h[41]) * Fr(9, 2) - q12 * Fr(9, 4)
+    H[26] = (h[40] - h[41]) * 3 - q12 * Fr(3, 4) + (H[15] + H[17]) * Fr(3, 8) - H[29]
+    H[32] = (h[40] - h[35] * 2 + h[41]) * 3 - H[7] * Fr(3, 2)
+    H[34] = (h[31] - h[32] - h[33] + h[34]) * 3 - H[9] * 3
+    H[35] = (h[25] - h[26] - h[29] + h[30]) * 3 - H[10] * 3
+
+    t = Fr(1, 10)
+    return [
+        -F[11] * t - F[2] - G[12] * t - G[3] - H[13] * t - H[4],
+        -(F[24] + G[25] + H[26]) * HALF,
+        -(F[27] + G[28] + H[29]) * THIRD,
+        -F[5] * 2 - G[8] - H[10],
+        -F[8] - G[6] * 2 - H[9],
+        -F[10] - G[9] - H[7] * 2,
+        -F[30] - G[33] * HALF - H[35] * HALF,
+        -F[33] * HALF - G[31] - H[34] * HALF,
+        -F[35] * HALF - G[34] * HALF - H[32],
+        -F[11] * 3 - G[14] - H[15],
+        -F[16] - G[12] * 3 - H[17],
+        -F[18] - G[19] - H[13] * 3,
+        -F[14] * 2 - G[16] * 2 - H[20],
+        -F[20] - G[17] * 2 - H[19] * 2,
+        -F[15] * 2 - G[20] - H[18] * 2,
+    ]
+
+
+def rules_nodal2(f, g, h):
+    # (A.4) with the z-difference taken at node 4, then (A.6): u5 = ubar5 - ubar1
+    return [-(f[2] - f[1]) * 2 - (g[3] - g[1]) * 2 - (h[4] - h[1]) * 2]
+
+
+def evolution_weights(order, form):
+    """W[k] = {(dir, node): weight}: evolutionary mode k as a combination of
+    the scaled nodal fluxes (dir 'f', 'g', 'h'; nodes 1-based)."""
+    n = len(pred_nodes(order, form))
+    f, g, h = unknowns('f', n), unknowns('g', n), unknowns('h', n)
+    if form == 'nodal':
+        return rules_nodal2(f, g, h)
+    return {2: rules_o2, 3: rules_o3, 4: rules_o4}[order](f, g, h)
+
+
+# ------------------------------------------------------------ facial nodes --
+
+def face_nodes(order):
+    h, q, t1, t2 = HALF, QTR, THIRD, 2 * THIRD
+    if order == 2:
+        return [(h, 0, h), (-h, 0, h), (0, h, h), (0, -h, h), (0, 0, 1)]
+    if order == 3:
+        return [(0, 0, 0), (h, h, 0), (-h, h, 0), (h, -h, 0), (-h, -h, 0),
+                (h, 0, h), (-h, 0, h), (0, h, h), (0, -h, h), (0, 0, 1)]
+    return [(0, 0, 0), (h, 0, 0), (q, 0, 0), (-q, 0, 0), (-h, 0, 0),
+            (0, h, 0), (0, q, 0), (0, -q, 0), (0, -h, 0),
+            (h, h, 0), (-h, h, 0), (h, -h, 0), (-h, -h, 0),
+            (0, 0, t1), (h, h, t1), (-h, h, t1), (h, -h, t1), (-h, -h, t1),
+            (0, 0, t2), (h, 0, t2), (-h, 0, t2), (0, h, t2), (0, -h, t2), (0, 0, 1)]
+
+
+def face_average_weights(order):
+    """Composition of (D.4)+(D.5), (D.9)+(D.10), (D.14)+(D.15): face
+    average of the normal flux as a weighted sum over facial nodes."""
+    n = len(face_nodes(order))
+    f = unknowns('f', n)
+    if order == 2:
+        m4 = f[5] * 2 - S(f[1], f[2], f[3], f[4]) * HALF
+        m1 = f[5] - m4
+        avg = m1 + m4 * HALF
+    elif order == 3:
+        q2 = (f[2] + f[4] - f[1] * 4 + f[3] + f[5]) * HALF
+        m1 = (f[1] + S(f[2], f[3], f[4], f[5]) * Fr(1, 8)) * Fr(2, 3)
+        m8 = (f[1] + f[10]) * 2 - S(f[6], f[7], f[8], f[9]) + q2
+        m7 = f[10] - f[1] - m8
+        avg = m1 + m7 * HALF + m8 * THIRD
+    else:
+        m1 = (f[1] * 2 + f[2] + f[5] + f[6] + f[9]) / 6
+        m4 = (f[2] - f[1] * 2 + f[5]) * 2
+        m5 = (f[6] - f[1] * 2 + f[9]) * 2
+        m13 = (f[24] - f[1]) * Fr(9, 2) - (f[19] - f[14]) * Fr(27, 2)
+        m12 = (f[24] - f[19] - f[14] + f[1] - m13 * Fr(2, 3)) * Fr(9, 4)
+        m11 = (f[24] * Fr(3, 2) - f[14] * Fr(5, 2) + S(f[15], f[16], f[17], f[18]) * QTR
+               - m4 * QTR - m5 * QTR - m12 * Fr(4, 3) - m13 * Fr(13, 9))
+        avg = m1 + m11 * HALF + m12 * THIRD + m13 * QTR
+    w = {}
+    for (name, j), c in avg.items():
+        w[j] = c
+    return w
+
+
+# ------------------------------------------------------------- sides --------
+
+SIDES = [(0, -1), (0, 1), (1, -1), (1, 1), (2, -1), (2, 1)]
+
+
+def transverse(d):
+    return {0: (1, 2), 1: (0, 2), 2: (0, 1)}[d]
+
+
+def side_point(d, s, t1, t2, tau):
+    p = [Fr(0)] * 3
+    p[d] = HALF * s
+    a, b = transverse(d)
+    p[a] = Fr(t1)
+    p[b] = Fr(t2)
+    return (p[0], p[1], p[2], Fr(tau))
+
+
+def face_average_u_row(order, d, s):
+    """eq. (55): weights on the modes for the face average of u."""
+    row = []
+    for (a, b, c, dd) in mode_list(order):
+        e = (a, b, c)
+        if all(e[x] == 0 for x in transverse(d)):
+            row.append(P(e[d], HALF * s) / (dd + 1))
+        else:
+            row.append(Fr(0))
+    return row
+
+
+# ---------------------------------------------------------------- WENO ------
+
+def weno_tables(order):
+    """Candidate matrices (cell averages -> moments 1..M-1) for the M-zone
+    stencils covering zone 0, and the smoothness quadratic forms."""
+    M = order
+
+    def cell_avg(a, o):
+        # average of P_a over [o - 1/2, o + 1/2], exactly from antiderivatives
+        lo, hi = Fr(o) - HALF, Fr(o) + HALF
+        coeffs = {0: [1], 1: [0, 1], 2: [Fr(-1, 12), 0, 1], 3: [0, Fr(-3, 20), 0, 1]}[a]
+        tot = Fr(0)
+        for p, c in enumerate(coeffs):
+            tot += Fr(c) * (hi ** (p + 1) - lo ** (p + 1)) / (p + 1)
+        return tot
+
+    mats = []
+    for start in range(-(M - 1), 1):
+        st = list(range(start, start + M))
+        V = [[cell_avg(a, o) for a in range(M)] for o in st]
+        mats.append(_inv(V))
+    return mats
+
+
+def _inv(A):
+    n = len(A)
+    M = [list(r) + [Fr(int(i == j)) for j in range(n)] for i, r in enumerate(A)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        piv = M[c][c]
+        M[c] = [x / piv for x in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                fac = M[r][c]
+                M[r] = [x - fac * y for x, y in zip(M[r], M[c])]
+    return [r[n:] for r in M]
+
+
+# ------------------------------------------------------------ emission ------
+
+def lit(c):
+    c = Fr(c)
+    if c.denominator == 1:
+        return "T(%d.0)" % c.numerator
+    return "T(%d.0 / %d.0)" % (c.numerator, c.denominator)
+
+
+def emit_eval(out, order, pt, dst, indent="    "):
+    """dst[v] = sum over modes with nonzero basis value at pt."""
+    row = point_row(order, pt)
+    ls = LS[order]
+    terms = []
+    for m, c in enumerate(row):
+        if c == 0:
+            continue
+        src = "w[%d][v]" % m if m < ls else "e[%d][v]" % (m - ls)
+        if c == 1:
+            terms.append(src)
+        else:
+            terms.append("%s * %s" % (lit(c), src))
+    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, " + ".join(terms)))
+
+
+def emit_spatial_eval(out, order, pt, dst, indent="    "):
+    row = point_row(order, (pt[0], pt[1], pt[2], 0))
+    ls = LS[order]
+    terms = []
+    for m, c in enumerate(row[:ls]):
+        if c == 0:
+            continue
+        src = "w[%d][v]" % m
+        terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
+    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, " + ".join(terms)))
+
+
+def gen_order(order, form):
+    nodes = pred_nodes(order, form)
+    W = evolution_weights(order, form)
+    ls = LS[order]
+    ne = len(mode_list(order)) - ls
+    tag = "%s%d" % ('N' if form == 'nodal' else 'M', order)
+    out = []
+    out.append("// ---- %s order %d ----" % ("nodal" if form == 'nodal' else "modal", order))
+    out.append("template <class T, int NV> struct Scheme%s {" % tag)
+    out.append("  static constexpr int LS = %d, NE = %d;" % (ls, ne))
+
+    # per node, per direction: list of (k, weight)
+    node_dirs = {}
+    for k, lin in enumerate(W):
+        for (dname, j), c in lin.items():
+            node_dirs.setdefault(j, {}).setdefault(dname, []).append((k, c))
+
+    def emit_node(j, accname, lines):
+        pt = nodes[j - 1]
+        lines.append("    // node %d at (%s)" % (j, ", ".join(str(x) for x in pt)))
+        emit_eval(lines, order, pt, "u")
+        for dname, axis in (('f', 0), ('g', 1), ('h', 2)):
+            ws = node_dirs.get(j, {}).get(dname)
+            if not ws:
+                continue
+            lines.append("    Phys::template flux<%d>(u, fl, gam);" % axis)
+            for k, c in ws:
+                lines.append("    for (int v = 0; v < NV; ++v) %s[%d][v] += (%s * s%s) * fl[v];"
+                             % (accname, k, lit(c), "xyz"[axis]))
+
+    # predictor
+    out.append("  // Picard iterations of the space-time predictor; fluxes at tau = 0")
+    out.append("  // nodes are taken once, the others on each of the %d iterations." % (order - 1))
+    out.append("  template <class Phys>")
+    out.append("  __device__ static inline void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
+    out.append("                                        T sx, T sy, T sz, T gam) {")
+    out.append("    T u[NV], fl[NV], a0[NE][NV];")
+    out.append("    for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) { a0[k][v] = T(0); e[k][v] = T(0); }")
+    for j in range(1, len(nodes) + 1):
+        if nodes[j - 1][3] == 0 and j in node_dirs:
+            emit_node(j, "a0", out)
+    later = [j for j in range(1, len(nodes) + 1) if nodes[j - 1][3] != 0 and j in node_dirs]
+    out.append("    for (int it = 0; it < %d; ++it) {" % (order - 1))
+    out.append("      T a1[NE][NV];")
+    out.append("      for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) a1[k][v] = a0[k][v];")
+    body = []
+    for j in later:
+        emit_node(j, "a1", body)
+    out.extend("  " + b for b in body)
+    out.append("      for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) e[k][v] = a1[k][v];")
+    out.append("    }")
+    out.append("  }")
+
+    # spatial check points (positivity, before the predictor)
+    fav = face_average_weights(order)
+    fnodes = face_nodes(order)
+    sp = set()
+    for p in nodes:
+        sp.add((Fr(p[0]), Fr(p[1]), Fr(p[2])))
+    for d, s in SIDES:
+        for j in sorted(fav):
+            t1, t2, tau = fnodes[j - 1]
+            p = side_point(d, s, t1, t2, tau)
+            sp.add(p[:3])
+        p = side_point(d, s, 0, 0, HALF)
+        sp.add(p[:3])
+    sp = sorted(sp)
+    out.append("  // %d spatial check points of the positivity safeguard" % len(sp))
+    out.append("  template <class Acc>")
+    out.append("  __device__ static inline void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("    T u[NV];")
+    for p in sp:
+        emit_spatial_eval(out, order, p, "u")
+        out.append("    acc(u);")
+    out.append("  }")
+
+    # facial check points after the predictor
+    out.append("  // facial nodes entering the face averages, and barycentres, of all sides")
+    out.append("  template <class Acc>")
+    out.append("  __device__ static inline void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("    T u[NV];")
+    for d, s in SIDES:
+        for j in sorted(fav):
+            t1, t2, tau = fnodes[j - 1]
+            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u")
+            out.append("    acc(u);")
+        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "u")
+        out.append("    acc(u);")
+    out.append("  }")
+
+    # face packets
+    out.append("  // side packet: barycentre state (eq. 54), face average of u (eq. 55),")
+    out.append("  // face average of the physical normal flux (App. D composed)")
+    out.append("  template <int SIDE, class Phys>")
+    out.append("  __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], T gam,")
+    out.append("                                     T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
+    out.append("    T u[NV], fl[NV];")
+    for si, (d, s) in enumerate(SIDES):
+        out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s))
+        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "ub", indent="      ")
+        row = face_average_u_row(order, d, s)
+        terms = []
+        for m, c in enumerate(row):
+            if c == 0:
+                continue
+            src = "w[%d][v]" % m if m < ls else "e[%d][v]" % (m - ls)
+            terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
+        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % " + ".join(terms))
+        out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
+        for j in sorted(fav):
+            t1, t2, tau = fnodes[j - 1]
+            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", indent="      ")
+            out.append("      Phys::template flux<%d>(u, fl, gam);" % d)
+            out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
+        out.append("    }")
+    out.append("  }")
+    out.append("};")
+    return out
+
+
+def gen_weno():
+    out = ["// ---- centred WENO tables: candidate moments from the stencil's averages ----"]
+    for order in (3, 4):
+        mats = weno_tables(order)
+        M = order
+        out.append("template <class T> struct Weno%d {" % order)
+        out.append("  // cand<s>(d, m): moments m[1..%d] of stencil s (zones s-%d .. s) from" % (M - 1, M - 1))
+        out.append("  // the averages d[0..%d] at offsets -%d..%d" % (2 * M - 2, M - 1, M - 1))
+        for s, mat in enumerate(mats):
+            out.append("  __device__ static inline void cand%d(const T* d, T* m) {" % s)
+            for a in range(1, M):
+                terms = []
+                for q in range(M):
+                    c = mat[a][q]
+                    if c != 0:
+                        terms.append("%s * d[%d]" % (lit(c), s + q))
+                out.append("    m[%d] = %s;" % (a, " + ".join(terms)))
+            out.append("  }")
+        out.append("};")
+    return out
+
+
+def main():
+    here = os.path.dirname(os.path.abspath(__file__))
+    lines = [
+        "// GENERATED by gen_scheme.py -- do not edit by hand.",
+        "// Straight-line per-zone pieces of the ADER-CG step (see gen_scheme.py for",
+        "// the derivation from the paper's equations).",
+        "#pragma once",
+        "namespace ader_gen {",
+    ]
+    for order, form in ((2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')):
+        lines += gen_order(order, form)
+    lines += gen_weno()
+    lines.append("}  // namespace ader_gen")
+    os.makedirs(os.path.join(here, "generated"), exist_ok=True)
+    with open(os.path.join(here, "generated", "ader_scheme.h"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,146 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  FP64 bar: relative L1 per conserved variable <= 1e-12
+per step (each step compared from the GPU's own previous state)."""
+
+import numpy as np
+import pytest
+
+from oracle import OracleConfig, compute_dt as oracle_dt, step as oracle_step, step_block
+from paper_1006_2146_amd import ader, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+
+RS = {"hll": ader.ADER_HLL, "linearized": ader.ADER_LINEARIZED}
+FORM = {"modal": ader.ADER_MODAL, "nodal": ader.ADER_NODAL}
+
+CASES = [(2, "modal", "hll"), (2, "nodal", "hll"), (2, "modal", "linearized"),
+         (3, "modal", "hll"), (3, "modal", "linearized"),
+         (4, "modal", "hll"), (4, "modal", "linearized")]
+
+
+def rel_l1(a, b):
+    num = np.abs(a - b).sum(axis=(1, 2, 3))
+    den = np.abs(b).sum(axis=(1, 2, 3))
+    return num / den
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _solver(shape, order, form, rs, lengths=(1.0, 1.0, 1.0), precision=ader.ADER_FP64):
+    return ader.Solver(shape, lengths=lengths, order=order, form=FORM[form], riemann=RS[rs],
+                       precision=precision)
+
+
+def _check_steps(U0, order, form, rs, nsteps, cfl=0.3, lengths=(1.0, 1.0, 1.0), tag=""):
+    shape = U0.shape[1:]
+    cfg = OracleConfig(order=order, form=form, riemann=rs, lengths=lengths)
+    with _solver(shape, order, form, rs, lengths) as s:
+        s.set_state(U0)
+        U = U0
+        for it in range(nsteps):
+            say(tag, "order", order, form, rs, "shape", shape, "step", it)
+            dt_gpu = s.compute_dt(cfl)
+            dt_ref = oracle_dt(U, cfg, cfl)
+            assert abs(dt_gpu - dt_ref) <= 1e-14 * dt_ref
+            s.step(dt_gpu)
+            Ug = s.get_state()
+            Uo = oracle_step(U, dt_gpu, cfg)
+            err = rel_l1(Ug, Uo)
+            assert np.all(err <= TOL_FP64), (it, err)
+            U = Ug
+    return U
+
+
+@pytest.mark.parametrize("order,form,rs", CASES)
+def test_parity_smooth_ragged(order, form, rs):
+    U0 = workloads.random_smooth((9, 14, 21), seed=order)
+    _check_steps(U0, order, form, rs, 2, lengths=(1.0, 0.8, 1.3), tag="smooth")
+
+
+@pytest.mark.parametrize("order,form,rs", CASES)
+def test_parity_blast_positivity(order, form, rs):
+    # strong blast: the positivity scaling is active in many zones
+    U0 = workloads.blast((12, 12, 12), p_in=100.0, p_out=0.1, radius=0.25)
+    _check_steps(U0, order, form, rs, 3, tag="blast")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 1), (3, 1, 2), (1, 5, 4)])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_parity_degenerate_meshes(shape, order):
+    U0 = workloads.random_smooth(shape, seed=3)
+    _check_steps(U0, order, "modal", "hll", 1, tag="tiny")
+
+
+def test_constant_state_bitwise():
+    U0 = np.zeros((5, 6, 7, 9))
+    U0[:] = np.array([1.3, 0.2, -0.1, 0.3, 2.5])[:, None, None, None]
+    for order in (2, 3, 4):
+        for rs in ("hll", "linearized"):
+            say("constant", order, rs)
+            with _solver((6, 7, 9), order, "modal", rs) as s:
+                s.set_state(U0)
+                s.step(0.01)
+                assert np.array_equal(s.get_state(), U0)
+
+
+def test_conservation_and_translation():
+    for order in (2, 3, 4):
+        U0 = workloads.random_smooth((10, 9, 8), seed=11)
+        say("conservation", order)
+        with _solver((10, 9, 8), order, "modal", "linearized") as s:
+            s.set_state(U0)
+            for _ in range(3):
+                s.step_cfl(0.3)
+            U = s.get_state()
+            tot0, tot1 = U0.sum(axis=(1, 2, 3)), U.sum(axis=(1, 2, 3))
+            assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(U0).sum(axis=(1, 2, 3)))
+        # exact translation by one zone at unit Courant number (linearized)
+        rng = np.random.default_rng(order)
+        n = (6, 5, 8)
+        rho = rng.uniform(0.8, 1.2, size=n)
+        U0 = np.zeros((5,) + n)
+        U0[0] = rho
+        U0[1] = 4.0 * rho
+        U0[4] = 0.01 / 0.4 + 0.5 * 16.0 * rho
+        say("translation", order)
+        with _solver(n, order, "modal", "linearized") as s:
+            s.set_state(U0)
+            s.step((1.0 / 8) / 4.0)
+            assert np.allclose(s.get_state()[0], np.roll(rho, 1, axis=2), rtol=0, atol=1e-9)
+
+
+def test_config1_density_wave_full():
+    # 32^3, order 2 nodal, minmod, HLL, CFL 0.4, 10 steps, parity every step
+    U0 = workloads.density_wave((32, 32, 32))
+    _check_steps(U0, 2, "nodal", "hll", 10, cfl=0.4, tag="config1")
+
+
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+def test_config2_full_size_sampled(rs):
+    # 128^3 Sedov-mode workload, order 3 modal, one CFL 0.3 step on the GPU;
+    # the oracle recomputes sampled blocks (one around the blast centre)
+    shape = (128, 128, 128)
+    U0 = workloads.sedov_modes(shape)
+    cfg = OracleConfig(order=3, riemann=rs)
+    with _solver(shape, 3, "modal", rs) as s:
+        s.set_state(U0)
+        say("config2", rs, "step_cfl")
+        s.step_cfl(0.3)
+        Ug = s.get_state()
+        dt = s.dt()
+    assert abs(dt - oracle_dt(U0, cfg, 0.3)) <= 1e-14 * dt
+    centre_zone = tuple(int(c) for c in np.argwhere(U0[4] == U0[4].max())[0])
+    origins = [(0, 0, 0), (125, 3, 64), (60, 127, 17),
+               tuple((c - 2) % 128 for c in centre_zone)]
+    for o in origins:
+        ref = step_block(U0, dt, cfg, o, (4, 4, 4))
+        iz = np.arange(o[0], o[0] + 4) % 128
+        iy = np.arange(o[1], o[1] + 4) % 128
+        ix = np.arange(o[2], o[2] + 4) % 128
+        got = Ug[:, iz][:, :, iy][:, :, :, ix]
+        err = rel_l1(got, ref)
+        assert np.all(err <= TOL_FP64), (o, err)
