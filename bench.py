@@ -1,0 +1,164 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X ADER-CG step on the 128^3 Sedov-mode Euler workload.
+
+One "step" is the whole hot path on the device: dt by CFL (wavefront max
+reduction), third-order WENO reconstruction, the ADER-CG space-time
+predictor, face-side quadrature, Riemann fluxes and the FP64 update.  The
+state stays resident in HBM (a torch tensor bound zero-copy to the library;
+torch is used for the device buffer and the stream only).
+
+Prints ONE JSON line (rank 0, one GPU).  Extra fields: the four variants
+(FP64 / mixed x HLL / linearized), per-stage device times, the roofline of
+the dominant kernel and the CPU oracle baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SHAPE = (128, 128, 128)
+CFL = 0.3
+WORKLOAD = "sedov-modes-128^3"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def flop_counts():
+    path = os.path.join(HERE, "paper_1006_2146_amd", "csrc", "generated", "flop_counts.json")
+    with open(path) as fh:
+        return json.load(fh)["counts"]
+
+
+def run_variant(ader, torch, U0, precision, riemann, steps, warmup):
+    nz, ny, nx = SHAPE
+    N = nx * ny * nz
+    stream = torch.cuda.current_stream()
+    s = ader.Solver(SHAPE, order=3, riemann=riemann, precision=precision,
+                    stream=stream.cuda_stream)
+    try:
+        dU = torch.from_numpy(U0).to("cuda")            # resident state, 5 x N doubles
+        ader.ader_bind_device_state(s.ctx, dU.data_ptr())
+        for _ in range(warmup):
+            s.step_cfl(CFL)
+        s.synchronize()
+        ader.ader_set_timing(s.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(CFL)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stages = ader.ader_stage_times(s.ctx)
+        ader.ader_set_timing(s.ctx, False)
+        s.synchronize()                                  # raises on an unphysical state
+        finite = bool(torch.isfinite(dU).all().item())
+    finally:
+        s.close()
+    wall = t1 - t0
+    return {
+        "zone_updates_per_s": N * steps / wall,
+        "ms_per_step": 1e3 * wall / steps,
+        "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "finite": finite,
+    }
+
+
+def cpu_baseline(U0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: one step of a 64^3 periodic sub-box (ghost zones included in
+    the work, only the 64^3 interior counted)."""
+    from oracle import OracleConfig, compute_dt, step_block
+    cfg = OracleConfig(order=3, riemann="hll")
+    dt = compute_dt(U0, cfg, CFL)
+    box = (64, 64, 64)
+    t0 = time.perf_counter()
+    step_block(U0, dt, cfg, (32, 32, 32), box)
+    el = time.perf_counter() - t0
+    return {"value": float(np.prod(box) / el), "unit": "zone-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one order-3 HLL FP64 step of a 64^3 periodic sub-box of the "
+                      "128^3 Sedov-mode workload (numpy, single thread), %.1f s" % el}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="fp64-hll,fp64-lin,mixed-hll,mixed-lin")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1006_2146_amd import ader, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    ader.load()
+    log("building the workload", SHAPE)
+    U0 = workloads.sedov_modes(SHAPE)
+    N = int(np.prod(SHAPE))
+
+    variants = {}
+    table = {"fp64-hll": (ader.ADER_FP64, ader.ADER_HLL), "fp64-lin": (ader.ADER_FP64, ader.ADER_LINEARIZED),
+             "mixed-hll": (ader.ADER_MIXED, ader.ADER_HLL), "mixed-lin": (ader.ADER_MIXED, ader.ADER_LINEARIZED)}
+    for name in args.variants.split(","):
+        prec, rs = table[name]
+        log("variant", name, "warmup", args.warmup, "steps", args.steps)
+        variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup)
+        log("variant", name, "%.3e zone-updates/s" % variants[name]["zone_updates_per_s"])
+
+    primary = "fp64-hll" if "fp64-hll" in variants else next(iter(variants))
+    pv = variants[primary]
+    flops_zone = flop_counts()["M3"]["total"]
+    pred_ms = pv["stage_ms_per_step"]["predict"]
+    achieved = flops_zone * N / (pred_ms * 1e-3) / 1e12
+    dtype = "f64" if primary.startswith("fp64") else "f32"
+    roofline = {"bound": "alu", "kernel": "k_predict", "achieved": achieved,
+                "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+                "flops_per_zone": flops_zone, "launch_ms": pred_ms}
+
+    out = {
+        "metric": METRIC,
+        "value": pv["zone_updates_per_s"],
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": pv["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "system": "euler", "order": 3, "form": "modal",
+                   "riemann": primary.split("-")[1], "precision": primary.split("-")[0],
+                   "zones": N, "cfl": CFL, "gamma": 1.4},
+        "roofline": roofline,
+        "variants": variants,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(U0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,18 @@ int ader_get_dt(ader_ctx* ctx, double* dt_out);
  * the last check met an unphysical zone, ADER_EDEVICE on a HIP error. */
 int ader_synchronize(ader_ctx* ctx);
 
+/* Per-stage device timing.  While enabled, every step records HIP events on
+ * the context's stream around its stages: ADER_STAGE_DT (CFL reduction),
+ * ADER_STAGE_RECON (reconstruction), ADER_STAGE_PREDICT (predictor and
+ * face-side packets), ADER_STAGE_FLUX (Riemann fluxes), ADER_STAGE_UPDATE
+ * (eq. 6).  ader_stage_times synchronises, returns for each stage the summed
+ * milliseconds and the number of timed launches since the previous call
+ * (arrays of ADER_NSTAGES), and starts a new accumulation. */
+enum { ADER_STAGE_DT = 0, ADER_STAGE_RECON = 1, ADER_STAGE_PREDICT = 2,
+       ADER_STAGE_FLUX = 3, ADER_STAGE_UPDATE = 4, ADER_NSTAGES = 5 };
+int ader_set_timing(ader_ctx* ctx, int enable);
+int ader_stage_times(ader_ctx* ctx, double* ms_out, int* counts_out);
+
 /* Bytes of device memory the context holds (state + work buffers). */
 int ader_device_bytes(ader_ctx* ctx, double* bytes_out);
 

@@ -28,9 +28,10 @@ EXPORTS = [
     "ader_create", "ader_set_gamma", "ader_set_order", "ader_set_riemann",
     "ader_set_precision", "ader_set_state", "ader_bind_device_state",
     "ader_get_state", "ader_compute_dt", "ader_step", "ader_step_cfl",
-    "ader_get_dt", "ader_synchronize", "ader_device_bytes", "ader_strerror",
-    "ader_destroy",
+    "ader_get_dt", "ader_synchronize", "ader_set_timing", "ader_stage_times",
+    "ader_device_bytes", "ader_strerror", "ader_destroy",
 ]
+STAGES = ["dt", "recon", "predict", "flux", "update"]
 
 
 class ader_mesh(ctypes.Structure):
@@ -74,6 +75,8 @@ def load():
         "ader_step_cfl": ([P, D], I),
         "ader_get_dt": ([P, DP], I),
         "ader_synchronize": ([P], I),
+        "ader_set_timing": ([P, I], I),
+        "ader_stage_times": ([P, DP, ctypes.POINTER(ctypes.c_int)], I),
         "ader_device_bytes": ([P, DP], I),
         "ader_strerror": ([I], ctypes.c_char_p),
         "ader_destroy": ([P], None),
@@ -168,6 +171,18 @@ def ader_get_dt(ctx):
 
 def ader_synchronize(ctx):
     _check(load().ader_synchronize(ctx), "ader_synchronize")
+
+
+def ader_set_timing(ctx, enable):
+    _check(load().ader_set_timing(ctx, 1 if enable else 0), "ader_set_timing")
+
+
+def ader_stage_times(ctx):
+    """{stage: (milliseconds, launches)} since the previous call."""
+    ms = (ctypes.c_double * len(STAGES))()
+    cnt = (ctypes.c_int * len(STAGES))()
+    _check(load().ader_stage_times(ctx, ms, cnt), "ader_stage_times")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
 
 def ader_device_bytes(ctx):

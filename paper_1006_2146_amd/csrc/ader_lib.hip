@@ -41,6 +41,10 @@ struct ader_ctx {
   bool have_state = false;
   bool have_dt = false;
   size_t bytes = 0;
+  // stage timing: events recorded around each stage while enabled
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  std::vector<int> marks;  // stage of each (start, stop) event pair
 };
 
 namespace {
@@ -61,6 +65,32 @@ int launched() { return check(hipGetLastError()); }
 unsigned blocks_for(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int set_device(ader_ctx* c) { return check(hipSetDevice(c->device)); }
+
+// Records an event pair around one stage when timing is on.
+struct StageTimer {
+  ader_ctx* c;
+  int stage;
+  bool on;
+  StageTimer(ader_ctx* ctx, int s) : c(ctx), stage(s), on(ctx->timing) {
+    if (!on) return;
+    const size_t k = 2 * c->marks.size();
+    while (c->events.size() < k + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on = false;
+        return;
+      }
+      c->events.push_back(e);
+    }
+    (void)hipEventRecord(c->events[k], c->stream);
+  }
+  ~StageTimer() {
+    if (!on) return;
+    const size_t k = 2 * c->marks.size();
+    (void)hipEventRecord(c->events[k + 1], c->stream);
+    c->marks.push_back(stage);
+  }
+};
 
 template <class T>
 int launch_recon(ader_ctx* c) {
@@ -106,19 +136,29 @@ int launch_flux_update(ader_ctx* c) {
   const unsigned nb = blocks_for(c->g.N, kBlock);
   const T* PK = static_cast<const T*>(c->PK);
   T* F = static_cast<T*>(c->F);
-  if (c->riemann == ADER_HLL)
-    k_face_flux<T, 0><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
-  else
-    k_face_flux<T, 1><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
-  ADER_TRY(launched());
+  {
+    StageTimer t(c, ADER_STAGE_FLUX);
+    if (c->riemann == ADER_HLL)
+      k_face_flux<T, 0><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
+    else
+      k_face_flux<T, 1><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
+    ADER_TRY(launched());
+  }
+  StageTimer t(c, ADER_STAGE_UPDATE);
   k_update<T><<<nb, kBlock, 0, c->stream>>>(c->U, F, c->g, c->d_dt, c->dx, c->dy, c->dz);
   return launched();
 }
 
 template <class T>
 int launch_step(ader_ctx* c) {
-  ADER_TRY(launch_recon<T>(c));
-  ADER_TRY(launch_predict<T>(c));
+  {
+    StageTimer t(c, ADER_STAGE_RECON);
+    ADER_TRY(launch_recon<T>(c));
+  }
+  {
+    StageTimer t(c, ADER_STAGE_PREDICT);
+    ADER_TRY(launch_predict<T>(c));
+  }
   return launch_flux_update<T>(c);
 }
 
@@ -127,6 +167,7 @@ int run_step(ader_ctx* c) {
 }
 
 int queue_dt(ader_ctx* c, double cfl) {
+  StageTimer t(c, ADER_STAGE_DT);
   k_dt_partial<<<c->nparts, kBlock, 0, c->stream>>>(c->U, c->g, c->gamma, c->dx, c->dy, c->dz,
                                                     c->d_partial, c->d_bad);
   ADER_TRY(launched());
@@ -161,6 +202,12 @@ bool host_state_ok(const double* U, long long N, double gamma) {
     if (!(p > 0.0)) return false;
   }
   return true;
+}
+
+void drop_events(ader_ctx* c) {
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
+  c->marks.clear();
 }
 
 void free_buffers(ader_ctx* c) {
@@ -338,6 +385,36 @@ int ader_synchronize(ader_ctx* c) {
   return read_status(c);
 }
 
+int ader_set_timing(ader_ctx* c, int enable) {
+  if (!c) return ADER_EINVAL;
+  ADER_TRY(set_device(c));
+  if (!enable) {
+    ADER_TRY(check(hipStreamSynchronize(c->stream)));
+    drop_events(c);
+  }
+  c->marks.clear();
+  c->timing = enable != 0;
+  return ADER_OK;
+}
+
+int ader_stage_times(ader_ctx* c, double* ms_out, int* counts_out) {
+  if (!c || !ms_out || !counts_out) return ADER_EINVAL;
+  ADER_TRY(set_device(c));
+  ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  for (int s = 0; s < ADER_NSTAGES; ++s) {
+    ms_out[s] = 0.0;
+    counts_out[s] = 0;
+  }
+  for (size_t q = 0; q < c->marks.size(); ++q) {
+    float ms = 0.f;
+    ADER_TRY(check(hipEventElapsedTime(&ms, c->events[2 * q], c->events[2 * q + 1])));
+    ms_out[c->marks[q]] += ms;
+    counts_out[c->marks[q]] += 1;
+  }
+  c->marks.clear();
+  return ADER_OK;
+}
+
 int ader_device_bytes(ader_ctx* c, double* bytes_out) {
   if (!c || !bytes_out) return ADER_EINVAL;
   *bytes_out = (double)c->bytes;
@@ -361,6 +438,7 @@ void ader_destroy(ader_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  drop_events(c);
   free_buffers(c);
   delete c;
 }

@@ -11,7 +11,7 @@ struct Euler {
 
   // Physical flux along AXIS (0: F, 1: G, 2: H) of the conserved state u.
   template <int AXIS>
-  __device__ static inline void flux(const T (&u)[5], T (&f)[5], T gam) {
+  __host__ __device__ static inline void flux(const T (&u)[5], T (&f)[5], T gam) {
     const T rinv = T(1) / u[0];
     const T vn = u[1 + AXIS] * rinv;
     const T ke = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * rinv;
@@ -24,7 +24,7 @@ struct Euler {
     f[4] = (u[4] + p) * vn;
   }
 
-  __device__ static inline T pressure(const T (&u)[5], T gam) {
+  __host__ __device__ static inline T pressure(const T (&u)[5], T gam) {
     return (gam - T(1)) * (u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0]);
   }
 };

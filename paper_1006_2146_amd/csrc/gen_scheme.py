@@ -382,6 +382,27 @@ def _inv(A):
 
 # ------------------------------------------------------------ emission ------
 
+# Floating-point operations per zone of the per-zone kernel, counted on the
+# emitted code (one per add, multiply, divide, square root; five variables):
+#   a point evaluation with t nonzero terms: t - 1 adds and one multiply per
+#     coefficient other than 1;
+#   one Euler flux (euler_device.h): 18;
+#   one accumulation into a mode: 2 per variable;
+#   one positivity check of a point (pressure of the state): 9.
+FLUX_FLOPS = 18
+CHECK_FLOPS = 9
+NVARS = 5
+COUNT = {}
+
+
+def _count(key, n):
+    COUNT[key] = COUNT.get(key, 0) + n
+
+
+def _eval_flops(row):
+    nz = [c for c in row if c != 0]
+    return NVARS * (len(nz) - 1 + sum(1 for c in nz if c != 1))
+
 def lit(c):
     c = Fr(c)
     if c.denominator == 1:
@@ -389,9 +410,11 @@ def lit(c):
     return "T(%d.0 / %d.0)" % (c.numerator, c.denominator)
 
 
-def emit_eval(out, order, pt, dst, indent="    "):
+def emit_eval(out, order, pt, dst, indent="    ", count=None):
     """dst[v] = sum over modes with nonzero basis value at pt."""
     row = point_row(order, pt)
+    if count:
+        _count(count, _eval_flops(row))
     ls = LS[order]
     terms = []
     for m, c in enumerate(row):
@@ -405,9 +428,11 @@ def emit_eval(out, order, pt, dst, indent="    "):
     out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, " + ".join(terms)))
 
 
-def emit_spatial_eval(out, order, pt, dst, indent="    "):
+def emit_spatial_eval(out, order, pt, dst, indent="    ", count=None):
     row = point_row(order, (pt[0], pt[1], pt[2], 0))
     ls = LS[order]
+    if count:
+        _count(count, _eval_flops(row[:ls]))
     terms = []
     for m, c in enumerate(row[:ls]):
         if c == 0:
@@ -434,15 +459,18 @@ def gen_order(order, form):
         for (dname, j), c in lin.items():
             node_dirs.setdefault(j, {}).setdefault(dname, []).append((k, c))
 
-    def emit_node(j, accname, lines):
+    def emit_node(j, accname, lines, reps):
         pt = nodes[j - 1]
+        key = (tag, 'predictor')
         lines.append("    // node %d at (%s)" % (j, ", ".join(str(x) for x in pt)))
+        _count(key, reps * _eval_flops(point_row(order, pt)))
         emit_eval(lines, order, pt, "u")
         for dname, axis in (('f', 0), ('g', 1), ('h', 2)):
             ws = node_dirs.get(j, {}).get(dname)
             if not ws:
                 continue
             lines.append("    Phys::template flux<%d>(u, fl, gam);" % axis)
+            _count(key, reps * (FLUX_FLOPS + len(ws) * (1 + 2 * NVARS)))
             for k, c in ws:
                 lines.append("    for (int v = 0; v < NV; ++v) %s[%d][v] += (%s * s%s) * fl[v];"
                              % (accname, k, lit(c), "xyz"[axis]))
@@ -451,23 +479,34 @@ def gen_order(order, form):
     out.append("  // Picard iterations of the space-time predictor; fluxes at tau = 0")
     out.append("  // nodes are taken once, the others on each of the %d iterations." % (order - 1))
     out.append("  template <class Phys>")
-    out.append("  __device__ static inline void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
+    out.append("  __host__ __device__ static inline void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
     out.append("                                        T sx, T sy, T sz, T gam) {")
     out.append("    T u[NV], fl[NV], a0[NE][NV];")
     out.append("    for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) { a0[k][v] = T(0); e[k][v] = T(0); }")
     for j in range(1, len(nodes) + 1):
         if nodes[j - 1][3] == 0 and j in node_dirs:
-            emit_node(j, "a0", out)
+            emit_node(j, "a0", out, 1)
     later = [j for j in range(1, len(nodes) + 1) if nodes[j - 1][3] != 0 and j in node_dirs]
-    out.append("    for (int it = 0; it < %d; ++it) {" % (order - 1))
-    out.append("      T a1[NE][NV];")
-    out.append("      for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) a1[k][v] = a0[k][v];")
-    body = []
-    for j in later:
-        emit_node(j, "a1", body)
-    out.extend("  " + b for b in body)
-    out.append("      for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) e[k][v] = a1[k][v];")
-    out.append("    }")
+    # modes that receive contributions from tau > 0 nodes change on every
+    # iteration; the others are final after the tau = 0 pass
+    moving = sorted({k for j in later for ws in node_dirs[j].values() for k, _ in ws})
+    if not later:
+        for k in range(ne):
+            out.append("    for (int v = 0; v < NV; ++v) e[%d][v] = a0[%d][v];" % (k, k))
+    else:
+        out.append("    for (int it = 0; it < %d; ++it) {" % (order - 1))
+        out.append("      T a1[NE][NV];")
+        for k in moving:
+            out.append("      for (int v = 0; v < NV; ++v) a1[%d][v] = a0[%d][v];" % (k, k))
+        body = []
+        for j in later:
+            emit_node(j, "a1", body, order - 1)
+        out.extend("  " + b for b in body)
+        # the new iterate; every node of this iteration used the previous one
+        for k in range(ne):
+            src = "a1" if k in moving else "a0"
+            out.append("      for (int v = 0; v < NV; ++v) e[%d][v] = %s[%d][v];" % (k, src, k))
+        out.append("    }")
     out.append("  }")
 
     # spatial check points (positivity, before the predictor)
@@ -486,24 +525,49 @@ def gen_order(order, form):
     sp = sorted(sp)
     out.append("  // %d spatial check points of the positivity safeguard" % len(sp))
     out.append("  template <class Acc>")
-    out.append("  __device__ static inline void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static inline void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
     out.append("    T u[NV];")
     for p in sp:
-        emit_spatial_eval(out, order, p, "u")
+        emit_spatial_eval(out, order, p, "u", count=(tag, 'positivity'))
+        _count((tag, 'positivity'), CHECK_FLOPS)
         out.append("    acc(u);")
     out.append("  }")
+
+    # tables of the same points for the exact (rare) positivity pass
+    fpts = []
+    for d, s_ in SIDES:
+        for j in sorted(fav):
+            t1, t2, tau = fnodes[j - 1]
+            fpts.append(side_point(d, s_, t1, t2, tau))
+        fpts.append(side_point(d, s_, 0, 0, HALF))
+    out.append("  static constexpr int NSPATIAL = %d, NFACIAL = %d;" % (len(sp), len(fpts)))
+    out.append("  // basis values of the spatial modes at the spatial check points")
+    out.append("  static constexpr double spatial_phi[%d][%d] = {" % (len(sp), ls))
+    for p in sp:
+        row = point_row(order, (p[0], p[1], p[2], 0))[:ls]
+        out.append("    {%s}," % ", ".join("%.17g" % float(c) for c in row))
+    out.append("  };")
+    L = len(mode_list(order))
+    out.append("  // basis values of all modes at the facial check points")
+    out.append("  static constexpr double facial_phi[%d][%d] = {" % (len(fpts), L))
+    for p in fpts:
+        row = point_row(order, p)
+        out.append("    {%s}," % ", ".join("%.17g" % float(c) for c in row))
+    out.append("  };")
 
     # facial check points after the predictor
     out.append("  // facial nodes entering the face averages, and barycentres, of all sides")
     out.append("  template <class Acc>")
-    out.append("  __device__ static inline void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static inline void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
     out.append("    T u[NV];")
     for d, s in SIDES:
         for j in sorted(fav):
             t1, t2, tau = fnodes[j - 1]
-            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u")
+            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", count=(tag, 'positivity'))
+            _count((tag, 'positivity'), CHECK_FLOPS)
             out.append("    acc(u);")
-        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "u")
+        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "u", count=(tag, 'positivity'))
+        _count((tag, 'positivity'), CHECK_FLOPS)
         out.append("    acc(u);")
     out.append("  }")
 
@@ -511,13 +575,15 @@ def gen_order(order, form):
     out.append("  // side packet: barycentre state (eq. 54), face average of u (eq. 55),")
     out.append("  // face average of the physical normal flux (App. D composed)")
     out.append("  template <int SIDE, class Phys>")
-    out.append("  __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], T gam,")
+    out.append("  __host__ __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], T gam,")
     out.append("                                     T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
     out.append("    T u[NV], fl[NV];")
     for si, (d, s) in enumerate(SIDES):
         out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s))
-        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "ub", indent="      ")
+        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "ub", indent="      ",
+                  count=(tag, 'faces'))
         row = face_average_u_row(order, d, s)
+        _count((tag, 'faces'), _eval_flops(row))
         terms = []
         for m, c in enumerate(row):
             if c == 0:
@@ -528,7 +594,9 @@ def gen_order(order, form):
         out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
         for j in sorted(fav):
             t1, t2, tau = fnodes[j - 1]
-            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", indent="      ")
+            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", indent="      ",
+                      count=(tag, 'faces'))
+            _count((tag, 'faces'), FLUX_FLOPS + 2 * NVARS)
             out.append("      Phys::template flux<%d>(u, fl, gam);" % d)
             out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
         out.append("    }")
@@ -546,7 +614,7 @@ def gen_weno():
         out.append("  // cand<s>(d, m): moments m[1..%d] of stencil s (zones s-%d .. s) from" % (M - 1, M - 1))
         out.append("  // the averages d[0..%d] at offsets -%d..%d" % (2 * M - 2, M - 1, M - 1))
         for s, mat in enumerate(mats):
-            out.append("  __device__ static inline void cand%d(const T* d, T* m) {" % s)
+            out.append("  __host__ __device__ static inline void cand%d(const T* d, T* m) {" % s)
             for a in range(1, M):
                 terms = []
                 for q in range(M):
@@ -575,6 +643,16 @@ def main():
     os.makedirs(os.path.join(here, "generated"), exist_ok=True)
     with open(os.path.join(here, "generated", "ader_scheme.h"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    counts = {}
+    for (tag, part), n in sorted(COUNT.items()):
+        counts.setdefault(tag, {})[part] = n
+    for tag in counts:
+        counts[tag]['total'] = sum(counts[tag].values())
+    import json
+    with open(os.path.join(here, "generated", "flop_counts.json"), "w") as fh:
+        json.dump({"unit": "flops per zone of k_predict (Euler, 5 variables)",
+                   "counts": counts}, fh, indent=1, sort_keys=True)
+        fh.write("\n")
 
 
 if __name__ == "__main__":

@@ -1,0 +1,66 @@
+"""Host (CPU) build of the HIP kernel source, for CPU tests of the kernel
+logic.  Test infrastructure: the product path never loads it."""
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+SRC = os.path.join(HERE, "ader_hostemu.hip")
+LIB = os.path.join(HERE, "libader_hostemu.so")
+DEPS = [SRC] + [os.path.join(ROOT, "paper_1006_2146_amd", "csrc", f)
+                for f in ("zone_ops.h", "euler_device.h", os.path.join("generated", "ader_scheme.h"))]
+
+_lib = None
+
+
+def build(force=False):
+    stale = force or not os.path.exists(LIB) or any(
+        os.path.getmtime(d) > os.path.getmtime(LIB) for d in DEPS)
+    if stale:
+        tmp = LIB + ".tmp"
+        subprocess.run(["hipcc", "-x", "hip", "--offload-host-only", "-O2", "-std=c++17",
+                        "-fPIC", "-shared", "-o", tmp, SRC], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(LIB)
+        D, I = ctypes.c_double, ctypes.c_int
+        DP = ctypes.POINTER(ctypes.c_double)
+        lib.hostemu_step.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, I, D]
+        lib.hostemu_step.restype = I
+        lib.hostemu_dt.argtypes = [DP, I, I, I, D, D, D, D, D]
+        lib.hostemu_dt.restype = D
+        _lib = lib
+    return _lib
+
+
+def _spacing(U, lengths):
+    nz, ny, nx = U.shape[1:]
+    return nx, ny, nz, lengths[0] / nx, lengths[1] / ny, lengths[2] / nz
+
+
+def step(U, dt, order, form="modal", riemann="hll", precision="fp64",
+         lengths=(1.0, 1.0, 1.0), gamma=1.4):
+    out = np.ascontiguousarray(U, dtype=np.float64).copy()
+    nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
+    load().hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
+                        dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
+                        1 if riemann == "linearized" else 0,
+                        0 if precision == "fp64" else 1, dt)
+    return out
+
+
+def compute_dt(U, cfl, lengths=(1.0, 1.0, 1.0), gamma=1.4):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    nx, ny, nz, dx, dy, dz = _spacing(U, lengths)
+    return load().hostemu_dt(U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
+                             dx, dy, dz, gamma, cfl)
