@@ -13,6 +13,10 @@ stays conservative, and theta = 1 (no change at all) wherever the polynomial
 is already positive there, so smooth solutions and every other pin are
 unaffected.
 
+For MHD the pressure includes B^2 / 8 pi, the facial check set holds every
+facial node (the edge averages use them all) and the pressure bound is
+located by bisection.
+
 Check sets.  Before the predictor the spatial modes are checked at the
 spatial positions of every predictor node (eq. 31/37/46, or A.1) and of every
 facial node that enters a face average; after the predictor all modes are
@@ -40,30 +44,50 @@ FACE_AVERAGE_NODES = {2: [1, 2, 3, 4], 3: [1, 6, 7, 8, 9, 10],
                       4: [1, 2, 5, 6, 9, 14, 15, 16, 17, 18, 19, 24]}
 
 
-def facial_check_points(order):
-    """Space-time points of the facial check set, six sides, fixed order."""
+def facial_check_points(order, all_nodes=False):
+    """Space-time points of the facial check set, six sides, fixed order
+    (every facial node when the edge averages of MHD use them all)."""
     pts = []
+    nodes = range(1, len(FACE_NODES[order]) + 1) if all_nodes else FACE_AVERAGE_NODES[order]
     for d in range(3):
         for s in (-1, 1):
-            for j in FACE_AVERAGE_NODES[order]:
+            for j in nodes:
                 t1, t2, tau = FACE_NODES[order][j - 1]
                 pts.append(zone_point(d, s, t1, t2, tau))
             pts.append(zone_point(d, s, 0.0, 0.0, 0.5))
     return [tuple(float(c) for c in p) for p in pts]
 
 
-def spatial_check_points(order, form):
+def spatial_check_points(order, form, all_nodes=False):
     """Distinct spatial positions of the predictor nodes and of the facial
     check points (tau set to 0)."""
     pts = list(NODES_NODAL_2 if form == 'nodal' else NODES_MODAL[order])
-    pts += facial_check_points(order)
+    pts += facial_check_points(order, all_nodes)
     return sorted(set((float(p[0]), float(p[1]), float(p[2]), 0.0) for p in pts))
 
 
 def _pressure_like(u, gamma):
-    """(gamma-1)(E - m^2 / 2 rho) of an Euler state."""
+    """(gamma-1)(E - m^2 / 2 rho [- B^2 / 8 pi]) of an Euler or MHD state."""
     m2 = u[1] ** 2 + u[2] ** 2 + u[3] ** 2
-    return (gamma - 1.0) * (u[4] - 0.5 * m2 / u[0])
+    mag = 0.0
+    if u.shape[0] == 8:
+        mag = (u[5] ** 2 + u[6] ** 2 + u[7] ** 2) / (8.0 * np.pi)
+    return (gamma - 1.0) * (u[4] - 0.5 * m2 / u[0] - mag)
+
+
+def _pressure_root_bisect(ubar, du, eps_p, gamma, iters=60):
+    """MHD: the pressure along ubar + t du is concave where rho > 0 (a cubic
+    after clearing rho); the largest t in [0, 1] with pressure >= eps_p and
+    rho > 0 up to it is found by bisection (lower end kept)."""
+    lo = np.zeros_like(ubar[0])
+    hi = np.ones_like(ubar[0])
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        v = ubar + mid * du
+        ok = (v[0] > 0.0) & (_pressure_like(v, gamma) >= eps_p)
+        lo = np.where(ok, mid, lo)
+        hi = np.where(ok, hi, mid)
+    return lo
 
 
 def _pressure_root(ubar, du, eps_p, gamma):
@@ -103,11 +127,11 @@ def scale_factor(ubar, values, gamma):
             t = np.where(u[0] < rho_eps, (ubar[0] - rho_eps) / (ubar[0] - u[0]), 1.0)
         theta = np.minimum(theta, t)
     theta_rho = theta
+    root = _pressure_root if ubar.shape[0] == 5 else _pressure_root_bisect
     for u in values:
         v = ubar + theta_rho * (u - ubar)
         p = _pressure_like(v, gamma)
-        t = np.where(p < p_eps,
-                     theta_rho * _pressure_root(ubar, v - ubar, p_eps, gamma), theta_rho)
+        t = np.where(p < p_eps, theta_rho * root(ubar, v - ubar, p_eps, gamma), theta_rho)
         theta = np.minimum(theta, t)
     return theta
 
@@ -115,7 +139,7 @@ def scale_factor(ubar, values, gamma):
 def limit_spatial(what, order, form, gamma):
     """Scale w_2..w_{L_S} so the spatial polynomial is positive at the
     spatial positions of the check set."""
-    pts = spatial_check_points(order, form)
+    pts = spatial_check_points(order, form, all_nodes=what.shape[1] == 8)
     vals = [evaluate(_as_spacetime(what, order), order, p) for p in pts]
     theta = scale_factor(what[0], vals, gamma)
     out = what.copy()
@@ -133,7 +157,7 @@ def _as_spacetime(what, order):
 def limit_spacetime(uhat, order, form, gamma):
     """Scale every mode but the zone average so the space-time polynomial is
     positive at the facial check points."""
-    vals = [evaluate(uhat, order, p) for p in facial_check_points(order)]
+    vals = [evaluate(uhat, order, p) for p in facial_check_points(order, uhat.shape[1] == 8)]
     theta = scale_factor(uhat[0], vals, gamma)
     out = uhat.copy()
     out[1:] = out[1:] * theta

@@ -23,15 +23,21 @@ import numpy as np
 from .physics import primitives, fast_speed
 
 
+def hll_speeds(ubl, ubr, axis, gamma):
+    """lambda_L, lambda_R from the two barycentre states, clipped at zero."""
+    _, vl, _, _ = primitives(ubl, gamma)
+    _, vr, _, _ = primitives(ubr, gamma)
+    cl = fast_speed(ubl, axis, gamma)
+    cr = fast_speed(ubr, axis, gamma)
+    lam_l = np.minimum(np.minimum(vl[axis] - cl, vr[axis] - cr), 0.0)
+    lam_r = np.maximum(np.maximum(vl[axis] + cl, vr[axis] + cr), 0.0)
+    return lam_l, lam_r
+
+
 def hll(pl, pr, axis, gamma):
     """Eq. (56) with the speeds read above; pl/pr are face-side packets
     (left = top side of the lower zone, right = bottom side of the upper)."""
-    _, vl, _, _ = primitives(pl['ub'], gamma)
-    _, vr, _, _ = primitives(pr['ub'], gamma)
-    cl = fast_speed(pl['ub'], axis, gamma)
-    cr = fast_speed(pr['ub'], axis, gamma)
-    lam_l = np.minimum(np.minimum(vl[axis] - cl, vr[axis] - cr), 0.0)
-    lam_r = np.maximum(np.maximum(vl[axis] + cl, vr[axis] + cr), 0.0)
+    lam_l, lam_r = hll_speeds(pl['ub'], pr['ub'], axis, gamma)
     return hll_combine(pl['f'], pr['f'], pl['u'], pr['u'], lam_l, lam_r)
 
 

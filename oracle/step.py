@@ -15,11 +15,12 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .faces import face_side_packet
+from .bweno import zone_b_mean, zone_b_modes
+from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
 from .positivity import limit_spatial, limit_spacetime
 from .predictor import predict_modal, predict_nodal_2
-from .riemann import hll, linearized_euler
+from .riemann import hll, hll_combine, hll_speeds, linearized_euler
 from .weno import reconstruct
 
 
@@ -38,8 +39,10 @@ class OracleConfig:
         nz, ny, nx = shape
         return (self.lengths[0] / nx, self.lengths[1] / ny, self.lengths[2] / nz)
 
-    def ghost(self):
+    def ghost(self, mhd=False):
         """Zones of neighbourhood one zone's update depends on, per side."""
+        if mhd:
+            return 2 * self.order + 1
         return {2: 2, 3: 3, 4: 4}[self.order]
 
 
@@ -48,8 +51,11 @@ def _nb(arr, axis, o):
 
 
 def compute_dt(U, cfg, cfl, B=None):
-    """dt = cfl / max_zones sum_d (|v_d| + c_d) / dx_d."""
+    """dt = cfl / max_zones sum_d (|v_d| + c_d) / dx_d (for MHD c_d is the
+    fast speed with the zone field taken as the mean of its face values)."""
     dx = cfg.spacing(U.shape[1:])
+    if B is not None:
+        U = np.concatenate([U, zone_b_mean(B)])
     rho, v, P, _ = primitives(U, cfg.gamma)
     rate = np.zeros_like(rho)
     for d in range(3):
@@ -57,11 +63,15 @@ def compute_dt(U, cfg, cfl, B=None):
     return cfl / rate.max()
 
 
-def predictor(U, dt, cfg):
-    """Spatial reconstruction followed by the space-time predictor, each
-    followed by the positivity safeguard."""
+def predictor(U, dt, cfg, B=None):
+    """Spatial reconstruction (for MHD the hydro variables plus the zone
+    field of Sec. III) followed by the space-time predictor, each followed by
+    the positivity safeguard."""
     dx = cfg.spacing(U.shape[1:])
-    what = limit_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma)
+    what = reconstruct(U, cfg.order)
+    if B is not None:
+        what = np.concatenate([what, zone_b_modes(B, cfg.order)], axis=1)
+    what = limit_spatial(what, cfg.order, cfg.form, cfg.gamma)
     if cfg.form == 'nodal':
         if cfg.order != 2:
             raise NotImplementedError('nodal formulation is built at order 2 only')
@@ -83,10 +93,74 @@ def face_fluxes(uhat, cfg):
     return out
 
 
+def _roll_packet(pk, d):
+    """The packet of the zone below along axis d."""
+    out = {}
+    for k, v in pk.items():
+        out[k] = {kk: _nb(vv, d, -1) for kk, vv in v.items()} if isinstance(v, dict) else _nb(v, d, -1)
+    return out
+
+
+def _levi(d, a, c):
+    return {(0, 1, 2): 1, (1, 2, 0): 1, (2, 0, 1): 1,
+            (0, 2, 1): -1, (2, 1, 0): -1, (1, 0, 2): -1}[(d, a, c)]
+
+
+def step_mhd(U, B, dt, cfg):
+    """Ideal MHD step: eq. (6) for the five hydro variables and the
+    constrained-transport update of eq. (8) for the face fields.
+
+    Edge electric fields (Sec. II.3, Sec. V): every face's HLL problem, with
+    its own barycentre speeds, is applied to the edge averages of eq. (57) on
+    each of its four edges; eq. (7) maps the induction flux of the component
+    along the edge's transverse axis to the edge field, E_c = -eps_{dac}
+    Flux_d(B_a), and each edge field is the mean of its four face values (the
+    reading of "averages of appropriate components").
+    """
+    if cfg.riemann != 'hll':
+        raise NotImplementedError('MHD is built with the HLL flux')
+    dx = cfg.spacing(U.shape[1:])
+    uhat = predictor(U, dt, cfg, B)
+    flows = []
+    E = [np.zeros_like(U[0]) for _ in range(3)]
+    for d in range(3):
+        plus = face_side_packet(uhat, cfg.order, d, +1, cfg.gamma, edges=True)
+        minus = face_side_packet(uhat, cfg.order, d, -1, cfg.gamma, edges=True)
+        left = _roll_packet(plus, d)
+        lam_l, lam_r = hll_speeds(left['ub'], minus['ub'], d, cfg.gamma)
+        flows.append(hll_combine(left['f'], minus['f'], left['u'], minus['u'], lam_l, lam_r)[:5])
+        tr = transverse_axes(d)
+        for which in (0, 1):
+            a = tr[which]
+            c = 3 - d - a
+            sgn = -_levi(d, a, c)
+            fe = {}
+            for sign in (-1, 1):
+                fe[sign] = hll_combine(left['f_edge'][(which, sign)][5 + a],
+                                       minus['f_edge'][(which, sign)][5 + a],
+                                       left['u_edge'][(which, sign)][5 + a],
+                                       minus['u_edge'][(which, sign)][5 + a], lam_l, lam_r)
+            # edge at x_a = lower edge of this zone's face: own face (side -)
+            # and the face of the zone below along a (side +)
+            E[c] = E[c] + sgn * (fe[-1] + _nb(fe[1], a, -1))
+    E = [0.25 * e for e in E]
+    Un = U.copy()
+    for d in range(3):
+        Un = Un - dt / dx[d] * (_nb(flows[d], d, 1) - flows[d])
+    # eq. (8), with B_d at the lower d-face and E_c at the lower edge of the zone
+    Ex, Ey, Ez = E
+    Bn = B.copy()
+    Bn[0] = B[0] - dt * ((_nb(Ez, 1, 1) - Ez) / dx[1] - (_nb(Ey, 2, 1) - Ey) / dx[2])
+    Bn[1] = B[1] - dt * ((_nb(Ex, 2, 1) - Ex) / dx[2] - (_nb(Ez, 0, 1) - Ez) / dx[0])
+    Bn[2] = B[2] - dt * ((_nb(Ey, 0, 1) - Ey) / dx[0] - (_nb(Ex, 1, 1) - Ex) / dx[1])
+    return Un, Bn
+
+
 def step(U, dt, cfg, B=None):
-    """Eq. (6): U^{n+1} = U^n - sum_d dt/dx_d (F_{i+1/2} - F_{i-1/2})."""
+    """Eq. (6): U^{n+1} = U^n - sum_d dt/dx_d (F_{i+1/2} - F_{i-1/2}).
+    With face fields B (MHD) returns (U^{n+1}, B^{n+1}), see step_mhd."""
     if B is not None:
-        raise NotImplementedError('MHD step is not part of this oracle module')
+        return step_mhd(U, B, dt, cfg)
     dx = cfg.spacing(U.shape[1:])
     uhat = predictor(U, dt, cfg)
     flows = face_fluxes(uhat, cfg)
@@ -99,8 +173,9 @@ def step(U, dt, cfg, B=None):
 def step_block(U, dt, cfg, origin, shape, B=None):
     """The updated state of the sub-box ``origin`` (z, y, x) of ``shape`` of a
     periodic mesh, computed from a periodically wrapped block with ghost
-    zones, so the oracle can check single zones of a large mesh."""
-    g = cfg.ghost()
+    zones, so the oracle can check single zones of a large mesh.  With face
+    fields B returns (U, B) of the sub-box."""
+    g = cfg.ghost(mhd=B is not None)
     nz, ny, nx = U.shape[1:]
     iz = (np.arange(origin[0] - g, origin[0] + shape[0] + g)) % nz
     iy = (np.arange(origin[1] - g, origin[1] + shape[1] + g)) % ny
@@ -109,6 +184,10 @@ def step_block(U, dt, cfg, origin, shape, B=None):
     # the block keeps the zone size of the full mesh
     sub = OracleConfig(order=cfg.order, form=cfg.form, riemann=cfg.riemann,
                        gamma=cfg.gamma, zone_size=cfg.spacing(U.shape[1:]))
+    cut = (slice(None), slice(g, g + shape[0]), slice(g, g + shape[1]), slice(g, g + shape[2]))
     with np.errstate(all='ignore'):
-        out = step(blk, dt, sub)
-    return out[:, g:g + shape[0], g:g + shape[1], g:g + shape[2]]
+        if B is None:
+            return step(blk, dt, sub)[cut]
+        bblk = B[:, iz][:, :, iy][:, :, :, ix]
+        Un, Bn = step(blk, dt, sub, bblk)
+    return Un[cut], Bn[cut]

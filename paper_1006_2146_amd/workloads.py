@@ -150,3 +150,155 @@ def blast(shape, p_in=10.0, p_out=0.1, radius=0.2, gamma=1.4):
     P = np.broadcast_to(P, tuple(shape))
     rho = np.ones(tuple(shape))
     return _euler_conserved(rho, np.zeros((3,) + tuple(shape)), P, gamma)
+
+
+# ---------------------------------------------------------------- MHD ------
+
+FOUR_PI = 4.0 * np.pi
+
+
+def _mhd_conserved(rho, v, P, Bbar, gamma):
+    """Hydro part (5 components) of the MHD state; E includes |Bbar|^2/8pi,
+    Bbar the zone field taken as the mean of its two face values."""
+    U = _euler_conserved(rho, v, P, gamma)
+    U[4] += (Bbar * Bbar).sum(axis=0) / (2.0 * FOUR_PI)
+    return U
+
+
+def face_mean(B):
+    """Zone field as the mean of the two face values of each component."""
+    return np.stack([0.5 * (B[d] + np.roll(B[d], -1, axis=2 - d)) for d in range(3)])
+
+
+def _edge_integrals(shape, modes):
+    """Line integrals of A = sum a sin(2 pi k.x + phi) along the lower zone
+    edges: L[c][k][j][i] = int A_c along the c-edge from the corner
+    (i dx, j dy, k dz), exactly."""
+    nz, ny, nx = shape
+    h = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    X = (np.arange(nx) / nx)[None, None, :]
+    Y = (np.arange(ny) / ny)[None, :, None]
+    Z = (np.arange(nz) / nz)[:, None, None]
+    L = np.zeros((3,) + tuple(shape))
+    for a, k, ph in modes:
+        base = 2.0 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph
+        for c in range(3):
+            if a[c] == 0.0:
+                continue
+            if k[c] == 0:
+                val = h[c] * np.sin(base)
+            else:
+                step = 2.0 * np.pi * k[c] * h[c]
+                val = (np.cos(base) - np.cos(base + step)) / (2.0 * np.pi * k[c])
+            L[c] += a[c] * np.broadcast_to(val, tuple(shape))
+    return L
+
+
+def curl_of_edges(L, shape):
+    """Face-averaged B = discrete curl (Stokes) of the edge integrals; the
+    discrete divergence vanishes identically."""
+    nz, ny, nx = shape
+    dx, dy, dz = 1.0 / nx, 1.0 / ny, 1.0 / nz
+    Lx, Ly, Lz = L
+    up = lambda f, axis: np.roll(f, -1, axis=2 - axis)  # noqa: E731
+    Bx = (up(Lz, 1) - Lz - up(Ly, 2) + Ly) / (dy * dz)
+    By = (up(Lx, 2) - Lx - up(Lz, 0) + Lz) / (dx * dz)
+    Bz = (up(Ly, 0) - Ly - up(Lx, 1) + Lx) / (dx * dy)
+    return np.stack([Bx, By, Bz])
+
+
+def mhd_random_field(shape, seed=2146, gamma=5.0 / 3.0, n_modes=16, kmax=4, b_rms=1.0,
+                     p0=0.1, drho=0.05):
+    """Ideal-MHD workload: face-centred B from the curl of a random vector
+    potential (``n_modes`` Fourier modes, integer k in [-kmax, kmax]^3,
+    normal random amplitudes, random phases), scaled to rms |B| = b_rms
+    (Gaussian units), so div B = 0 to rounding; rho = 1 + drho * delta with
+    delta a smooth random field (16 modes, max |delta| = 1); P = p0; v = 0.
+    Returns (U[5], B[3]) with B[d] on the lower d-faces."""
+    rng = np.random.default_rng(seed)
+    modes = [(rng.normal(size=3), k, ph) for k, ph in _random_modes(rng, n_modes, kmax)]
+    B = curl_of_edges(_edge_integrals(shape, modes), shape)
+    B *= b_rms / np.sqrt((B * B).sum(axis=0).mean())
+    nz, ny, nx = shape
+    X = _centres(nx)[None, None, :]
+    Y = _centres(ny)[None, :, None]
+    Z = _centres(nz)[:, None, None]
+    delta = np.zeros(tuple(shape))
+    for k, ph in _random_modes(rng, 16, kmax):
+        delta = delta + rng.normal() * np.sin(2.0 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+    delta /= np.abs(delta).max()
+    rho = 1.0 + drho * delta
+    v = np.zeros((3,) + tuple(shape))
+    P = np.full(tuple(shape), p0)
+    return _mhd_conserved(rho, v, P, face_mean(B), gamma), B
+
+
+def alfven_wave_x(shape, t=0.0, gamma=5.0 / 3.0, eps=0.1, p0=1.0, vx=0.0):
+    """Circularly polarised Alfven wave along x (an exact nonlinear solution
+    of ideal MHD): rho = 1, P = p0, B_x = sqrt(4 pi), v_y + i v_z =
+    eps e^{i phi}, B_y + i B_z = -eps sqrt(4 pi) e^{i phi},
+    phi = 2 pi (x - (vx + 1) t).  Zone and face averages are exact."""
+    nz, ny, nx = shape
+    b0 = np.sqrt(FOUR_PI)
+    h = 1.0 / nx
+    s = np.sin(np.pi * h) / (np.pi * h)
+    xc = _centres(nx)[None, None, :]
+    ph = 2.0 * np.pi * (xc - (vx + 1.0) * t)
+    shp = tuple(shape)
+    rho = np.ones(shp)
+    v = np.zeros((3,) + shp)
+    v[0] = vx
+    v[1] = np.broadcast_to(eps * s * np.cos(ph), shp)
+    v[2] = np.broadcast_to(eps * s * np.sin(ph), shp)
+    B = np.zeros((3,) + shp)
+    B[0] = b0
+    B[1] = np.broadcast_to(-eps * b0 * s * np.cos(ph), shp)   # y-faces: x-average over the zone
+    B[2] = np.broadcast_to(-eps * b0 * s * np.sin(ph), shp)
+    U = _euler_conserved(rho, v, np.full(shp, p0), gamma)
+    # exact zone average of rho v^2/2 + B^2/8pi (no sinc on the squares)
+    U[4] = p0 / (gamma - 1.0) + 0.5 * vx * vx + 0.5 * eps * eps + (b0 * b0 * (1.0 + eps * eps)) / (2.0 * FOUR_PI)
+    U[2] = rho * v[1]
+    U[3] = rho * v[2]
+    return U, B
+
+
+def alfven_wave_diagonal(shape, t=0.0, gamma=5.0 / 3.0, eps=0.1, p0=1.0):
+    """Torsional (circularly polarised) Alfven wave travelling along the cube
+    diagonal n = (1,1,1)/sqrt(3) on the periodic unit box (the Sec. VI.3
+    set-up with a wave vector k = 2 pi (1,1,1), periodic on the box):
+    rho = 1, P = p0, B = sqrt(4 pi) n + dB, v = dv,
+    dv = eps (cos phi e2 + sin phi e3), dB = -sqrt(4 pi) dv, phi = k.x - |k| t.
+    The face fields come from the exact edge integrals of the vector
+    potential of dB plus the uniform part, so div B = 0 to rounding; zone
+    averages are exact.  Returns (U[5], B[3])."""
+    nz, ny, nx = shape
+    shp = tuple(shape)
+    b0 = np.sqrt(FOUR_PI)
+    n = np.ones(3) / np.sqrt(3.0)
+    e2 = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    e3 = np.cross(n, e2)
+    kvec = 2.0 * np.pi * np.ones(3)
+    kabs = np.sqrt(kvec @ kvec)
+    ph0 = -kabs * t
+    alpha = eps * b0 / kabs
+    # A = alpha (cos phi e2 + sin phi e3) = alpha e2 sin(phi + pi/2) + alpha e3 sin(phi)
+    modes = [(alpha * e2, np.array([1, 1, 1]), ph0 + 0.5 * np.pi),
+             (alpha * e3, np.array([1, 1, 1]), ph0)]
+    B = curl_of_edges(_edge_integrals(shp, modes), shp)
+    for d in range(3):
+        B[d] += b0 * n[d]
+    X = _centres(nx)[None, None, :]
+    Y = _centres(ny)[None, :, None]
+    Z = _centres(nz)[:, None, None]
+    sinc = lambda h: np.sin(np.pi * h) / (np.pi * h)  # noqa: E731
+    s = sinc(1.0 / nx) * sinc(1.0 / ny) * sinc(1.0 / nz)
+    phc = 2.0 * np.pi * (X + Y + Z) + ph0
+    cos_avg = np.broadcast_to(s * np.cos(phc), shp)
+    sin_avg = np.broadcast_to(s * np.sin(phc), shp)
+    U = np.zeros((5,) + shp)
+    U[0] = 1.0
+    for d in range(3):
+        U[1 + d] = eps * (e2[d] * cos_avg + e3[d] * sin_avg)
+    # |v|^2 = eps^2 and |B|^2 = 4 pi (1 + eps^2) are uniform, so E is exact
+    U[4] = p0 / (gamma - 1.0) + 0.5 * eps * eps + b0 * b0 * (1.0 + eps * eps) / (2.0 * FOUR_PI)
+    return U, B
