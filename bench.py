@@ -40,15 +40,18 @@ def flop_counts():
         return json.load(fh)["counts"]
 
 
-def run_variant(ader, torch, U0, precision, riemann, steps, warmup):
+def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None):
     nz, ny, nx = SHAPE
     N = nx * ny * nz
     stream = torch.cuda.current_stream()
-    s = ader.Solver(SHAPE, order=3, riemann=riemann, precision=precision,
-                    stream=stream.cuda_stream)
+    mhd = B0 is not None
+    s = ader.Solver(SHAPE, order=order, riemann=riemann, precision=precision,
+                    stream=stream.cuda_stream, gamma=5.0 / 3.0 if mhd else 1.4,
+                    system=ader.ADER_MHD if mhd else ader.ADER_EULER)
     try:
         dU = torch.from_numpy(U0).to("cuda")            # resident state, 5 x N doubles
-        ader.ader_bind_device_state(s.ctx, dU.data_ptr())
+        dB = torch.from_numpy(B0).to("cuda") if mhd else None
+        ader.ader_bind_device_state(s.ctx, dU.data_ptr(), dB.data_ptr() if mhd else None)
         for _ in range(warmup):
             s.step_cfl(CFL)
         s.synchronize()
@@ -98,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="fp64-hll,fp64-lin,mixed-hll,mixed-lin")
+    ap.add_argument("--mhd-variants", default="fp64,mixed",
+                    help="order-4 MHD runs on the 128^3 random-field workload ('' for none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -123,6 +128,18 @@ def main():
         log("variant", name, "warmup", args.warmup, "steps", args.steps)
         variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup)
         log("variant", name, "%.3e zone-updates/s" % variants[name]["zone_updates_per_s"])
+
+    mhd_variants = {}
+    if args.mhd_variants:
+        log("building the MHD workload", SHAPE)
+        Um, Bm = workloads.mhd_random_field(SHAPE)
+        for name in args.mhd_variants.split(","):
+            prec = ader.ADER_FP64 if name == "fp64" else ader.ADER_MIXED
+            log("mhd variant", name)
+            mhd_variants["mhd-o4-" + name] = run_variant(ader, torch, Um, prec, ader.ADER_HLL,
+                                                         args.steps, args.warmup, order=4, B0=Bm)
+            log("mhd variant", name, "%.3e zone-updates/s"
+                % mhd_variants["mhd-o4-" + name]["zone_updates_per_s"])
 
     primary = "fp64-hll" if "fp64-hll" in variants else next(iter(variants))
     pv = variants[primary]
@@ -153,6 +170,8 @@ def main():
                    "zones": N, "cfl": CFL, "gamma": 1.4},
         "roofline": roofline,
         "variants": variants,
+        "mhd_variants": {"workload": "mhd-random-field-128^3, order 4 modal, HLL, CT, gamma 5/3",
+                         **mhd_variants},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -10,9 +10,13 @@
  *
  * Conventions
  *  - State layout: SoA double U[5][nz][ny][nx], x fastest; components
- *    (rho, rho vx, rho vy, rho vz, E) with E = rho v^2/2 + P/(gamma-1)
- *    (eq. 3 with B = 0), zone averages.  Zone (i,j,k) covers
- *    [i dx, (i+1) dx] x [j dy, (j+1) dy] x [k dz, (k+1) dz], dx = lx/nx, ...
+ *    (rho, rho vx, rho vy, rho vz, E), zone averages, with
+ *    E = rho v^2/2 + P/(gamma-1) (+ B^2/8pi for MHD, Gaussian units, eq. 3).
+ *    Zone (i,j,k) covers [i dx, (i+1) dx] x [j dy, (j+1) dy] x [k dz, (k+1) dz],
+ *    dx = lx/nx, ...  MHD adds the face-centred field B[3][nz][ny][nx]:
+ *    B[0][k][j][i] is B_x averaged over the x-face at x = i dx (the lower
+ *    x-face of zone (i,j,k)), B[1] and B[2] likewise on the lower y- and
+ *    z-faces; the step keeps its discrete divergence at round-off (eq. 8).
  *  - Every call is ordered on the HIP stream given to ader_create (NULL =
  *    the default stream).  Calls that return data to the host synchronise
  *    that stream; ader_step and ader_step_cfl do not.
@@ -43,7 +47,7 @@ enum {
   ADER_ESEQ = -6           /* call out of sequence (e.g. step before set_state) */
 };
 
-enum { ADER_EULER = 0 };                       /* eq. (3) with B = 0 */
+enum { ADER_EULER = 0, ADER_MHD = 1 };         /* eq. (3) with B = 0; ideal MHD */
 enum { ADER_HLL = 0, ADER_LINEARIZED = 1 };     /* eq. (17)/(56); Sec. II.3 */
 enum { ADER_MODAL = 0, ADER_NODAL = 1 };        /* Sec. IV; App. A (order 2) */
 enum { ADER_FP64 = 0, ADER_MIXED = 1 };         /* all-FP64, or FP32 bulk with FP64
@@ -69,26 +73,31 @@ int ader_set_gamma(ader_ctx* ctx, double gamma);
  * reconstruction is minmod-limited linear; at 3 and 4 it is centred WENO. */
 int ader_set_order(ader_ctx* ctx, int order, int form);
 
-/* ADER_HLL or ADER_LINEARIZED. */
+/* ADER_HLL or ADER_LINEARIZED (Euler only: ADER_EUNSUPPORTED for MHD). */
 int ader_set_riemann(ader_ctx* ctx, int riemann);
 
 /* ADER_FP64 or ADER_MIXED. */
 int ader_set_precision(ader_ctx* ctx, int precision);
 
-/* Copy a host state U[5][nz][ny][nx] (conserved zone averages) to the
- * device.  Returns ADER_ESTATE (and keeps the old state) if any zone has
- * rho <= 0, P <= 0 or a non-finite component. */
-int ader_set_state(ader_ctx* ctx, const double* U);
+/* Copy a host state U[5][nz][ny][nx] (conserved zone averages) and, for
+ * MHD, the face field B[3][nz][ny][nx] (NULL for Euler; ADER_EINVAL if the
+ * presence of B does not match the system) to the device.  Returns
+ * ADER_ESTATE (and keeps the old state) if any zone has rho <= 0, P <= 0 or
+ * a non-finite value (MHD pressure with the face-mean zone field). */
+int ader_set_state(ader_ctx* ctx, const double* U, const double* B);
 
-/* Use a caller-owned device buffer of 5*nx*ny*nz doubles as the state
- * (zero copy, e.g. a torch tensor's data pointer).  The library reads and
- * updates it in place on the context's stream. */
-int ader_bind_device_state(ader_ctx* ctx, void* dU);
+/* Use caller-owned device buffers of 5*nx*ny*nz (U) and, for MHD,
+ * 3*nx*ny*nz (B; NULL for Euler) doubles as the state (zero copy, e.g.
+ * torch tensors' data pointers).  The library reads and updates them in
+ * place on the context's stream. */
+int ader_bind_device_state(ader_ctx* ctx, void* dU, void* dB);
 
-/* Copy the state to the host array U[5][nz][ny][nx] (synchronises). */
-int ader_get_state(ader_ctx* ctx, double* U);
+/* Copy the state to the host arrays U[5][nz][ny][nx] and, if B is not NULL
+ * and the system is MHD, B[3][nz][ny][nx] (synchronises). */
+int ader_get_state(ader_ctx* ctx, double* U, double* B);
 
-/* dt = cfl / max over zones of sum_d (|v_d| + c) / dx_d (c = sound speed),
+/* dt = cfl / max over zones of sum_d (|v_d| + c_d) / dx_d (c_d the sound
+ * speed, or for MHD the fast speed along d with the face-mean zone field),
  * computed on the device into the context's dt slot.  If dt_out is not
  * NULL the value is copied back (synchronises) and ADER_ESTATE is returned
  * if a zone is unphysical.  cfl > 0. */

@@ -18,7 +18,7 @@ ADER_EDEVICE = -4
 ADER_ESTATE = -5
 ADER_ESEQ = -6
 
-ADER_EULER = 0
+ADER_EULER, ADER_MHD = 0, 1
 ADER_HLL, ADER_LINEARIZED = 0, 1
 ADER_MODAL, ADER_NODAL = 0, 1
 ADER_FP64, ADER_MIXED = 0, 1
@@ -67,9 +67,9 @@ def load():
         "ader_set_order": ([P, I, I], I),
         "ader_set_riemann": ([P, I], I),
         "ader_set_precision": ([P, I], I),
-        "ader_set_state": ([P, DP], I),
-        "ader_bind_device_state": ([P, P], I),
-        "ader_get_state": ([P, DP], I),
+        "ader_set_state": ([P, DP, DP], I),
+        "ader_bind_device_state": ([P, P, P], I),
+        "ader_get_state": ([P, DP, DP], I),
         "ader_compute_dt": ([P, D, DP], I),
         "ader_step": ([P, D], I),
         "ader_step_cfl": ([P, D], I),
@@ -130,20 +130,25 @@ def ader_set_precision(ctx, precision):
     _check(load().ader_set_precision(ctx, precision), "ader_set_precision")
 
 
-def ader_set_state(ctx, U):
+def ader_set_state(ctx, U, B=None):
     U = np.ascontiguousarray(U, dtype=np.float64)
-    _check(load().ader_set_state(ctx, _dptr(U)), "ader_set_state")
+    if B is not None:
+        B = np.ascontiguousarray(B, dtype=np.float64)
+    _check(load().ader_set_state(ctx, _dptr(U), None if B is None else _dptr(B)),
+           "ader_set_state")
 
 
-def ader_bind_device_state(ctx, device_ptr):
-    _check(load().ader_bind_device_state(ctx, ctypes.c_void_p(device_ptr)),
+def ader_bind_device_state(ctx, device_ptr, b_device_ptr=None):
+    _check(load().ader_bind_device_state(ctx, ctypes.c_void_p(device_ptr),
+                                         ctypes.c_void_p(b_device_ptr) if b_device_ptr else None),
            "ader_bind_device_state")
 
 
-def ader_get_state(ctx, shape):
+def ader_get_state(ctx, shape, with_b=False):
     U = np.empty(shape, dtype=np.float64)
-    _check(load().ader_get_state(ctx, _dptr(U)), "ader_get_state")
-    return U
+    B = np.empty((3,) + tuple(shape[1:]), dtype=np.float64) if with_b else None
+    _check(load().ader_get_state(ctx, _dptr(U), None if B is None else _dptr(B)), "ader_get_state")
+    return (U, B) if with_b else U
 
 
 def ader_compute_dt(ctx, cfl, want_host=True):
@@ -201,10 +206,11 @@ class Solver:
 
     def __init__(self, shape, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3,
                  form=ADER_MODAL, riemann=ADER_HLL, precision=ADER_FP64,
-                 device=0, stream=None):
+                 device=0, stream=None, system=ADER_EULER):
         nz, ny, nx = shape
         self.shape = (5, nz, ny, nx)
-        self.ctx = ader_create(nx, ny, nz, *lengths, device=device, stream=stream)
+        self.mhd = system == ADER_MHD
+        self.ctx = ader_create(nx, ny, nz, *lengths, system=system, device=device, stream=stream)
         try:
             ader_set_gamma(self.ctx, gamma)
             ader_set_order(self.ctx, order, form)
@@ -214,11 +220,12 @@ class Solver:
             self.close()
             raise
 
-    def set_state(self, U):
-        ader_set_state(self.ctx, U)
+    def set_state(self, U, B=None):
+        ader_set_state(self.ctx, U, B)
 
     def get_state(self):
-        return ader_get_state(self.ctx, self.shape)
+        """U (Euler) or (U, B) (MHD)."""
+        return ader_get_state(self.ctx, self.shape, with_b=self.mhd)
 
     def compute_dt(self, cfl):
         return ader_compute_dt(self.ctx, cfl)

@@ -8,18 +8,68 @@
 
 namespace ader {
 
-template <class T, int M, int AXIS>
+template <class T, int M, int AXIS, int NVAR>
 __global__ void __launch_bounds__(256) k_weno_sweep(const double* __restrict__ U,
                                                     T* __restrict__ W, Grid g) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) weno_sweep_zone<T, M, AXIS>(U, W, g, n);
+  if (n < g.N) weno_sweep_zone<T, M, AXIS, NVAR>(U, W, g, n);
 }
 
-template <class T>
+template <class T, int NVAR>
 __global__ void __launch_bounds__(256) k_minmod(const double* __restrict__ U,
                                                 T* __restrict__ W, Grid g) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) minmod_zone<T>(U, W, g, n);
+  if (n < g.N) minmod_zone<T, NVAR>(U, W, g, n);
+}
+
+template <class T, int M>
+__global__ void __launch_bounds__(256) k_bface(const double* __restrict__ B, double* __restrict__ B0,
+                                               T* __restrict__ BN, Grid g) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < g.N) bface_zone<T, M>(B, B0, BN, g, n);
+}
+
+template <class T, int ORDER, int FORM>
+__global__ void __launch_bounds__(128) k_predict_mhd(const double* __restrict__ U,
+                                                     const T* __restrict__ W,
+                                                     const double* __restrict__ B0,
+                                                     const T* __restrict__ WB,
+                                                     const T* __restrict__ BN, T* __restrict__ PK,
+                                                     Grid g, const double* __restrict__ dt,
+                                                     double inv_dx, double inv_dy, double inv_dz,
+                                                     double gam) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < g.N)
+    predict_zone_mhd<T, ORDER, FORM>(U, W, B0, WB, BN, PK, g, *dt, inv_dx, inv_dy, inv_dz, gam, n);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_face_flux_mhd(const T* __restrict__ PK, T* __restrict__ F,
+                                                       T* __restrict__ FE, Grid g, double gam) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < g.N) face_flux_zone_mhd<T>(PK, F, FE, g, gam, n);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_edge_e(const T* __restrict__ FE, double* __restrict__ E,
+                                                Grid g) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < g.N) edge_e_zone<T>(FE, E, g, n);
+}
+
+// eq. (6) for the hydro variables and eq. (8) for the face fields
+template <class T>
+__global__ void __launch_bounds__(256) k_update_mhd(double* __restrict__ U, double* __restrict__ B,
+                                                    const T* __restrict__ F,
+                                                    const double* __restrict__ E, Grid g,
+                                                    const double* __restrict__ dt, double dx,
+                                                    double dy, double dz) {
+  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < g.N) {
+    const double h = *dt;
+    update_zone<T>(U, F, g, h, dx, dy, dz, n);
+    ct_zone(B, E, g, h, dx, dy, dz, n);
+  }
 }
 
 template <class T, int ORDER, int FORM>
@@ -54,7 +104,9 @@ __device__ __forceinline__ double wave_max(double x) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) k_dt_partial(const double* __restrict__ U, Grid g, double gam,
+// B == nullptr: Euler; otherwise MHD with the face fields B
+__global__ void __launch_bounds__(256) k_dt_partial(const double* __restrict__ U,
+                                                    const double* __restrict__ B, Grid g, double gam,
                                                     double dx, double dy, double dz,
                                                     double* __restrict__ partial,
                                                     int* __restrict__ bad) {
@@ -63,7 +115,9 @@ __global__ void __launch_bounds__(256) k_dt_partial(const double* __restrict__ U
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double rate = 0.0;
   int isbad = 0;
-  if (n < g.N) rate = dt_rate_zone(U, g, gam, dx, dy, dz, n, isbad);
+  if (n < g.N)
+    rate = B ? dt_rate_zone_mhd(U, B, g, gam, dx, dy, dz, n, isbad)
+             : dt_rate_zone(U, g, gam, dx, dy, dz, n, isbad);
   rate = wave_max(rate);
   int wb = isbad;
 #pragma unroll

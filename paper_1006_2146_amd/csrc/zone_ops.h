@@ -18,7 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "euler_device.h"
+#include "physics_device.h"
 #include "generated/ader_scheme.h"
 
 namespace ader {
@@ -115,7 +115,10 @@ __host__ __device__ __forceinline__ void weno1d(const T (&d)[2 * M - 1], T (&m)[
 // x: the zone averages give the x-moments (a,0,0);  y: each field (a,0,0),
 // a <= M-2, gives (a,b,0);  z: each field (a,b,0), a+b <= M-2, gives (a,b,c);
 // moments of total degree > M-1 are not formed.
-template <class T, int M, int AXIS>
+// NVAR fields; their zone averages (mode 0) are the double array U[NVAR][N]
+// (the conserved variables, or for MHD the zone field b_0) and their modes
+// 2..L_S go to W[L_S-1][NVAR][N].
+template <class T, int M, int AXIS, int NVAR = 5>
 __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restrict__ U,
                                                          T* __restrict__ W, const Grid& g,
                                                          long long n) {
@@ -142,12 +145,12 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
       if (nout == 0) continue;
       const int src = spatial_mode(a, b, 0);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
+      for (int v = 0; v < NVAR; ++v) {
         T d[2 * M - 1];
 #pragma unroll
         for (int q = 0; q < 2 * R + 1; ++q)
           d[q] = src == 0 ? T(U[(long long)v * g.N + idx[q]])
-                          : W[((long long)(src - 1) * 5 + v) * g.N + idx[q]];
+                          : W[((long long)(src - 1) * NVAR + v) * g.N + idx[q]];
         T mo[M];
         weno1d<T, M>(d, mo);
 #pragma unroll
@@ -157,7 +160,7 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
           if constexpr (AXIS == 0) dst = spatial_mode(c, 0, 0);
           else if constexpr (AXIS == 1) dst = spatial_mode(a, c, 0);
           else dst = spatial_mode(a, b, c);
-          W[((long long)(dst - 1) * 5 + v) * g.N + n] = mo[c];
+          W[((long long)(dst - 1) * NVAR + v) * g.N + n] = mo[c];
         }
       }
     }
@@ -166,7 +169,7 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
 
 // Second order: per axis the minmod of the two one-sided differences
 // (the limiter of the second-order workload).
-template <class T>
+template <class T, int NVAR = 5>
 __host__ __device__ __forceinline__ void minmod_zone(const double* __restrict__ U,
                                                      T* __restrict__ W, const Grid& g,
                                                      long long n) {
@@ -178,7 +181,7 @@ __host__ __device__ __forceinline__ void minmod_zone(const double* __restrict__ 
       {zone_of(i, wrap(j - 1, g.ny), k, g), zone_of(i, wrap(j + 1, g.ny), k, g)},
       {zone_of(i, j, wrap(k - 1, g.nz), g), zone_of(i, j, wrap(k + 1, g.nz), g)}};
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < NVAR; ++v) {
     const double c = U[(long long)v * g.N + n];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -186,31 +189,38 @@ __host__ __device__ __forceinline__ void minmod_zone(const double* __restrict__ 
       const double bwd = c - U[(long long)v * g.N + nb[ax][0]];
       double s = 0.0;
       if (fwd * bwd > 0.0) s = fabs(fwd) < fabs(bwd) ? fwd : bwd;
-      W[((long long)ax * 5 + v) * g.N + n] = T(s);
+      W[((long long)ax * NVAR + v) * g.N + n] = T(s);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Positivity safeguard (the reading that keeps strong blasts physical: one
-// Zhang-Shu scaling factor per zone polynomial, computed in double).
+// Zhang-Shu scaling factor per zone polynomial, computed in double).  NV = 5
+// (Euler) or 8 (MHD: the pressure carries B^2/8pi).
 // ---------------------------------------------------------------------------
-template <class T>
+template <int NV>
+__host__ __device__ __forceinline__ double pressure_of(const double (&u)[NV], double gam) {
+  double e = u[4] - 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+  if constexpr (NV == 8) e -= (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * (1.0 / (8.0 * 3.14159265358979323846));
+  return (gam - 1.0) * e;
+}
+
+template <class T, int NV>
 struct PosTheta {
-  double ub[5];
+  double ub[NV];
   double eps_rho, eps_p, gam, theta;
 
-  __host__ __device__ PosTheta(const T (&w0)[5], double g) : gam(g), theta(1.0) {
+  __host__ __device__ PosTheta(const T (&w0)[NV], double g) : gam(g), theta(1.0) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) ub[v] = double(w0[v]);
+    for (int v = 0; v < NV; ++v) ub[v] = double(w0[v]);
     eps_rho = 1.0e-8 * ub[0];
-    const double pb = (gam - 1.0) * (ub[4] - 0.5 * (ub[1] * ub[1] + ub[2] * ub[2] + ub[3] * ub[3]) / ub[0]);
-    eps_p = 1.0e-8 * pb;
+    eps_p = 1.0e-8 * pressure_of<NV>(ub, gam);
   }
 
-  // smallest t in (0, 1] where the pressure along ub + t (u - ub) falls to
+  // Euler: smallest t in (0, 1] where the pressure along ub + t du falls to
   // eps_p: root of rho(t)(E(t) - e) - |m(t)|^2/2 = a t^2 + b t + c
-  __host__ __device__ double pressure_root(const double (&du)[5]) const {
+  __host__ __device__ double pressure_root(const double (&du)[NV]) const {
     const double e = eps_p / (gam - 1.0);
     const double a = du[0] * du[4] - 0.5 * (du[1] * du[1] + du[2] * du[2] + du[3] * du[3]);
     const double b = ub[0] * du[4] + du[0] * (ub[4] - e) - (ub[1] * du[1] + ub[2] * du[2] + ub[3] * du[3]);
@@ -229,22 +239,39 @@ struct PosTheta {
     return fmin(fmax(t, 0.0), 1.0);
   }
 
+  // MHD: the pressure is concave along the line where rho > 0; its bound is
+  // located by bisection, keeping the admissible end
+  __host__ __device__ double pressure_bisect(const double (&du)[NV]) const {
+    double lo = 0.0, hi = 1.0;
+#pragma unroll 1
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      double v[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) v[q] = ub[q] + mid * du[q];
+      const bool ok = v[0] > 0.0 && pressure_of<NV>(v, gam) >= eps_p;
+      if (ok) lo = mid; else hi = mid;
+    }
+    return lo;
+  }
+
   // theta = min over points of the largest admissible scale along the line
   // from the zone average to the point: the density bound (linear) and the
-  // first crossing of the pressure bound (root above); the same value as
-  // scaling for density first and then for pressure.
-  __host__ __device__ void operator()(const T (&uT)[5]) {
-    double u[5];
+  // first crossing of the pressure bound; the same value as scaling for
+  // density first and then for pressure.
+  __host__ __device__ void operator()(const T (&uT)[NV]) {
+    double u[NV];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) u[v] = double(uT[v]);
-    const double p = (gam - 1.0) * (u[4] - 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0]);
+    for (int v = 0; v < NV; ++v) u[v] = double(uT[v]);
+    const double p = pressure_of<NV>(u, gam);
     if (u[0] < eps_rho || p < eps_p) {
       double t = 1.0;
       if (u[0] < eps_rho) t = (ub[0] - eps_rho) / (ub[0] - u[0]);
-      double du[5];
+      double du[NV];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) du[v] = u[v] - ub[v];
-      t = fmin(t, pressure_root(du));
+      for (int v = 0; v < NV; ++v) du[v] = u[v] - ub[v];
+      if constexpr (NV == 5) t = fmin(t, pressure_root(du));
+      else t = fmin(t, pressure_bisect(du));
       theta = fmin(theta, t);
     }
   }
@@ -253,38 +280,43 @@ struct PosTheta {
 // Cheap scan of the same points: flags a zone whose polynomial comes near
 // the bounds (within a factor 2, so that rounding in T never hides a
 // violation); only such zones run the exact pass in double.
-template <class T>
+template <class T, int NV>
 struct PosScan {
   T eps_rho, eps_e;
   int near = 0;
-  __host__ __device__ PosScan(const T (&w0)[5], T gam) {
-    // internal energy per volume of the zone average, and twice-relaxed bounds
-    const T rhoe = w0[4] - T(0.5) * (w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]) / w0[0];
+  __host__ __device__ static T rho_internal(const T (&u)[NV]) {
+    // rho times the internal energy per volume, free of divisions
+    T r = u[0] * u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]);
+    if constexpr (NV == 8)
+      r -= u[0] * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * T(1.0 / (8.0 * 3.14159265358979323846));
+    return r;
+  }
+  __host__ __device__ PosScan(const T (&w0)[NV], T gam) {
     eps_rho = T(2.0e-8) * w0[0];
-    eps_e = T(2.0e-8) * rhoe;
+    eps_e = T(2.0e-8) * rho_internal(w0) / w0[0];
     (void)gam;
   }
-  // rho >= eps_rho and rho E - |m|^2/2 >= rho eps_e, free of divisions
-  __host__ __device__ void operator()(const T (&u)[5]) {
-    const T m2 = u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
-    const int ok = int(u[0] >= eps_rho) & int(u[0] * u[4] - T(0.5) * m2 >= u[0] * eps_e);
+  // rho >= eps_rho and rho (internal energy) >= rho eps_e
+  __host__ __device__ void operator()(const T (&u)[NV]) {
+    const int ok = int(u[0] >= eps_rho) & int(rho_internal(u) >= u[0] * eps_e);
     near |= ok ^ 1;
   }
 };
 
 // Exact pass for a flagged zone: a runtime loop over the check points with
 // the basis values from the scheme's tables, so the rare path stays small.
-template <class S, class T>
-__host__ __device__ double theta_spatial(const T (&w)[S::LS][5], double gam) {
-  PosTheta<T> acc(w[0], gam);
+template <int NP, int LS, class T, int NV>
+__host__ __device__ double theta_spatial_tab(const T (&w)[LS][NV], const double (&phi)[NP][LS],
+                                             double gam) {
+  PosTheta<T, NV> acc(w[0], gam);
 #pragma unroll 1
-  for (int p = 0; p < S::NSPATIAL; ++p) {
-    T u[5];
+  for (int p = 0; p < NP; ++p) {
+    T u[NV];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < NV; ++v) {
       T s = T(0);
 #pragma unroll
-      for (int m = 0; m < S::LS; ++m) s += T(S::spatial_phi[p][m]) * w[m][v];
+      for (int m = 0; m < LS; ++m) s += T(phi[p][m]) * w[m][v];
       u[v] = s;
     }
     acc(u);
@@ -292,19 +324,20 @@ __host__ __device__ double theta_spatial(const T (&w)[S::LS][5], double gam) {
   return acc.theta;
 }
 
-template <class S, class T>
-__host__ __device__ double theta_facial(const T (&w)[S::LS][5], const T (&e)[S::NE][5], double gam) {
-  PosTheta<T> acc(w[0], gam);
+template <int NP, int LS, int NE, class T, int NV>
+__host__ __device__ double theta_facial_tab(const T (&w)[LS][NV], const T (&e)[NE][NV],
+                                            const double (&phi)[NP][LS + NE], double gam) {
+  PosTheta<T, NV> acc(w[0], gam);
 #pragma unroll 1
-  for (int p = 0; p < S::NFACIAL; ++p) {
-    T u[5];
+  for (int p = 0; p < NP; ++p) {
+    T u[NV];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < NV; ++v) {
       T s = T(0);
 #pragma unroll
-      for (int m = 0; m < S::LS; ++m) s += T(S::facial_phi[p][m]) * w[m][v];
+      for (int m = 0; m < LS; ++m) s += T(phi[p][m]) * w[m][v];
 #pragma unroll
-      for (int m = 0; m < S::NE; ++m) s += T(S::facial_phi[p][S::LS + m]) * e[m][v];
+      for (int m = 0; m < NE; ++m) s += T(phi[p][LS + m]) * e[m][v];
       u[v] = s;
     }
     acc(u);
@@ -312,12 +345,12 @@ __host__ __device__ double theta_facial(const T (&w)[S::LS][5], const T (&e)[S::
   return acc.theta;
 }
 
-template <int ORDER, int FORM, class T>
+template <int ORDER, int FORM, class T, int NV = 5>
 struct SchemeOf;
-template <class T> struct SchemeOf<2, 0, T> { using type = ader_gen::SchemeM2<T, 5>; };
-template <class T> struct SchemeOf<2, 1, T> { using type = ader_gen::SchemeN2<T, 5>; };
-template <class T> struct SchemeOf<3, 0, T> { using type = ader_gen::SchemeM3<T, 5>; };
-template <class T> struct SchemeOf<4, 0, T> { using type = ader_gen::SchemeM4<T, 5>; };
+template <class T, int NV> struct SchemeOf<2, 0, T, NV> { using type = ader_gen::SchemeM2<T, NV>; };
+template <class T, int NV> struct SchemeOf<2, 1, T, NV> { using type = ader_gen::SchemeN2<T, NV>; };
+template <class T, int NV> struct SchemeOf<3, 0, T, NV> { using type = ader_gen::SchemeM3<T, NV>; };
+template <class T, int NV> struct SchemeOf<4, 0, T, NV> { using type = ader_gen::SchemeM4<T, NV>; };
 
 template <class S, class T, int SIDE>
 __host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], const T (&e)[S::NE][5], T gam,
@@ -351,9 +384,9 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
     for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.N + n];
 
   {
-    PosScan<T> scan(w[0], T(gam));
+    PosScan<T, 5> scan(w[0], T(gam));
     S::spatial_points(w, scan);
-    const double theta = scan.near ? theta_spatial<S, T>(w, gam) : 1.0;
+    const double theta = scan.near ? theta_spatial_tab(w, S::spatial_phi, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -365,9 +398,9 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   T e[NE][5];
   S::template predict<Euler<T>>(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), T(gam));
   {
-    PosScan<T> scan(w[0], T(gam));
+    PosScan<T, 5> scan(w[0], T(gam));
     S::facial_points(w, e, scan);
-    const double theta = scan.near ? theta_facial<S, T>(w, e, gam) : 1.0;
+    const double theta = scan.near ? theta_facial_tab(w, e, S::facial_phi, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -526,6 +559,304 @@ __host__ __device__ __forceinline__ double dt_rate_zone(const double* __restrict
   }
   const double c = sqrt(gam * p / r);
   return (fabs(m[0] / r) + c) / dx + (fabs(m[1] / r) + c) / dy + (fabs(m[2] / r) + c) / dz;
+}
+
+// ---------------------------------------------------------------------------
+// Ideal MHD.  Face layout: B[d][n] is B_d on the lower d-face of zone n; the
+// zone field b_0 is B0[d][n] (double), the normal moments of Sec. III are
+// BN[a-1][d][n], the modes of the remaining reconstruction WB[m-1][d][n].
+// ---------------------------------------------------------------------------
+
+__host__ __device__ __forceinline__ long long shifted(const Grid& g, int i, int j, int k, int axis,
+                                                      int o) {
+  if (axis == 0) return zone_of(wrap(i + o, g.nx), j, k, g);
+  if (axis == 1) return zone_of(i, wrap(j + o, g.ny), k, g);
+  return zone_of(i, j, wrap(k + o, g.nz), g);
+}
+
+// Sec. III: each component's zone average and normal moments from its own
+// faces.  f[q] is the face at offset q - 1/2 from the zone centre (q = -2..3).
+// Order 2: mean and difference; order 3: stencils of eq. (22)-(23),
+// smoothness eq. (24), equal linear weights; order 4: eq. (26)-(28),
+// smoothness eq. (29), linear weights (1, 100, 1).
+template <class T, int M>
+__host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B,
+                                                    double* __restrict__ B0, T* __restrict__ BN,
+                                                    const Grid& g, long long n) {
+  constexpr double kEps = 1.0e-12;
+  const int i = (int)(n % g.nx);
+  const int j = (int)((n / g.nx) % g.ny);
+  const int k = (int)(n / ((long long)g.nx * g.ny));
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double f[6];  // offsets -2 .. 3
+#pragma unroll
+    for (int q = -2; q <= 3; ++q) {
+      const bool need = (M == 2 && q >= 0 && q <= 1) || (M == 3 && q >= -1 && q <= 2) || M == 4;
+      f[q + 2] = need ? B[(long long)d * g.N + shifted(g, i, j, k, d, q)] : 0.0;
+    }
+    const double fm25 = f[0], fm15 = f[1], fm05 = f[2], fp05 = f[3], fp15 = f[4], fp25 = f[5];
+    double b[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (M == 2) {
+      b[0] = 0.5 * (fm05 + fp05);
+      b[1] = fp05 - fm05;
+    } else if constexpr (M == 3) {
+      const double s1[3] = {(8.0 * fm05 - fm15 + 5.0 * fp05) / 12.0, fp05 - fm05,
+                            (fp05 + fm15 - 2.0 * fm05) / 2.0};
+      const double s2[3] = {(8.0 * fp05 - fp15 + 5.0 * fm05) / 12.0, fp05 - fm05,
+                            (fm05 + fp15 - 2.0 * fp05) / 2.0};
+      const double i1 = s1[1] * s1[1] + 13.0 * s1[2] * s1[2] / 3.0;
+      const double i2 = s2[1] * s2[1] + 13.0 * s2[2] * s2[2] / 3.0;
+      const double a1 = 1.0 / ((kEps + i1) * (kEps + i1)), a2 = 1.0 / ((kEps + i2) * (kEps + i2));
+      const double tot = a1 + a2;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) b[q] = (a1 * s1[q] + a2 * s2[q]) / tot;
+    } else {
+      const double s[3][4] = {
+          {(9.0 * fp05 + 19.0 * fm05 - 5.0 * fm15 + fm25) / 24.0,
+           (59.0 * fp05 - 57.0 * fm05 - 3.0 * fm15 + fm25) / 60.0,
+           (3.0 * fp05 - 7.0 * fm05 + 5.0 * fm15 - fm25) / 4.0,
+           (fp05 - 3.0 * fm05 + 3.0 * fm15 - fm25) / 6.0},
+          {(-fp15 + 13.0 * fp05 + 13.0 * fm05 - fm15) / 24.0,
+           (-fp15 + 63.0 * fp05 - 63.0 * fm05 + fm15) / 60.0,
+           (fp15 - fp05 - fm05 + fm15) / 4.0,
+           (fp15 - 3.0 * fp05 + 3.0 * fm05 - fm15) / 6.0},
+          {(fp25 - 5.0 * fp15 + 19.0 * fp05 + 9.0 * fm05) / 24.0,
+           (-fp25 + 3.0 * fp15 + 57.0 * fp05 - 59.0 * fm05) / 60.0,
+           (-fp25 + 5.0 * fp15 - 7.0 * fp05 + 3.0 * fm05) / 4.0,
+           (fp25 - 3.0 * fp15 + 3.0 * fp05 - fm05) / 6.0}};
+      double a[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double t = s[q][1] + 0.1 * s[q][3];
+        const double is = t * t + 13.0 * s[q][2] * s[q][2] / 3.0 + 781.0 * s[q][3] * s[q][3] / 20.0;
+        a[q] = (q == 1 ? 100.0 : 1.0) / ((kEps + is) * (kEps + is));
+      }
+      const double tot = a[0] + a[1] + a[2];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = (a[0] * s[0][q] + a[1] * s[1][q] + a[2] * s[2][q]) / tot;
+    }
+    B0[(long long)d * g.N + n] = b[0];
+#pragma unroll
+    for (int a = 1; a < M; ++a) BN[((long long)(a - 1) * 3 + d) * g.N + n] = T(b[a]);
+  }
+}
+
+template <class S, class T, int SIDE>
+__host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], const T (&e)[S::NE][8],
+                                                        T gam, T* __restrict__ PK, long long N,
+                                                        long long n) {
+  T ub[8], ua[8], fa[8], ue[4], fe[4];
+  S::template side_edges<SIDE, Mhd<T>>(w, e, gam, ub, ua, fa, ue, fe);
+  T* base = PK + (long long)SIDE * 32 * N + n;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    base[(long long)v * N] = ub[v];
+    base[(long long)(8 + v) * N] = ua[v];
+    base[(long long)(16 + v) * N] = fa[v];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    base[(long long)(24 + q) * N] = ue[q];
+    base[(long long)(28 + q) * N] = fe[q];
+  }
+}
+
+// Per zone (MHD): hydro modes from U/W, field modes from B0/WB with the
+// Sec. III normal moments BN on the pure-normal slots, positivity scaling,
+// predictor, positivity scaling and the six side packets of 32 values
+// (barycentre state, face averages of u and F, edge averages of u and F of
+// the field component along each edge's transverse axis).
+template <class T, int ORDER, int FORM>
+__host__ __device__ __forceinline__ void predict_zone_mhd(
+    const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
+    const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
+    double h, double inv_dx, double inv_dy, double inv_dz, double gam, long long n) {
+  using S = typename SchemeOf<ORDER, FORM, T, 8>::type;
+  constexpr int LS = S::LS, NE = S::NE;
+  T w[LS][8];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[0][v] = T(U[(long long)v * g.N + n]);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[0][5 + c] = T(B0[(long long)c * g.N + n]);
+#pragma unroll
+  for (int m = 1; m < LS; ++m) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.N + n];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[m][5 + c] = WB[((long long)(m - 1) * 3 + c) * g.N + n];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 1; a < ORDER; ++a) {
+      const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
+      w[m][5 + c] = BN[((long long)(a - 1) * 3 + c) * g.N + n];
+    }
+  {
+    PosScan<T, 8> scan(w[0], T(gam));
+    S::spatial_points_all(w, scan);
+    const double theta = scan.near ? theta_spatial_tab(w, S::spatial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) w[m][v] *= th;
+    }
+  }
+  T e[NE][8];
+  S::template predict<Mhd<T>>(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), T(gam));
+  {
+    PosScan<T, 8> scan(w[0], T(gam));
+    S::facial_points_all(w, e, scan);
+    const double theta = scan.near ? theta_facial_tab(w, e, S::facial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) w[m][v] *= th;
+#pragma unroll
+      for (int m = 0; m < NE; ++m)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) e[m][v] *= th;
+    }
+  }
+  const T tg = T(gam);
+  store_side_mhd<S, T, 0>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 1>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 2>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 3>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 4>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 5>(w, e, tg, PK, g.N, n);
+}
+
+// HLL at the lower AXIS-face of zone n (MHD): the five hydro fluxes, and the
+// same HLL combination, with this face's speeds, of the edge averages on its
+// four edges (eq. 56-57).
+template <class T, int AXIS>
+__host__ __device__ __forceinline__ void face_flux_axis_mhd(const T* __restrict__ PK,
+                                                            T* __restrict__ F, T* __restrict__ FE,
+                                                            const Grid& g, long long n,
+                                                            long long nl, T gam) {
+  constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
+  const T* L = PK + (long long)SL * 32 * g.N + nl;
+  const T* R = PK + (long long)SR * 32 * g.N + n;
+  T ubl[8], ubr[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    ubl[v] = L[(long long)v * g.N];
+    ubr[v] = R[(long long)v * g.N];
+  }
+  const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
+  const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, gam);
+  const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, gam);
+  const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
+  const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
+  const T inv = T(1) / (lam_r - lam_l);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T ul = L[(long long)(8 + v) * g.N], ur = R[(long long)(8 + v) * g.N];
+    const T fl = L[(long long)(16 + v) * g.N], fr = R[(long long)(16 + v) * g.N];
+    F[((long long)AXIS * 5 + v) * g.N + n] = (lam_r * fl - lam_l * fr + lam_r * lam_l * (ur - ul)) * inv;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const T ul = L[(long long)(24 + q) * g.N], ur = R[(long long)(24 + q) * g.N];
+    const T fl = L[(long long)(28 + q) * g.N], fr = R[(long long)(28 + q) * g.N];
+    FE[((long long)AXIS * 4 + q) * g.N + n] = (lam_r * fl - lam_l * fr + lam_r * lam_l * (ur - ul)) * inv;
+  }
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void face_flux_zone_mhd(const T* __restrict__ PK, T* __restrict__ F,
+                                                            T* __restrict__ FE, const Grid& g,
+                                                            double gam, long long n) {
+  const int i = (int)(n % g.nx);
+  const int j = (int)((n / g.nx) % g.ny);
+  const int k = (int)(n / ((long long)g.nx * g.ny));
+  face_flux_axis_mhd<T, 0>(PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), T(gam));
+  face_flux_axis_mhd<T, 1>(PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), T(gam));
+  face_flux_axis_mhd<T, 2>(PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), T(gam));
+}
+
+// Edge fields at the three lower edges of zone n: E_c is the mean of the
+// four face values -eps_{dac} Flux_d(B_a) of eq. (7) on the faces that abut
+// the edge (edge q = 2 w + (side > 0) of a face, w the transverse slot of a).
+template <class T>
+__host__ __device__ __forceinline__ void edge_e_zone(const T* __restrict__ FE, double* __restrict__ E,
+                                                     const Grid& g, long long n) {
+  const int i = (int)(n % g.nx);
+  const int j = (int)((n / g.nx) % g.ny);
+  const int k = (int)(n / ((long long)g.nx * g.ny));
+  const long long mx = zone_of(wrap(i - 1, g.nx), j, k, g);
+  const long long my = zone_of(i, wrap(j - 1, g.ny), k, g);
+  const long long mz = zone_of(i, j, wrap(k - 1, g.nz), g);
+  auto fe = [&](int face, int q, long long zone) { return double(FE[((long long)face * 4 + q) * g.N + zone]); };
+  // E_x: y-faces (component B_z, sign -1), z-faces (component B_y, sign +1)
+  double ex = 0.0;
+  ex = ex - (fe(1, 2, n) + fe(1, 3, mz));
+  ex = ex + (fe(2, 2, n) + fe(2, 3, my));
+  // E_y: x-faces (component B_z, sign +1), z-faces (component B_x, sign -1)
+  double ey = 0.0;
+  ey = ey + (fe(0, 2, n) + fe(0, 3, mz));
+  ey = ey - (fe(2, 0, n) + fe(2, 1, mx));
+  // E_z: x-faces (component B_y, sign -1), y-faces (component B_x, sign +1)
+  double ez = 0.0;
+  ez = ez - (fe(0, 0, n) + fe(0, 1, my));
+  ez = ez + (fe(1, 0, n) + fe(1, 1, mx));
+  E[n] = 0.25 * ex;
+  E[g.N + n] = 0.25 * ey;
+  E[2 * g.N + n] = 0.25 * ez;
+}
+
+// eq. (8) for the three lower faces of zone n (double), with the eq. (6)
+// hydro update done by update_zone.
+__host__ __device__ __forceinline__ void ct_zone(double* __restrict__ B, const double* __restrict__ E,
+                                                 const Grid& g, double h, double dx, double dy,
+                                                 double dz, long long n) {
+  const int i = (int)(n % g.nx);
+  const int j = (int)((n / g.nx) % g.ny);
+  const int k = (int)(n / ((long long)g.nx * g.ny));
+  const long long px = zone_of(wrap(i + 1, g.nx), j, k, g);
+  const long long py = zone_of(i, wrap(j + 1, g.ny), k, g);
+  const long long pz = zone_of(i, j, wrap(k + 1, g.nz), g);
+  const double* Ex = E;
+  const double* Ey = E + g.N;
+  const double* Ez = E + 2 * g.N;
+  B[n] = B[n] - h * ((Ez[py] - Ez[n]) / dy - (Ey[pz] - Ey[n]) / dz);
+  B[g.N + n] = B[g.N + n] - h * ((Ex[pz] - Ex[n]) / dz - (Ez[px] - Ez[n]) / dx);
+  B[2 * g.N + n] = B[2 * g.N + n] - h * ((Ey[px] - Ey[n]) / dx - (Ex[py] - Ex[n]) / dy);
+}
+
+// CFL rate of one MHD zone, with the zone field taken as the mean of its
+// two face values per component.
+__host__ __device__ __forceinline__ double dt_rate_zone_mhd(const double* __restrict__ U,
+                                                            const double* __restrict__ B,
+                                                            const Grid& g, double gam, double dx,
+                                                            double dy, double dz, long long n,
+                                                            int& isbad) {
+  const int i = (int)(n % g.nx);
+  const int j = (int)((n / g.nx) % g.ny);
+  const int k = (int)(n / ((long long)g.nx * g.ny));
+  double u[8];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = U[(long long)v * g.N + n];
+  u[5] = 0.5 * (B[n] + B[zone_of(wrap(i + 1, g.nx), j, k, g)]);
+  u[6] = 0.5 * (B[g.N + n] + B[g.N + zone_of(i, wrap(j + 1, g.ny), k, g)]);
+  u[7] = 0.5 * (B[2 * g.N + n] + B[2 * g.N + zone_of(i, j, wrap(k + 1, g.nz), g)]);
+  const double p = Mhd<double>::pressure(u, gam);
+  bool ok = u[0] > 0.0 && p > 0.0;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) ok = ok && __builtin_isfinite(u[v]);
+  if (!ok) {
+    isbad = 1;
+    return 0.0;
+  }
+  return (fabs(u[1] / u[0]) + Mhd<double>::fast_speed<0>(u, gam)) / dx +
+         (fabs(u[2] / u[0]) + Mhd<double>::fast_speed<1>(u, gam)) / dy +
+         (fabs(u[3] / u[0]) + Mhd<double>::fast_speed<2>(u, gam)) / dz;
 }
 
 }  // namespace ader

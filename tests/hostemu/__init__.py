@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 SRC = os.path.join(HERE, "ader_hostemu.hip")
 LIB = os.path.join(HERE, "libader_hostemu.so")
 DEPS = [SRC] + [os.path.join(ROOT, "paper_1006_2146_amd", "csrc", f)
-                for f in ("zone_ops.h", "euler_device.h", os.path.join("generated", "ader_scheme.h"))]
+                for f in ("zone_ops.h", "physics_device.h", os.path.join("generated", "ader_scheme.h"))]
 
 _lib = None
 
@@ -39,6 +39,10 @@ def load():
         lib.hostemu_step.restype = I
         lib.hostemu_dt.argtypes = [DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt.restype = D
+        lib.hostemu_step_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, I, I, I, D]
+        lib.hostemu_step_mhd.restype = I
+        lib.hostemu_dt_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, D]
+        lib.hostemu_dt_mhd.restype = D
         _lib = lib
     return _lib
 
@@ -64,3 +68,24 @@ def compute_dt(U, cfl, lengths=(1.0, 1.0, 1.0), gamma=1.4):
     nx, ny, nz, dx, dy, dz = _spacing(U, lengths)
     return load().hostemu_dt(U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
                              dx, dy, dz, gamma, cfl)
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def step_mhd(U, B, dt, order, form="modal", precision="fp64", lengths=(1.0, 1.0, 1.0),
+             gamma=5.0 / 3.0):
+    Uo = np.ascontiguousarray(U, dtype=np.float64).copy()
+    Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
+    nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
+    load().hostemu_step_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
+                            1 if form == "nodal" else 0, 0 if precision == "fp64" else 1, dt)
+    return Uo, Bo
+
+
+def compute_dt_mhd(U, B, cfl, lengths=(1.0, 1.0, 1.0), gamma=5.0 / 3.0):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    nx, ny, nz, dx, dy, dz = _spacing(U, lengths)
+    return load().hostemu_dt_mhd(_dp(U), _dp(B), nx, ny, nz, dx, dy, dz, gamma, cfl)

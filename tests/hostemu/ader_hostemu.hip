@@ -48,7 +48,88 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
   for (long long n = 0; n < N; ++n) update_zone<T>(U, F.data(), g, dt, dx, dy, dz, n);
 }
 
+template <class T>
+static void emu_recon(const double* src, T* W, Grid g, int order, int nvar) {
+  const long long N = g.N;
+  if (nvar == 5) {
+    if (order == 2) for (long long n = 0; n < N; ++n) minmod_zone<T, 5>(src, W, g, n);
+    if (order == 3) {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 0, 5>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 1, 5>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 2, 5>(src, W, g, n);
+    }
+    if (order == 4) {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 0, 5>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 1, 5>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 2, 5>(src, W, g, n);
+    }
+  } else {
+    if (order == 2) for (long long n = 0; n < N; ++n) minmod_zone<T, 3>(src, W, g, n);
+    if (order == 3) {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 0, 3>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 1, 3>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 2, 3>(src, W, g, n);
+    }
+    if (order == 4) {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 0, 3>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 1, 3>(src, W, g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 2, 3>(src, W, g, n);
+    }
+  }
+}
+
+template <class T>
+static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, double dz, double gam,
+                         int order, int form, double dt) {
+  const long long N = g.N;
+  std::vector<T> W((size_t)19 * 5 * N), WB((size_t)19 * 3 * N), BN((size_t)9 * N),
+      PK((size_t)6 * 32 * N), F((size_t)15 * N), FE((size_t)12 * N);
+  std::vector<double> B0((size_t)3 * N), E((size_t)3 * N);
+  for (long long n = 0; n < N; ++n) {
+    if (order == 2) bface_zone<T, 2>(B, B0.data(), BN.data(), g, n);
+    if (order == 3) bface_zone<T, 3>(B, B0.data(), BN.data(), g, n);
+    if (order == 4) bface_zone<T, 4>(B, B0.data(), BN.data(), g, n);
+  }
+  emu_recon<T>(U, W.data(), g, order, 5);
+  emu_recon<T>(B0.data(), WB.data(), g, order, 3);
+  const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
+  for (long long n = 0; n < N; ++n) {
+    if (order == 2 && form == 1)
+      predict_zone_mhd<T, 2, 1>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 2)
+      predict_zone_mhd<T, 2, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 3)
+      predict_zone_mhd<T, 3, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else
+      predict_zone_mhd<T, 4, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+  }
+  for (long long n = 0; n < N; ++n) face_flux_zone_mhd<T>(PK.data(), F.data(), FE.data(), g, gam, n);
+  for (long long n = 0; n < N; ++n) edge_e_zone<T>(FE.data(), E.data(), g, n);
+  for (long long n = 0; n < N; ++n) update_zone<T>(U, F.data(), g, dt, dx, dy, dz, n);
+  for (long long n = 0; n < N; ++n) ct_zone(B, E.data(), g, dt, dx, dy, dz, n);
+}
+
 extern "C" {
+
+// One MHD step of the host build, in place on U[5][N] and the face field B[3][N].
+int hostemu_step_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,
+                     double dz, double gam, int order, int form, int precision, double dt) {
+  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  if (precision == 0)
+    emu_step_mhd<double>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  else
+    emu_step_mhd<float>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  return 0;
+}
+
+double hostemu_dt_mhd(const double* U, const double* B, int nx, int ny, int nz, double dx,
+                      double dy, double dz, double gam, double cfl) {
+  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  double mx = 0.0;
+  int bad = 0;
+  for (long long n = 0; n < g.N; ++n) mx = fmax(mx, dt_rate_zone_mhd(U, B, g, gam, dx, dy, dz, n, bad));
+  return bad ? -1.0 : cfl / mx;
+}
 
 // One step of the host build, in place on U[5][nz][ny][nx].
 int hostemu_step(double* U, int nx, int ny, int nz, double dx, double dy, double dz, double gam,

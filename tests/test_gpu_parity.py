@@ -144,3 +144,78 @@ def test_config2_full_size_sampled(rs):
         got = Ug[:, iz][:, :, iy][:, :, :, ix]
         err = rel_l1(got, ref)
         assert np.all(err <= TOL_FP64), (o, err)
+
+
+# ----------------------------------------------------------------- MHD ------
+
+G53 = 5.0 / 3.0
+MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
+
+
+def _mhd_solver(shape, order, form, lengths=(1.0, 1.0, 1.0), precision=ader.ADER_FP64):
+    return ader.Solver(shape, lengths=lengths, gamma=G53, order=order, form=FORM[form],
+                       riemann=ader.ADER_HLL, precision=precision, system=ader.ADER_MHD)
+
+
+def _check_steps_mhd(U0, B0, order, form, nsteps, cfl=0.3, lengths=(1.0, 1.0, 1.0), tag=""):
+    shape = U0.shape[1:]
+    cfg = OracleConfig(order=order, form=form, gamma=G53, lengths=lengths)
+    with _mhd_solver(shape, order, form, lengths) as s:
+        s.set_state(U0, B0)
+        U, B = U0, B0
+        for it in range(nsteps):
+            say(tag, "mhd order", order, form, "shape", shape, "step", it)
+            dt_gpu = s.compute_dt(cfl)
+            assert abs(dt_gpu - oracle_dt(U, cfg, cfl, B)) <= 1e-14 * dt_gpu
+            s.step(dt_gpu)
+            Ug, Bg = s.get_state()
+            Uo, Bo = oracle_step(U, dt_gpu, cfg, B)
+            err, errb = rel_l1(Ug, Uo), rel_l1(Bg, Bo)
+            assert np.all(err <= TOL_FP64) and np.all(errb <= TOL_FP64), (it, err, errb)
+            U, B = Ug, Bg
+    return U, B
+
+
+@pytest.mark.parametrize("order,form", MHD_CASES)
+def test_parity_mhd_random_field_ragged(order, form):
+    U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order)
+    _check_steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), tag="mhd-random")
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_parity_mhd_alfven_and_div_b(order):
+    from oracle.bweno import divergence
+    U0, B0 = workloads.alfven_wave_diagonal((8, 8, 8))
+    U, B = _check_steps_mhd(U0, B0, order, "modal", 3, tag="mhd-alfven")
+    dx = (1.0 / 8,) * 3
+    assert np.abs(divergence(B, dx)).max() <= 1e-12 * np.abs(B).max() / dx[0]
+    assert np.all(np.abs(U.sum(axis=(1, 2, 3)) - U0.sum(axis=(1, 2, 3))) <= 1e-13 * np.abs(U0).sum())
+
+
+def test_mhd_linearized_is_unsupported():
+    with _mhd_solver((4, 4, 4), 3, "modal") as s:
+        rc = ader.load().ader_set_riemann(s.ctx, ader.ADER_LINEARIZED)
+        assert rc == ader.ADER_EUNSUPPORTED
+
+
+def test_config3_mhd_full_size_sampled():
+    # 128^3 MHD, order 4, HLL, CT: one CFL 0.3 step on the GPU, sampled blocks
+    # recomputed by the oracle
+    shape = (128, 128, 128)
+    U0, B0 = workloads.mhd_random_field(shape)
+    cfg = OracleConfig(order=4, gamma=G53)
+    with _mhd_solver(shape, 4, "modal") as s:
+        s.set_state(U0, B0)
+        say("config3", "step_cfl")
+        s.step_cfl(0.3)
+        Ug, Bg = s.get_state()
+        dt = s.dt()
+    assert abs(dt - oracle_dt(U0, cfg, 0.3, B0)) <= 1e-14 * dt
+    for o in [(0, 0, 0), (100, 37, 127), (64, 64, 64)]:
+        Ur, Br = step_block(U0, dt, cfg, o, (3, 3, 3), B0)
+        iz = np.arange(o[0], o[0] + 3) % 128
+        iy = np.arange(o[1], o[1] + 3) % 128
+        ix = np.arange(o[2], o[2] + 3) % 128
+        pick = lambda A: A[:, iz][:, :, iy][:, :, :, ix]  # noqa: E731
+        assert np.all(rel_l1(pick(Ug), Ur) <= TOL_FP64), o
+        assert np.all(rel_l1(pick(Bg), Br) <= TOL_FP64), o

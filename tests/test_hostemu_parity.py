@@ -52,3 +52,33 @@ def test_kernel_source_blast(order, form, rs):
 def test_kernel_source_tiny_meshes(order):
     for shape in [(1, 1, 1), (2, 3, 1), (3, 1, 2)]:
         _steps(workloads.random_smooth(shape, seed=3), order, "modal", "hll", 1)
+
+
+MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
+
+
+def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3):
+    cfg = OracleConfig(order=order, form=form, gamma=5.0 / 3.0, lengths=lengths)
+    U, B = U0, B0
+    for it in range(nsteps):
+        dt = hostemu.compute_dt_mhd(U, B, cfl, lengths)
+        assert abs(dt - oracle_dt(U, cfg, cfl, B)) <= 1e-14 * dt
+        Ue, Be = hostemu.step_mhd(U, B, dt, order, form, lengths=lengths)
+        Uo, Bo = oracle_step(U, dt, cfg, B)
+        err = rel_l1(Ue, Uo)
+        errb = rel_l1(Be, Bo)
+        assert np.all(err <= 1e-12) and np.all(errb <= 1e-12), (it, err, errb)
+        U, B = Ue, Be
+    return U, B
+
+
+@pytest.mark.parametrize("order,form", MHD_CASES)
+def test_kernel_source_mhd_random_field(order, form):
+    U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=order)
+    _steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2))
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_kernel_source_mhd_alfven(order):
+    U0, B0 = workloads.alfven_wave_diagonal((6, 6, 6))
+    _steps_mhd(U0, B0, order, "modal", 2)
