@@ -77,6 +77,46 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
     }
 
 
+def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
+    """Untimed accuracy pass of the mixed path: the FP64 path takes `steps`
+    CFL steps, the mixed path repeats them with the same dt sequence, and the
+    relative L1 distance (largest over the variables) is reported.  With
+    trunc_order, the FP64 result at that higher order on the same steps
+    estimates the truncation error of the scheme at this resolution."""
+    mhd = B0 is not None
+    kw = dict(order=order, riemann=riemann, gamma=5.0 / 3.0 if mhd else 1.4,
+              system=ader.ADER_MHD if mhd else ader.ADER_EULER)
+
+    def run(precision, dts=None, order_=None):
+        args = dict(kw, order=order_ or order)
+        with ader.Solver(SHAPE, precision=precision, **args) as s:
+            s.set_state(U0, B0) if mhd else s.set_state(U0)
+            out = []
+            for q in range(steps):
+                if dts is None:
+                    out.append(s.compute_dt(CFL))
+                    s.step(out[-1])
+                else:
+                    s.step(dts[q])
+            st = s.get_state()
+        return (st if mhd else (st,)), out
+
+    ref, dts = run(ader.ADER_FP64)
+    mix, _ = run(ader.ADER_MIXED, dts)
+
+    def rel(a, b):
+        return float(max((np.abs(x - y).sum(axis=(1, 2, 3)) / np.abs(y).sum(axis=(1, 2, 3))).max()
+                         for x, y in zip(a, b)))
+
+    res = {"steps": steps, "l1_rel_vs_fp64": rel(mix, ref)}
+    if trunc_order:
+        hi, _ = run(ader.ADER_FP64, dts, trunc_order)
+        res["trunc_rel_estimate"] = rel(ref, hi)
+        res["trunc_estimate"] = "order-%d FP64 result on the same steps" % trunc_order
+        res["ratio"] = res["l1_rel_vs_fp64"] / res["trunc_rel_estimate"]
+    return res
+
+
 def cpu_baseline(U0):
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: one step of a 64^3 periodic sub-box (ghost zones included in
@@ -140,6 +180,16 @@ def main():
                                                          args.steps, args.warmup, order=4, B0=Bm)
             log("mhd variant", name, "%.3e zone-updates/s"
                 % mhd_variants["mhd-o4-" + name]["zone_updates_per_s"])
+
+    for name in variants:
+        if name.startswith("mixed"):
+            log("accuracy", name)
+            rs = ader.ADER_HLL if name.endswith("hll") else ader.ADER_LINEARIZED
+            variants[name]["accuracy"] = accuracy(ader, U0, 3, rs, 10, trunc_order=4)
+    for name in mhd_variants:
+        if name.endswith("mixed"):
+            log("accuracy", name)
+            mhd_variants[name]["accuracy"] = accuracy(ader, Um, 4, ader.ADER_HLL, 3, B0=Bm)
 
     primary = "fp64-hll" if "fp64-hll" in variants else next(iter(variants))
     pv = variants[primary]

@@ -8,6 +8,11 @@
 
 namespace ader {
 
+// The FP32 (mixed-precision) kernels run the deviation form, the FP64 ones
+// the point form.
+template <class T>
+constexpr bool kDeviation = sizeof(T) == 4;
+
 template <class T, int M, int AXIS, int NVAR>
 __global__ void __launch_bounds__(256) k_weno_sweep(const double* __restrict__ U,
                                                     T* __restrict__ W, Grid g) {
@@ -40,34 +45,36 @@ __global__ void __launch_bounds__(128) k_predict_mhd(const double* __restrict__ 
                                                      double gam) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < g.N)
-    predict_zone_mhd<T, ORDER, FORM>(U, W, B0, WB, BN, PK, g, *dt, inv_dx, inv_dy, inv_dz, gam, n);
+    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>>(U, W, B0, WB, BN, PK, g, *dt, inv_dx, inv_dy,
+                                                    inv_dz, gam, n);
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_face_flux_mhd(const T* __restrict__ PK, T* __restrict__ F,
-                                                       T* __restrict__ FE, Grid g, double gam) {
+__global__ void __launch_bounds__(256) k_face_flux_mhd(const double* __restrict__ U,
+                                                       const double* __restrict__ B0,
+                                                       const T* __restrict__ PK,
+                                                       double* __restrict__ F,
+                                                       double* __restrict__ FE, Grid g, double gam) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) face_flux_zone_mhd<T>(PK, F, FE, g, gam, n);
+  if (n < g.N) face_flux_zone_mhd<T, kDeviation<T>>(U, B0, PK, F, FE, g, gam, n);
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) k_edge_e(const T* __restrict__ FE, double* __restrict__ E,
-                                                Grid g) {
+__global__ void __launch_bounds__(256) k_edge_e(const double* __restrict__ FE,
+                                                double* __restrict__ E, Grid g) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) edge_e_zone<T>(FE, E, g, n);
+  if (n < g.N) edge_e_zone(FE, E, g, n);
 }
 
 // eq. (6) for the hydro variables and eq. (8) for the face fields
-template <class T>
 __global__ void __launch_bounds__(256) k_update_mhd(double* __restrict__ U, double* __restrict__ B,
-                                                    const T* __restrict__ F,
+                                                    const double* __restrict__ F,
                                                     const double* __restrict__ E, Grid g,
                                                     const double* __restrict__ dt, double dx,
                                                     double dy, double dz) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n < g.N) {
     const double h = *dt;
-    update_zone<T>(U, F, g, h, dx, dy, dz, n);
+    update_zone(U, F, g, h, dx, dy, dz, n);
     ct_zone(B, E, g, h, dx, dy, dz, n);
   }
 }
@@ -80,22 +87,23 @@ __global__ void __launch_bounds__(128) k_predict(const double* __restrict__ U,
                                                  double inv_dx, double inv_dy,
                                                  double inv_dz, double gam) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) predict_zone<T, ORDER, FORM>(U, W, PK, g, *dt, inv_dx, inv_dy, inv_dz, gam, n);
+  if (n < g.N)
+    predict_zone<T, ORDER, FORM, kDeviation<T>>(U, W, PK, g, *dt, inv_dx, inv_dy, inv_dz, gam, n);
 }
 
 template <class T, int RS>
-__global__ void __launch_bounds__(256) k_face_flux(const T* __restrict__ PK, T* __restrict__ F,
-                                                   Grid g, double gam) {
+__global__ void __launch_bounds__(256) k_face_flux(const double* __restrict__ U,
+                                                   const T* __restrict__ PK,
+                                                   double* __restrict__ F, Grid g, double gam) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) face_flux_zone<T, RS>(PK, F, g, gam, n);
+  if (n < g.N) face_flux_zone<T, RS, kDeviation<T>>(U, PK, F, g, gam, n);
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) k_update(double* __restrict__ U, const T* __restrict__ F,
+__global__ void __launch_bounds__(256) k_update(double* __restrict__ U, const double* __restrict__ F,
                                                 Grid g, const double* __restrict__ dt,
                                                 double dx, double dy, double dz) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) update_zone<T>(U, F, g, *dt, dx, dy, dz, n);
+  if (n < g.N) update_zone(U, F, g, *dt, dx, dy, dz, n);
 }
 
 __device__ __forceinline__ double wave_max(double x) {

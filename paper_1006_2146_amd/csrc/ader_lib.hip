@@ -174,30 +174,30 @@ template <class T>
 int launch_flux_update(ader_ctx* c) {
   const unsigned nb = blocks_for(c->g.N, kBlock);
   const T* PK = static_cast<const T*>(c->PK);
-  T* F = static_cast<T*>(c->F);
+  double* F = static_cast<double*>(c->F);
   if (c->system == ADER_MHD) {
-    T* FE = static_cast<T*>(c->FE);
+    double* FE = static_cast<double*>(c->FE);
     {
       StageTimer t(c, ADER_STAGE_FLUX);
-      k_face_flux_mhd<T><<<nb, kBlock, 0, c->stream>>>(PK, F, FE, c->g, c->gamma);
+      k_face_flux_mhd<T><<<nb, kBlock, 0, c->stream>>>(c->U, c->B0, PK, F, FE, c->g, c->gamma);
       ADER_TRY(launched());
-      k_edge_e<T><<<nb, kBlock, 0, c->stream>>>(FE, c->E, c->g);
+      k_edge_e<<<nb, kBlock, 0, c->stream>>>(FE, c->E, c->g);
       ADER_TRY(launched());
     }
     StageTimer t(c, ADER_STAGE_UPDATE);
-    k_update_mhd<T><<<nb, kBlock, 0, c->stream>>>(c->U, c->B, F, c->E, c->g, c->d_dt, c->dx, c->dy, c->dz);
+    k_update_mhd<<<nb, kBlock, 0, c->stream>>>(c->U, c->B, F, c->E, c->g, c->d_dt, c->dx, c->dy, c->dz);
     return launched();
   }
   {
     StageTimer t(c, ADER_STAGE_FLUX);
     if (c->riemann == ADER_HLL)
-      k_face_flux<T, 0><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
+      k_face_flux<T, 0><<<nb, kBlock, 0, c->stream>>>(c->U, PK, F, c->g, c->gamma);
     else
-      k_face_flux<T, 1><<<nb, kBlock, 0, c->stream>>>(PK, F, c->g, c->gamma);
+      k_face_flux<T, 1><<<nb, kBlock, 0, c->stream>>>(c->U, PK, F, c->g, c->gamma);
     ADER_TRY(launched());
   }
   StageTimer t(c, ADER_STAGE_UPDATE);
-  k_update<T><<<nb, kBlock, 0, c->stream>>>(c->U, F, c->g, c->d_dt, c->dx, c->dy, c->dz);
+  k_update<<<nb, kBlock, 0, c->stream>>>(c->U, F, c->g, c->d_dt, c->dx, c->dy, c->dz);
   return launched();
 }
 

@@ -452,31 +452,42 @@ def _inv(A):
 # Floating-point operations per zone of the per-zone kernel, counted on the
 # emitted code (one per add, multiply, divide, square root; five variables):
 #   a point evaluation with t nonzero terms: t - 1 adds and one multiply per
-#     coefficient other than 1;
-#   one Euler flux (physics_device.h): 18;
+#     coefficient other than 1 (the deviation form drops the add of mode 0);
+#   one Euler flux (physics_device.h): 18, or 43 as a deviation flux;
 #   one accumulation into a mode: 2 per variable;
-#   one positivity check of a point (pressure of the state): 9.
-#   (MHD: eight variables, one MHD flux 50, one check 16.)
-FLUX_FLOPS = {'euler': 18, 'mhd': 50}
-CHECK_FLOPS = {'euler': 9, 'mhd': 16}
-NV_OF = {'euler': 5, 'mhd': 8}
+#   one positivity check of a point (pressure of the state): 9, plus 5 adds
+#     of the zone average in the deviation form.
+#   (MHD: eight variables, one MHD flux 50 or 103, one check 16 or 24.)
+FLUX_FLOPS = {'euler': 18, 'mhd': 50, 'euler-dev': 43, 'mhd-dev': 103}
+CHECK_FLOPS = {'euler': 9, 'mhd': 16, 'euler-dev': 14, 'mhd-dev': 24}
+NV_OF = {'euler': 5, 'mhd': 8, 'euler-dev': 5, 'mhd-dev': 8}
 SYSTEM = 'euler'    # system whose flops the current emission pass counts
 COUNT = {}
+
+
+def _is_mhd():
+    return SYSTEM.startswith('mhd')
+
+
+def _is_dev():
+    return SYSTEM.endswith('-dev')
 
 
 def _count(key, n):
     """Count under (tag, part) for the system of this pass; parts of the other
     system's code are not counted."""
     tag, part = key
-    if part.endswith('-mhd') != (SYSTEM == 'mhd') and part != 'predictor':
+    if part.endswith('-mhd') != _is_mhd() and part != 'predictor':
         return
-    k = (tag + ('-mhd' if SYSTEM == 'mhd' else ''), part.replace('-mhd', ''))
+    k = (tag + ('-mhd' if _is_mhd() else '') + ('-dev' if _is_dev() else ''),
+         part.replace('-mhd', ''))
     COUNT[k] = COUNT.get(k, 0) + n
 
 
 def _eval_flops(row):
     nz = [c for c in row if c != 0]
-    return NV_OF[SYSTEM] * (len(nz) - 1 + sum(1 for c in nz if c != 1))
+    adds = len(nz) - 1 - (1 if _is_dev() and row[0] != 0 and len(nz) > 1 else 0)
+    return NV_OF[SYSTEM] * (adds + sum(1 for c in nz if c != 1))
 
 def lit(c):
     c = Fr(c)
@@ -485,22 +496,37 @@ def lit(c):
     return "T(%d.0 / %d.0)" % (c.numerator, c.denominator)
 
 
+def _terms(row, ls, comp="v"):
+    """Source terms of a point evaluation except mode 0."""
+    terms = []
+    for m, c in enumerate(row):
+        if c == 0 or m == 0:
+            continue
+        src = ("w[%d][%s]" % (m, comp)) if m < ls else ("e[%d][%s]" % (m - ls, comp))
+        terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
+    return terms
+
+
+def _value(row, ls, comp="v"):
+    """Expression of a point value: with the zone average (mode 0) in the
+    point form, without it (the deviation from the average) in the deviation
+    form, selected by the constant DEV of the enclosing function."""
+    terms = _terms(row, ls, comp)
+    if row[0] == 0:
+        return " + ".join(terms) if terms else "T(0)"
+    assert row[0] == 1
+    rest = " + ".join(terms)
+    if not terms:
+        return "DEV ? T(0) : w[0][%s]" % comp
+    return "DEV ? (%s) : (w[0][%s] + %s)" % (rest, comp, rest)
+
+
 def emit_eval(out, order, pt, dst, indent="    ", count=None):
     """dst[v] = sum over modes with nonzero basis value at pt."""
     row = point_row(order, pt)
     if count:
         _count(count, _eval_flops(row))
-    ls = LS[order]
-    terms = []
-    for m, c in enumerate(row):
-        if c == 0:
-            continue
-        src = "w[%d][v]" % m if m < ls else "e[%d][v]" % (m - ls)
-        if c == 1:
-            terms.append(src)
-        else:
-            terms.append("%s * %s" % (lit(c), src))
-    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, " + ".join(terms)))
+    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, _value(row, LS[order])))
 
 
 def emit_spatial_eval(out, order, pt, dst, indent="    ", count=None):
@@ -508,13 +534,7 @@ def emit_spatial_eval(out, order, pt, dst, indent="    ", count=None):
     ls = LS[order]
     if count:
         _count(count, _eval_flops(row[:ls]))
-    terms = []
-    for m, c in enumerate(row[:ls]):
-        if c == 0:
-            continue
-        src = "w[%d][v]" % m
-        terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
-    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, " + ".join(terms)))
+    out.append(indent + "for (int v = 0; v < NV; ++v) %s[v] = %s;" % (dst, _value(row[:ls], ls)))
 
 
 def gen_order(order, form):
@@ -544,7 +564,7 @@ def gen_order(order, form):
             ws = node_dirs.get(j, {}).get(dname)
             if not ws:
                 continue
-            lines.append("    Phys::template flux<%d>(u, fl, gam);" % axis)
+            lines.append("    ph.template flux<%d>(u, fl);" % axis)
             _count(key, reps * (FLUX_FLOPS[SYSTEM] + len(ws) * (1 + 2 * NV_OF[SYSTEM])))
             for k, c in ws:
                 lines.append("    for (int v = 0; v < NV; ++v) %s[%d][v] += (%s * s%s) * fl[v];"
@@ -553,9 +573,12 @@ def gen_order(order, form):
     # predictor
     out.append("  // Picard iterations of the space-time predictor; fluxes at tau = 0")
     out.append("  // nodes are taken once, the others on each of the %d iterations." % (order - 1))
+    out.append("  // ph evaluates the physical flux at a point (point form) or")
+    out.append("  // the flux minus that of the zone average (deviation form: w[0] unused).")
     out.append("  template <class Phys>")
     out.append("  __host__ __device__ static inline void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
-    out.append("                                        T sx, T sy, T sz, T gam) {")
+    out.append("                                        T sx, T sy, T sz, const Phys& ph) {")
+    out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV], a0[NE][NV];")
     out.append("    for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) { a0[k][v] = T(0); e[k][v] = T(0); }")
     for j in range(1, len(nodes) + 1):
@@ -601,6 +624,7 @@ def gen_order(order, form):
     out.append("  // %d spatial check points of the positivity safeguard" % len(sp))
     out.append("  template <class Acc>")
     out.append("  __host__ __device__ static inline void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in sp:
         emit_spatial_eval(out, order, p, "u", count=(tag, 'positivity'))
@@ -634,6 +658,7 @@ def gen_order(order, form):
     out.append("  // facial nodes entering the face averages, and barycentres, of all sides")
     out.append("  template <class Acc>")
     out.append("  __host__ __device__ static inline void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for d, s in SIDES:
         for j in sorted(fav):
@@ -648,10 +673,12 @@ def gen_order(order, form):
 
     # face packets
     out.append("  // side packet: barycentre state (eq. 54), face average of u (eq. 55),")
-    out.append("  // face average of the physical normal flux (App. D composed)")
+    out.append("  // face average of the physical normal flux (App. D composed); in the")
+    out.append("  // deviation form all three are taken minus their zone-average values")
     out.append("  template <int SIDE, class Phys>")
-    out.append("  __host__ __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], T gam,")
+    out.append("  __host__ __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
     out.append("                                     T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
+    out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV];")
     for si, (d, s) in enumerate(SIDES):
         out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s))
@@ -659,20 +686,14 @@ def gen_order(order, form):
                   count=(tag, 'faces'))
         row = face_average_u_row(order, d, s)
         _count((tag, 'faces'), _eval_flops(row))
-        terms = []
-        for m, c in enumerate(row):
-            if c == 0:
-                continue
-            src = "w[%d][v]" % m if m < ls else "e[%d][v]" % (m - ls)
-            terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
-        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % " + ".join(terms))
+        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
         out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
         for j in sorted(fav):
             t1, t2, tau = fnodes[j - 1]
             emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", indent="      ",
                       count=(tag, 'faces'))
             _count((tag, 'faces'), FLUX_FLOPS[SYSTEM] + 2 * NV_OF[SYSTEM])
-            out.append("      Phys::template flux<%d>(u, fl, gam);" % d)
+            out.append("      ph.template flux<%d>(u, fl);" % d)
             out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
         out.append("    }")
     out.append("  }")
@@ -711,6 +732,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
     out.append("  };")
     out.append("  template <class Acc>")
     out.append("  __host__ __device__ static inline void spatial_points_all(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in sp:
         emit_spatial_eval(out, order, p, "u", count=(tag, 'positivity-mhd'))
@@ -719,6 +741,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
     out.append("  }")
     out.append("  template <class Acc>")
     out.append("  __host__ __device__ static inline void facial_points_all(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in fpts:
         emit_eval(out, order, p, "u", count=(tag, 'positivity-mhd'))
@@ -730,8 +753,9 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
     out.append("  // ue[q], fe[q]: edge averages of u and of the normal flux of the field")
     out.append("  // component along transverse axis t_w, edge q = 2 w + (sign > 0)")
     out.append("  template <int SIDE, class Phys>")
-    out.append("  __host__ __device__ static inline void side_edges(const T (&w)[LS][NV], const T (&e)[NE][NV], T gam,")
+    out.append("  __host__ __device__ static inline void side_edges(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
     out.append("      T (&ub)[NV], T (&ua)[NV], T (&fa)[NV], T (&ue)[4], T (&fe)[4]) {")
+    out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV];")
     for si, (d, s_) in enumerate(SIDES):
         tr = transverse(d)
@@ -740,30 +764,20 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                   count=(tag, 'faces-mhd'))
         row = face_average_u_row(order, d, s_)
         _count((tag, 'faces-mhd'), _eval_flops(row))
-        terms = []
-        for m, c in enumerate(row):
-            if c != 0:
-                src = "w[%d][v]" % m if m < ls else "e[%d][v]" % (m - ls)
-                terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
-        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % " + ".join(terms))
+        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
         # edge averages of u, component of the edge's transverse axis
         for which in (0, 1):
             a = tr[which]
             free = 3 - d - a
             for sg in (-1, 1):
                 q = 2 * which + (1 if sg > 0 else 0)
-                terms = []
+                row = []
                 for m, (ea, eb, ec, dd) in enumerate(mode_list(order)):
                     ex = (ea, eb, ec)
-                    if ex[free] != 0:
-                        continue
-                    c = P(ex[d], HALF * s_) * P(ex[a], HALF * sg) / (dd + 1)
-                    if c == 0:
-                        continue
-                    src = ("w[%d][%d]" % (m, 5 + a)) if m < ls else ("e[%d][%d]" % (m - ls, 5 + a))
-                    terms.append(src if c == 1 else "%s * %s" % (lit(c), src))
-                _count((tag, 'faces-mhd'), 2 * len(terms))
-                out.append("      ue[%d] = %s;" % (q, " + ".join(terms)))
+                    row.append(0 if ex[free] != 0 else
+                               P(ex[d], HALF * s_) * P(ex[a], HALF * sg) / (dd + 1))
+                _count((tag, 'faces-mhd'), 2 * (sum(1 for c in row if c != 0) - (1 if _is_dev() else 0)))
+                out.append("      ue[%d] = %s;" % (q, _value(row, ls, str(5 + a))))
         out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
         out.append("      for (int q = 0; q < 4; ++q) fe[q] = T(0);")
         for j in range(1, nf + 1):
@@ -773,7 +787,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                 continue
             emit_eval(out, order, side_point(d, s_, *fnodes[j - 1]), "u", indent="      ",
                       count=(tag, 'faces-mhd'))
-            out.append("      Phys::template flux<%d>(u, fl, gam);" % d)
+            out.append("      ph.template flux<%d>(u, fl);" % d)
             _count((tag, 'faces-mhd'), FLUX_FLOPS[SYSTEM])
             if used_face:
                 out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
@@ -823,8 +837,8 @@ def main():
     for order, form in ((2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')):
         SYSTEM = 'euler'
         lines += gen_order(order, form)
-        SYSTEM = 'mhd'          # same code, counted with eight variables
-        gen_order(order, form)
+        for SYSTEM in ('mhd', 'euler-dev', 'mhd-dev'):   # same code, counted again
+            gen_order(order, form)
     SYSTEM = 'euler'
     lines += gen_weno()
     lines.append("}  // namespace ader_gen")
@@ -839,7 +853,8 @@ def main():
     import json
     with open(os.path.join(here, "generated", "flop_counts.json"), "w") as fh:
         json.dump({"unit": "flops per zone of k_predict (tags without -mhd: Euler, 5 "
-                           "variables; -mhd: ideal MHD, 8 variables)",
+                           "variables; -mhd: ideal MHD, 8 variables; -dev: the deviation "
+                           "form of the mixed-precision path)",
                    "counts": counts}, fh, indent=1, sort_keys=True)
         fh.write("\n")
 

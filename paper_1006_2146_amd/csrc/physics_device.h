@@ -32,6 +32,44 @@ struct Euler {
   __host__ __device__ static inline T fast_speed(const T (&u)[5], T gam) {
     return sqrt(gam * pressure(u, gam) / u[0]);
   }
+
+  // Deviation form (mixed-precision path): the state at a point is carried as
+  // du = u - ubar, ubar the zone average held in double, and the flux as
+  // dF = F(ubar + du) - F(ubar).  Every term of dF below is a product with a
+  // deviation, so its rounding error is relative to |dF| rather than |F|.
+  struct Ref {
+    T rho, m[3], v[3], h;   // density, momentum, velocity, E + p of ubar
+  };
+  __host__ __device__ static inline Ref make_ref(const double (&ub)[5], double gam) {
+    const double v0 = ub[1] / ub[0], v1 = ub[2] / ub[0], v2 = ub[3] / ub[0];
+    const double p = (gam - 1.0) * (ub[4] - 0.5 * (ub[1] * v0 + ub[2] * v1 + ub[3] * v2));
+    Ref r;
+    r.rho = T(ub[0]);
+    r.m[0] = T(ub[1]); r.m[1] = T(ub[2]); r.m[2] = T(ub[3]);
+    r.v[0] = T(v0); r.v[1] = T(v1); r.v[2] = T(v2);
+    r.h = T(ub[4] + p);
+    return r;
+  }
+
+  template <int AXIS>
+  __host__ __device__ static inline void dflux(const Ref& r, const T (&du)[5], T (&f)[5], T gam) {
+    const T rinv = T(1) / (r.rho + du[0]);
+    T dv[3], v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = (du[1 + a] - r.v[a] * du[0]) * rinv;   // v - vbar
+      v[a] = r.v[a] + dv[a];
+    }
+    // kinetic energy: m.v/2 - mbar.vbar/2 = (mbar.dv + dm.v)/2
+    const T dk = T(0.5) * (r.m[0] * dv[0] + r.m[1] * dv[1] + r.m[2] * dv[2] +
+                           du[1] * v[0] + du[2] * v[1] + du[3] * v[2]);
+    const T dp = (gam - T(1)) * (du[4] - dk);
+    f[0] = du[1 + AXIS];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f[1 + a] = du[1 + a] * v[AXIS] + r.m[a] * dv[AXIS];
+    f[1 + AXIS] += dp;
+    f[4] = (du[4] + dp) * v[AXIS] + r.h * dv[AXIS];
+  }
 };
 
 template <class T>
@@ -84,6 +122,84 @@ struct Mhd {
     const T s = a2 + b2;
     const T disc = s * s - T(4) * a2 * bn2;
     return sqrt(T(0.5) * (s + sqrt(disc > T(0) ? disc : T(0))));
+  }
+
+  // Deviation form, as for Euler: dF = F(ubar + du) - F(ubar).
+  struct Ref {
+    T rho, m[3], v[3], b[3], h, vb;   // ..., E + p + B^2/8pi, v.B of ubar
+  };
+  __host__ __device__ static inline Ref make_ref(const double (&ub)[8], double gam) {
+    const double v0 = ub[1] / ub[0], v1 = ub[2] / ub[0], v2 = ub[3] / ub[0];
+    const double pm = (ub[5] * ub[5] + ub[6] * ub[6] + ub[7] * ub[7]) * (1.0 / (8.0 * 3.14159265358979323846));
+    const double p = (gam - 1.0) * (ub[4] - 0.5 * (ub[1] * v0 + ub[2] * v1 + ub[3] * v2) - pm);
+    Ref r;
+    r.rho = T(ub[0]);
+    r.m[0] = T(ub[1]); r.m[1] = T(ub[2]); r.m[2] = T(ub[3]);
+    r.v[0] = T(v0); r.v[1] = T(v1); r.v[2] = T(v2);
+    r.b[0] = T(ub[5]); r.b[1] = T(ub[6]); r.b[2] = T(ub[7]);
+    r.h = T(ub[4] + p + pm);
+    r.vb = T(v0 * ub[5] + v1 * ub[6] + v2 * ub[7]);
+    return r;
+  }
+
+  template <int AXIS>
+  __host__ __device__ static inline void dflux(const Ref& r, const T (&du)[8], T (&f)[8], T gam) {
+    constexpr T i4p = T(1.0 / (4.0 * 3.14159265358979323846));
+    constexpr T i8p = T(1.0 / (8.0 * 3.14159265358979323846));
+    const T rinv = T(1) / (r.rho + du[0]);
+    T dv[3], v[3], b[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      dv[a] = (du[1 + a] - r.v[a] * du[0]) * rinv;
+      v[a] = r.v[a] + dv[a];
+      b[a] = r.b[a] + du[5 + a];
+    }
+    const T dk = T(0.5) * (r.m[0] * dv[0] + r.m[1] * dv[1] + r.m[2] * dv[2] +
+                           du[1] * v[0] + du[2] * v[1] + du[3] * v[2]);
+    // magnetic pressure: (B.B - Bbar.Bbar)/8pi = dB.(Bbar + B)/8pi
+    const T dpm = (du[5] * (r.b[0] + b[0]) + du[6] * (r.b[1] + b[1]) + du[7] * (r.b[2] + b[2])) * i8p;
+    const T dpt = (gam - T(1)) * (du[4] - dk - dpm) + dpm;   // total pressure
+    // v.B - vbar.Bbar = dv.B + vbar.dB
+    const T dvb = dv[0] * b[0] + dv[1] * b[1] + dv[2] * b[2] +
+                  r.v[0] * du[5] + r.v[1] * du[6] + r.v[2] * du[7];
+    f[0] = du[1 + AXIS];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      f[1 + a] = du[1 + a] * v[AXIS] + r.m[a] * dv[AXIS] -
+                 (du[5 + a] * b[AXIS] + r.b[a] * du[5 + AXIS]) * i4p;
+    f[1 + AXIS] += dpt;
+    f[4] = (du[4] + dpt) * v[AXIS] + r.h * dv[AXIS] -
+           (du[5 + AXIS] * (r.vb + dvb) + r.b[AXIS] * dvb) * i4p;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      f[5 + a] = dv[AXIS] * b[a] + r.v[AXIS] * du[5 + a] - du[5 + AXIS] * v[a] - r.b[AXIS] * dv[a];
+    f[5 + AXIS] = T(0);
+  }
+};
+
+// Flux evaluators for the generated per-zone code.  PointFlux takes the state
+// at a point and returns its physical flux; DeviationFlux takes the deviation
+// of the state from the zone average and returns the deviation of the flux
+// (exact algebra, the mixed-precision path).  kDeviation tells the generated
+// code whether point values carry the zone average.
+template <class P, class T>
+struct PointFlux {
+  static constexpr bool kDeviation = false;
+  T gam;
+  template <int AXIS, int NV>
+  __host__ __device__ inline void flux(const T (&u)[NV], T (&f)[NV]) const {
+    P::template flux<AXIS>(u, f, gam);
+  }
+};
+
+template <class P, class T>
+struct DeviationFlux {
+  static constexpr bool kDeviation = true;
+  typename P::Ref ref;
+  T gam;
+  template <int AXIS, int NV>
+  __host__ __device__ inline void flux(const T (&du)[NV], T (&f)[NV]) const {
+    P::template dflux<AXIS>(ref, du, f, gam);
   }
 };
 

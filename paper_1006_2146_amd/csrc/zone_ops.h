@@ -10,10 +10,14 @@
 //                                z-, z+) the barycentre state (eq. 54), the
 //                                face average of u (eq. 55) and of the normal
 //                                flux (App. D)
-//   F   T      [3][5][N]         numerical flux at the lower x/y/z face of each
+//   F   double [3][5][N]         numerical flux at the lower x/y/z face of each
 //                                zone (eq. 56 or the linearized flux)
-// T is double on the FP64 path and float on the mixed path; U, the update and
-// dt stay double on both.
+// T is double on the FP64 path and float on the mixed path; U, F, the update
+// and dt stay double on both.  The mixed path runs in deviation form (DEV):
+// the FP32 quantities are differences from the zone average (states) or from
+// the flux of the zone average (fluxes), which is held in double, so FP32
+// rounding is relative to the small variation inside a zone and not to the
+// state itself; the face flux adds the FP64 flux of the two zone averages.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -146,10 +150,12 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
       const int src = spatial_mode(a, b, 0);
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
+        // the zone averages enter as differences to the centre zone, formed
+        // in double (the moments do not see a constant shift)
         T d[2 * M - 1];
 #pragma unroll
         for (int q = 0; q < 2 * R + 1; ++q)
-          d[q] = src == 0 ? T(U[(long long)v * g.N + idx[q]])
+          d[q] = src == 0 ? T(U[(long long)v * g.N + idx[q]] - U[(long long)v * g.N + n])
                           : W[((long long)(src - 1) * NVAR + v) * g.N + idx[q]];
         T mo[M];
         weno1d<T, M>(d, mo);
@@ -211,9 +217,9 @@ struct PosTheta {
   double ub[NV];
   double eps_rho, eps_p, gam, theta;
 
-  __host__ __device__ PosTheta(const T (&w0)[NV], double g) : gam(g), theta(1.0) {
+  __host__ __device__ PosTheta(const double (&w0)[NV], double g) : gam(g), theta(1.0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) ub[v] = double(w0[v]);
+    for (int v = 0; v < NV; ++v) ub[v] = w0[v];
     eps_rho = 1.0e-8 * ub[0];
     eps_p = 1.0e-8 * pressure_of<NV>(ub, gam);
   }
@@ -259,10 +265,7 @@ struct PosTheta {
   // from the zone average to the point: the density bound (linear) and the
   // first crossing of the pressure bound; the same value as scaling for
   // density first and then for pressure.
-  __host__ __device__ void operator()(const T (&uT)[NV]) {
-    double u[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = double(uT[v]);
+  __host__ __device__ void operator()(const double (&u)[NV]) {
     const double p = pressure_of<NV>(u, gam);
     if (u[0] < eps_rho || p < eps_p) {
       double t = 1.0;
@@ -278,10 +281,16 @@ struct PosTheta {
 };
 
 // Cheap scan of the same points: flags a zone whose polynomial comes near
-// the bounds (within a factor 2, so that rounding in T never hides a
-// violation); only such zones run the exact pass in double.
-template <class T, int NV>
+// the bounds (within a factor 2 of the bounds, plus a margin of 64 rounding
+// units of T for the error of the point values, so that rounding in T never
+// hides a violation); only such zones run the exact pass in double.  In the
+// deviation form the point values come without the zone average, which the
+// scan adds back.
+template <class T, int NV, bool DEV>
 struct PosScan {
+  static constexpr bool kDeviation = DEV;
+  static constexpr T kSlack = T(64) * T(sizeof(T) == 4 ? 5.96e-8 : 1.11e-16);
+  T base[NV];
   T eps_rho, eps_e;
   int near = 0;
   __host__ __device__ static T rho_internal(const T (&u)[NV]) {
@@ -291,32 +300,42 @@ struct PosScan {
       r -= u[0] * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]) * T(1.0 / (8.0 * 3.14159265358979323846));
     return r;
   }
-  __host__ __device__ PosScan(const T (&w0)[NV], T gam) {
-    eps_rho = T(2.0e-8) * w0[0];
-    eps_e = T(2.0e-8) * rho_internal(w0) / w0[0];
-    (void)gam;
+  __host__ __device__ PosScan(const double (&w0)[NV]) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) base[v] = DEV ? T(w0[v]) : T(0);
+    T u0[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u0[v] = T(w0[v]);
+    eps_rho = (T(2.0e-8) + kSlack) * u0[0];
+    eps_e = T(2.0e-8) * rho_internal(u0) / u0[0];
   }
-  // rho >= eps_rho and rho (internal energy) >= rho eps_e
-  __host__ __device__ void operator()(const T (&u)[NV]) {
-    const int ok = int(u[0] >= eps_rho) & int(rho_internal(u) >= u[0] * eps_e);
+  // rho >= eps_rho and rho (internal energy) >= rho eps_e, with the margin
+  __host__ __device__ void operator()(const T (&du)[NV]) {
+    T u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = DEV ? base[v] + du[v] : du[v];
+    const int ok = int(u[0] >= eps_rho) &
+                   int(rho_internal(u) >= u[0] * eps_e + kSlack * fabs(u[0] * u[4]));
     near |= ok ^ 1;
   }
 };
 
 // Exact pass for a flagged zone: a runtime loop over the check points with
 // the basis values from the scheme's tables, so the rare path stays small.
+// The zone average w0 comes in double; the modes w[1..] (and e) are summed in
+// double, so both forms (w[0] is not read) give the same point values.
 template <int NP, int LS, class T, int NV>
-__host__ __device__ double theta_spatial_tab(const T (&w)[LS][NV], const double (&phi)[NP][LS],
-                                             double gam) {
-  PosTheta<T, NV> acc(w[0], gam);
+__host__ __device__ double theta_spatial_tab(const double (&w0)[NV], const T (&w)[LS][NV],
+                                             const double (&phi)[NP][LS], double gam) {
+  PosTheta<T, NV> acc(w0, gam);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
-    T u[NV];
+    double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      T s = T(0);
+      double s = w0[v];
 #pragma unroll
-      for (int m = 0; m < LS; ++m) s += T(phi[p][m]) * w[m][v];
+      for (int m = 1; m < LS; ++m) s += phi[p][m] * double(w[m][v]);
       u[v] = s;
     }
     acc(u);
@@ -325,25 +344,42 @@ __host__ __device__ double theta_spatial_tab(const T (&w)[LS][NV], const double 
 }
 
 template <int NP, int LS, int NE, class T, int NV>
-__host__ __device__ double theta_facial_tab(const T (&w)[LS][NV], const T (&e)[NE][NV],
+__host__ __device__ double theta_facial_tab(const double (&w0)[NV], const T (&w)[LS][NV],
+                                            const T (&e)[NE][NV],
                                             const double (&phi)[NP][LS + NE], double gam) {
-  PosTheta<T, NV> acc(w[0], gam);
+  PosTheta<T, NV> acc(w0, gam);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
-    T u[NV];
+    double u[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      T s = T(0);
+      double s = w0[v];
 #pragma unroll
-      for (int m = 0; m < LS; ++m) s += T(phi[p][m]) * w[m][v];
+      for (int m = 1; m < LS; ++m) s += phi[p][m] * double(w[m][v]);
 #pragma unroll
-      for (int m = 0; m < NE; ++m) s += T(phi[p][LS + m]) * e[m][v];
+      for (int m = 0; m < NE; ++m) s += phi[p][LS + m] * double(e[m][v]);
       u[v] = s;
     }
     acc(u);
   }
   return acc.theta;
 }
+
+// The flux evaluator of each form.
+template <class P, class T, bool DEV>
+struct FluxOf;
+template <class P, class T>
+struct FluxOf<P, T, false> {
+  using type = PointFlux<P, T>;
+  __host__ __device__ static type make(const double (&)[P::NV], double gam) { return type{T(gam)}; }
+};
+template <class P, class T>
+struct FluxOf<P, T, true> {
+  using type = DeviationFlux<P, T>;
+  __host__ __device__ static type make(const double (&w0)[P::NV], double gam) {
+    return type{P::make_ref(w0, gam), T(gam)};
+  }
+};
 
 template <int ORDER, int FORM, class T, int NV = 5>
 struct SchemeOf;
@@ -352,11 +388,12 @@ template <class T, int NV> struct SchemeOf<2, 1, T, NV> { using type = ader_gen:
 template <class T, int NV> struct SchemeOf<3, 0, T, NV> { using type = ader_gen::SchemeM3<T, NV>; };
 template <class T, int NV> struct SchemeOf<4, 0, T, NV> { using type = ader_gen::SchemeM4<T, NV>; };
 
-template <class S, class T, int SIDE>
-__host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], const T (&e)[S::NE][5], T gam,
-                                           T* __restrict__ PK, long long N, long long n) {
+template <class S, class T, int SIDE, class Phys>
+__host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], const T (&e)[S::NE][5],
+                                                    const Phys& ph, T* __restrict__ PK, long long N,
+                                                    long long n) {
   T ub[5], ua[5], fa[5];
-  S::template side<SIDE, Euler<T>>(w, e, gam, ub, ua, fa);
+  S::template side<SIDE>(w, e, ph, ub, ua, fa);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     PK[((long long)(SIDE * 3 + 0) * 5 + v) * N + n] = ub[v];
@@ -366,8 +403,9 @@ __host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], cons
 }
 
 // Per zone: load the reconstruction, positivity scaling, space-time predictor
-// (Sec. IV / App. A), positivity scaling, and the six face-side packets.
-template <class T, int ORDER, int FORM>
+// (Sec. IV / App. A), positivity scaling, and the six face-side packets (in
+// the deviation form without the zone-average part).
+template <class T, int ORDER, int FORM, bool DEV>
 __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__ U,
                                                       const T* __restrict__ W,
                                                       T* __restrict__ PK, const Grid& g,
@@ -375,18 +413,21 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
                                                       double inv_dz, double gam, long long n) {
   using S = typename SchemeOf<ORDER, FORM, T>::type;
   constexpr int LS = S::LS, NE = S::NE;
+  double w0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.N + n];
   T w[LS][5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w[0][v] = T(U[(long long)v * g.N + n]);
+  for (int v = 0; v < 5; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
 #pragma unroll
   for (int m = 1; m < LS; ++m)
 #pragma unroll
     for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.N + n];
 
   {
-    PosScan<T, 5> scan(w[0], T(gam));
+    PosScan<T, 5, DEV> scan(w0);
     S::spatial_points(w, scan);
-    const double theta = scan.near ? theta_spatial_tab(w, S::spatial_phi, gam) : 1.0;
+    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -395,12 +436,13 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
         for (int v = 0; v < 5; ++v) w[m][v] *= th;
     }
   }
+  const auto ph = FluxOf<Euler<T>, T, DEV>::make(w0, gam);
   T e[NE][5];
-  S::template predict<Euler<T>>(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), T(gam));
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
   {
-    PosScan<T, 5> scan(w[0], T(gam));
+    PosScan<T, 5, DEV> scan(w0);
     S::facial_points(w, e, scan);
-    const double theta = scan.near ? theta_facial_tab(w, e, S::facial_phi, gam) : 1.0;
+    const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -413,31 +455,26 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
         for (int v = 0; v < 5; ++v) e[m][v] *= th;
     }
   }
-  const T tg = T(gam);
-  store_side<S, T, 0>(w, e, tg, PK, g.N, n);
-  store_side<S, T, 1>(w, e, tg, PK, g.N, n);
-  store_side<S, T, 2>(w, e, tg, PK, g.N, n);
-  store_side<S, T, 3>(w, e, tg, PK, g.N, n);
-  store_side<S, T, 4>(w, e, tg, PK, g.N, n);
-  store_side<S, T, 5>(w, e, tg, PK, g.N, n);
+  store_side<S, T, 0>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 1>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 2>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 3>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 4>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 5>(w, e, ph, PK, g.N, n);
 }
 
 // ---------------------------------------------------------------------------
 // Riemann fluxes at the faces (Sec. II.3, V): wave structure frozen at the
 // two barycentre states.
 // ---------------------------------------------------------------------------
-template <class T, int AXIS>
-__host__ __device__ __forceinline__ void hll_flux(const T (&ubl)[5], const T (&ul)[5], const T (&fl)[5],
-                                         const T (&ubr)[5], const T (&ur)[5], const T (&fr)[5],
-                                         T gam, T (&out)[5]) {
-  const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
-  const T cl = sqrt(gam * Euler<T>::pressure(ubl, gam) / ubl[0]);
-  const T cr = sqrt(gam * Euler<T>::pressure(ubr, gam) / ubr[0]);
-  const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
-  const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
+// HLL combination (eq. 17 / 56) with signal speeds lam_l <= 0 <= lam_r.
+template <class T, int NV>
+__host__ __device__ __forceinline__ void hll_combine(T lam_l, T lam_r, const T (&ul)[NV],
+                                                     const T (&fl)[NV], const T (&ur)[NV],
+                                                     const T (&fr)[NV], T (&out)[NV]) {
   const T inv = T(1) / (lam_r - lam_l);
 #pragma unroll
-  for (int v = 0; v < 5; ++v)
+  for (int v = 0; v < NV; ++v)
     out[v] = (lam_r * fl[v] - lam_l * fr[v] + lam_r * lam_l * (ur[v] - ul[v])) * inv;
 }
 
@@ -482,10 +519,21 @@ __host__ __device__ __forceinline__ void linearized_flux(const T (&ubl)[5], cons
   for (int v = 0; v < 5; ++v) out[v] = T(0.5) * (fl[v] + fr[v]) - T(0.5) * dis[v];
 }
 
-template <class T, int RS, int AXIS>
-__host__ __device__ __forceinline__ void face_flux_axis(const T* __restrict__ PK, T* __restrict__ F,
-                                               const Grid& g, long long n, long long nl, T gam) {
+// Flux at the lower AXIS-face of zone n from the packets of the upper side of
+// zone nl and the lower side of zone n.  Deviation form: the packets hold
+// differences from the zone averages wl, wr (double), and both solvers are
+// affine in (u_L, u_R, F_L, F_R) for frozen wave speeds / eigen-system, so
+// the flux splits exactly into the solver applied to the zone averages (in
+// double: HLL (lr F(wl) - ll F(wr))/(lr - ll) with the jump term moved to the
+// FP32 part, linearized (F(wl) + F(wr))/2) plus the solver applied to the
+// deviations with the jump wr - wl added to the right state (FP32).
+template <class T, int RS, int AXIS, bool DEV>
+__host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict__ U,
+                                                        const T* __restrict__ PK,
+                                                        double* __restrict__ F, const Grid& g,
+                                                        long long n, long long nl, double gam) {
   T ubl[5], ul[5], fl[5], ubr[5], ur[5], fr[5], out[5];
+  double wl[5], wr[5];
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;  // top side of the lower zone, bottom side of this
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -496,28 +544,67 @@ __host__ __device__ __forceinline__ void face_flux_axis(const T* __restrict__ PK
     ur[v] = PK[((long long)(SR * 3 + 1) * 5 + v) * g.N + n];
     fr[v] = PK[((long long)(SR * 3 + 2) * 5 + v) * g.N + n];
   }
-  if constexpr (RS == 0) hll_flux<T, AXIS>(ubl, ul, fl, ubr, ur, fr, gam, out);
-  else linearized_flux<T, AXIS>(ubl, ul, fl, ubr, ur, fr, gam, out);
+  if constexpr (DEV) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = out[v];
+    for (int v = 0; v < 5; ++v) {
+      wl[v] = U[(long long)v * g.N + nl];
+      wr[v] = U[(long long)v * g.N + n];
+      ubl[v] += T(wl[v]);
+      ubr[v] += T(wr[v]);
+      ur[v] += T(wr[v] - wl[v]);
+    }
+  }
+  const T tg = T(gam);
+  if constexpr (RS == 0) {
+    const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
+    const T cl = sqrt(tg * Euler<T>::pressure(ubl, tg) / ubl[0]);
+    const T cr = sqrt(tg * Euler<T>::pressure(ubr, tg) / ubr[0]);
+    const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
+    const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
+    hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
+    if constexpr (DEV) {
+      double Fl[5], Fr[5];
+      Euler<double>::template flux<AXIS>(wl, Fl, gam);
+      Euler<double>::template flux<AXIS>(wr, Fr, gam);
+      const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        F[((long long)AXIS * 5 + v) * g.N + n] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
+      return;
+    }
+  } else {
+    linearized_flux<T, AXIS>(ubl, ul, fl, ubr, ur, fr, tg, out);
+    if constexpr (DEV) {
+      double Fl[5], Fr[5];
+      Euler<double>::template flux<AXIS>(wl, Fl, gam);
+      Euler<double>::template flux<AXIS>(wr, Fr, gam);
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        F[((long long)AXIS * 5 + v) * g.N + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+      return;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = double(out[v]);
 }
 
 // Each face flux is formed once, by the zone above it, so both zones that
 // share a face see the same value and the update conserves exactly.
-template <class T, int RS>
-__host__ __device__ __forceinline__ void face_flux_zone(const T* __restrict__ PK, T* __restrict__ F,
-                                                        const Grid& g, double gam, long long n) {
+template <class T, int RS, bool DEV>
+__host__ __device__ __forceinline__ void face_flux_zone(const double* __restrict__ U,
+                                                        const T* __restrict__ PK,
+                                                        double* __restrict__ F, const Grid& g,
+                                                        double gam, long long n) {
   const int i = (int)(n % g.nx);
   const int j = (int)((n / g.nx) % g.ny);
   const int k = (int)(n / ((long long)g.nx * g.ny));
-  face_flux_axis<T, RS, 0>(PK, F, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), T(gam));
-  face_flux_axis<T, RS, 1>(PK, F, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), T(gam));
-  face_flux_axis<T, RS, 2>(PK, F, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), T(gam));
+  face_flux_axis<T, RS, 0, DEV>(U, PK, F, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
+  face_flux_axis<T, RS, 1, DEV>(U, PK, F, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
+  face_flux_axis<T, RS, 2, DEV>(U, PK, F, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
 }
 
 // eq. (6) in double: U -= dt/dx (F_{i+1/2} - F_{i-1/2}) + ... (y, z)
-template <class T>
-__host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, const T* __restrict__ F,
+__host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, const double* __restrict__ F,
                                                      const Grid& g, double h, double dx,
                                                      double dy, double dz, long long n) {
   const int i = (int)(n % g.nx);
@@ -531,8 +618,8 @@ __host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, con
     double u = U[(long long)v * g.N + n];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double fp = double(F[((long long)ax * 5 + v) * g.N + up[ax]]);
-      const double fm = double(F[((long long)ax * 5 + v) * g.N + n]);
+      const double fp = F[((long long)ax * 5 + v) * g.N + up[ax]];
+      const double fm = F[((long long)ax * 5 + v) * g.N + n];
       u = u - c[ax] * (fp - fm);
     }
     U[(long long)v * g.N + n] = u;
@@ -642,12 +729,12 @@ __host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B
   }
 }
 
-template <class S, class T, int SIDE>
+template <class S, class T, int SIDE, class Phys>
 __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], const T (&e)[S::NE][8],
-                                                        T gam, T* __restrict__ PK, long long N,
-                                                        long long n) {
+                                                        const Phys& ph, T* __restrict__ PK,
+                                                        long long N, long long n) {
   T ub[8], ua[8], fa[8], ue[4], fe[4];
-  S::template side_edges<SIDE, Mhd<T>>(w, e, gam, ub, ua, fa, ue, fe);
+  S::template side_edges<SIDE>(w, e, ph, ub, ua, fa, ue, fe);
   T* base = PK + (long long)SIDE * 32 * N + n;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
@@ -667,18 +754,21 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
 // predictor, positivity scaling and the six side packets of 32 values
 // (barycentre state, face averages of u and F, edge averages of u and F of
 // the field component along each edge's transverse axis).
-template <class T, int ORDER, int FORM>
+template <class T, int ORDER, int FORM, bool DEV>
 __host__ __device__ __forceinline__ void predict_zone_mhd(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
     double h, double inv_dx, double inv_dy, double inv_dz, double gam, long long n) {
   using S = typename SchemeOf<ORDER, FORM, T, 8>::type;
   constexpr int LS = S::LS, NE = S::NE;
+  double w0[8];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.N + n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w0[5 + c] = B0[(long long)c * g.N + n];
   T w[LS][8];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w[0][v] = T(U[(long long)v * g.N + n]);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) w[0][5 + c] = T(B0[(long long)c * g.N + n]);
+  for (int v = 0; v < 8; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
 #pragma unroll
   for (int m = 1; m < LS; ++m) {
 #pragma unroll
@@ -694,9 +784,9 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
       w[m][5 + c] = BN[((long long)(a - 1) * 3 + c) * g.N + n];
     }
   {
-    PosScan<T, 8> scan(w[0], T(gam));
+    PosScan<T, 8, DEV> scan(w0);
     S::spatial_points_all(w, scan);
-    const double theta = scan.near ? theta_spatial_tab(w, S::spatial_phi_all, gam) : 1.0;
+    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi_all, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -705,12 +795,13 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
         for (int v = 0; v < 8; ++v) w[m][v] *= th;
     }
   }
+  const auto ph = FluxOf<Mhd<T>, T, DEV>::make(w0, gam);
   T e[NE][8];
-  S::template predict<Mhd<T>>(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), T(gam));
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
   {
-    PosScan<T, 8> scan(w[0], T(gam));
+    PosScan<T, 8, DEV> scan(w0);
     S::facial_points_all(w, e, scan);
-    const double theta = scan.near ? theta_facial_tab(w, e, S::facial_phi_all, gam) : 1.0;
+    const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi_all, gam) : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -723,69 +814,119 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
         for (int v = 0; v < 8; ++v) e[m][v] *= th;
     }
   }
-  const T tg = T(gam);
-  store_side_mhd<S, T, 0>(w, e, tg, PK, g.N, n);
-  store_side_mhd<S, T, 1>(w, e, tg, PK, g.N, n);
-  store_side_mhd<S, T, 2>(w, e, tg, PK, g.N, n);
-  store_side_mhd<S, T, 3>(w, e, tg, PK, g.N, n);
-  store_side_mhd<S, T, 4>(w, e, tg, PK, g.N, n);
-  store_side_mhd<S, T, 5>(w, e, tg, PK, g.N, n);
+  store_side_mhd<S, T, 0>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 1>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 2>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 3>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 4>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 5>(w, e, ph, PK, g.N, n);
 }
 
 // HLL at the lower AXIS-face of zone n (MHD): the five hydro fluxes, and the
 // same HLL combination, with this face's speeds, of the edge averages on its
-// four edges (eq. 56-57).
-template <class T, int AXIS>
-__host__ __device__ __forceinline__ void face_flux_axis_mhd(const T* __restrict__ PK,
-                                                            T* __restrict__ F, T* __restrict__ FE,
+// four edges (eq. 56-57).  Deviation form as for Euler: the HLL of the zone
+// averages (double) plus the HLL of the deviations (FP32); on the edges the
+// zone-average part is the field component of the same double flux.
+template <class T, int AXIS, bool DEV>
+__host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __restrict__ U,
+                                                            const double* __restrict__ B0,
+                                                            const T* __restrict__ PK,
+                                                            double* __restrict__ F,
+                                                            double* __restrict__ FE,
                                                             const Grid& g, long long n,
-                                                            long long nl, T gam) {
+                                                            long long nl, double gam) {
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
+  constexpr int TA[2] = {AXIS == 0 ? 1 : 0, AXIS == 2 ? 1 : 2};   // transverse axes
   const T* L = PK + (long long)SL * 32 * g.N + nl;
   const T* R = PK + (long long)SR * 32 * g.N + n;
+  double wl[8], wr[8];
+  if constexpr (DEV) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      wl[v] = U[(long long)v * g.N + nl];
+      wr[v] = U[(long long)v * g.N + n];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      wl[5 + c] = B0[(long long)c * g.N + nl];
+      wr[5 + c] = B0[(long long)c * g.N + n];
+    }
+  }
   T ubl[8], ubr[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     ubl[v] = L[(long long)v * g.N];
     ubr[v] = R[(long long)v * g.N];
+    if constexpr (DEV) {
+      ubl[v] += T(wl[v]);
+      ubr[v] += T(wr[v]);
+    }
   }
+  const T tg = T(gam);
   const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
-  const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, gam);
-  const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, gam);
+  const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, tg);
+  const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, tg);
   const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
   const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
-  const T inv = T(1) / (lam_r - lam_l);
+  T ul[5], ur[5], fl[5], fr[5], out[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    const T ul = L[(long long)(8 + v) * g.N], ur = R[(long long)(8 + v) * g.N];
-    const T fl = L[(long long)(16 + v) * g.N], fr = R[(long long)(16 + v) * g.N];
-    F[((long long)AXIS * 5 + v) * g.N + n] = (lam_r * fl - lam_l * fr + lam_r * lam_l * (ur - ul)) * inv;
+    ul[v] = L[(long long)(8 + v) * g.N];
+    ur[v] = R[(long long)(8 + v) * g.N];
+    fl[v] = L[(long long)(16 + v) * g.N];
+    fr[v] = R[(long long)(16 + v) * g.N];
+    if constexpr (DEV) ur[v] += T(wr[v] - wl[v]);
   }
+  hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
+  T el[4], er[4], gl[4], gr[4], eout[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const T ul = L[(long long)(24 + q) * g.N], ur = R[(long long)(24 + q) * g.N];
-    const T fl = L[(long long)(28 + q) * g.N], fr = R[(long long)(28 + q) * g.N];
-    FE[((long long)AXIS * 4 + q) * g.N + n] = (lam_r * fl - lam_l * fr + lam_r * lam_l * (ur - ul)) * inv;
+    el[q] = L[(long long)(24 + q) * g.N];
+    er[q] = R[(long long)(24 + q) * g.N];
+    gl[q] = L[(long long)(28 + q) * g.N];
+    gr[q] = R[(long long)(28 + q) * g.N];
+    if constexpr (DEV) er[q] += T(wr[5 + TA[q / 2]] - wl[5 + TA[q / 2]]);
+  }
+  hll_combine<T, 4>(lam_l, lam_r, el, gl, er, gr, eout);
+  if constexpr (DEV) {
+    double Fl[8], Fr[8], Fa[8];
+    Mhd<double>::template flux<AXIS>(wl, Fl, gam);
+    Mhd<double>::template flux<AXIS>(wr, Fr, gam);
+    const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) Fa[v] = (lr * Fl[v] - ll * Fr[v]) * inv;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = Fa[v] + double(out[v]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      FE[((long long)AXIS * 4 + q) * g.N + n] = Fa[5 + TA[q / 2]] + double(eout[q]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = double(out[v]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.N + n] = double(eout[q]);
   }
 }
 
-template <class T>
-__host__ __device__ __forceinline__ void face_flux_zone_mhd(const T* __restrict__ PK, T* __restrict__ F,
-                                                            T* __restrict__ FE, const Grid& g,
+template <class T, bool DEV>
+__host__ __device__ __forceinline__ void face_flux_zone_mhd(const double* __restrict__ U,
+                                                            const double* __restrict__ B0,
+                                                            const T* __restrict__ PK,
+                                                            double* __restrict__ F,
+                                                            double* __restrict__ FE, const Grid& g,
                                                             double gam, long long n) {
   const int i = (int)(n % g.nx);
   const int j = (int)((n / g.nx) % g.ny);
   const int k = (int)(n / ((long long)g.nx * g.ny));
-  face_flux_axis_mhd<T, 0>(PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), T(gam));
-  face_flux_axis_mhd<T, 1>(PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), T(gam));
-  face_flux_axis_mhd<T, 2>(PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), T(gam));
+  face_flux_axis_mhd<T, 0, DEV>(U, B0, PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
+  face_flux_axis_mhd<T, 1, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
+  face_flux_axis_mhd<T, 2, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
 }
 
 // Edge fields at the three lower edges of zone n: E_c is the mean of the
 // four face values -eps_{dac} Flux_d(B_a) of eq. (7) on the faces that abut
 // the edge (edge q = 2 w + (side > 0) of a face, w the transverse slot of a).
-template <class T>
-__host__ __device__ __forceinline__ void edge_e_zone(const T* __restrict__ FE, double* __restrict__ E,
+__host__ __device__ __forceinline__ void edge_e_zone(const double* __restrict__ FE, double* __restrict__ E,
                                                      const Grid& g, long long n) {
   const int i = (int)(n % g.nx);
   const int j = (int)((n / g.nx) % g.ny);
@@ -793,7 +934,7 @@ __host__ __device__ __forceinline__ void edge_e_zone(const T* __restrict__ FE, d
   const long long mx = zone_of(wrap(i - 1, g.nx), j, k, g);
   const long long my = zone_of(i, wrap(j - 1, g.ny), k, g);
   const long long mz = zone_of(i, j, wrap(k - 1, g.nz), g);
-  auto fe = [&](int face, int q, long long zone) { return double(FE[((long long)face * 4 + q) * g.N + zone]); };
+  auto fe = [&](int face, int q, long long zone) { return FE[((long long)face * 4 + q) * g.N + zone]; };
   // E_x: y-faces (component B_z, sign -1), z-faces (component B_y, sign +1)
   double ex = 0.0;
   ex = ex - (fe(1, 2, n) + fe(1, 3, mz));

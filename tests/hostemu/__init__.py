@@ -16,6 +16,10 @@ DEPS = [SRC] + [os.path.join(ROOT, "paper_1006_2146_amd", "csrc", f)
 
 _lib = None
 
+# precision: "fp64" (the FP64 path), "mixed" (FP32 deviation form, the mixed
+# path), "fp64dev" (the deviation form in double)
+PRECISION = {"fp64": 0, "mixed": 1, "fp64dev": 2}
+
 
 def build(force=False):
     stale = force or not os.path.exists(LIB) or any(
@@ -58,8 +62,7 @@ def step(U, dt, order, form="modal", riemann="hll", precision="fp64",
     nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
     load().hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
                         dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
-                        1 if riemann == "linearized" else 0,
-                        0 if precision == "fp64" else 1, dt)
+                        1 if riemann == "linearized" else 0, PRECISION[precision], dt)
     return out
 
 
@@ -80,7 +83,7 @@ def step_mhd(U, B, dt, order, form="modal", precision="fp64", lengths=(1.0, 1.0,
     Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
     load().hostemu_step_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
-                            1 if form == "nodal" else 0, 0 if precision == "fp64" else 1, dt)
+                            1 if form == "nodal" else 0, PRECISION[precision], dt)
     return Uo, Bo
 
 

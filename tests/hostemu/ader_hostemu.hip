@@ -12,10 +12,11 @@
 
 using namespace ader;
 
-template <class T>
+template <class T, bool DEV>
 static void emu_step(double* U, Grid g, double dx, double dy, double dz, double gam, int order,
                      int form, int riemann, double dt) {
-  std::vector<T> W((size_t)19 * 5 * g.N), PK((size_t)90 * g.N), F((size_t)15 * g.N);
+  std::vector<T> W((size_t)19 * 5 * g.N), PK((size_t)90 * g.N);
+  std::vector<double> F((size_t)15 * g.N);
   const long long N = g.N;
   if (order == 2) {
     for (long long n = 0; n < N; ++n) minmod_zone<T>(U, W.data(), g, n);
@@ -31,21 +32,21 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
     if (order == 2 && form == 1)
-      predict_zone<T, 2, 1>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 2, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
-      predict_zone<T, 2, 0>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 2, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
-      predict_zone<T, 3, 0>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 3, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else
-      predict_zone<T, 4, 0>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 4, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
   }
   for (long long n = 0; n < N; ++n) {
     if (riemann == 0)
-      face_flux_zone<T, 0>(PK.data(), F.data(), g, gam, n);
+      face_flux_zone<T, 0, DEV>(U, PK.data(), F.data(), g, gam, n);
     else
-      face_flux_zone<T, 1>(PK.data(), F.data(), g, gam, n);
+      face_flux_zone<T, 1, DEV>(U, PK.data(), F.data(), g, gam, n);
   }
-  for (long long n = 0; n < N; ++n) update_zone<T>(U, F.data(), g, dt, dx, dy, dz, n);
+  for (long long n = 0; n < N; ++n) update_zone(U, F.data(), g, dt, dx, dy, dz, n);
 }
 
 template <class T>
@@ -78,13 +79,13 @@ static void emu_recon(const double* src, T* W, Grid g, int order, int nvar) {
   }
 }
 
-template <class T>
+template <class T, bool DEV>
 static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, double dz, double gam,
                          int order, int form, double dt) {
   const long long N = g.N;
   std::vector<T> W((size_t)19 * 5 * N), WB((size_t)19 * 3 * N), BN((size_t)9 * N),
-      PK((size_t)6 * 32 * N), F((size_t)15 * N), FE((size_t)12 * N);
-  std::vector<double> B0((size_t)3 * N), E((size_t)3 * N);
+      PK((size_t)6 * 32 * N);
+  std::vector<double> B0((size_t)3 * N), E((size_t)3 * N), F((size_t)15 * N), FE((size_t)12 * N);
   for (long long n = 0; n < N; ++n) {
     if (order == 2) bface_zone<T, 2>(B, B0.data(), BN.data(), g, n);
     if (order == 3) bface_zone<T, 3>(B, B0.data(), BN.data(), g, n);
@@ -95,30 +96,36 @@ static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, dou
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
     if (order == 2 && form == 1)
-      predict_zone_mhd<T, 2, 1>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 1, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
-      predict_zone_mhd<T, 2, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
-      predict_zone_mhd<T, 3, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 3, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else
-      predict_zone_mhd<T, 4, 0>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 4, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
   }
-  for (long long n = 0; n < N; ++n) face_flux_zone_mhd<T>(PK.data(), F.data(), FE.data(), g, gam, n);
-  for (long long n = 0; n < N; ++n) edge_e_zone<T>(FE.data(), E.data(), g, n);
-  for (long long n = 0; n < N; ++n) update_zone<T>(U, F.data(), g, dt, dx, dy, dz, n);
+  for (long long n = 0; n < N; ++n)
+    face_flux_zone_mhd<T, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
+  for (long long n = 0; n < N; ++n) edge_e_zone(FE.data(), E.data(), g, n);
+  for (long long n = 0; n < N; ++n) update_zone(U, F.data(), g, dt, dx, dy, dz, n);
   for (long long n = 0; n < N; ++n) ct_zone(B, E.data(), g, dt, dx, dy, dz, n);
 }
 
 extern "C" {
+
+// precision: 0 FP64 point form (the FP64 path), 1 FP32 deviation form (the
+// mixed path), 2 FP64 deviation form (checks the deviation algebra alone).
 
 // One MHD step of the host build, in place on U[5][N] and the face field B[3][N].
 int hostemu_step_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,
                      double dz, double gam, int order, int form, int precision, double dt) {
   Grid g{nx, ny, nz, (long long)nx * ny * nz};
   if (precision == 0)
-    emu_step_mhd<double>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    emu_step_mhd<double, false>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  else if (precision == 1)
+    emu_step_mhd<float, true>(U, B, g, dx, dy, dz, gam, order, form, dt);
   else
-    emu_step_mhd<float>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    emu_step_mhd<double, true>(U, B, g, dx, dy, dz, gam, order, form, dt);
   return 0;
 }
 
@@ -136,9 +143,11 @@ int hostemu_step(double* U, int nx, int ny, int nz, double dx, double dy, double
                  int order, int form, int riemann, int precision, double dt) {
   Grid g{nx, ny, nz, (long long)nx * ny * nz};
   if (precision == 0)
-    emu_step<double>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
+    emu_step<double, false>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
+  else if (precision == 1)
+    emu_step<float, true>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
   else
-    emu_step<float>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
+    emu_step<double, true>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
   return 0;
 }
 

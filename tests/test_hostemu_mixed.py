@@ -1,0 +1,82 @@
+"""Accuracy of the mixed-precision path (FP32 bulk in deviation form, FP64
+update), run through the host build of the kernel source: its L1 distance to
+the FP64 path must stay below 1% of the scheme's truncation error, measured
+against the exact solution of the advected density wave (Sec. VI.1), and it
+must keep the FP64 properties that do not depend on the bulk precision
+(conservation, constant states, positivity on a strong blast)."""
+
+import numpy as np
+import pytest
+
+from paper_1006_2146_amd import workloads
+from tests import hostemu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    hostemu.load()
+
+
+def _run(U, order, precision, T, rs="hll", cfl=0.3):
+    t = 0.0
+    while t < T - 1e-14:
+        dt = min(hostemu.compute_dt(U, cfl), T - t)
+        U = hostemu.step(U, dt, order, riemann=rs, precision=precision)
+        t += dt
+    return U
+
+
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("order,n", [(2, 24), (3, 24), (4, 20)])
+def test_mixed_error_below_one_percent_of_truncation(order, n, rs):
+    T = 0.02
+    U0 = workloads.density_wave((n, n, n))
+    U64 = _run(U0, order, "fp64", T, rs)
+    U32 = _run(U0, order, "mixed", T, rs)
+    exact = workloads.density_wave((n, n, n), t=T)
+    trunc = np.abs(U64[0] - exact[0]).mean()
+    mixed = np.abs(U32[0] - U64[0]).mean()
+    assert mixed <= 1e-2 * trunc, (mixed, trunc)
+
+
+def test_mixed_conserves_and_keeps_constant_states():
+    U0 = workloads.random_smooth((9, 8, 7), seed=5)
+    U = _run(U0, 3, "mixed", 0.01)
+    tot0, tot1 = U0.sum(axis=(1, 2, 3)), U.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(U0).sum(axis=(1, 2, 3)))
+    C = np.zeros((5, 4, 5, 6))
+    C[:] = np.array([1.3, 0.2, -0.1, 0.3, 2.5])[:, None, None, None]
+    for order in (2, 3, 4):
+        assert np.array_equal(hostemu.step(C, 0.01, order, precision="mixed"), C)
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_mixed_blast_stays_physical(order):
+    U = workloads.blast((10, 10, 10), p_in=100.0, p_out=0.1, radius=0.25)
+    for _ in range(4):
+        dt = hostemu.compute_dt(U, 0.3)
+        assert dt > 0
+        U = hostemu.step(U, dt, order, precision="mixed")
+    rho = U[0]
+    p = 0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / rho)
+    assert np.all(np.isfinite(U)) and rho.min() > 0 and p.min() > 0
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_mixed_mhd_error_and_div_b(order):
+    # torsional Alfven wave along the diagonal (Sec. VI.3), exact solution known
+    from oracle.bweno import divergence
+    n = 10
+    U, B = workloads.alfven_wave_diagonal((n, n, n))
+    U64, B64 = U, B
+    t = 0.0
+    for _ in range(3):
+        dt = hostemu.compute_dt_mhd(U64, B64, 0.3)
+        U64, B64 = hostemu.step_mhd(U64, B64, dt, order, precision="fp64")
+        U, B = hostemu.step_mhd(U, B, dt, order, precision="mixed")
+        t += dt
+    _, Be = workloads.alfven_wave_diagonal((n, n, n), t=t)
+    trunc = np.abs(B64 - Be).mean()
+    assert np.abs(B - B64).mean() <= 1e-2 * trunc
+    dx = (1.0 / n,) * 3
+    assert np.abs(divergence(B, dx)).max() <= 1e-12 * np.abs(B).max() / dx[0]

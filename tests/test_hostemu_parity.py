@@ -1,6 +1,9 @@
-"""CPU parity of the kernel source (host build of ader_kernels.h) against the
-oracle: the same FP64 bar as the GPU parity tests, so logic errors in the
-generated scheme code or the kernels show up before any GPU run."""
+"""CPU parity of the kernel source (host build of the per-zone kernel code)
+against the oracle: the same FP64 bar as the GPU parity tests, so logic
+errors in the generated scheme code or the kernels show up before any GPU
+run.  Each FP64 case runs in both forms: the point form of the FP64 path and
+the deviation form of the mixed path evaluated in double, which checks the
+deviation algebra exactly (its FP32 accuracy is tested separately)."""
 
 import numpy as np
 import pytest
@@ -23,13 +26,13 @@ def _built():
     hostemu.load()
 
 
-def _steps(U0, order, form, rs, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3):
+def _steps(U0, order, form, rs, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, precision="fp64"):
     cfg = OracleConfig(order=order, form=form, riemann=rs, lengths=lengths)
     U = U0
     for it in range(nsteps):
         dt = hostemu.compute_dt(U, cfl, lengths)
         assert abs(dt - oracle_dt(U, cfg, cfl)) <= 1e-14 * dt
-        Ue = hostemu.step(U, dt, order, form, rs, lengths=lengths)
+        Ue = hostemu.step(U, dt, order, form, rs, precision=precision, lengths=lengths)
         Uo = oracle_step(U, dt, cfg)
         err = rel_l1(Ue, Uo)
         assert np.all(err <= 1e-12), (it, err)
@@ -37,33 +40,40 @@ def _steps(U0, order, form, rs, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3):
     return U
 
 
+FORMS = ["fp64", "fp64dev"]
+
+
+@pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order,form,rs", CASES)
-def test_kernel_source_smooth(order, form, rs):
+def test_kernel_source_smooth(order, form, rs, precision):
     _steps(workloads.random_smooth((7, 9, 11), seed=order), order, form, rs, 2,
-           lengths=(1.0, 0.8, 1.3))
+           lengths=(1.0, 0.8, 1.3), precision=precision)
 
 
+@pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order,form,rs", CASES)
-def test_kernel_source_blast(order, form, rs):
-    _steps(workloads.blast((10, 10, 10), p_in=100.0, p_out=0.1, radius=0.25), order, form, rs, 3)
+def test_kernel_source_blast(order, form, rs, precision):
+    _steps(workloads.blast((10, 10, 10), p_in=100.0, p_out=0.1, radius=0.25), order, form, rs, 3,
+           precision=precision)
 
 
+@pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_kernel_source_tiny_meshes(order):
+def test_kernel_source_tiny_meshes(order, precision):
     for shape in [(1, 1, 1), (2, 3, 1), (3, 1, 2)]:
-        _steps(workloads.random_smooth(shape, seed=3), order, "modal", "hll", 1)
+        _steps(workloads.random_smooth(shape, seed=3), order, "modal", "hll", 1, precision=precision)
 
 
 MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
 
 
-def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3):
+def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, precision="fp64"):
     cfg = OracleConfig(order=order, form=form, gamma=5.0 / 3.0, lengths=lengths)
     U, B = U0, B0
     for it in range(nsteps):
         dt = hostemu.compute_dt_mhd(U, B, cfl, lengths)
         assert abs(dt - oracle_dt(U, cfg, cfl, B)) <= 1e-14 * dt
-        Ue, Be = hostemu.step_mhd(U, B, dt, order, form, lengths=lengths)
+        Ue, Be = hostemu.step_mhd(U, B, dt, order, form, precision=precision, lengths=lengths)
         Uo, Bo = oracle_step(U, dt, cfg, B)
         err = rel_l1(Ue, Uo)
         errb = rel_l1(Be, Bo)
@@ -72,13 +82,15 @@ def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3):
     return U, B
 
 
+@pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order,form", MHD_CASES)
-def test_kernel_source_mhd_random_field(order, form):
+def test_kernel_source_mhd_random_field(order, form, precision):
     U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=order)
-    _steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2))
+    _steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), precision=precision)
 
 
+@pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_kernel_source_mhd_alfven(order):
+def test_kernel_source_mhd_alfven(order, precision):
     U0, B0 = workloads.alfven_wave_diagonal((6, 6, 6))
-    _steps_mhd(U0, B0, order, "modal", 2)
+    _steps_mhd(U0, B0, order, "modal", 2, precision=precision)
