@@ -41,31 +41,41 @@ def flop_counts():
 
 
 def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None):
+    """Autotune the launch shapes, time `steps` graph-replayed CFL steps
+    (wall clock between synchronisations), then take a separate eager pass
+    with per-stage HIP events for the stage breakdown."""
     nz, ny, nx = SHAPE
     N = nx * ny * nz
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
     mhd = B0 is not None
     s = ader.Solver(SHAPE, order=order, riemann=riemann, precision=precision,
                     stream=stream.cuda_stream, gamma=5.0 / 3.0 if mhd else 1.4,
                     system=ader.ADER_MHD if mhd else ader.ADER_EULER)
     try:
-        dU = torch.from_numpy(U0).to("cuda")            # resident state, 5 x N doubles
-        dB = torch.from_numpy(B0).to("cuda") if mhd else None
+        with torch.cuda.stream(stream):
+            dU = torch.from_numpy(U0).to("cuda")            # resident state, 5 x N doubles
+            dB = torch.from_numpy(B0).to("cuda") if mhd else None
+        stream.synchronize()
         ader.ader_bind_device_state(s.ctx, dU.data_ptr(), dB.data_ptr() if mhd else None)
+        ader.ader_autotune(s.ctx, 2)
+        ader.ader_set_graph(s.ctx, True)
         for _ in range(warmup):
             s.step_cfl(CFL)
         s.synchronize()
-        ader.ader_set_timing(s.ctx, True)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             s.step_cfl(CFL)
-        torch.cuda.synchronize()
+        s.synchronize()                                  # raises on an unphysical state
         t1 = time.perf_counter()
+        # stage breakdown: eager steps with events around each stage
+        ader.ader_set_timing(s.ctx, True)
+        for _ in range(steps):
+            s.step_cfl(CFL)
         stages = ader.ader_stage_times(s.ctx)
         ader.ader_set_timing(s.ctx, False)
-        s.synchronize()                                  # raises on an unphysical state
+        s.synchronize()
         finite = bool(torch.isfinite(dU).all().item())
+        launch = ader.ader_get_launch(s.ctx)
     finally:
         s.close()
     wall = t1 - t0
@@ -73,8 +83,48 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         "zone_updates_per_s": N * steps / wall,
         "ms_per_step": 1e3 * wall / steps,
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+        "launch": launch,
         "finite": finite,
     }
+
+
+def run_ensemble(ader, torch, steps, warmup):
+    """The batched ensemble: 64 uneven problems, order 3, HLL, mixed
+    precision, one persistent launch per stage, graph-replayed, autotuned."""
+    from paper_1006_2146_amd import workloads
+    ens = workloads.ensemble()
+    shapes = [s for s, _ in ens]
+    zones = int(sum(np.prod(s) for s in shapes))
+    out = {"workload": "64 problems, sides from {32,48,64,96} per axis (seed 4096), order 3 "
+                       "modal, HLL, gamma 1.4, smooth random modes", "zones": zones}
+    for name, prec in (("mixed", ader.ADER_MIXED), ("fp64", ader.ADER_FP64)):
+        stream = torch.cuda.Stream()
+        with ader.BatchSolver(shapes, order=3, precision=prec, stream=stream.cuda_stream) as b:
+            for i, (_, U) in enumerate(ens):
+                b.set_state(i, U)
+            ader.ader_autotune(b.ctx, 2)
+            ader.ader_set_graph(b.ctx, True)
+            for _ in range(warmup):
+                b.step_cfl(CFL)
+            b.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                b.step_cfl(CFL)
+            b.synchronize()
+            t1 = time.perf_counter()
+            ader.ader_set_timing(b.ctx, True)
+            for _ in range(steps):
+                b.step_cfl(CFL)
+            stages = ader.ader_stage_times(b.ctx)
+            ader.ader_set_timing(b.ctx, False)
+            b.synchronize()
+            out[name] = {"zone_updates_per_s": zones * steps / (t1 - t0),
+                         "ms_per_step": 1e3 * (t1 - t0) / steps,
+                         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+                         "launch": ader.ader_get_launch(b.ctx)}
+        log("ensemble", name, "%.3e zone-updates/s" % out[name]["zone_updates_per_s"])
+    out["mixed_over_fp64"] = out["mixed"]["zone_updates_per_s"] / out["fp64"]["zone_updates_per_s"]
+    return out
 
 
 def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
@@ -143,6 +193,8 @@ def main():
     ap.add_argument("--variants", default="fp64-hll,fp64-lin,mixed-hll,mixed-lin")
     ap.add_argument("--mhd-variants", default="fp64,mixed",
                     help="order-4 MHD runs on the 128^3 random-field workload ('' for none)")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 64-problem batched ensemble")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -191,12 +243,17 @@ def main():
             log("accuracy", name)
             mhd_variants[name]["accuracy"] = accuracy(ader, Um, 4, ader.ADER_HLL, 3, B0=Bm)
 
-    primary = "fp64-hll" if "fp64-hll" in variants else next(iter(variants))
+    ensemble = None
+    if not args.no_ensemble:
+        log("batched ensemble")
+        ensemble = run_ensemble(ader, torch, args.steps, args.warmup)
+
+    primary = "mixed-hll" if "mixed-hll" in variants else next(iter(variants))
     pv = variants[primary]
-    flops_zone = flop_counts()["M3"]["total"]
+    dtype = "f64" if primary.startswith("fp64") else "f32"
+    flops_zone = flop_counts()["M3" if dtype == "f64" else "M3-dev"]["total"]
     pred_ms = pv["stage_ms_per_step"]["predict"]
     achieved = flops_zone * N / (pred_ms * 1e-3) / 1e12
-    dtype = "f64" if primary.startswith("fp64") else "f32"
     roofline = {"bound": "alu", "kernel": "k_predict", "achieved": achieved,
                 "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
@@ -217,12 +274,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "system": "euler", "order": 3, "form": "modal",
                    "riemann": primary.split("-")[1], "precision": primary.split("-")[0],
-                   "zones": N, "cfl": CFL, "gamma": 1.4},
+                   "precision_detail": "FP32 bulk in deviation form; FP64 state, fluxes, "
+                                       "update and dt" if dtype == "f32" else "FP64 throughout",
+                   "zones": N, "cfl": CFL, "gamma": 1.4, "steps_replayed_as": "hipGraph",
+                   "launch": "autotuned"},
         "roofline": roofline,
         "variants": variants,
         "mhd_variants": {"workload": "mhd-random-field-128^3, order 4 modal, HLL, CT, gamma 5/3",
                          **mhd_variants},
+        "ensemble": ensemble,
     }
+    if "mixed-hll" in variants and "fp64-hll" in variants:
+        out["mixed_over_fp64"] = (variants["mixed-hll"]["zone_updates_per_s"] /
+                                  variants["fp64-hll"]["zone_updates_per_s"])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U0)

@@ -27,6 +27,13 @@
  *    it allocates are freed by ader_destroy.  A device state bound with
  *    ader_bind_device_state stays owned by the caller and must outlive the
  *    context (or the next bind).
+ *  - Batches: ader_batch_create makes one context for n independent periodic
+ *    problems of any sizes; every stage of a step is one persistent launch
+ *    over the zones of all of them, each problem with its own CFL dt.  The
+ *    context's arrays hold the problems one after the other: with
+ *    S = sum of N_i = nx_i ny_i nz_i, the state is U[5][S] (problem i at
+ *    offsets base_i = N_0 + ... + N_{i-1} of each row) and B[3][S].  A single
+ *    problem is a batch of one (S = N), so every call below applies to both.
  */
 #ifndef ADER_H
 #define ADER_H
@@ -81,7 +88,8 @@ int ader_set_precision(ader_ctx* ctx, int precision);
 
 /* Copy a host state U[5][nz][ny][nx] (conserved zone averages) and, for
  * MHD, the face field B[3][nz][ny][nx] (NULL for Euler; ADER_EINVAL if the
- * presence of B does not match the system) to the device.  Returns
+ * presence of B does not match the system) to the device (a batch: the
+ * whole U[5][S], B[3][S] layout).  Returns
  * ADER_ESTATE (and keeps the old state) if any zone has rho <= 0, P <= 0 or
  * a non-finite value (MHD pressure with the face-mean zone field). */
 int ader_set_state(ader_ctx* ctx, const double* U, const double* B);
@@ -98,19 +106,21 @@ int ader_get_state(ader_ctx* ctx, double* U, double* B);
 
 /* dt = cfl / max over zones of sum_d (|v_d| + c_d) / dx_d (c_d the sound
  * speed, or for MHD the fast speed along d with the face-mean zone field),
- * computed on the device into the context's dt slot.  If dt_out is not
- * NULL the value is copied back (synchronises) and ADER_ESTATE is returned
- * if a zone is unphysical.  cfl > 0. */
+ * computed on the device into the context's dt slot (per problem).  If
+ * dt_out is not NULL the value is copied back (synchronises; single-problem
+ * contexts only, ADER_EINVAL for a batch) and ADER_ESTATE is returned if a
+ * zone is unphysical.  cfl > 0. */
 int ader_compute_dt(ader_ctx* ctx, double cfl, double* dt_out);
 
-/* One ADER-CG step of size dt > 0 (finite).  Asynchronous. */
+/* One ADER-CG step of size dt > 0 (finite; every problem of a batch).
+ * Asynchronous. */
 int ader_step(ader_ctx* ctx, double dt);
 
 /* dt by CFL on the device, then one step with it; no host round trip. */
 int ader_step_cfl(ader_ctx* ctx, double cfl);
 
 /* The dt of the latest ader_compute_dt / ader_step_cfl / ader_step
- * (synchronises). */
+ * (synchronises); dt_out holds one value per problem (n for a batch). */
 int ader_get_dt(ader_ctx* ctx, double* dt_out);
 
 /* Wait for all queued work; returns ADER_ESTATE if a dt evaluation since
@@ -137,6 +147,54 @@ const char* ader_strerror(int code);
 
 /* Free the context and its device buffers (NULL is a no-op). */
 void ader_destroy(ader_ctx* ctx);
+
+/* ---- batches, graphs, launch shapes (the batched execution of the step) --
+ *
+ * ader_batch_create: n >= 1 problems, meshes[i] as in ader_create; all share
+ * the system and the settings of the set_* calls.  Buffers are sized for
+ * order 4 in FP64 over all S zones.  Errors as ader_create. */
+int ader_batch_create(int n, const ader_mesh* meshes, int system, int device, void* stream,
+                      ader_ctx** out);
+
+/* Number of problems of the context (1 for ader_create). */
+int ader_batch_size(ader_ctx* ctx, int* n_out);
+
+/* Copy problem i's host state U[5][nz_i][ny_i][nx_i] (and, MHD, its face
+ * field B[3][...]) into the batch (synchronises).  ADER_ESTATE as in
+ * ader_set_state.  Stepping needs every problem set (ADER_ESEQ before). */
+int ader_batch_set_state(ader_ctx* ctx, int i, const double* U, const double* B);
+
+/* Copy problem i's state back into U[5][...] and, if B is not NULL (MHD),
+ * B[3][...] (synchronises). */
+int ader_batch_get_state(ader_ctx* ctx, int i, double* U, double* B);
+
+/* ader_step_cfl for every problem with its own dt; if dts_out is not NULL
+ * (n doubles) the dt values are copied back (synchronises) and ADER_ESTATE
+ * is returned if a zone of any problem was unphysical. */
+int ader_batch_step_cfl(ader_ctx* ctx, double cfl, double* dts_out);
+
+/* Graph mode (enable != 0): ader_step_cfl / ader_batch_step_cfl replay one
+ * hipGraph of the whole CFL step (dt reduction and all stages; no memset
+ * nodes), captured on first use and again whenever cfl, a set_* setting,
+ * the launch shapes or the bound state buffers change.  Needs a stream
+ * other than NULL (ADER_EUNSUPPORTED).  Stage timing, while on, runs the
+ * step eagerly. */
+int ader_set_graph(ader_ctx* ctx, int enable);
+
+/* Autotuner: for each kernel class (dt, reconstruction, predictor, fluxes,
+ * update) times every candidate launch shape -- threads per block in
+ * {64, 128, 256} x persistent blocks per compute unit -- on the context's
+ * own problems and settings, `reps` launches each (1..1000), and keeps the
+ * fastest.  The state and dt are saved before and restored after, so the
+ * solution does not advance; results do not depend on the launch shape.
+ * Needs a state (ADER_ESEQ); allocates a temporary copy of it. */
+int ader_autotune(ader_ctx* ctx, int reps);
+
+/* Launch shape per kernel class (arrays of 5, in the class order above):
+ * threads per block (64, 128, 192 or 256) and blocks per compute unit
+ * (1..64). */
+int ader_get_launch(ader_ctx* ctx, int* block_out, int* blocks_per_cu_out);
+int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
 
 #ifdef __cplusplus
 }

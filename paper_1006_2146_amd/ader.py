@@ -30,7 +30,11 @@ EXPORTS = [
     "ader_get_state", "ader_compute_dt", "ader_step", "ader_step_cfl",
     "ader_get_dt", "ader_synchronize", "ader_set_timing", "ader_stage_times",
     "ader_device_bytes", "ader_strerror", "ader_destroy",
+    "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
+    "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
+    "ader_set_launch",
 ]
+LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
 
 
@@ -80,6 +84,15 @@ def load():
         "ader_device_bytes": ([P, DP], I),
         "ader_strerror": ([I], ctypes.c_char_p),
         "ader_destroy": ([P], None),
+        "ader_batch_create": ([I, ctypes.POINTER(ader_mesh), I, I, P, ctypes.POINTER(P)], I),
+        "ader_batch_size": ([P, ctypes.POINTER(I)], I),
+        "ader_batch_set_state": ([P, I, DP, DP], I),
+        "ader_batch_get_state": ([P, I, DP, DP], I),
+        "ader_batch_step_cfl": ([P, D, DP], I),
+        "ader_set_graph": ([P, I], I),
+        "ader_autotune": ([P, I], I),
+        "ader_get_launch": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "ader_set_launch": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -168,10 +181,11 @@ def ader_step_cfl(ctx, cfl):
     _check(load().ader_step_cfl(ctx, cfl), "ader_step_cfl")
 
 
-def ader_get_dt(ctx):
-    dt = ctypes.c_double()
-    _check(load().ader_get_dt(ctx, ctypes.byref(dt)), "ader_get_dt")
-    return dt.value
+def ader_get_dt(ctx, n=1):
+    """dt of the latest step; a list of n values for a batch of n problems."""
+    dt = (ctypes.c_double * n)()
+    _check(load().ader_get_dt(ctx, dt), "ader_get_dt")
+    return dt[0] if n == 1 else list(dt)
 
 
 def ader_synchronize(ctx):
@@ -201,6 +215,140 @@ def ader_destroy(ctx):
         load().ader_destroy(ctx)
 
 
+def ader_batch_create(meshes, system=ADER_EULER, device=0, stream=None):
+    """meshes: sequence of (nx, ny, nz, lx, ly, lz)."""
+    lib = load()
+    arr = (ader_mesh * len(meshes))(*[ader_mesh(*m) for m in meshes])
+    out = ctypes.c_void_p()
+    rc = lib.ader_batch_create(len(meshes), arr, system, device,
+                               ctypes.c_void_p(stream) if stream else None, ctypes.byref(out))
+    _check(rc, "ader_batch_create")
+    return out
+
+
+def ader_batch_size(ctx):
+    n = ctypes.c_int()
+    _check(load().ader_batch_size(ctx, ctypes.byref(n)), "ader_batch_size")
+    return n.value
+
+
+def ader_batch_set_state(ctx, i, U, B=None):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if B is not None:
+        B = np.ascontiguousarray(B, dtype=np.float64)
+    _check(load().ader_batch_set_state(ctx, i, _dptr(U), None if B is None else _dptr(B)),
+           "ader_batch_set_state")
+
+
+def ader_batch_get_state(ctx, i, shape, with_b=False):
+    U = np.empty(shape, dtype=np.float64)
+    B = np.empty((3,) + tuple(shape[1:]), dtype=np.float64) if with_b else None
+    _check(load().ader_batch_get_state(ctx, i, _dptr(U), None if B is None else _dptr(B)),
+           "ader_batch_get_state")
+    return (U, B) if with_b else U
+
+
+def ader_batch_step_cfl(ctx, cfl, n=None):
+    """One CFL step of every problem; with n, returns the n dt values taken."""
+    if n is None:
+        _check(load().ader_batch_step_cfl(ctx, cfl, None), "ader_batch_step_cfl")
+        return None
+    dts = np.empty(n, dtype=np.float64)
+    _check(load().ader_batch_step_cfl(ctx, cfl, _dptr(dts)), "ader_batch_step_cfl")
+    return dts
+
+
+def ader_set_graph(ctx, enable):
+    _check(load().ader_set_graph(ctx, 1 if enable else 0), "ader_set_graph")
+
+
+def ader_autotune(ctx, reps=3):
+    _check(load().ader_autotune(ctx, reps), "ader_autotune")
+
+
+def ader_get_launch(ctx):
+    """{class: (threads per block, blocks per CU)}."""
+    k = len(LAUNCH_CLASSES)
+    b = (ctypes.c_int * k)()
+    g = (ctypes.c_int * k)()
+    _check(load().ader_get_launch(ctx, b, g), "ader_get_launch")
+    return {name: (b[i], g[i]) for i, name in enumerate(LAUNCH_CLASSES)}
+
+
+def ader_set_launch(ctx, shapes):
+    """shapes: {class: (threads per block, blocks per CU)} for every class."""
+    k = len(LAUNCH_CLASSES)
+    b = (ctypes.c_int * k)(*[shapes[n][0] for n in LAUNCH_CLASSES])
+    g = (ctypes.c_int * k)(*[shapes[n][1] for n in LAUNCH_CLASSES])
+    _check(load().ader_set_launch(ctx, b, g), "ader_set_launch")
+
+
+def _configure(ctx, gamma, order, form, riemann, precision):
+    ader_set_gamma(ctx, gamma)
+    ader_set_order(ctx, order, form)
+    ader_set_riemann(ctx, riemann)
+    ader_set_precision(ctx, precision)
+
+
+class BatchSolver:
+    """Owner of a batch context of independent problems (marshalling only).
+    shapes: (nz, ny, nx) per problem; lengths: one (lx, ly, lz) or one per
+    problem."""
+
+    def __init__(self, shapes, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3, form=ADER_MODAL,
+                 riemann=ADER_HLL, precision=ADER_FP64, device=0, stream=None,
+                 system=ADER_EULER):
+        if lengths and not isinstance(lengths[0], (tuple, list)):
+            lengths = [lengths] * len(shapes)
+        self.shapes = [tuple(s) for s in shapes]
+        self.mhd = system == ADER_MHD
+        meshes = [(s[2], s[1], s[0]) + tuple(L) for s, L in zip(self.shapes, lengths)]
+        self.ctx = ader_batch_create(meshes, system=system, device=device, stream=stream)
+        try:
+            _configure(self.ctx, gamma, order, form, riemann, precision)
+        except Exception:
+            self.close()
+            raise
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def set_state(self, i, U, B=None):
+        ader_batch_set_state(self.ctx, i, U, B)
+
+    def get_state(self, i):
+        return ader_batch_get_state(self.ctx, i, (5,) + self.shapes[i], with_b=self.mhd)
+
+    def step_cfl(self, cfl, want_dts=False):
+        return ader_batch_step_cfl(self.ctx, cfl, len(self) if want_dts else None)
+
+    def step(self, dt):
+        ader_step(self.ctx, dt)
+
+    def dts(self):
+        return ader_get_dt(self.ctx, len(self))
+
+    def synchronize(self):
+        ader_synchronize(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            ader_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """Convenience owner of one context (still marshalling only)."""
 
@@ -212,10 +360,7 @@ class Solver:
         self.mhd = system == ADER_MHD
         self.ctx = ader_create(nx, ny, nz, *lengths, system=system, device=device, stream=stream)
         try:
-            ader_set_gamma(self.ctx, gamma)
-            ader_set_order(self.ctx, order, form)
-            ader_set_riemann(self.ctx, riemann)
-            ader_set_precision(self.ctx, precision)
+            _configure(self.ctx, gamma, order, form, riemann, precision)
         except Exception:
             self.close()
             raise

@@ -1,0 +1,138 @@
+// Host-side context shared by the library's translation units: the device
+// buffers, the problem table of a batch, the launch configuration and the
+// stage functions of each (system, precision, order, form) variant.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/ader.h"
+#include "zone_ops.h"
+
+namespace ader {
+
+// One periodic mesh of a batch, as the kernels see it.  Its zones sit at
+// indices base .. base+N-1 of every batch array (stride S = all zones).
+struct Problem {
+  int nx, ny, nz, pad;
+  long long N, base;
+  double dx, dy, dz;
+};
+
+// Kernel argument: the device problem table and the array stride.
+struct Batch {
+  const Problem* P;
+  int np;
+  long long S;
+};
+
+// Launch shape of one kernel class: threads per block and the number of
+// persistent blocks per compute unit.
+struct LaunchShape {
+  int block;
+  int blocks_per_cu;
+};
+
+enum { kClassDt = 0, kClassRecon = 1, kClassPredict = 2, kClassFlux = 3, kClassUpdate = 4,
+       kNumClasses = 5 };
+
+}  // namespace ader
+
+struct ader_ctx;
+
+namespace ader {
+
+// The stages of one step for one variant, each one persistent launch over
+// every problem of the context (reconstruction: one per sweep).
+struct StageFns {
+  int (*recon)(ader_ctx*);
+  int (*predict)(ader_ctx*);
+  int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
+  int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
+};
+
+}  // namespace ader
+
+struct ader_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  // problems: host copy and device table
+  std::vector<ader::Problem> probs;
+  ader::Problem* d_probs = nullptr;
+  long long S = 0;                 // total zones (array stride)
+  double gamma = 1.4;
+  int system = ADER_EULER;
+  int order = 3, form = ADER_MODAL, riemann = ADER_HLL, precision = ADER_FP64;
+  double* U = nullptr;
+  bool owns_U = true;
+  void* W = nullptr;
+  void* PK = nullptr;
+  double* F = nullptr;
+  // MHD: face fields, zone field b_0, its modes, the Sec. III normal moments,
+  // face-edge fluxes and edge fields
+  double* B = nullptr;
+  bool owns_B = true;
+  double* B0 = nullptr;
+  void* WB = nullptr;
+  void* BN = nullptr;
+  double* FE = nullptr;
+  double* E = nullptr;
+  // per problem: dt, the CFL rate as the bit pattern of a non-negative
+  // double (atomic max), and the status flag of the dt evaluations
+  double* d_dt = nullptr;
+  unsigned long long* d_rate = nullptr;
+  int* d_bad = nullptr;
+  bool have_state = false;
+  std::vector<char> set_flags;     // problems given a state by ader_batch_set_state
+  bool have_dt = false;
+  size_t bytes = 0;
+  ader::LaunchShape shape[ader::kNumClasses] = {{256, 8}, {256, 8}, {128, 4}, {256, 8}, {256, 8}};
+  // stage timing: events recorded around each stage while enabled
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  std::vector<int> marks;  // stage of each (start, stop) event pair
+  // hipGraph of one CFL step, rebuilt when the configuration changes
+  bool use_graph = false;
+  hipGraphExec_t graph_exec = nullptr;
+  double graph_cfl = 0.0;
+  unsigned long long graph_key = 0;
+
+  ader::Batch batch() const { return ader::Batch{d_probs, (int)probs.size(), S}; }
+  int np() const { return (int)probs.size(); }
+};
+
+namespace ader {
+
+inline int check(hipError_t e) { return e == hipSuccess ? ADER_OK : ADER_EDEVICE; }
+inline int launched() { return check(hipGetLastError()); }
+
+#define ADER_TRY(expr)              \
+  do {                              \
+    int _rc = (expr);               \
+    if (_rc != ADER_OK) return _rc; \
+  } while (0)
+
+// Persistent grid of a kernel class: blocks_per_cu blocks per compute unit,
+// and never more blocks than the zones need.
+inline unsigned grid_for(const ader_ctx* c, int cls) {
+  const LaunchShape& s = c->shape[cls];
+  const long long need = (c->S + s.block - 1) / s.block;
+  const long long cap = (long long)s.blocks_per_cu * c->num_cus;
+  const long long g = need < cap ? need : cap;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Stage tables of the variants, one translation unit each.
+#define ADER_VARIANTS(X)                                                     \
+  X(euler, fp64, 2, 0) X(euler, fp64, 2, 1) X(euler, fp64, 3, 0) X(euler, fp64, 4, 0) \
+  X(euler, mixed, 2, 0) X(euler, mixed, 2, 1) X(euler, mixed, 3, 0) X(euler, mixed, 4, 0) \
+  X(mhd, fp64, 2, 0) X(mhd, fp64, 2, 1) X(mhd, fp64, 3, 0) X(mhd, fp64, 4, 0)     \
+  X(mhd, mixed, 2, 0) X(mhd, mixed, 2, 1) X(mhd, mixed, 3, 0) X(mhd, mixed, 4, 0)
+#define ADER_STAGES_NAME(sys, prec, order, form) stages_##sys##_##prec##_o##order##_f##form
+#define ADER_DECLARE_STAGES(sys, prec, order, form) \
+  const StageFns* ADER_STAGES_NAME(sys, prec, order, form)();
+ADER_VARIANTS(ADER_DECLARE_STAGES)
+#undef ADER_DECLARE_STAGES
+
+}  // namespace ader

@@ -1,52 +1,118 @@
-// HIP kernels of one ADER-CG step on a periodic mesh (gfx950): one thread per
-// zone over the per-zone operations of zone_ops.h, plus the wavefront/block
-// reductions of the CFL time step.
+// HIP kernels of one ADER-CG step (gfx950).  Every kernel is persistent over
+// all zones of all problems of a batch (a lone problem is a batch of one):
+// each thread walks zones of its block's contiguous chunk and applies the
+// per-zone operation of zone_ops.h with the problem the zone belongs to.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "ader_ctx.h"
 #include "zone_ops.h"
 
 namespace ader {
 
 // The FP32 (mixed-precision) kernels run the deviation form, the FP64 ones
-// the point form.
+// the point form.  Kernels without a natural template parameter take a
+// dummy one, so this header can go into several translation units.
 template <class T>
 constexpr bool kDeviation = sizeof(T) == 4;
 
+__device__ __forceinline__ Grid grid_of(const Problem& pr, const Batch& b) {
+  return Grid{pr.nx, pr.ny, pr.nz, pr.N, b.S, pr.base};
+}
+
+// Problem holding array index n (the table is sorted by base).
+__device__ __forceinline__ int find_problem(const Batch& b, long long n) {
+  int lo = 0, hi = b.np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.P[mid].base <= n) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Zone loop of the persistent kernels.  The hardware deals blocks to the 8
+// XCDs in turn (block b on XCD b mod 8), so the zone range is cut into 8
+// contiguous regions, one per XCD, and each region into contiguous chunks,
+// one per block of that XCD: a zone's stencil neighbours (+-1, +-nx, +-nx ny)
+// mostly lie in the same region and are read through the same L2.  Threads
+// walk their chunk with stride blockDim.x (coalesced) and track the problem
+// of the current zone.  Every zone of [0, S) is visited exactly once for any
+// grid size.
+template <class Body>
+__device__ __forceinline__ void for_zones(const Batch& b, Body&& body) {
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long rlo = b.S * x / nreg, rhi = b.S * (x + 1) / nreg;
+  const long long lo = rlo + (rhi - rlo) * r / nb, hi = rlo + (rhi - rlo) * (r + 1) / nb;
+  long long n = lo + threadIdx.x;
+  if (n >= hi) return;
+  int p = find_problem(b, n);
+  Problem pr = b.P[p];
+  for (; n < hi; n += blockDim.x) {
+    while (n >= pr.base + pr.N) pr = b.P[++p];
+    body(pr, p, n);
+  }
+}
+
 template <class T, int M, int AXIS, int NVAR>
 __global__ void __launch_bounds__(256) k_weno_sweep(const double* __restrict__ U,
-                                                    T* __restrict__ W, Grid g) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) weno_sweep_zone<T, M, AXIS, NVAR>(U, W, g, n);
+                                                    T* __restrict__ W, Batch b) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    weno_sweep_zone<T, M, AXIS, NVAR>(U, W, grid_of(pr, b), n);
+  });
 }
 
 template <class T, int NVAR>
-__global__ void __launch_bounds__(256) k_minmod(const double* __restrict__ U,
-                                                T* __restrict__ W, Grid g) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) minmod_zone<T, NVAR>(U, W, g, n);
+__global__ void __launch_bounds__(256) k_minmod(const double* __restrict__ U, T* __restrict__ W,
+                                                Batch b) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    minmod_zone<T, NVAR>(U, W, grid_of(pr, b), n);
+  });
 }
 
 template <class T, int M>
 __global__ void __launch_bounds__(256) k_bface(const double* __restrict__ B, double* __restrict__ B0,
-                                               T* __restrict__ BN, Grid g) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) bface_zone<T, M>(B, B0, BN, g, n);
+                                               T* __restrict__ BN, Batch b) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    bface_zone<T, M>(B, B0, BN, grid_of(pr, b), n);
+  });
 }
 
 template <class T, int ORDER, int FORM>
-__global__ void __launch_bounds__(128) k_predict_mhd(const double* __restrict__ U,
+__global__ void __launch_bounds__(256) k_predict(const double* __restrict__ U,
+                                                 const T* __restrict__ W, T* __restrict__ PK,
+                                                 Batch b, const double* __restrict__ dt,
+                                                 double gam) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    predict_zone<T, ORDER, FORM, kDeviation<T>>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
+                                                1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+  });
+}
+
+template <class T, int ORDER, int FORM>
+__global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ U,
                                                      const T* __restrict__ W,
                                                      const double* __restrict__ B0,
                                                      const T* __restrict__ WB,
                                                      const T* __restrict__ BN, T* __restrict__ PK,
-                                                     Grid g, const double* __restrict__ dt,
-                                                     double inv_dx, double inv_dy, double inv_dz,
+                                                     Batch b, const double* __restrict__ dt,
                                                      double gam) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N)
-    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>>(U, W, B0, WB, BN, PK, g, *dt, inv_dx, inv_dy,
-                                                    inv_dz, gam, n);
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>>(U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p],
+                                                    1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+  });
+}
+
+template <class T, int RS>
+__global__ void __launch_bounds__(256) k_face_flux(const double* __restrict__ U,
+                                                   const T* __restrict__ PK,
+                                                   double* __restrict__ F, Batch b, double gam) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    face_flux_zone<T, RS, kDeviation<T>>(U, PK, F, grid_of(pr, b), gam, n);
+  });
 }
 
 template <class T>
@@ -54,137 +120,125 @@ __global__ void __launch_bounds__(256) k_face_flux_mhd(const double* __restrict_
                                                        const double* __restrict__ B0,
                                                        const T* __restrict__ PK,
                                                        double* __restrict__ F,
-                                                       double* __restrict__ FE, Grid g, double gam) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) face_flux_zone_mhd<T, kDeviation<T>>(U, B0, PK, F, FE, g, gam, n);
+                                                       double* __restrict__ FE, Batch b,
+                                                       double gam) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    face_flux_zone_mhd<T, kDeviation<T>>(U, B0, PK, F, FE, grid_of(pr, b), gam, n);
+  });
 }
 
+template <int = 0>
 __global__ void __launch_bounds__(256) k_edge_e(const double* __restrict__ FE,
-                                                double* __restrict__ E, Grid g) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) edge_e_zone(FE, E, g, n);
+                                                double* __restrict__ E, Batch b) {
+  for_zones(b, [&](const Problem& pr, int, long long n) { edge_e_zone(FE, E, grid_of(pr, b), n); });
+}
+
+// eq. (6)
+template <int = 0>
+__global__ void __launch_bounds__(256) k_update(double* __restrict__ U, const double* __restrict__ F,
+                                                Batch b, const double* __restrict__ dt) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    update_zone(U, F, grid_of(pr, b), dt[p], pr.dx, pr.dy, pr.dz, n);
+  });
 }
 
 // eq. (6) for the hydro variables and eq. (8) for the face fields
+template <int = 0>
 __global__ void __launch_bounds__(256) k_update_mhd(double* __restrict__ U, double* __restrict__ B,
                                                     const double* __restrict__ F,
-                                                    const double* __restrict__ E, Grid g,
-                                                    const double* __restrict__ dt, double dx,
-                                                    double dy, double dz) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) {
-    const double h = *dt;
-    update_zone(U, F, g, h, dx, dy, dz, n);
-    ct_zone(B, E, g, h, dx, dy, dz, n);
+                                                    const double* __restrict__ E, Batch b,
+                                                    const double* __restrict__ dt) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    const Grid g = grid_of(pr, b);
+    update_zone(U, F, g, dt[p], pr.dx, pr.dy, pr.dz, n);
+    ct_zone(B, E, g, dt[p], pr.dx, pr.dy, pr.dz, n);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// CFL dt per problem: every zone's rate sum_d (|v_d| + c_d)/dx_d is maxed into
+// rate[p] (the bit pattern of a non-negative double orders like the value,
+// so an unsigned 64-bit atomic max is a max of doubles).  A block's threads
+// keep a running max for their current problem and flush it when the
+// problem changes; at the end the wave and then the block combine the
+// maxima of equal problems, so a block issues one atomic per problem it
+// touched.  k_dt_final turns the rates into dt and clears them for the next
+// step (no memset, so the step can be captured in a graph).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void flush_rate(unsigned long long* rate, int p, double r) {
+  if (p >= 0 && r > 0.0) atomicMax(&rate[p], (unsigned long long)__double_as_longlong(r));
+}
+
+template <int = 0>
+__global__ void __launch_bounds__(256) k_dt(const double* __restrict__ U,
+                                            const double* __restrict__ B, Batch b, double gam,
+                                            unsigned long long* __restrict__ rate,
+                                            int* __restrict__ bad) {
+  __shared__ int sp[4];
+  __shared__ double sr[4];
+  double rmax = 0.0;
+  int pcur = -1;
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    if (p != pcur) {
+      flush_rate(rate, pcur, rmax);
+      rmax = 0.0;
+      pcur = p;
+    }
+    int isbad = 0;
+    const Grid g = grid_of(pr, b);
+    const double r = B ? dt_rate_zone_mhd(U, B, g, gam, pr.dx, pr.dy, pr.dz, n, isbad)
+                       : dt_rate_zone(U, g, gam, pr.dx, pr.dy, pr.dz, n, isbad);
+    if (isbad) bad[p] = 1;
+    rmax = fmax(rmax, r);
+  });
+  // wave: lanes that agree on the problem (idle lanes hold -1) combine
+  int pmax = pcur, pmin = pcur < 0 ? 0x7fffffff : pcur;
+  for (int off = 32; off >= 1; off >>= 1) {
+    pmax = max(pmax, __shfl_xor(pmax, off, 64));
+    pmin = min(pmin, __shfl_xor(pmin, off, 64));
   }
-}
-
-template <class T, int ORDER, int FORM>
-__global__ void __launch_bounds__(128) k_predict(const double* __restrict__ U,
-                                                 const T* __restrict__ W,
-                                                 T* __restrict__ PK, Grid g,
-                                                 const double* __restrict__ dt,
-                                                 double inv_dx, double inv_dy,
-                                                 double inv_dz, double gam) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N)
-    predict_zone<T, ORDER, FORM, kDeviation<T>>(U, W, PK, g, *dt, inv_dx, inv_dy, inv_dz, gam, n);
-}
-
-template <class T, int RS>
-__global__ void __launch_bounds__(256) k_face_flux(const double* __restrict__ U,
-                                                   const T* __restrict__ PK,
-                                                   double* __restrict__ F, Grid g, double gam) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) face_flux_zone<T, RS, kDeviation<T>>(U, PK, F, g, gam, n);
-}
-
-__global__ void __launch_bounds__(256) k_update(double* __restrict__ U, const double* __restrict__ F,
-                                                Grid g, const double* __restrict__ dt,
-                                                double dx, double dy, double dz) {
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (n < g.N) update_zone(U, F, g, *dt, dx, dy, dz, n);
-}
-
-__device__ __forceinline__ double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
-}
-
-// B == nullptr: Euler; otherwise MHD with the face fields B
-__global__ void __launch_bounds__(256) k_dt_partial(const double* __restrict__ U,
-                                                    const double* __restrict__ B, Grid g, double gam,
-                                                    double dx, double dy, double dz,
-                                                    double* __restrict__ partial,
-                                                    int* __restrict__ bad) {
-  __shared__ double red[4];
-  __shared__ int redbad[4];
-  const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double rate = 0.0;
-  int isbad = 0;
-  if (n < g.N)
-    rate = B ? dt_rate_zone_mhd(U, B, g, gam, dx, dy, dz, n, isbad)
-             : dt_rate_zone(U, g, gam, dx, dy, dz, n, isbad);
-  rate = wave_max(rate);
-  int wb = isbad;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) wb |= __shfl_xor(wb, off, 64);
+  const bool uniform = pmax >= 0 && pmin == pmax;
+  double rw = uniform ? rmax : 0.0;
+  for (int off = 32; off >= 1; off >>= 1) rw = fmax(rw, __shfl_xor(rw, off, 64));
+  if (!uniform) flush_rate(rate, pcur, rmax);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
-    red[wid] = rate;
-    redbad[wid] = wb;
+    sp[wid] = uniform ? pmax : -1;
+    sr[wid] = rw;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double r = red[0];
-    int b = redbad[0];
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
-      r = fmax(r, red[q]);
-      b |= redbad[q];
+    const int nw = (blockDim.x + 63) >> 6;
+    int p = -1;
+    double r = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      if (sp[q] != p) {
+        flush_rate(rate, p, r);
+        p = sp[q];
+        r = 0.0;
+      }
+      r = fmax(r, sr[q]);
     }
-    partial[blockIdx.x] = r;
-    bad[blockIdx.x] = b;
+    flush_rate(rate, p, r);
   }
 }
 
-__global__ void __launch_bounds__(1024) k_dt_final(const double* __restrict__ partial,
-                                                   const int* __restrict__ bad, int nparts,
-                                                   double cfl, double* __restrict__ dt,
-                                                   int* __restrict__ status) {
-  __shared__ double red[16];
-  __shared__ int redbad[16];
-  double r = 0.0;
-  int b = 0;
-  for (int q = threadIdx.x; q < nparts; q += blockDim.x) {
-    r = fmax(r, partial[q]);
-    b |= bad[q];
-  }
-  r = wave_max(r);
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) b |= __shfl_xor(b, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[wid] = r;
-    redbad[wid] = b;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
-      r = fmax(r, red[q]);
-      b |= redbad[q];
-    }
-    r = fmax(r, red[0]);
-    b |= redbad[0];
-    if (b || !(r > 0.0)) {
-      *status = 1;
-    } else {
-      *dt = cfl / r;
-    }
-  }
+template <int = 0>
+__global__ void __launch_bounds__(64) k_dt_final(unsigned long long* __restrict__ rate,
+                                                 int* __restrict__ bad, int np, double cfl,
+                                                 double* __restrict__ dt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double r = __longlong_as_double((long long)rate[p]);
+  if (!(r > 0.0) || !__builtin_isfinite(r)) bad[p] = 1;
+  else if (!bad[p]) dt[p] = cfl / r;
+  rate[p] = 0ull;
 }
 
-__global__ void k_set_scalar(double* __restrict__ p, double value) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *p = value;
+template <int = 0>
+__global__ void __launch_bounds__(64) k_set_dt(double* __restrict__ dt, int np, double value) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < np) dt[p] = value;
 }
+
 }  // namespace ader

@@ -1,83 +1,46 @@
-// Host side of libader_hip.so: the C ABI of include/ader.h, device buffers
-// and the kernel sequence of one ADER-CG step.
+// Host side of libader_hip.so: the C ABI of include/ader.h, device buffers,
+// the kernel sequence of one ADER-CG step, its hipGraph and the autotuner.
 //
-// Step sequence on the context's stream (no host involvement):
+// Step sequence on the context's stream (no host involvement), each stage
+// one persistent launch over every problem of the context:
+//   dt               k_dt (per-problem CFL rate, atomic max) + k_dt_final
 //   reconstruction   k_minmod (order 2) or k_weno_sweep x, y, z (orders 3, 4);
-//                    MHD first k_bface (Sec. III) and the same sweeps of b_0
+//                    MHD adds k_bface (Sec. III) and the sweeps of b_0
 //   predictor+faces  k_predict / k_predict_mhd: positivity scaling, space-time
 //                    predictor, face-side packets of all six sides
-//   Riemann          k_face_flux / k_face_flux_mhd: one flux per face; MHD
-//                    also the edge fluxes and k_edge_e (edge fields)
+//   Riemann          k_face_flux / k_face_flux_mhd (+ k_edge_e for MHD)
 //   update           k_update: eq. (6) in double; MHD k_update_mhd adds the
 //                    constrained transport of eq. (8)
-// and, for a CFL step, k_dt_partial + k_dt_final before it.
+// The stage launches of each (system, precision, order, form) variant live
+// in their own translation unit (ader_stages.hip).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
 
-#include "../../include/ader.h"
+#include "ader_ctx.h"
 #include "ader_kernels.h"
 
 using namespace ader;
 
-struct ader_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  Grid g{};
-  double lx = 1, ly = 1, lz = 1, dx = 1, dy = 1, dz = 1;
-  double gamma = 1.4;
-  int system = ADER_EULER;
-  int order = 3, form = ADER_MODAL, riemann = ADER_HLL, precision = ADER_FP64;
-  double* U = nullptr;
-  bool owns_U = true;
-  void* W = nullptr;
-  void* PK = nullptr;
-  void* F = nullptr;
-  // MHD: face fields, zone field b_0, its modes, the Sec. III normal moments,
-  // edge fluxes and edge fields
-  double* B = nullptr;
-  bool owns_B = true;
-  double* B0 = nullptr;
-  void* WB = nullptr;
-  void* BN = nullptr;
-  void* FE = nullptr;
-  double* E = nullptr;
-  double* d_dt = nullptr;
-  double* d_partial = nullptr;
-  int* d_bad = nullptr;
-  int* d_status = nullptr;
-  int nparts = 0;
-  bool have_state = false;
-  bool have_dt = false;
-  size_t bytes = 0;
-  // stage timing: events recorded around each stage while enabled
-  bool timing = false;
-  std::vector<hipEvent_t> events;
-  std::vector<int> marks;  // stage of each (start, stop) event pair
-};
-
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kPredBlock = 128;
-
-int check(hipError_t e) { return e == hipSuccess ? ADER_OK : ADER_EDEVICE; }
-
-#define ADER_TRY(expr)            \
-  do {                            \
-    int _rc = (expr);             \
-    if (_rc != ADER_OK) return _rc; \
-  } while (0)
-
-int launched() { return check(hipGetLastError()); }
-
-unsigned blocks_for(long long n, int b) { return (unsigned)((n + b - 1) / b); }
-
 int set_device(ader_ctx* c) { return check(hipSetDevice(c->device)); }
+
+const StageFns* stages_of(const ader_ctx* c) {
+#define ADER_PICK(SY, PR, OR, FM)                                                                \
+  if (c->system == (#SY[0] == 'm' ? ADER_MHD : ADER_EULER) &&                                    \
+      c->precision == (#PR[0] == 'm' ? ADER_MIXED : ADER_FP64) && c->order == OR && c->form == FM) \
+    return ADER_STAGES_NAME(SY, PR, OR, FM)();
+  ADER_VARIANTS(ADER_PICK)
+#undef ADER_PICK
+  return nullptr;
+}
 
 // Records an event pair around one stage when timing is on.
 struct StageTimer {
@@ -105,163 +68,123 @@ struct StageTimer {
   }
 };
 
-// zone-centred reconstruction of NVAR fields with zone averages src
-template <class T, int NVAR>
-int launch_sweeps(ader_ctx* c, const double* src, T* W) {
-  const unsigned nb = blocks_for(c->g.N, kBlock);
-  switch (c->order) {
-    case 2:
-      k_minmod<T, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      return launched();
-    case 3:
-      k_weno_sweep<T, 3, 0, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      k_weno_sweep<T, 3, 1, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      k_weno_sweep<T, 3, 2, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      return launched();
-    case 4:
-      k_weno_sweep<T, 4, 0, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      k_weno_sweep<T, 4, 1, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      k_weno_sweep<T, 4, 2, NVAR><<<nb, kBlock, 0, c->stream>>>(src, W, c->g);
-      return launched();
-  }
-  return ADER_EINVAL;
-}
-
-template <class T>
-int launch_recon(ader_ctx* c) {
-  ADER_TRY((launch_sweeps<T, 5>(c, c->U, static_cast<T*>(c->W))));
-  if (c->system != ADER_MHD) return ADER_OK;
-  const unsigned nb = blocks_for(c->g.N, kBlock);
-  T* BN = static_cast<T*>(c->BN);
-  if (c->order == 2) k_bface<T, 2><<<nb, kBlock, 0, c->stream>>>(c->B, c->B0, BN, c->g);
-  if (c->order == 3) k_bface<T, 3><<<nb, kBlock, 0, c->stream>>>(c->B, c->B0, BN, c->g);
-  if (c->order == 4) k_bface<T, 4><<<nb, kBlock, 0, c->stream>>>(c->B, c->B0, BN, c->g);
-  ADER_TRY(launched());
-  return launch_sweeps<T, 3>(c, c->B0, static_cast<T*>(c->WB));
-}
-
-template <class T>
-int launch_predict(ader_ctx* c) {
-  const T* W = static_cast<const T*>(c->W);
-  T* PK = static_cast<T*>(c->PK);
-  const unsigned nb = blocks_for(c->g.N, kPredBlock);
-  const double ix = 1.0 / c->dx, iy = 1.0 / c->dy, iz = 1.0 / c->dz;
-  if (c->system == ADER_MHD) {
-    const double* B0 = c->B0;
-    const T* WB = static_cast<const T*>(c->WB);
-    const T* BN = static_cast<const T*>(c->BN);
-#define ADER_PM(O, FM) \
-  k_predict_mhd<T, O, FM><<<nb, kPredBlock, 0, c->stream>>>(c->U, W, B0, WB, BN, PK, c->g, c->d_dt, ix, iy, iz, c->gamma)
-    if (c->order == 2 && c->form == ADER_NODAL) ADER_PM(2, 1);
-    else if (c->order == 2) ADER_PM(2, 0);
-    else if (c->order == 3) ADER_PM(3, 0);
-    else ADER_PM(4, 0);
-#undef ADER_PM
-    return launched();
-  }
-  if (c->order == 2 && c->form == ADER_NODAL)
-    k_predict<T, 2, 1><<<nb, kPredBlock, 0, c->stream>>>(c->U, W, PK, c->g, c->d_dt, ix, iy, iz, c->gamma);
-  else if (c->order == 2)
-    k_predict<T, 2, 0><<<nb, kPredBlock, 0, c->stream>>>(c->U, W, PK, c->g, c->d_dt, ix, iy, iz, c->gamma);
-  else if (c->order == 3)
-    k_predict<T, 3, 0><<<nb, kPredBlock, 0, c->stream>>>(c->U, W, PK, c->g, c->d_dt, ix, iy, iz, c->gamma);
-  else
-    k_predict<T, 4, 0><<<nb, kPredBlock, 0, c->stream>>>(c->U, W, PK, c->g, c->d_dt, ix, iy, iz, c->gamma);
-  return launched();
-}
-
-template <class T>
-int launch_flux_update(ader_ctx* c) {
-  const unsigned nb = blocks_for(c->g.N, kBlock);
-  const T* PK = static_cast<const T*>(c->PK);
-  double* F = static_cast<double*>(c->F);
-  if (c->system == ADER_MHD) {
-    double* FE = static_cast<double*>(c->FE);
-    {
-      StageTimer t(c, ADER_STAGE_FLUX);
-      k_face_flux_mhd<T><<<nb, kBlock, 0, c->stream>>>(c->U, c->B0, PK, F, FE, c->g, c->gamma);
-      ADER_TRY(launched());
-      k_edge_e<<<nb, kBlock, 0, c->stream>>>(FE, c->E, c->g);
-      ADER_TRY(launched());
-    }
-    StageTimer t(c, ADER_STAGE_UPDATE);
-    k_update_mhd<<<nb, kBlock, 0, c->stream>>>(c->U, c->B, F, c->E, c->g, c->d_dt, c->dx, c->dy, c->dz);
-    return launched();
-  }
-  {
-    StageTimer t(c, ADER_STAGE_FLUX);
-    if (c->riemann == ADER_HLL)
-      k_face_flux<T, 0><<<nb, kBlock, 0, c->stream>>>(c->U, PK, F, c->g, c->gamma);
-    else
-      k_face_flux<T, 1><<<nb, kBlock, 0, c->stream>>>(c->U, PK, F, c->g, c->gamma);
-    ADER_TRY(launched());
-  }
-  StageTimer t(c, ADER_STAGE_UPDATE);
-  k_update<<<nb, kBlock, 0, c->stream>>>(c->U, F, c->g, c->d_dt, c->dx, c->dy, c->dz);
-  return launched();
-}
-
-template <class T>
-int launch_step(ader_ctx* c) {
-  {
-    StageTimer t(c, ADER_STAGE_RECON);
-    ADER_TRY(launch_recon<T>(c));
-  }
-  {
-    StageTimer t(c, ADER_STAGE_PREDICT);
-    ADER_TRY(launch_predict<T>(c));
-  }
-  return launch_flux_update<T>(c);
-}
-
-int run_step(ader_ctx* c) {
-  return c->precision == ADER_FP64 ? launch_step<double>(c) : launch_step<float>(c);
-}
-
 int queue_dt(ader_ctx* c, double cfl) {
   StageTimer t(c, ADER_STAGE_DT);
-  k_dt_partial<<<c->nparts, kBlock, 0, c->stream>>>(c->U, c->system == ADER_MHD ? c->B : nullptr,
-                                                    c->g, c->gamma, c->dx, c->dy, c->dz,
-                                                    c->d_partial, c->d_bad);
+  k_dt<><<<grid_for(c, kClassDt), c->shape[kClassDt].block, 0, c->stream>>>(
+      c->U, c->system == ADER_MHD ? c->B : nullptr, c->batch(), c->gamma, c->d_rate, c->d_bad);
   ADER_TRY(launched());
-  k_dt_final<<<1, 1024, 0, c->stream>>>(c->d_partial, c->d_bad, c->nparts, cfl, c->d_dt,
-                                        c->d_status);
+  k_dt_final<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->d_rate, c->d_bad, c->np(), cfl, c->d_dt);
   ADER_TRY(launched());
   c->have_dt = true;
   return ADER_OK;
 }
 
+int queue_step(ader_ctx* c) {
+  const StageFns* s = stages_of(c);
+  if (!s) return ADER_EUNSUPPORTED;
+  {
+    StageTimer t(c, ADER_STAGE_RECON);
+    ADER_TRY(s->recon(c));
+  }
+  {
+    StageTimer t(c, ADER_STAGE_PREDICT);
+    ADER_TRY(s->predict(c));
+  }
+  {
+    StageTimer t(c, ADER_STAGE_FLUX);
+    ADER_TRY(s->flux(c));
+  }
+  StageTimer t(c, ADER_STAGE_UPDATE);
+  return s->update(c);
+}
+
+// Everything a captured step depends on besides the device buffers' contents.
+unsigned long long config_key(const ader_ctx* c) {
+  unsigned long long k = (unsigned long long)c->order;
+  k = k * 3 + (unsigned long long)c->form;
+  k = k * 3 + (unsigned long long)c->riemann;
+  k = k * 3 + (unsigned long long)c->precision;
+  for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
+                                            (unsigned long long)c->shape[q].blocks_per_cu;
+  k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
+  k ^= (unsigned long long)(uintptr_t)c->B * 0xc2b2ae3d27d4eb4full;
+  unsigned long long g;
+  std::memcpy(&g, &c->gamma, sizeof g);
+  return k ^ (g * 0x165667b19e3779f9ull);
+}
+
+void drop_graph(ader_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = nullptr;
+}
+
+// One CFL step: replayed from a hipGraph when graph mode is on (captured on
+// first use and whenever the configuration, cfl or bound buffers change),
+// launched eagerly otherwise or while stage timing is on.
+int run_step_cfl(ader_ctx* c, double cfl) {
+  if (!c->use_graph || c->timing) {
+    ADER_TRY(queue_dt(c, cfl));
+    return queue_step(c);
+  }
+  const unsigned long long key = config_key(c);
+  if (!c->graph_exec || c->graph_cfl != cfl || c->graph_key != key) {
+    drop_graph(c);
+    ADER_TRY(check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal)));
+    int rc = queue_dt(c, cfl);
+    if (rc == ADER_OK) rc = queue_step(c);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (rc != ADER_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    ADER_TRY(check(e));
+    const hipError_t ei = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    ADER_TRY(check(ei));
+    c->graph_cfl = cfl;
+    c->graph_key = key;
+  }
+  c->have_dt = true;
+  return check(hipGraphLaunch(c->graph_exec, c->stream));
+}
+
+// Copies the per-problem flags back; any set flag is ADER_ESTATE (and the
+// flags are cleared).
 int read_status(ader_ctx* c) {
-  int st = 0;
-  ADER_TRY(check(hipMemcpyAsync(&st, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream)));
+  std::vector<int> bad(c->np(), 0);
+  ADER_TRY(check(hipMemcpyAsync(bad.data(), c->d_bad, sizeof(int) * bad.size(),
+                                hipMemcpyDeviceToHost, c->stream)));
   ADER_TRY(check(hipStreamSynchronize(c->stream)));
-  if (st) {
-    const int zero = 0;
-    ADER_TRY(check(hipMemcpyAsync(c->d_status, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream)));
+  if (std::any_of(bad.begin(), bad.end(), [](int b) { return b != 0; })) {
+    ADER_TRY(check(hipMemsetAsync(c->d_bad, 0, sizeof(int) * bad.size(), c->stream)));
     ADER_TRY(check(hipStreamSynchronize(c->stream)));
     return ADER_ESTATE;
   }
   return ADER_OK;
 }
 
-// rho > 0, P > 0 and finite values in every zone (MHD: the zone field is
-// the mean of its two face values, as in the CFL rate)
-bool host_state_ok(const double* U, const double* B, const Grid& g, double gamma) {
-  const long long N = g.N;
-  for (long long n = 0; n < N; ++n) {
-    const double r = U[n], mx = U[N + n], my = U[2 * N + n], mz = U[3 * N + n], E = U[4 * N + n];
+// rho > 0, P > 0 and finite values in every zone of one problem stored with
+// stride S at base (MHD: the zone field is the mean of its two face values,
+// as in the CFL rate)
+bool host_state_ok(const double* U, const double* B, const Problem& pr, long long S,
+                   double gamma) {
+  for (long long l = 0; l < pr.N; ++l) {
+    const long long n = pr.base + l;
+    const double r = U[n], mx = U[S + n], my = U[2 * S + n], mz = U[3 * S + n], E = U[4 * S + n];
     if (!(std::isfinite(r) && std::isfinite(mx) && std::isfinite(my) && std::isfinite(mz) &&
           std::isfinite(E)))
       return false;
     if (!(r > 0.0)) return false;
     double b2 = 0.0;
     if (B) {
-      const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / ((long long)g.nx * g.ny));
-      const long long up[3] = {((long long)k * g.ny + j) * g.nx + (i + 1) % g.nx,
-                               ((long long)k * g.ny + (j + 1) % g.ny) * g.nx + i,
-                               ((long long)((k + 1) % g.nz) * g.ny + j) * g.nx + i};
+      const int i = (int)(l % pr.nx), j = (int)((l / pr.nx) % pr.ny),
+                k = (int)(l / ((long long)pr.nx * pr.ny));
+      const long long up[3] = {pr.base + ((long long)k * pr.ny + j) * pr.nx + (i + 1) % pr.nx,
+                               pr.base + ((long long)k * pr.ny + (j + 1) % pr.ny) * pr.nx + i,
+                               pr.base + ((long long)((k + 1) % pr.nz) * pr.ny + j) * pr.nx + i};
       for (int d = 0; d < 3; ++d) {
-        const double lo = B[d * N + n], hi = B[d * N + up[d]];
+        const double lo = B[d * S + n], hi = B[d * S + up[d]];
         if (!(std::isfinite(lo) && std::isfinite(hi))) return false;
         const double bm = 0.5 * (lo + hi);
         b2 += bm * bm;
@@ -283,33 +206,28 @@ void drop_events(ader_ctx* c) {
 void free_buffers(ader_ctx* c) {
   if (c->owns_U && c->U) (void)hipFree(c->U);
   if (c->owns_B && c->B) (void)hipFree(c->B);
-  if (c->B0) (void)hipFree(c->B0);
-  if (c->WB) (void)hipFree(c->WB);
-  if (c->BN) (void)hipFree(c->BN);
-  if (c->FE) (void)hipFree(c->FE);
-  if (c->E) (void)hipFree(c->E);
-  if (c->W) (void)hipFree(c->W);
-  if (c->PK) (void)hipFree(c->PK);
-  if (c->F) (void)hipFree(c->F);
-  if (c->d_dt) (void)hipFree(c->d_dt);
-  if (c->d_partial) (void)hipFree(c->d_partial);
-  if (c->d_bad) (void)hipFree(c->d_bad);
-  if (c->d_status) (void)hipFree(c->d_status);
+  for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
+                  (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs})
+    if (p) (void)hipFree(p);
 }
 
-}  // namespace
+bool mesh_ok(const ader_mesh& m) {
+  return m.nx >= 1 && m.ny >= 1 && m.nz >= 1 && m.lx > 0 && m.ly > 0 && m.lz > 0 &&
+         std::isfinite(m.lx) && std::isfinite(m.ly) && std::isfinite(m.lz) &&
+         (long long)m.nx * m.ny * m.nz <= (1LL << 40);
+}
 
-extern "C" {
-
-int ader_create(const ader_mesh* mesh, int system, int device, void* stream, ader_ctx** out) {
-  if (!mesh || !out) return ADER_EINVAL;
+// Context for n independent problems stored one after the other.
+int create(int n, const ader_mesh* meshes, int system, int device, void* stream, ader_ctx** out) {
+  if (!meshes || !out || n < 1 || n > (1 << 20)) return ADER_EINVAL;
   *out = nullptr;
   if (system != ADER_EULER && system != ADER_MHD) return ADER_EINVAL;
-  if (mesh->nx < 1 || mesh->ny < 1 || mesh->nz < 1) return ADER_EINVAL;
-  if (!(mesh->lx > 0 && mesh->ly > 0 && mesh->lz > 0)) return ADER_EINVAL;
-  if (!(std::isfinite(mesh->lx) && std::isfinite(mesh->ly) && std::isfinite(mesh->lz))) return ADER_EINVAL;
-  const long long N = (long long)mesh->nx * mesh->ny * mesh->nz;
-  if (N > (1LL << 40)) return ADER_EINVAL;
+  long long S = 0;
+  for (int q = 0; q < n; ++q) {
+    if (!mesh_ok(meshes[q])) return ADER_EINVAL;
+    S += (long long)meshes[q].nx * meshes[q].ny * meshes[q].nz;
+  }
+  if (S > (1LL << 40)) return ADER_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ADER_EDEVICE;
   ader_ctx* c = new (std::nothrow) ader_ctx();
@@ -317,26 +235,41 @@ int ader_create(const ader_mesh* mesh, int system, int device, void* stream, ade
   c->device = device;
   c->system = system;
   c->stream = static_cast<hipStream_t>(stream);
-  c->g = Grid{mesh->nx, mesh->ny, mesh->nz, N};
-  c->lx = mesh->lx;
-  c->ly = mesh->ly;
-  c->lz = mesh->lz;
-  c->dx = mesh->lx / mesh->nx;
-  c->dy = mesh->ly / mesh->ny;
-  c->dz = mesh->lz / mesh->nz;
-  c->nparts = (int)blocks_for(N, kBlock);
+  c->S = S;
+  long long base = 0;
+  for (int q = 0; q < n; ++q) {
+    const ader_mesh& m = meshes[q];
+    Problem pr{};
+    pr.nx = m.nx;
+    pr.ny = m.ny;
+    pr.nz = m.nz;
+    pr.N = (long long)m.nx * m.ny * m.nz;
+    pr.base = base;
+    pr.dx = m.lx / m.nx;
+    pr.dy = m.ly / m.ny;
+    pr.dz = m.lz / m.nz;
+    base += pr.N;
+    c->probs.push_back(pr);
+  }
+  c->set_flags.assign(n, 0);
   if (set_device(c) != ADER_OK) {
     delete c;
     return ADER_EDEVICE;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    c->num_cus = cus;
   // buffers sized for the largest case: order 4 and double work arrays
   const bool mhd = system == ADER_MHD;
-  const size_t sU = sizeof(double) * 5 * (size_t)N;
-  const size_t sW = sizeof(double) * 19 * 5 * (size_t)N;
-  const size_t sPK = sizeof(double) * 6 * (mhd ? 32 : 15) * (size_t)N;
-  const size_t sF = sizeof(double) * 3 * 5 * (size_t)N;
-  const size_t s3 = sizeof(double) * 3 * (size_t)N;
+  const size_t Z = (size_t)S;
+  const size_t sU = sizeof(double) * 5 * Z;
+  const size_t sW = sizeof(double) * 19 * 5 * Z;
+  const size_t sPK = sizeof(double) * 6 * (mhd ? 32 : 15) * Z;
+  const size_t sF = sizeof(double) * 3 * 5 * Z;
+  const size_t s3 = sizeof(double) * 3 * Z;
   const size_t sM = mhd ? s3 * (1 + 1 + 19 + 3 + 4 + 1) : 0;  // B, B0, WB, BN, FE, E
+  const size_t sP = sizeof(Problem) * n, sD = sizeof(double) * n;
   bool ok = hipMalloc(&c->U, sU) == hipSuccess && hipMalloc(&c->W, sW) == hipSuccess &&
             hipMalloc(&c->PK, sPK) == hipSuccess && hipMalloc(&c->F, sF) == hipSuccess &&
             (!mhd || (hipMalloc(&c->B, s3) == hipSuccess && hipMalloc(&c->B0, s3) == hipSuccess &&
@@ -344,26 +277,163 @@ int ader_create(const ader_mesh* mesh, int system, int device, void* stream, ade
                       hipMalloc(&c->BN, 3 * s3) == hipSuccess &&
                       hipMalloc(&c->FE, 4 * s3) == hipSuccess &&
                       hipMalloc(&c->E, s3) == hipSuccess)) &&
-            hipMalloc(&c->d_dt, sizeof(double)) == hipSuccess &&
-            hipMalloc(&c->d_partial, sizeof(double) * c->nparts) == hipSuccess &&
-            hipMalloc(&c->d_bad, sizeof(int) * c->nparts) == hipSuccess &&
-            hipMalloc(&c->d_status, sizeof(int)) == hipSuccess;
+            hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
+            hipMalloc(&c->d_rate, sizeof(unsigned long long) * n) == hipSuccess &&
+            hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess;
   if (!ok) {
     free_buffers(c);
     delete c;
     (void)hipGetLastError();
     return ADER_ENOMEM;
   }
-  c->bytes = sU + sW + sPK + sF + sM + sizeof(double) * (1 + c->nparts) + sizeof(int) * (c->nparts + 1);
-  const int zero = 0;
-  const double no_dt = 0.0;
-  if (hipMemcpy(c->d_status, &zero, sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_dt, &no_dt, sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+  c->bytes = sU + sW + sPK + sF + sM + sP + 2 * sD + sizeof(int) * n;
+  if (hipMemcpy(c->d_probs, c->probs.data(), sP, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->d_dt, 0, sD) != hipSuccess ||
+      hipMemset(c->d_rate, 0, sizeof(unsigned long long) * n) != hipSuccess ||
+      hipMemset(c->d_bad, 0, sizeof(int) * n) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     free_buffers(c);
     delete c;
     return ADER_EDEVICE;
   }
   *out = c;
+  return ADER_OK;
+}
+
+// Copy problem q's host arrays (U[5][N], B[3][N]) into the batch layout.
+int put_problem(ader_ctx* c, int q, const double* U, const double* B) {
+  const Problem& pr = c->probs[q];
+  const size_t bytes = sizeof(double) * (size_t)pr.N;
+  for (int v = 0; v < 5; ++v)
+    ADER_TRY(check(hipMemcpyAsync(c->U + v * c->S + pr.base, U + v * pr.N, bytes,
+                                  hipMemcpyHostToDevice, c->stream)));
+  if (B)
+    for (int d = 0; d < 3; ++d)
+      ADER_TRY(check(hipMemcpyAsync(c->B + d * c->S + pr.base, B + d * pr.N, bytes,
+                                    hipMemcpyHostToDevice, c->stream)));
+  return ADER_OK;
+}
+
+int get_problem(ader_ctx* c, int q, double* U, double* B) {
+  const Problem& pr = c->probs[q];
+  const size_t bytes = sizeof(double) * (size_t)pr.N;
+  for (int v = 0; v < 5; ++v)
+    ADER_TRY(check(hipMemcpyAsync(U + v * pr.N, c->U + v * c->S + pr.base, bytes,
+                                  hipMemcpyDeviceToHost, c->stream)));
+  if (B && c->system == ADER_MHD)
+    for (int d = 0; d < 3; ++d)
+      ADER_TRY(check(hipMemcpyAsync(B + d * pr.N, c->B + d * c->S + pr.base, bytes,
+                                    hipMemcpyDeviceToHost, c->stream)));
+  return check(hipStreamSynchronize(c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: for each kernel class, time each candidate launch shape on the
+// context's own problems and configuration (HIP events around a few launches
+// of that stage alone) and keep the fastest.  The state is saved first and
+// restored at the end, so tuning does not advance the solution.
+// ---------------------------------------------------------------------------
+constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
+                                       {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
+
+int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
+  hipEvent_t e0, e1;
+  ADER_TRY(check(hipEventCreate(&e0)));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return ADER_EDEVICE;
+  }
+  int rc = check(hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps && rc == ADER_OK; ++r) {
+    switch (cls) {
+      case kClassDt: rc = queue_dt(c, 0.3); break;
+      case kClassRecon: rc = s->recon(c); break;
+      case kClassPredict: rc = s->predict(c); break;
+      case kClassFlux: rc = s->flux(c); break;
+      default: rc = s->update(c); break;
+    }
+  }
+  if (rc == ADER_OK) rc = check(hipEventRecord(e1, c->stream));
+  if (rc == ADER_OK) rc = check(hipEventSynchronize(e1));
+  if (rc == ADER_OK) rc = check(hipEventElapsedTime(ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int autotune(ader_ctx* c, int reps) {
+  const StageFns* s = stages_of(c);
+  if (!s) return ADER_EUNSUPPORTED;
+  const bool mhd = c->system == ADER_MHD;
+  const size_t bU = sizeof(double) * 5 * (size_t)c->S, bB = sizeof(double) * 3 * (size_t)c->S;
+  double *sU = nullptr, *sB = nullptr, *sdt = nullptr;
+  const size_t bD = sizeof(double) * c->np();
+  if (hipMalloc(&sU, bU) != hipSuccess || hipMalloc(&sdt, bD) != hipSuccess ||
+      (mhd && hipMalloc(&sB, bB) != hipSuccess)) {
+    if (sU) (void)hipFree(sU);
+    if (sdt) (void)hipFree(sdt);
+    (void)hipGetLastError();
+    return ADER_ENOMEM;
+  }
+  int rc = check(hipMemcpyAsync(sU, c->U, bU, hipMemcpyDeviceToDevice, c->stream));
+  if (rc == ADER_OK && mhd) rc = check(hipMemcpyAsync(sB, c->B, bB, hipMemcpyDeviceToDevice, c->stream));
+  if (rc == ADER_OK) rc = check(hipMemcpyAsync(sdt, c->d_dt, bD, hipMemcpyDeviceToDevice, c->stream));
+  const bool timing = c->timing;
+  c->timing = false;
+  // one full step fills every work buffer the single stages read
+  if (rc == ADER_OK) rc = queue_dt(c, 0.3);
+  if (rc == ADER_OK) rc = queue_step(c);
+  // the update changes the state in place: tune it (and dt) last
+  const int order_of_classes[kNumClasses] = {kClassRecon, kClassPredict, kClassFlux, kClassDt,
+                                             kClassUpdate};
+  for (int qi = 0; qi < kNumClasses && rc == ADER_OK; ++qi) {
+    const int cls = order_of_classes[qi];
+    LaunchShape best = c->shape[cls];
+    float best_ms = 1e30f;
+    for (const LaunchShape& cand : kCandidates) {
+      c->shape[cls] = cand;
+      float ms = 0.f;
+      rc = time_stage(c, cls, s, 1, &ms);  // warm-up
+      if (rc == ADER_OK) rc = time_stage(c, cls, s, reps, &ms);
+      if (rc != ADER_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+    c->shape[cls] = best;
+  }
+  c->timing = timing;
+  // restore the state, dt and clear the flags the trial steps may have set
+  const int rc2 = check(hipMemcpyAsync(c->U, sU, bU, hipMemcpyDeviceToDevice, c->stream));
+  if (mhd) (void)hipMemcpyAsync(c->B, sB, bB, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemcpyAsync(c->d_dt, sdt, bD, hipMemcpyDeviceToDevice, c->stream);
+  (void)hipMemsetAsync(c->d_bad, 0, sizeof(int) * c->np(), c->stream);
+  (void)hipMemsetAsync(c->d_rate, 0, sizeof(unsigned long long) * c->np(), c->stream);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(sU);
+  (void)hipFree(sdt);
+  if (sB) (void)hipFree(sB);
+  drop_graph(c);
+  return rc != ADER_OK ? rc : rc2;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ader_create(const ader_mesh* mesh, int system, int device, void* stream, ader_ctx** out) {
+  return create(1, mesh, system, device, stream, out);
+}
+
+int ader_batch_create(int n, const ader_mesh* meshes, int system, int device, void* stream,
+                      ader_ctx** out) {
+  return create(n, meshes, system, device, stream, out);
+}
+
+int ader_batch_size(ader_ctx* c, int* n_out) {
+  if (!c || !n_out) return ADER_EINVAL;
+  *n_out = c->np();
   return ADER_OK;
 }
 
@@ -399,15 +469,32 @@ int ader_set_state(ader_ctx* c, const double* U, const double* B) {
   if (!c || !U) return ADER_EINVAL;
   const bool mhd = c->system == ADER_MHD;
   if (mhd != (B != nullptr)) return ADER_EINVAL;
-  if (!host_state_ok(U, B, c->g, c->gamma)) return ADER_ESTATE;
+  for (const Problem& pr : c->probs)
+    if (!host_state_ok(U, B, pr, c->S, c->gamma)) return ADER_ESTATE;
   ADER_TRY(set_device(c));
-  ADER_TRY(check(hipMemcpyAsync(c->U, U, sizeof(double) * 5 * (size_t)c->g.N, hipMemcpyHostToDevice,
+  ADER_TRY(check(hipMemcpyAsync(c->U, U, sizeof(double) * 5 * (size_t)c->S, hipMemcpyHostToDevice,
                                 c->stream)));
   if (mhd)
-    ADER_TRY(check(hipMemcpyAsync(c->B, B, sizeof(double) * 3 * (size_t)c->g.N,
+    ADER_TRY(check(hipMemcpyAsync(c->B, B, sizeof(double) * 3 * (size_t)c->S,
                                   hipMemcpyHostToDevice, c->stream)));
   ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  c->set_flags.assign(c->np(), 1);
   c->have_state = true;
+  return ADER_OK;
+}
+
+int ader_batch_set_state(ader_ctx* c, int i, const double* U, const double* B) {
+  if (!c || !U || i < 0 || i >= c->np()) return ADER_EINVAL;
+  const bool mhd = c->system == ADER_MHD;
+  if (mhd != (B != nullptr)) return ADER_EINVAL;
+  Problem lone = c->probs[i];
+  lone.base = 0;
+  if (!host_state_ok(U, B, lone, lone.N, c->gamma)) return ADER_ESTATE;
+  ADER_TRY(set_device(c));
+  ADER_TRY(put_problem(c, i, U, B));
+  ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  c->set_flags[i] = 1;
+  c->have_state = std::all_of(c->set_flags.begin(), c->set_flags.end(), [](char f) { return f != 0; });
   return ADER_OK;
 }
 
@@ -423,6 +510,7 @@ int ader_bind_device_state(ader_ctx* c, void* dU, void* dB) {
     c->B = static_cast<double*>(dB);
     c->owns_B = false;
   }
+  c->set_flags.assign(c->np(), 1);
   c->have_state = true;
   return ADER_OK;
 }
@@ -431,16 +519,24 @@ int ader_get_state(ader_ctx* c, double* U, double* B) {
   if (!c || !U) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
-  ADER_TRY(check(hipMemcpyAsync(U, c->U, sizeof(double) * 5 * (size_t)c->g.N, hipMemcpyDeviceToHost,
+  ADER_TRY(check(hipMemcpyAsync(U, c->U, sizeof(double) * 5 * (size_t)c->S, hipMemcpyDeviceToHost,
                                 c->stream)));
   if (B && c->system == ADER_MHD)
-    ADER_TRY(check(hipMemcpyAsync(B, c->B, sizeof(double) * 3 * (size_t)c->g.N,
+    ADER_TRY(check(hipMemcpyAsync(B, c->B, sizeof(double) * 3 * (size_t)c->S,
                                   hipMemcpyDeviceToHost, c->stream)));
   return check(hipStreamSynchronize(c->stream));
 }
 
+int ader_batch_get_state(ader_ctx* c, int i, double* U, double* B) {
+  if (!c || !U || i < 0 || i >= c->np()) return ADER_EINVAL;
+  if (!c->have_state) return ADER_ESEQ;
+  ADER_TRY(set_device(c));
+  return get_problem(c, i, U, B);
+}
+
 int ader_compute_dt(ader_ctx* c, double cfl, double* dt_out) {
   if (!c || !(cfl > 0.0) || !std::isfinite(cfl)) return ADER_EINVAL;
+  if (dt_out && c->np() != 1) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
   ADER_TRY(queue_dt(c, cfl));
@@ -456,25 +552,34 @@ int ader_step(ader_ctx* c, double dt) {
   if (!c || !(dt > 0.0) || !std::isfinite(dt)) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
-  k_set_scalar<<<1, 64, 0, c->stream>>>(c->d_dt, dt);
+  k_set_dt<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->d_dt, c->np(), dt);
   ADER_TRY(launched());
   c->have_dt = true;
-  return run_step(c);
+  return queue_step(c);
 }
 
 int ader_step_cfl(ader_ctx* c, double cfl) {
   if (!c || !(cfl > 0.0) || !std::isfinite(cfl)) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
-  ADER_TRY(queue_dt(c, cfl));
-  return run_step(c);
+  return run_step_cfl(c, cfl);
+}
+
+int ader_batch_step_cfl(ader_ctx* c, double cfl, double* dts_out) {
+  ADER_TRY(ader_step_cfl(c, cfl));
+  if (!dts_out) return ADER_OK;
+  ADER_TRY(read_status(c));
+  ADER_TRY(check(hipMemcpyAsync(dts_out, c->d_dt, sizeof(double) * c->np(), hipMemcpyDeviceToHost,
+                                c->stream)));
+  return check(hipStreamSynchronize(c->stream));
 }
 
 int ader_get_dt(ader_ctx* c, double* dt_out) {
   if (!c || !dt_out) return ADER_EINVAL;
   if (!c->have_dt) return ADER_ESEQ;
   ADER_TRY(set_device(c));
-  ADER_TRY(check(hipMemcpyAsync(dt_out, c->d_dt, sizeof(double), hipMemcpyDeviceToHost, c->stream)));
+  ADER_TRY(check(hipMemcpyAsync(dt_out, c->d_dt, sizeof(double) * c->np(), hipMemcpyDeviceToHost,
+                                c->stream)));
   return check(hipStreamSynchronize(c->stream));
 }
 
@@ -484,6 +589,45 @@ int ader_synchronize(ader_ctx* c) {
   ADER_TRY(check(hipStreamSynchronize(c->stream)));
   ADER_TRY(check(hipGetLastError()));
   return read_status(c);
+}
+
+int ader_set_graph(ader_ctx* c, int enable) {
+  if (!c) return ADER_EINVAL;
+  if (enable && c->stream == nullptr) return ADER_EUNSUPPORTED;
+  ADER_TRY(set_device(c));
+  if (!enable) {
+    ADER_TRY(check(hipStreamSynchronize(c->stream)));
+    drop_graph(c);
+  }
+  c->use_graph = enable != 0;
+  return ADER_OK;
+}
+
+int ader_autotune(ader_ctx* c, int reps) {
+  if (!c || reps < 1 || reps > 1000) return ADER_EINVAL;
+  if (!c->have_state) return ADER_ESEQ;
+  ADER_TRY(set_device(c));
+  ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  return autotune(c, reps);
+}
+
+int ader_get_launch(ader_ctx* c, int* block_out, int* blocks_per_cu_out) {
+  if (!c || !block_out || !blocks_per_cu_out) return ADER_EINVAL;
+  for (int q = 0; q < kNumClasses; ++q) {
+    block_out[q] = c->shape[q].block;
+    blocks_per_cu_out[q] = c->shape[q].blocks_per_cu;
+  }
+  return ADER_OK;
+}
+
+int ader_set_launch(ader_ctx* c, const int* block, const int* blocks_per_cu) {
+  if (!c || !block || !blocks_per_cu) return ADER_EINVAL;
+  for (int q = 0; q < kNumClasses; ++q)
+    if (block[q] < 64 || block[q] > 256 || block[q] % 64 != 0 || blocks_per_cu[q] < 1 ||
+        blocks_per_cu[q] > 64)
+      return ADER_EINVAL;
+  for (int q = 0; q < kNumClasses; ++q) c->shape[q] = LaunchShape{block[q], blocks_per_cu[q]};
+  return ADER_OK;
 }
 
 int ader_set_timing(ader_ctx* c, int enable) {
@@ -526,9 +670,9 @@ const char* ader_strerror(int code) {
   switch (code) {
     case ADER_OK: return "ok";
     case ADER_EINVAL: return "invalid argument";
-    case ADER_EUNSUPPORTED: return "unsupported configuration";
+    case ADER_EUNSUPPORTED: return "not supported";
     case ADER_ENOMEM: return "device allocation failed";
-    case ADER_EDEVICE: return "HIP device error";
+    case ADER_EDEVICE: return "HIP runtime error";
     case ADER_ESTATE: return "unphysical state (rho <= 0, P <= 0 or non-finite)";
     case ADER_ESEQ: return "call out of sequence";
   }
@@ -539,6 +683,7 @@ void ader_destroy(ader_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   drop_events(c);
   free_buffers(c);
   delete c;

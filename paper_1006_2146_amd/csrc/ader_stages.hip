@@ -1,0 +1,101 @@
+// Stage launches of one variant of the step, compiled once per (system,
+// precision, order, form) with
+//   -DADER_SYS=euler|mhd -DADER_PREC=fp64|mixed -DADER_ORDER=2|3|4 -DADER_FORM=0|1
+// so the variants build in parallel.  Each stage is one persistent launch
+// over all problems of the context (the reconstruction one per sweep).
+#include "ader_ctx.h"
+#include "ader_kernels.h"
+
+#define ADER_STR_euler 0
+#define ADER_STR_mhd 1
+#define ADER_CAT_(a, b) a##b
+#define ADER_CAT(a, b) ADER_CAT_(a, b)
+#define ADER_IS_MHD ADER_CAT(ADER_STR_, ADER_SYS)
+#define ADER_PREC_fp64 double
+#define ADER_PREC_mixed float
+
+namespace ader {
+namespace {
+
+using T = ADER_CAT(ADER_PREC_, ADER_PREC);
+constexpr int kOrder = ADER_ORDER;
+constexpr int kForm = ADER_FORM;
+constexpr bool kMhd = ADER_IS_MHD == 1;
+
+template <int NVAR>
+int sweeps(ader_ctx* c, const double* src, T* W) {
+  const Batch b = c->batch();
+  const unsigned g = grid_for(c, kClassRecon);
+  const int bs = c->shape[kClassRecon].block;
+  if constexpr (kOrder == 2) {
+    k_minmod<T, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+  } else {
+    k_weno_sweep<T, kOrder, 0, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+    ADER_TRY(launched());
+    k_weno_sweep<T, kOrder, 1, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+    ADER_TRY(launched());
+    k_weno_sweep<T, kOrder, 2, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+  }
+  return launched();
+}
+
+int recon(ader_ctx* c) {
+  ADER_TRY(sweeps<5>(c, c->U, static_cast<T*>(c->W)));
+  if constexpr (kMhd) {
+    k_bface<T, kOrder><<<grid_for(c, kClassRecon), c->shape[kClassRecon].block, 0, c->stream>>>(
+        c->B, c->B0, static_cast<T*>(c->BN), c->batch());
+    ADER_TRY(launched());
+    ADER_TRY(sweeps<3>(c, c->B0, static_cast<T*>(c->WB)));
+  }
+  return ADER_OK;
+}
+
+int predict(ader_ctx* c) {
+  const unsigned g = grid_for(c, kClassPredict);
+  const int bs = c->shape[kClassPredict].block;
+  const T* W = static_cast<const T*>(c->W);
+  T* PK = static_cast<T*>(c->PK);
+  if constexpr (kMhd)
+    k_predict_mhd<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(
+        c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK, c->batch(),
+        c->d_dt, c->gamma);
+  else
+    k_predict<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt, c->gamma);
+  return launched();
+}
+
+int flux(ader_ctx* c) {
+  const unsigned g = grid_for(c, kClassFlux);
+  const int bs = c->shape[kClassFlux].block;
+  const T* PK = static_cast<const T*>(c->PK);
+  if constexpr (kMhd) {
+    k_face_flux_mhd<T><<<g, bs, 0, c->stream>>>(c->U, c->B0, PK, c->F, c->FE, c->batch(), c->gamma);
+    ADER_TRY(launched());
+    k_edge_e<><<<g, bs, 0, c->stream>>>(c->FE, c->E, c->batch());
+  } else if (c->riemann == ADER_HLL) {
+    k_face_flux<T, 0><<<g, bs, 0, c->stream>>>(c->U, PK, c->F, c->batch(), c->gamma);
+  } else {
+    k_face_flux<T, 1><<<g, bs, 0, c->stream>>>(c->U, PK, c->F, c->batch(), c->gamma);
+  }
+  return launched();
+}
+
+int update(ader_ctx* c) {
+  const unsigned g = grid_for(c, kClassUpdate);
+  const int bs = c->shape[kClassUpdate].block;
+  if constexpr (kMhd)
+    k_update_mhd<><<<g, bs, 0, c->stream>>>(c->U, c->B, c->F, c->E, c->batch(), c->d_dt);
+  else
+    k_update<><<<g, bs, 0, c->stream>>>(c->U, c->F, c->batch(), c->d_dt);
+  return launched();
+}
+
+const StageFns kStages = {recon, predict, flux, update};
+
+}  // namespace
+
+// expand the variant macros before pasting the name
+#define ADER_STAGES_NAME_X(s, p, o, f) ADER_STAGES_NAME(s, p, o, f)
+const StageFns* ADER_STAGES_NAME_X(ADER_SYS, ADER_PREC, ADER_ORDER, ADER_FORM)() { return &kStages; }
+
+}  // namespace ader

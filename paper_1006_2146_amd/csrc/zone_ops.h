@@ -27,9 +27,14 @@
 
 namespace ader {
 
+// One periodic mesh inside the arrays: nx*ny*nz = N zones stored at indices
+// base .. base+N-1 of arrays whose per-variable stride is S (S = N and base =
+// 0 for a lone problem; a batch concatenates its problems).
 struct Grid {
   int nx, ny, nz;
   long long N;
+  long long S;
+  long long base;
 };
 
 __host__ __device__ __forceinline__ int wrap(int i, int n) {
@@ -38,7 +43,16 @@ __host__ __device__ __forceinline__ int wrap(int i, int n) {
 }
 
 __host__ __device__ __forceinline__ long long zone_of(int i, int j, int k, const Grid& g) {
-  return ((long long)k * g.ny + j) * g.nx + i;
+  return g.base + ((long long)k * g.ny + j) * g.nx + i;
+}
+
+// (i, j, k) of the array index n of a zone of g
+__host__ __device__ __forceinline__ void zone_ijk(const Grid& g, long long n, int& i, int& j, int& k) {
+  const long long l = n - g.base;
+  const long long row = l / g.nx;
+  i = (int)(l - row * g.nx);
+  k = (int)(row / g.ny);
+  j = (int)(row - (long long)k * g.ny);
 }
 
 // Position of spatial mode P_a(xi) P_b(eta) P_c(zeta) in the order of
@@ -126,9 +140,8 @@ template <class T, int M, int AXIS, int NVAR = 5>
 __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restrict__ U,
                                                          T* __restrict__ W, const Grid& g,
                                                          long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   constexpr int R = M - 1;
   long long idx[2 * R + 1];
 #pragma unroll
@@ -155,8 +168,8 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
         T d[2 * M - 1];
 #pragma unroll
         for (int q = 0; q < 2 * R + 1; ++q)
-          d[q] = src == 0 ? T(U[(long long)v * g.N + idx[q]] - U[(long long)v * g.N + n])
-                          : W[((long long)(src - 1) * NVAR + v) * g.N + idx[q]];
+          d[q] = src == 0 ? T(U[(long long)v * g.S + idx[q]] - U[(long long)v * g.S + n])
+                          : W[((long long)(src - 1) * NVAR + v) * g.S + idx[q]];
         T mo[M];
         weno1d<T, M>(d, mo);
 #pragma unroll
@@ -166,7 +179,7 @@ __host__ __device__ __forceinline__ void weno_sweep_zone(const double* __restric
           if constexpr (AXIS == 0) dst = spatial_mode(c, 0, 0);
           else if constexpr (AXIS == 1) dst = spatial_mode(a, c, 0);
           else dst = spatial_mode(a, b, c);
-          W[((long long)(dst - 1) * NVAR + v) * g.N + n] = mo[c];
+          W[((long long)(dst - 1) * NVAR + v) * g.S + n] = mo[c];
         }
       }
     }
@@ -179,23 +192,22 @@ template <class T, int NVAR = 5>
 __host__ __device__ __forceinline__ void minmod_zone(const double* __restrict__ U,
                                                      T* __restrict__ W, const Grid& g,
                                                      long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   const long long nb[3][2] = {
       {zone_of(wrap(i - 1, g.nx), j, k, g), zone_of(wrap(i + 1, g.nx), j, k, g)},
       {zone_of(i, wrap(j - 1, g.ny), k, g), zone_of(i, wrap(j + 1, g.ny), k, g)},
       {zone_of(i, j, wrap(k - 1, g.nz), g), zone_of(i, j, wrap(k + 1, g.nz), g)}};
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) {
-    const double c = U[(long long)v * g.N + n];
+    const double c = U[(long long)v * g.S + n];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double fwd = U[(long long)v * g.N + nb[ax][1]] - c;
-      const double bwd = c - U[(long long)v * g.N + nb[ax][0]];
+      const double fwd = U[(long long)v * g.S + nb[ax][1]] - c;
+      const double bwd = c - U[(long long)v * g.S + nb[ax][0]];
       double s = 0.0;
       if (fwd * bwd > 0.0) s = fabs(fwd) < fabs(bwd) ? fwd : bwd;
-      W[((long long)ax * NVAR + v) * g.N + n] = T(s);
+      W[((long long)ax * NVAR + v) * g.S + n] = T(s);
     }
   }
 }
@@ -415,14 +427,14 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   constexpr int LS = S::LS, NE = S::NE;
   double w0[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.N + n];
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
   T w[LS][5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
 #pragma unroll
   for (int m = 1; m < LS; ++m)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.N + n];
+    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.S + n];
 
   {
     PosScan<T, 5, DEV> scan(w0);
@@ -455,12 +467,12 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
         for (int v = 0; v < 5; ++v) e[m][v] *= th;
     }
   }
-  store_side<S, T, 0>(w, e, ph, PK, g.N, n);
-  store_side<S, T, 1>(w, e, ph, PK, g.N, n);
-  store_side<S, T, 2>(w, e, ph, PK, g.N, n);
-  store_side<S, T, 3>(w, e, ph, PK, g.N, n);
-  store_side<S, T, 4>(w, e, ph, PK, g.N, n);
-  store_side<S, T, 5>(w, e, ph, PK, g.N, n);
+  store_side<S, T, 0>(w, e, ph, PK, g.S, n);
+  store_side<S, T, 1>(w, e, ph, PK, g.S, n);
+  store_side<S, T, 2>(w, e, ph, PK, g.S, n);
+  store_side<S, T, 3>(w, e, ph, PK, g.S, n);
+  store_side<S, T, 4>(w, e, ph, PK, g.S, n);
+  store_side<S, T, 5>(w, e, ph, PK, g.S, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -537,18 +549,18 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;  // top side of the lower zone, bottom side of this
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    ubl[v] = PK[((long long)(SL * 3 + 0) * 5 + v) * g.N + nl];
-    ul[v] = PK[((long long)(SL * 3 + 1) * 5 + v) * g.N + nl];
-    fl[v] = PK[((long long)(SL * 3 + 2) * 5 + v) * g.N + nl];
-    ubr[v] = PK[((long long)(SR * 3 + 0) * 5 + v) * g.N + n];
-    ur[v] = PK[((long long)(SR * 3 + 1) * 5 + v) * g.N + n];
-    fr[v] = PK[((long long)(SR * 3 + 2) * 5 + v) * g.N + n];
+    ubl[v] = PK[((long long)(SL * 3 + 0) * 5 + v) * g.S + nl];
+    ul[v] = PK[((long long)(SL * 3 + 1) * 5 + v) * g.S + nl];
+    fl[v] = PK[((long long)(SL * 3 + 2) * 5 + v) * g.S + nl];
+    ubr[v] = PK[((long long)(SR * 3 + 0) * 5 + v) * g.S + n];
+    ur[v] = PK[((long long)(SR * 3 + 1) * 5 + v) * g.S + n];
+    fr[v] = PK[((long long)(SR * 3 + 2) * 5 + v) * g.S + n];
   }
   if constexpr (DEV) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      wl[v] = U[(long long)v * g.N + nl];
-      wr[v] = U[(long long)v * g.N + n];
+      wl[v] = U[(long long)v * g.S + nl];
+      wr[v] = U[(long long)v * g.S + n];
       ubl[v] += T(wl[v]);
       ubr[v] += T(wr[v]);
       ur[v] += T(wr[v] - wl[v]);
@@ -569,7 +581,7 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
 #pragma unroll
       for (int v = 0; v < 5; ++v)
-        F[((long long)AXIS * 5 + v) * g.N + n] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
+        F[((long long)AXIS * 5 + v) * g.S + n] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
       return;
     }
   } else {
@@ -580,12 +592,12 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       Euler<double>::template flux<AXIS>(wr, Fr, gam);
 #pragma unroll
       for (int v = 0; v < 5; ++v)
-        F[((long long)AXIS * 5 + v) * g.N + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+        F[((long long)AXIS * 5 + v) * g.S + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
       return;
     }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = double(out[v]);
+  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
 }
 
 // Each face flux is formed once, by the zone above it, so both zones that
@@ -595,9 +607,8 @@ __host__ __device__ __forceinline__ void face_flux_zone(const double* __restrict
                                                         const T* __restrict__ PK,
                                                         double* __restrict__ F, const Grid& g,
                                                         double gam, long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   face_flux_axis<T, RS, 0, DEV>(U, PK, F, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
   face_flux_axis<T, RS, 1, DEV>(U, PK, F, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
   face_flux_axis<T, RS, 2, DEV>(U, PK, F, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
@@ -607,22 +618,21 @@ __host__ __device__ __forceinline__ void face_flux_zone(const double* __restrict
 __host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, const double* __restrict__ F,
                                                      const Grid& g, double h, double dx,
                                                      double dy, double dz, long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   const long long up[3] = {zone_of(wrap(i + 1, g.nx), j, k, g), zone_of(i, wrap(j + 1, g.ny), k, g),
                            zone_of(i, j, wrap(k + 1, g.nz), g)};
   const double c[3] = {h / dx, h / dy, h / dz};
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    double u = U[(long long)v * g.N + n];
+    double u = U[(long long)v * g.S + n];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const double fp = F[((long long)ax * 5 + v) * g.N + up[ax]];
-      const double fm = F[((long long)ax * 5 + v) * g.N + n];
+      const double fp = F[((long long)ax * 5 + v) * g.S + up[ax]];
+      const double fm = F[((long long)ax * 5 + v) * g.S + n];
       u = u - c[ax] * (fp - fm);
     }
-    U[(long long)v * g.N + n] = u;
+    U[(long long)v * g.S + n] = u;
   }
 }
 
@@ -635,8 +645,8 @@ __host__ __device__ __forceinline__ double dt_rate_zone(const double* __restrict
                                                         double gam, double dx, double dy, double dz,
                                                         long long n, int& isbad) {
   const double r = U[n];
-  const double m[3] = {U[g.N + n], U[2 * g.N + n], U[3 * g.N + n]};
-  const double E = U[4 * g.N + n];
+  const double m[3] = {U[g.S + n], U[2 * g.S + n], U[3 * g.S + n]};
+  const double E = U[4 * g.S + n];
   const double p = (gam - 1.0) * (E - 0.5 * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) / r);
   const bool ok = r > 0.0 && p > 0.0 && __builtin_isfinite(r) && __builtin_isfinite(p) && __builtin_isfinite(m[0]) &&
                   __builtin_isfinite(m[1]) && __builtin_isfinite(m[2]);
@@ -671,16 +681,15 @@ __host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B
                                                     double* __restrict__ B0, T* __restrict__ BN,
                                                     const Grid& g, long long n) {
   constexpr double kEps = 1.0e-12;
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     double f[6];  // offsets -2 .. 3
 #pragma unroll
     for (int q = -2; q <= 3; ++q) {
       const bool need = (M == 2 && q >= 0 && q <= 1) || (M == 3 && q >= -1 && q <= 2) || M == 4;
-      f[q + 2] = need ? B[(long long)d * g.N + shifted(g, i, j, k, d, q)] : 0.0;
+      f[q + 2] = need ? B[(long long)d * g.S + shifted(g, i, j, k, d, q)] : 0.0;
     }
     const double fm25 = f[0], fm15 = f[1], fm05 = f[2], fp05 = f[3], fp15 = f[4], fp25 = f[5];
     double b[4] = {0.0, 0.0, 0.0, 0.0};
@@ -723,9 +732,9 @@ __host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B
 #pragma unroll
       for (int q = 0; q < 4; ++q) b[q] = (a[0] * s[0][q] + a[1] * s[1][q] + a[2] * s[2][q]) / tot;
     }
-    B0[(long long)d * g.N + n] = b[0];
+    B0[(long long)d * g.S + n] = b[0];
 #pragma unroll
-    for (int a = 1; a < M; ++a) BN[((long long)(a - 1) * 3 + d) * g.N + n] = T(b[a]);
+    for (int a = 1; a < M; ++a) BN[((long long)(a - 1) * 3 + d) * g.S + n] = T(b[a]);
   }
 }
 
@@ -763,25 +772,25 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   constexpr int LS = S::LS, NE = S::NE;
   double w0[8];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.N + n];
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) w0[5 + c] = B0[(long long)c * g.N + n];
+  for (int c = 0; c < 3; ++c) w0[5 + c] = B0[(long long)c * g.S + n];
   T w[LS][8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
 #pragma unroll
   for (int m = 1; m < LS; ++m) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.N + n];
+    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.S + n];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) w[m][5 + c] = WB[((long long)(m - 1) * 3 + c) * g.N + n];
+    for (int c = 0; c < 3; ++c) w[m][5 + c] = WB[((long long)(m - 1) * 3 + c) * g.S + n];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int a = 1; a < ORDER; ++a) {
       const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
-      w[m][5 + c] = BN[((long long)(a - 1) * 3 + c) * g.N + n];
+      w[m][5 + c] = BN[((long long)(a - 1) * 3 + c) * g.S + n];
     }
   {
     PosScan<T, 8, DEV> scan(w0);
@@ -814,12 +823,12 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
         for (int v = 0; v < 8; ++v) e[m][v] *= th;
     }
   }
-  store_side_mhd<S, T, 0>(w, e, ph, PK, g.N, n);
-  store_side_mhd<S, T, 1>(w, e, ph, PK, g.N, n);
-  store_side_mhd<S, T, 2>(w, e, ph, PK, g.N, n);
-  store_side_mhd<S, T, 3>(w, e, ph, PK, g.N, n);
-  store_side_mhd<S, T, 4>(w, e, ph, PK, g.N, n);
-  store_side_mhd<S, T, 5>(w, e, ph, PK, g.N, n);
+  store_side_mhd<S, T, 0>(w, e, ph, PK, g.S, n);
+  store_side_mhd<S, T, 1>(w, e, ph, PK, g.S, n);
+  store_side_mhd<S, T, 2>(w, e, ph, PK, g.S, n);
+  store_side_mhd<S, T, 3>(w, e, ph, PK, g.S, n);
+  store_side_mhd<S, T, 4>(w, e, ph, PK, g.S, n);
+  store_side_mhd<S, T, 5>(w, e, ph, PK, g.S, n);
 }
 
 // HLL at the lower AXIS-face of zone n (MHD): the five hydro fluxes, and the
@@ -837,26 +846,26 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
                                                             long long nl, double gam) {
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
   constexpr int TA[2] = {AXIS == 0 ? 1 : 0, AXIS == 2 ? 1 : 2};   // transverse axes
-  const T* L = PK + (long long)SL * 32 * g.N + nl;
-  const T* R = PK + (long long)SR * 32 * g.N + n;
+  const T* L = PK + (long long)SL * 32 * g.S + nl;
+  const T* R = PK + (long long)SR * 32 * g.S + n;
   double wl[8], wr[8];
   if constexpr (DEV) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      wl[v] = U[(long long)v * g.N + nl];
-      wr[v] = U[(long long)v * g.N + n];
+      wl[v] = U[(long long)v * g.S + nl];
+      wr[v] = U[(long long)v * g.S + n];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      wl[5 + c] = B0[(long long)c * g.N + nl];
-      wr[5 + c] = B0[(long long)c * g.N + n];
+      wl[5 + c] = B0[(long long)c * g.S + nl];
+      wr[5 + c] = B0[(long long)c * g.S + n];
     }
   }
   T ubl[8], ubr[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    ubl[v] = L[(long long)v * g.N];
-    ubr[v] = R[(long long)v * g.N];
+    ubl[v] = L[(long long)v * g.S];
+    ubr[v] = R[(long long)v * g.S];
     if constexpr (DEV) {
       ubl[v] += T(wl[v]);
       ubr[v] += T(wr[v]);
@@ -871,20 +880,20 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
   T ul[5], ur[5], fl[5], fr[5], out[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
-    ul[v] = L[(long long)(8 + v) * g.N];
-    ur[v] = R[(long long)(8 + v) * g.N];
-    fl[v] = L[(long long)(16 + v) * g.N];
-    fr[v] = R[(long long)(16 + v) * g.N];
+    ul[v] = L[(long long)(8 + v) * g.S];
+    ur[v] = R[(long long)(8 + v) * g.S];
+    fl[v] = L[(long long)(16 + v) * g.S];
+    fr[v] = R[(long long)(16 + v) * g.S];
     if constexpr (DEV) ur[v] += T(wr[v] - wl[v]);
   }
   hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
   T el[4], er[4], gl[4], gr[4], eout[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    el[q] = L[(long long)(24 + q) * g.N];
-    er[q] = R[(long long)(24 + q) * g.N];
-    gl[q] = L[(long long)(28 + q) * g.N];
-    gr[q] = R[(long long)(28 + q) * g.N];
+    el[q] = L[(long long)(24 + q) * g.S];
+    er[q] = R[(long long)(24 + q) * g.S];
+    gl[q] = L[(long long)(28 + q) * g.S];
+    gr[q] = R[(long long)(28 + q) * g.S];
     if constexpr (DEV) er[q] += T(wr[5 + TA[q / 2]] - wl[5 + TA[q / 2]]);
   }
   hll_combine<T, 4>(lam_l, lam_r, el, gl, er, gr, eout);
@@ -896,15 +905,15 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
 #pragma unroll
     for (int v = 0; v < 8; ++v) Fa[v] = (lr * Fl[v] - ll * Fr[v]) * inv;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = Fa[v] + double(out[v]);
+    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = Fa[v] + double(out[v]);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      FE[((long long)AXIS * 4 + q) * g.N + n] = Fa[5 + TA[q / 2]] + double(eout[q]);
+      FE[((long long)AXIS * 4 + q) * g.S + n] = Fa[5 + TA[q / 2]] + double(eout[q]);
   } else {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.N + n] = double(out[v]);
+    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.N + n] = double(eout[q]);
+    for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.S + n] = double(eout[q]);
   }
 }
 
@@ -915,9 +924,8 @@ __host__ __device__ __forceinline__ void face_flux_zone_mhd(const double* __rest
                                                             double* __restrict__ F,
                                                             double* __restrict__ FE, const Grid& g,
                                                             double gam, long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   face_flux_axis_mhd<T, 0, DEV>(U, B0, PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
   face_flux_axis_mhd<T, 1, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
   face_flux_axis_mhd<T, 2, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
@@ -928,13 +936,12 @@ __host__ __device__ __forceinline__ void face_flux_zone_mhd(const double* __rest
 // the edge (edge q = 2 w + (side > 0) of a face, w the transverse slot of a).
 __host__ __device__ __forceinline__ void edge_e_zone(const double* __restrict__ FE, double* __restrict__ E,
                                                      const Grid& g, long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   const long long mx = zone_of(wrap(i - 1, g.nx), j, k, g);
   const long long my = zone_of(i, wrap(j - 1, g.ny), k, g);
   const long long mz = zone_of(i, j, wrap(k - 1, g.nz), g);
-  auto fe = [&](int face, int q, long long zone) { return FE[((long long)face * 4 + q) * g.N + zone]; };
+  auto fe = [&](int face, int q, long long zone) { return FE[((long long)face * 4 + q) * g.S + zone]; };
   // E_x: y-faces (component B_z, sign -1), z-faces (component B_y, sign +1)
   double ex = 0.0;
   ex = ex - (fe(1, 2, n) + fe(1, 3, mz));
@@ -948,8 +955,8 @@ __host__ __device__ __forceinline__ void edge_e_zone(const double* __restrict__ 
   ez = ez - (fe(0, 0, n) + fe(0, 1, my));
   ez = ez + (fe(1, 0, n) + fe(1, 1, mx));
   E[n] = 0.25 * ex;
-  E[g.N + n] = 0.25 * ey;
-  E[2 * g.N + n] = 0.25 * ez;
+  E[g.S + n] = 0.25 * ey;
+  E[2 * g.S + n] = 0.25 * ez;
 }
 
 // eq. (8) for the three lower faces of zone n (double), with the eq. (6)
@@ -957,18 +964,17 @@ __host__ __device__ __forceinline__ void edge_e_zone(const double* __restrict__ 
 __host__ __device__ __forceinline__ void ct_zone(double* __restrict__ B, const double* __restrict__ E,
                                                  const Grid& g, double h, double dx, double dy,
                                                  double dz, long long n) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   const long long px = zone_of(wrap(i + 1, g.nx), j, k, g);
   const long long py = zone_of(i, wrap(j + 1, g.ny), k, g);
   const long long pz = zone_of(i, j, wrap(k + 1, g.nz), g);
   const double* Ex = E;
-  const double* Ey = E + g.N;
-  const double* Ez = E + 2 * g.N;
+  const double* Ey = E + g.S;
+  const double* Ez = E + 2 * g.S;
   B[n] = B[n] - h * ((Ez[py] - Ez[n]) / dy - (Ey[pz] - Ey[n]) / dz);
-  B[g.N + n] = B[g.N + n] - h * ((Ex[pz] - Ex[n]) / dz - (Ez[px] - Ez[n]) / dx);
-  B[2 * g.N + n] = B[2 * g.N + n] - h * ((Ey[px] - Ey[n]) / dx - (Ex[py] - Ex[n]) / dy);
+  B[g.S + n] = B[g.S + n] - h * ((Ex[pz] - Ex[n]) / dz - (Ez[px] - Ez[n]) / dx);
+  B[2 * g.S + n] = B[2 * g.S + n] - h * ((Ey[px] - Ey[n]) / dx - (Ex[py] - Ex[n]) / dy);
 }
 
 // CFL rate of one MHD zone, with the zone field taken as the mean of its
@@ -978,15 +984,14 @@ __host__ __device__ __forceinline__ double dt_rate_zone_mhd(const double* __rest
                                                             const Grid& g, double gam, double dx,
                                                             double dy, double dz, long long n,
                                                             int& isbad) {
-  const int i = (int)(n % g.nx);
-  const int j = (int)((n / g.nx) % g.ny);
-  const int k = (int)(n / ((long long)g.nx * g.ny));
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
   double u[8];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) u[v] = U[(long long)v * g.N + n];
+  for (int v = 0; v < 5; ++v) u[v] = U[(long long)v * g.S + n];
   u[5] = 0.5 * (B[n] + B[zone_of(wrap(i + 1, g.nx), j, k, g)]);
-  u[6] = 0.5 * (B[g.N + n] + B[g.N + zone_of(i, wrap(j + 1, g.ny), k, g)]);
-  u[7] = 0.5 * (B[2 * g.N + n] + B[2 * g.N + zone_of(i, j, wrap(k + 1, g.nz), g)]);
+  u[6] = 0.5 * (B[g.S + n] + B[g.S + zone_of(i, wrap(j + 1, g.ny), k, g)]);
+  u[7] = 0.5 * (B[2 * g.S + n] + B[2 * g.S + zone_of(i, j, wrap(k + 1, g.nz), g)]);
   const double p = Mhd<double>::pressure(u, gam);
   bool ok = u[0] > 0.0 && p > 0.0;
 #pragma unroll

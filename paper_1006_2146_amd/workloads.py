@@ -302,3 +302,22 @@ def alfven_wave_diagonal(shape, t=0.0, gamma=5.0 / 3.0, eps=0.1, p0=1.0):
     # |v|^2 = eps^2 and |B|^2 = 4 pi (1 + eps^2) are uniform, so E is exact
     U[4] = p0 / (gamma - 1.0) + 0.5 * eps * eps + b0 * b0 * (1.0 + eps * eps) / (2.0 * FOUR_PI)
     return U, B
+
+
+ENSEMBLE_SIDES = (32, 48, 64, 96)
+
+
+def ensemble_shapes(n=64, seed=4096, sides=ENSEMBLE_SIDES):
+    """(nz, ny, nx) of n problems, each side drawn independently and
+    uniformly from ``sides`` (the uneven batched-ensemble workload)."""
+    rng = np.random.default_rng(seed)
+    return [tuple(int(s) for s in rng.choice(sides, size=3)) for _ in range(n)]
+
+
+def ensemble(n=64, seed=4096, sides=ENSEMBLE_SIDES):
+    """The batched ensemble: n independent periodic unit-box problems of the
+    uneven shapes of ``ensemble_shapes``, each with its own seeded smooth
+    random-mode state (``random_smooth`` with seed ``seed + 1 + i``).
+    Returns a list of (shape, U)."""
+    return [(s, random_smooth(s, seed + 1 + i))
+            for i, s in enumerate(ensemble_shapes(n, seed, sides))]

@@ -119,7 +119,7 @@ extern "C" {
 // One MHD step of the host build, in place on U[5][N] and the face field B[3][N].
 int hostemu_step_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,
                      double dz, double gam, int order, int form, int precision, double dt) {
-  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
   if (precision == 0)
     emu_step_mhd<double, false>(U, B, g, dx, dy, dz, gam, order, form, dt);
   else if (precision == 1)
@@ -131,7 +131,7 @@ int hostemu_step_mhd(double* U, double* B, int nx, int ny, int nz, double dx, do
 
 double hostemu_dt_mhd(const double* U, const double* B, int nx, int ny, int nz, double dx,
                       double dy, double dz, double gam, double cfl) {
-  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
   double mx = 0.0;
   int bad = 0;
   for (long long n = 0; n < g.N; ++n) mx = fmax(mx, dt_rate_zone_mhd(U, B, g, gam, dx, dy, dz, n, bad));
@@ -141,7 +141,7 @@ double hostemu_dt_mhd(const double* U, const double* B, int nx, int ny, int nz, 
 // One step of the host build, in place on U[5][nz][ny][nx].
 int hostemu_step(double* U, int nx, int ny, int nz, double dx, double dy, double dz, double gam,
                  int order, int form, int riemann, int precision, double dt) {
-  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
   if (precision == 0)
     emu_step<double, false>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
   else if (precision == 1)
@@ -154,7 +154,7 @@ int hostemu_step(double* U, int nx, int ny, int nz, double dx, double dy, double
 // dt of the host build; returns -1 if a zone is unphysical.
 double hostemu_dt(const double* U, int nx, int ny, int nz, double dx, double dy, double dz,
                   double gam, double cfl) {
-  Grid g{nx, ny, nz, (long long)nx * ny * nz};
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
   double mx = 0.0;
   int bad = 0;
   for (long long n = 0; n < g.N; ++n) mx = fmax(mx, dt_rate_zone(U, g, gam, dx, dy, dz, n, bad));

@@ -1,0 +1,207 @@
+"""Batched execution on the GPU through the C ABI: many independent problems
+of uneven sizes advance with one persistent launch per stage, each with its
+own CFL dt.  Every zone's arithmetic is the same as in a lone run, so a
+problem of a batch must match its solo run bit for bit, whatever the launch
+shapes, in graph mode as eagerly, and after autotuning."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import OracleConfig, step_block
+from paper_1006_2146_amd import ader, workloads
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(5, 7, 9), (8, 8, 8), (3, 4, 12), (1, 6, 2), (9, 5, 4), (2, 1, 1)]
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _states(shapes, mhd=False):
+    out = []
+    for i, s in enumerate(shapes):
+        if mhd:
+            out.append(workloads.mhd_random_field(s, seed=100 + i))
+        else:
+            out.append((workloads.random_smooth(s, seed=100 + i), None))
+    return out
+
+
+def _solo(shape, U, B, steps, cfl=0.3, **kw):
+    with ader.Solver(shape, **kw) as s:
+        s.set_state(U, B)
+        dts = []
+        for _ in range(steps):
+            s.step_cfl(cfl)
+            dts.append(s.dt())
+        st = s.get_state()
+    return (st if B is not None else (st, None)), dts
+
+
+def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=False,
+               launch=None, **kw):
+    with ader.BatchSolver(shapes, stream=stream, **kw) as b:
+        for i, (U, B) in enumerate(states):
+            b.set_state(i, U, B)
+        if launch:
+            ader.ader_set_launch(b.ctx, launch)
+        if tune:
+            ader.ader_autotune(b.ctx, 2)
+        if graph:
+            ader.ader_set_graph(b.ctx, True)
+        dts = []
+        for _ in range(steps):
+            dts.append(b.step_cfl(cfl, want_dts=True))
+        res = [b.get_state(i) for i in range(len(shapes))]
+        shapes_used = ader.ader_get_launch(b.ctx)
+    res = [r if isinstance(r, tuple) else (r, None) for r in res]
+    return res, np.array(dts), shapes_used
+
+
+CONFIGS = [dict(order=3, precision=ader.ADER_FP64),
+           dict(order=3, precision=ader.ADER_MIXED),
+           dict(order=2, form=ader.ADER_NODAL, precision=ader.ADER_FP64),
+           dict(order=4, riemann=ader.ADER_LINEARIZED, precision=ader.ADER_MIXED)]
+
+
+@pytest.mark.parametrize("cfg", range(len(CONFIGS)))
+def test_batch_equals_solo_bitwise(cfg):
+    kw = CONFIGS[cfg]
+    states = _states(SHAPES)
+    say("batch vs solo", kw)
+    res, dts, _ = _batch_run(SHAPES, states, 2, **kw)
+    for i, (s, (U, _)) in enumerate(zip(SHAPES, states)):
+        (Us, _), sdts = _solo(s, U, None, 2, **kw)
+        assert np.array_equal(res[i][0], Us), i
+        assert np.array_equal(dts[:, i], np.array(sdts)), i
+
+
+@pytest.mark.parametrize("precision", [ader.ADER_FP64, ader.ADER_MIXED])
+def test_mhd_batch_equals_solo_bitwise(precision):
+    shapes = SHAPES[:4]
+    states = _states(shapes, mhd=True)
+    kw = dict(order=3, precision=precision, gamma=5.0 / 3.0, system=ader.ADER_MHD)
+    say("mhd batch vs solo", precision)
+    res, dts, _ = _batch_run(shapes, states, 2, **kw)
+    for i, (s, (U, B)) in enumerate(zip(shapes, states)):
+        (Us, Bs), sdts = _solo(s, U, B, 2, **kw)
+        assert np.array_equal(res[i][0], Us) and np.array_equal(res[i][1], Bs), i
+        assert np.array_equal(dts[:, i], np.array(sdts)), i
+
+
+def test_launch_shapes_graph_and_autotune_do_not_change_results():
+    states = _states(SHAPES)
+    kw = dict(order=3, precision=ader.ADER_MIXED)
+    ref, rdts, _ = _batch_run(SHAPES, states, 3, **kw)
+    stream = torch.cuda.Stream()
+    for launch in ({c: (64, 1) for c in ader.LAUNCH_CLASSES},
+                   {c: (256, 16) for c in ader.LAUNCH_CLASSES},
+                   {"dt": (128, 3), "recon": (192, 2), "predict": (64, 7), "flux": (256, 1),
+                    "update": (64, 64)}):
+        say("launch", launch)
+        got, dts, used = _batch_run(SHAPES, states, 3, launch=launch, **kw)
+        assert used == launch
+        assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
+    say("graph")
+    got, dts, _ = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream, **kw)
+    assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
+    say("autotune + graph")
+    got, dts, used = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream,
+                                tune=True, **kw)
+    assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
+    say("tuned shapes", used)
+
+
+def test_graph_replays_match_eager_with_host_work_between():
+    # each replay checked against the eager step, with host reads and
+    # synchronisations between replays
+    shape = (12, 10, 14)
+    U0 = workloads.random_smooth(shape, seed=9)
+    stream = torch.cuda.Stream()
+    kw = dict(order=3, precision=ader.ADER_FP64)
+    with ader.Solver(shape, **kw) as e, ader.Solver(shape, stream=stream.cuda_stream, **kw) as g:
+        e.set_state(U0)
+        g.set_state(U0)
+        ader.ader_set_graph(g.ctx, True)
+        for it in range(5):
+            say("replay", it)
+            e.step_cfl(0.3)
+            g.step_cfl(0.3)
+            g.synchronize()
+            assert np.array_equal(g.get_state(), e.get_state()), it
+            assert g.dt() == e.dt()
+        # a new cfl re-captures the graph
+        e.step_cfl(0.2)
+        g.step_cfl(0.2)
+        assert np.array_equal(g.get_state(), e.get_state())
+
+
+def test_graph_needs_a_stream():
+    with ader.Solver((4, 4, 4)) as s:
+        assert ader.load().ader_set_graph(s.ctx, 1) == ader.ADER_EUNSUPPORTED
+
+
+def test_batch_sequence_and_errors():
+    lib = ader.load()
+    with ader.BatchSolver([(4, 4, 4), (3, 5, 2)]) as b:
+        # stepping before every problem has a state
+        assert lib.ader_step_cfl(b.ctx, 0.3) == ader.ADER_ESEQ
+        b.set_state(0, workloads.random_smooth((4, 4, 4), seed=1))
+        assert lib.ader_step_cfl(b.ctx, 0.3) == ader.ADER_ESEQ
+        bad = workloads.random_smooth((3, 5, 2), seed=2)
+        bad[0, 1, 2, 1] = -1.0
+        with pytest.raises(ader.AderError):
+            b.set_state(1, bad)
+        b.set_state(1, workloads.random_smooth((3, 5, 2), seed=2))
+        b.step_cfl(0.3)
+        assert ader.ader_batch_size(b.ctx) == 2
+        assert lib.ader_compute_dt(b.ctx, 0.3, ader.ctypes.byref(ader.ctypes.c_double())) == \
+            ader.ADER_EINVAL
+        assert len(b.dts()) == 2 and all(d > 0 for d in b.dts())
+
+
+def test_config4_ensemble_full_size():
+    # 64 problems, sides drawn from {32, 48, 64, 96} per axis, order 3, HLL,
+    # mixed precision, autotuned, graph-captured: sampled problems match
+    # their solo runs bit for bit, and an FP64 batch matches the oracle on
+    # sampled blocks of sampled problems
+    ens = workloads.ensemble()
+    shapes = [s for s, _ in ens]
+    stream = torch.cuda.Stream()
+    say("config4 mixed batch", sum(int(np.prod(s)) for s in shapes), "zones")
+    with ader.BatchSolver(shapes, order=3, precision=ader.ADER_MIXED,
+                          stream=stream.cuda_stream) as b:
+        for i, (_, U) in enumerate(ens):
+            b.set_state(i, U)
+        ader.ader_autotune(b.ctx, 2)
+        ader.ader_set_graph(b.ctx, True)
+        for _ in range(3):
+            b.step_cfl(0.3)
+        b.synchronize()
+        pick = [0, 17, 42, 63]
+        got = {i: b.get_state(i) for i in pick}
+        dts = b.dts()
+    for i in pick:
+        say("config4 solo", i, shapes[i])
+        (Us, _), sdts = _solo(shapes[i], ens[i][1], None, 3, order=3, precision=ader.ADER_MIXED)
+        assert np.array_equal(got[i], Us), i
+        assert dts[i] == sdts[-1]
+    say("config4 fp64 batch vs oracle")
+    with ader.BatchSolver(shapes, order=3, precision=ader.ADER_FP64) as b:
+        for i, (_, U) in enumerate(ens):
+            b.set_state(i, U)
+        b.step_cfl(0.3)
+        dts = b.dts()
+        for i in (5, 33):
+            U1 = b.get_state(i)
+            cfg = OracleConfig(order=3)
+            o = (1, shapes[i][1] - 2, 7)
+            ref = step_block(ens[i][1], dts[i], cfg, o, (3, 4, 3))
+            n = shapes[i]
+            sub = U1[:, np.arange(o[0], o[0] + 3) % n[0]][:, :, np.arange(o[1], o[1] + 4) % n[1]][
+                :, :, :, np.arange(o[2], o[2] + 3) % n[2]]
+            err = np.abs(sub - ref).sum(axis=(1, 2, 3)) / np.abs(ref).sum(axis=(1, 2, 3))
+            assert np.all(err <= 1e-12), (i, err)
