@@ -187,6 +187,7 @@ int ader_set_graph(ader_ctx* ctx, int enable);
  * own problems and settings, `reps` launches each (1..1000), and keeps the
  * fastest.  The state and dt are saved before and restored after, so the
  * solution does not advance; results do not depend on the launch shape.
+ * For the predictor it also tries both layouts (ader_set_layout).
  * Needs a state (ADER_ESEQ); allocates a temporary copy of it. */
 int ader_autotune(ader_ctx* ctx, int reps);
 
@@ -195,6 +196,19 @@ int ader_autotune(ader_ctx* ctx, int reps);
  * (1..64). */
 int ader_get_launch(ader_ctx* ctx, int* block_out, int* blocks_per_cu_out);
 int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
+
+/* Layout of the predictor kernel (Sec. IV and App. D work of a zone):
+ * ADER_LAYOUT_ZONE, one lane per zone holding all variables, or
+ * ADER_LAYOUT_SPLIT, one lane per (zone, variable) gathering the zone's
+ * state across lanes at each flux evaluation (orders 3 and 4 only,
+ * ADER_EUNSUPPORTED at order 2), ADER_LAYOUT_SPLIT2, the same compiled to
+ * fit two waves per SIMD, or -1 for the default of the setting (split for
+ * MHD at orders 3-4 and Euler at order 4).  Results do not
+ * depend on the layout beyond rounding order.  ader_autotune also picks it.
+ * ader_get_layout returns the layout the current setting uses. */
+enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2 };
+int ader_set_layout(ader_ctx* ctx, int layout);
+int ader_get_layout(ader_ctx* ctx, int* layout_out);
 
 #ifdef __cplusplus
 }

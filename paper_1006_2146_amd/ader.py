@@ -32,8 +32,9 @@ EXPORTS = [
     "ader_device_bytes", "ader_strerror", "ader_destroy",
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
-    "ader_set_launch",
+    "ader_set_launch", "ader_set_layout", "ader_get_layout",
 ]
+ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2 = 0, 1, 2
 LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
 
@@ -93,6 +94,8 @@ def load():
         "ader_autotune": ([P, I], I),
         "ader_get_launch": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "ader_set_launch": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], I),
+        "ader_set_layout": ([P, I], I),
+        "ader_get_layout": ([P, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,6 +276,16 @@ def ader_get_launch(ctx):
     g = (ctypes.c_int * k)()
     _check(load().ader_get_launch(ctx, b, g), "ader_get_launch")
     return {name: (b[i], g[i]) for i, name in enumerate(LAUNCH_CLASSES)}
+
+
+def ader_set_layout(ctx, layout):
+    _check(load().ader_set_layout(ctx, layout), "ader_set_layout")
+
+
+def ader_get_layout(ctx):
+    out = ctypes.c_int()
+    _check(load().ader_get_layout(ctx, ctypes.byref(out)), "ader_get_layout")
+    return out.value
 
 
 def ader_set_launch(ctx, shapes):

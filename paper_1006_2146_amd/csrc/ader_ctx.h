@@ -47,6 +47,8 @@ namespace ader {
 struct StageFns {
   int (*recon)(ader_ctx*);
   int (*predict)(ader_ctx*);
+  int (*predict_split)(ader_ctx*);    // lane-split layout, nullptr if not built
+  int (*predict_split2)(ader_ctx*);   // the same, registers capped for 2 waves/SIMD
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
 };
@@ -88,6 +90,8 @@ struct ader_ctx {
   bool have_dt = false;
   size_t bytes = 0;
   ader::LaunchShape shape[ader::kNumClasses] = {{256, 8}, {256, 8}, {128, 4}, {256, 8}, {256, 8}};
+  // predictor layout: -1 the variant's default, else an ADER_LAYOUT_*
+  int layout = -1;
   // stage timing: events recorded around each stage while enabled
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -114,10 +118,12 @@ inline int launched() { return check(hipGetLastError()); }
   } while (0)
 
 // Persistent grid of a kernel class: blocks_per_cu blocks per compute unit,
-// and never more blocks than the zones need.
-inline unsigned grid_for(const ader_ctx* c, int cls) {
+// and never more blocks than the zones need (zones_per_wave zones per 64
+// lanes: 64 for one zone per lane, 64 / NV in the lane-split layout).
+inline unsigned grid_for(const ader_ctx* c, int cls, int zones_per_wave = 64) {
   const LaunchShape& s = c->shape[cls];
-  const long long need = (c->S + s.block - 1) / s.block;
+  const long long per_block = (long long)zones_per_wave * (s.block / 64);
+  const long long need = (c->S + per_block - 1) / per_block;
   const long long cap = (long long)s.blocks_per_cu * c->num_cus;
   const long long g = need < cap ? need : cap;
   return (unsigned)(g < 1 ? 1 : g);

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ader_ctx.h"
+#include "lane_split.h"
 #include "zone_ops.h"
 
 namespace ader {
@@ -103,6 +104,56 @@ __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ 
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone_mhd<T, ORDER, FORM, kDeviation<T>>(U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p],
                                                     1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+  });
+}
+
+// Zone loop of the lane-split kernels: the same chunks as for_zones, walked
+// Z = 64 / NV zones per wave and step, lane var * Z + z on zone slot z.
+// Lanes past NV Z (when 64 is not a multiple of NV) stay idle.
+template <int NV, class Body>
+__device__ __forceinline__ void for_zone_groups(const Batch& b, Body&& body) {
+  constexpr int Z = 64 / NV;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const SplitLane L{lane / Z, lane % Z, Z};
+  if (L.var >= NV) return;
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long rlo = b.S * x / nreg, rhi = b.S * (x + 1) / nreg;
+  const long long lo = rlo + (rhi - rlo) * r / nb, hi = rlo + (rhi - rlo) * (r + 1) / nb;
+  long long n = lo + (long long)wave * Z + L.z;
+  if (n >= hi) return;
+  int p = find_problem(b, n);
+  Problem pr = b.P[p];
+  for (; n < hi; n += (long long)nw * Z) {
+    while (n >= pr.base + pr.N) pr = b.P[++p];
+    body(L, pr, p, n);
+  }
+}
+
+// WAVES: the compiler keeps the registers low enough for that many waves
+// per SIMD (1: no cap); the autotuner picks between the instances.
+template <class T, int ORDER, int FORM, int WAVES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_split(const double* __restrict__ U,
+                                                       const T* __restrict__ W, T* __restrict__ PK,
+                                                       Batch b, const double* __restrict__ dt,
+                                                       double gam) {
+  for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
+    predict_zone_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, PK, grid_of(pr, b), dt[p],
+                                                      1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+  });
+}
+
+template <class T, int ORDER, int FORM, int WAVES>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_split(
+    const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
+    const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, Batch b,
+    const double* __restrict__ dt, double gam) {
+  for_zone_groups<8>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
+    predict_zone_mhd_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, B0, WB, BN, PK, grid_of(pr, b),
+                                                          dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
+                                                          1.0 / pr.dz, gam, n);
   });
 }
 

@@ -79,6 +79,23 @@ int queue_dt(ader_ctx* c, double cfl) {
   return ADER_OK;
 }
 
+// The predictor layout in use: the one set, else lane-split where it keeps
+// the per-lane state small enough to avoid spills (MHD at orders 3 and 4,
+// Euler at order 4), one lane per zone otherwise.
+int layout_of(const ader_ctx* c, const StageFns* s) {
+  if (!s->predict_split) return ADER_LAYOUT_ZONE;
+  if (c->layout >= 0) return c->layout;
+  return (c->system == ADER_MHD || c->order == 4) ? ADER_LAYOUT_SPLIT : ADER_LAYOUT_ZONE;
+}
+
+int queue_predict(ader_ctx* c, const StageFns* s) {
+  switch (layout_of(c, s)) {
+    case ADER_LAYOUT_SPLIT: return s->predict_split(c);
+    case ADER_LAYOUT_SPLIT2: return s->predict_split2(c);
+    default: return s->predict(c);
+  }
+}
+
 int queue_step(ader_ctx* c) {
   const StageFns* s = stages_of(c);
   if (!s) return ADER_EUNSUPPORTED;
@@ -88,7 +105,7 @@ int queue_step(ader_ctx* c) {
   }
   {
     StageTimer t(c, ADER_STAGE_PREDICT);
-    ADER_TRY(s->predict(c));
+    ADER_TRY(queue_predict(c, s));
   }
   {
     StageTimer t(c, ADER_STAGE_FLUX);
@@ -104,6 +121,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)c->form;
   k = k * 3 + (unsigned long long)c->riemann;
   k = k * 3 + (unsigned long long)c->precision;
+  k = k * 3 + (unsigned long long)(c->layout + 1);
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
@@ -348,7 +366,7 @@ int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
     switch (cls) {
       case kClassDt: rc = queue_dt(c, 0.3); break;
       case kClassRecon: rc = s->recon(c); break;
-      case kClassPredict: rc = s->predict(c); break;
+      case kClassPredict: rc = queue_predict(c, s); break;
       case kClassFlux: rc = s->flux(c); break;
       default: rc = s->update(c); break;
     }
@@ -389,19 +407,27 @@ int autotune(ader_ctx* c, int reps) {
   for (int qi = 0; qi < kNumClasses && rc == ADER_OK; ++qi) {
     const int cls = order_of_classes[qi];
     LaunchShape best = c->shape[cls];
+    int best_layout = c->layout;
     float best_ms = 1e30f;
-    for (const LaunchShape& cand : kCandidates) {
-      c->shape[cls] = cand;
-      float ms = 0.f;
-      rc = time_stage(c, cls, s, 1, &ms);  // warm-up
-      if (rc == ADER_OK) rc = time_stage(c, cls, s, reps, &ms);
-      if (rc != ADER_OK) break;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = cand;
+    // the predictor also tries both layouts where the lane-split one is built
+    const int nlayouts = (cls == kClassPredict && s->predict_split) ? 3 : 1;
+    for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
+      if (nlayouts > 1) c->layout = lay;
+      for (const LaunchShape& cand : kCandidates) {
+        c->shape[cls] = cand;
+        float ms = 0.f;
+        rc = time_stage(c, cls, s, 1, &ms);  // warm-up
+        if (rc == ADER_OK) rc = time_stage(c, cls, s, reps, &ms);
+        if (rc != ADER_OK) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cand;
+          best_layout = c->layout;
+        }
       }
     }
     c->shape[cls] = best;
+    c->layout = best_layout;
   }
   c->timing = timing;
   // restore the state, dt and clear the flags the trial steps may have set
@@ -627,6 +653,20 @@ int ader_set_launch(ader_ctx* c, const int* block, const int* blocks_per_cu) {
         blocks_per_cu[q] > 64)
       return ADER_EINVAL;
   for (int q = 0; q < kNumClasses; ++q) c->shape[q] = LaunchShape{block[q], blocks_per_cu[q]};
+  return ADER_OK;
+}
+
+int ader_set_layout(ader_ctx* c, int layout) {
+  if (!c || layout < -1 || layout > ADER_LAYOUT_SPLIT2) return ADER_EINVAL;
+  if (layout > ADER_LAYOUT_ZONE && c->order < 3) return ADER_EUNSUPPORTED;
+  c->layout = layout;
+  return ADER_OK;
+}
+
+int ader_get_layout(ader_ctx* c, int* layout_out) {
+  if (!c || !layout_out) return ADER_EINVAL;
+  const StageFns* s = stages_of(c);
+  *layout_out = s ? layout_of(c, s) : (c->layout < 0 ? ADER_LAYOUT_ZONE : c->layout);
   return ADER_OK;
 }
 

@@ -64,6 +64,29 @@ int predict(ader_ctx* c) {
   return launched();
 }
 
+// the lane-split layout (orders 3 and 4); WAVES caps the registers for that
+// many waves per SIMD
+template <int WAVES>
+int predict_split(ader_ctx* c) {
+  if constexpr (kOrder >= 3) {
+    constexpr int NV = kMhd ? 8 : 5;
+    const unsigned g = grid_for(c, kClassPredict, 64 / NV);
+    const int bs = c->shape[kClassPredict].block;
+    const T* W = static_cast<const T*>(c->W);
+    T* PK = static_cast<T*>(c->PK);
+    if constexpr (kMhd)
+      k_predict_mhd_split<T, kOrder, kForm, WAVES><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK,
+          c->batch(), c->d_dt, c->gamma);
+    else
+      k_predict_split<T, kOrder, kForm, WAVES><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(),
+                                                                        c->d_dt, c->gamma);
+    return launched();
+  } else {
+    return ADER_EUNSUPPORTED;
+  }
+}
+
 int flux(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassFlux);
   const int bs = c->shape[kClassFlux].block;
@@ -90,7 +113,8 @@ int update(ader_ctx* c) {
   return launched();
 }
 
-const StageFns kStages = {recon, predict, flux, update};
+const StageFns kStages = {recon, predict, kOrder >= 3 ? predict_split<1> : nullptr,
+                          kOrder >= 3 ? predict_split<2> : nullptr, flux, update};
 
 }  // namespace
 

@@ -751,7 +751,8 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
     fav = face_average_weights(order)
     ew = {(which, sg): edge_average_weights(order, which, sg) for which in (0, 1) for sg in (-1, 1)}
     out.append("  // ue[q], fe[q]: edge averages of u and of the normal flux of the field")
-    out.append("  // component along transverse axis t_w, edge q = 2 w + (sign > 0)")
+    out.append("  // component along transverse axis t_w, edge q = 2 w + (sign > 0);")
+    out.append("  // Phys::comp(c) is where variable c sits in this lane's arrays")
     out.append("  template <int SIDE, class Phys>")
     out.append("  __host__ __device__ static inline void side_edges(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
     out.append("      T (&ub)[NV], T (&ua)[NV], T (&fa)[NV], T (&ue)[4], T (&fe)[4]) {")
@@ -777,7 +778,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                     row.append(0 if ex[free] != 0 else
                                P(ex[d], HALF * s_) * P(ex[a], HALF * sg) / (dd + 1))
                 _count((tag, 'faces-mhd'), 2 * (sum(1 for c in row if c != 0) - (1 if _is_dev() else 0)))
-                out.append("      ue[%d] = %s;" % (q, _value(row, ls, str(5 + a))))
+                out.append("      ue[%d] = %s;" % (q, _value(row, ls, "Phys::comp(%d)" % (5 + a))))
         out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
         out.append("      for (int q = 0; q < 4; ++q) fe[q] = T(0);")
         for j in range(1, nf + 1):
@@ -795,7 +796,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
             for which, sg in used_edge:
                 q = 2 * which + (1 if sg > 0 else 0)
                 a = tr[which]
-                out.append("      fe[%d] += %s * fl[%d];" % (q, lit(ew[(which, sg)][j]), 5 + a))
+                out.append("      fe[%d] += %s * fl[Phys::comp(%d)];" % (q, lit(ew[(which, sg)][j]), 5 + a))
                 _count((tag, 'faces-mhd'), 2)
         out.append("    }")
     out.append("  }")

@@ -1,0 +1,269 @@
+// Lane-split layout of the predictor (device only): the NV variables of a
+// zone live in NV lanes of one wavefront, one variable per lane, so a lane
+// keeps only its own variable's spatial modes, evolutionary modes and
+// accumulators (about 65 values at order 4 instead of 65 NV).  Lane
+// var * Z + z holds variable var of zone slot z; a wave serves Z = 64 / NV
+// zones.  Wherever the scheme needs a whole state (a flux, a positivity
+// check) the zone's lanes gather it with ds_bpermute and evaluate it
+// redundantly, each keeping its own component.  The generated per-zone code
+// runs unchanged with one variable per lane: the flux evaluator and the
+// positivity scan below do the gathering.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "zone_ops.h"
+
+namespace ader {
+
+struct SplitLane {
+  int var;  // the variable this lane holds
+  int z;    // zone slot in the wave
+  int Z;    // zones per wave
+};
+
+__device__ __forceinline__ float lane_read(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(lane << 2, __float_as_int(x)));
+}
+
+__device__ __forceinline__ double lane_read(double x, int lane) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(lane << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(lane << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// full[c] = variable c of this lane's zone
+template <int NV, class T>
+__device__ __forceinline__ void gather(const SplitLane& L, T own, T (&full)[NV]) {
+#pragma unroll
+  for (int c = 0; c < NV; ++c) full[c] = lane_read(own, c * L.Z + L.z);
+}
+
+// this lane's component of a full vector (selects, no dynamic indexing)
+template <int NV, class T>
+__device__ __forceinline__ T pick(const SplitLane& L, const T (&full)[NV]) {
+  T r = full[0];
+#pragma unroll
+  for (int c = 1; c < NV; ++c) r = L.var == c ? full[c] : r;
+  return r;
+}
+
+// Flux evaluator of the lane-split layout: gathers the zone's state at the
+// point, evaluates the whole flux (point or deviation form) and returns this
+// lane's component.
+template <class P, class T, bool DEV>
+struct SplitFlux {
+  static constexpr bool kDeviation = DEV;
+  static constexpr int comp(int) { return 0; }
+  typename FluxOf<P, T, DEV>::type inner;
+  SplitLane L;
+  template <int AXIS>
+  __device__ inline void flux(const T (&u)[1], T (&f)[1]) const {
+    T full[P::NV], fl[P::NV];
+    gather(L, u[0], full);
+    inner.template flux<AXIS>(full, fl);
+    f[0] = pick(L, fl);
+  }
+};
+
+// Positivity scan of the lane-split layout (every lane of a zone scans the
+// same gathered states, so the flag agrees across them).
+template <class T, int NV, bool DEV>
+struct SplitScan {
+  static constexpr bool kDeviation = DEV;
+  PosScan<T, NV, DEV> inner;
+  SplitLane L;
+  __device__ void operator()(const T (&u)[1]) {
+    T full[NV];
+    gather(L, u[0], full);
+    inner(full);
+  }
+};
+
+// Exact positivity pass (rare): this lane's component at each check point in
+// double, the zone's state gathered, the same theta in every lane of a zone.
+template <int NP, int LS, class T, int NV>
+__device__ double theta_spatial_split(const SplitLane& L, const double (&w0)[NV],
+                                      const T (&w)[LS][1], const double (&phi)[NP][LS],
+                                      double gam) {
+  PosTheta<T, NV> acc(w0, gam);
+  const double own0 = pick(L, w0);
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    double s = own0;
+#pragma unroll
+    for (int m = 1; m < LS; ++m) s += phi[p][m] * double(w[m][0]);
+    double u[NV];
+    gather(L, s, u);
+    acc(u);
+  }
+  return acc.theta;
+}
+
+template <int NP, int LS, int NE, class T, int NV>
+__device__ double theta_facial_split(const SplitLane& L, const double (&w0)[NV],
+                                     const T (&w)[LS][1], const T (&e)[NE][1],
+                                     const double (&phi)[NP][LS + NE], double gam) {
+  PosTheta<T, NV> acc(w0, gam);
+  const double own0 = pick(L, w0);
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    double s = own0;
+#pragma unroll
+    for (int m = 1; m < LS; ++m) s += phi[p][m] * double(w[m][0]);
+#pragma unroll
+    for (int m = 0; m < NE; ++m) s += phi[p][LS + m] * double(e[m][0]);
+    double u[NV];
+    gather(L, s, u);
+    acc(u);
+  }
+  return acc.theta;
+}
+
+// The same operations as predict_zone (Euler), in the lane-split layout.
+template <class T, int ORDER, int FORM, bool DEV>
+__device__ __forceinline__ void predict_zone_split(const SplitLane& L, const double* __restrict__ U,
+                                                   const T* __restrict__ W, T* __restrict__ PK,
+                                                   const Grid& g, double h, double inv_dx,
+                                                   double inv_dy, double inv_dz, double gam,
+                                                   long long n) {
+  using S = typename SchemeOf<ORDER, FORM, T, 1>::type;
+  constexpr int LS = S::LS, NE = S::NE;
+  double w0[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
+  T w[LS][1];
+  w[0][0] = DEV ? T(0) : T(pick(L, w0));
+#pragma unroll
+  for (int m = 1; m < LS; ++m) w[m][0] = W[((long long)(m - 1) * 5 + L.var) * g.S + n];
+  {
+    SplitScan<T, 5, DEV> scan{PosScan<T, 5, DEV>(w0), L};
+    S::spatial_points(w, scan);
+    const double theta = scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m) w[m][0] *= th;
+    }
+  }
+  const SplitFlux<Euler<T>, T, DEV> ph{FluxOf<Euler<T>, T, DEV>::make(w0, gam), L};
+  T e[NE][1];
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  {
+    SplitScan<T, 5, DEV> scan{PosScan<T, 5, DEV>(w0), L};
+    S::facial_points(w, e, scan);
+    const double theta =
+        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m) w[m][0] *= th;
+#pragma unroll
+      for (int m = 0; m < NE; ++m) e[m][0] *= th;
+    }
+  }
+  T* base = PK + (long long)L.var * g.S + n;
+  auto side = [&](auto side_c) {
+    constexpr int SIDE = decltype(side_c)::value;
+    T ub[1], ua[1], fa[1];
+    S::template side<SIDE>(w, e, ph, ub, ua, fa);
+    base[(long long)((SIDE * 3 + 0) * 5) * g.S] = ub[0];
+    base[(long long)((SIDE * 3 + 1) * 5) * g.S] = ua[0];
+    base[(long long)((SIDE * 3 + 2) * 5) * g.S] = fa[0];
+  };
+  side(std::integral_constant<int, 0>{});
+  side(std::integral_constant<int, 1>{});
+  side(std::integral_constant<int, 2>{});
+  side(std::integral_constant<int, 3>{});
+  side(std::integral_constant<int, 4>{});
+  side(std::integral_constant<int, 5>{});
+}
+
+// The same operations as predict_zone_mhd, in the lane-split layout.
+template <class T, int ORDER, int FORM, bool DEV>
+__device__ __forceinline__ void predict_zone_mhd_split(
+    const SplitLane& L, const double* __restrict__ U, const T* __restrict__ W,
+    const double* __restrict__ B0, const T* __restrict__ WB, const T* __restrict__ BN,
+    T* __restrict__ PK, const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz,
+    double gam, long long n) {
+  using S = typename SchemeOf<ORDER, FORM, T, 1>::type;
+  constexpr int LS = S::LS, NE = S::NE;
+  double w0[8];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w0[5 + c] = B0[(long long)c * g.S + n];
+  const bool field = L.var >= 5;
+  // this lane's modes: hydro from W, field from WB
+  const T* src = field ? WB + (long long)(L.var - 5) * g.S + n : W + (long long)L.var * g.S + n;
+  const long long stride = (long long)(field ? 3 : 5) * g.S;
+  T w[LS][1];
+  w[0][0] = DEV ? T(0) : T(pick(L, w0));
+#pragma unroll
+  for (int m = 1; m < LS; ++m) w[m][0] = src[(long long)(m - 1) * stride];
+  // the Sec. III normal moments on the pure-normal slots of each field lane
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int a = 1; a < ORDER; ++a) {
+      const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
+      if (L.var == 5 + c) w[m][0] = BN[((long long)(a - 1) * 3 + c) * g.S + n];
+    }
+  {
+    SplitScan<T, 8, DEV> scan{PosScan<T, 8, DEV>(w0), L};
+    S::spatial_points_all(w, scan);
+    const double theta =
+        scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m) w[m][0] *= th;
+    }
+  }
+  const SplitFlux<Mhd<T>, T, DEV> ph{FluxOf<Mhd<T>, T, DEV>::make(w0, gam), L};
+  T e[NE][1];
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  {
+    SplitScan<T, 8, DEV> scan{PosScan<T, 8, DEV>(w0), L};
+    S::facial_points_all(w, e, scan);
+    const double theta =
+        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m) w[m][0] *= th;
+#pragma unroll
+      for (int m = 0; m < NE; ++m) e[m][0] *= th;
+    }
+  }
+  auto side = [&](auto side_c) {
+    constexpr int SIDE = decltype(side_c)::value;
+    constexpr int AX = SIDE / 2;
+    constexpr int TA0 = AX == 0 ? 1 : 0, TA1 = AX == 2 ? 1 : 2;   // transverse axes
+    T ub[1], ua[1], fa[1], ue[4], fe[4];
+    S::template side_edges<SIDE>(w, e, ph, ub, ua, fa, ue, fe);
+    T* base = PK + (long long)SIDE * 32 * g.S + n;
+    base[(long long)L.var * g.S] = ub[0];
+    base[(long long)(8 + L.var) * g.S] = ua[0];
+    base[(long long)(16 + L.var) * g.S] = fa[0];
+    // edge values of the field component along each transverse axis: the
+    // lane holding that component has them
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (L.var == 5 + (q < 2 ? TA0 : TA1)) {
+        base[(long long)(24 + q) * g.S] = ue[q];
+        base[(long long)(28 + q) * g.S] = fe[q];
+      }
+    }
+  };
+  side(std::integral_constant<int, 0>{});
+  side(std::integral_constant<int, 1>{});
+  side(std::integral_constant<int, 2>{});
+  side(std::integral_constant<int, 3>{});
+  side(std::integral_constant<int, 4>{});
+  side(std::integral_constant<int, 5>{});
+}
+
+}  // namespace ader

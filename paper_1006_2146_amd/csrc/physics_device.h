@@ -181,10 +181,12 @@ struct Mhd {
 // at a point and returns its physical flux; DeviationFlux takes the deviation
 // of the state from the zone average and returns the deviation of the flux
 // (exact algebra, the mixed-precision path).  kDeviation tells the generated
-// code whether point values carry the zone average.
+// code whether point values carry the zone average; comp(c) is the slot of
+// variable c in the arrays it is handed.
 template <class P, class T>
 struct PointFlux {
   static constexpr bool kDeviation = false;
+  static constexpr int comp(int c) { return c; }
   T gam;
   template <int AXIS, int NV>
   __host__ __device__ inline void flux(const T (&u)[NV], T (&f)[NV]) const {
@@ -195,6 +197,7 @@ struct PointFlux {
 template <class P, class T>
 struct DeviationFlux {
   static constexpr bool kDeviation = true;
+  static constexpr int comp(int c) { return c; }
   typename P::Ref ref;
   T gam;
   template <int AXIS, int NV>

@@ -219,3 +219,59 @@ def test_config3_mhd_full_size_sampled():
         pick = lambda A: A[:, iz][:, :, iy][:, :, :, ix]  # noqa: E731
         assert np.all(rel_l1(pick(Ug), Ur) <= TOL_FP64), o
         assert np.all(rel_l1(pick(Bg), Br) <= TOL_FP64), o
+
+
+# --------------------------------------------------------- predictor layouts --
+
+LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("order,rs", [(3, "hll"), (4, "linearized")])
+def test_parity_layouts_euler(layout, order, rs):
+    # every predictor layout against the oracle: smooth ragged mesh, and a
+    # blast where the positivity scaling (and its exact pass) is active
+    for tag, U0, lengths, steps in (
+            ("smooth", workloads.random_smooth((9, 14, 21), seed=order + 7), (1.0, 0.8, 1.3), 2),
+            ("blast", workloads.blast((12, 12, 12), p_in=100.0, p_out=0.1, radius=0.25),
+             (1.0, 1.0, 1.0), 2)):
+        cfg = OracleConfig(order=order, riemann=rs, lengths=lengths)
+        with _solver(U0.shape[1:], order, "modal", rs, lengths) as s:
+            ader.ader_set_layout(s.ctx, layout)
+            assert ader.ader_get_layout(s.ctx) == layout
+            s.set_state(U0)
+            U = U0
+            for it in range(steps):
+                say("layout", layout, tag, order, rs, "step", it)
+                dt = s.compute_dt(0.3)
+                s.step(dt)
+                Ug = s.get_state()
+                err = rel_l1(Ug, oracle_step(U, dt, cfg))
+                assert np.all(err <= TOL_FP64), (tag, it, err)
+                U = Ug
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("order", [3, 4])
+def test_parity_layouts_mhd(layout, order):
+    U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order + 20)
+    cfg = OracleConfig(order=order, gamma=G53, lengths=(1.0, 0.9, 1.2))
+    with _mhd_solver((7, 9, 10), order, "modal", lengths=(1.0, 0.9, 1.2)) as s:
+        ader.ader_set_layout(s.ctx, layout)
+        s.set_state(U0, B0)
+        U, B = U0, B0
+        for it in range(2):
+            say("mhd layout", layout, order, "step", it)
+            dt = s.compute_dt(0.3)
+            s.step(dt)
+            Ug, Bg = s.get_state()
+            Uo, Bo = oracle_step(U, dt, cfg, B)
+            assert np.all(rel_l1(Ug, Uo) <= TOL_FP64) and np.all(rel_l1(Bg, Bo) <= TOL_FP64), it
+            U, B = Ug, Bg
+
+
+def test_layout_errors():
+    with _solver((4, 4, 4), 2, "modal", "hll") as s:
+        assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_SPLIT) == ader.ADER_EUNSUPPORTED
+        assert ader.load().ader_set_layout(s.ctx, 7) == ader.ADER_EINVAL
+        assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE
