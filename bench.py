@@ -27,6 +27,7 @@ SHAPE = (128, 128, 128)
 CFL = 0.3
 WORKLOAD = "sedov-modes-128^3"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
 
 
@@ -76,6 +77,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         s.synchronize()
         finite = bool(torch.isfinite(dU).all().item())
         launch = ader.ader_get_launch(s.ctx)
+        layout = LAYOUT_NAMES[ader.ader_get_layout(s.ctx)]
     finally:
         s.close()
     wall = t1 - t0
@@ -84,6 +86,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         "ms_per_step": 1e3 * wall / steps,
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "launch": launch,
+        "predict_layout": layout,
         "finite": finite,
     }
 
@@ -121,7 +124,8 @@ def run_ensemble(ader, torch, steps, warmup):
             out[name] = {"zone_updates_per_s": zones * steps / (t1 - t0),
                          "ms_per_step": 1e3 * (t1 - t0) / steps,
                          "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
-                         "launch": ader.ader_get_launch(b.ctx)}
+                         "launch": ader.ader_get_launch(b.ctx),
+                         "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(b.ctx)]}
         log("ensemble", name, "%.3e zone-updates/s" % out[name]["zone_updates_per_s"])
     out["mixed_over_fp64"] = out["mixed"]["zone_updates_per_s"] / out["fp64"]["zone_updates_per_s"]
     return out

@@ -202,11 +202,13 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * ADER_LAYOUT_SPLIT, one lane per (zone, variable) gathering the zone's
  * state across lanes at each flux evaluation (orders 3 and 4 only,
  * ADER_EUNSUPPORTED at order 2), ADER_LAYOUT_SPLIT2, the same compiled to
- * fit two waves per SIMD, or -1 for the default of the setting (split for
- * MHD at orders 3-4 and Euler at order 4).  Results do not
+ * fit two waves per SIMD, ADER_LAYOUT_ZONE2, one lane per zone with the
+ * facial positivity check in a pass of its own rather than inside the face
+ * quadrature (orders 2 and 3 only), or -1 for the default of the setting
+ * (split for MHD at orders 3-4 and Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
-enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2 };
+enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
     "ader_set_launch", "ader_set_layout", "ader_get_layout",
 ]
-ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2 = 0, 1, 2
+ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
 LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
 

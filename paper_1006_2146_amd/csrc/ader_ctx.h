@@ -49,6 +49,7 @@ struct StageFns {
   int (*predict)(ader_ctx*);
   int (*predict_split)(ader_ctx*);    // lane-split layout, nullptr if not built
   int (*predict_split2)(ader_ctx*);   // the same, registers capped for 2 waves/SIMD
+  int (*predict_zone2)(ader_ctx*);    // one lane per zone, facial check in its own pass
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
 };

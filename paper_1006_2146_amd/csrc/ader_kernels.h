@@ -82,18 +82,19 @@ __global__ void __launch_bounds__(256) k_bface(const double* __restrict__ B, dou
   });
 }
 
-template <class T, int ORDER, int FORM>
+// FUSED: where the facial positivity check runs (see predict_zone)
+template <class T, int ORDER, int FORM, bool FUSED>
 __global__ void __launch_bounds__(256) k_predict(const double* __restrict__ U,
                                                  const T* __restrict__ W, T* __restrict__ PK,
                                                  Batch b, const double* __restrict__ dt,
                                                  double gam) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
-    predict_zone<T, ORDER, FORM, kDeviation<T>>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
-                                                1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+    predict_zone<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
+                                                       1.0 / pr.dy, 1.0 / pr.dz, gam, n);
   });
 }
 
-template <class T, int ORDER, int FORM>
+template <class T, int ORDER, int FORM, bool FUSED>
 __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ U,
                                                      const T* __restrict__ W,
                                                      const double* __restrict__ B0,
@@ -102,8 +103,9 @@ __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ 
                                                      Batch b, const double* __restrict__ dt,
                                                      double gam) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
-    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>>(U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p],
-                                                    1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, B0, WB, BN, PK, grid_of(pr, b),
+                                                           dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
+                                                           1.0 / pr.dz, gam, n);
   });
 }
 

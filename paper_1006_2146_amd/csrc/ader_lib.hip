@@ -82,16 +82,27 @@ int queue_dt(ader_ctx* c, double cfl) {
 // The predictor layout in use: the one set, else lane-split where it keeps
 // the per-lane state small enough to avoid spills (MHD at orders 3 and 4,
 // Euler at order 4), one lane per zone otherwise.
+bool layout_built(const StageFns* s, int layout) {
+  switch (layout) {
+    case ADER_LAYOUT_ZONE: return true;
+    case ADER_LAYOUT_SPLIT: return s->predict_split != nullptr;
+    case ADER_LAYOUT_SPLIT2: return s->predict_split2 != nullptr;
+    case ADER_LAYOUT_ZONE2: return s->predict_zone2 != nullptr;
+  }
+  return false;
+}
+
 int layout_of(const ader_ctx* c, const StageFns* s) {
-  if (!s->predict_split) return ADER_LAYOUT_ZONE;
-  if (c->layout >= 0) return c->layout;
-  return (c->system == ADER_MHD || c->order == 4) ? ADER_LAYOUT_SPLIT : ADER_LAYOUT_ZONE;
+  if (c->layout >= 0 && layout_built(s, c->layout)) return c->layout;
+  if (s->predict_split && (c->system == ADER_MHD || c->order == 4)) return ADER_LAYOUT_SPLIT;
+  return ADER_LAYOUT_ZONE;
 }
 
 int queue_predict(ader_ctx* c, const StageFns* s) {
   switch (layout_of(c, s)) {
     case ADER_LAYOUT_SPLIT: return s->predict_split(c);
     case ADER_LAYOUT_SPLIT2: return s->predict_split2(c);
+    case ADER_LAYOUT_ZONE2: return s->predict_zone2(c);
     default: return s->predict(c);
   }
 }
@@ -351,6 +362,7 @@ int get_problem(ader_ctx* c, int q, double* U, double* B) {
 // of that stage alone) and keep the fastest.  The state is saved first and
 // restored at the end, so tuning does not advance the solution.
 // ---------------------------------------------------------------------------
+constexpr int kNumLayouts = 4;
 constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
                                        {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
 
@@ -410,9 +422,12 @@ int autotune(ader_ctx* c, int reps) {
     int best_layout = c->layout;
     float best_ms = 1e30f;
     // the predictor also tries both layouts where the lane-split one is built
-    const int nlayouts = (cls == kClassPredict && s->predict_split) ? 3 : 1;
+    const int nlayouts = cls == kClassPredict ? kNumLayouts : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
-      if (nlayouts > 1) c->layout = lay;
+      if (cls == kClassPredict) {
+        if (!layout_built(s, lay)) continue;
+        c->layout = lay;
+      }
       for (const LaunchShape& cand : kCandidates) {
         c->shape[cls] = cand;
         float ms = 0.f;
@@ -657,8 +672,10 @@ int ader_set_launch(ader_ctx* c, const int* block, const int* blocks_per_cu) {
 }
 
 int ader_set_layout(ader_ctx* c, int layout) {
-  if (!c || layout < -1 || layout > ADER_LAYOUT_SPLIT2) return ADER_EINVAL;
-  if (layout > ADER_LAYOUT_ZONE && c->order < 3) return ADER_EUNSUPPORTED;
+  if (!c || layout < -1 || layout >= kNumLayouts) return ADER_EINVAL;
+  if ((layout == ADER_LAYOUT_SPLIT || layout == ADER_LAYOUT_SPLIT2) && c->order < 3)
+    return ADER_EUNSUPPORTED;
+  if (layout == ADER_LAYOUT_ZONE2 && c->order > 3) return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;
 }

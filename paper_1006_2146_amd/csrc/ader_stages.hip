@@ -50,17 +50,20 @@ int recon(ader_ctx* c) {
   return ADER_OK;
 }
 
+// one lane per zone; FUSED: facial positivity check inside the side code
+template <bool FUSED>
 int predict(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassPredict);
   const int bs = c->shape[kClassPredict].block;
   const T* W = static_cast<const T*>(c->W);
   T* PK = static_cast<T*>(c->PK);
   if constexpr (kMhd)
-    k_predict_mhd<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(
+    k_predict_mhd<T, kOrder, kForm, FUSED><<<g, bs, 0, c->stream>>>(
         c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK, c->batch(),
         c->d_dt, c->gamma);
   else
-    k_predict<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt, c->gamma);
+    k_predict<T, kOrder, kForm, FUSED><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt,
+                                                                c->gamma);
   return launched();
 }
 
@@ -113,8 +116,15 @@ int update(ader_ctx* c) {
   return launched();
 }
 
-const StageFns kStages = {recon, predict, kOrder >= 3 ? predict_split<1> : nullptr,
-                          kOrder >= 3 ? predict_split<2> : nullptr, flux, update};
+// the one-lane-per-zone instance with a separate facial pass is built where
+// the zone layout is the likely winner (orders 2 and 3)
+const StageFns kStages = {recon,
+                          predict<true>,
+                          kOrder >= 3 ? predict_split<1> : nullptr,
+                          kOrder >= 3 ? predict_split<2> : nullptr,
+                          kOrder <= 3 ? predict<false> : nullptr,
+                          flux,
+                          update};
 
 }  // namespace
 

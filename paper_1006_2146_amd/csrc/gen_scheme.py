@@ -576,7 +576,7 @@ def gen_order(order, form):
     out.append("  // ph evaluates the physical flux at a point (point form) or")
     out.append("  // the flux minus that of the zone average (deviation form: w[0] unused).")
     out.append("  template <class Phys>")
-    out.append("  __host__ __device__ static inline void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
+    out.append("  __host__ __device__ static __forceinline__ void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
     out.append("                                        T sx, T sy, T sz, const Phys& ph) {")
     out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV], a0[NE][NV];")
@@ -623,7 +623,7 @@ def gen_order(order, form):
     sp = sorted(sp)
     out.append("  // %d spatial check points of the positivity safeguard" % len(sp))
     out.append("  template <class Acc>")
-    out.append("  __host__ __device__ static inline void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static __forceinline__ void spatial_points(const T (&w)[LS][NV], Acc& acc) {")
     out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in sp:
@@ -657,33 +657,35 @@ def gen_order(order, form):
     # facial check points after the predictor
     out.append("  // facial nodes entering the face averages, and barycentres, of all sides")
     out.append("  template <class Acc>")
-    out.append("  __host__ __device__ static inline void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static __forceinline__ void facial_points(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
     out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for d, s in SIDES:
         for j in sorted(fav):
             t1, t2, tau = fnodes[j - 1]
-            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", count=(tag, 'positivity'))
-            _count((tag, 'positivity'), CHECK_FLOPS[SYSTEM])
+            emit_eval(out, order, side_point(d, s, t1, t2, tau), "u")
             out.append("    acc(u);")
-        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "u", count=(tag, 'positivity'))
-        _count((tag, 'positivity'), CHECK_FLOPS[SYSTEM])
+        emit_eval(out, order, side_point(d, s, 0, 0, HALF), "u")
         out.append("    acc(u);")
     out.append("  }")
 
     # face packets
     out.append("  // side packet: barycentre state (eq. 54), face average of u (eq. 55),")
     out.append("  // face average of the physical normal flux (App. D composed); in the")
-    out.append("  // deviation form all three are taken minus their zone-average values")
-    out.append("  template <int SIDE, class Phys>")
-    out.append("  __host__ __device__ static inline void side(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
-    out.append("                                     T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
+    out.append("  // deviation form all three are taken minus their zone-average values.")
+    out.append("  // acc sees every state the side evaluates (the facial check set of the")
+    out.append("  // positivity safeguard: the barycentre and the face-average nodes).")
+    out.append("  template <int SIDE, class Phys, class Acc>")
+    out.append("  __host__ __device__ static __forceinline__ void side(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
+    out.append("                                     Acc& acc, T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
     out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV];")
     for si, (d, s) in enumerate(SIDES):
         out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s))
         emit_eval(out, order, side_point(d, s, 0, 0, HALF), "ub", indent="      ",
                   count=(tag, 'faces'))
+        out.append("      acc(ub);")
+        _count((tag, 'positivity'), CHECK_FLOPS[SYSTEM])
         row = face_average_u_row(order, d, s)
         _count((tag, 'faces'), _eval_flops(row))
         out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
@@ -692,6 +694,8 @@ def gen_order(order, form):
             t1, t2, tau = fnodes[j - 1]
             emit_eval(out, order, side_point(d, s, t1, t2, tau), "u", indent="      ",
                       count=(tag, 'faces'))
+            out.append("      acc(u);")
+            _count((tag, 'positivity'), CHECK_FLOPS[SYSTEM])
             _count((tag, 'faces'), FLUX_FLOPS[SYSTEM] + 2 * NV_OF[SYSTEM])
             out.append("      ph.template flux<%d>(u, fl);" % d)
             out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
@@ -731,7 +735,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
         out.append("    {%s}," % ", ".join("%.17g" % float(c) for c in point_row(order, p)))
     out.append("  };")
     out.append("  template <class Acc>")
-    out.append("  __host__ __device__ static inline void spatial_points_all(const T (&w)[LS][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static __forceinline__ void spatial_points_all(const T (&w)[LS][NV], Acc& acc) {")
     out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in sp:
@@ -740,22 +744,22 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
         out.append("    acc(u);")
     out.append("  }")
     out.append("  template <class Acc>")
-    out.append("  __host__ __device__ static inline void facial_points_all(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
+    out.append("  __host__ __device__ static __forceinline__ void facial_points_all(const T (&w)[LS][NV], const T (&e)[NE][NV], Acc& acc) {")
     out.append("    constexpr bool DEV = Acc::kDeviation;")
     out.append("    T u[NV];")
     for p in fpts:
-        emit_eval(out, order, p, "u", count=(tag, 'positivity-mhd'))
-        _count((tag, 'positivity-mhd'), CHECK_FLOPS[SYSTEM])
+        emit_eval(out, order, p, "u")
         out.append("    acc(u);")
     out.append("  }")
     fav = face_average_weights(order)
     ew = {(which, sg): edge_average_weights(order, which, sg) for which in (0, 1) for sg in (-1, 1)}
     out.append("  // ue[q], fe[q]: edge averages of u and of the normal flux of the field")
     out.append("  // component along transverse axis t_w, edge q = 2 w + (sign > 0);")
-    out.append("  // Phys::comp(c) is where variable c sits in this lane's arrays")
-    out.append("  template <int SIDE, class Phys>")
-    out.append("  __host__ __device__ static inline void side_edges(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
-    out.append("      T (&ub)[NV], T (&ua)[NV], T (&fa)[NV], T (&ue)[4], T (&fe)[4]) {")
+    out.append("  // Phys::comp(c) is where variable c sits in this lane's arrays.  acc sees")
+    out.append("  // the barycentre and every facial node (the MHD facial check set).")
+    out.append("  template <int SIDE, class Phys, class Acc>")
+    out.append("  __host__ __device__ static __forceinline__ void side_edges(const T (&w)[LS][NV], const T (&e)[NE][NV], const Phys& ph,")
+    out.append("      Acc& acc, T (&ub)[NV], T (&ua)[NV], T (&fa)[NV], T (&ue)[4], T (&fe)[4]) {")
     out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV];")
     for si, (d, s_) in enumerate(SIDES):
@@ -763,6 +767,8 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
         out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s_))
         emit_eval(out, order, side_point(d, s_, 0, 0, HALF), "ub", indent="      ",
                   count=(tag, 'faces-mhd'))
+        out.append("      acc(ub);")
+        _count((tag, 'positivity-mhd'), CHECK_FLOPS[SYSTEM])
         row = face_average_u_row(order, d, s_)
         _count((tag, 'faces-mhd'), _eval_flops(row))
         out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
@@ -784,10 +790,12 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
         for j in range(1, nf + 1):
             used_face = j in fav
             used_edge = [(which, sg) for which in (0, 1) for sg in (-1, 1) if j in ew[(which, sg)]]
-            if not used_face and not used_edge:
-                continue
             emit_eval(out, order, side_point(d, s_, *fnodes[j - 1]), "u", indent="      ",
                       count=(tag, 'faces-mhd'))
+            out.append("      acc(u);")
+            _count((tag, 'positivity-mhd'), CHECK_FLOPS[SYSTEM])
+            if not used_face and not used_edge:
+                continue
             out.append("      ph.template flux<%d>(u, fl);" % d)
             _count((tag, 'faces-mhd'), FLUX_FLOPS[SYSTEM])
             if used_face:
@@ -812,7 +820,7 @@ def gen_weno():
         out.append("  // cand<s>(d, m): moments m[1..%d] of stencil s (zones s-%d .. s) from" % (M - 1, M - 1))
         out.append("  // the averages d[0..%d] at offsets -%d..%d" % (2 * M - 2, M - 1, M - 1))
         for s, mat in enumerate(mats):
-            out.append("  __host__ __device__ static inline void cand%d(const T* d, T* m) {" % s)
+            out.append("  __host__ __device__ static __forceinline__ void cand%d(const T* d, T* m) {" % s)
             for a in range(1, M):
                 terms = []
                 for q in range(M):

@@ -82,6 +82,9 @@ struct SplitScan {
   }
 };
 
+// (NoScan: in this layout the facial check set is scanned on its own before
+// the sides are formed, which keeps the register use of the side code low.)
+
 // Exact positivity pass (rare): this lane's component at each check point in
 // double, the zone's state gathered, the same theta in every lane of a zone.
 template <int NP, int LS, class T, int NV>
@@ -168,7 +171,8 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
   auto side = [&](auto side_c) {
     constexpr int SIDE = decltype(side_c)::value;
     T ub[1], ua[1], fa[1];
-    S::template side<SIDE>(w, e, ph, ub, ua, fa);
+    NoScan none;
+    S::template side<SIDE>(w, e, ph, none, ub, ua, fa);
     base[(long long)((SIDE * 3 + 0) * 5) * g.S] = ub[0];
     base[(long long)((SIDE * 3 + 1) * 5) * g.S] = ua[0];
     base[(long long)((SIDE * 3 + 2) * 5) * g.S] = fa[0];
@@ -243,7 +247,8 @@ __device__ __forceinline__ void predict_zone_mhd_split(
     constexpr int AX = SIDE / 2;
     constexpr int TA0 = AX == 0 ? 1 : 0, TA1 = AX == 2 ? 1 : 2;   // transverse axes
     T ub[1], ua[1], fa[1], ue[4], fe[4];
-    S::template side_edges<SIDE>(w, e, ph, ub, ua, fa, ue, fe);
+    NoScan none;
+    S::template side_edges<SIDE>(w, e, ph, none, ub, ua, fa, ue, fe);
     T* base = PK + (long long)SIDE * 32 * g.S + n;
     base[(long long)L.var * g.S] = ub[0];
     base[(long long)(8 + L.var) * g.S] = ua[0];

@@ -400,12 +400,12 @@ template <class T, int NV> struct SchemeOf<2, 1, T, NV> { using type = ader_gen:
 template <class T, int NV> struct SchemeOf<3, 0, T, NV> { using type = ader_gen::SchemeM3<T, NV>; };
 template <class T, int NV> struct SchemeOf<4, 0, T, NV> { using type = ader_gen::SchemeM4<T, NV>; };
 
-template <class S, class T, int SIDE, class Phys>
+template <class S, class T, int SIDE, class Phys, class Acc>
 __host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], const T (&e)[S::NE][5],
-                                                    const Phys& ph, T* __restrict__ PK, long long N,
-                                                    long long n) {
+                                                    const Phys& ph, Acc& acc, T* __restrict__ PK,
+                                                    long long N, long long n) {
   T ub[5], ua[5], fa[5];
-  S::template side<SIDE>(w, e, ph, ub, ua, fa);
+  S::template side<SIDE>(w, e, ph, acc, ub, ua, fa);
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     PK[((long long)(SIDE * 3 + 0) * 5 + v) * N + n] = ub[v];
@@ -414,10 +414,18 @@ __host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], cons
   }
 }
 
+// A scan that ignores the states handed to it.
+struct NoScan {
+  template <class U>
+  __host__ __device__ void operator()(const U&) const {}
+};
+
 // Per zone: load the reconstruction, positivity scaling, space-time predictor
 // (Sec. IV / App. A), positivity scaling, and the six face-side packets (in
-// the deviation form without the zone-average part).
-template <class T, int ORDER, int FORM, bool DEV>
+// the deviation form without the zone-average part).  FUSED: the facial
+// check set is scanned while the sides are formed (their states are that
+// set), else in a pass of its own before them; the results are the same.
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true>
 __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__ U,
                                                       const T* __restrict__ W,
                                                       T* __restrict__ PK, const Grid& g,
@@ -451,7 +459,7 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   const auto ph = FluxOf<Euler<T>, T, DEV>::make(w0, gam);
   T e[NE][5];
   S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
-  {
+  if constexpr (!FUSED) {
     PosScan<T, 5, DEV> scan(w0);
     S::facial_points(w, e, scan);
     const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi, gam) : 1.0;
@@ -466,13 +474,42 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
 #pragma unroll
         for (int v = 0; v < 5; ++v) e[m][v] *= th;
     }
+    NoScan none;
+    store_side<S, T, 0>(w, e, ph, none, PK, g.S, n);
+    store_side<S, T, 1>(w, e, ph, none, PK, g.S, n);
+    store_side<S, T, 2>(w, e, ph, none, PK, g.S, n);
+    store_side<S, T, 3>(w, e, ph, none, PK, g.S, n);
+    store_side<S, T, 4>(w, e, ph, none, PK, g.S, n);
+    store_side<S, T, 5>(w, e, ph, none, PK, g.S, n);
+    return;
   }
-  store_side<S, T, 0>(w, e, ph, PK, g.S, n);
-  store_side<S, T, 1>(w, e, ph, PK, g.S, n);
-  store_side<S, T, 2>(w, e, ph, PK, g.S, n);
-  store_side<S, T, 3>(w, e, ph, PK, g.S, n);
-  store_side<S, T, 4>(w, e, ph, PK, g.S, n);
-  store_side<S, T, 5>(w, e, ph, PK, g.S, n);
+  // The six face-side packets.  The states they evaluate are the facial
+  // check set of the positivity safeguard and are scanned on the way; in the
+  // rare zone the scan flags, theta comes from the exact pass and the sides
+  // are formed again from the scaled polynomial (the same result as scaling
+  // before forming them).
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    PosScan<T, 5, DEV> scan(w0);
+    store_side<S, T, 0>(w, e, ph, scan, PK, g.S, n);
+    store_side<S, T, 1>(w, e, ph, scan, PK, g.S, n);
+    store_side<S, T, 2>(w, e, ph, scan, PK, g.S, n);
+    store_side<S, T, 3>(w, e, ph, scan, PK, g.S, n);
+    store_side<S, T, 4>(w, e, ph, scan, PK, g.S, n);
+    store_side<S, T, 5>(w, e, ph, scan, PK, g.S, n);
+    if (pass == 1 || !scan.near) break;
+    const double theta = theta_facial_tab(w0, w, e, S::facial_phi, gam);
+    if (!(theta < 1.0)) break;
+    const T th = T(theta);
+#pragma unroll
+    for (int m = 1; m < LS; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) w[m][v] *= th;
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) e[m][v] *= th;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -738,12 +775,12 @@ __host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B
   }
 }
 
-template <class S, class T, int SIDE, class Phys>
+template <class S, class T, int SIDE, class Phys, class Acc>
 __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], const T (&e)[S::NE][8],
-                                                        const Phys& ph, T* __restrict__ PK,
+                                                        const Phys& ph, Acc& acc, T* __restrict__ PK,
                                                         long long N, long long n) {
   T ub[8], ua[8], fa[8], ue[4], fe[4];
-  S::template side_edges<SIDE>(w, e, ph, ub, ua, fa, ue, fe);
+  S::template side_edges<SIDE>(w, e, ph, acc, ub, ua, fa, ue, fe);
   T* base = PK + (long long)SIDE * 32 * N + n;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
@@ -763,7 +800,7 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
 // predictor, positivity scaling and the six side packets of 32 values
 // (barycentre state, face averages of u and F, edge averages of u and F of
 // the field component along each edge's transverse axis).
-template <class T, int ORDER, int FORM, bool DEV>
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true>
 __host__ __device__ __forceinline__ void predict_zone_mhd(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
@@ -807,7 +844,7 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   const auto ph = FluxOf<Mhd<T>, T, DEV>::make(w0, gam);
   T e[NE][8];
   S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
-  {
+  if constexpr (!FUSED) {
     PosScan<T, 8, DEV> scan(w0);
     S::facial_points_all(w, e, scan);
     const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi_all, gam) : 1.0;
@@ -822,13 +859,38 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
 #pragma unroll
         for (int v = 0; v < 8; ++v) e[m][v] *= th;
     }
+    NoScan none;
+    store_side_mhd<S, T, 0>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 1>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 2>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 3>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 4>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 5>(w, e, ph, none, PK, g.S, n);
+    return;
   }
-  store_side_mhd<S, T, 0>(w, e, ph, PK, g.S, n);
-  store_side_mhd<S, T, 1>(w, e, ph, PK, g.S, n);
-  store_side_mhd<S, T, 2>(w, e, ph, PK, g.S, n);
-  store_side_mhd<S, T, 3>(w, e, ph, PK, g.S, n);
-  store_side_mhd<S, T, 4>(w, e, ph, PK, g.S, n);
-  store_side_mhd<S, T, 5>(w, e, ph, PK, g.S, n);
+  // side packets with the facial scan on the way, as in predict_zone
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    PosScan<T, 8, DEV> scan(w0);
+    store_side_mhd<S, T, 0>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 1>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 2>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 3>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 4>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 5>(w, e, ph, scan, PK, g.S, n);
+    if (pass == 1 || !scan.near) break;
+    const double theta = theta_facial_tab(w0, w, e, S::facial_phi_all, gam);
+    if (!(theta < 1.0)) break;
+    const T th = T(theta);
+#pragma unroll
+    for (int m = 1; m < LS; ++m)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) w[m][v] *= th;
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) e[m][v] *= th;
+  }
 }
 
 // HLL at the lower AXIS-face of zone n (MHD): the five hydro fluxes, and the

@@ -2,7 +2,9 @@
 of uneven sizes advance with one persistent launch per stage, each with its
 own CFL dt.  Every zone's arithmetic is the same as in a lone run, so a
 problem of a batch must match its solo run bit for bit, whatever the launch
-shapes, in graph mode as eagerly, and after autotuning."""
+shapes and in graph mode as eagerly.  The autotuner may also switch the
+predictor layout, which changes rounding order only: its result must match,
+bit for bit, a run forced to the layout it chose."""
 
 import numpy as np
 import pytest
@@ -30,8 +32,10 @@ def _states(shapes, mhd=False):
     return out
 
 
-def _solo(shape, U, B, steps, cfl=0.3, **kw):
+def _solo(shape, U, B, steps, cfl=0.3, layout=None, **kw):
     with ader.Solver(shape, **kw) as s:
+        if layout is not None:
+            ader.ader_set_layout(s.ctx, layout)
         s.set_state(U, B)
         dts = []
         for _ in range(steps):
@@ -42,12 +46,14 @@ def _solo(shape, U, B, steps, cfl=0.3, **kw):
 
 
 def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=False,
-               launch=None, **kw):
+               launch=None, layout=None, **kw):
     with ader.BatchSolver(shapes, stream=stream, **kw) as b:
         for i, (U, B) in enumerate(states):
             b.set_state(i, U, B)
         if launch:
             ader.ader_set_launch(b.ctx, launch)
+        if layout is not None:
+            ader.ader_set_layout(b.ctx, layout)
         if tune:
             ader.ader_autotune(b.ctx, 2)
         if graph:
@@ -57,6 +63,7 @@ def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=Fa
             dts.append(b.step_cfl(cfl, want_dts=True))
         res = [b.get_state(i) for i in range(len(shapes))]
         shapes_used = ader.ader_get_launch(b.ctx)
+        shapes_used["layout"] = ader.ader_get_layout(b.ctx)
     res = [r if isinstance(r, tuple) else (r, None) for r in res]
     return res, np.array(dts), shapes_used
 
@@ -103,7 +110,7 @@ def test_launch_shapes_graph_and_autotune_do_not_change_results():
                     "update": (64, 64)}):
         say("launch", launch)
         got, dts, used = _batch_run(SHAPES, states, 3, launch=launch, **kw)
-        assert used == launch
+        assert {k: v for k, v in used.items() if k != "layout"} == launch
         assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
     say("graph")
     got, dts, _ = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream, **kw)
@@ -111,8 +118,12 @@ def test_launch_shapes_graph_and_autotune_do_not_change_results():
     say("autotune + graph")
     got, dts, used = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream,
                                 tune=True, **kw)
-    assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
     say("tuned shapes", used)
+    ref2, rdts2, _ = _batch_run(SHAPES, states, 3, layout=used["layout"], **kw)
+    assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref2)) and np.array_equal(dts, rdts2)
+    # and within FP32 rounding of the default layout
+    for a, b in zip(got, ref):
+        assert np.abs(a[0] - b[0]).max() <= 1e-6 * np.abs(b[0]).max()
 
 
 def test_graph_replays_match_eager_with_host_work_between():
@@ -177,6 +188,7 @@ def test_config4_ensemble_full_size():
         for i, (_, U) in enumerate(ens):
             b.set_state(i, U)
         ader.ader_autotune(b.ctx, 2)
+        layout = ader.ader_get_layout(b.ctx)
         ader.ader_set_graph(b.ctx, True)
         for _ in range(3):
             b.step_cfl(0.3)
@@ -186,7 +198,8 @@ def test_config4_ensemble_full_size():
         dts = b.dts()
     for i in pick:
         say("config4 solo", i, shapes[i])
-        (Us, _), sdts = _solo(shapes[i], ens[i][1], None, 3, order=3, precision=ader.ADER_MIXED)
+        (Us, _), sdts = _solo(shapes[i], ens[i][1], None, 3, layout=layout, order=3,
+                              precision=ader.ADER_MIXED)
         assert np.array_equal(got[i], Us), i
         assert dts[i] == sdts[-1]
     say("config4 fp64 batch vs oracle")
