@@ -35,13 +35,76 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+class Tuning:
+    """Launch shapes and predictor layout per run, autotuned on the GPU, or
+    read back from a file an earlier run wrote (so that a profiled run uses
+    the tuned configuration without the tuner's own trial launches)."""
+
+    def __init__(self, path):
+        self.path = path
+        self.saved = {}
+        self.reuse = bool(path) and os.path.exists(path)
+        if self.reuse:
+            with open(path) as fh:
+                self.saved = json.load(fh)
+
+    def apply(self, ader, ctx, key):
+        if self.reuse:
+            cfg = self.saved[key]
+            ader.ader_set_launch(ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
+            ader.ader_set_layout(ctx, cfg["layout"])
+        else:
+            ader.ader_autotune(ctx, 2)
+            self.saved[key] = {"launch": ader.ader_get_launch(ctx),
+                               "layout": ader.ader_get_layout(ctx)}
+
+    def write(self):
+        if self.path and not self.reuse:
+            with open(self.path, "w") as fh:
+                json.dump(self.saved, fh, indent=1)
+
+
+TUNE = Tuning(None)
+
+
+def kernel_source_hash():
+    """sha256 over the kernel sources (file name and bytes, in name order)."""
+    import glob
+    import hashlib
+    csrc = os.path.join(HERE, "paper_1006_2146_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip")) +
+                   [os.path.join(csrc, "generated", "ader_scheme.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` at 128^3 from the committed counter
+    summary, if it was taken on these kernel sources; else None."""
+    path = os.path.join(HERE, "profiles", "traffic_sedov128_o3.md")
+    if not os.path.exists(path):
+        return None
+    value, digest = None, None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic_bytes_per_launch %s 128^3:" % kernel):
+                value = float(line.rsplit(":", 1)[1])
+            if line.startswith("kernel sources: sha256 "):
+                digest = line.split()[-1]
+    return value if value is not None and digest == kernel_source_hash() else None
+
+
 def flop_counts():
     path = os.path.join(HERE, "paper_1006_2146_amd", "csrc", "generated", "flop_counts.json")
     with open(path) as fh:
         return json.load(fh)["counts"]
 
 
-def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None):
+def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None, key=""):
     """Autotune the launch shapes, time `steps` graph-replayed CFL steps
     (wall clock between synchronisations), then take a separate eager pass
     with per-stage HIP events for the stage breakdown."""
@@ -58,7 +121,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
             dB = torch.from_numpy(B0).to("cuda") if mhd else None
         stream.synchronize()
         ader.ader_bind_device_state(s.ctx, dU.data_ptr(), dB.data_ptr() if mhd else None)
-        ader.ader_autotune(s.ctx, 2)
+        TUNE.apply(ader, s.ctx, key)
         ader.ader_set_graph(s.ctx, True)
         for _ in range(warmup):
             s.step_cfl(CFL)
@@ -105,7 +168,7 @@ def run_ensemble(ader, torch, steps, warmup):
         with ader.BatchSolver(shapes, order=3, precision=prec, stream=stream.cuda_stream) as b:
             for i, (_, U) in enumerate(ens):
                 b.set_state(i, U)
-            ader.ader_autotune(b.ctx, 2)
+            TUNE.apply(ader, b.ctx, "ensemble-" + name)
             ader.ader_set_graph(b.ctx, True)
             for _ in range(warmup):
                 b.step_cfl(CFL)
@@ -199,6 +262,14 @@ def main():
                     help="order-4 MHD runs on the 128^3 random-field workload ('' for none)")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-problem batched ensemble")
+    ap.add_argument("--tune-file", default=None,
+                    help="reuse the launch shapes and layouts in this file if it exists, "
+                         "else autotune and write them there")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the untimed mixed-vs-FP64 accuracy pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device-to-device copy (a reference kernel "
+                         "of known traffic for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -207,6 +278,9 @@ def main():
 
     import torch
     from paper_1006_2146_amd import ader, workloads
+
+    global TUNE
+    TUNE = Tuning(args.tune_file)
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -222,7 +296,7 @@ def main():
     for name in args.variants.split(","):
         prec, rs = table[name]
         log("variant", name, "warmup", args.warmup, "steps", args.steps)
-        variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup)
+        variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup, key=name)
         log("variant", name, "%.3e zone-updates/s" % variants[name]["zone_updates_per_s"])
 
     mhd_variants = {}
@@ -233,19 +307,29 @@ def main():
             prec = ader.ADER_FP64 if name == "fp64" else ader.ADER_MIXED
             log("mhd variant", name)
             mhd_variants["mhd-o4-" + name] = run_variant(ader, torch, Um, prec, ader.ADER_HLL,
-                                                         args.steps, args.warmup, order=4, B0=Bm)
+                                                         args.steps, args.warmup, order=4, B0=Bm,
+                                                         key="mhd-o4-" + name)
             log("mhd variant", name, "%.3e zone-updates/s"
                 % mhd_variants["mhd-o4-" + name]["zone_updates_per_s"])
 
-    for name in variants:
+    for name in ([] if args.no_accuracy else variants):
         if name.startswith("mixed"):
             log("accuracy", name)
             rs = ader.ADER_HLL if name.endswith("hll") else ader.ADER_LINEARIZED
             variants[name]["accuracy"] = accuracy(ader, U0, 3, rs, 10, trunc_order=4)
-    for name in mhd_variants:
+    for name in ([] if args.no_accuracy else mhd_variants):
         if name.endswith("mixed"):
             log("accuracy", name)
             mhd_variants[name]["accuracy"] = accuracy(ader, Um, 4, ader.ADER_HLL, 3, B0=Bm)
+
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of %d bytes" % nbytes)
 
     ensemble = None
     if not args.no_ensemble:
@@ -258,9 +342,16 @@ def main():
     flops_zone = flop_counts()["M3" if dtype == "f64" else "M3-dev"]["total"]
     pred_ms = pv["stage_ms_per_step"]["predict"]
     achieved = flops_zone * N / (pred_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_predict", "achieved": achieved,
+    layout = pv.get("predict_layout")
+    kernel = {("f32", "zone"): "k_predict<float,3,0,true>",
+              ("f32", "zone-prescan"): "k_predict<float,3,0,false>",
+              ("f64", "zone"): "k_predict<double,3,0,true>",
+              ("f64", "zone-prescan"): "k_predict<double,3,0,false>"}.get((dtype, layout),
+                                                                          "k_predict (%s)" % layout)
+    roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved,
                 "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+                "frac": achieved / PEAK_TFLOPS[dtype], "traffic": recorded_traffic(kernel),
+                "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                 "flops_per_zone": flops_zone, "launch_ms": pred_ms}
 
     out = {
@@ -294,6 +385,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(U0)
+    TUNE.write()
     print(json.dumps(out), flush=True)
 
 
