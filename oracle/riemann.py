@@ -14,13 +14,22 @@ Readings where the paper is silent:
 * Linearized solver (Euler): F = (<F>_L + <F>_R)/2 - R |Lambda| L (<u>_R -
   <u>_L)/2 with the eigen-system of the Euler flux Jacobian at the arithmetic
   mean of the two barycentre primitive states; no entropy fix.
+* Linearized solver (ideal MHD): the same formula with |A| = R |Lambda| R^-1
+  of the seven-wave system -- the conserved variables (rho, m, E, B_t1, B_t2)
+  with the normal field B_n held at its frozen value -- at the mean of the two
+  barycentre primitive states (rho, v, P, B).  The normal field is the
+  face's own (continuous) field, so its jump, which the time evolution of the
+  two sides' polynomials leaves at truncation level, is not dissipated; the
+  normal-field flux is zero as in eq. (7).  Here |A| is formed from its
+  definition: the flux Jacobian by complex-step differentiation of the flux
+  (exact to rounding) and a library eigen-decomposition.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 """
 
 import numpy as np
 
-from .physics import primitives, fast_speed
+from .physics import primitives, conserved, flux, fast_speed
 
 
 def hll_speeds(ubl, ubr, axis, gamma):
@@ -93,3 +102,65 @@ def linearized_euler(pl, pr, axis, gamma):
     du = pr['u'] - pl['u']
     return 0.5 * (pl['f'] + pr['f']) - 0.5 * euler_eigen_dissipation(
         pl['ub'], pr['ub'], du, axis, gamma)
+
+
+# ------------------------------------------------------- linearized MHD ----
+
+def _transverse(axis):
+    return {0: (1, 2), 1: (0, 2), 2: (0, 1)}[axis]
+
+
+def seven_wave_slots(axis):
+    """Rows of the 8-vector (rho, m, E, B) that form the seven-wave system
+    along ``axis``: (rho, m_x, m_y, m_z, E, B_t1, B_t2)."""
+    t1, t2 = _transverse(axis)
+    return [0, 1, 2, 3, 4, 5 + t1, 5 + t2]
+
+
+def frozen_state(ubl, ubr, gamma):
+    """Conserved 8-vector at the mean of the two barycentre primitive states."""
+    rl, vl, Pl, Bl = primitives(ubl, gamma)
+    rr, vr, Pr, Br = primitives(ubr, gamma)
+    return conserved(0.5 * (rl + rr), 0.5 * (vl + vr), 0.5 * (Pl + Pr), 0.5 * (Bl + Br), gamma)
+
+
+def mhd_jacobian(u8, axis, gamma, h=1e-30):
+    """7x7 Jacobian d F7 / d q7 (seven-wave slots, B_n fixed) of the flux
+    along ``axis`` at the states u8 (8, M): complex-step derivatives, exact
+    to rounding.  Returns (M, 7, 7)."""
+    slots = seven_wave_slots(axis)
+    M = u8.shape[1]
+    J = np.zeros((M, 7, 7))
+    for k, s in enumerate(slots):
+        uc = u8.astype(complex)
+        uc[s] = uc[s] + 1j * h
+        F = flux(uc, axis, gamma)
+        J[:, :, k] = (F[slots].imag / h).T
+    return J
+
+
+def mhd_abs_jacobian(ubl, ubr, axis, gamma):
+    """|A| = R |Lambda| R^-1 of the seven-wave Jacobian at the frozen state of
+    each face; ubl, ubr (8, ...) -> (M, 7, 7) over the flattened faces."""
+    u8 = frozen_state(ubl, ubr, gamma).reshape(8, -1)
+    A = mhd_jacobian(u8, axis, gamma)
+    lam, R = np.linalg.eig(A)
+    absA = (R * np.abs(lam.real)[:, None, :]) @ np.linalg.inv(R)
+    return absA.real
+
+
+def mhd_dissipation(absA, du8, axis):
+    """|A| du on the seven-wave slots of du8 (8, ...); the normal-field row of
+    the result is zero."""
+    slots = seven_wave_slots(axis)
+    shape = du8.shape[1:]
+    d7 = du8[slots].reshape(7, -1).T[:, :, None]
+    D7 = (absA @ d7)[:, :, 0].T
+    out = np.zeros_like(du8)
+    out[slots] = D7.reshape((7,) + shape)
+    return out
+
+
+def linearized_mhd_combine(fl, fr, ul, ur, absA, axis):
+    """(F_L + F_R)/2 - |A| (u_R - u_L)/2 for 8-vectors."""
+    return 0.5 * (fl + fr) - 0.5 * mhd_dissipation(absA, ur - ul, axis)

@@ -20,7 +20,8 @@ from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
 from .positivity import limit_spatial, limit_spacetime
 from .predictor import predict_modal, predict_nodal_2
-from .riemann import hll, hll_combine, hll_speeds, linearized_euler
+from .riemann import (hll, hll_combine, hll_speeds, linearized_euler, linearized_mhd_combine,
+                      mhd_abs_jacobian)
 from .weno import reconstruct
 
 
@@ -110,16 +111,16 @@ def step_mhd(U, B, dt, cfg):
     """Ideal MHD step: eq. (6) for the five hydro variables and the
     constrained-transport update of eq. (8) for the face fields.
 
-    Edge electric fields (Sec. II.3, Sec. V): every face's HLL problem, with
-    its own barycentre speeds, is applied to the edge averages of eq. (57) on
-    each of its four edges; eq. (7) maps the induction flux of the component
-    along the edge's transverse axis to the edge field, E_c = -eps_{dac}
-    Flux_d(B_a), and each edge field is the mean of its four face values (the
-    reading of "averages of appropriate components").
+    Edge electric fields (Sec. II.3, Sec. V): every face's Riemann problem,
+    with its own barycentre speeds (HLL) or frozen eigen-system (linearized),
+    is applied to the edge averages of eq. (57) on each of its four edges;
+    eq. (7) maps the induction flux of the component along the edge's
+    transverse axis to the edge field, E_c = -eps_{dac} Flux_d(B_a), and each
+    edge field is the mean of its four face values (the reading of "averages
+    of appropriate components").
     """
-    if cfg.riemann != 'hll':
-        raise NotImplementedError('MHD is built with the HLL flux')
     dx = cfg.spacing(U.shape[1:])
+    lin = cfg.riemann == 'linearized'
     uhat = predictor(U, dt, cfg, B)
     flows = []
     E = [np.zeros_like(U[0]) for _ in range(3)]
@@ -127,8 +128,17 @@ def step_mhd(U, B, dt, cfg):
         plus = face_side_packet(uhat, cfg.order, d, +1, cfg.gamma, edges=True)
         minus = face_side_packet(uhat, cfg.order, d, -1, cfg.gamma, edges=True)
         left = _roll_packet(plus, d)
-        lam_l, lam_r = hll_speeds(left['ub'], minus['ub'], d, cfg.gamma)
-        flows.append(hll_combine(left['f'], minus['f'], left['u'], minus['u'], lam_l, lam_r)[:5])
+        if lin:
+            absA = mhd_abs_jacobian(left['ub'], minus['ub'], d, cfg.gamma)
+
+            def combine(fl, fr, ul, ur):
+                return linearized_mhd_combine(fl, fr, ul, ur, absA, d)
+        else:
+            lam_l, lam_r = hll_speeds(left['ub'], minus['ub'], d, cfg.gamma)
+
+            def combine(fl, fr, ul, ur):
+                return hll_combine(fl, fr, ul, ur, lam_l, lam_r)
+        flows.append(combine(left['f'], minus['f'], left['u'], minus['u'])[:5])
         tr = transverse_axes(d)
         for which in (0, 1):
             a = tr[which]
@@ -136,10 +146,13 @@ def step_mhd(U, B, dt, cfg):
             sgn = -_levi(d, a, c)
             fe = {}
             for sign in (-1, 1):
-                fe[sign] = hll_combine(left['f_edge'][(which, sign)][5 + a],
-                                       minus['f_edge'][(which, sign)][5 + a],
-                                       left['u_edge'][(which, sign)][5 + a],
-                                       minus['u_edge'][(which, sign)][5 + a], lam_l, lam_r)
+                # the whole edge-averaged state enters (the linearized
+                # dissipation couples the components); its field row 5 + a
+                # is the induction flux
+                fe[sign] = combine(left['f_edge'][(which, sign)],
+                                   minus['f_edge'][(which, sign)],
+                                   left['u_edge'][(which, sign)],
+                                   minus['u_edge'][(which, sign)])[5 + a]
             # edge at x_a = lower edge of this zone's face: own face (side -)
             # and the face of the zone below along a (side +)
             E[c] = E[c] + sgn * (fe[-1] + _nb(fe[1], a, -1))
