@@ -54,7 +54,7 @@ class Tuning:
             ader.ader_set_launch(ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
             ader.ader_set_layout(ctx, cfg["layout"])
         else:
-            ader.ader_autotune(ctx, 2)
+            ader.ader_autotune(ctx, 4)
             self.saved[key] = {"launch": ader.ader_get_launch(ctx),
                                "layout": ader.ader_get_layout(ctx)}
 
@@ -258,8 +258,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="fp64-hll,fp64-lin,mixed-hll,mixed-lin")
-    ap.add_argument("--mhd-variants", default="fp64,mixed",
-                    help="order-4 MHD runs on the 128^3 random-field workload ('' for none)")
+    ap.add_argument("--mhd-variants", default="fp64,mixed,mixed-lin",
+                    help="order-4 MHD runs on the 128^3 random-field workload: fp64, mixed "
+                         "(HLL), fp64-lin, mixed-lin (linearized); '' for none")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-problem batched ensemble")
     ap.add_argument("--tune-file", default=None,
@@ -304,9 +305,10 @@ def main():
         log("building the MHD workload", SHAPE)
         Um, Bm = workloads.mhd_random_field(SHAPE)
         for name in args.mhd_variants.split(","):
-            prec = ader.ADER_FP64 if name == "fp64" else ader.ADER_MIXED
+            prec = ader.ADER_FP64 if name.startswith("fp64") else ader.ADER_MIXED
+            rs = ader.ADER_LINEARIZED if name.endswith("-lin") else ader.ADER_HLL
             log("mhd variant", name)
-            mhd_variants["mhd-o4-" + name] = run_variant(ader, torch, Um, prec, ader.ADER_HLL,
+            mhd_variants["mhd-o4-" + name] = run_variant(ader, torch, Um, prec, rs,
                                                          args.steps, args.warmup, order=4, B0=Bm,
                                                          key="mhd-o4-" + name)
             log("mhd variant", name, "%.3e zone-updates/s"
@@ -318,9 +320,10 @@ def main():
             rs = ader.ADER_HLL if name.endswith("hll") else ader.ADER_LINEARIZED
             variants[name]["accuracy"] = accuracy(ader, U0, 3, rs, 10, trunc_order=4)
     for name in ([] if args.no_accuracy else mhd_variants):
-        if name.endswith("mixed"):
+        if "mixed" in name:
             log("accuracy", name)
-            mhd_variants[name]["accuracy"] = accuracy(ader, Um, 4, ader.ADER_HLL, 3, B0=Bm)
+            rs = ader.ADER_LINEARIZED if name.endswith("-lin") else ader.ADER_HLL
+            mhd_variants[name]["accuracy"] = accuracy(ader, Um, 4, rs, 3, B0=Bm)
 
     if args.copy_calibration:
         nbytes = 256 << 20
@@ -375,7 +378,8 @@ def main():
                    "launch": "autotuned"},
         "roofline": roofline,
         "variants": variants,
-        "mhd_variants": {"workload": "mhd-random-field-128^3, order 4 modal, HLL, CT, gamma 5/3",
+        "mhd_variants": {"workload": "mhd-random-field-128^3, order 4 modal, CT, gamma 5/3; "
+                                     "HLL, or linearized (-lin)",
                          **mhd_variants},
         "ensemble": ensemble,
     }

@@ -80,7 +80,11 @@ int ader_set_gamma(ader_ctx* ctx, double gamma);
  * reconstruction is minmod-limited linear; at 3 and 4 it is centred WENO. */
 int ader_set_order(ader_ctx* ctx, int order, int form);
 
-/* ADER_HLL or ADER_LINEARIZED (Euler only: ADER_EUNSUPPORTED for MHD). */
+/* ADER_HLL (eq. 17/56, Davis speeds from the barycentre states) or
+ * ADER_LINEARIZED (Sec. II.3: (F_L + F_R)/2 - R|Lambda|L (u_R - u_L)/2 with
+ * the eigen-system frozen at the mean of the two barycentre primitive
+ * states; for MHD the seven-wave system with the normal field held, applied
+ * to the face and to each edge state of eq. (57)). */
 int ader_set_riemann(ader_ctx* ctx, int riemann);
 
 /* ADER_FP64 or ADER_MIXED. */

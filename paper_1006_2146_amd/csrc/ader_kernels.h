@@ -94,7 +94,8 @@ __global__ void __launch_bounds__(256) k_predict(const double* __restrict__ U,
   });
 }
 
-template <class T, int ORDER, int FORM, bool FUSED>
+// EDGES_ALL: the side packets carry every variable's edge averages
+template <class T, int ORDER, int FORM, bool FUSED, bool EDGES_ALL>
 __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ U,
                                                      const T* __restrict__ W,
                                                      const double* __restrict__ B0,
@@ -103,7 +104,7 @@ __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ 
                                                      Batch b, const double* __restrict__ dt,
                                                      double gam) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
-    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, B0, WB, BN, PK, grid_of(pr, b),
+    predict_zone_mhd<T, ORDER, FORM, kDeviation<T>, FUSED, EDGES_ALL>(U, W, B0, WB, BN, PK, grid_of(pr, b),
                                                            dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
                                                            1.0 / pr.dz, gam, n);
   });
@@ -168,7 +169,7 @@ __global__ void __launch_bounds__(256) k_face_flux(const double* __restrict__ U,
   });
 }
 
-template <class T>
+template <class T, int RS>
 __global__ void __launch_bounds__(256) k_face_flux_mhd(const double* __restrict__ U,
                                                        const double* __restrict__ B0,
                                                        const T* __restrict__ PK,
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(256) k_face_flux_mhd(const double* __restrict_
                                                        double* __restrict__ FE, Batch b,
                                                        double gam) {
   for_zones(b, [&](const Problem& pr, int, long long n) {
-    face_flux_zone_mhd<T, kDeviation<T>>(U, B0, PK, F, FE, grid_of(pr, b), gam, n);
+    face_flux_zone_mhd<T, RS, kDeviation<T>>(U, B0, PK, F, FE, grid_of(pr, b), gam, n);
   });
 }
 

@@ -82,7 +82,9 @@ int queue_dt(ader_ctx* c, double cfl) {
 // The predictor layout in use: the one set, else lane-split where it keeps
 // the per-lane state small enough to avoid spills (MHD at orders 3 and 4,
 // Euler at order 4), one lane per zone otherwise.
-bool layout_built(const StageFns* s, int layout) {
+bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
+  if (layout == ADER_LAYOUT_ZONE2 && c->system == ADER_MHD && c->riemann == ADER_LINEARIZED)
+    return false;
   switch (layout) {
     case ADER_LAYOUT_ZONE: return true;
     case ADER_LAYOUT_SPLIT: return s->predict_split != nullptr;
@@ -93,7 +95,7 @@ bool layout_built(const StageFns* s, int layout) {
 }
 
 int layout_of(const ader_ctx* c, const StageFns* s) {
-  if (c->layout >= 0 && layout_built(s, c->layout)) return c->layout;
+  if (c->layout >= 0 && layout_built(c, s, c->layout)) return c->layout;
   if (s->predict_split && (c->system == ADER_MHD || c->order == 4)) return ADER_LAYOUT_SPLIT;
   return ADER_LAYOUT_ZONE;
 }
@@ -294,7 +296,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
   const size_t Z = (size_t)S;
   const size_t sU = sizeof(double) * 5 * Z;
   const size_t sW = sizeof(double) * 19 * 5 * Z;
-  const size_t sPK = sizeof(double) * 6 * (mhd ? 32 : 15) * Z;
+  const size_t sPK = sizeof(double) * 6 * (mhd ? kMhdSlots : 15) * Z;
   const size_t sF = sizeof(double) * 3 * 5 * Z;
   const size_t s3 = sizeof(double) * 3 * Z;
   const size_t sM = mhd ? s3 * (1 + 1 + 19 + 3 + 4 + 1) : 0;  // B, B0, WB, BN, FE, E
@@ -425,7 +427,7 @@ int autotune(ader_ctx* c, int reps) {
     const int nlayouts = cls == kClassPredict ? kNumLayouts : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
       if (cls == kClassPredict) {
-        if (!layout_built(s, lay)) continue;
+        if (!layout_built(c, s, lay)) continue;
         c->layout = lay;
       }
       for (const LaunchShape& cand : kCandidates) {
@@ -495,7 +497,6 @@ int ader_set_order(ader_ctx* c, int order, int form) {
 
 int ader_set_riemann(ader_ctx* c, int riemann) {
   if (!c || (riemann != ADER_HLL && riemann != ADER_LINEARIZED)) return ADER_EINVAL;
-  if (c->system == ADER_MHD && riemann != ADER_HLL) return ADER_EUNSUPPORTED;
   c->riemann = riemann;
   return ADER_OK;
 }

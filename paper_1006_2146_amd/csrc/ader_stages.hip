@@ -57,11 +57,21 @@ int predict(ader_ctx* c) {
   const int bs = c->shape[kClassPredict].block;
   const T* W = static_cast<const T*>(c->W);
   T* PK = static_cast<T*>(c->PK);
-  if constexpr (kMhd)
-    k_predict_mhd<T, kOrder, kForm, FUSED><<<g, bs, 0, c->stream>>>(
-        c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK, c->batch(),
-        c->d_dt, c->gamma);
-  else
+  if constexpr (kMhd) {
+    if (c->riemann == ADER_LINEARIZED) {
+      // the linearized flux needs every variable's edge states (fused instance only)
+      if constexpr (FUSED)
+        k_predict_mhd<T, kOrder, kForm, FUSED, true><<<g, bs, 0, c->stream>>>(
+            c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK,
+            c->batch(), c->d_dt, c->gamma);
+      else
+        return ADER_EUNSUPPORTED;
+    } else {
+      k_predict_mhd<T, kOrder, kForm, FUSED, false><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK,
+          c->batch(), c->d_dt, c->gamma);
+    }
+  } else
     k_predict<T, kOrder, kForm, FUSED><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt,
                                                                 c->gamma);
   return launched();
@@ -95,7 +105,10 @@ int flux(ader_ctx* c) {
   const int bs = c->shape[kClassFlux].block;
   const T* PK = static_cast<const T*>(c->PK);
   if constexpr (kMhd) {
-    k_face_flux_mhd<T><<<g, bs, 0, c->stream>>>(c->U, c->B0, PK, c->F, c->FE, c->batch(), c->gamma);
+    if (c->riemann == ADER_HLL)
+      k_face_flux_mhd<T, 0><<<g, bs, 0, c->stream>>>(c->U, c->B0, PK, c->F, c->FE, c->batch(), c->gamma);
+    else
+      k_face_flux_mhd<T, 1><<<g, bs, 0, c->stream>>>(c->U, c->B0, PK, c->F, c->FE, c->batch(), c->gamma);
     ADER_TRY(launched());
     k_edge_e<><<<g, bs, 0, c->stream>>>(c->FE, c->E, c->batch());
   } else if (c->riemann == ADER_HLL) {

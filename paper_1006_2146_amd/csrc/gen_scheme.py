@@ -477,6 +477,8 @@ def _count(key, n):
     """Count under (tag, part) for the system of this pass; parts of the other
     system's code are not counted."""
     tag, part = key
+    if part.endswith('-mhd-lin'):
+        return
     if part.endswith('-mhd') != _is_mhd() and part != 'predictor':
         return
     k = (tag + ('-mhd' if _is_mhd() else '') + ('-dev' if _is_dev() else ''),
@@ -762,6 +764,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
     out.append("      Acc& acc, T (&ub)[NV], T (&ua)[NV], T (&fa)[NV], T (&ue)[4], T (&fe)[4]) {")
     out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV];")
+    edge_rows = {}
     for si, (d, s_) in enumerate(SIDES):
         tr = transverse(d)
         out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s_))
@@ -785,6 +788,7 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                                P(ex[d], HALF * s_) * P(ex[a], HALF * sg) / (dd + 1))
                 _count((tag, 'faces-mhd'), 2 * (sum(1 for c in row if c != 0) - (1 if _is_dev() else 0)))
                 out.append("      ue[%d] = %s;" % (q, _value(row, ls, "Phys::comp(%d)" % (5 + a))))
+                edge_rows.setdefault(si, {})[q] = row
         out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
         out.append("      for (int q = 0; q < 4; ++q) fe[q] = T(0);")
         for j in range(1, nf + 1):
@@ -806,6 +810,19 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                 a = tr[which]
                 out.append("      fe[%d] += %s * fl[Phys::comp(%d)];" % (q, lit(ew[(which, sg)][j]), 5 + a))
                 _count((tag, 'faces-mhd'), 2)
+        out.append("    }")
+    out.append("  }")
+    # every component's edge averages (the linearized solver's edge problems)
+    out.append("  // ue[q][v]: edge average (eq. 57) of variable v on edge q of side SIDE")
+    out.append("  template <int SIDE, bool DEV>")
+    out.append("  __host__ __device__ static __forceinline__ void edge_states(const T (&w)[LS][NV], const T (&e)[NE][NV],")
+    out.append("                                                         T (&ue)[4][NV]) {")
+    for si in range(len(SIDES)):
+        out.append("    %sif constexpr (SIDE == %d) {" % ("" if si == 0 else "else ", si))
+        for q in range(4):
+            row = edge_rows[si][q]
+            _count((tag, 'faces-mhd-lin'), NV_OF[SYSTEM] * (2 * sum(1 for c in row if c != 0) - 1))
+            out.append("      for (int v = 0; v < NV; ++v) ue[%d][v] = %s;" % (q, _value(row, ls)))
         out.append("    }")
     out.append("  }")
     return out

@@ -249,18 +249,16 @@ __device__ __forceinline__ void predict_zone_mhd_split(
     T ub[1], ua[1], fa[1], ue[4], fe[4];
     NoScan none;
     S::template side_edges<SIDE>(w, e, ph, none, ub, ua, fa, ue, fe);
-    T* base = PK + (long long)SIDE * 32 * g.S + n;
+    T* base = PK + (long long)SIDE * kMhdSlots * g.S + n;
     base[(long long)L.var * g.S] = ub[0];
     base[(long long)(8 + L.var) * g.S] = ua[0];
     base[(long long)(16 + L.var) * g.S] = fa[0];
-    // edge values of the field component along each transverse axis: the
-    // lane holding that component has them
+    // every lane has its own variable's edge averages; the lane holding the
+    // field component along an edge's transverse axis has its flux
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (L.var == 5 + (q < 2 ? TA0 : TA1)) {
-        base[(long long)(24 + q) * g.S] = ue[q];
-        base[(long long)(28 + q) * g.S] = fe[q];
-      }
+      base[(long long)mhd_ue_slot(q, 0) * g.S + (long long)L.var * g.S] = ue[q];
+      if (L.var == 5 + (q < 2 ? TA0 : TA1)) base[(long long)mhd_fe_slot(q) * g.S] = fe[q];
     }
   };
   side(std::integral_constant<int, 0>{});

@@ -177,6 +177,134 @@ struct Mhd {
   }
 };
 
+// Linearized dissipation of ideal MHD along AXIS (Sec. II.3): D = |A| du with
+// |A| = R |Lambda| L of the seven-wave system -- primitive variables
+// (rho, u_n, u_t1, u_t2, p, b_t1, b_t2), b = B / sqrt(4 pi), with b_n held at
+// its frozen value -- at a frozen state, here the mean of the two barycentre
+// primitive states.  Eigenvectors in the Roe & Balsara (1996) normalisation:
+// with alpha_f^2 = (a^2 - c_s^2) / (c_f^2 - c_s^2), alpha_s^2 = (c_f^2 -
+// a^2) / (c_f^2 - c_s^2), beta = b_t / |b_t| and s = sign(b_n), right vectors
+// (sigma = -1, +1)
+//   fast    (rho af, sig af cf, -sig as cs s beta, rho af a^2, as a sqrt(rho) beta)
+//   Alfven  (0, 0, (-beta_2, beta_1), 0, sig s sqrt(rho) (beta_2, -beta_1))
+//   slow    (rho as, sig as cs, sig af cf s beta, rho as a^2, -af a sqrt(rho) beta)
+//   entropy (1, 0, 0, 0, 0, 0, 0)
+// and the dual left vectors; beta = (1, 1)/sqrt(2) when b_t = 0, and
+// (alpha_f, alpha_s) = (1, 0) when c_f = c_s.  Conserved jumps are mapped to
+// primitive ones and back with the Jacobian of the variable change at the
+// frozen state; the normal-field row of D is zero.
+template <class T, int AXIS>
+struct MhdEigen {
+  static constexpr int T1 = AXIS == 0 ? 1 : 0, T2 = AXIS == 2 ? 1 : 2;
+  T rho, sr, un, u1, u2, q2, bn, b1, b2, a2, a, cf, cs, ca, af, as, be1, be2, sg, gm1;
+
+  __host__ __device__ MhdEigen(const T (&ul)[8], const T (&ur)[8], T gam) {
+    constexpr T i4p = T(1.0 / (4.0 * 3.14159265358979323846));
+    const T isq4p = sqrt(i4p);
+    const T il = T(1) / ul[0], ir = T(1) / ur[0];
+    rho = T(0.5) * (ul[0] + ur[0]);
+    T v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v[d] = T(0.5) * (ul[1 + d] * il + ur[1 + d] * ir);
+    const T p = T(0.5) * (Mhd<T>::pressure(ul, gam) + Mhd<T>::pressure(ur, gam));
+    T B[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) B[d] = T(0.5) * (ul[5 + d] + ur[5 + d]);
+    un = v[AXIS];
+    u1 = v[T1];
+    u2 = v[T2];
+    q2 = un * un + u1 * u1 + u2 * u2;
+    bn = B[AXIS] * isq4p;
+    b1 = B[T1] * isq4p;
+    b2 = B[T2] * isq4p;
+    gm1 = gam - T(1);
+    sr = sqrt(rho);
+    a2 = gam * p / rho;
+    a = sqrt(a2);
+    const T ca2 = bn * bn / rho;
+    const T bt2 = (b1 * b1 + b2 * b2) / rho;
+    const T s = a2 + ca2 + bt2;
+    const T disc = s * s - T(4) * a2 * ca2;
+    const T cf2 = T(0.5) * (s + sqrt(disc > T(0) ? disc : T(0)));
+    const T cs2 = cf2 > T(0) ? a2 * ca2 / cf2 : T(0);    // c_f^2 c_s^2 = a^2 c_a^2
+    cf = sqrt(cf2);
+    cs = sqrt(cs2);
+    ca = sqrt(ca2);
+    const T bperp = sqrt(b1 * b1 + b2 * b2);
+    if (bperp > T(0)) {
+      be1 = b1 / bperp;
+      be2 = b2 / bperp;
+    } else {
+      be1 = be2 = T(0.70710678118654752);
+    }
+    const T dd = cf2 - cs2;
+    if (dd > T(0)) {
+      const T f = (a2 - cs2) / dd, g = (cf2 - a2) / dd;
+      af = sqrt(fmin(fmax(f, T(0)), T(1)));
+      as = sqrt(fmin(fmax(g, T(0)), T(1)));
+    } else {
+      af = T(1);
+      as = T(0);
+    }
+    sg = bn >= T(0) ? T(1) : T(-1);
+  }
+
+  __host__ __device__ void apply(const T (&du)[8], T (&D)[8]) const {
+    constexpr T s4p = T(3.5449077018110321);   // sqrt(4 pi)
+    // conserved -> primitive jump at the frozen state
+    const T dr = du[0];
+    const T irho = T(1) / rho;
+    const T dun = (du[1 + AXIS] - un * dr) * irho;
+    const T du1 = (du[1 + T1] - u1 * dr) * irho;
+    const T du2 = (du[1 + T2] - u2 * dr) * irho;
+    const T db1 = du[5 + T1] / s4p, db2 = du[5 + T2] / s4p;
+    const T dp = gm1 * (du[4] - (un * du[1 + AXIS] + u1 * du[1 + T1] + u2 * du[1 + T2]) +
+                        T(0.5) * q2 * dr - (b1 * db1 + b2 * db2));
+    // wave strengths (left vectors) times |lambda|
+    const T ia2 = T(0.5) / a2;
+    const T isr = T(1) / sr;
+    const T par = dp * irho;                                  // common parts
+    const T bdu = be1 * du1 + be2 * du2;                      // beta . du_t
+    const T bdb = (be1 * db1 + be2 * db2) * isr;              // beta . db_t / sqrt(rho)
+    const T xdu = -be2 * du1 + be1 * du2;                     // beta^perp . du_t
+    const T xdb = (-be2 * db1 + be1 * db2) * isr;
+    T w[7];
+    {
+      const T fa = af * par + as * a * bdb, fb = af * cf * dun - as * cs * sg * bdu;
+      w[0] = fabs(un - cf) * ia2 * (fa - fb);   // fast -
+      w[1] = fabs(un + cf) * ia2 * (fa + fb);   // fast +
+      const T sa = as * par - af * a * bdb, sb = as * cs * dun + af * cf * sg * bdu;
+      w[2] = fabs(un - cs) * ia2 * (sa - sb);   // slow -
+      w[3] = fabs(un + cs) * ia2 * (sa + sb);   // slow +
+      w[4] = fabs(un - ca) * T(0.5) * (xdu + sg * xdb);   // Alfven -
+      w[5] = fabs(un + ca) * T(0.5) * (xdu - sg * xdb);   // Alfven +
+      w[6] = fabs(un) * (dr - dp / a2);                    // entropy
+    }
+    // primitive result: sum of w_k R_k
+    const T fsum = w[0] + w[1], fdif = w[1] - w[0];
+    const T ssum = w[2] + w[3], sdif = w[3] - w[2];
+    const T asum = w[4] + w[5], adif = w[5] - w[4];
+    const T r_ = rho * (af * fsum + as * ssum) + w[6];
+    const T un_ = af * cf * fdif + as * cs * sdif;
+    const T tpar = -as * cs * sg * fdif + af * cf * sg * sdif;   // along beta
+    const T u1_ = tpar * be1 - be2 * asum;
+    const T u2_ = tpar * be2 + be1 * asum;
+    const T p_ = rho * a2 * (af * fsum + as * ssum);
+    const T bpar = a * sr * (as * fsum - af * ssum);
+    const T b1_ = bpar * be1 + sg * sr * be2 * adif;
+    const T b2_ = bpar * be2 - sg * sr * be1 * adif;
+    // primitive -> conserved
+    D[0] = r_;
+    D[1 + AXIS] = rho * un_ + un * r_;
+    D[1 + T1] = rho * u1_ + u1 * r_;
+    D[1 + T2] = rho * u2_ + u2 * r_;
+    D[4] = T(0.5) * q2 * r_ + rho * (un * un_ + u1 * u1_ + u2 * u2_) + p_ / gm1 + b1 * b1_ + b2 * b2_;
+    D[5 + AXIS] = T(0);
+    D[5 + T1] = s4p * b1_;
+    D[5 + T2] = s4p * b2_;
+  }
+};
+
 // Flux evaluators for the generated per-zone code.  PointFlux takes the state
 // at a point and returns its physical flux; DeviationFlux takes the deviation
 // of the state from the zone average and returns the deviation of the flux

@@ -775,13 +775,27 @@ __host__ __device__ __forceinline__ void bface_zone(const double* __restrict__ B
   }
 }
 
-template <class S, class T, int SIDE, class Phys, class Acc>
+// MHD side packet, kMhdSlots values per side: barycentre state (0-7), face
+// averages of u (8-15) and F (16-23), on each edge q = 2 w + (side > 0) the
+// edge average of the field flux of the component along transverse axis t_w
+// (24 + q) and the edge averages of u (28 + 8 q + v).  The HLL flux reads
+// only the field component of the edge states, the linearized flux all.
+constexpr int kMhdSlots = 60;
+__host__ __device__ constexpr int mhd_fe_slot(int q) { return 24 + q; }
+__host__ __device__ constexpr int mhd_ue_slot(int q, int v) { return 28 + 8 * q + v; }
+__host__ __device__ constexpr int mhd_edge_comp(int axis, int q) {
+  return 5 + (q < 2 ? (axis == 0 ? 1 : 0) : (axis == 2 ? 1 : 2));
+}
+
+// EDGES_ALL: store every variable's edge average (linearized flux), else only
+// the field component each edge needs (HLL)
+template <class S, class T, int SIDE, bool EDGES_ALL, class Phys, class Acc>
 __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], const T (&e)[S::NE][8],
                                                         const Phys& ph, Acc& acc, T* __restrict__ PK,
                                                         long long N, long long n) {
   T ub[8], ua[8], fa[8], ue[4], fe[4];
   S::template side_edges<SIDE>(w, e, ph, acc, ub, ua, fa, ue, fe);
-  T* base = PK + (long long)SIDE * 32 * N + n;
+  T* base = PK + (long long)SIDE * kMhdSlots * N + n;
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
     base[(long long)v * N] = ub[v];
@@ -789,9 +803,18 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
     base[(long long)(16 + v) * N] = fa[v];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    base[(long long)(24 + q) * N] = ue[q];
-    base[(long long)(28 + q) * N] = fe[q];
+  for (int q = 0; q < 4; ++q) base[(long long)mhd_fe_slot(q) * N] = fe[q];
+  if constexpr (EDGES_ALL) {
+    T ues[4][8];
+    S::template edge_states<SIDE, Phys::kDeviation>(w, e, ues);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) base[(long long)mhd_ue_slot(q, v) * N] = ues[q][v];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      base[(long long)mhd_ue_slot(q, mhd_edge_comp(SIDE / 2, q)) * N] = ue[q];
   }
 }
 
@@ -800,7 +823,7 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
 // predictor, positivity scaling and the six side packets of 32 values
 // (barycentre state, face averages of u and F, edge averages of u and F of
 // the field component along each edge's transverse axis).
-template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true>
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool EDGES_ALL = false>
 __host__ __device__ __forceinline__ void predict_zone_mhd(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
@@ -860,24 +883,24 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
         for (int v = 0; v < 8; ++v) e[m][v] *= th;
     }
     NoScan none;
-    store_side_mhd<S, T, 0>(w, e, ph, none, PK, g.S, n);
-    store_side_mhd<S, T, 1>(w, e, ph, none, PK, g.S, n);
-    store_side_mhd<S, T, 2>(w, e, ph, none, PK, g.S, n);
-    store_side_mhd<S, T, 3>(w, e, ph, none, PK, g.S, n);
-    store_side_mhd<S, T, 4>(w, e, ph, none, PK, g.S, n);
-    store_side_mhd<S, T, 5>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 0, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 1, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 2, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 3, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 4, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 5, EDGES_ALL>(w, e, ph, none, PK, g.S, n);
     return;
   }
   // side packets with the facial scan on the way, as in predict_zone
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     PosScan<T, 8, DEV> scan(w0);
-    store_side_mhd<S, T, 0>(w, e, ph, scan, PK, g.S, n);
-    store_side_mhd<S, T, 1>(w, e, ph, scan, PK, g.S, n);
-    store_side_mhd<S, T, 2>(w, e, ph, scan, PK, g.S, n);
-    store_side_mhd<S, T, 3>(w, e, ph, scan, PK, g.S, n);
-    store_side_mhd<S, T, 4>(w, e, ph, scan, PK, g.S, n);
-    store_side_mhd<S, T, 5>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 0, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 1, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 2, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 3, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 4, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
+    store_side_mhd<S, T, 5, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
     if (pass == 1 || !scan.near) break;
     const double theta = theta_facial_tab(w0, w, e, S::facial_phi_all, gam);
     if (!(theta < 1.0)) break;
@@ -893,12 +916,15 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   }
 }
 
-// HLL at the lower AXIS-face of zone n (MHD): the five hydro fluxes, and the
-// same HLL combination, with this face's speeds, of the edge averages on its
-// four edges (eq. 56-57).  Deviation form as for Euler: the HLL of the zone
-// averages (double) plus the HLL of the deviations (FP32); on the edges the
-// zone-average part is the field component of the same double flux.
-template <class T, int AXIS, bool DEV>
+// Riemann flux at the lower AXIS-face of zone n (MHD): the five hydro fluxes,
+// and the same solver, with this face's speeds (HLL) or frozen eigen-system
+// (linearized), applied to the edge states (eq. 57) on its four edges, of
+// which the induction flux of the edge's field component enters the edge
+// field.  Deviation form as for Euler: the solver applied to the zone
+// averages (double) plus the solver applied to the deviations (FP32); on the
+// edges the zone-average part is the field component of the same double
+// flux.
+template <class T, int RS, int AXIS, bool DEV>
 __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __restrict__ U,
                                                             const double* __restrict__ B0,
                                                             const T* __restrict__ PK,
@@ -907,9 +933,8 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
                                                             const Grid& g, long long n,
                                                             long long nl, double gam) {
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
-  constexpr int TA[2] = {AXIS == 0 ? 1 : 0, AXIS == 2 ? 1 : 2};   // transverse axes
-  const T* L = PK + (long long)SL * 32 * g.S + nl;
-  const T* R = PK + (long long)SR * 32 * g.S + n;
+  const T* L = PK + (long long)SL * kMhdSlots * g.S + nl;
+  const T* R = PK + (long long)SR * kMhdSlots * g.S + n;
   double wl[8], wr[8];
   if constexpr (DEV) {
 #pragma unroll
@@ -934,52 +959,95 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
     }
   }
   const T tg = T(gam);
-  const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
-  const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, tg);
-  const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, tg);
-  const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
-  const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
-  T ul[5], ur[5], fl[5], fr[5], out[5];
+  T out[5], eout[4];
+  if constexpr (RS == 0) {
+    const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
+    const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, tg);
+    const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, tg);
+    const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
+    const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
+    T ul[5], ur[5], fl[5], fr[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    ul[v] = L[(long long)(8 + v) * g.S];
-    ur[v] = R[(long long)(8 + v) * g.S];
-    fl[v] = L[(long long)(16 + v) * g.S];
-    fr[v] = R[(long long)(16 + v) * g.S];
-    if constexpr (DEV) ur[v] += T(wr[v] - wl[v]);
-  }
-  hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
-  T el[4], er[4], gl[4], gr[4], eout[4];
+    for (int v = 0; v < 5; ++v) {
+      ul[v] = L[(long long)(8 + v) * g.S];
+      ur[v] = R[(long long)(8 + v) * g.S];
+      fl[v] = L[(long long)(16 + v) * g.S];
+      fr[v] = R[(long long)(16 + v) * g.S];
+      if constexpr (DEV) ur[v] += T(wr[v] - wl[v]);
+    }
+    hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
+    T el[4], er[4], gl[4], gr[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    el[q] = L[(long long)(24 + q) * g.S];
-    er[q] = R[(long long)(24 + q) * g.S];
-    gl[q] = L[(long long)(28 + q) * g.S];
-    gr[q] = R[(long long)(28 + q) * g.S];
-    if constexpr (DEV) er[q] += T(wr[5 + TA[q / 2]] - wl[5 + TA[q / 2]]);
-  }
-  hll_combine<T, 4>(lam_l, lam_r, el, gl, er, gr, eout);
-  if constexpr (DEV) {
-    double Fl[8], Fr[8], Fa[8];
-    Mhd<double>::template flux<AXIS>(wl, Fl, gam);
-    Mhd<double>::template flux<AXIS>(wr, Fr, gam);
-    const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
+    for (int q = 0; q < 4; ++q) {
+      const int c = mhd_edge_comp(AXIS, q);
+      el[q] = L[(long long)mhd_ue_slot(q, c) * g.S];
+      er[q] = R[(long long)mhd_ue_slot(q, c) * g.S];
+      gl[q] = L[(long long)mhd_fe_slot(q) * g.S];
+      gr[q] = R[(long long)mhd_fe_slot(q) * g.S];
+      if constexpr (DEV) er[q] += T(wr[c] - wl[c]);
+    }
+    hll_combine<T, 4>(lam_l, lam_r, el, gl, er, gr, eout);
+    if constexpr (DEV) {
+      double Fl[8], Fr[8], Fa[8];
+      Mhd<double>::template flux<AXIS>(wl, Fl, gam);
+      Mhd<double>::template flux<AXIS>(wr, Fr, gam);
+      const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) Fa[v] = (lr * Fl[v] - ll * Fr[v]) * inv;
+      for (int v = 0; v < 8; ++v) Fa[v] = (lr * Fl[v] - ll * Fr[v]) * inv;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = Fa[v] + double(out[v]);
+      for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = Fa[v] + double(out[v]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      FE[((long long)AXIS * 4 + q) * g.S + n] = Fa[5 + TA[q / 2]] + double(eout[q]);
+      for (int q = 0; q < 4; ++q)
+        FE[((long long)AXIS * 4 + q) * g.S + n] = Fa[mhd_edge_comp(AXIS, q)] + double(eout[q]);
+      return;
+    }
   } else {
+    const MhdEigen<T, AXIS> eg(ubl, ubr, tg);
+    T du[8], D[8];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
+    for (int v = 0; v < 8; ++v) {
+      du[v] = R[(long long)(8 + v) * g.S] - L[(long long)(8 + v) * g.S];
+      if constexpr (DEV) du[v] += T(wr[v] - wl[v]);
+    }
+    eg.apply(du, D);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.S + n] = double(eout[q]);
+    for (int v = 0; v < 5; ++v)
+      out[v] = T(0.5) * (L[(long long)(16 + v) * g.S] + R[(long long)(16 + v) * g.S]) - T(0.5) * D[v];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = mhd_edge_comp(AXIS, q);
+      T de[8], De[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        de[v] = R[(long long)mhd_ue_slot(q, v) * g.S] - L[(long long)mhd_ue_slot(q, v) * g.S];
+        if constexpr (DEV) de[v] += T(wr[v] - wl[v]);
+      }
+      eg.apply(de, De);
+      eout[q] = T(0.5) * (L[(long long)mhd_fe_slot(q) * g.S] + R[(long long)mhd_fe_slot(q) * g.S]) -
+                T(0.5) * De[c];
+    }
+    if constexpr (DEV) {
+      double Fl[8], Fr[8];
+      Mhd<double>::template flux<AXIS>(wl, Fl, gam);
+      Mhd<double>::template flux<AXIS>(wr, Fr, gam);
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        F[((long long)AXIS * 5 + v) * g.S + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = mhd_edge_comp(AXIS, q);
+        FE[((long long)AXIS * 4 + q) * g.S + n] = 0.5 * (Fl[c] + Fr[c]) + double(eout[q]);
+      }
+      return;
+    }
   }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.S + n] = double(eout[q]);
 }
 
-template <class T, bool DEV>
+template <class T, int RS, bool DEV>
 __host__ __device__ __forceinline__ void face_flux_zone_mhd(const double* __restrict__ U,
                                                             const double* __restrict__ B0,
                                                             const T* __restrict__ PK,
@@ -988,9 +1056,9 @@ __host__ __device__ __forceinline__ void face_flux_zone_mhd(const double* __rest
                                                             double gam, long long n) {
   int i, j, k;
   zone_ijk(g, n, i, j, k);
-  face_flux_axis_mhd<T, 0, DEV>(U, B0, PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
-  face_flux_axis_mhd<T, 1, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
-  face_flux_axis_mhd<T, 2, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
+  face_flux_axis_mhd<T, RS, 0, DEV>(U, B0, PK, F, FE, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
+  face_flux_axis_mhd<T, RS, 1, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
+  face_flux_axis_mhd<T, RS, 2, DEV>(U, B0, PK, F, FE, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
 }
 
 // Edge fields at the three lower edges of zone n: E_c is the mean of the

@@ -43,8 +43,9 @@ def load():
         lib.hostemu_step.restype = I
         lib.hostemu_dt.argtypes = [DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt.restype = D
-        lib.hostemu_step_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, I, I, I, D]
+        lib.hostemu_step_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, I, I, I, I, D]
         lib.hostemu_step_mhd.restype = I
+        lib.hostemu_mhd_dissipation.argtypes = [DP, DP, DP, I, D, DP]
         lib.hostemu_dt_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt_mhd.restype = D
         _lib = lib
@@ -78,12 +79,13 @@ def _dp(a):
 
 
 def step_mhd(U, B, dt, order, form="modal", precision="fp64", lengths=(1.0, 1.0, 1.0),
-             gamma=5.0 / 3.0):
+             gamma=5.0 / 3.0, riemann="hll"):
     Uo = np.ascontiguousarray(U, dtype=np.float64).copy()
     Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
     load().hostemu_step_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
-                            1 if form == "nodal" else 0, PRECISION[precision], dt)
+                            1 if form == "nodal" else 0, 1 if riemann == "linearized" else 0,
+                            PRECISION[precision], dt)
     return Uo, Bo
 
 
@@ -92,3 +94,11 @@ def compute_dt_mhd(U, B, cfl, lengths=(1.0, 1.0, 1.0), gamma=5.0 / 3.0):
     B = np.ascontiguousarray(B, dtype=np.float64)
     nx, ny, nz, dx, dy, dz = _spacing(U, lengths)
     return load().hostemu_dt_mhd(_dp(U), _dp(B), nx, ny, nz, dx, dy, dz, gamma, cfl)
+
+
+def mhd_dissipation(ubl, ubr, du, axis, gamma=5.0 / 3.0):
+    """|A| du of the kernel source's analytic MHD eigen-system (one face)."""
+    out = np.zeros(8)
+    args = [np.ascontiguousarray(a, dtype=np.float64) for a in (ubl, ubr, du)]
+    load().hostemu_mhd_dissipation(_dp(args[0]), _dp(args[1]), _dp(args[2]), axis, gamma, _dp(out))
+    return out

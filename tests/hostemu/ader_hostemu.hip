@@ -79,12 +79,13 @@ static void emu_recon(const double* src, T* W, Grid g, int order, int nvar) {
   }
 }
 
-template <class T, bool DEV>
+template <class T, bool DEV, int RS>
 static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, double dz, double gam,
                          int order, int form, double dt) {
+  constexpr bool ALL = RS == 1;
   const long long N = g.N;
   std::vector<T> W((size_t)19 * 5 * N), WB((size_t)19 * 3 * N), BN((size_t)9 * N),
-      PK((size_t)6 * 32 * N);
+      PK((size_t)6 * kMhdSlots * N);
   std::vector<double> B0((size_t)3 * N), E((size_t)3 * N), F((size_t)15 * N), FE((size_t)12 * N);
   for (long long n = 0; n < N; ++n) {
     if (order == 2) bface_zone<T, 2>(B, B0.data(), BN.data(), g, n);
@@ -96,16 +97,16 @@ static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, dou
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
     if (order == 2 && form == 1)
-      predict_zone_mhd<T, 2, 1, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
-      predict_zone_mhd<T, 2, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
-      predict_zone_mhd<T, 3, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 3, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else
-      predict_zone_mhd<T, 4, 0, DEV>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 4, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
   }
   for (long long n = 0; n < N; ++n)
-    face_flux_zone_mhd<T, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
+    face_flux_zone_mhd<T, RS, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
   for (long long n = 0; n < N; ++n) edge_e_zone(FE.data(), E.data(), g, n);
   for (long long n = 0; n < N; ++n) update_zone(U, F.data(), g, dt, dx, dy, dz, n);
   for (long long n = 0; n < N; ++n) ct_zone(B, E.data(), g, dt, dx, dy, dz, n);
@@ -118,14 +119,35 @@ extern "C" {
 
 // One MHD step of the host build, in place on U[5][N] and the face field B[3][N].
 int hostemu_step_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,
-                     double dz, double gam, int order, int form, int precision, double dt) {
+                     double dz, double gam, int order, int form, int riemann, int precision,
+                     double dt) {
   Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
-  if (precision == 0)
-    emu_step_mhd<double, false>(U, B, g, dx, dy, dz, gam, order, form, dt);
-  else if (precision == 1)
-    emu_step_mhd<float, true>(U, B, g, dx, dy, dz, gam, order, form, dt);
-  else
-    emu_step_mhd<double, true>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  if (riemann == 0) {
+    if (precision == 0) emu_step_mhd<double, false, 0>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    else if (precision == 1) emu_step_mhd<float, true, 0>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    else emu_step_mhd<double, true, 0>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  } else {
+    if (precision == 0) emu_step_mhd<double, false, 1>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    else if (precision == 1) emu_step_mhd<float, true, 1>(U, B, g, dx, dy, dz, gam, order, form, dt);
+    else emu_step_mhd<double, true, 1>(U, B, g, dx, dy, dz, gam, order, form, dt);
+  }
+  return 0;
+}
+
+// |A| du of the linearized MHD solver along axis for one face (host check of
+// the analytic eigen-system): ubl, ubr barycentre states, du a jump, out D.
+int hostemu_mhd_dissipation(const double* ubl, const double* ubr, const double* du, int axis,
+                            double gam, double* out) {
+  double l[8], r[8], d[8], D[8];
+  for (int v = 0; v < 8; ++v) {
+    l[v] = ubl[v];
+    r[v] = ubr[v];
+    d[v] = du[v];
+  }
+  if (axis == 0) MhdEigen<double, 0>(l, r, gam).apply(d, D);
+  else if (axis == 1) MhdEigen<double, 1>(l, r, gam).apply(d, D);
+  else MhdEigen<double, 2>(l, r, gam).apply(d, D);
+  for (int v = 0; v < 8; ++v) out[v] = D[v];
   return 0;
 }
 

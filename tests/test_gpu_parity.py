@@ -152,19 +152,20 @@ G53 = 5.0 / 3.0
 MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
 
 
-def _mhd_solver(shape, order, form, lengths=(1.0, 1.0, 1.0), precision=ader.ADER_FP64):
+def _mhd_solver(shape, order, form, lengths=(1.0, 1.0, 1.0), precision=ader.ADER_FP64, rs="hll"):
     return ader.Solver(shape, lengths=lengths, gamma=G53, order=order, form=FORM[form],
-                       riemann=ader.ADER_HLL, precision=precision, system=ader.ADER_MHD)
+                       riemann=RS[rs], precision=precision, system=ader.ADER_MHD)
 
 
-def _check_steps_mhd(U0, B0, order, form, nsteps, cfl=0.3, lengths=(1.0, 1.0, 1.0), tag=""):
+def _check_steps_mhd(U0, B0, order, form, nsteps, cfl=0.3, lengths=(1.0, 1.0, 1.0), tag="",
+                     rs="hll"):
     shape = U0.shape[1:]
-    cfg = OracleConfig(order=order, form=form, gamma=G53, lengths=lengths)
-    with _mhd_solver(shape, order, form, lengths) as s:
+    cfg = OracleConfig(order=order, form=form, gamma=G53, lengths=lengths, riemann=rs)
+    with _mhd_solver(shape, order, form, lengths, rs=rs) as s:
         s.set_state(U0, B0)
         U, B = U0, B0
         for it in range(nsteps):
-            say(tag, "mhd order", order, form, "shape", shape, "step", it)
+            say(tag, "mhd order", order, form, rs, "shape", shape, "step", it)
             dt_gpu = s.compute_dt(cfl)
             assert abs(dt_gpu - oracle_dt(U, cfg, cfl, B)) <= 1e-14 * dt_gpu
             s.step(dt_gpu)
@@ -176,26 +177,38 @@ def _check_steps_mhd(U0, B0, order, form, nsteps, cfl=0.3, lengths=(1.0, 1.0, 1.
     return U, B
 
 
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("order,form", MHD_CASES)
-def test_parity_mhd_random_field_ragged(order, form):
+def test_parity_mhd_random_field_ragged(order, form, rs):
     U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order)
-    _check_steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), tag="mhd-random")
+    _check_steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), tag="mhd-random", rs=rs)
 
 
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_parity_mhd_alfven_and_div_b(order):
+def test_parity_mhd_alfven_and_div_b(order, rs):
     from oracle.bweno import divergence
     U0, B0 = workloads.alfven_wave_diagonal((8, 8, 8))
-    U, B = _check_steps_mhd(U0, B0, order, "modal", 3, tag="mhd-alfven")
+    U, B = _check_steps_mhd(U0, B0, order, "modal", 3, tag="mhd-alfven", rs=rs)
     dx = (1.0 / 8,) * 3
     assert np.abs(divergence(B, dx)).max() <= 1e-12 * np.abs(B).max() / dx[0]
     assert np.all(np.abs(U.sum(axis=(1, 2, 3)) - U0.sum(axis=(1, 2, 3))) <= 1e-13 * np.abs(U0).sum())
 
 
-def test_mhd_linearized_is_unsupported():
-    with _mhd_solver((4, 4, 4), 3, "modal") as s:
-        rc = ader.load().ader_set_riemann(s.ctx, ader.ADER_LINEARIZED)
-        assert rc == ader.ADER_EUNSUPPORTED
+def test_mhd_linearized_layouts():
+    # the linearized MHD flux in every layout that carries full edge states
+    U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=31)
+    cfg = OracleConfig(order=3, gamma=G53, riemann="linearized")
+    for layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2):
+        with _mhd_solver((6, 7, 8), 3, "modal", rs="linearized") as s:
+            ader.ader_set_layout(s.ctx, layout)
+            s.set_state(U0, B0)
+            say("mhd linearized layout", layout)
+            dt = s.compute_dt(0.3)
+            s.step(dt)
+            Ug, Bg = s.get_state()
+        Uo, Bo = oracle_step(U0, dt, cfg, B0)
+        assert np.all(rel_l1(Ug, Uo) <= TOL_FP64) and np.all(rel_l1(Bg, Bo) <= TOL_FP64), layout
 
 
 def test_config3_mhd_full_size_sampled():

@@ -67,13 +67,15 @@ def test_kernel_source_tiny_meshes(order, precision):
 MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
 
 
-def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, precision="fp64"):
-    cfg = OracleConfig(order=order, form=form, gamma=5.0 / 3.0, lengths=lengths)
+def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, precision="fp64",
+               rs="hll"):
+    cfg = OracleConfig(order=order, form=form, gamma=5.0 / 3.0, lengths=lengths, riemann=rs)
     U, B = U0, B0
     for it in range(nsteps):
         dt = hostemu.compute_dt_mhd(U, B, cfl, lengths)
         assert abs(dt - oracle_dt(U, cfg, cfl, B)) <= 1e-14 * dt
-        Ue, Be = hostemu.step_mhd(U, B, dt, order, form, precision=precision, lengths=lengths)
+        Ue, Be = hostemu.step_mhd(U, B, dt, order, form, precision=precision, lengths=lengths,
+                                  riemann=rs)
         Uo, Bo = oracle_step(U, dt, cfg, B)
         err = rel_l1(Ue, Uo)
         errb = rel_l1(Be, Bo)
@@ -82,15 +84,38 @@ def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, pr
     return U, B
 
 
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order,form", MHD_CASES)
-def test_kernel_source_mhd_random_field(order, form, precision):
+def test_kernel_source_mhd_random_field(order, form, precision, rs):
     U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=order)
-    _steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), precision=precision)
+    _steps_mhd(U0, B0, order, form, 2, lengths=(1.0, 0.9, 1.2), precision=precision, rs=rs)
 
 
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("precision", FORMS)
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_kernel_source_mhd_alfven(order, precision):
+def test_kernel_source_mhd_alfven(order, precision, rs):
     U0, B0 = workloads.alfven_wave_diagonal((6, 6, 6))
-    _steps_mhd(U0, B0, order, "modal", 2, precision=precision)
+    _steps_mhd(U0, B0, order, "modal", 2, precision=precision, rs=rs)
+
+
+def test_kernel_source_mhd_eigensystem():
+    # the kernel source's analytic eigen-system (Roe-Balsara vectors) against
+    # the oracle's |A| from its definition, on random face pairs and axes
+    from oracle.physics import conserved
+    from oracle.riemann import mhd_abs_jacobian, mhd_dissipation
+    rng = np.random.default_rng(3)
+    G = 5.0 / 3.0
+
+    def state():
+        return conserved(rng.uniform(0.5, 2.0), rng.normal(0, 0.5, 3), rng.uniform(0.5, 2.0),
+                         rng.normal(0, 2.0, 3), G)
+    for _ in range(30):
+        ul, ur = state(), state()
+        du = rng.normal(0, 1, 8)
+        for axis in range(3):
+            Do = mhd_dissipation(mhd_abs_jacobian(ul[:, None], ur[:, None], axis, G),
+                                 du[:, None], axis)[:, 0]
+            Dk = hostemu.mhd_dissipation(ul, ur, du, axis, G)
+            assert np.abs(Dk - Do).max() <= 1e-12 * np.abs(Do).max()
