@@ -53,10 +53,12 @@ class Tuning:
             cfg = self.saved[key]
             ader.ader_set_launch(ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
             ader.ader_set_layout(ctx, cfg["layout"])
+            ader.ader_set_recon(ctx, cfg["recon"])
         else:
             ader.ader_autotune(ctx, 4)
             self.saved[key] = {"launch": ader.ader_get_launch(ctx),
-                               "layout": ader.ader_get_layout(ctx)}
+                               "layout": ader.ader_get_layout(ctx),
+                               "recon": ader.ader_get_recon(ctx)}
 
     def write(self):
         if self.path and not self.reuse:
@@ -141,6 +143,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         finite = bool(torch.isfinite(dU).all().item())
         launch = ader.ader_get_launch(s.ctx)
         layout = LAYOUT_NAMES[ader.ader_get_layout(s.ctx)]
+        recon_mode = ["sweeps", "tiled"][ader.ader_get_recon(s.ctx)]
     finally:
         s.close()
     wall = t1 - t0
@@ -150,6 +153,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
         "launch": launch,
         "predict_layout": layout,
+        "recon_mode": recon_mode,
         "finite": finite,
     }
 
@@ -188,7 +192,8 @@ def run_ensemble(ader, torch, steps, warmup):
                          "ms_per_step": 1e3 * (t1 - t0) / steps,
                          "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
                          "launch": ader.ader_get_launch(b.ctx),
-                         "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(b.ctx)]}
+                         "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(b.ctx)],
+                         "recon_mode": ["sweeps", "tiled"][ader.ader_get_recon(b.ctx)]}
         log("ensemble", name, "%.3e zone-updates/s" % out[name]["zone_updates_per_s"])
     out["mixed_over_fp64"] = out["mixed"]["zone_updates_per_s"] / out["fp64"]["zone_updates_per_s"]
     return out

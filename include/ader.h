@@ -191,7 +191,8 @@ int ader_set_graph(ader_ctx* ctx, int enable);
  * own problems and settings, `reps` launches each (1..1000), and keeps the
  * fastest.  The state and dt are saved before and restored after, so the
  * solution does not advance; results do not depend on the launch shape.
- * For the predictor it also tries both layouts (ader_set_layout).
+ * For the predictor it also tries the layouts (ader_set_layout), for the
+ * reconstruction both modes (ader_set_recon).
  * Needs a state (ADER_ESEQ); allocates a temporary copy of it. */
 int ader_autotune(ader_ctx* ctx, int reps);
 
@@ -215,6 +216,18 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
+
+/* Execution of the WENO reconstruction (Sec. II.1; orders 3 and 4):
+ * ADER_RECON_SWEEPS, one launch per sweep direction, or ADER_RECON_TILED,
+ * one launch doing the x, y and z sweeps of 8 x 8 x 8-zone tiles in LDS
+ * (halo M-1 zones), or -1 for the default (sweeps: measured faster at
+ * 128^3).  Both run the same line
+ * reconstructions (modes equal up to rounding); order 2 (minmod) always runs
+ * per zone.  ader_autotune also picks
+ * it; ader_get_recon returns the mode in use. */
+enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1 };
+int ader_set_recon(ader_ctx* ctx, int mode);
+int ader_get_recon(ader_ctx* ctx, int* mode_out);
 
 #ifdef __cplusplus
 }

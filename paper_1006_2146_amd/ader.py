@@ -32,8 +32,9 @@ EXPORTS = [
     "ader_device_bytes", "ader_strerror", "ader_destroy",
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
-    "ader_set_launch", "ader_set_layout", "ader_get_layout",
+    "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
 ]
+ADER_RECON_SWEEPS, ADER_RECON_TILED = 0, 1
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
 LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
@@ -96,6 +97,8 @@ def load():
         "ader_set_launch": ([P, ctypes.POINTER(I), ctypes.POINTER(I)], I),
         "ader_set_layout": ([P, I], I),
         "ader_get_layout": ([P, ctypes.POINTER(I)], I),
+        "ader_set_recon": ([P, I], I),
+        "ader_get_recon": ([P, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -285,6 +288,16 @@ def ader_set_layout(ctx, layout):
 def ader_get_layout(ctx):
     out = ctypes.c_int()
     _check(load().ader_get_layout(ctx, ctypes.byref(out)), "ader_get_layout")
+    return out.value
+
+
+def ader_set_recon(ctx, mode):
+    _check(load().ader_set_recon(ctx, mode), "ader_set_recon")
+
+
+def ader_get_recon(ctx):
+    out = ctypes.c_int()
+    _check(load().ader_get_recon(ctx, ctypes.byref(out)), "ader_get_recon")
     return out.value
 
 

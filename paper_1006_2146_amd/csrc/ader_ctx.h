@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/ader.h"
+#include "recon_tile.h"
 #include "zone_ops.h"
 
 namespace ader {
@@ -93,6 +94,11 @@ struct ader_ctx {
   ader::LaunchShape shape[ader::kNumClasses] = {{256, 8}, {256, 8}, {128, 4}, {256, 8}, {256, 8}};
   // predictor layout: -1 the variant's default, else an ADER_LAYOUT_*
   int layout = -1;
+  // reconstruction: -1 default, else an ADER_RECON_*; tiles of kTile^3
+  // zones, problem p's tiles at tile_base[p] .. tile_base[p+1]-1
+  int recon_mode = -1;
+  long long* d_tile_base = nullptr;
+  long long ntiles = 0;
   // stage timing: events recorded around each stage while enabled
   bool timing = false;
   std::vector<hipEvent_t> events;

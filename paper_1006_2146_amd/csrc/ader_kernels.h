@@ -7,6 +7,7 @@
 
 #include "ader_ctx.h"
 #include "lane_split.h"
+#include "recon_tile.h"
 #include "zone_ops.h"
 
 namespace ader {
@@ -64,6 +65,34 @@ __global__ void __launch_bounds__(256) k_weno_sweep(const double* __restrict__ U
   for_zones(b, [&](const Problem& pr, int, long long n) {
     weno_sweep_zone<T, M, AXIS, NVAR>(U, W, grid_of(pr, b), n);
   });
+}
+
+// Tiled reconstruction: tiles in the same XCD-aware order as for_zones (the
+// tile range cut into one region per XCD, blocks of an XCD walking theirs),
+// so neighbouring tiles, which share halo zones, run on the same L2.
+template <class T, int M, int NVAR>
+__global__ void __launch_bounds__(256) k_recon_tile(const double* __restrict__ U,
+                                                    T* __restrict__ W, Batch b,
+                                                    const long long* __restrict__ tile_base) {
+  using RT = ReconTile<T, M, NVAR>;
+  __shared__ double su[RT::kSu];
+  __shared__ T sx[RT::kSx];
+  __shared__ T sy[RT::kSy];
+  const long long ntiles = tile_base[b.np];
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long lo = ntiles * x / nreg, hi = ntiles * (x + 1) / nreg;
+  for (long long t = lo + r; t < hi; t += nb) {
+    const int p = problem_of_tile(tile_base, b.np, t);
+    const Problem pr = b.P[p];
+    const long long lt = t - tile_base[p];
+    const int ntx = (pr.nx + kTile - 1) / kTile, nty = (pr.ny + kTile - 1) / kTile;
+    const int tx = (int)(lt % ntx), ty = (int)((lt / ntx) % nty);
+    const int tz = (int)(lt / ((long long)ntx * nty));
+    RT::run(U, W, grid_of(pr, b), tx * kTile, ty * kTile, tz * kTile, su, sx, sy);
+  }
 }
 
 template <class T, int NVAR>

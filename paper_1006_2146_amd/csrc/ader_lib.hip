@@ -135,6 +135,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)c->riemann;
   k = k * 3 + (unsigned long long)c->precision;
   k = k * 3 + (unsigned long long)(c->layout + 1);
+  k = k * 3 + (unsigned long long)(c->recon_mode + 1);
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
@@ -238,7 +239,8 @@ void free_buffers(ader_ctx* c) {
   if (c->owns_U && c->U) (void)hipFree(c->U);
   if (c->owns_B && c->B) (void)hipFree(c->B);
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
-                  (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs})
+                  (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs,
+                  (void*)c->d_tile_base})
     if (p) (void)hipFree(p);
 }
 
@@ -310,7 +312,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
                       hipMalloc(&c->E, s3) == hipSuccess)) &&
             hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
             hipMalloc(&c->d_rate, sizeof(unsigned long long) * n) == hipSuccess &&
-            hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess;
+            hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess &&
+            hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess;
   if (!ok) {
     free_buffers(c);
     delete c;
@@ -318,7 +321,17 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     return ADER_ENOMEM;
   }
   c->bytes = sU + sW + sPK + sF + sM + sP + 2 * sD + sizeof(int) * n;
-  if (hipMemcpy(c->d_probs, c->probs.data(), sP, hipMemcpyHostToDevice) != hipSuccess ||
+  // reconstruction tiles of kTile^3 zones per problem
+  std::vector<long long> tile_base(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const Problem& pr = c->probs[q];
+    tile_base[q + 1] = tile_base[q] + (long long)((pr.nx + kTile - 1) / kTile) *
+                                          ((pr.ny + kTile - 1) / kTile) * ((pr.nz + kTile - 1) / kTile);
+  }
+  c->ntiles = tile_base[n];
+  if (hipMemcpy(c->d_tile_base, tile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_probs, c->probs.data(), sP, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_dt, 0, sD) != hipSuccess ||
       hipMemset(c->d_rate, 0, sizeof(unsigned long long) * n) != hipSuccess ||
       hipMemset(c->d_bad, 0, sizeof(int) * n) != hipSuccess ||
@@ -423,12 +436,17 @@ int autotune(ader_ctx* c, int reps) {
     LaunchShape best = c->shape[cls];
     int best_layout = c->layout;
     float best_ms = 1e30f;
-    // the predictor also tries both layouts where the lane-split one is built
-    const int nlayouts = cls == kClassPredict ? kNumLayouts : 1;
+    // the predictor also tries its layouts, the reconstruction its modes
+    int best_recon = c->recon_mode;
+    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 2 : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
       if (cls == kClassPredict) {
         if (!layout_built(c, s, lay)) continue;
         c->layout = lay;
+      }
+      if (cls == kClassRecon) {
+        if (lay == ADER_RECON_TILED && c->order < 3) continue;
+        c->recon_mode = lay;
       }
       for (const LaunchShape& cand : kCandidates) {
         c->shape[cls] = cand;
@@ -440,11 +458,13 @@ int autotune(ader_ctx* c, int reps) {
           best_ms = ms;
           best = cand;
           best_layout = c->layout;
+          best_recon = c->recon_mode;
         }
       }
     }
     c->shape[cls] = best;
     c->layout = best_layout;
+    c->recon_mode = best_recon;
   }
   c->timing = timing;
   // restore the state, dt and clear the flags the trial steps may have set
@@ -678,6 +698,19 @@ int ader_set_layout(ader_ctx* c, int layout) {
     return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_ZONE2 && c->order > 3) return ADER_EUNSUPPORTED;
   c->layout = layout;
+  return ADER_OK;
+}
+
+int ader_set_recon(ader_ctx* c, int mode) {
+  if (!c || (mode != -1 && mode != ADER_RECON_SWEEPS && mode != ADER_RECON_TILED)) return ADER_EINVAL;
+  c->recon_mode = mode;
+  return ADER_OK;
+}
+
+int ader_get_recon(ader_ctx* c, int* mode_out) {
+  if (!c || !mode_out) return ADER_EINVAL;
+  *mode_out = (c->order >= 3 && c->recon_mode == ADER_RECON_TILED) ? ADER_RECON_TILED
+                                                                   : ADER_RECON_SWEEPS;
   return ADER_OK;
 }
 

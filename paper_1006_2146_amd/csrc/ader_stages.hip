@@ -27,6 +27,14 @@ int sweeps(ader_ctx* c, const double* src, T* W) {
   const Batch b = c->batch();
   const unsigned g = grid_for(c, kClassRecon);
   const int bs = c->shape[kClassRecon].block;
+  if constexpr (kOrder >= 3) {
+    if (c->recon_mode == ADER_RECON_TILED) {
+      const long long cap = (long long)c->shape[kClassRecon].blocks_per_cu * c->num_cus;
+      const unsigned gt = (unsigned)(c->ntiles < cap ? c->ntiles : cap);
+      k_recon_tile<T, kOrder, NVAR><<<gt, bs, 0, c->stream>>>(src, W, b, c->d_tile_base);
+      return launched();
+    }
+  }
   if constexpr (kOrder == 2) {
     k_minmod<T, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
   } else {

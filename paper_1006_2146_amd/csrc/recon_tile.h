@@ -1,0 +1,147 @@
+// Reconstruction on LDS tiles (device only): the x, y and z sweeps of the
+// centred WENO reconstruction (Sec. II.1; the reading of all M-zone
+// stencils, x -> y -> z) for a tile of 8 x 8 x 8 zones in one kernel.  The
+// zone averages of the tile and its halo of M-1 zones are staged in LDS; the
+// x sweep runs on the tile widened by the halo in y and z, the y sweep on
+// the tile widened in z, the z sweep on the tile, each reading the previous
+// sweep's moments from LDS, and every moment is written to HBM once.  Each
+// line is reconstructed by the same weno1d on the same inputs as in the
+// one-sweep-per-kernel path; the compiler may contract its multiply-adds
+// differently in the two kernels, so the modes agree to rounding.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "zone_ops.h"
+
+namespace ader {
+
+constexpr int kTile = 8;   // zones per tile edge
+
+// (a, b) with b >= 1 and a + b <= M - 1, in the order a, then b
+template <int M>
+__host__ __device__ constexpr int ymoment_slot(int a, int b) {
+  int s = 0;
+  for (int aa = 0; aa <= M - 2; ++aa)
+    for (int bb = 1; aa + bb <= M - 1; ++bb) {
+      if (aa == a && bb == b) return s;
+      ++s;
+    }
+  return -1;
+}
+
+// Tiles of problem p: tile_base[p] .. tile_base[p+1]-1; tile t -> (p, tx, ty, tz)
+__device__ __forceinline__ int problem_of_tile(const long long* __restrict__ tile_base, int np,
+                                               long long t) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_base[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class T, int M, int NVAR>
+struct ReconTile {
+  static constexpr int R = M - 1;
+  static constexpr int EX = kTile + 2 * R, EY = kTile + 2 * R, EZ = kTile + 2 * R;
+  static constexpr int NXF = M - 1;             // x-moment fields a = 1..M-1
+  static constexpr int NYF = M * (M - 1) / 2;   // y-moment fields (a, b), b >= 1
+  static constexpr int kSu = EZ * EY * EX;
+  static constexpr int kSx = NXF * EZ * EY * kTile;
+  static constexpr int kSy = NYF * EZ * kTile * kTile;
+
+  // One tile: origin (i0, j0, k0) of problem g; su, sx, sy in LDS.
+  __device__ static void run(const double* __restrict__ U, T* __restrict__ W, const Grid& g,
+                             int i0, int j0, int k0, double* su, T* sx, T* sy) {
+    for (int v = 0; v < NVAR; ++v) {
+      const double* Uv = U + (long long)v * g.S;
+      for (int e = threadIdx.x; e < kSu; e += blockDim.x) {
+        const int x = e % EX, y = (e / EX) % EY, z = e / (EX * EY);
+        su[e] = Uv[zone_of(wrap(i0 + x - R, g.nx), wrap(j0 + y - R, g.ny), wrap(k0 + z - R, g.nz), g)];
+      }
+      __syncthreads();
+      // x sweep on kTile x EY x EZ: moments (a, 0, 0)
+      for (int e = threadIdx.x; e < kTile * EY * EZ; e += blockDim.x) {
+        const int x = e % kTile, y = (e / kTile) % EY, z = e / (kTile * EY);
+        const double* row = su + (z * EY + y) * EX + x;
+        const double c = row[R];
+        T d[2 * M - 1];
+#pragma unroll
+        for (int q = 0; q < 2 * M - 1; ++q) d[q] = T(row[q] - c);
+        T m[M];
+        weno1d<T, M>(d, m);
+        const bool inside = y >= R && y < R + kTile && z >= R && z < R + kTile &&
+                            i0 + x < g.nx && j0 + y - R < g.ny && k0 + z - R < g.nz;
+        const long long n = inside ? zone_of(i0 + x, j0 + y - R, k0 + z - R, g) : 0;
+#pragma unroll
+        for (int a = 1; a <= M - 1; ++a) {
+          sx[(((a - 1) * EZ + z) * EY + y) * kTile + x] = m[a];
+          if (inside) W[((long long)(spatial_mode(a, 0, 0) - 1) * NVAR + v) * g.S + n] = m[a];
+        }
+      }
+      __syncthreads();
+      // y sweep on kTile x kTile x EZ of the fields (a, 0), a <= M-2: (a, b, 0)
+      for (int e = threadIdx.x; e < kTile * kTile * EZ; e += blockDim.x) {
+        const int x = e % kTile, y = (e / kTile) % kTile, z = e / (kTile * kTile);
+        const bool inside = z >= R && z < R + kTile && i0 + x < g.nx && j0 + y < g.ny &&
+                            k0 + z - R < g.nz;
+        const long long n = inside ? zone_of(i0 + x, j0 + y, k0 + z - R, g) : 0;
+#pragma unroll
+        for (int a = 0; a <= M - 2; ++a) {
+          T d[2 * M - 1];
+          if (a == 0) {
+            const double c = su[(z * EY + y + R) * EX + x + R];
+#pragma unroll
+            for (int q = 0; q < 2 * M - 1; ++q) d[q] = T(su[(z * EY + y + q) * EX + x + R] - c);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 2 * M - 1; ++q) d[q] = sx[(((a - 1) * EZ + z) * EY + y + q) * kTile + x];
+          }
+          T m[M];
+          weno1d<T, M>(d, m);
+#pragma unroll
+          for (int bb = 1; bb <= M - 1 - a; ++bb) {
+            sy[((ymoment_slot<M>(a, bb) * EZ + z) * kTile + y) * kTile + x] = m[bb];
+            if (inside) W[((long long)(spatial_mode(a, bb, 0) - 1) * NVAR + v) * g.S + n] = m[bb];
+          }
+        }
+      }
+      __syncthreads();
+      // z sweep on the tile of the fields (a, b, 0), a + b <= M-2: (a, b, c)
+      for (int e = threadIdx.x; e < kTile * kTile * kTile; e += blockDim.x) {
+        const int x = e % kTile, y = (e / kTile) % kTile, z = e / (kTile * kTile);
+        const bool inside = i0 + x < g.nx && j0 + y < g.ny && k0 + z < g.nz;
+        if (!inside) continue;
+        const long long n = zone_of(i0 + x, j0 + y, k0 + z, g);
+#pragma unroll
+        for (int a = 0; a <= M - 2; ++a)
+#pragma unroll
+          for (int bb = 0; a + bb <= M - 2; ++bb) {
+            T d[2 * M - 1];
+            if (a == 0 && bb == 0) {
+              const double c = su[((z + R) * EY + y + R) * EX + x + R];
+#pragma unroll
+              for (int q = 0; q < 2 * M - 1; ++q) d[q] = T(su[((z + q) * EY + y + R) * EX + x + R] - c);
+            } else if (bb == 0) {
+#pragma unroll
+              for (int q = 0; q < 2 * M - 1; ++q)
+                d[q] = sx[(((a - 1) * EZ + z + q) * EY + y + R) * kTile + x];
+            } else {
+#pragma unroll
+              for (int q = 0; q < 2 * M - 1; ++q)
+                d[q] = sy[((ymoment_slot<M>(a, bb) * EZ + z + q) * kTile + y) * kTile + x];
+            }
+            T m[M];
+            weno1d<T, M>(d, m);
+#pragma unroll
+            for (int cc = 1; cc <= M - 1 - a - bb; ++cc)
+              W[((long long)(spatial_mode(a, bb, cc) - 1) * NVAR + v) * g.S + n] = m[cc];
+          }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+}  // namespace ader

@@ -218,7 +218,9 @@ def mhd_random_field(shape, seed=2146, gamma=5.0 / 3.0, n_modes=16, kmax=4, b_rm
     rng = np.random.default_rng(seed)
     modes = [(rng.normal(size=3), k, ph) for k, ph in _random_modes(rng, n_modes, kmax)]
     B = curl_of_edges(_edge_integrals(shape, modes), shape)
-    B *= b_rms / np.sqrt((B * B).sum(axis=0).mean())
+    rms = np.sqrt((B * B).sum(axis=0).mean())
+    if rms > 0:        # a mesh too small to carry a curl field (1 zone) keeps B = 0
+        B *= b_rms / rms
     nz, ny, nx = shape
     X = _centres(nx)[None, None, :]
     Y = _centres(ny)[None, :, None]

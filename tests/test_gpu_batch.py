@@ -3,8 +3,9 @@ of uneven sizes advance with one persistent launch per stage, each with its
 own CFL dt.  Every zone's arithmetic is the same as in a lone run, so a
 problem of a batch must match its solo run bit for bit, whatever the launch
 shapes and in graph mode as eagerly.  The autotuner may also switch the
-predictor layout, which changes rounding order only: its result must match,
-bit for bit, a run forced to the layout it chose."""
+predictor layout and the reconstruction mode, which change rounding only: its
+result must match, bit for bit, a run forced to the layout and mode it
+chose."""
 
 import numpy as np
 import pytest
@@ -32,10 +33,12 @@ def _states(shapes, mhd=False):
     return out
 
 
-def _solo(shape, U, B, steps, cfl=0.3, layout=None, **kw):
+def _solo(shape, U, B, steps, cfl=0.3, layout=None, recon=None, **kw):
     with ader.Solver(shape, **kw) as s:
         if layout is not None:
             ader.ader_set_layout(s.ctx, layout)
+        if recon is not None:
+            ader.ader_set_recon(s.ctx, recon)
         s.set_state(U, B)
         dts = []
         for _ in range(steps):
@@ -46,7 +49,7 @@ def _solo(shape, U, B, steps, cfl=0.3, layout=None, **kw):
 
 
 def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=False,
-               launch=None, layout=None, **kw):
+               launch=None, layout=None, recon=None, **kw):
     with ader.BatchSolver(shapes, stream=stream, **kw) as b:
         for i, (U, B) in enumerate(states):
             b.set_state(i, U, B)
@@ -54,6 +57,8 @@ def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=Fa
             ader.ader_set_launch(b.ctx, launch)
         if layout is not None:
             ader.ader_set_layout(b.ctx, layout)
+        if recon is not None:
+            ader.ader_set_recon(b.ctx, recon)
         if tune:
             ader.ader_autotune(b.ctx, 2)
         if graph:
@@ -64,6 +69,7 @@ def _batch_run(shapes, states, steps, cfl=0.3, graph=False, stream=None, tune=Fa
         res = [b.get_state(i) for i in range(len(shapes))]
         shapes_used = ader.ader_get_launch(b.ctx)
         shapes_used["layout"] = ader.ader_get_layout(b.ctx)
+        shapes_used["recon_mode"] = ader.ader_get_recon(b.ctx)
     res = [r if isinstance(r, tuple) else (r, None) for r in res]
     return res, np.array(dts), shapes_used
 
@@ -110,7 +116,7 @@ def test_launch_shapes_graph_and_autotune_do_not_change_results():
                     "update": (64, 64)}):
         say("launch", launch)
         got, dts, used = _batch_run(SHAPES, states, 3, launch=launch, **kw)
-        assert {k: v for k, v in used.items() if k != "layout"} == launch
+        assert {k: v for k, v in used.items() if k not in ("layout", "recon_mode")} == launch
         assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref)) and np.array_equal(dts, rdts)
     say("graph")
     got, dts, _ = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream, **kw)
@@ -119,7 +125,7 @@ def test_launch_shapes_graph_and_autotune_do_not_change_results():
     got, dts, used = _batch_run(SHAPES, states, 3, graph=True, stream=stream.cuda_stream,
                                 tune=True, **kw)
     say("tuned shapes", used)
-    ref2, rdts2, _ = _batch_run(SHAPES, states, 3, layout=used["layout"], **kw)
+    ref2, rdts2, _ = _batch_run(SHAPES, states, 3, layout=used["layout"], recon=used["recon_mode"], **kw)
     assert all(np.array_equal(a[0], b[0]) for a, b in zip(got, ref2)) and np.array_equal(dts, rdts2)
     # and within FP32 rounding of the default layout
     for a, b in zip(got, ref):
@@ -189,6 +195,7 @@ def test_config4_ensemble_full_size():
             b.set_state(i, U)
         ader.ader_autotune(b.ctx, 2)
         layout = ader.ader_get_layout(b.ctx)
+        recon = ader.ader_get_recon(b.ctx)
         ader.ader_set_graph(b.ctx, True)
         for _ in range(3):
             b.step_cfl(0.3)
@@ -198,7 +205,7 @@ def test_config4_ensemble_full_size():
         dts = b.dts()
     for i in pick:
         say("config4 solo", i, shapes[i])
-        (Us, _), sdts = _solo(shapes[i], ens[i][1], None, 3, layout=layout, order=3,
+        (Us, _), sdts = _solo(shapes[i], ens[i][1], None, 3, layout=layout, recon=recon, order=3,
                               precision=ader.ADER_MIXED)
         assert np.array_equal(got[i], Us), i
         assert dts[i] == sdts[-1]
@@ -218,3 +225,34 @@ def test_config4_ensemble_full_size():
                 :, :, :, np.arange(o[2], o[2] + 3) % n[2]]
             err = np.abs(sub - ref).sum(axis=(1, 2, 3)) / np.abs(ref).sum(axis=(1, 2, 3))
             assert np.all(err <= 1e-12), (i, err)
+
+
+@pytest.mark.parametrize("system", ["euler", "mhd"])
+@pytest.mark.parametrize("precision", [ader.ADER_FP64, ader.ADER_MIXED])
+@pytest.mark.parametrize("order", [3, 4])
+def test_tiled_reconstruction_equals_sweeps(order, precision, system):
+    # the LDS-tiled reconstruction runs the same line reconstructions as the
+    # one-kernel-per-sweep path: whole steps agree to rounding (multiply-adds
+    # may be contracted differently), on ragged problems smaller and larger
+    # than a tile
+    shapes = [(9, 14, 21), (1, 1, 1), (5, 3, 17), (16, 16, 16), (2, 9, 1)]
+    mhd = system == "mhd"
+    states = _states(shapes, mhd=mhd)
+    kw = dict(order=order, precision=precision)
+    if mhd:
+        kw.update(gamma=5.0 / 3.0, system=ader.ADER_MHD)
+    out = {}
+    for mode in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_TILED):
+        say("recon mode", mode, order, precision, system)
+        with ader.BatchSolver(shapes, **kw) as b:
+            ader.ader_set_recon(b.ctx, mode)
+            assert ader.ader_get_recon(b.ctx) == mode
+            for i, (U, B) in enumerate(states):
+                b.set_state(i, U, B)
+            for _ in range(2):
+                b.step_cfl(0.3)
+            out[mode] = [b.get_state(i) for i in range(len(shapes))]
+    tol = 1e-14 if precision == ader.ADER_FP64 else 1e-7
+    for a, c in zip(out[ader.ADER_RECON_SWEEPS], out[ader.ADER_RECON_TILED]):
+        for x, y in (zip(a, c) if mhd else [(a, c)]):
+            assert np.abs(x - y).max() <= tol * np.abs(x).max()
