@@ -158,6 +158,60 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
     }
 
 
+def run_turbulent(ader, torch, steps, warmup):
+    """384^3 turbulent-like MHD, order 4, linearized flux, CT, FP32 bulk with
+    FP64 update: graph-replayed CFL steps with the launch configuration tuned
+    on the 128^3 MHD run (tuning at this size would take minutes)."""
+    from paper_1006_2146_amd import workloads
+    shape = (384, 384, 384)
+    t0 = time.perf_counter()
+    U0, B0 = workloads.turbulent_mhd(shape)
+    log("turbulent MHD generated in %.1f s" % (time.perf_counter() - t0))
+    zones = int(np.prod(shape))
+    stream = torch.cuda.Stream()
+    s = ader.Solver(shape, order=4, riemann=ader.ADER_LINEARIZED, precision=ader.ADER_MIXED,
+                    stream=stream.cuda_stream, gamma=5.0 / 3.0, system=ader.ADER_MHD)
+    try:
+        with torch.cuda.stream(stream):
+            dU = torch.from_numpy(U0).to("cuda")
+            dB = torch.from_numpy(B0).to("cuda")
+        stream.synchronize()
+        del U0, B0
+        ader.ader_bind_device_state(s.ctx, dU.data_ptr(), dB.data_ptr())
+        cfg = TUNE.saved.get("mhd-o4-mixed-lin")
+        if cfg:
+            ader.ader_set_launch(s.ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
+            ader.ader_set_layout(s.ctx, cfg["layout"])
+            ader.ader_set_recon(s.ctx, cfg["recon"])
+        ader.ader_set_graph(s.ctx, True)
+        for _ in range(warmup):
+            s.step_cfl(CFL)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(CFL)
+        s.synchronize()
+        t1 = time.perf_counter()
+        ader.ader_set_timing(s.ctx, True)
+        s.step_cfl(CFL)
+        stages = ader.ader_stage_times(s.ctx)
+        ader.ader_set_timing(s.ctx, False)
+        s.synchronize()
+        out = {"workload": "turbulent-mhd-384^3: 64-mode k^-5/3 velocity (rms Mach 1) and vector "
+                           "potential, rho 1, P 0.6, rms |B| 1; order 4 modal, linearized, CT, "
+                           "gamma 5/3, FP32 bulk / FP64 update",
+               "zones": zones, "steps": steps,
+               "zone_updates_per_s": zones * steps / (t1 - t0), "ms_per_step": 1e3 * (t1 - t0) / steps,
+               "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
+               "device_gb": ader.ader_device_bytes(s.ctx) / 1e9,
+               "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(s.ctx)],
+               "finite": bool(torch.isfinite(dU).all().item())}
+    finally:
+        s.close()
+    log("turbulent MHD %.3e zone-updates/s" % out["zone_updates_per_s"])
+    return out
+
+
 def run_ensemble(ader, torch, steps, warmup):
     """The batched ensemble: 64 uneven problems, order 3, HLL, mixed
     precision, one persistent launch per stage, graph-replayed, autotuned."""
@@ -268,6 +322,8 @@ def main():
                          "(HLL), fp64-lin, mixed-lin (linearized); '' for none")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-problem batched ensemble")
+    ap.add_argument("--no-turbulent", action="store_true",
+                    help="skip the 384^3 turbulent MHD run (order 4, linearized, mixed)")
     ap.add_argument("--tune-file", default=None,
                     help="reuse the launch shapes and layouts in this file if it exists, "
                          "else autotune and write them there")
@@ -339,6 +395,11 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % nbytes)
 
+    turbulent = None
+    if not args.no_turbulent and args.mhd_variants:
+        log("turbulent MHD 384^3")
+        turbulent = run_turbulent(ader, torch, max(2, min(args.steps, 5)), 1)
+
     ensemble = None
     if not args.no_ensemble:
         log("batched ensemble")
@@ -387,6 +448,7 @@ def main():
                                      "HLL, or linearized (-lin)",
                          **mhd_variants},
         "ensemble": ensemble,
+        "turbulent_mhd": turbulent,
     }
     if "mixed-hll" in variants and "fp64-hll" in variants:
         out["mixed_over_fp64"] = (variants["mixed-hll"]["zone_updates_per_s"] /

@@ -67,7 +67,10 @@ typedef struct {
 
 /* Create a context on HIP device `device` with `stream` (a hipStream_t, or
  * NULL).  Defaults: gamma 1.4, order 3 modal, HLL, FP64.  Allocates the
- * state and the work buffers of the largest order.  Returns ADER_EINVAL for
+ * state, fluxes and per-problem scalars; the work arrays (modes, side
+ * packets) are allocated at the first step for the order and precision then
+ * set, and grown if a later setting needs more (a step may so return
+ * ADER_ENOMEM).  Returns ADER_EINVAL for
  * a bad mesh or system, ADER_ENOMEM / ADER_EDEVICE on HIP failures. */
 int ader_create(const ader_mesh* mesh, int system, int device, void* stream,
                 ader_ctx** out);
@@ -143,7 +146,8 @@ enum { ADER_STAGE_DT = 0, ADER_STAGE_RECON = 1, ADER_STAGE_PREDICT = 2,
 int ader_set_timing(ader_ctx* ctx, int enable);
 int ader_stage_times(ader_ctx* ctx, double* ms_out, int* counts_out);
 
-/* Bytes of device memory the context holds (state + work buffers). */
+/* Bytes of device memory the context holds now (state, fluxes, scalars and
+ * the work arrays allocated so far). */
 int ader_device_bytes(ader_ctx* ctx, double* bytes_out);
 
 /* Static description of an error code. */

@@ -90,7 +90,9 @@ struct ader_ctx {
   bool have_state = false;
   std::vector<char> set_flags;     // problems given a state by ader_batch_set_state
   bool have_dt = false;
-  size_t bytes = 0;
+  size_t bytes = 0;          // device bytes held: fixed part plus work arrays
+  size_t fixed_bytes = 0;
+  size_t work_bytes[4] = {0, 0, 0, 0};   // W, PK, WB, BN as allocated
   ader::LaunchShape shape[ader::kNumClasses] = {{256, 8}, {256, 8}, {128, 4}, {256, 8}, {256, 8}};
   // predictor layout: -1 the variant's default, else an ADER_LAYOUT_*
   int layout = -1;

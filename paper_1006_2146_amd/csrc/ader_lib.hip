@@ -128,6 +128,44 @@ int queue_step(ader_ctx* c) {
   return s->update(c);
 }
 
+void drop_graph(ader_ctx* c);
+
+// Work arrays for the current order and precision: W (modes 2..L_S of the 5
+// hydro variables), PK (six side packets), and for MHD WB (modes of the zone
+// field) and BN (its Sec. III normal moments), in the bulk type (double or
+// float).  Grown (freed and allocated again) when a setting needs more; never
+// called while a stream capture is open.
+int ensure_work(ader_ctx* c) {
+  const size_t Z = (size_t)c->S;
+  const size_t t = c->precision == ADER_FP64 ? sizeof(double) : sizeof(float);
+  const size_t ls = c->order == 2 ? 4 : c->order == 3 ? 10 : 20;
+  const bool mhd = c->system == ADER_MHD;
+  const size_t need[4] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
+                          mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0};
+  void** buf[4] = {&c->W, &c->PK, &c->WB, &c->BN};
+  for (int q = 0; q < 4; ++q) {
+    if (need[q] <= c->work_bytes[q]) continue;
+    if (*buf[q]) {
+      // a captured step holds the old address: rebuild it on its next use
+      ADER_TRY(check(hipStreamSynchronize(c->stream)));
+      drop_graph(c);
+      (void)hipFree(*buf[q]);
+      *buf[q] = nullptr;
+      c->work_bytes[q] = 0;
+    }
+    if (hipMalloc(buf[q], need[q]) != hipSuccess) {
+      *buf[q] = nullptr;
+      (void)hipGetLastError();
+      c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] +
+                 c->work_bytes[3];
+      return ADER_ENOMEM;
+    }
+    c->work_bytes[q] = need[q];
+  }
+  c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] + c->work_bytes[3];
+  return ADER_OK;
+}
+
 // Everything a captured step depends on besides the device buffers' contents.
 unsigned long long config_key(const ader_ctx* c) {
   unsigned long long k = (unsigned long long)c->order;
@@ -140,6 +178,8 @@ unsigned long long config_key(const ader_ctx* c) {
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
   k ^= (unsigned long long)(uintptr_t)c->B * 0xc2b2ae3d27d4eb4full;
+  k ^= (unsigned long long)(uintptr_t)c->W * 0xd6e8feb86659fd93ull;
+  k ^= (unsigned long long)(uintptr_t)c->PK * 0xa0761d6478bd642full;
   unsigned long long g;
   std::memcpy(&g, &c->gamma, sizeof g);
   return k ^ (g * 0x165667b19e3779f9ull);
@@ -154,6 +194,7 @@ void drop_graph(ader_ctx* c) {
 // first use and whenever the configuration, cfl or bound buffers change),
 // launched eagerly otherwise or while stage timing is on.
 int run_step_cfl(ader_ctx* c, double cfl) {
+  ADER_TRY(ensure_work(c));
   if (!c->use_graph || c->timing) {
     ADER_TRY(queue_dt(c, cfl));
     return queue_step(c);
@@ -293,21 +334,17 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)
     c->num_cus = cus;
-  // buffers sized for the largest case: order 4 and double work arrays
+  // state, fluxes and per-problem scalars now; the work arrays (modes,
+  // packets) are sized for the order and precision in use at the first step
   const bool mhd = system == ADER_MHD;
   const size_t Z = (size_t)S;
   const size_t sU = sizeof(double) * 5 * Z;
-  const size_t sW = sizeof(double) * 19 * 5 * Z;
-  const size_t sPK = sizeof(double) * 6 * (mhd ? kMhdSlots : 15) * Z;
   const size_t sF = sizeof(double) * 3 * 5 * Z;
   const size_t s3 = sizeof(double) * 3 * Z;
-  const size_t sM = mhd ? s3 * (1 + 1 + 19 + 3 + 4 + 1) : 0;  // B, B0, WB, BN, FE, E
+  const size_t sM = mhd ? s3 * (1 + 1 + 4 + 1) : 0;  // B, B0, FE, E
   const size_t sP = sizeof(Problem) * n, sD = sizeof(double) * n;
-  bool ok = hipMalloc(&c->U, sU) == hipSuccess && hipMalloc(&c->W, sW) == hipSuccess &&
-            hipMalloc(&c->PK, sPK) == hipSuccess && hipMalloc(&c->F, sF) == hipSuccess &&
+  bool ok = hipMalloc(&c->U, sU) == hipSuccess && hipMalloc(&c->F, sF) == hipSuccess &&
             (!mhd || (hipMalloc(&c->B, s3) == hipSuccess && hipMalloc(&c->B0, s3) == hipSuccess &&
-                      hipMalloc(&c->WB, 19 * s3) == hipSuccess &&
-                      hipMalloc(&c->BN, 3 * s3) == hipSuccess &&
                       hipMalloc(&c->FE, 4 * s3) == hipSuccess &&
                       hipMalloc(&c->E, s3) == hipSuccess)) &&
             hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
@@ -320,7 +357,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     (void)hipGetLastError();
     return ADER_ENOMEM;
   }
-  c->bytes = sU + sW + sPK + sF + sM + sP + 2 * sD + sizeof(int) * n;
+  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + sizeof(int) * n + sizeof(long long) * (n + 1);
+  c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
   std::vector<long long> tile_base(n + 1, 0);
   for (int q = 0; q < n; ++q) {
@@ -409,6 +447,7 @@ int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
 int autotune(ader_ctx* c, int reps) {
   const StageFns* s = stages_of(c);
   if (!s) return ADER_EUNSUPPORTED;
+  ADER_TRY(ensure_work(c));
   const bool mhd = c->system == ADER_MHD;
   const size_t bU = sizeof(double) * 5 * (size_t)c->S, bB = sizeof(double) * 3 * (size_t)c->S;
   double *sU = nullptr, *sB = nullptr, *sdt = nullptr;
@@ -614,6 +653,7 @@ int ader_step(ader_ctx* c, double dt) {
   if (!c || !(dt > 0.0) || !std::isfinite(dt)) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
+  ADER_TRY(ensure_work(c));
   k_set_dt<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->d_dt, c->np(), dt);
   ADER_TRY(launched());
   c->have_dt = true;

@@ -323,3 +323,75 @@ def ensemble(n=64, seed=4096, sides=ENSEMBLE_SIDES):
     Returns a list of (shape, U)."""
     return [(s, random_smooth(s, seed + 1 + i))
             for i, s in enumerate(ensemble_shapes(n, seed, sides))]
+
+
+def _spectral_modes(rng, count, kmax, slope=-5.0 / 3.0):
+    """count random integer wave vectors in [-kmax, kmax]^3 \\ 0, each with a
+    random phase and a random direction of amplitude |k|^slope."""
+    ks, amps, phases = [], [], []
+    while len(ks) < count:
+        k = rng.integers(-kmax, kmax + 1, size=3)
+        if not np.any(k != 0):
+            continue
+        d = rng.normal(size=3)
+        ks.append(k)
+        amps.append(d / np.linalg.norm(d) * np.linalg.norm(k) ** slope)
+        phases.append(rng.uniform(0.0, 2.0 * np.pi))
+    return np.array(ks), np.array(amps), np.array(phases)
+
+
+def _separable_sum(shape, ks, coef, factors):
+    """Im sum_m coef_m X_m(i) Y_m(j) Z_m(k) on the mesh, one plane at a time
+    as a matrix product (factors(axis, k, n) gives the per-axis factor)."""
+    nz, ny, nx = shape
+    out = np.empty(tuple(shape))
+    FX = np.stack([factors(0, ks[m, 0], nx) for m in range(len(ks))], axis=0)   # (M, nx)
+    FY = np.stack([factors(1, ks[m, 1], ny) for m in range(len(ks))], axis=1)   # (ny, M)
+    FZ = np.stack([factors(2, ks[m, 2], nz) for m in range(len(ks))], axis=1)   # (nz, M)
+    for kz in range(nz):
+        out[kz] = ((FY * (coef * FZ[kz])[None, :]) @ FX).imag
+    return out
+
+
+def turbulent_mhd(shape, seed=384, gamma=5.0 / 3.0, n_modes=64, kmax=8, p0=0.6, mach=1.0,
+                  b_rms=1.0):
+    """Turbulent-like ideal-MHD state on the periodic unit box: velocity and
+    vector potential each from ``n_modes`` random Fourier modes (integer
+    wave vectors in [-kmax, kmax]^3, random directions, amplitudes |k|^-5/3),
+    velocity scaled to rms Mach ``mach`` at rho = 1, P = ``p0``; face B the
+    exact face fluxes of curl A (edge line integrals, Stokes), scaled to rms
+    |B| = ``b_rms``, so div B = 0 to rounding.  Velocity at zone centres.
+    Returns (U[5], B[3]).  Evaluated as sums of separable products, one
+    z-plane per matrix product, so 384^3 takes seconds."""
+    rng = np.random.default_rng(seed)
+    kv, av, pv = _spectral_modes(rng, n_modes, kmax)
+    ka, aa, pa = _spectral_modes(rng, n_modes, kmax)
+    nz, ny, nx = shape
+
+    def centre(axis, k, n):
+        x = (np.arange(n) + 0.5) / n
+        return np.exp(2j * np.pi * k * x)
+
+    v = np.stack([_separable_sum(shape, kv, av[:, c] * np.exp(1j * pv), centre) for c in range(3)])
+    rms = np.sqrt((v * v).sum(axis=0).mean())
+    v *= mach * np.sqrt(gamma * p0) / rms
+
+    # line integrals of A_c along the lower c-edges: the c-factor integrated
+    # over the zone, the other two taken at the lower corner
+    L = []
+    for c in range(3):
+        def edge(axis, k, n, c=c):
+            x = np.arange(n) / n
+            if axis != c:
+                return np.exp(2j * np.pi * k * x)
+            if k == 0:
+                return np.full(n, 1.0 / n, dtype=complex)
+            return (np.exp(2j * np.pi * k * (x + 1.0 / n)) - np.exp(2j * np.pi * k * x)) / (2j * np.pi * k)
+        L.append(_separable_sum(shape, ka, aa[:, c] * np.exp(1j * pa), edge))
+    B = curl_of_edges(np.stack(L), shape)
+    rms = np.sqrt((B * B).sum(axis=0).mean())
+    if rms > 0:
+        B *= b_rms / rms
+    rho = np.ones(tuple(shape))
+    P = np.full(tuple(shape), p0)
+    return _mhd_conserved(rho, v, P, face_mean(B), gamma), B

@@ -156,6 +156,31 @@ def test_graph_replays_match_eager_with_host_work_between():
         assert np.array_equal(g.get_state(), e.get_state())
 
 
+def test_graph_follows_order_and_precision_changes():
+    # the work arrays are sized for the order and precision in use and grown
+    # when a change needs more; the captured step must follow them
+    shape = (9, 11, 10)
+    U0 = workloads.random_smooth(shape, seed=12)
+    stream = torch.cuda.Stream()
+    seq = [(2, ader.ADER_MIXED), (3, ader.ADER_MIXED), (3, ader.ADER_FP64), (2, ader.ADER_FP64),
+           (4, ader.ADER_FP64), (4, ader.ADER_MIXED)]
+    with ader.Solver(shape, order=2) as e, \
+            ader.Solver(shape, order=2, stream=stream.cuda_stream) as g:
+        e.set_state(U0)
+        g.set_state(U0)
+        ader.ader_set_graph(g.ctx, True)
+        for order, prec in seq:
+            say("graph with order", order, "precision", prec)
+            for s in (e, g):
+                ader.ader_set_order(s.ctx, order)
+                ader.ader_set_precision(s.ctx, prec)
+            for _ in range(2):
+                e.step_cfl(0.3)
+                g.step_cfl(0.3)
+            g.synchronize()
+            assert np.array_equal(g.get_state(), e.get_state()), (order, prec)
+
+
 def test_graph_needs_a_stream():
     with ader.Solver((4, 4, 4)) as s:
         assert ader.load().ader_set_graph(s.ctx, 1) == ader.ADER_EUNSUPPORTED

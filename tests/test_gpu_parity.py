@@ -300,3 +300,46 @@ def test_layout_errors():
         assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE2
     with _solver((4, 4, 4), 4, "modal", "hll") as s:
         assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE2) == ader.ADER_EUNSUPPORTED
+
+
+# ----------------------------------------- turbulent MHD, linearized, order 4 --
+
+def test_turbulent_mhd_linearized_order4_parity():
+    # the turbulent-like MHD workload (64-mode k^-5/3 velocity and vector
+    # potential, rms Mach 1) at a size the oracle steps whole
+    U0, B0 = workloads.turbulent_mhd((10, 12, 14), seed=7)
+    _check_steps_mhd(U0, B0, 4, "modal", 2, tag="turbulent", rs="linearized")
+
+
+def test_config5_turbulent_mhd_384_mixed():
+    # 384^3 MHD, order 4, linearized flux, CT, FP32 bulk with FP64 update: one
+    # CFL step on the GPU; sampled blocks against the FP64 oracle at the
+    # mixed path's per-step accuracy, div B at round-off over the whole mesh,
+    # conserved totals, and the device memory within one GPU
+    from oracle.bweno import divergence
+    shape = (384, 384, 384)
+    say("config5 generate")
+    U0, B0 = workloads.turbulent_mhd(shape)
+    cfg = OracleConfig(order=4, gamma=G53, riemann="linearized")
+    with _mhd_solver(shape, 4, "modal", precision=ader.ADER_MIXED, rs="linearized") as s:
+        s.set_state(U0, B0)
+        say("config5 step")
+        s.step_cfl(0.3)
+        Ug, Bg = s.get_state()
+        dt = s.dt()
+        assert ader.ader_device_bytes(s.ctx) < 200e9
+    assert abs(dt - oracle_dt(U0, cfg, 0.3, B0)) <= 1e-14 * dt
+    dx = (1.0 / 384,) * 3
+    assert np.abs(divergence(Bg, dx)).max() <= 1e-12 * np.abs(Bg).max() / dx[0]
+    tot0, tot1 = U0.sum(axis=(1, 2, 3)), Ug.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(tot1 - tot0) <= 1e-12 * np.abs(U0).sum(axis=(1, 2, 3)))
+    for o in [(0, 0, 0), (200, 383, 17)]:
+        say("config5 oracle block", o)
+        Ur, Br = step_block(U0, dt, cfg, o, (2, 2, 2), B0)
+        iz = np.arange(o[0], o[0] + 2) % 384
+        iy = np.arange(o[1], o[1] + 2) % 384
+        ix = np.arange(o[2], o[2] + 2) % 384
+        pick = lambda A: A[:, iz][:, :, iy][:, :, :, ix]  # noqa: E731
+        # FP32 bulk: the step's change is resolved to ~1e-6 relative
+        assert np.all(rel_l1(pick(Ug), Ur) <= 1e-6), o
+        assert np.all(rel_l1(pick(Bg), Br) <= 1e-6), o
