@@ -26,8 +26,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SHAPE = (128, 128, 128)
 CFL = 0.3
 WORKLOAD = "sedov-modes-128^3"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan"}
+# Vector ALU peaks from the unit counts and clock: 256 CUs x 4 SIMDs x 16
+# lanes x 2 flops per FMA x 2.4 GHz = 78.6 TFLOP/s, for FP64 and for FP32 as
+# compiled here (without packed FP32 instructions, so one FP32 FMA per lane
+# per clock); the published FP32 vector figure, 157.3, counts packed FP32.
+PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
+PUBLISHED_TFLOPS = {"f64": 78.6, "f32": 157.3}
+HBM_PEAK_GBS = 8000.0
+LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
 
 
@@ -253,6 +259,33 @@ def run_ensemble(ader, torch, steps, warmup):
     return out
 
 
+# Algorithmic HBM bytes per zone of the memory-bound stages of the order-3
+# Euler step (5 variables; b = 4 bytes per bulk value in the mixed path, 8 in
+# FP64; state and fluxes always double):
+#   recon  (x, y, z WENO sweeps): U read once per sweep (3 x 40 B), the 9
+#          higher modes written once (45 b), and the moments the later
+#          sweeps read back (y reads (1,0,0): 5 b; z reads (1,0,0) and
+#          (0,1,0): 10 b);
+#   flux   three faces' two side packets (2 x 3 x 15 b), U of the zone (40 B),
+#          F written (3 x 5 doubles = 120 B);
+#   update U and the zone's own F read (40 + 120 B), U written (40 B).
+def hbm_bytes_per_zone(b):
+    return {"recon": 120 + 45 * b + 15 * b, "flux": 90 * b + 40 + 120, "update": 200}
+
+
+def hbm_stages(pv, N, dtype, probes):
+    b = 8 if dtype == "f64" else 4
+    out = {}
+    for stage, per_zone in hbm_bytes_per_zone(b).items():
+        ms = pv["stage_ms_per_step"][stage]
+        gbs = per_zone * N / (ms * 1e-3) / 1e9
+        out[stage] = {"bytes_per_zone": per_zone, "ms": ms, "achieved_gbs": gbs,
+                      "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+        if probes:
+            out[stage]["frac_of_copy"] = gbs / probes["hbm_copy_gbs"]
+    return out
+
+
 def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
     """Untimed accuracy pass of the mixed path: the FP64 path takes `steps`
     CFL steps, the mixed path repeats them with the same dt sequence, and the
@@ -327,6 +360,8 @@ def main():
     ap.add_argument("--tune-file", default=None,
                     help="reuse the launch shapes and layouts in this file if it exists, "
                          "else autotune and write them there")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the FMA and HBM-copy peak probes")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the untimed mixed-vs-FP64 accuracy pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -348,6 +383,13 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     ader.load()
+    probes = None
+    if not args.no_probes:
+        log("peak probes")
+        probes = {"fp32_fma_tflops": ader.ader_probe_peak(ader.ADER_PROBE_FP32_FMA),
+                  "fp64_fma_tflops": ader.ader_probe_peak(ader.ADER_PROBE_FP64_FMA),
+                  "hbm_copy_gbs": ader.ader_probe_peak(ader.ADER_PROBE_HBM_COPY)}
+        log("probes", probes)
     log("building the workload", SHAPE)
     U0 = workloads.sedov_modes(SHAPE)
     N = int(np.prod(SHAPE))
@@ -415,13 +457,23 @@ def main():
     kernel = {("f32", "zone"): "k_predict<float,3,0,true>",
               ("f32", "zone-prescan"): "k_predict<float,3,0,false>",
               ("f64", "zone"): "k_predict<double,3,0,true>",
-              ("f64", "zone-prescan"): "k_predict<double,3,0,false>"}.get((dtype, layout),
+              ("f64", "zone-prescan"): "k_predict<double,3,0,false>",
+              ("f32", "zone-2waves"): "k_predict<float,3,0,true,2>",
+              ("f64", "zone-2waves"): "k_predict<double,3,0,true,2>"}.get((dtype, layout),
                                                                           "k_predict (%s)" % layout)
     roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved,
                 "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_TFLOPS[dtype], "traffic": recorded_traffic(kernel),
                 "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                "flops_per_zone": flops_zone, "launch_ms": pred_ms}
+                "flops_per_zone": flops_zone, "launch_ms": pred_ms,
+                "peak_basis": "256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz; FP32 without "
+                              "packed instructions (disabled in this build)",
+                "peak_published": PUBLISHED_TFLOPS[dtype],
+                "frac_published": achieved / PUBLISHED_TFLOPS[dtype]}
+    if probes:
+        key = "fp64_fma_tflops" if dtype == "f64" else "fp32_fma_tflops"
+        roofline["peak_measured"] = probes[key]
+        roofline["frac_measured"] = achieved / probes[key]
 
     out = {
         "metric": METRIC,
@@ -443,6 +495,8 @@ def main():
                    "zones": N, "cfl": CFL, "gamma": 1.4, "steps_replayed_as": "hipGraph",
                    "launch": "autotuned"},
         "roofline": roofline,
+        "peak_probes": probes,
+        "hbm_stages": hbm_stages(pv, N, dtype, probes),
         "variants": variants,
         "mhd_variants": {"workload": "mhd-random-field-128^3, order 4 modal, CT, gamma 5/3; "
                                      "HLL, or linearized (-lin)",

@@ -213,11 +213,14 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * ADER_EUNSUPPORTED at order 2), ADER_LAYOUT_SPLIT2, the same compiled to
  * fit two waves per SIMD, ADER_LAYOUT_ZONE2, one lane per zone with the
  * facial positivity check in a pass of its own rather than inside the face
- * quadrature (orders 2 and 3 only), or -1 for the default of the setting
+ * quadrature (orders 2 and 3 only), ADER_LAYOUT_ZONE_2W, one lane per zone
+ * compiled to fit two waves per SIMD (Euler, orders 2 and 3 only), or -1 for
+ * the default of the setting
  * (split for MHD at orders 3-4 and Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
-enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3 };
+enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,
+       ADER_LAYOUT_ZONE_2W = 4 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
 
@@ -232,6 +235,20 @@ int ader_get_layout(ader_ctx* ctx, int* layout_out);
 enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1 };
 int ader_set_recon(ader_ctx* ctx, int mode);
 int ader_get_recon(ader_ctx* ctx, int* mode_out);
+
+/* Measurement support, not part of a step: the peak rates this library's
+ * code reaches on `device`, the denominators of its kernels' rooflines.
+ * ADER_PROBE_FP32_FMA and ADER_PROBE_FP64_FMA time independent FMA chains
+ * (8 per thread, 32 waves per compute unit; FP32 as this library compiles
+ * it, without packed FP32 instructions) and return TFLOP/s;
+ * ADER_PROBE_HBM_COPY times a 1 GiB device-to-device copy kernel and
+ * returns GB/s (bytes read plus bytes written).  Each takes the best of
+ * several launches on a stream of its own and synchronises; the copy
+ * allocates 2 GiB for its duration (ADER_ENOMEM if it cannot).
+ * ADER_EINVAL for an unknown kind, a device out of range or a null
+ * value_out. */
+enum { ADER_PROBE_FP32_FMA = 0, ADER_PROBE_FP64_FMA = 1, ADER_PROBE_HBM_COPY = 2 };
+int ader_probe_peak(int device, int kind, double* value_out);
 
 #ifdef __cplusplus
 }

@@ -33,9 +33,12 @@ EXPORTS = [
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
+    "ader_probe_peak",
 ]
+ADER_PROBE_FP32_FMA, ADER_PROBE_FP64_FMA, ADER_PROBE_HBM_COPY = 0, 1, 2
 ADER_RECON_SWEEPS, ADER_RECON_TILED = 0, 1
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
+ADER_LAYOUT_ZONE_2W = 4
 LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
 
@@ -99,6 +102,7 @@ def load():
         "ader_get_layout": ([P, ctypes.POINTER(I)], I),
         "ader_set_recon": ([P, I], I),
         "ader_get_recon": ([P, ctypes.POINTER(I)], I),
+        "ader_probe_peak": ([I, I, DP], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -214,6 +218,14 @@ def ader_device_bytes(ctx):
     b = ctypes.c_double()
     _check(load().ader_device_bytes(ctx, ctypes.byref(b)), "ader_device_bytes")
     return b.value
+
+
+def ader_probe_peak(kind, device=0):
+    """Measured peak of `kind` (ADER_PROBE_*): TFLOP/s for the FMA probes,
+    GB/s (read + write) for the HBM copy."""
+    v = ctypes.c_double()
+    _check(load().ader_probe_peak(device, kind, ctypes.byref(v)), "ader_probe_peak")
+    return v.value
 
 
 def ader_destroy(ctx):

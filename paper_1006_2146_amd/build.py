@@ -63,7 +63,8 @@ def _compile(src, obj, defines, verbose):
 
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
-    jobs = [(os.path.join(CSRC, "ader_lib.hip"), os.path.join(OBJ, "ader_lib.o"), [])]
+    jobs = [(os.path.join(CSRC, "ader_lib.hip"), os.path.join(OBJ, "ader_lib.o"), []),
+            (os.path.join(CSRC, "peak_probe.hip"), os.path.join(OBJ, "peak_probe.o"), [])]
     for sys_, prec, order, form in VARIANTS:
         obj = os.path.join(OBJ, "stages_%s_%s_o%d_f%d.o" % (sys_, prec, order, form))
         jobs.append((os.path.join(CSRC, "ader_stages.hip"), obj,

@@ -51,6 +51,7 @@ struct StageFns {
   int (*predict_split)(ader_ctx*);    // lane-split layout, nullptr if not built
   int (*predict_split2)(ader_ctx*);   // the same, registers capped for 2 waves/SIMD
   int (*predict_zone2)(ader_ctx*);    // one lane per zone, facial check in its own pass
+  int (*predict_zone_2w)(ader_ctx*);  // one lane per zone, registers capped for 2 waves/SIMD
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
 };

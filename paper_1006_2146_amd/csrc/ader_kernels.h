@@ -111,9 +111,10 @@ __global__ void __launch_bounds__(256) k_bface(const double* __restrict__ B, dou
   });
 }
 
-// FUSED: where the facial positivity check runs (see predict_zone)
-template <class T, int ORDER, int FORM, bool FUSED>
-__global__ void __launch_bounds__(256) k_predict(const double* __restrict__ U,
+// FUSED: where the facial positivity check runs (see predict_zone); WAVES
+// caps the registers for that many waves per SIMD
+template <class T, int ORDER, int FORM, bool FUSED, int WAVES = 1>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict(const double* __restrict__ U,
                                                  const T* __restrict__ W, T* __restrict__ PK,
                                                  Batch b, const double* __restrict__ dt,
                                                  double gam) {

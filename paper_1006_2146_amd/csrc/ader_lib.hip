@@ -90,6 +90,7 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
     case ADER_LAYOUT_SPLIT: return s->predict_split != nullptr;
     case ADER_LAYOUT_SPLIT2: return s->predict_split2 != nullptr;
     case ADER_LAYOUT_ZONE2: return s->predict_zone2 != nullptr;
+    case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w != nullptr;
   }
   return false;
 }
@@ -105,6 +106,7 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_SPLIT: return s->predict_split(c);
     case ADER_LAYOUT_SPLIT2: return s->predict_split2(c);
     case ADER_LAYOUT_ZONE2: return s->predict_zone2(c);
+    case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w(c);
     default: return s->predict(c);
   }
 }
@@ -415,7 +417,7 @@ int get_problem(ader_ctx* c, int q, double* U, double* B) {
 // of that stage alone) and keep the fastest.  The state is saved first and
 // restored at the end, so tuning does not advance the solution.
 // ---------------------------------------------------------------------------
-constexpr int kNumLayouts = 4;
+constexpr int kNumLayouts = 5;
 constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
                                        {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
 
@@ -737,6 +739,8 @@ int ader_set_layout(ader_ctx* c, int layout) {
   if ((layout == ADER_LAYOUT_SPLIT || layout == ADER_LAYOUT_SPLIT2) && c->order < 3)
     return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_ZONE2 && c->order > 3) return ADER_EUNSUPPORTED;
+  if (layout == ADER_LAYOUT_ZONE_2W && (c->order > 3 || c->system == ADER_MHD))
+    return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;
 }

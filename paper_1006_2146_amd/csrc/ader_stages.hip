@@ -58,8 +58,9 @@ int recon(ader_ctx* c) {
   return ADER_OK;
 }
 
-// one lane per zone; FUSED: facial positivity check inside the side code
-template <bool FUSED>
+// one lane per zone; FUSED: facial positivity check inside the side code;
+// WAVES (Euler only): registers capped for that many waves per SIMD
+template <bool FUSED, int WAVES = 1>
 int predict(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassPredict);
   const int bs = c->shape[kClassPredict].block;
@@ -80,8 +81,8 @@ int predict(ader_ctx* c) {
           c->batch(), c->d_dt, c->gamma);
     }
   } else
-    k_predict<T, kOrder, kForm, FUSED><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt,
-                                                                c->gamma);
+    k_predict<T, kOrder, kForm, FUSED, WAVES><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(),
+                                                                       c->d_dt, c->gamma);
   return launched();
 }
 
@@ -137,13 +138,15 @@ int update(ader_ctx* c) {
   return launched();
 }
 
-// the one-lane-per-zone instance with a separate facial pass is built where
-// the zone layout is the likely winner (orders 2 and 3)
+// the one-lane-per-zone instances with a separate facial pass, and with two
+// waves per SIMD (Euler), are built where the zone layout is the likely
+// winner (orders 2 and 3)
 const StageFns kStages = {recon,
                           predict<true>,
                           kOrder >= 3 ? predict_split<1> : nullptr,
                           kOrder >= 3 ? predict_split<2> : nullptr,
                           kOrder <= 3 ? predict<false> : nullptr,
+                          (!kMhd && kOrder <= 3) ? predict<true, 2> : nullptr,
                           flux,
                           update};
 

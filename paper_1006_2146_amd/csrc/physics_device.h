@@ -5,6 +5,30 @@
 
 namespace ader {
 
+// 1/x for the flux evaluations: correctly rounded in double; in float on the
+// device the hardware reciprocal (within 1 ulp, one instruction where the
+// IEEE divide takes about ten), an error far below what the FP32 bulk of the
+// mixed path already carries.
+__host__ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__host__ __device__ __forceinline__ float recip(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
+// sqrt(x) for wave-speed estimates: correctly rounded in double; in float on
+// the device the hardware square root (within 1 ulp).
+__host__ __device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__host__ __device__ __forceinline__ float fsqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_sqrtf(x);
+#else
+  return sqrtf(x);
+#endif
+}
+
 template <class T>
 struct Euler {
   static constexpr int NV = 5;
@@ -12,7 +36,7 @@ struct Euler {
   // Physical flux along AXIS (0: F, 1: G, 2: H) of the conserved state u.
   template <int AXIS>
   __host__ __device__ static inline void flux(const T (&u)[5], T (&f)[5], T gam) {
-    const T rinv = T(1) / u[0];
+    const T rinv = recip(u[0]);
     const T vn = u[1 + AXIS] * rinv;
     const T ke = T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * rinv;
     const T p = (gam - T(1)) * (u[4] - ke);
@@ -41,7 +65,8 @@ struct Euler {
     T rho, m[3], v[3], h;   // density, momentum, velocity, E + p of ubar
   };
   __host__ __device__ static inline Ref make_ref(const double (&ub)[5], double gam) {
-    const double v0 = ub[1] / ub[0], v1 = ub[2] / ub[0], v2 = ub[3] / ub[0];
+    const double ir = 1.0 / ub[0];
+    const double v0 = ub[1] * ir, v1 = ub[2] * ir, v2 = ub[3] * ir;
     const double p = (gam - 1.0) * (ub[4] - 0.5 * (ub[1] * v0 + ub[2] * v1 + ub[3] * v2));
     Ref r;
     r.rho = T(ub[0]);
@@ -53,7 +78,7 @@ struct Euler {
 
   template <int AXIS>
   __host__ __device__ static inline void dflux(const Ref& r, const T (&du)[5], T (&f)[5], T gam) {
-    const T rinv = T(1) / (r.rho + du[0]);
+    const T rinv = recip(r.rho + du[0]);
     T dv[3], v[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -81,7 +106,7 @@ struct Mhd {
   // induction part is v_AXIS B - B_AXIS v (zero in the AXIS component).
   template <int AXIS>
   __host__ __device__ static inline void flux(const T (&u)[8], T (&f)[8], T gam) {
-    const T rinv = T(1) / u[0];
+    const T rinv = recip(u[0]);
     const T vx = u[1] * rinv, vy = u[2] * rinv, vz = u[3] * rinv;
     const T bx = u[5], by = u[6], bz = u[7];
     const T b2 = bx * bx + by * by + bz * bz;
@@ -129,7 +154,8 @@ struct Mhd {
     T rho, m[3], v[3], b[3], h, vb;   // ..., E + p + B^2/8pi, v.B of ubar
   };
   __host__ __device__ static inline Ref make_ref(const double (&ub)[8], double gam) {
-    const double v0 = ub[1] / ub[0], v1 = ub[2] / ub[0], v2 = ub[3] / ub[0];
+    const double ir = 1.0 / ub[0];
+    const double v0 = ub[1] * ir, v1 = ub[2] * ir, v2 = ub[3] * ir;
     const double pm = (ub[5] * ub[5] + ub[6] * ub[6] + ub[7] * ub[7]) * (1.0 / (8.0 * 3.14159265358979323846));
     const double p = (gam - 1.0) * (ub[4] - 0.5 * (ub[1] * v0 + ub[2] * v1 + ub[3] * v2) - pm);
     Ref r;
@@ -146,7 +172,7 @@ struct Mhd {
   __host__ __device__ static inline void dflux(const Ref& r, const T (&du)[8], T (&f)[8], T gam) {
     constexpr T i4p = T(1.0 / (4.0 * 3.14159265358979323846));
     constexpr T i8p = T(1.0 / (8.0 * 3.14159265358979323846));
-    const T rinv = T(1) / (r.rho + du[0]);
+    const T rinv = recip(r.rho + du[0]);
     T dv[3], v[3], b[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {

@@ -27,6 +27,43 @@
 
 namespace ader {
 
+// One zone's walk down the rows of an SoA array (row stride N): the address
+// advances by one row per access.  On the device an empty asm fences each
+// step, so the compiler keeps it as one 64-bit add instead of hoisting a
+// separate row offset per row out of the zone loop, which it cannot hold in
+// scalar registers and spills.
+template <class P>
+__host__ __device__ __forceinline__ P* next_row(P* p, long long N) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  // fenced as a global-memory pointer, so accesses through it stay global
+  __attribute__((address_space(1))) P* g = (__attribute__((address_space(1))) P*)p;
+  g += N;
+  asm("" : "+v"(g));
+  return (P*)g;
+#else
+  return p + N;
+#endif
+}
+
+// Cursor over one zone's rows of an SoA array: row(r) moves the address by
+// r - (current row) rows with next_row and returns the element, so accesses
+// in increasing row order cost one add each.
+template <class P>
+struct RowCursor {
+  P* p;
+  long long N;
+  int at;
+  __host__ __device__ RowCursor(P* base, long long stride, long long n, int row0 = 0)
+      : p(base + (long long)row0 * stride + n), N(stride), at(row0) {}
+  __host__ __device__ __forceinline__ P& row(int r) {
+    if (r != at) {
+      p = next_row(p, (long long)(r - at) * N);
+      at = r;
+    }
+    return *p;
+  }
+};
+
 // One periodic mesh inside the arrays: nx*ny*nz = N zones stored at indices
 // base .. base+N-1 of arrays whose per-variable stride is S (S = N and base =
 // 0 for a lone problem; a batch concatenates its problems).
@@ -400,18 +437,19 @@ template <class T, int NV> struct SchemeOf<2, 1, T, NV> { using type = ader_gen:
 template <class T, int NV> struct SchemeOf<3, 0, T, NV> { using type = ader_gen::SchemeM3<T, NV>; };
 template <class T, int NV> struct SchemeOf<4, 0, T, NV> { using type = ader_gen::SchemeM4<T, NV>; };
 
+// Side SIDE's packet, rows SIDE*15 .. SIDE*15+14 of PK (u_b, <u>, <F>, each
+// for the five variables); q walks the rows and is left at the next side.
 template <class S, class T, int SIDE, class Phys, class Acc>
 __host__ __device__ __forceinline__ void store_side(const T (&w)[S::LS][5], const T (&e)[S::NE][5],
-                                                    const Phys& ph, Acc& acc, T* __restrict__ PK,
-                                                    long long N, long long n) {
+                                                    const Phys& ph, Acc& acc, T*& q, long long N) {
   T ub[5], ua[5], fa[5];
   S::template side<SIDE>(w, e, ph, acc, ub, ua, fa);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    PK[((long long)(SIDE * 3 + 0) * 5 + v) * N + n] = ub[v];
-    PK[((long long)(SIDE * 3 + 1) * 5 + v) * N + n] = ua[v];
-    PK[((long long)(SIDE * 3 + 2) * 5 + v) * N + n] = fa[v];
-  }
+  for (int v = 0; v < 5; ++v) { *q = ub[v]; q = next_row(q, N); }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { *q = ua[v]; q = next_row(q, N); }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { *q = fa[v]; q = next_row(q, N); }
 }
 
 // A scan that ignores the states handed to it.
@@ -434,15 +472,21 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   using S = typename SchemeOf<ORDER, FORM, T>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[5];
+  {
+    const double* q = U + n;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
+    for (int v = 0; v < 5; ++v) { w0[v] = *q; q = next_row(q, g.S); }
+  }
   T w[LS][5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
+  {
+    const T* q = W + n;
 #pragma unroll
-  for (int m = 1; m < LS; ++m)
+    for (int m = 1; m < LS; ++m)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.S + n];
+      for (int v = 0; v < 5; ++v) { w[m][v] = *q; q = next_row(q, g.S); }
+  }
 
   {
     PosScan<T, 5, DEV> scan(w0);
@@ -475,12 +519,13 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
         for (int v = 0; v < 5; ++v) e[m][v] *= th;
     }
     NoScan none;
-    store_side<S, T, 0>(w, e, ph, none, PK, g.S, n);
-    store_side<S, T, 1>(w, e, ph, none, PK, g.S, n);
-    store_side<S, T, 2>(w, e, ph, none, PK, g.S, n);
-    store_side<S, T, 3>(w, e, ph, none, PK, g.S, n);
-    store_side<S, T, 4>(w, e, ph, none, PK, g.S, n);
-    store_side<S, T, 5>(w, e, ph, none, PK, g.S, n);
+    T* q = PK + n;
+    store_side<S, T, 0>(w, e, ph, none, q, g.S);
+    store_side<S, T, 1>(w, e, ph, none, q, g.S);
+    store_side<S, T, 2>(w, e, ph, none, q, g.S);
+    store_side<S, T, 3>(w, e, ph, none, q, g.S);
+    store_side<S, T, 4>(w, e, ph, none, q, g.S);
+    store_side<S, T, 5>(w, e, ph, none, q, g.S);
     return;
   }
   // The six face-side packets.  The states they evaluate are the facial
@@ -491,12 +536,13 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
 #pragma unroll 1
   for (int pass = 0; pass < 2; ++pass) {
     PosScan<T, 5, DEV> scan(w0);
-    store_side<S, T, 0>(w, e, ph, scan, PK, g.S, n);
-    store_side<S, T, 1>(w, e, ph, scan, PK, g.S, n);
-    store_side<S, T, 2>(w, e, ph, scan, PK, g.S, n);
-    store_side<S, T, 3>(w, e, ph, scan, PK, g.S, n);
-    store_side<S, T, 4>(w, e, ph, scan, PK, g.S, n);
-    store_side<S, T, 5>(w, e, ph, scan, PK, g.S, n);
+    T* q = PK + n;
+    store_side<S, T, 0>(w, e, ph, scan, q, g.S);
+    store_side<S, T, 1>(w, e, ph, scan, q, g.S);
+    store_side<S, T, 2>(w, e, ph, scan, q, g.S);
+    store_side<S, T, 3>(w, e, ph, scan, q, g.S);
+    store_side<S, T, 4>(w, e, ph, scan, q, g.S);
+    store_side<S, T, 5>(w, e, ph, scan, q, g.S);
     if (pass == 1 || !scan.near) break;
     const double theta = theta_facial_tab(w0, w, e, S::facial_phi, gam);
     if (!(theta < 1.0)) break;
@@ -584,30 +630,45 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
   T ubl[5], ul[5], fl[5], ubr[5], ur[5], fr[5], out[5];
   double wl[5], wr[5];
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;  // top side of the lower zone, bottom side of this
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    ubl[v] = PK[((long long)(SL * 3 + 0) * 5 + v) * g.S + nl];
-    ul[v] = PK[((long long)(SL * 3 + 1) * 5 + v) * g.S + nl];
-    fl[v] = PK[((long long)(SL * 3 + 2) * 5 + v) * g.S + nl];
-    ubr[v] = PK[((long long)(SR * 3 + 0) * 5 + v) * g.S + n];
-    ur[v] = PK[((long long)(SR * 3 + 1) * 5 + v) * g.S + n];
-    fr[v] = PK[((long long)(SR * 3 + 2) * 5 + v) * g.S + n];
-  }
-  if constexpr (DEV) {
+  {
+    const T* ql = PK + (long long)(SL * 15) * g.S + nl;
+    const T* qr = PK + (long long)(SR * 15) * g.S + n;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      wl[v] = U[(long long)v * g.S + nl];
-      wr[v] = U[(long long)v * g.S + n];
+      ubl[v] = *ql; ql = next_row(ql, g.S);
+      ubr[v] = *qr; qr = next_row(qr, g.S);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      ul[v] = *ql; ql = next_row(ql, g.S);
+      ur[v] = *qr; qr = next_row(qr, g.S);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      fl[v] = *ql; ql = next_row(ql, g.S);
+      fr[v] = *qr; qr = next_row(qr, g.S);
+    }
+  }
+  if constexpr (DEV) {
+    const double* pl = U + nl;
+    const double* pr = U + n;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      wl[v] = *pl; pl = next_row(pl, g.S);
+      wr[v] = *pr; pr = next_row(pr, g.S);
       ubl[v] += T(wl[v]);
       ubr[v] += T(wr[v]);
       ur[v] += T(wr[v] - wl[v]);
     }
   }
+  double* qf = F + (long long)(AXIS * 5) * g.S + n;
   const T tg = T(gam);
   if constexpr (RS == 0) {
-    const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
-    const T cl = sqrt(tg * Euler<T>::pressure(ubl, tg) / ubl[0]);
-    const T cr = sqrt(tg * Euler<T>::pressure(ubr, tg) / ubr[0]);
+    // signal speeds of the barycentre states
+    const T il = recip(ubl[0]), ir = recip(ubr[0]);
+    const T vl = ubl[1 + AXIS] * il, vr = ubr[1 + AXIS] * ir;
+    const T cl = fsqrt(tg * Euler<T>::pressure(ubl, tg) * il);
+    const T cr = fsqrt(tg * Euler<T>::pressure(ubr, tg) * ir);
     const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
     const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
     hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
@@ -617,8 +678,10 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       Euler<double>::template flux<AXIS>(wr, Fr, gam);
       const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        F[((long long)AXIS * 5 + v) * g.S + n] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
+      for (int v = 0; v < 5; ++v) {
+        *qf = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
+        qf = next_row(qf, g.S);
+      }
       return;
     }
   } else {
@@ -628,13 +691,18 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       Euler<double>::template flux<AXIS>(wl, Fl, gam);
       Euler<double>::template flux<AXIS>(wr, Fr, gam);
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        F[((long long)AXIS * 5 + v) * g.S + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+      for (int v = 0; v < 5; ++v) {
+        *qf = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+        qf = next_row(qf, g.S);
+      }
       return;
     }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
+  for (int v = 0; v < 5; ++v) {
+    *qf = double(out[v]);
+    qf = next_row(qf, g.S);
+  }
 }
 
 // Each face flux is formed once, by the zone above it, so both zones that
@@ -795,26 +863,26 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
                                                         long long N, long long n) {
   T ub[8], ua[8], fa[8], ue[4], fe[4];
   S::template side_edges<SIDE>(w, e, ph, acc, ub, ua, fa, ue, fe);
-  T* base = PK + (long long)SIDE * kMhdSlots * N + n;
+  RowCursor<T> r(PK, N, n, SIDE * kMhdSlots);
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    base[(long long)v * N] = ub[v];
-    base[(long long)(8 + v) * N] = ua[v];
-    base[(long long)(16 + v) * N] = fa[v];
-  }
+  for (int v = 0; v < 8; ++v) r.row(SIDE * kMhdSlots + v) = ub[v];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) base[(long long)mhd_fe_slot(q) * N] = fe[q];
+  for (int v = 0; v < 8; ++v) r.row(SIDE * kMhdSlots + 8 + v) = ua[v];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) r.row(SIDE * kMhdSlots + 16 + v) = fa[v];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r.row(SIDE * kMhdSlots + mhd_fe_slot(q)) = fe[q];
   if constexpr (EDGES_ALL) {
     T ues[4][8];
     S::template edge_states<SIDE, Phys::kDeviation>(w, e, ues);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int v = 0; v < 8; ++v) base[(long long)mhd_ue_slot(q, v) * N] = ues[q][v];
+      for (int v = 0; v < 8; ++v) r.row(SIDE * kMhdSlots + mhd_ue_slot(q, v)) = ues[q][v];
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      base[(long long)mhd_ue_slot(q, mhd_edge_comp(SIDE / 2, q)) * N] = ue[q];
+      r.row(SIDE * kMhdSlots + mhd_ue_slot(q, mhd_edge_comp(SIDE / 2, q))) = ue[q];
   }
 }
 
@@ -831,27 +899,33 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   using S = typename SchemeOf<ORDER, FORM, T, 8>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[8];
+  {
+    RowCursor<const double> ru(U, g.S, n), rb(B0, g.S, n);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) w0[v] = U[(long long)v * g.S + n];
+    for (int v = 0; v < 5; ++v) w0[v] = ru.row(v);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) w0[5 + c] = B0[(long long)c * g.S + n];
+    for (int c = 0; c < 3; ++c) w0[5 + c] = rb.row(c);
+  }
   T w[LS][8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
+  {
+    RowCursor<const T> rw(W, g.S, n), rf(WB, g.S, n), rn(BN, g.S, n);
 #pragma unroll
-  for (int m = 1; m < LS; ++m) {
+    for (int m = 1; m < LS; ++m) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) w[m][v] = W[((long long)(m - 1) * 5 + v) * g.S + n];
+      for (int v = 0; v < 5; ++v) w[m][v] = rw.row((m - 1) * 5 + v);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) w[m][5 + c] = WB[((long long)(m - 1) * 3 + c) * g.S + n];
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int a = 1; a < ORDER; ++a) {
-      const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
-      w[m][5 + c] = BN[((long long)(a - 1) * 3 + c) * g.S + n];
+      for (int c = 0; c < 3; ++c) w[m][5 + c] = rf.row((m - 1) * 3 + c);
     }
+#pragma unroll
+    for (int a = 1; a < ORDER; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
+        w[m][5 + c] = rn.row((a - 1) * 3 + c);
+      }
+  }
   {
     PosScan<T, 8, DEV> scan(w0);
     S::spatial_points_all(w, scan);
@@ -933,35 +1007,38 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
                                                             const Grid& g, long long n,
                                                             long long nl, double gam) {
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
-  const T* L = PK + (long long)SL * kMhdSlots * g.S + nl;
-  const T* R = PK + (long long)SR * kMhdSlots * g.S + n;
+  constexpr int l0 = SL * kMhdSlots, r0 = SR * kMhdSlots;   // first rows of the two sides
+  RowCursor<const T> L(PK, g.S, nl, l0), R(PK, g.S, n, r0);
   double wl[8], wr[8];
   if constexpr (DEV) {
+    RowCursor<const double> ul_(U, g.S, nl), ur_(U, g.S, n), bl_(B0, g.S, nl), br_(B0, g.S, n);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      wl[v] = U[(long long)v * g.S + nl];
-      wr[v] = U[(long long)v * g.S + n];
+      wl[v] = ul_.row(v);
+      wr[v] = ur_.row(v);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      wl[5 + c] = B0[(long long)c * g.S + nl];
-      wr[5 + c] = B0[(long long)c * g.S + n];
+      wl[5 + c] = bl_.row(c);
+      wr[5 + c] = br_.row(c);
     }
   }
   T ubl[8], ubr[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
-    ubl[v] = L[(long long)v * g.S];
-    ubr[v] = R[(long long)v * g.S];
+    ubl[v] = L.row(l0 + v);
+    ubr[v] = R.row(r0 + v);
     if constexpr (DEV) {
       ubl[v] += T(wl[v]);
       ubr[v] += T(wr[v]);
     }
   }
+  RowCursor<double> rf(F, g.S, n, AXIS * 5), re(FE, g.S, n, AXIS * 4);
   const T tg = T(gam);
   T out[5], eout[4];
   if constexpr (RS == 0) {
-    const T vl = ubl[1 + AXIS] / ubl[0], vr = ubr[1 + AXIS] / ubr[0];
+    const T il = recip(ubl[0]), ir = recip(ubr[0]);
+    const T vl = ubl[1 + AXIS] * il, vr = ubr[1 + AXIS] * ir;
     const T cl = Mhd<T>::template fast_speed<AXIS>(ubl, tg);
     const T cr = Mhd<T>::template fast_speed<AXIS>(ubr, tg);
     const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
@@ -969,21 +1046,27 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
     T ul[5], ur[5], fl[5], fr[5];
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      ul[v] = L[(long long)(8 + v) * g.S];
-      ur[v] = R[(long long)(8 + v) * g.S];
-      fl[v] = L[(long long)(16 + v) * g.S];
-      fr[v] = R[(long long)(16 + v) * g.S];
+      ul[v] = L.row(l0 + 8 + v);
+      ur[v] = R.row(r0 + 8 + v);
       if constexpr (DEV) ur[v] += T(wr[v] - wl[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      fl[v] = L.row(l0 + 16 + v);
+      fr[v] = R.row(r0 + 16 + v);
     }
     hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
     T el[4], er[4], gl[4], gr[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      gl[q] = L.row(l0 + mhd_fe_slot(q));
+      gr[q] = R.row(r0 + mhd_fe_slot(q));
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
       const int c = mhd_edge_comp(AXIS, q);
-      el[q] = L[(long long)mhd_ue_slot(q, c) * g.S];
-      er[q] = R[(long long)mhd_ue_slot(q, c) * g.S];
-      gl[q] = L[(long long)mhd_fe_slot(q) * g.S];
-      gr[q] = R[(long long)mhd_fe_slot(q) * g.S];
+      el[q] = L.row(l0 + mhd_ue_slot(q, c));
+      er[q] = R.row(r0 + mhd_ue_slot(q, c));
       if constexpr (DEV) er[q] += T(wr[c] - wl[c]);
     }
     hll_combine<T, 4>(lam_l, lam_r, el, gl, er, gr, eout);
@@ -995,10 +1078,9 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
 #pragma unroll
       for (int v = 0; v < 8; ++v) Fa[v] = (lr * Fl[v] - ll * Fr[v]) * inv;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = Fa[v] + double(out[v]);
+      for (int v = 0; v < 5; ++v) rf.row(AXIS * 5 + v) = Fa[v] + double(out[v]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        FE[((long long)AXIS * 4 + q) * g.S + n] = Fa[mhd_edge_comp(AXIS, q)] + double(eout[q]);
+      for (int q = 0; q < 4; ++q) re.row(AXIS * 4 + q) = Fa[mhd_edge_comp(AXIS, q)] + double(eout[q]);
       return;
     }
   } else {
@@ -1006,45 +1088,53 @@ __host__ __device__ __forceinline__ void face_flux_axis_mhd(const double* __rest
     T du[8], D[8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      du[v] = R[(long long)(8 + v) * g.S] - L[(long long)(8 + v) * g.S];
+      const T a = L.row(l0 + 8 + v);
+      du[v] = R.row(r0 + 8 + v) - a;
       if constexpr (DEV) du[v] += T(wr[v] - wl[v]);
     }
     eg.apply(du, D);
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
-      out[v] = T(0.5) * (L[(long long)(16 + v) * g.S] + R[(long long)(16 + v) * g.S]) - T(0.5) * D[v];
+    for (int v = 0; v < 5; ++v) {
+      const T a = L.row(l0 + 16 + v);
+      out[v] = T(0.5) * (a + R.row(r0 + 16 + v)) - T(0.5) * D[v];
+    }
+    T gsum[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T a = L.row(l0 + mhd_fe_slot(q));
+      gsum[q] = a + R.row(r0 + mhd_fe_slot(q));
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = mhd_edge_comp(AXIS, q);
       T de[8], De[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v) {
-        de[v] = R[(long long)mhd_ue_slot(q, v) * g.S] - L[(long long)mhd_ue_slot(q, v) * g.S];
+        const T a = L.row(l0 + mhd_ue_slot(q, v));
+        de[v] = R.row(r0 + mhd_ue_slot(q, v)) - a;
         if constexpr (DEV) de[v] += T(wr[v] - wl[v]);
       }
       eg.apply(de, De);
-      eout[q] = T(0.5) * (L[(long long)mhd_fe_slot(q) * g.S] + R[(long long)mhd_fe_slot(q) * g.S]) -
-                T(0.5) * De[c];
+      eout[q] = T(0.5) * gsum[q] - T(0.5) * De[c];
     }
     if constexpr (DEV) {
       double Fl[8], Fr[8];
       Mhd<double>::template flux<AXIS>(wl, Fl, gam);
       Mhd<double>::template flux<AXIS>(wr, Fr, gam);
 #pragma unroll
-      for (int v = 0; v < 5; ++v)
-        F[((long long)AXIS * 5 + v) * g.S + n] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
+      for (int v = 0; v < 5; ++v) rf.row(AXIS * 5 + v) = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = mhd_edge_comp(AXIS, q);
-        FE[((long long)AXIS * 4 + q) * g.S + n] = 0.5 * (Fl[c] + Fr[c]) + double(eout[q]);
+        re.row(AXIS * 4 + q) = 0.5 * (Fl[c] + Fr[c]) + double(eout[q]);
       }
       return;
     }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) F[((long long)AXIS * 5 + v) * g.S + n] = double(out[v]);
+  for (int v = 0; v < 5; ++v) rf.row(AXIS * 5 + v) = double(out[v]);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) FE[((long long)AXIS * 4 + q) * g.S + n] = double(eout[q]);
+  for (int q = 0; q < 4; ++q) re.row(AXIS * 4 + q) = double(eout[q]);
 }
 
 template <class T, int RS, bool DEV>

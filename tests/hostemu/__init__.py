@@ -25,7 +25,7 @@ def build(force=False):
     stale = force or not os.path.exists(LIB) or any(
         os.path.getmtime(d) > os.path.getmtime(LIB) for d in DEPS)
     if stale:
-        tmp = LIB + ".tmp"
+        tmp = "%s.tmp%d" % (LIB, os.getpid())   # parallel test workers build apart
         subprocess.run(["hipcc", "-x", "hip", "--offload-host-only", "-O2", "-std=c++17",
                         "-fPIC", "-shared", "-o", tmp, SRC], check=True)
         os.replace(tmp, LIB)

@@ -237,12 +237,15 @@ def test_config3_mhd_full_size_sampled():
 # --------------------------------------------------------- predictor layouts --
 
 LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
-           ader.ADER_LAYOUT_ZONE2]
+           ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W]
 
 
-def _skip_unbuilt(layout, order):
+def _skip_unbuilt(layout, order, mhd=False):
     if layout == ader.ADER_LAYOUT_ZONE2 and order > 3:
-        pytest.skip("the capped one-lane-per-zone instance is built for orders 2 and 3")
+        pytest.skip("the one-lane-per-zone instance with its own facial pass is built for "
+                    "orders 2 and 3")
+    if layout == ader.ADER_LAYOUT_ZONE_2W and (order > 3 or mhd):
+        pytest.skip("the two-wave one-lane-per-zone instance is built for Euler at orders 2-3")
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
@@ -274,7 +277,7 @@ def test_parity_layouts_euler(layout, order, rs):
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("order", [3, 4])
 def test_parity_layouts_mhd(layout, order):
-    _skip_unbuilt(layout, order)
+    _skip_unbuilt(layout, order, mhd=True)
     U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order + 20)
     cfg = OracleConfig(order=order, gamma=G53, lengths=(1.0, 0.9, 1.2))
     with _mhd_solver((7, 9, 10), order, "modal", lengths=(1.0, 0.9, 1.2)) as s:
@@ -300,6 +303,11 @@ def test_layout_errors():
         assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE2
     with _solver((4, 4, 4), 4, "modal", "hll") as s:
         assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE2) == ader.ADER_EUNSUPPORTED
+        assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE_2W) == \
+            ader.ADER_EUNSUPPORTED
+    with _mhd_solver((4, 4, 4), 3, "modal") as s:
+        assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE_2W) == \
+            ader.ADER_EUNSUPPORTED
 
 
 # ----------------------------------------- turbulent MHD, linearized, order 4 --
