@@ -454,11 +454,11 @@ def main():
     pred_ms = pv["stage_ms_per_step"]["predict"]
     achieved = flops_zone * N / (pred_ms * 1e-3) / 1e12
     layout = pv.get("predict_layout")
-    kernel = {("f32", "zone"): "k_predict<float,3,0,true>",
-              ("f32", "zone-prescan"): "k_predict<float,3,0,false>",
-              ("f64", "zone"): "k_predict<double,3,0,true>",
-              ("f64", "zone-prescan"): "k_predict<double,3,0,false>",
+    kernel = {("f32", "zone"): "k_predict<float,3,0,true,1>",
+              ("f32", "zone-prescan"): "k_predict<float,3,0,false,1>",
               ("f32", "zone-2waves"): "k_predict<float,3,0,true,2>",
+              ("f64", "zone"): "k_predict<double,3,0,true,1>",
+              ("f64", "zone-prescan"): "k_predict<double,3,0,false,1>",
               ("f64", "zone-2waves"): "k_predict<double,3,0,true,2>"}.get((dtype, layout),
                                                                           "k_predict (%s)" % layout)
     roofline = {"bound": "alu", "kernel": kernel, "achieved": achieved,
