@@ -19,7 +19,7 @@ basis     -- Hermite/temporal basis (eq. 9, 13), mode orderings (eq. 10-16)
 physics   -- Euler / ideal-MHD conserved fluxes in Gaussian units (eq. 3)
 weno      -- zone-centred WENO / minmod reconstruction (Sec. II.1)
 bweno     -- WENO zone-averaging of face-centred B (Sec. III)
-predictor -- ADER-CG space-time predictor, modal (Sec. IV) and nodal (App. A)
+predictor -- ADER-CG space-time predictor, modal (Sec. IV) and nodal (App. A, B)
 faces     -- barycentre states and face/edge space-time averages (Sec. V, App. D)
 riemann   -- HLL (eq. 17, 56) and linearized Riemann fluxes at frozen states
 step      -- whole step: dt by CFL, flux-difference update (eq. 6), CT (eq. 8)

@@ -34,7 +34,7 @@ import numpy as np
 
 from .basis import N_SPATIAL, evaluate
 from .faces import FACE_NODES, zone_point
-from .predictor import NODES_MODAL, NODES_NODAL_2
+from .predictor import NODES_MODAL, NODES_NODAL
 
 EPS_REL = 1.0e-8
 
@@ -61,7 +61,7 @@ def facial_check_points(order, all_nodes=False):
 def spatial_check_points(order, form, all_nodes=False):
     """Distinct spatial positions of the predictor nodes and of the facial
     check points (tau set to 0)."""
-    pts = list(NODES_NODAL_2 if form == 'nodal' else NODES_MODAL[order])
+    pts = list(NODES_NODAL[order] if form == 'nodal' else NODES_MODAL[order])
     pts += facial_check_points(order, all_nodes)
     return sorted(set((float(p[0]), float(p[1]), float(p[2]), 0.0) for p in pts))
 

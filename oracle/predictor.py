@@ -1,4 +1,4 @@
-"""ADER-CG space-time predictor (Sec. IV modal, Appendix A nodal).
+"""ADER-CG space-time predictor (Sec. IV modal; Appendices A, B nodal).
 
 Starting from the spatial modes w_1..w_{L_S} of a zone, the evolutionary modes
 u_{L_S+1}..u_L of eq. (14)-(16) are found by M-1 Picard iterations (Sec. IV.2):
@@ -52,6 +52,13 @@ NODES_MODAL_4 = [(0, 0, 0, 0), (H, 0, 0, 0), (Q4, 0, 0, 0), (-Q4, 0, 0, 0), (-H,
 
 # Eq. (A.1): the five nodes of the second-order nodal formulation.
 NODES_NODAL_2 = [(0, 0, 0, 0), (H, 0, 0, 0), (0, H, 0, 0), (0, 0, H, 0), (0, 0, 0, 1)]
+
+# Eq. (B.1): the fifteen nodes of the third-order nodal formulation.
+NODES_NODAL_3 = [(0, 0, 0, 0), (H, 0, 0, 0), (-H, 0, 0, 0), (0, H, 0, 0), (0, -H, 0, 0),
+                 (0, 0, H, 0), (0, 0, -H, 0), (0, H, H, 0), (H, 0, H, 0), (H, H, 0, 0),
+                 (0, 0, 0, H), (H, 0, 0, H), (0, H, 0, H), (0, 0, H, H), (0, 0, 0, 1)]
+
+NODES_NODAL = {2: NODES_NODAL_2, 3: NODES_NODAL_3}
 
 NODES_MODAL = {2: NODES_MODAL_2, 3: NODES_MODAL_3, 4: NODES_MODAL_4}
 
@@ -291,3 +298,76 @@ def predict_nodal_2(what, dt, dx, gamma, flux_fn=None):
     uhat[:4] = what
     uhat[4] = u5 - ubar[1]
     return uhat
+
+
+def nodal3_b2(u, f, g, h):
+    """(B.2) without source terms: the temporaries q_11 .. q_15 from the
+    nodal values u_1 .. u_10 at the tau = 0 nodes and their scaled fluxes
+    (sequences indexed by the paper's 1-based node numbers)."""
+    return {
+        11: u[1] + 0.5 * (f[3] - f[1]) + 0.5 * (g[5] - g[1]) + 0.5 * (h[7] - h[1]),
+        12: u[2] + (36 * f[1] - 24 * f[2] - 12 * f[3]
+                    - 36 * g[1] + 24 * g[2] + 24 * g[4] + 12 * g[5] - 24 * g[10]
+                    - 36 * h[1] + 24 * h[2] + 24 * h[6] + 12 * h[7] - 24 * h[9]) / 24.0,
+        13: u[4] + (-36 * f[1] + 24 * f[2] + 12 * f[3] + 24 * f[4] - 24 * f[10]
+                    + 36 * g[1] - 24 * g[4] - 12 * g[5]
+                    - 36 * h[1] + 24 * h[4] + 24 * h[6] + 12 * h[7] - 24 * h[8]) / 24.0,
+        14: u[6] + (-36 * f[1] + 24 * f[2] + 12 * f[3] + 24 * f[6] - 24 * f[9]
+                    - 36 * g[1] + 24 * g[4] + 12 * g[5] + 24 * g[6] - 24 * g[8]
+                    + 36 * h[1] - 24 * h[6] - 12 * h[7]) / 24.0,
+        15: u[1] + (-60 * f[1] + 30 * f[2] + 30 * f[3] - 60 * g[1] + 30 * g[4] + 30 * g[5]
+                    - 60 * h[1] + 30 * h[6] + 30 * h[7]) / 30.0,
+    }
+
+
+def nodal3_b3(q, f, g, h):
+    """(B.3) without source terms: the nodal values at the later nodes 11 ..
+    15 from the temporaries q of (B.2) and the scaled fluxes at nodes 11-14
+    (indexed by node number)."""
+    q1 = 0.5 * (f[11] - f[12]) + 0.5 * (g[11] - g[13]) + 0.5 * (h[11] - h[14])
+    q2 = q1
+    return {11: q[11] + q1, 12: q[12] + q2, 13: q[13] + q2, 14: q[14] + q2, 15: q[15] + 4.0 * q1}
+
+
+def predict_nodal_3(what, dt, dx, gamma, flux_fn=None):
+    """Nodal ADER-CG at third order, Appendix B (no source terms).
+
+    The nodal values at the ten tau = 0 nodes of (B.1) are the spatial
+    polynomial there (what (B.4) evaluates); their scaled fluxes build the
+    temporaries of (B.2) once.  The five later nodal values start from the
+    spatial polynomial at their positions (no time dependence, as in the
+    modal iteration) and take two iterations of (B.3), each with the fluxes
+    of the previous iterate; (B.5) returns modes 11-15.
+    """
+    if flux_fn is None:
+        fn = lambda u, a: flux(u, a, gamma)  # noqa: E731
+    else:
+        fn = flux_fn
+    uhat = np.zeros((15,) + what.shape[1:])
+    uhat[:10] = what
+    u = _one_based([evaluate(uhat, 3, x) for x in NODES_NODAL_3[:10]])
+    f = [None] + [dt / dx[0] * fn(u[k], 0) for k in range(1, 11)]
+    g = [None] + [dt / dx[1] * fn(u[k], 1) for k in range(1, 11)]
+    h = [None] + [dt / dx[2] * fn(u[k], 2) for k in range(1, 11)]
+    q = nodal3_b2(u, f, g, h)
+    # later nodes 11..15 start from the tau = 0 values at the same positions
+    later = {11: u[1], 12: u[2], 13: u[4], 14: u[6], 15: u[1]}
+    for _ in range(2):
+        fl = {k: dt / dx[0] * fn(later[k], 0) for k in (11, 12)}
+        gl = {k: dt / dx[1] * fn(later[k], 1) for k in (11, 13)}
+        hl = {k: dt / dx[2] * fn(later[k], 2) for k in (11, 14)}
+        later = nodal3_b3(q, fl, gl, hl)
+    uhat[10:] = np.stack(nodal3_b5(u, later))
+    return uhat
+
+
+def nodal3_b5(u, later):
+    """(B.5): modes 11 (tau), 12 (tau^2), 13 (xi tau), 14 (eta tau) and 15
+    (zeta tau) from the nodal values at nodes 1, 2, 4, 6 (u, 1-based) and at
+    the later nodes 11-15."""
+    m12 = 2.0 * (later[15] - 2.0 * later[11] + u[1])
+    m11 = 2.0 * (later[11] - u[1] - 0.25 * m12)
+    m13 = 4.0 * (later[12] - later[11] - u[2] + u[1])
+    m14 = 4.0 * (later[13] - later[11] - u[4] + u[1])
+    m15 = 4.0 * (later[14] - later[11] - u[6] + u[1])
+    return [m11, m12, m13, m14, m15]

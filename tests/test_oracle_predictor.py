@@ -149,6 +149,55 @@ def test_nodal_A4_reading():
     assert sp.simplify(sol - (ub[0] - 2 * (hb[3] - hb[0]))) == 0
 
 
+def test_nodal_B2_B3_from_galerkin():
+    # (B.2) and (B.3) at their fixed point are the continuous-Galerkin
+    # equations written with the nodal basis of the fifteen nodes (B.1):
+    # interpolate u and the scaled fluxes f, g, h on that basis, require the
+    # residual u_t + f_x + g_y + h_z to be orthogonal to the basis functions
+    # of the five later nodes, and solve for their nodal values.  This pins
+    # every printed flux coefficient of (B.2)-(B.3) (sources are zero here).
+    x, y, z, t = sp.symbols('x y z t')
+    h = sp.Rational(1, 2)
+    nodes = [(0, 0, 0, 0), (h, 0, 0, 0), (-h, 0, 0, 0), (0, h, 0, 0), (0, -h, 0, 0),
+             (0, 0, h, 0), (0, 0, -h, 0), (0, h, h, 0), (h, 0, h, 0), (h, h, 0, 0),
+             (0, 0, 0, h), (h, 0, 0, h), (0, h, 0, h), (0, 0, h, h), (0, 0, 0, 1)]
+    assert [tuple(float(c) for c in n) for n in nodes] == pr.NODES_NODAL_3
+    p2 = lambda s: s ** 2 - sp.Rational(1, 12)  # noqa: E731
+    modes = [sp.Integer(1), x, y, z, p2(x), p2(y), p2(z), x * y, y * z, x * z,
+             t, t ** 2, x * t, y * t, z * t]
+    V = sp.Matrix([[m.subs({x: n[0], y: n[1], z: n[2], t: n[3]}) for m in modes] for n in nodes])
+    Vi = V.inv()
+    Pn = [sp.expand(sum(modes[m] * Vi[m, i] for m in range(15))) for i in range(15)]
+    u, f, g, hh = (sp.symbols(s + '1:16') for s in ('u', 'f', 'g', 'h'))
+    interp = lambda c: sum(c[i] * Pn[i] for i in range(15))  # noqa: E731
+    R = sp.diff(interp(u), t) + sp.diff(interp(f), x) + sp.diff(interp(g), y) + sp.diff(interp(hh), z)
+    box = [(x, -h, h), (y, -h, h), (z, -h, h), (t, 0, 1)]
+    eqs = [sp.integrate(sp.expand(w * R), *box) for w in Pn[10:]]
+    sol = sp.solve(eqs, u[10:], dict=True)[0]
+    # the oracle's (B.2) then (B.3), every nodal value and flux an
+    # independent random number (later-node fluxes at their fixed point)
+    rng = np.random.default_rng(3)
+    vals = {s: rng.normal() for s in list(u[:10]) + list(f) + list(g) + list(hh)}
+    one = lambda c, n: [None] + [vals[c[k]] for k in range(n)]  # noqa: E731
+    F, G, H = one(f, 15), one(g, 15), one(hh, 15)
+    got = pr.nodal3_b3(pr.nodal3_b2(one(u, 10), F, G, H), F, G, H)
+    for k in range(11, 16):
+        ref = float(sol[u[k - 1]].subs(vals))
+        assert abs(got[k] - ref) < 1e-12, (k, got[k], ref)
+
+
+def test_nodal_B5_recovers_the_modes():
+    # (B.5) inverts the nodal values of (B.1) back to modes 11-15: a random
+    # space-time polynomial, evaluated at the nodes by the tests' own
+    # evaluator, must give back its own evolutionary modes
+    rng = np.random.default_rng(8)
+    uhat = rng.normal(size=15)
+    val = [None] + [indep.st_value(uhat, 3, p) for p in pr.NODES_NODAL_3]
+    later = {k: val[k] for k in range(11, 16)}
+    got = pr.nodal3_b5(val, later)
+    assert np.allclose(got, uhat[10:], rtol=0, atol=1e-13)
+
+
 def _linear_flux(adv):
     return lambda u, axis: adv[axis] * u
 
@@ -160,7 +209,8 @@ def _spatial_value(what, order, point):
     return indep.st_value(c, order, (point[0], point[1], point[2], 0.0))
 
 
-@pytest.mark.parametrize("order,form", [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')])
+@pytest.mark.parametrize("order,form", [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'),
+                                        (4, 'modal')])
 def test_predictor_exact_for_linear_advection(order, form):
     # constant-coefficient linear flux on data of degree <= M-1: the
     # space-time polynomial must be w(x - c tau) after M-1 iterations
@@ -171,7 +221,8 @@ def test_predictor_exact_for_linear_advection(order, form):
     dt, dx = 0.05, (0.1, 0.2, 0.125)
     c = adv * dt / np.array(dx)
     if form == 'nodal':
-        uhat = pr.predict_nodal_2(what, dt, dx, 1.4, flux_fn=_linear_flux(adv))
+        nodal = {2: pr.predict_nodal_2, 3: pr.predict_nodal_3}[order]
+        uhat = nodal(what, dt, dx, 1.4, flux_fn=_linear_flux(adv))
     else:
         uhat = pr.predict_modal(what, order, dt, dx, 1.4, flux_fn=_linear_flux(adv))
     for p in rng.uniform(-0.5, 0.5, size=(10, 4)):

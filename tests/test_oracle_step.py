@@ -11,7 +11,7 @@ from oracle.physics import conserved, primitives
 
 GOLDEN = os.path.join(os.path.dirname(__file__), 'golden')
 
-CONFIGS = [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')]
+CONFIGS = [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'), (4, 'modal')]
 
 
 @pytest.mark.parametrize("order,form", CONFIGS)
@@ -113,13 +113,17 @@ def _read_golden_rates():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("order,sizes,T", [(2, (16, 32), 0.02), (3, (8, 16), 0.05), (4, (8, 16), 0.05)])
-def test_design_order_density_wave(order, sizes, T):
+@pytest.mark.parametrize("order,sizes,T,form", [(2, (16, 32), 0.02, 'modal'),
+                                               (3, (8, 16), 0.05, 'modal'),
+                                               (3, (8, 16), 0.05, 'nodal'),
+                                               (4, (8, 16), 0.05, 'modal')])
+def test_design_order_density_wave(order, sizes, T, form):
     # Table IV demonstrates L1 rates near the design order on a smooth
-    # diagonal density wave; the oracle must reach its design order too
+    # diagonal density wave; the oracle must reach its design order too, in
+    # either formulation of the predictor
     paper = _read_golden_rates()[order]
     assert min(paper) > order - 0.5
-    cfg = OracleConfig(order=order, form='modal', riemann='hll')
+    cfg = OracleConfig(order=order, form=form, riemann='hll')
     errs = []
     for n in sizes:
         U = _run(_density_wave(n, 0.0), cfg, T)
@@ -153,9 +157,10 @@ def test_modal_blast_is_mirror_symmetric(order):
     assert np.abs(rho - rho[::-1, ::-1, ::-1]).max() < 1e-12
 
 
-def test_nodal_blast_is_not_mirror_symmetric():
-    # Sec. VIII.3: the asymmetric nodes of App. A break the mirror symmetry
-    cfg = OracleConfig(order=2, form='nodal', riemann='hll')
+@pytest.mark.parametrize("order", [2, 3])
+def test_nodal_blast_is_not_mirror_symmetric(order):
+    # Sec. VIII.3: the asymmetric nodes of App. A and B break the mirror symmetry
+    cfg = OracleConfig(order=order, form='nodal', riemann='hll')
     U = _blast(10)
     for _ in range(4):
         U = step(U, compute_dt(U, cfg, 0.3), cfg)
