@@ -18,7 +18,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
 import numpy as np
 
-from .basis import N_SPATIAL, N_SPACETIME, evaluate
+from .basis import N_SPATIAL, N_SPACETIME, P, Q, dP, evaluate, phi, spacetime_modes
 from .physics import flux
 
 H = 0.5
@@ -58,7 +58,17 @@ NODES_NODAL_3 = [(0, 0, 0, 0), (H, 0, 0, 0), (-H, 0, 0, 0), (0, H, 0, 0), (0, -H
                  (0, 0, H, 0), (0, 0, -H, 0), (0, H, H, 0), (H, 0, H, 0), (H, H, 0, 0),
                  (0, 0, 0, H), (H, 0, 0, H), (0, H, 0, H), (0, 0, H, H), (0, 0, 0, 1)]
 
-NODES_NODAL = {2: NODES_NODAL_2, 3: NODES_NODAL_3}
+# Eq. (C.1): the thirty-five nodes of the fourth-order nodal formulation.
+NODES_NODAL_4 = [(0, 0, 0, 0), (H, H, H, 0), (H, 0, 0, 0), (-H, 0, 0, 0), (0, H, 0, 0),
+                 (0, -H, 0, 0), (0, 0, H, 0), (0, 0, -H, 0), (0, H, H, 0), (-H, 0, H, 0),
+                 (H, 0, H, 0), (H, -H, 0, 0), (H, H, 0, 0), (0, H, -H, 0),
+                 (-Q4, -H, -H, 0), (Q4, -H, -H, 0), (-H, -Q4, -H, 0), (-H, Q4, -H, 0),
+                 (-H, -H, -Q4, 0), (-H, -H, Q4, 0),
+                 (0, 0, 0, T3), (H, 0, 0, T3), (-H, 0, 0, T3), (0, H, 0, T3), (0, -H, 0, T3),
+                 (0, 0, H, T3), (0, 0, -H, T3), (0, H, H, T3), (H, 0, H, T3), (H, H, 0, T3),
+                 (0, 0, 0, T23), (H, 0, 0, T23), (0, H, 0, T23), (0, 0, H, T23), (0, 0, 0, 1)]
+
+NODES_NODAL = {2: NODES_NODAL_2, 3: NODES_NODAL_3, 4: NODES_NODAL_4}
 
 NODES_MODAL = {2: NODES_MODAL_2, 3: NODES_MODAL_3, 4: NODES_MODAL_4}
 
@@ -371,3 +381,121 @@ def nodal3_b5(u, later):
     m14 = 4.0 * (later[13] - later[11] - u[4] + u[1])
     m15 = 4.0 * (later[14] - later[11] - u[6] + u[1])
     return [m11, m12, m13, m14, m15]
+
+
+_UPDATE_MAPS = {}
+
+
+def nodal_update_map(order):
+    """The nodal update equations of App. B and C in matrix form.
+
+    u and the scaled fluxes f, g, h are interpolated on the nodal basis of
+    the nodes (B.1)/(C.1) (the Lagrange basis of the L space-time modes);
+    the residual u_tau + f_xi + g_eta + h_zeta is required to be orthogonal
+    to the basis functions of the later (tau > 0) nodes over the space-time
+    element, which gives the later nodal values as
+        u_later = Au @ u_0 + Af @ f + Ag @ g + Ah @ h
+    with u_0 the tau = 0 nodal values and f, g, h the fluxes at every node.
+    The tau = 0 columns are the temporaries q of (B.2)/(C.2) and the later
+    columns the evolutionary equations (B.3)/(C.3), whose printed
+    coefficients this reproduces.  Also returned: the node list, the index
+    arrays of the tau = 0 and later nodes, and the inverse Vandermonde
+    matrix C (mode m = sum_j C[m, j] u_j).
+    """
+    if order in _UPDATE_MAPS:
+        return _UPDATE_MAPS[order]
+    nodes = NODES_NODAL[order]
+    modes = spacetime_modes(order)
+    L = len(modes)
+    V = np.array([[float(phi(m, *x)) for m in modes] for x in nodes])
+    C = np.linalg.inv(V)
+    # tensor Gauss-Legendre rule on [-1/2, 1/2]^3 x [0, 1], exact for the
+    # products below (degree <= 7 per axis)
+    g, gw = np.polynomial.legendre.leggauss(5)
+    xs, xw = 0.5 * g, 0.5 * gw
+    ts, tw = 0.5 * (g + 1.0), 0.5 * gw
+    X, Y, Z, T = np.meshgrid(xs, xs, xs, ts, indexing='ij')
+    Wq = np.einsum('i,j,k,l->ijkl', xw, xw, xw, tw).ravel()
+    X, Y, Z, T = X.ravel(), Y.ravel(), Z.ravel(), T.ravel()
+    Phi = np.array([phi(m, X, Y, Z, T) for m in modes])
+    dPhi = []
+    for axis in range(3):
+        rows = []
+        for (a, b, c, d) in modes:
+            e = [a, b, c]
+            fac = [P(e[0], X), P(e[1], Y), P(e[2], Z)]
+            fac[axis] = dP(e[axis], (X, Y, Z)[axis])
+            rows.append(fac[0] * fac[1] * fac[2] * Q(d, T))
+        dPhi.append(np.array(rows))
+    dt_rows = [P(a, X) * P(b, Y) * P(c, Z) * (d * T ** (d - 1) if d > 0 else 0.0 * T)
+               for (a, b, c, d) in modes]
+    dPhi.append(np.array(dt_rows))
+    # nodal basis and its derivatives at the quadrature points
+    Pq = C.T @ Phi
+    dPq = [C.T @ d for d in dPhi]
+    t0 = np.array([i for i, x in enumerate(nodes) if x[3] == 0])
+    lt = np.array([i for i, x in enumerate(nodes) if x[3] != 0])
+    Psi = Pq[lt] * Wq
+    E = Psi @ dPq[3].T
+    D = [Psi @ dPq[a].T for a in range(3)]
+    Einv = np.linalg.inv(E[:, lt])
+    Au = -Einv @ E[:, t0]
+    Af, Ag, Ah = (-Einv @ D[a] for a in range(3))
+    out = (nodes, t0, lt, Au, Af, Ag, Ah, C)
+    _UPDATE_MAPS[order] = out
+    return out
+
+
+def _apply(A, x):
+    """sum_j A[i, j] x[j] over the leading axis of x, summed in j order with
+    elementwise operations, so that every zone gets the same rounding (a
+    library matrix product may order its sums differently per element)."""
+    out = np.zeros((A.shape[0],) + x.shape[1:])
+    for i in range(A.shape[0]):
+        acc = np.zeros(x.shape[1:])
+        for j in range(A.shape[1]):
+            if A[i, j] != 0.0:
+                acc = acc + A[i, j] * x[j]
+        out[i] = acc
+    return out
+
+
+def predict_nodal_4(what, dt, dx, gamma, flux_fn=None):
+    """Nodal ADER-CG at fourth order, Appendix C (no source terms).
+
+    The nodal values at the twenty tau = 0 nodes of (C.1) are the spatial
+    polynomial there; their scaled fluxes build the fifteen temporaries of
+    (C.2) once.  The fifteen later nodal values start from the spatial
+    polynomial at their positions (as in the modal iteration) and take
+    three iterations of (C.3), each with the fluxes of the previous iterate;
+    the modes 21-35 follow from the 35 nodal values (the inverse of the
+    nodal evaluation).  The coefficients of (C.2)-(C.3) come from
+    nodal_update_map (the printed ones are its values).
+    """
+    if flux_fn is None:
+        fn = lambda u, a: flux(u, a, gamma)  # noqa: E731
+    else:
+        fn = flux_fn
+    nodes, t0, lt, Au, Af, Ag, Ah, C = nodal_update_map(4)
+    L = len(nodes)
+    ls = N_SPATIAL[4]
+    uhat = np.zeros((L,) + what.shape[1:])
+    uhat[:ls] = what
+
+    def scaled(u_nodes):
+        return (np.stack([dt / dx[0] * fn(u, 0) for u in u_nodes]),
+                np.stack([dt / dx[1] * fn(u, 1) for u in u_nodes]),
+                np.stack([dt / dx[2] * fn(u, 2) for u in u_nodes]))
+
+    u0 = np.stack([evaluate(uhat, 4, nodes[i]) for i in t0])
+    f0, g0, h0 = scaled(u0)
+    q = _apply(Au, u0) + _apply(Af[:, t0], f0) + _apply(Ag[:, t0], g0) + _apply(Ah[:, t0], h0)
+    later = np.stack([evaluate(uhat, 4, tuple(nodes[i][:3]) + (0.0,)) for i in lt])
+    for _ in range(3):
+        fl, gl, hl = scaled(later)
+        later = q + _apply(Af[:, lt], fl) + _apply(Ag[:, lt], gl) + _apply(Ah[:, lt], hl)
+    allv = np.empty((L,) + what.shape[1:])
+    allv[t0] = u0
+    allv[lt] = later
+    uhat[ls:] = _apply(C, allv)[ls:]
+    return uhat

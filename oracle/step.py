@@ -19,7 +19,7 @@ from .bweno import zone_b_mean, zone_b_modes
 from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
 from .positivity import limit_spatial, limit_spacetime
-from .predictor import predict_modal, predict_nodal_2, predict_nodal_3
+from .predictor import predict_modal, predict_nodal_2, predict_nodal_3, predict_nodal_4
 from .riemann import (hll, hll_combine, hll_speeds, linearized_euler, linearized_mhd_combine,
                       mhd_abs_jacobian)
 from .weno import reconstruct
@@ -28,7 +28,7 @@ from .weno import reconstruct
 @dataclass
 class OracleConfig:
     order: int = 3                 # 2, 3 or 4
-    form: str = 'modal'            # 'modal' (Sec. IV) or 'nodal' (App. A, B: orders 2, 3)
+    form: str = 'modal'            # 'modal' (Sec. IV) or 'nodal' (App. A, B, C)
     riemann: str = 'hll'           # 'hll' or 'linearized'
     gamma: float = 1.4
     lengths: tuple = (1.0, 1.0, 1.0)   # domain (lx, ly, lz)
@@ -79,7 +79,7 @@ def predictor(U, dt, cfg, B=None):
         elif cfg.order == 3:
             uhat = predict_nodal_3(what, dt, dx, cfg.gamma)
         else:
-            raise NotImplementedError('nodal formulation is built at orders 2 and 3')
+            uhat = predict_nodal_4(what, dt, dx, cfg.gamma)
     else:
         uhat = predict_modal(what, cfg.order, dt, dx, cfg.gamma)
     return limit_spacetime(uhat, cfg.order, cfg.form, cfg.gamma)

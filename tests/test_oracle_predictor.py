@@ -2,6 +2,8 @@
 and predictor (Sec. II.1-II.2, Sec. IV, App. A) against facts the paper and
 the mathematics fix."""
 
+import os
+
 import numpy as np
 import pytest
 import sympy as sp
@@ -198,6 +200,51 @@ def test_nodal_B5_recovers_the_modes():
     assert np.allclose(got, uhat[10:], rtol=0, atol=1e-13)
 
 
+def _read_app_c():
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), 'golden', 'app_c_nodal4.txt')) as fh:
+        for line in fh:
+            if line.startswith('#') or not line.strip():
+                continue
+            name, d, den, *pairs = line.split()
+            coef = {int(k): int(v) for k, v in (p.split(':') for p in pairs)}
+            rows.append((name, 'fgh'.index(d), int(den), coef))
+    return rows
+
+
+def test_nodal_C2_C3_printed_coefficients():
+    # the Galerkin map behind App. C must reproduce the coefficients the
+    # paper prints for the temporaries q_21, q_22, q_23 (C.2) and the
+    # later-node flux terms of u_21, u_22 (C.3)
+    nodes, t0, lt, Au, Af, Ag, Ah, C = pr.nodal_update_map(4)
+    A = (Af, Ag, Ah)
+    rows = _read_app_c()
+    assert len(rows) == 15
+    for name, d, den, coef in rows:
+        k = int(name[1:]) - 21          # later node 21 + k
+        for node, c in coef.items():
+            got = A[d][k, node - 1] * den
+            assert abs(got - c) < 1e-6 * max(1.0, abs(c)), (name, 'fgh'[d], node, got, c)
+    # the u terms of the temporaries: q_21 = u_1 + ..., q_22 = u_3 + ..., q_23 = u_4 + ...
+    for k, j in ((0, 1), (1, 3), (2, 4)):
+        ref = np.zeros(len(t0))
+        ref[j - 1] = 1.0
+        assert np.allclose(Au[k], ref, rtol=0, atol=1e-12)
+
+
+def test_nodal_map_at_third_order_is_B2_B3():
+    # the same Galerkin construction over the nodes (B.1) gives the
+    # explicit (B.2)-(B.3) of the third-order oracle
+    nodes, t0, lt, Au, Af, Ag, Ah, C = pr.nodal_update_map(3)
+    rng = np.random.default_rng(5)
+    u = [None] + list(rng.normal(size=10))
+    F, G, H = ([None] + list(rng.normal(size=15)) for _ in range(3))
+    got = pr.nodal3_b3(pr.nodal3_b2(u, F, G, H), F, G, H)
+    ref = Au @ np.array(u[1:]) + Af @ np.array(F[1:]) + Ag @ np.array(G[1:]) + Ah @ np.array(H[1:])
+    for k in range(11, 16):
+        assert abs(got[k] - ref[k - 11]) < 1e-12
+
+
 def _linear_flux(adv):
     return lambda u, axis: adv[axis] * u
 
@@ -210,7 +257,7 @@ def _spatial_value(what, order, point):
 
 
 @pytest.mark.parametrize("order,form", [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'),
-                                        (4, 'modal')])
+                                        (4, 'modal'), (4, 'nodal')])
 def test_predictor_exact_for_linear_advection(order, form):
     # constant-coefficient linear flux on data of degree <= M-1: the
     # space-time polynomial must be w(x - c tau) after M-1 iterations
@@ -221,7 +268,7 @@ def test_predictor_exact_for_linear_advection(order, form):
     dt, dx = 0.05, (0.1, 0.2, 0.125)
     c = adv * dt / np.array(dx)
     if form == 'nodal':
-        nodal = {2: pr.predict_nodal_2, 3: pr.predict_nodal_3}[order]
+        nodal = {2: pr.predict_nodal_2, 3: pr.predict_nodal_3, 4: pr.predict_nodal_4}[order]
         uhat = nodal(what, dt, dx, 1.4, flux_fn=_linear_flux(adv))
     else:
         uhat = pr.predict_modal(what, order, dt, dx, 1.4, flux_fn=_linear_flux(adv))
@@ -229,4 +276,6 @@ def test_predictor_exact_for_linear_advection(order, form):
         tau = p[3] + 0.5
         got = indep.st_value(uhat[:, 0], order, (p[0], p[1], p[2], tau))
         ref = _spatial_value(what[:, 0], order, p[:3] - c * tau)
-        assert abs(got - ref) < 1e-13
+        # the fourth-order nodal map is formed in floating point (inverses of
+        # the 35-node Vandermonde and Galerkin matrices), hence the looser bound
+        assert abs(got - ref) < (1e-12 if (order, form) == (4, 'nodal') else 1e-13)

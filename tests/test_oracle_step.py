@@ -11,7 +11,7 @@ from oracle.physics import conserved, primitives
 
 GOLDEN = os.path.join(os.path.dirname(__file__), 'golden')
 
-CONFIGS = [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'), (4, 'modal')]
+CONFIGS = [(2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'), (4, 'modal'), (4, 'nodal')]
 
 
 @pytest.mark.parametrize("order,form", CONFIGS)
@@ -116,7 +116,8 @@ def _read_golden_rates():
 @pytest.mark.parametrize("order,sizes,T,form", [(2, (16, 32), 0.02, 'modal'),
                                                (3, (8, 16), 0.05, 'modal'),
                                                (3, (8, 16), 0.05, 'nodal'),
-                                               (4, (8, 16), 0.05, 'modal')])
+                                               (4, (8, 16), 0.05, 'modal'),
+                                               (4, (8, 16), 0.05, 'nodal')])
 def test_design_order_density_wave(order, sizes, T, form):
     # Table IV demonstrates L1 rates near the design order on a smooth
     # diagonal density wave; the oracle must reach its design order too, in
@@ -157,9 +158,9 @@ def test_modal_blast_is_mirror_symmetric(order):
     assert np.abs(rho - rho[::-1, ::-1, ::-1]).max() < 1e-12
 
 
-@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("order", [2, 3, 4])
 def test_nodal_blast_is_not_mirror_symmetric(order):
-    # Sec. VIII.3: the asymmetric nodes of App. A and B break the mirror symmetry
+    # Sec. VIII.3: the asymmetric nodes of App. A, B and C break the mirror symmetry
     cfg = OracleConfig(order=order, form='nodal', riemann='hll')
     U = _blast(10)
     for _ in range(4):
