@@ -33,7 +33,8 @@ WORKLOAD = "sedov-modes-128^3"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
 PUBLISHED_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
-LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves"}
+LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves",
+                5: "pair", 6: "pair-2waves"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
 
 
@@ -112,7 +113,8 @@ def flop_counts():
         return json.load(fh)["counts"]
 
 
-def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None, key=""):
+def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=None, key="",
+                form=None):
     """Autotune the launch shapes, time `steps` graph-replayed CFL steps
     (wall clock between synchronisations), then take a separate eager pass
     with per-stage HIP events for the stage breakdown."""
@@ -122,7 +124,8 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
     mhd = B0 is not None
     s = ader.Solver(SHAPE, order=order, riemann=riemann, precision=precision,
                     stream=stream.cuda_stream, gamma=5.0 / 3.0 if mhd else 1.4,
-                    system=ader.ADER_MHD if mhd else ader.ADER_EULER)
+                    system=ader.ADER_MHD if mhd else ader.ADER_EULER,
+                    form=ader.ADER_MODAL if form is None else form)
     try:
         with torch.cuda.stream(stream):
             dU = torch.from_numpy(U0).to("cuda")            # resident state, 5 x N doubles
@@ -286,7 +289,7 @@ def hbm_stages(pv, N, dtype, probes):
     return out
 
 
-def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
+def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None, form=None):
     """Untimed accuracy pass of the mixed path: the FP64 path takes `steps`
     CFL steps, the mixed path repeats them with the same dt sequence, and the
     relative L1 distance (largest over the variables) is reported.  With
@@ -294,10 +297,13 @@ def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
     estimates the truncation error of the scheme at this resolution."""
     mhd = B0 is not None
     kw = dict(order=order, riemann=riemann, gamma=5.0 / 3.0 if mhd else 1.4,
-              system=ader.ADER_MHD if mhd else ader.ADER_EULER)
+              system=ader.ADER_MHD if mhd else ader.ADER_EULER,
+              form=ader.ADER_MODAL if form is None else form)
 
-    def run(precision, dts=None, order_=None):
+    def run(precision, dts=None, order_=None, form_=None):
         args = dict(kw, order=order_ or order)
+        if form_ is not None:
+            args["form"] = form_
         with ader.Solver(SHAPE, precision=precision, **args) as s:
             s.set_state(U0, B0) if mhd else s.set_state(U0)
             out = []
@@ -319,7 +325,7 @@ def accuracy(ader, U0, order, riemann, steps, B0=None, trunc_order=None):
 
     res = {"steps": steps, "l1_rel_vs_fp64": rel(mix, ref)}
     if trunc_order:
-        hi, _ = run(ader.ADER_FP64, dts, trunc_order)
+        hi, _ = run(ader.ADER_FP64, dts, trunc_order, ader.ADER_MODAL)
         res["trunc_rel_estimate"] = rel(ref, hi)
         res["trunc_estimate"] = "order-%d FP64 result on the same steps" % trunc_order
         res["ratio"] = res["l1_rel_vs_fp64"] / res["trunc_rel_estimate"]
@@ -349,7 +355,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp64-hll,fp64-lin,mixed-hll,mixed-lin")
+    ap.add_argument("--variants",
+                    default="fp64-hll,fp64-lin,mixed-hll,mixed-lin,fp64-hll-nodal,mixed-hll-nodal",
+                    help="order-3 Euler runs: {fp64,mixed}-{hll,lin}[-nodal]")
     ap.add_argument("--mhd-variants", default="fp64,mixed,mixed-lin",
                     help="order-4 MHD runs on the 128^3 random-field workload: fp64, mixed "
                          "(HLL), fp64-lin, mixed-lin (linearized); '' for none")
@@ -398,9 +406,12 @@ def main():
     table = {"fp64-hll": (ader.ADER_FP64, ader.ADER_HLL), "fp64-lin": (ader.ADER_FP64, ader.ADER_LINEARIZED),
              "mixed-hll": (ader.ADER_MIXED, ader.ADER_HLL), "mixed-lin": (ader.ADER_MIXED, ader.ADER_LINEARIZED)}
     for name in args.variants.split(","):
-        prec, rs = table[name]
+        # "-nodal": the nodal predictor of App. B instead of the modal one
+        prec, rs = table[name.replace("-nodal", "")]
+        form = ader.ADER_NODAL if name.endswith("-nodal") else ader.ADER_MODAL
         log("variant", name, "warmup", args.warmup, "steps", args.steps)
-        variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup, key=name)
+        variants[name] = run_variant(ader, torch, U0, prec, rs, args.steps, args.warmup, key=name,
+                                     form=form)
         log("variant", name, "%.3e zone-updates/s" % variants[name]["zone_updates_per_s"])
 
     mhd_variants = {}
@@ -420,8 +431,10 @@ def main():
     for name in ([] if args.no_accuracy else variants):
         if name.startswith("mixed"):
             log("accuracy", name)
-            rs = ader.ADER_HLL if name.endswith("hll") else ader.ADER_LINEARIZED
-            variants[name]["accuracy"] = accuracy(ader, U0, 3, rs, 10, trunc_order=4)
+            base = name.replace("-nodal", "")
+            rs = ader.ADER_HLL if base.endswith("hll") else ader.ADER_LINEARIZED
+            form = ader.ADER_NODAL if name.endswith("-nodal") else ader.ADER_MODAL
+            variants[name]["accuracy"] = accuracy(ader, U0, 3, rs, 10, trunc_order=4, form=form)
     for name in ([] if args.no_accuracy else mhd_variants):
         if "mixed" in name:
             log("accuracy", name)
@@ -504,6 +517,11 @@ def main():
         "ensemble": ensemble,
         "turbulent_mhd": turbulent,
     }
+    for prec in ("fp64", "mixed"):
+        if prec + "-hll" in variants and prec + "-hll-nodal" in variants:
+            out.setdefault("nodal_over_modal", {})[prec + "-hll"] = (
+                variants[prec + "-hll-nodal"]["zone_updates_per_s"] /
+                variants[prec + "-hll"]["zone_updates_per_s"])
     if "mixed-hll" in variants and "fp64-hll" in variants:
         out["mixed_over_fp64"] = (variants["mixed-hll"]["zone_updates_per_s"] /
                                   variants["fp64-hll"]["zone_updates_per_s"])

@@ -47,7 +47,7 @@ typedef struct ader_ctx ader_ctx;
 enum {
   ADER_OK = 0,
   ADER_EINVAL = -1,        /* bad argument (size, order, gamma, dt, ...) */
-  ADER_EUNSUPPORTED = -2,  /* valid but not built (e.g. nodal at order 3) */
+  ADER_EUNSUPPORTED = -2,  /* valid but not built (e.g. a layout at an order it lacks) */
   ADER_ENOMEM = -3,        /* device allocation failed */
   ADER_EDEVICE = -4,       /* a HIP call failed */
   ADER_ESTATE = -5,        /* state has rho <= 0, P <= 0 or a non-finite value */
@@ -56,7 +56,7 @@ enum {
 
 enum { ADER_EULER = 0, ADER_MHD = 1 };         /* eq. (3) with B = 0; ideal MHD */
 enum { ADER_HLL = 0, ADER_LINEARIZED = 1 };     /* eq. (17)/(56); Sec. II.3 */
-enum { ADER_MODAL = 0, ADER_NODAL = 1 };        /* Sec. IV; App. A (order 2) */
+enum { ADER_MODAL = 0, ADER_NODAL = 1 };        /* Sec. IV; App. A, B, C (orders 2, 3, 4) */
 enum { ADER_FP64 = 0, ADER_MIXED = 1 };         /* all-FP64, or FP32 bulk with FP64
                                                    update and dt */
 
@@ -78,9 +78,9 @@ int ader_create(const ader_mesh* mesh, int system, int device, void* stream,
 /* Ratio of specific heats, gamma > 1 (eq. 3). */
 int ader_set_gamma(ader_ctx* ctx, double gamma);
 
-/* order in {2, 3, 4}; form ADER_MODAL (Sec. IV) or ADER_NODAL (App. A,
- * order 2 only: ADER_EUNSUPPORTED otherwise).  At order 2 the
- * reconstruction is minmod-limited linear; at 3 and 4 it is centred WENO. */
+/* order in {2, 3, 4}; form ADER_MODAL (Sec. IV) or ADER_NODAL (App. A, B, C
+ * at orders 2, 3, 4).  At order 2 the reconstruction is minmod-limited
+ * linear; at 3 and 4 it is centred WENO. */
 int ader_set_order(ader_ctx* ctx, int order, int form);
 
 /* ADER_HLL (eq. 17/56, Davis speeds from the barycentre states) or
@@ -214,13 +214,16 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * fit two waves per SIMD, ADER_LAYOUT_ZONE2, one lane per zone with the
  * facial positivity check in a pass of its own rather than inside the face
  * quadrature (orders 2 and 3 only), ADER_LAYOUT_ZONE_2W, one lane per zone
- * compiled to fit two waves per SIMD (Euler, orders 2 and 3 only), or -1 for
+ * compiled to fit two waves per SIMD (Euler, orders 2 and 3 only),
+ * ADER_LAYOUT_PAIR, two lanes per zone each holding four of the eight MHD
+ * variables and exchanging them for each flux (MHD, orders 3 and 4 only),
+ * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD, or -1 for
  * the default of the setting
  * (split for MHD at orders 3-4 and Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,
-       ADER_LAYOUT_ZONE_2W = 4 };
+       ADER_LAYOUT_ZONE_2W = 4, ADER_LAYOUT_PAIR = 5, ADER_LAYOUT_PAIR2 = 6 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
 

@@ -31,7 +31,7 @@ HIPCC_FLAGS = [
 
 VARIANTS = [(sys_, prec, order, form)
             for sys_ in ("euler", "mhd") for prec in ("fp64", "mixed")
-            for order, form in ((2, 0), (2, 1), (3, 0), (4, 0))]
+            for order, form in ((2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1))]
 
 
 def hipcc():

@@ -52,6 +52,8 @@ struct StageFns {
   int (*predict_split2)(ader_ctx*);   // the same, registers capped for 2 waves/SIMD
   int (*predict_zone2)(ader_ctx*);    // one lane per zone, facial check in its own pass
   int (*predict_zone_2w)(ader_ctx*);  // one lane per zone, registers capped for 2 waves/SIMD
+  int (*predict_pair)(ader_ctx*);     // MHD: two lanes per zone
+  int (*predict_pair2)(ader_ctx*);    // the same, registers capped for 2 waves/SIMD
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
 };
@@ -140,11 +142,15 @@ inline unsigned grid_for(const ader_ctx* c, int cls, int zones_per_wave = 64) {
 }
 
 // Stage tables of the variants, one translation unit each.
-#define ADER_VARIANTS(X)                                                     \
-  X(euler, fp64, 2, 0) X(euler, fp64, 2, 1) X(euler, fp64, 3, 0) X(euler, fp64, 4, 0) \
-  X(euler, mixed, 2, 0) X(euler, mixed, 2, 1) X(euler, mixed, 3, 0) X(euler, mixed, 4, 0) \
-  X(mhd, fp64, 2, 0) X(mhd, fp64, 2, 1) X(mhd, fp64, 3, 0) X(mhd, fp64, 4, 0)     \
-  X(mhd, mixed, 2, 0) X(mhd, mixed, 2, 1) X(mhd, mixed, 3, 0) X(mhd, mixed, 4, 0)
+#define ADER_VARIANTS(X)                                                                  \
+  X(euler, fp64, 2, 0) X(euler, fp64, 2, 1) X(euler, fp64, 3, 0) X(euler, fp64, 3, 1)     \
+  X(euler, fp64, 4, 0) X(euler, fp64, 4, 1)                                              \
+  X(euler, mixed, 2, 0) X(euler, mixed, 2, 1) X(euler, mixed, 3, 0) X(euler, mixed, 3, 1) \
+  X(euler, mixed, 4, 0) X(euler, mixed, 4, 1)                                             \
+  X(mhd, fp64, 2, 0) X(mhd, fp64, 2, 1) X(mhd, fp64, 3, 0) X(mhd, fp64, 3, 1)             \
+  X(mhd, fp64, 4, 0) X(mhd, fp64, 4, 1)                                                   \
+  X(mhd, mixed, 2, 0) X(mhd, mixed, 2, 1) X(mhd, mixed, 3, 0) X(mhd, mixed, 3, 1)         \
+  X(mhd, mixed, 4, 0) X(mhd, mixed, 4, 1)
 #define ADER_STAGES_NAME(sys, prec, order, form) stages_##sys##_##prec##_o##order##_f##form
 #define ADER_DECLARE_STAGES(sys, prec, order, form) \
   const StageFns* ADER_STAGES_NAME(sys, prec, order, form)();

@@ -91,6 +91,8 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
     case ADER_LAYOUT_SPLIT2: return s->predict_split2 != nullptr;
     case ADER_LAYOUT_ZONE2: return s->predict_zone2 != nullptr;
     case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w != nullptr;
+    case ADER_LAYOUT_PAIR: return s->predict_pair != nullptr;
+    case ADER_LAYOUT_PAIR2: return s->predict_pair2 != nullptr;
   }
   return false;
 }
@@ -107,6 +109,8 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_SPLIT2: return s->predict_split2(c);
     case ADER_LAYOUT_ZONE2: return s->predict_zone2(c);
     case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w(c);
+    case ADER_LAYOUT_PAIR: return s->predict_pair(c);
+    case ADER_LAYOUT_PAIR2: return s->predict_pair2(c);
     default: return s->predict(c);
   }
 }
@@ -417,7 +421,7 @@ int get_problem(ader_ctx* c, int q, double* U, double* B) {
 // of that stage alone) and keep the fastest.  The state is saved first and
 // restored at the end, so tuning does not advance the solution.
 // ---------------------------------------------------------------------------
-constexpr int kNumLayouts = 5;
+constexpr int kNumLayouts = 7;
 constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
                                        {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
 
@@ -550,7 +554,6 @@ int ader_set_gamma(ader_ctx* c, double gamma) {
 int ader_set_order(ader_ctx* c, int order, int form) {
   if (!c || order < 2 || order > 4) return ADER_EINVAL;
   if (form != ADER_MODAL && form != ADER_NODAL) return ADER_EINVAL;
-  if (form == ADER_NODAL && order != 2) return ADER_EUNSUPPORTED;
   c->order = order;
   c->form = form;
   return ADER_OK;
@@ -740,6 +743,9 @@ int ader_set_layout(ader_ctx* c, int layout) {
     return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_ZONE2 && c->order > 3) return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_ZONE_2W && (c->order > 3 || c->system == ADER_MHD))
+    return ADER_EUNSUPPORTED;
+  if ((layout == ADER_LAYOUT_PAIR || layout == ADER_LAYOUT_PAIR2) &&
+      (c->order < 3 || c->system != ADER_MHD))
     return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;

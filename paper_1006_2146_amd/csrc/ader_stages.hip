@@ -109,6 +109,29 @@ int predict_split(ader_ctx* c) {
   }
 }
 
+// the pair layout (MHD, orders 3 and 4): two lanes per zone; WAVES caps the
+// registers for that many waves per SIMD
+template <int WAVES>
+int predict_pair(ader_ctx* c) {
+  if constexpr (kMhd && kOrder >= 3) {
+    const unsigned g = grid_for(c, kClassPredict, 32);
+    const int bs = c->shape[kClassPredict].block;
+    const T* W = static_cast<const T*>(c->W);
+    T* PK = static_cast<T*>(c->PK);
+    const T* WB = static_cast<const T*>(c->WB);
+    const T* BN = static_cast<const T*>(c->BN);
+    if (c->riemann == ADER_LINEARIZED)
+      k_predict_mhd_pair<T, kOrder, kForm, WAVES, true><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma);
+    else
+      k_predict_mhd_pair<T, kOrder, kForm, WAVES, false><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma);
+    return launched();
+  } else {
+    return ADER_EUNSUPPORTED;
+  }
+}
+
 int flux(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassFlux);
   const int bs = c->shape[kClassFlux].block;
@@ -147,6 +170,8 @@ const StageFns kStages = {recon,
                           kOrder >= 3 ? predict_split<2> : nullptr,
                           kOrder <= 3 ? predict<false> : nullptr,
                           (!kMhd && kOrder <= 3) ? predict<true, 2> : nullptr,
+                          (kMhd && kOrder >= 3) ? predict_pair<1> : nullptr,
+                          (kMhd && kOrder >= 3) ? predict_pair<2> : nullptr,
                           flux,
                           update};
 

@@ -7,11 +7,13 @@ committed and compiled by ``build.py``.  Everything is derived here in exact
 rational arithmetic (``fractions.Fraction``) from the paper's definitions:
 
 * basis: Hermite P0..P3 (eq. 9) and tau^d (eq. 13), mode orders eq. (10)-(16);
-* predictor nodes: eq. (31), (37), (46) (modal) and (A.1) (nodal);
+* predictor nodes: eq. (31), (37), (46) (modal) and (A.1), (B.1) (nodal);
 * nodal-to-modal flux rules (33), (40)-(42), (49)-(51) composed with the
   evolution equations (30), (36), (45): every evolutionary mode becomes a
   weighted sum of the scaled nodal fluxes f = dt F/dx, g, h; the nodal
-  second-order update (A.4) (z-term read as h4 - h1) and (A.6) likewise;
+  second-order update (A.4) (z-term read as h4 - h1) and (A.6) likewise, and
+  the third-order (B.2), (B.3), (B.5) composed (their nodal values cancel,
+  leaving each evolutionary mode a weighted sum of nodal fluxes);
 * facial nodes (D.1)/(D.6)/(D.11) with the rules (D.4)/(D.9)/(D.14) composed
   with the face integrals (D.5)/(D.10)/(D.15): the face average of the
   normal flux is a weighted sum of facial nodal fluxes (nodes of zero weight
@@ -72,8 +74,21 @@ def point_row(order, pt):
 
 def pred_nodes(order, form):
     h, q, t1, t2 = HALF, QTR, THIRD, 2 * THIRD
-    if form == 'nodal':
+    if form == 'nodal' and order == 2:
         return [(0, 0, 0, 0), (h, 0, 0, 0), (0, h, 0, 0), (0, 0, h, 0), (0, 0, 0, 1)]
+    if form == 'nodal' and order == 3:
+        return [(0, 0, 0, 0), (h, 0, 0, 0), (-h, 0, 0, 0), (0, h, 0, 0), (0, -h, 0, 0),
+                (0, 0, h, 0), (0, 0, -h, 0), (0, h, h, 0), (h, 0, h, 0), (h, h, 0, 0),
+                (0, 0, 0, h), (h, 0, 0, h), (0, h, 0, h), (0, 0, h, h), (0, 0, 0, 1)]
+    if form == 'nodal':   # (C.1)
+        return [(0, 0, 0, 0), (h, h, h, 0), (h, 0, 0, 0), (-h, 0, 0, 0), (0, h, 0, 0),
+                (0, -h, 0, 0), (0, 0, h, 0), (0, 0, -h, 0), (0, h, h, 0), (-h, 0, h, 0),
+                (h, 0, h, 0), (h, -h, 0, 0), (h, h, 0, 0), (0, h, -h, 0),
+                (-q, -h, -h, 0), (q, -h, -h, 0), (-h, -q, -h, 0), (-h, q, -h, 0),
+                (-h, -h, -q, 0), (-h, -h, q, 0),
+                (0, 0, 0, t1), (h, 0, 0, t1), (-h, 0, 0, t1), (0, h, 0, t1), (0, -h, 0, t1),
+                (0, 0, h, t1), (0, 0, -h, t1), (0, h, h, t1), (h, 0, h, t1), (h, h, 0, t1),
+                (0, 0, 0, t2), (h, 0, 0, t2), (0, h, 0, t2), (0, 0, h, t2), (0, 0, 0, 1)]
     if order == 2:
         return [(h, 0, 0, 0), (-h, 0, 0, 0), (0, h, 0, 0), (0, -h, 0, 0),
                 (0, 0, h, 0), (0, 0, -h, 0), (0, 0, 0, 1)]
@@ -255,13 +270,169 @@ def rules_nodal2(f, g, h):
     return [-(f[2] - f[1]) * 2 - (g[3] - g[1]) * 2 - (h[4] - h[1]) * 2]
 
 
+def rules_nodal3(f, g, h):
+    # (B.2): temporaries from the tau = 0 nodes; (B.3) at one iterate; (B.5)
+    # to the modes tau, tau^2, xi tau, eta tau, zeta tau.  The nodal values u
+    # enter only as differences that (B.5) cancels.
+    u = unknowns('u', 15)
+    F = Fr(1, 24)
+    q11 = u[1] + (f[3] - f[1]) * HALF + (g[5] - g[1]) * HALF + (h[7] - h[1]) * HALF
+    q12 = u[2] + (f[1] * 36 - f[2] * 24 - f[3] * 12
+                  - g[1] * 36 + g[2] * 24 + g[4] * 24 + g[5] * 12 - g[10] * 24
+                  - h[1] * 36 + h[2] * 24 + h[6] * 24 + h[7] * 12 - h[9] * 24) * F
+    q13 = u[4] + (-f[1] * 36 + f[2] * 24 + f[3] * 12 + f[4] * 24 - f[10] * 24
+                  + g[1] * 36 - g[4] * 24 - g[5] * 12
+                  - h[1] * 36 + h[4] * 24 + h[6] * 24 + h[7] * 12 - h[8] * 24) * F
+    q14 = u[6] + (-f[1] * 36 + f[2] * 24 + f[3] * 12 + f[6] * 24 - f[9] * 24
+                  - g[1] * 36 + g[4] * 24 + g[5] * 12 + g[6] * 24 - g[8] * 24
+                  + h[1] * 36 - h[6] * 24 - h[7] * 12) * F
+    q15 = u[1] + (-f[1] * 60 + f[2] * 30 + f[3] * 30 - g[1] * 60 + g[4] * 30 + g[5] * 30
+                  - h[1] * 60 + h[6] * 30 + h[7] * 30) * Fr(1, 30)
+    q1 = (f[11] - f[12]) * HALF + (g[11] - g[13]) * HALF + (h[11] - h[14]) * HALF
+    n11, n12, n13, n14, n15 = q11 + q1, q12 + q1, q13 + q1, q14 + q1, q15 + q1 * 4
+    m12 = (n15 - n11 * 2 + u[1]) * 2
+    m11 = (n11 - u[1] - m12 * QTR) * 2
+    m13 = (n12 - n11 - u[2] + u[1]) * 4
+    m14 = (n13 - n11 - u[4] + u[1]) * 4
+    m15 = (n14 - n11 - u[6] + u[1]) * 4
+    out = [m11, m12, m13, m14, m15]
+    for m in out:
+        assert all(k[0] != 'u' for k in m), m
+    return out
+
+
+# exact polynomial algebra for the fourth-order nodal derivation: a
+# polynomial is {(a, b, c, d): coefficient} for xi^a eta^b zeta^c tau^d
+P_POW = [{0: Fr(1)}, {1: Fr(1)}, {2: Fr(1), 0: Fr(-1, 12)}, {3: Fr(1), 1: Fr(-3, 20)}]
+
+
+def _mode_poly(m):
+    a, b, c, d = m
+    out = {}
+    for pa, ca in P_POW[a].items():
+        for pb, cb in P_POW[b].items():
+            for pc, cc in P_POW[c].items():
+                k = (pa, pb, pc, d)
+                out[k] = out.get(k, 0) + ca * cb * cc
+    return out
+
+
+def _poly_add(p, q, s=Fr(1)):
+    r = dict(p)
+    for k, v in q.items():
+        r[k] = r.get(k, 0) + s * v
+    return {k: v for k, v in r.items() if v != 0}
+
+
+def _poly_mul(p, q):
+    out = {}
+    for k1, v1 in p.items():
+        for k2, v2 in q.items():
+            k = tuple(a + b for a, b in zip(k1, k2))
+            out[k] = out.get(k, 0) + v1 * v2
+    return out
+
+
+def _poly_diff(p, axis):
+    out = {}
+    for k, v in p.items():
+        if k[axis]:
+            kk = list(k)
+            kk[axis] -= 1
+            out[tuple(kk)] = out.get(tuple(kk), 0) + v * k[axis]
+    return out
+
+
+def _integral(p):
+    """Over xi, eta, zeta in [-1/2, 1/2] and tau in [0, 1]."""
+    s = Fr(0)
+    for (a, b, c, d), v in p.items():
+        if a % 2 or b % 2 or c % 2:
+            continue
+        s += v * Fr(1, 2 ** a * (a + 1)) * Fr(1, 2 ** b * (b + 1)) * Fr(1, 2 ** c * (c + 1)) / (d + 1)
+    return s
+
+
+def _inverse(A):
+    n = len(A)
+    M = [list(row) + [Fr(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        pv = M[c][c]
+        M[c] = [x / pv for x in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [x - f * y for x, y in zip(M[r], M[c])]
+    return [row[n:] for row in M]
+
+
+def rules_nodal4(f, g, h):
+    # App. C: the nodal update of (C.2)-(C.3) is the continuous-Galerkin
+    # system written with the nodal basis of (C.1): u and the fluxes
+    # interpolated on it, the residual u_tau + f_xi + g_eta + h_zeta
+    # orthogonal to the basis functions of the 15 later nodes.  Solved for the
+    # later nodal values and mapped back to modes 21-35, the tau = 0 nodal
+    # values cancel and each evolutionary mode is a weighted sum of fluxes.
+    nodes = pred_nodes(4, 'nodal')
+    modes = mode_list(4)
+    n = len(nodes)
+    mp = [_mode_poly(m) for m in modes]
+    V = [[sum(v * Fr(x[0]) ** k[0] * Fr(x[1]) ** k[1] * Fr(x[2]) ** k[2] * Fr(x[3]) ** k[3]
+              for k, v in mp[m].items()) for m in range(n)] for x in nodes]
+    Ci = _inverse(V)                      # mode m = sum_j Ci[m][j] u_j
+    basis = []
+    for j in range(n):
+        p = {}
+        for m in range(n):
+            if Ci[m][j] != 0:
+                p = _poly_add(p, mp[m], Ci[m][j])
+        basis.append(p)
+    t0 = [j for j in range(n) if nodes[j][3] == 0]
+    lt = [j for j in range(n) if nodes[j][3] != 0]
+    dB = [[_poly_diff(basis[j], ax) for ax in range(4)] for j in range(n)]
+    E = [[_integral(_poly_mul(basis[i], dB[j][3])) for j in range(n)] for i in lt]
+    D = [[[_integral(_poly_mul(basis[i], dB[j][ax])) for j in range(n)] for i in lt]
+         for ax in range(3)]
+    Ei = _inverse([[E[r][j] for j in lt] for r in range(len(lt))])
+    u = unknowns('u', n)
+    flx = (f, g, h)
+    later = []
+    for r in range(len(lt)):
+        v = Lin()
+        for s in range(len(lt)):
+            c = Ei[r][s]
+            if c == 0:
+                continue
+            for j in t0:
+                if E[s][j] != 0:
+                    v = v - u[j + 1] * (c * E[s][j])
+            for ax in range(3):
+                for j in range(n):
+                    if D[ax][s][j] != 0:
+                        v = v - flx[ax][j + 1] * (c * D[ax][s][j])
+        later.append(v)
+    value = {j: u[j + 1] for j in t0}
+    value.update({j: later[r] for r, j in enumerate(lt)})
+    out = []
+    for m in range(LS[4], n):
+        v = Lin()
+        for j in range(n):
+            if Ci[m][j] != 0:
+                v = v + value[j] * Ci[m][j]
+        assert all(k[0] != 'u' for k in v), m
+        out.append(v)
+    return out
+
+
 def evolution_weights(order, form):
     """W[k] = {(dir, node): weight}: evolutionary mode k as a combination of
     the scaled nodal fluxes (dir 'f', 'g', 'h'; nodes 1-based)."""
     n = len(pred_nodes(order, form))
     f, g, h = unknowns('f', n), unknowns('g', n), unknowns('h', n)
     if form == 'nodal':
-        return rules_nodal2(f, g, h)
+        return {2: rules_nodal2, 3: rules_nodal3, 4: rules_nodal4}[order](f, g, h)
     return {2: rules_o2, 3: rules_o3, 4: rules_o4}[order](f, g, h)
 
 
@@ -860,7 +1031,8 @@ def main():
         "namespace ader_gen {",
     ]
     global SYSTEM
-    for order, form in ((2, 'modal'), (2, 'nodal'), (3, 'modal'), (4, 'modal')):
+    for order, form in ((2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'), (4, 'modal'),
+                        (4, 'nodal')):
         SYSTEM = 'euler'
         lines += gen_order(order, form)
         for SYSTEM in ('mhd', 'euler-dev', 'mhd-dev'):   # same code, counted again

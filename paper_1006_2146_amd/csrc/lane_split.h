@@ -269,4 +269,241 @@ __device__ __forceinline__ void predict_zone_mhd_split(
   side(std::integral_constant<int, 5>{});
 }
 
+// ---------------------------------------------------------------------------
+// Pair layout (MHD): two lanes per zone, lane g in {0, 1} of a zone holding
+// variables 4g .. 4g+3 (rho, m | E, B), so a lane keeps half of the zone's
+// modes and accumulators and a whole state costs one exchange of four
+// values with the partner lane; the flux is evaluated twice per point (once
+// per lane) where the one-variable split evaluates it eight times.  L.var is
+// the lane's group g, and a wave serves Z = 32 zones.
+constexpr int kPairVars = 4;
+
+// full = the zone's whole state from this lane's half and its partner's
+template <int VPL, class T>
+__device__ __forceinline__ void pair_gather(const SplitLane& L, const T (&own)[VPL],
+                                            T (&full)[2 * VPL]) {
+  const int other = (L.var ^ 1) * L.Z + L.z;
+#pragma unroll
+  for (int k = 0; k < VPL; ++k) {
+    const T o = lane_read(own[k], other);
+    full[k] = L.var == 0 ? own[k] : o;
+    full[VPL + k] = L.var == 0 ? o : own[k];
+  }
+}
+
+// this lane's half of a whole vector
+template <int VPL, class T>
+__device__ __forceinline__ void pair_pick(const SplitLane& L, const T (&full)[2 * VPL],
+                                          T (&out)[VPL]) {
+#pragma unroll
+  for (int k = 0; k < VPL; ++k) out[k] = L.var == 0 ? full[k] : full[VPL + k];
+}
+
+template <class P, class T, bool DEV>
+struct PairFlux {
+  static constexpr bool kDeviation = DEV;
+  // variable c sits at index c % 4 of the lane that holds it
+  static constexpr int comp(int c) { return c % kPairVars; }
+  typename FluxOf<P, T, DEV>::type inner;
+  SplitLane L;
+  template <int AXIS>
+  __device__ inline void flux(const T (&u)[kPairVars], T (&f)[kPairVars]) const {
+    T full[2 * kPairVars], fl[2 * kPairVars];
+    pair_gather(L, u, full);
+    inner.template flux<AXIS>(full, fl);
+    pair_pick(L, fl, f);
+  }
+};
+
+template <class T, bool DEV>
+struct PairScan {
+  static constexpr bool kDeviation = DEV;
+  PosScan<T, 2 * kPairVars, DEV> inner;
+  SplitLane L;
+  __device__ void operator()(const T (&u)[kPairVars]) {
+    T full[2 * kPairVars];
+    pair_gather(L, u, full);
+    inner(full);
+  }
+};
+
+// Exact positivity pass (rare) of the pair layout: this lane's half at each
+// check point in double, the other half from the partner.
+template <int NP, int LS, class T>
+__device__ double theta_spatial_pair(const SplitLane& L, const double (&w0)[8],
+                                     const T (&w)[LS][kPairVars], const double (&phi)[NP][LS],
+                                     double gam) {
+  PosTheta<T, 8> acc(w0, gam);
+  double own0[kPairVars];
+  pair_pick(L, w0, own0);
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    double s[kPairVars];
+#pragma unroll
+    for (int k = 0; k < kPairVars; ++k) {
+      s[k] = own0[k];
+#pragma unroll
+      for (int m = 1; m < LS; ++m) s[k] += phi[p][m] * double(w[m][k]);
+    }
+    double u[8];
+    pair_gather(L, s, u);
+    acc(u);
+  }
+  return acc.theta;
+}
+
+template <int NP, int LS, int NE, class T>
+__device__ double theta_facial_pair(const SplitLane& L, const double (&w0)[8],
+                                    const T (&w)[LS][kPairVars], const T (&e)[NE][kPairVars],
+                                    const double (&phi)[NP][LS + NE], double gam) {
+  PosTheta<T, 8> acc(w0, gam);
+  double own0[kPairVars];
+  pair_pick(L, w0, own0);
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    double s[kPairVars];
+#pragma unroll
+    for (int k = 0; k < kPairVars; ++k) {
+      s[k] = own0[k];
+#pragma unroll
+      for (int m = 1; m < LS; ++m) s[k] += phi[p][m] * double(w[m][k]);
+#pragma unroll
+      for (int m = 0; m < NE; ++m) s[k] += phi[p][LS + m] * double(e[m][k]);
+    }
+    double u[8];
+    pair_gather(L, s, u);
+    acc(u);
+  }
+  return acc.theta;
+}
+
+// The same operations as predict_zone_mhd, in the pair layout.  EDGES_ALL:
+// every variable's edge averages are stored (linearized flux), else only the
+// field component each edge needs.
+template <class T, int ORDER, int FORM, bool DEV, bool EDGES_ALL>
+__device__ __forceinline__ void predict_zone_mhd_pair(
+    const SplitLane& L, const double* __restrict__ U, const T* __restrict__ W,
+    const double* __restrict__ B0, const T* __restrict__ WB, const T* __restrict__ BN,
+    T* __restrict__ PK, const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz,
+    double gam, long long n) {
+  constexpr int VPL = kPairVars;
+  using S = typename SchemeOf<ORDER, FORM, T, VPL>::type;
+  constexpr int LS = S::LS, NE = S::NE;
+  double w0[8];
+  {
+    RowCursor<const double> ru(U, g.S, n), rb(B0, g.S, n);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w0[v] = ru.row(v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w0[5 + c] = rb.row(c);
+  }
+  const int v0 = L.var * VPL;   // first variable of this lane
+  T w[LS][VPL];
+  {
+    double own0[VPL];
+    pair_pick(L, w0, own0);
+#pragma unroll
+    for (int k = 0; k < VPL; ++k) w[0][k] = DEV ? T(0) : T(own0[k]);
+  }
+  // this lane's modes: variable v from row (m-1) * 5 + v of W (v < 5) or
+  // (m-1) * 3 + v - 5 of WB
+#pragma unroll
+  for (int k = 0; k < VPL; ++k) {
+    const int v = v0 + k;
+    const bool field = v >= 5;
+    const T* q = field ? WB + (long long)(v - 5) * g.S + n : W + (long long)v * g.S + n;
+    const long long stride = (long long)(field ? 3 : 5) * g.S;
+#pragma unroll
+    for (int m = 1; m < LS; ++m) {
+      w[m][k] = *q;
+      q = next_row(q, stride);
+    }
+  }
+  // the Sec. III normal moments on the pure-normal slots of the field lane
+  if (L.var == 1) {
+    RowCursor<const T> rn(BN, g.S, n);
+#pragma unroll
+    for (int a = 1; a < ORDER; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int m = spatial_mode(c == 0 ? a : 0, c == 1 ? a : 0, c == 2 ? a : 0);
+        w[m][1 + c] = rn.row((a - 1) * 3 + c);
+      }
+  }
+  {
+    PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
+    S::spatial_points_all(w, scan);
+    const double theta =
+        scan.inner.near ? theta_spatial_pair(L, w0, w, S::spatial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) w[m][k] *= th;
+    }
+  }
+  const PairFlux<Mhd<T>, T, DEV> ph{FluxOf<Mhd<T>, T, DEV>::make(w0, gam), L};
+  T e[NE][VPL];
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  {
+    PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
+    S::facial_points_all(w, e, scan);
+    const double theta =
+        scan.inner.near ? theta_facial_pair(L, w0, w, e, S::facial_phi_all, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) w[m][k] *= th;
+#pragma unroll
+      for (int m = 0; m < NE; ++m)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) e[m][k] *= th;
+    }
+  }
+  auto side = [&](auto side_c) {
+    constexpr int SIDE = decltype(side_c)::value;
+    constexpr int AX = SIDE / 2;
+    constexpr int TA0 = AX == 0 ? 1 : 0, TA1 = AX == 2 ? 1 : 2;   // transverse axes
+    T ub[VPL], ua[VPL], fa[VPL], ue[4], fe[4];
+    NoScan none;
+    S::template side_edges<SIDE>(w, e, ph, none, ub, ua, fa, ue, fe);
+    T* base = PK + (long long)SIDE * kMhdSlots * g.S + n;
+    RowCursor<T> r(base + (long long)v0 * g.S, g.S, 0);
+#pragma unroll
+    for (int k = 0; k < VPL; ++k) r.row(k) = ub[k];
+#pragma unroll
+    for (int k = 0; k < VPL; ++k) r.row(8 + k) = ua[k];
+#pragma unroll
+    for (int k = 0; k < VPL; ++k) r.row(16 + k) = fa[k];
+    if constexpr (EDGES_ALL) {
+      T ues[4][VPL];
+      S::template edge_states<SIDE, DEV>(w, e, ues);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) r.row(mhd_ue_slot(q, k)) = ues[q][k];
+    }
+    // the field lane has the field components along the edges' transverse
+    // axes: their edge averages (HLL) and their edge fluxes
+    if (L.var == 1) {
+      RowCursor<T> rf(base, g.S, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rf.row(mhd_fe_slot(q)) = fe[q];
+      if constexpr (!EDGES_ALL) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rf.row(mhd_ue_slot(q, 5 + (q < 2 ? TA0 : TA1))) = ue[q];
+      }
+    }
+  };
+  side(std::integral_constant<int, 0>{});
+  side(std::integral_constant<int, 1>{});
+  side(std::integral_constant<int, 2>{});
+  side(std::integral_constant<int, 3>{});
+  side(std::integral_constant<int, 4>{});
+  side(std::integral_constant<int, 5>{});
+}
+
 }  // namespace ader

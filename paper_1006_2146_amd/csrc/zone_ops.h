@@ -435,7 +435,9 @@ struct SchemeOf;
 template <class T, int NV> struct SchemeOf<2, 0, T, NV> { using type = ader_gen::SchemeM2<T, NV>; };
 template <class T, int NV> struct SchemeOf<2, 1, T, NV> { using type = ader_gen::SchemeN2<T, NV>; };
 template <class T, int NV> struct SchemeOf<3, 0, T, NV> { using type = ader_gen::SchemeM3<T, NV>; };
+template <class T, int NV> struct SchemeOf<3, 1, T, NV> { using type = ader_gen::SchemeN3<T, NV>; };
 template <class T, int NV> struct SchemeOf<4, 0, T, NV> { using type = ader_gen::SchemeM4<T, NV>; };
+template <class T, int NV> struct SchemeOf<4, 1, T, NV> { using type = ader_gen::SchemeN4<T, NV>; };
 
 // Side SIDE's packet, rows SIDE*15 .. SIDE*15+14 of PK (u_b, <u>, <F>, each
 // for the five variables); q walks the rows and is left at the next side.

@@ -35,6 +35,10 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
       predict_zone<T, 2, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
       predict_zone<T, 2, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 3 && form == 1)
+      predict_zone<T, 3, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 4 && form == 1)
+      predict_zone<T, 4, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
       predict_zone<T, 3, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else
@@ -100,6 +104,10 @@ static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, dou
       predict_zone_mhd<T, 2, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
       predict_zone_mhd<T, 2, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 3 && form == 1)
+      predict_zone_mhd<T, 3, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+    else if (order == 4 && form == 1)
+      predict_zone_mhd<T, 4, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
       predict_zone_mhd<T, 3, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
     else

@@ -43,7 +43,8 @@ def _advance(s, T, cfl=0.3):
 @pytest.mark.parametrize("layout", [-1, ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT2,
                                     ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W])
 @pytest.mark.parametrize("order,form,rs", [(2, "nodal", "hll"), (3, "modal", "hll"),
-                                           (3, "modal", "linearized"), (4, "modal", "hll")])
+                                           (3, "modal", "linearized"), (3, "nodal", "hll"),
+                                           (4, "modal", "hll"), (4, "nodal", "hll")])
 def test_mixed_step_close_to_oracle(order, form, rs, layout):
     if order == 2 and layout in (ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2):
         pytest.skip("the lane-split layout is built for orders 3 and 4")
@@ -94,6 +95,35 @@ def test_mixed_error_vs_truncation(order, n, rs):
     err = np.abs(res[ader.ADER_MIXED][0] - res[ader.ADER_FP64][0]).mean()
     say("  trunc %.3e mixed %.3e ratio %.2e" % (trunc, err, err / trunc))
     assert err <= BOUND[(order, n)] * trunc
+
+
+MHD_LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT2, ader.ADER_LAYOUT_PAIR,
+               ader.ADER_LAYOUT_PAIR2]
+
+
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("layout", MHD_LAYOUTS)
+@pytest.mark.parametrize("order", [3, 4])
+def test_mixed_mhd_step_close_to_oracle(order, layout, rs):
+    # every MHD predictor layout of the mixed path, one step after another
+    # against the FP64 oracle on a ragged random-field mesh
+    U, B = workloads.mhd_random_field((7, 9, 10), seed=40 + order)
+    cfg = OracleConfig(order=order, gamma=G53, riemann=rs)
+    with ader.Solver((7, 9, 10), order=order, gamma=G53, precision=ader.ADER_MIXED,
+                     riemann=ader.ADER_HLL if rs == "hll" else ader.ADER_LINEARIZED,
+                     system=ader.ADER_MHD) as s:
+        ader.ader_set_layout(s.ctx, layout)
+        assert ader.ader_get_layout(s.ctx) == layout
+        s.set_state(U, B)
+        for it in range(2):
+            say("mixed mhd layout", layout, order, rs, "step", it)
+            dt = s.compute_dt(0.3)
+            s.step(dt)
+            Ug, Bg = s.get_state()
+            Uo, Bo = oracle_step(U, dt, cfg, B)
+            assert np.all(rel_l1(Ug, Uo) <= 1e-6), (it, rel_l1(Ug, Uo))
+            assert np.all(rel_l1(Bg, Bo) <= 1e-6), (it, rel_l1(Bg, Bo))
+            U, B = Ug, Bg
 
 
 @pytest.mark.parametrize("order", [2, 3, 4])

@@ -16,8 +16,9 @@ RS = {"hll": ader.ADER_HLL, "linearized": ader.ADER_LINEARIZED}
 FORM = {"modal": ader.ADER_MODAL, "nodal": ader.ADER_NODAL}
 
 CASES = [(2, "modal", "hll"), (2, "nodal", "hll"), (2, "modal", "linearized"),
-         (3, "modal", "hll"), (3, "modal", "linearized"),
-         (4, "modal", "hll"), (4, "modal", "linearized")]
+         (3, "modal", "hll"), (3, "modal", "linearized"), (3, "nodal", "hll"),
+         (3, "nodal", "linearized"), (4, "modal", "hll"), (4, "modal", "linearized"),
+         (4, "nodal", "hll")]
 
 
 def rel_l1(a, b):
@@ -149,7 +150,7 @@ def test_config2_full_size_sampled(rs):
 # ----------------------------------------------------------------- MHD ------
 
 G53 = 5.0 / 3.0
-MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
+MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (3, "nodal"), (4, "modal"), (4, "nodal")]
 
 
 def _mhd_solver(shape, order, form, lengths=(1.0, 1.0, 1.0), precision=ader.ADER_FP64, rs="hll"):
@@ -199,7 +200,8 @@ def test_mhd_linearized_layouts():
     # the linearized MHD flux in every layout that carries full edge states
     U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=31)
     cfg = OracleConfig(order=3, gamma=G53, riemann="linearized")
-    for layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2):
+    for layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
+                   ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2):
         with _mhd_solver((6, 7, 8), 3, "modal", rs="linearized") as s:
             ader.ader_set_layout(s.ctx, layout)
             s.set_state(U0, B0)
@@ -237,7 +239,8 @@ def test_config3_mhd_full_size_sampled():
 # --------------------------------------------------------- predictor layouts --
 
 LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
-           ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W]
+           ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W, ader.ADER_LAYOUT_PAIR,
+           ader.ADER_LAYOUT_PAIR2]
 
 
 def _skip_unbuilt(layout, order, mhd=False):
@@ -246,6 +249,8 @@ def _skip_unbuilt(layout, order, mhd=False):
                     "orders 2 and 3")
     if layout == ader.ADER_LAYOUT_ZONE_2W and (order > 3 or mhd):
         pytest.skip("the two-wave one-lane-per-zone instance is built for Euler at orders 2-3")
+    if layout in (ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2) and (order < 3 or not mhd):
+        pytest.skip("the pair layout is built for MHD at orders 3-4")
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)

@@ -13,8 +13,9 @@ from paper_1006_2146_amd import workloads
 from tests import hostemu
 
 CASES = [(2, "modal", "hll"), (2, "nodal", "hll"), (2, "modal", "linearized"),
-         (3, "modal", "hll"), (3, "modal", "linearized"),
-         (4, "modal", "hll"), (4, "modal", "linearized")]
+         (3, "modal", "hll"), (3, "modal", "linearized"), (3, "nodal", "hll"),
+         (3, "nodal", "linearized"), (4, "modal", "hll"), (4, "modal", "linearized"),
+         (4, "nodal", "hll")]
 
 
 def rel_l1(a, b):
@@ -64,7 +65,7 @@ def test_kernel_source_tiny_meshes(order, precision):
         _steps(workloads.random_smooth(shape, seed=3), order, "modal", "hll", 1, precision=precision)
 
 
-MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (4, "modal")]
+MHD_CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (3, "nodal"), (4, "modal"), (4, "nodal")]
 
 
 def _steps_mhd(U0, B0, order, form, nsteps, lengths=(1.0, 1.0, 1.0), cfl=0.3, precision="fp64",
