@@ -10,7 +10,9 @@ and forms L(U) = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d, the right-hand side
 of eq. (4) written as dU/dt = L(U).  The stage combinations are those of
 eq. (18) (SSP-RK2), (19) (SSP-RK3) and (20) (the optimal five-stage,
 fourth-order scheme), matched to the spatial order 2, 3, 4 as in Sec. VII.
-Euler equations only.
+For ideal MHD the face fields advance with the same weights, their rate
+being minus the curl of the stage's edge fields (eq. 8 per unit time), and
+the zone field of Sec. III is rebuilt from the stage's face fields.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 """
@@ -19,7 +21,8 @@ import numpy as np
 
 from .basis import N_SPACETIME, N_SPATIAL
 from .positivity import limit_spatial
-from .step import _nb, face_fluxes
+from .bweno import zone_b_modes
+from .step import _nb, curl_e, face_fluxes, mhd_fluxes
 from .weno import reconstruct
 
 SCHEME_OF_ORDER = {2: 'ssprk2', 3: 'ssprk3', 4: 'ssprk54'}
@@ -37,6 +40,44 @@ def spatial_operator(U, cfg):
     for d in range(3):
         out = out - (_nb(flows[d], d, 1) - flows[d]) / dx[d]
     return out
+
+
+def mhd_operator(state, cfg):
+    """(L_U, L_B) for ideal MHD: the hydro flux divergence and minus the curl
+    of the edge fields, from the face-side packets of the spatial polynomial
+    of the eight variables (hydro from U, field from B by Sec. III)."""
+    U, B = state
+    dx = cfg.spacing(U.shape[1:])
+    what = np.concatenate([reconstruct(U, cfg.order), zone_b_modes(B, cfg.order)], axis=1)
+    what = limit_spatial(what, cfg.order, 'modal', cfg.gamma)
+    uhat = np.zeros((N_SPACETIME[cfg.order],) + what.shape[1:])
+    uhat[:N_SPATIAL[cfg.order]] = what
+    flows, E = mhd_fluxes(uhat, cfg)
+    LU = np.zeros_like(U)
+    for d in range(3):
+        LU = LU - (_nb(flows[d], d, 1) - flows[d]) / dx[d]
+    return _Pair(LU, -curl_e(E, dx))
+
+
+class _Pair:
+    """(U, B) with the linear operations the stage combinations use."""
+
+    def __init__(self, a, b):
+        self.a, self.b = a, b
+
+    def __add__(self, o):
+        return _Pair(self.a + o.a, self.b + o.b)
+
+    def __mul__(self, s):
+        return _Pair(self.a * s, self.b * s)
+
+    __rmul__ = __mul__
+
+    def __truediv__(self, s):
+        return _Pair(self.a / s, self.b / s)
+
+    def __iter__(self):
+        return iter((self.a, self.b))
 
 
 def ssp_step(U, dt, L, scheme):
@@ -65,3 +106,9 @@ def ssp_step(U, dt, L, scheme):
 def step_rk(U, dt, cfg):
     """One SSP-RK step of the order-matched scheme (Euler)."""
     return ssp_step(U, dt, lambda V: spatial_operator(V, cfg), SCHEME_OF_ORDER[cfg.order])
+
+
+def step_rk_mhd(U, B, dt, cfg):
+    """One SSP-RK step of ideal MHD: returns (U, B)."""
+    out = ssp_step(_Pair(U, B), dt, lambda S: mhd_operator(S, cfg), SCHEME_OF_ORDER[cfg.order])
+    return out.a, out.b

@@ -123,10 +123,21 @@ def step_mhd(U, B, dt, cfg):
     of appropriate components").
     """
     dx = cfg.spacing(U.shape[1:])
-    lin = cfg.riemann == 'linearized'
     uhat = predictor(U, dt, cfg, B)
+    flows, E = mhd_fluxes(uhat, cfg)
+    Un = U.copy()
+    for d in range(3):
+        Un = Un - dt / dx[d] * (_nb(flows[d], d, 1) - flows[d])
+    return Un, B - dt * curl_e(E, dx)
+
+
+def mhd_fluxes(uhat, cfg):
+    """Face fluxes of the five hydro variables at the lower face of every
+    zone along each axis, and the edge fields E_c at the lower c-edges, from
+    the space-time modes of the eight MHD variables."""
+    lin = cfg.riemann == 'linearized'
     flows = []
-    E = [np.zeros_like(U[0]) for _ in range(3)]
+    E = [np.zeros_like(uhat[0, 0]) for _ in range(3)]
     for d in range(3):
         plus = face_side_packet(uhat, cfg.order, d, +1, cfg.gamma, edges=True)
         minus = face_side_packet(uhat, cfg.order, d, -1, cfg.gamma, edges=True)
@@ -159,17 +170,18 @@ def step_mhd(U, B, dt, cfg):
             # edge at x_a = lower edge of this zone's face: own face (side -)
             # and the face of the zone below along a (side +)
             E[c] = E[c] + sgn * (fe[-1] + _nb(fe[1], a, -1))
-    E = [0.25 * e for e in E]
-    Un = U.copy()
-    for d in range(3):
-        Un = Un - dt / dx[d] * (_nb(flows[d], d, 1) - flows[d])
-    # eq. (8), with B_d at the lower d-face and E_c at the lower edge of the zone
+    return flows, [0.25 * e for e in E]
+
+
+def curl_e(E, dx):
+    """Eq. (8) per unit time: the face-field rate is minus this (B_d at the
+    lower d-face, E_c at the lower c-edge of the zone)."""
     Ex, Ey, Ez = E
-    Bn = B.copy()
-    Bn[0] = B[0] - dt * ((_nb(Ez, 1, 1) - Ez) / dx[1] - (_nb(Ey, 2, 1) - Ey) / dx[2])
-    Bn[1] = B[1] - dt * ((_nb(Ex, 2, 1) - Ex) / dx[2] - (_nb(Ez, 0, 1) - Ez) / dx[0])
-    Bn[2] = B[2] - dt * ((_nb(Ey, 0, 1) - Ey) / dx[0] - (_nb(Ex, 1, 1) - Ex) / dx[1])
-    return Un, Bn
+    out = np.empty((3,) + Ex.shape)
+    out[0] = (_nb(Ez, 1, 1) - Ez) / dx[1] - (_nb(Ey, 2, 1) - Ey) / dx[2]
+    out[1] = (_nb(Ex, 2, 1) - Ex) / dx[2] - (_nb(Ez, 0, 1) - Ez) / dx[0]
+    out[2] = (_nb(Ey, 0, 1) - Ey) / dx[0] - (_nb(Ex, 1, 1) - Ex) / dx[1]
+    return out
 
 
 def step(U, dt, cfg, B=None):

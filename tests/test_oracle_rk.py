@@ -92,3 +92,74 @@ def test_rk_design_order_density_wave(order, sizes, T):
         errs.append(np.abs(U[0] - _density_wave(n, T)[0]).mean())
     rate = np.log2(errs[0] / errs[1])
     assert rate > order - 0.6, (errs, rate)
+
+
+# ------------------------------------------------------------------- MHD --
+
+G53 = 5.0 / 3.0
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_rk_mhd_div_b_conservation_and_constant_state(order):
+    from oracle.bweno import divergence
+    from paper_1006_2146_amd import workloads
+    cfg = OracleConfig(order=order, gamma=G53, riemann='hll')
+    U, B = workloads.mhd_random_field((7, 8, 9), seed=order)
+    dt = compute_dt(U, cfg, 0.3, B)
+    Un, Bn = rk.step_rk_mhd(U, B, dt, cfg)
+    dx = cfg.spacing(U.shape[1:])
+    assert np.abs(divergence(Bn, dx)).max() <= 1e-12 * np.abs(Bn).max() / min(dx)
+    tot0, tot1 = U.sum(axis=(1, 2, 3)), Un.sum(axis=(1, 2, 3))
+    # (the random field starts at rest: the momenta sum to zero)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * np.abs(U).sum())
+    assert np.allclose(Bn.sum(axis=(1, 2, 3)), B.sum(axis=(1, 2, 3)), rtol=0, atol=1e-11)
+    # a uniform magnetised flow stays uniform
+    Uc = np.zeros((5, 4, 5, 6))
+    Uc[:] = np.array([1.1, 0.2, -0.3, 0.1, 3.0])[:, None, None, None]
+    Bc = np.zeros((3, 4, 5, 6))
+    Bc[:] = np.array([0.4, -0.2, 0.7])[:, None, None, None]
+    Un, Bn = rk.step_rk_mhd(Uc, Bc, 0.01, cfg)
+    tol = 3e-14 if order == 4 else 1e-15
+    assert np.allclose(Un, Uc, rtol=tol, atol=0) and np.allclose(Bn, Bc, rtol=tol, atol=0)
+
+
+def test_rk_mhd_stage_is_the_ader_step_of_a_frozen_polynomial():
+    import sys
+    from oracle import predictor as pr
+    from paper_1006_2146_amd import workloads
+    st = sys.modules['oracle.step']
+    cfg = OracleConfig(order=3, gamma=G53, riemann='linearized')
+    U, B = workloads.mhd_random_field((6, 7, 8), seed=11)
+    dt = compute_dt(U, cfg, 0.3, B)
+    orig = st.predict_modal
+    try:
+        def frozen(what, order, *a, **k):
+            out = np.zeros((pr.N_SPACETIME[order],) + what.shape[1:])
+            out[:pr.N_SPATIAL[order]] = what
+            return out
+        st.predict_modal = frozen
+        Ur, Br = st.step(U, dt, cfg, B)
+    finally:
+        st.predict_modal = orig
+    LU, LB = rk.mhd_operator((U, B), cfg)
+    assert np.allclose(U + dt * LU, Ur, rtol=0, atol=1e-14 * np.abs(U).max())
+    assert np.allclose(B + dt * LB, Br, rtol=0, atol=1e-14 * np.abs(B).max())
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("order,floor", [(2, 1.7), (3, 2.6)])
+def test_rk_mhd_design_order_alfven_wave(order, floor):
+    from paper_1006_2146_amd import workloads
+    errs = []
+    T = 0.04
+    cfg = OracleConfig(order=order, gamma=G53)
+    for n in (8, 16):
+        U, B = workloads.alfven_wave_diagonal((n, n, n))
+        t = 0.0
+        while t < T - 1e-14:
+            dt = min(compute_dt(U, cfg, 0.3, B), T - t)
+            U, B = rk.step_rk_mhd(U, B, dt, cfg)
+            t += dt
+        _, Be = workloads.alfven_wave_diagonal((n, n, n), t=T)
+        errs.append(np.abs(B[0] - Be[0]).mean())
+    assert np.log2(errs[0] / errs[1]) > floor, errs
