@@ -221,6 +221,62 @@ def run_turbulent(ader, torch, steps, warmup):
     return out
 
 
+# Table V (one 2.53 GHz Nehalem core, 97^3 blast problems): ADER-WENO over
+# RK-WENO speed at the same order and Riemann solver, Euler
+PAPER_ADER_OVER_RK = {"euler-hll": {2: 198817 / 126935, 3: 75105 / 37049, 4: 21065 / 8623},
+                      "euler-linearized": {2: 154674 / 92448, 3: 67025 / 31598, 4: 20348 / 8119},
+                      "mhd-hll": {2: 118280 / 72047, 3: 46418 / 21791, 4: 12076 / 3778}}
+
+
+def run_schemes(ader, torch, U0, steps, warmup, Um=None, Bm=None):
+    """ADER-CG against SSP-RK (Sec. II.d) on the same 128^3 workloads, HLL,
+    orders 2-4: Euler (Sedov modes) mixed and FP64, and MHD (random field)
+    mixed; each autotuned, graph-replayed CFL steps at the same CFL."""
+    nz, ny, nx = SHAPE
+    N = nx * ny * nz
+    out = {"workload": WORKLOAD + " (Euler) and mhd-random-field-128^3 (MHD), HLL, CFL %.2f; "
+           "SSP-RK2/RK3/SSP(5,4) at orders 2/3/4" % CFL,
+           "paper_ader_over_rk": {"euler-hll": PAPER_ADER_OVER_RK["euler-hll"],
+                                  "mhd-hll": PAPER_ADER_OVER_RK["mhd-hll"]},
+           "paper_hardware": "Intel Nehalem 2.53 GHz, one core (Table V)"}
+    cases = [("mixed", ader.ADER_MIXED, False), ("fp64", ader.ADER_FP64, False)]
+    if Um is not None:
+        cases.append(("mhd-mixed", ader.ADER_MIXED, True))
+    for prec_name, prec, mhd in cases:
+        for order in (2, 3, 4):
+            res = {}
+            for sname, scheme in (("ader", ader.ADER_SCHEME_ADER), ("rk", ader.ADER_SCHEME_SSPRK)):
+                stream = torch.cuda.Stream()
+                s = ader.Solver(SHAPE, order=order, riemann=ader.ADER_HLL, precision=prec,
+                                stream=stream.cuda_stream, gamma=5.0 / 3.0 if mhd else 1.4,
+                                system=ader.ADER_MHD if mhd else ader.ADER_EULER)
+                try:
+                    ader.ader_set_scheme(s.ctx, scheme)
+                    with torch.cuda.stream(stream):
+                        dU = torch.from_numpy(Um if mhd else U0).to("cuda")
+                        dB = torch.from_numpy(Bm).to("cuda") if mhd else None
+                    stream.synchronize()
+                    ader.ader_bind_device_state(s.ctx, dU.data_ptr(), dB.data_ptr() if mhd else None)
+                    ader.ader_autotune(s.ctx, 2)
+                    ader.ader_set_graph(s.ctx, True)
+                    for _ in range(warmup):
+                        s.step_cfl(CFL)
+                    s.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        s.step_cfl(CFL)
+                    s.synchronize()
+                    res[sname] = N * steps / (time.perf_counter() - t0)
+                finally:
+                    s.close()
+            out["%s-o%d" % (prec_name, order)] = {
+                "ader_zone_updates_per_s": res["ader"], "rk_zone_updates_per_s": res["rk"],
+                "ader_over_rk": res["ader"] / res["rk"]}
+            log("schemes %s order %d: ADER %.3e, RK %.3e zone-updates/s (ratio %.2f)"
+                % (prec_name, order, res["ader"], res["rk"], res["ader"] / res["rk"]))
+    return out
+
+
 def run_ensemble(ader, torch, steps, warmup):
     """The batched ensemble: 64 uneven problems, order 3, HLL, mixed
     precision, one persistent launch per stage, graph-replayed, autotuned."""
@@ -363,6 +419,8 @@ def main():
                          "(HLL), fp64-lin, mixed-lin (linearized); '' for none")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 64-problem batched ensemble")
+    ap.add_argument("--no-schemes", action="store_true",
+                    help="skip the ADER vs SSP-RK comparison (orders 2-4)")
     ap.add_argument("--no-turbulent", action="store_true",
                     help="skip the 384^3 turbulent MHD run (order 4, linearized, mixed)")
     ap.add_argument("--tune-file", default=None,
@@ -450,6 +508,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % nbytes)
 
+    schemes = None
+    if not args.no_schemes:
+        log("ADER vs SSP-RK")
+        schemes = run_schemes(ader, torch, U0, max(3, min(args.steps, 10)), 1,
+                              *((Um, Bm) if args.mhd_variants else (None, None)))
+
     turbulent = None
     if not args.no_turbulent and args.mhd_variants:
         log("turbulent MHD 384^3")
@@ -516,6 +580,7 @@ def main():
                          **mhd_variants},
         "ensemble": ensemble,
         "turbulent_mhd": turbulent,
+        "ader_vs_ssprk": schemes,
     }
     for prec in ("fp64", "mixed"):
         if prec + "-hll" in variants and prec + "-hll-nodal" in variants:

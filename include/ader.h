@@ -83,6 +83,22 @@ int ader_set_gamma(ader_ctx* ctx, double gamma);
  * linear; at 3 and 4 it is centred WENO. */
 int ader_set_order(ader_ctx* ctx, int order, int form);
 
+/* Time stepping: ADER_SCHEME_ADER, the ADER-CG step (default), or
+ * ADER_SCHEME_SSPRK, the strong-stability-preserving Runge-Kutta schemes of
+ * Sec. II.d matched to the order (eq. 18 SSP-RK2 at order 2, eq. 19 SSP-RK3
+ * at 3, eq. 20 the five-stage fourth-order scheme at 4): each stage runs the
+ * reconstruction, the face-side packets of the spatial polynomial (the App.
+ * D quadrature with the time direction dropped), the Riemann fluxes and the
+ * stage combination in double, with the predictor bypassed; for MHD each
+ * stage also rebuilds the zone field from the stage's face fields and
+ * advances the face fields by minus the curl of its edge fields (eq. 8).
+ * The form setting does not apply to it.  The scheme allocates four more
+ * copies of the state on its first step (160 bytes per zone, 256 for MHD).
+ * ADER_EINVAL for an unknown scheme. */
+enum { ADER_SCHEME_ADER = 0, ADER_SCHEME_SSPRK = 1 };
+int ader_set_scheme(ader_ctx* ctx, int scheme);
+int ader_get_scheme(ader_ctx* ctx, int* scheme_out);
+
 /* ADER_HLL (eq. 17/56, Davis speeds from the barycentre states) or
  * ADER_LINEARIZED (Sec. II.3: (F_L + F_R)/2 - R|Lambda|L (u_R - u_L)/2 with
  * the eigen-system frozen at the mean of the two barycentre primitive

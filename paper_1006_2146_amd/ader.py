@@ -33,8 +33,9 @@ EXPORTS = [
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
-    "ader_probe_peak",
+    "ader_probe_peak", "ader_set_scheme", "ader_get_scheme",
 ]
+ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_PROBE_FP32_FMA, ADER_PROBE_FP64_FMA, ADER_PROBE_HBM_COPY = 0, 1, 2
 ADER_RECON_SWEEPS, ADER_RECON_TILED = 0, 1
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
@@ -103,6 +104,8 @@ def load():
         "ader_set_recon": ([P, I], I),
         "ader_get_recon": ([P, ctypes.POINTER(I)], I),
         "ader_probe_peak": ([I, I, DP], I),
+        "ader_set_scheme": ([P, I], I),
+        "ader_get_scheme": ([P, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -218,6 +221,16 @@ def ader_device_bytes(ctx):
     b = ctypes.c_double()
     _check(load().ader_device_bytes(ctx, ctypes.byref(b)), "ader_device_bytes")
     return b.value
+
+
+def ader_set_scheme(ctx, scheme):
+    _check(load().ader_set_scheme(ctx, scheme), "ader_set_scheme")
+
+
+def ader_get_scheme(ctx):
+    v = ctypes.c_int()
+    _check(load().ader_get_scheme(ctx, ctypes.byref(v)), "ader_get_scheme")
+    return v.value
 
 
 def ader_probe_peak(kind, device=0):

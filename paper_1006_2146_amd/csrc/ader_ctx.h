@@ -54,6 +54,7 @@ struct StageFns {
   int (*predict_zone_2w)(ader_ctx*);  // one lane per zone, registers capped for 2 waves/SIMD
   int (*predict_pair)(ader_ctx*);     // MHD: two lanes per zone
   int (*predict_pair2)(ader_ctx*);    // the same, registers capped for 2 waves/SIMD
+  int (*rk_sides)(ader_ctx*);         // SSP-RK stage: side packets (Euler, modal tables)
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
 };
@@ -95,7 +96,11 @@ struct ader_ctx {
   bool have_dt = false;
   size_t bytes = 0;          // device bytes held: fixed part plus work arrays
   size_t fixed_bytes = 0;
-  size_t work_bytes[4] = {0, 0, 0, 0};   // W, PK, WB, BN as allocated
+  size_t work_bytes[5] = {0, 0, 0, 0, 0};   // W, PK, WB, BN, RK as allocated
+  // time stepping (ADER_SCHEME_*); SSP-RK keeps four extra states in RK:
+  // the step's starting state, the stage states 2 and 3 and dt L(U^(3))
+  int scheme = ADER_SCHEME_ADER;
+  double* RK = nullptr;
   ader::LaunchShape shape[ader::kNumClasses] = {{256, 8}, {256, 8}, {128, 4}, {256, 8}, {256, 8}};
   // predictor layout: -1 the variant's default, else an ADER_LAYOUT_*
   int layout = -1;

@@ -190,6 +190,59 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   });
 }
 
+// SSP-RK stage (Euler): side packets of the spatial polynomial
+template <class T, int ORDER>
+__global__ void __launch_bounds__(256) k_rk_sides(const double* __restrict__ U,
+                                                  const T* __restrict__ W, T* __restrict__ PK,
+                                                  Batch b, double gam) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    rk_sides_zone<T, ORDER, kDeviation<T>>(U, W, PK, grid_of(pr, b), gam, n);
+  });
+}
+
+// SSP-RK stage combination (eq. 18-20)
+template <int = 0>
+__global__ void __launch_bounds__(256) k_rk_stage(double* __restrict__ U,
+                                                  const double* __restrict__ F, RkStage st,
+                                                  Batch b, const double* __restrict__ dt) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    rk_stage_zone(U, F, st, grid_of(pr, b), dt[p], pr.dx, pr.dy, pr.dz, n);
+  });
+}
+
+// SSP-RK stage (MHD): side packets of the spatial polynomial
+template <class T, int ORDER, bool EDGES_ALL>
+__global__ void __launch_bounds__(256) k_rk_sides_mhd(const double* __restrict__ U,
+                                                      const T* __restrict__ W,
+                                                      const double* __restrict__ B0,
+                                                      const T* __restrict__ WB,
+                                                      const T* __restrict__ BN,
+                                                      T* __restrict__ PK, Batch b, double gam) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    predict_zone_mhd<T, ORDER, 0, kDeviation<T>, true, EDGES_ALL, true>(
+        U, W, B0, WB, BN, PK, grid_of(pr, b), 0.0, 0.0, 0.0, 0.0, gam, n);
+  });
+}
+
+// SSP-RK stage combination of the MHD face fields
+template <int = 0>
+__global__ void __launch_bounds__(256) k_rk_stage_field(double* __restrict__ B,
+                                                        const double* __restrict__ E, RkStage st,
+                                                        Batch b, const double* __restrict__ dt) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    rk_stage_field_zone(B, E, st, grid_of(pr, b), dt[p], pr.dx, pr.dy, pr.dz, n);
+  });
+}
+
+// dst <- src for `rows` state rows (the step's starting state of SSP-RK)
+template <int = 0>
+__global__ void __launch_bounds__(256) k_copy_state(const double* __restrict__ src,
+                                                    double* __restrict__ dst, int rows, Batch b) {
+  for_zones(b, [&](const Problem&, int, long long n) {
+    for (int v = 0; v < rows; ++v) dst[(long long)v * b.S + n] = src[(long long)v * b.S + n];
+  });
+}
+
 // pair layout (MHD): two lanes per zone, 32 zones per wave
 template <class T, int ORDER, int FORM, int WAVES, bool EDGES_ALL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_pair(

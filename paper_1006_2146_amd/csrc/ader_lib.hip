@@ -32,10 +32,13 @@ namespace {
 
 int set_device(ader_ctx* c) { return check(hipSetDevice(c->device)); }
 
+// The stage table of the setting (SSP-RK uses the modal tables: it has no
+// predictor, so the form does not apply to it).
 const StageFns* stages_of(const ader_ctx* c) {
+  const int form = c->scheme == ADER_SCHEME_SSPRK ? ADER_MODAL : c->form;
 #define ADER_PICK(SY, PR, OR, FM)                                                                \
   if (c->system == (#SY[0] == 'm' ? ADER_MHD : ADER_EULER) &&                                    \
-      c->precision == (#PR[0] == 'm' ? ADER_MIXED : ADER_FP64) && c->order == OR && c->form == FM) \
+      c->precision == (#PR[0] == 'm' ? ADER_MIXED : ADER_FP64) && c->order == OR && form == FM) \
     return ADER_STAGES_NAME(SY, PR, OR, FM)();
   ADER_VARIANTS(ADER_PICK)
 #undef ADER_PICK
@@ -115,9 +118,87 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
   }
 }
 
+// SSP-RK weights of eq. (18), (19) and (20), one row per stage: U <- a_n Un
+// + a_c U + c_l dt L(U) + a_2 U^(2) + a_3 U^(3) + c_d dt L(U^(3)); the flags
+// keep U^(2), U^(3) and dt L(U^(3)) for the last stage of (20).
+struct RkRow {
+  double a_n, a_c, c_l, a_2, a_3, c_d;
+  int keep;   // 2: keep the result as U^(2); 3: as U^(3); 4: keep dt L
+};
+constexpr RkRow kRk2[] = {{0, 1, 1, 0, 0, 0, 0}, {0.5, 0.5, 0.5, 0, 0, 0, 0}};
+constexpr RkRow kRk3[] = {{0, 1, 1, 0, 0, 0, 0}, {0.75, 0.25, 0.25, 0, 0, 0, 0},
+                          {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 0, 0, 0, 0}};
+constexpr RkRow kRk54[] = {
+    {0, 1, 0.39175222700392, 0, 0, 0, 0},
+    {0.44437049406734, 0.55562950593266, 0.36841059262959, 0, 0, 0, 2},
+    {0.62010185138540, 0.37989814861460, 0.25189177424738, 0, 0, 0, 3},
+    {0.17807995410773, 0.82192004589227, 0.54497475021237, 0, 0, 0, 4},
+    {0.00683325884039, 0.34833675773694, 0.22600748319395, 0.51723167208978, 0.12759831133288,
+     0.08460416338212, 0}};
+
+// One SSP-RK step (Sec. II.d): the starting state saved, then per stage the
+// reconstruction, the side packets of the spatial polynomial, the face
+// fluxes and the stage combination, all on the stream.
+int queue_rk_step(ader_ctx* c, const StageFns* s) {
+  if (!s->rk_sides) return ADER_EUNSUPPORTED;
+  const RkRow* rows = c->order == 2 ? kRk2 : c->order == 3 ? kRk3 : kRk54;
+  const int nst = c->order == 2 ? 2 : c->order == 3 ? 3 : 5;
+  const long long row = 5 * c->S, brow = 3 * c->S;
+  const bool mhd = c->system == ADER_MHD;
+  double* Un = c->RK;
+  double* S2 = c->RK + row;
+  double* S3 = c->RK + 2 * row;
+  double* D3 = c->RK + 3 * row;
+  // MHD: the same four arrays for the face fields after the hydro ones
+  double* Bn = c->RK + 4 * row;
+  double* SB2 = Bn + brow;
+  double* SB3 = Bn + 2 * brow;
+  double* DB3 = Bn + 3 * brow;
+  const unsigned gu = grid_for(c, kClassUpdate);
+  const int bu = c->shape[kClassUpdate].block;
+  {
+    StageTimer t(c, ADER_STAGE_UPDATE);
+    k_copy_state<><<<gu, bu, 0, c->stream>>>(c->U, Un, 5, c->batch());
+    ADER_TRY(launched());
+    if (mhd) {
+      k_copy_state<><<<gu, bu, 0, c->stream>>>(c->B, Bn, 3, c->batch());
+      ADER_TRY(launched());
+    }
+  }
+  for (int k = 0; k < nst; ++k) {
+    const RkRow& r = rows[k];
+    {
+      StageTimer t(c, ADER_STAGE_RECON);
+      ADER_TRY(s->recon(c));
+    }
+    {
+      StageTimer t(c, ADER_STAGE_PREDICT);
+      ADER_TRY(s->rk_sides(c));
+    }
+    {
+      StageTimer t(c, ADER_STAGE_FLUX);
+      ADER_TRY(s->flux(c));
+    }
+    StageTimer t(c, ADER_STAGE_UPDATE);
+    const RkStage st{r.a_n, r.a_c, r.c_l, r.a_2, r.a_3, r.c_d, Un, S2, S3, D3,
+                     r.keep == 2 ? S2 : r.keep == 3 ? S3 : nullptr, r.keep == 4 ? D3 : nullptr};
+    k_rk_stage<><<<gu, bu, 0, c->stream>>>(c->U, c->F, st, c->batch(), c->d_dt);
+    ADER_TRY(launched());
+    if (mhd) {
+      const RkStage sb{r.a_n, r.a_c, r.c_l, r.a_2, r.a_3, r.c_d, Bn, SB2, SB3, DB3,
+                       r.keep == 2 ? SB2 : r.keep == 3 ? SB3 : nullptr,
+                       r.keep == 4 ? DB3 : nullptr};
+      k_rk_stage_field<><<<gu, bu, 0, c->stream>>>(c->B, c->E, sb, c->batch(), c->d_dt);
+      ADER_TRY(launched());
+    }
+  }
+  return ADER_OK;
+}
+
 int queue_step(ader_ctx* c) {
   const StageFns* s = stages_of(c);
   if (!s) return ADER_EUNSUPPORTED;
+  if (c->scheme == ADER_SCHEME_SSPRK) return queue_rk_step(c, s);
   {
     StageTimer t(c, ADER_STAGE_RECON);
     ADER_TRY(s->recon(c));
@@ -146,10 +227,12 @@ int ensure_work(ader_ctx* c) {
   const size_t t = c->precision == ADER_FP64 ? sizeof(double) : sizeof(float);
   const size_t ls = c->order == 2 ? 4 : c->order == 3 ? 10 : 20;
   const bool mhd = c->system == ADER_MHD;
-  const size_t need[4] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
-                          mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0};
-  void** buf[4] = {&c->W, &c->PK, &c->WB, &c->BN};
-  for (int q = 0; q < 4; ++q) {
+  const size_t need[5] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
+                          mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0,
+                          c->scheme == ADER_SCHEME_SSPRK ? sizeof(double) * 4 * (mhd ? 8 : 5) * Z
+                                                         : 0};
+  void** buf[5] = {&c->W, &c->PK, &c->WB, &c->BN, (void**)&c->RK};
+  for (int q = 0; q < 5; ++q) {
     if (need[q] <= c->work_bytes[q]) continue;
     if (*buf[q]) {
       // a captured step holds the old address: rebuild it on its next use
@@ -163,12 +246,13 @@ int ensure_work(ader_ctx* c) {
       *buf[q] = nullptr;
       (void)hipGetLastError();
       c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] +
-                 c->work_bytes[3];
+                 c->work_bytes[3] + c->work_bytes[4];
       return ADER_ENOMEM;
     }
     c->work_bytes[q] = need[q];
   }
-  c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] + c->work_bytes[3];
+  c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] +
+             c->work_bytes[3] + c->work_bytes[4];
   return ADER_OK;
 }
 
@@ -180,6 +264,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)c->precision;
   k = k * 3 + (unsigned long long)(c->layout + 1);
   k = k * 3 + (unsigned long long)(c->recon_mode + 1);
+  k = k * 3 + (unsigned long long)c->scheme;
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
@@ -286,6 +371,7 @@ void free_buffers(ader_ctx* c) {
   if (c->owns_U && c->U) (void)hipFree(c->U);
   if (c->owns_B && c->B) (void)hipFree(c->B);
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
+                  (void*)c->RK,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs,
                   (void*)c->d_tile_base})
     if (p) (void)hipFree(p);
@@ -748,6 +834,18 @@ int ader_set_layout(ader_ctx* c, int layout) {
       (c->order < 3 || c->system != ADER_MHD))
     return ADER_EUNSUPPORTED;
   c->layout = layout;
+  return ADER_OK;
+}
+
+int ader_set_scheme(ader_ctx* c, int scheme) {
+  if (!c || (scheme != ADER_SCHEME_ADER && scheme != ADER_SCHEME_SSPRK)) return ADER_EINVAL;
+  c->scheme = scheme;
+  return ADER_OK;
+}
+
+int ader_get_scheme(ader_ctx* c, int* scheme_out) {
+  if (!c || !scheme_out) return ADER_EINVAL;
+  *scheme_out = c->scheme;
   return ADER_OK;
 }
 

@@ -132,6 +132,32 @@ int predict_pair(ader_ctx* c) {
   }
 }
 
+// SSP-RK stage (Euler): side packets of the spatial polynomial; the tables
+// are those of the modal scheme of the order
+int rk_sides(ader_ctx* c) {
+  if constexpr (kForm == 0) {
+    const unsigned g = grid_for(c, kClassPredict);
+    const int bs = c->shape[kClassPredict].block;
+    const T* W = static_cast<const T*>(c->W);
+    T* PK = static_cast<T*>(c->PK);
+    if constexpr (kMhd) {
+      const T* WB = static_cast<const T*>(c->WB);
+      const T* BN = static_cast<const T*>(c->BN);
+      if (c->riemann == ADER_LINEARIZED)
+        k_rk_sides_mhd<T, kOrder, true><<<g, bs, 0, c->stream>>>(c->U, W, c->B0, WB, BN, PK,
+                                                                  c->batch(), c->gamma);
+      else
+        k_rk_sides_mhd<T, kOrder, false><<<g, bs, 0, c->stream>>>(c->U, W, c->B0, WB, BN, PK,
+                                                                   c->batch(), c->gamma);
+    } else {
+      k_rk_sides<T, kOrder><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->gamma);
+    }
+    return launched();
+  } else {
+    return ADER_EUNSUPPORTED;
+  }
+}
+
 int flux(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassFlux);
   const int bs = c->shape[kClassFlux].block;
@@ -172,6 +198,7 @@ const StageFns kStages = {recon,
                           (!kMhd && kOrder <= 3) ? predict<true, 2> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair<1> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair<2> : nullptr,
+                          kForm == 0 ? rk_sides : nullptr,
                           flux,
                           update};
 

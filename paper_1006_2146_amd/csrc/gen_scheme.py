@@ -874,8 +874,52 @@ def gen_order(order, form):
             out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(fav[j]))
         out.append("    }")
     out.append("  }")
+    if form == 'modal':
+        out += gen_rk_side(order, tag, fav, fnodes)
     out += gen_mhd_parts(order, form, tag, nodes, fnodes)
     out.append("};")
+    return out
+
+
+def gen_rk_side(order, tag, fav, fnodes):
+    """Side packet of an SSP-RK stage (Sec. II.d): the App. D quadrature
+    applied to the spatial polynomial held constant in time.  Facial nodes
+    that differ only in tau then carry the same state, so their weights are
+    merged and each distinct face point is evaluated once."""
+    ls = LS[order]
+    merged = {}
+    for j in sorted(fav):
+        t1, t2, _ = fnodes[j - 1]
+        key = (Fr(t1), Fr(t2))
+        merged[key] = merged.get(key, 0) + fav[j]
+    pts = [(k, c) for k, c in sorted(merged.items()) if c != 0]
+    key = (tag + "rk", 'faces')
+    out = []
+    out.append("  // side packet of an SSP-RK stage (the predictor bypassed): barycentre")
+    out.append("  // state, face average of u and of the normal flux of the spatial")
+    out.append("  // polynomial at the stage time (App. D with the tau-direction dropped:")
+    out.append("  // %d face points per side)." % len(pts))
+    out.append("  template <int SIDE, class Phys, class Acc>")
+    out.append("  __host__ __device__ static __forceinline__ void side_rk(const T (&w)[LS][NV], const Phys& ph,")
+    out.append("                                     Acc& acc, T (&ub)[NV], T (&ua)[NV], T (&fa)[NV]) {")
+    out.append("    constexpr bool DEV = Phys::kDeviation;")
+    out.append("    T u[NV], fl[NV];")
+    for si, (d, s) in enumerate(SIDES):
+        out.append("    %sif constexpr (SIDE == %d) {  // axis %d, side %+d" % ("" if si == 0 else "else ", si, d, s))
+        emit_spatial_eval(out, order, side_point(d, s, 0, 0, 0), "ub", indent="      ", count=key)
+        out.append("      acc(ub);")
+        row = face_average_u_row(order, d, s)[:ls]
+        _count(key, _eval_flops(row))
+        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
+        out.append("      for (int v = 0; v < NV; ++v) fa[v] = T(0);")
+        for (t1, t2), c in pts:
+            emit_spatial_eval(out, order, side_point(d, s, t1, t2, 0), "u", indent="      ", count=key)
+            out.append("      acc(u);")
+            _count(key, FLUX_FLOPS[SYSTEM] + 2 * NV_OF[SYSTEM])
+            out.append("      ph.template flux<%d>(u, fl);" % d)
+            out.append("      for (int v = 0; v < NV; ++v) fa[v] += %s * fl[v];" % lit(c))
+        out.append("    }")
+    out.append("  }")
     return out
 
 

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "physics_device.h"
 #include "generated/ader_scheme.h"
 
@@ -560,6 +562,150 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   }
 }
 
+// An SSP-RK stage (Sec. II.d; Euler): the predictor is bypassed, so a zone
+// loads its reconstruction, applies the spatial positivity scaling (whose
+// check set holds every point the RK side packets evaluate) and writes the
+// six side packets of its spatial polynomial at the stage time, in the
+// layout the face-flux kernel reads.
+template <class T, int ORDER, bool DEV>
+__host__ __device__ __forceinline__ void rk_sides_zone(const double* __restrict__ U,
+                                                       const T* __restrict__ W,
+                                                       T* __restrict__ PK, const Grid& g,
+                                                       double gam, long long n) {
+  using S = typename SchemeOf<ORDER, 0, T>::type;
+  constexpr int LS = S::LS;
+  double w0[5];
+  {
+    const double* q = U + n;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { w0[v] = *q; q = next_row(q, g.S); }
+  }
+  T w[LS][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
+  {
+    const T* q = W + n;
+#pragma unroll
+    for (int m = 1; m < LS; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { w[m][v] = *q; q = next_row(q, g.S); }
+  }
+  {
+    PosScan<T, 5, DEV> scan(w0);
+    S::spatial_points(w, scan);
+    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam) : 1.0;
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int v = 0; v < 5; ++v) w[m][v] *= th;
+    }
+  }
+  const auto ph = FluxOf<Euler<T>, T, DEV>::make(w0, gam);
+  NoScan none;
+  T* q = PK + n;
+  auto side = [&](auto side_c) {
+    constexpr int SIDE = decltype(side_c)::value;
+    T ub[5], ua[5], fa[5];
+    S::template side_rk<SIDE>(w, ph, none, ub, ua, fa);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { *q = ub[v]; q = next_row(q, g.S); }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { *q = ua[v]; q = next_row(q, g.S); }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { *q = fa[v]; q = next_row(q, g.S); }
+  };
+  side(std::integral_constant<int, 0>{});
+  side(std::integral_constant<int, 1>{});
+  side(std::integral_constant<int, 2>{});
+  side(std::integral_constant<int, 3>{});
+  side(std::integral_constant<int, 4>{});
+  side(std::integral_constant<int, 5>{});
+}
+
+// One SSP-RK stage combination (eq. 18-20) in double, with L(U) = -sum_d
+// (F_{i+1/2} - F_{i-1/2}) / dx_d from the fluxes of the current stage state:
+//   U <- a_n Un + a_c U + c_l h L + a_2 S2 + a_3 S3 + c_d D3
+// (terms with a zero weight are not read).  save_state receives the result
+// and save_hl receives h L, for the later stages of (20) that reuse them.
+struct RkStage {
+  double a_n, a_c, c_l, a_2, a_3, c_d;
+  const double* Un;
+  const double* S2;
+  const double* S3;
+  const double* D3;
+  double* save_state;
+  double* save_hl;
+};
+
+// The same combination for the MHD face fields, their rate L_B = -curl E
+// (eq. 8 per unit time; B_d at the lower d-face, E_c at the lower c-edge).
+__host__ __device__ __forceinline__ void rk_stage_field_zone(double* __restrict__ B,
+                                                             const double* __restrict__ E,
+                                                             const RkStage& st, const Grid& g,
+                                                             double h, double dx, double dy,
+                                                             double dz, long long n) {
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
+  const long long px = zone_of(wrap(i + 1, g.nx), j, k, g);
+  const long long py = zone_of(i, wrap(j + 1, g.ny), k, g);
+  const long long pz = zone_of(i, j, wrap(k + 1, g.nz), g);
+  const double* Ex = E;
+  const double* Ey = E + g.S;
+  const double* Ez = E + 2 * g.S;
+  const double curl[3] = {(Ez[py] - Ez[n]) / dy - (Ey[pz] - Ey[n]) / dz,
+                          (Ex[pz] - Ex[n]) / dz - (Ez[px] - Ez[n]) / dx,
+                          (Ey[px] - Ey[n]) / dx - (Ex[py] - Ex[n]) / dy};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const long long at = (long long)c * g.S + n;
+    const double hl = -(h * curl[c]);
+    double b = st.a_c * B[at];
+    if (st.a_n != 0.0) b = st.a_n * st.Un[at] + b;
+    b = b + st.c_l * hl;
+    if (st.a_2 != 0.0) b = b + st.a_2 * st.S2[at];
+    if (st.a_3 != 0.0) b = b + st.a_3 * st.S3[at];
+    if (st.c_d != 0.0) b = b + st.c_d * st.D3[at];
+    if (st.save_hl) st.save_hl[at] = hl;
+    if (st.save_state) st.save_state[at] = b;
+    B[at] = b;
+  }
+}
+
+__host__ __device__ __forceinline__ void rk_stage_zone(double* __restrict__ U,
+                                                       const double* __restrict__ F,
+                                                       const RkStage& st, const Grid& g,
+                                                       double h, double dx, double dy,
+                                                       double dz, long long n) {
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
+  const long long up[3] = {zone_of(wrap(i + 1, g.nx), j, k, g), zone_of(i, wrap(j + 1, g.ny), k, g),
+                           zone_of(i, j, wrap(k + 1, g.nz), g)};
+  const double inv[3] = {1.0 / dx, 1.0 / dy, 1.0 / dz};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const long long at = (long long)v * g.S + n;
+    double l = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const double fp = F[((long long)ax * 5 + v) * g.S + up[ax]];
+      const double fm = F[((long long)ax * 5 + v) * g.S + n];
+      l = l - (fp - fm) * inv[ax];
+    }
+    const double hl = h * l;
+    double u = st.a_c * U[at];
+    if (st.a_n != 0.0) u = st.a_n * st.Un[at] + u;
+    u = u + st.c_l * hl;
+    if (st.a_2 != 0.0) u = u + st.a_2 * st.S2[at];
+    if (st.a_3 != 0.0) u = u + st.a_3 * st.S3[at];
+    if (st.c_d != 0.0) u = u + st.c_d * st.D3[at];
+    if (st.save_hl) st.save_hl[at] = hl;
+    if (st.save_state) st.save_state[at] = u;
+    U[at] = u;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Riemann fluxes at the faces (Sec. II.3, V): wave structure frozen at the
 // two barycentre states.
@@ -893,7 +1039,12 @@ __host__ __device__ __forceinline__ void store_side_mhd(const T (&w)[S::LS][8], 
 // predictor, positivity scaling and the six side packets of 32 values
 // (barycentre state, face averages of u and F, edge averages of u and F of
 // the field component along each edge's transverse axis).
-template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool EDGES_ALL = false>
+// RK: an SSP-RK stage (Sec. II.d): the predictor is bypassed (the
+// evolutionary modes are a constant zero, so coinciding face points fold
+// together) and the spatial check set, which holds every face point, is the
+// only positivity check.
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool EDGES_ALL = false,
+          bool RK = false>
 __host__ __device__ __forceinline__ void predict_zone_mhd(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
@@ -941,6 +1092,17 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
     }
   }
   const auto ph = FluxOf<Mhd<T>, T, DEV>::make(w0, gam);
+  if constexpr (RK) {
+    constexpr T ez[NE][8] = {};
+    NoScan none;
+    store_side_mhd<S, T, 0, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 1, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 2, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 3, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 4, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    store_side_mhd<S, T, 5, EDGES_ALL>(w, ez, ph, none, PK, g.S, n);
+    return;
+  }
   T e[NE][8];
   S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
   if constexpr (!FUSED) {

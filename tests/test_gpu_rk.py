@@ -1,0 +1,121 @@
+"""SSP-RK stepping (Sec. II.d, eq. 18-20) on the GPU through the C ABI:
+FP64 parity with the oracle's RK steps, the mixed path per step, batches,
+graph replays and the unsupported MHD case."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import OracleConfig
+from oracle import rk as ork
+from paper_1006_2146_amd import ader, workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+RS = {"hll": ader.ADER_HLL, "linearized": ader.ADER_LINEARIZED}
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def rel_l1(a, b):
+    return np.abs(a - b).sum(axis=(1, 2, 3)) / np.abs(b).sum(axis=(1, 2, 3))
+
+
+def _rk_solver(shape, order, rs, precision=ader.ADER_FP64, lengths=(1.0, 1.0, 1.0), **kw):
+    s = ader.Solver(shape, order=order, riemann=RS[rs], precision=precision, lengths=lengths, **kw)
+    ader.ader_set_scheme(s.ctx, ader.ADER_SCHEME_SSPRK)
+    return s
+
+
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_rk_parity_smooth_and_blast(order, rs):
+    for tag, U0, lengths in (
+            ("smooth", workloads.random_smooth((9, 14, 21), seed=order + 30), (1.0, 0.8, 1.3)),
+            ("blast", workloads.blast((12, 12, 12), p_in=100.0, p_out=0.1, radius=0.25),
+             (1.0, 1.0, 1.0))):
+        cfg = OracleConfig(order=order, riemann=rs, lengths=lengths)
+        with _rk_solver(U0.shape[1:], order, rs, lengths=lengths) as s:
+            assert ader.ader_get_scheme(s.ctx) == ader.ADER_SCHEME_SSPRK
+            s.set_state(U0)
+            U = U0
+            for it in range(2):
+                say("rk", tag, order, rs, "step", it)
+                dt = s.compute_dt(0.3)
+                s.step(dt)
+                Ug = s.get_state()
+                err = rel_l1(Ug, ork.step_rk(U, dt, cfg))
+                assert np.all(err <= TOL_FP64), (tag, it, err)
+                U = Ug
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_rk_mixed_close_to_oracle(order):
+    U = workloads.random_smooth((9, 14, 21), seed=order + 40)
+    cfg = OracleConfig(order=order, riemann="hll")
+    with _rk_solver(U.shape[1:], order, "hll", precision=ader.ADER_MIXED) as s:
+        s.set_state(U)
+        for it in range(2):
+            say("rk mixed", order, "step", it)
+            dt = s.compute_dt(0.3)
+            s.step(dt)
+            Ug = s.get_state()
+            assert np.all(rel_l1(Ug, ork.step_rk(U, dt, cfg)) <= 1e-7), it
+            U = Ug
+
+
+def test_rk_batch_graph_and_errors():
+    shapes = [(8, 10, 12), (6, 7, 9)]
+    states = [workloads.random_smooth(sh, seed=50 + q) for q, sh in enumerate(shapes)]
+    solo = []
+    for sh, U0 in zip(shapes, states):
+        with _rk_solver(sh, 3, "hll") as s:
+            s.set_state(U0)
+            for _ in range(2):
+                s.step_cfl(0.3)
+            solo.append(s.get_state())
+    stream = torch.cuda.Stream()
+    with ader.BatchSolver(shapes, order=3, stream=stream.cuda_stream) as b:
+        ader.ader_set_scheme(b.ctx, ader.ADER_SCHEME_SSPRK)
+        ader.ader_set_graph(b.ctx, True)
+        for q, U0 in enumerate(states):
+            b.set_state(q, U0)
+        for it in range(2):
+            say("rk batch graph step", it)
+            b.step_cfl(0.3)
+        b.synchronize()
+        for q in range(len(shapes)):
+            assert np.array_equal(b.get_state(q), solo[q]), q
+    with ader.Solver((4, 4, 4), gamma=5.0 / 3.0, system=ader.ADER_MHD) as s:
+        assert ader.load().ader_set_scheme(s.ctx, 5) == ader.ADER_EINVAL
+
+
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_rk_mhd_parity_and_div_b(order, rs):
+    from oracle.bweno import divergence
+    G53 = 5.0 / 3.0
+    U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order + 60)
+    lengths = (1.0, 0.9, 1.2)
+    cfg = OracleConfig(order=order, gamma=G53, riemann=rs, lengths=lengths)
+    for prec, tol in ((ader.ADER_FP64, TOL_FP64), (ader.ADER_MIXED, 1e-6)):
+        with _rk_solver((7, 9, 10), order, rs, precision=prec, lengths=lengths, gamma=G53,
+                        system=ader.ADER_MHD) as s:
+            s.set_state(U0, B0)
+            U, B = U0, B0
+            for it in range(2):
+                say("rk mhd", order, rs, prec, "step", it)
+                dt = s.compute_dt(0.3)
+                s.step(dt)
+                Ug, Bg = s.get_state()
+                Uo, Bo = ork.step_rk_mhd(U, B, dt, cfg)
+                assert np.all(rel_l1(Ug, Uo) <= tol) and np.all(rel_l1(Bg, Bo) <= tol), it
+                # CT keeps the discrete divergence of the face field (the field
+                # is solenoidal for the unit box, not for these lengths)
+                dx = cfg.spacing(U.shape[1:])
+                ddiv = divergence(Bg, dx) - divergence(B0, dx)
+                assert np.abs(ddiv).max() <= 1e-12 * np.abs(Bg).max() / min(dx)
+                U, B = Ug, Bg
