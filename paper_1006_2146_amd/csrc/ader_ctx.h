@@ -109,6 +109,9 @@ struct ader_ctx {
   int recon_mode = -1;
   long long* d_tile_base = nullptr;
   long long ntiles = 0;
+  // z-column segments of the column mode: problem p's at seg_base[p] ..
+  long long* d_seg_base = nullptr;
+  long long nsegs = 0;
   // stage timing: events recorded around each stage while enabled
   bool timing = false;
   std::vector<hipEvent_t> events;

@@ -190,6 +190,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   });
 }
 
+// z sweep by column segments: thread t -> problem p (seg_base), then i
+// fastest, j, segment; one segment of kZSeg planes per thread
+template <class T, int M, int NVAR>
+__global__ void __launch_bounds__(256) k_weno_z_columns(const double* __restrict__ U,
+                                                        T* __restrict__ W, Batch b,
+                                                        const long long* __restrict__ seg_base) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= seg_base[b.np]) return;
+  const int p = problem_of_tile(seg_base, b.np, t);
+  const Problem pr = b.P[p];
+  const long long local = t - seg_base[p];
+  const int i = (int)(local % pr.nx);
+  const long long r = local / pr.nx;
+  const int j = (int)(r % pr.ny);
+  const int s = (int)(r / pr.ny);
+  const int k0 = s * kZSeg;
+  const int k1 = k0 + kZSeg < pr.nz ? k0 + kZSeg : pr.nz;
+  ZColumn<T, M, NVAR>::run(U, W, grid_of(pr, b), i, j, k0, k1);
+}
+
 // SSP-RK stage (Euler): side packets of the spatial polynomial
 template <class T, int ORDER>
 __global__ void __launch_bounds__(256) k_rk_sides(const double* __restrict__ U,

@@ -373,7 +373,7 @@ void free_buffers(ader_ctx* c) {
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
                   (void*)c->RK,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs,
-                  (void*)c->d_tile_base})
+                  (void*)c->d_tile_base, (void*)c->d_seg_base})
     if (p) (void)hipFree(p);
 }
 
@@ -442,14 +442,15 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
             hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
             hipMalloc(&c->d_rate, sizeof(unsigned long long) * n) == hipSuccess &&
             hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess &&
-            hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess;
+            hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
+            hipMalloc(&c->d_seg_base, sizeof(long long) * (n + 1)) == hipSuccess;
   if (!ok) {
     free_buffers(c);
     delete c;
     (void)hipGetLastError();
     return ADER_ENOMEM;
   }
-  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + sizeof(int) * n + sizeof(long long) * (n + 1);
+  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + sizeof(int) * n + 2 * sizeof(long long) * (n + 1);
   c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
   std::vector<long long> tile_base(n + 1, 0);
@@ -459,7 +460,16 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
                                           ((pr.ny + kTile - 1) / kTile) * ((pr.nz + kTile - 1) / kTile);
   }
   c->ntiles = tile_base[n];
+  // z-column segments of kZSeg planes per (i, j) column
+  std::vector<long long> seg_base(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const Problem& pr = c->probs[q];
+    seg_base[q + 1] = seg_base[q] + (long long)pr.nx * pr.ny * ((pr.nz + kZSeg - 1) / kZSeg);
+  }
+  c->nsegs = seg_base[n];
   if (hipMemcpy(c->d_tile_base, tile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_seg_base, seg_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_probs, c->probs.data(), sP, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_dt, 0, sD) != hipSuccess ||
@@ -569,14 +579,14 @@ int autotune(ader_ctx* c, int reps) {
     float best_ms = 1e30f;
     // the predictor also tries its layouts, the reconstruction its modes
     int best_recon = c->recon_mode;
-    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 2 : 1;
+    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 3 : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
       if (cls == kClassPredict) {
         if (!layout_built(c, s, lay)) continue;
         c->layout = lay;
       }
       if (cls == kClassRecon) {
-        if (lay == ADER_RECON_TILED && c->order < 3) continue;
+        if ((lay == ADER_RECON_TILED || lay == ADER_RECON_COLUMNS) && c->order < 3) continue;
         c->recon_mode = lay;
       }
       for (const LaunchShape& cand : kCandidates) {
@@ -850,15 +860,16 @@ int ader_get_scheme(ader_ctx* c, int* scheme_out) {
 }
 
 int ader_set_recon(ader_ctx* c, int mode) {
-  if (!c || (mode != -1 && mode != ADER_RECON_SWEEPS && mode != ADER_RECON_TILED)) return ADER_EINVAL;
+  if (!c || (mode != -1 && mode != ADER_RECON_SWEEPS && mode != ADER_RECON_TILED &&
+             mode != ADER_RECON_COLUMNS))
+    return ADER_EINVAL;
   c->recon_mode = mode;
   return ADER_OK;
 }
 
 int ader_get_recon(ader_ctx* c, int* mode_out) {
   if (!c || !mode_out) return ADER_EINVAL;
-  *mode_out = (c->order >= 3 && c->recon_mode == ADER_RECON_TILED) ? ADER_RECON_TILED
-                                                                   : ADER_RECON_SWEEPS;
+  *mode_out = (c->order >= 3 && c->recon_mode >= 0) ? c->recon_mode : ADER_RECON_SWEEPS;
   return ADER_OK;
 }
 

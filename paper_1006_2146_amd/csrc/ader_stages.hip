@@ -42,7 +42,12 @@ int sweeps(ader_ctx* c, const double* src, T* W) {
     ADER_TRY(launched());
     k_weno_sweep<T, kOrder, 1, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
     ADER_TRY(launched());
-    k_weno_sweep<T, kOrder, 2, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+    if (c->recon_mode == ADER_RECON_COLUMNS) {
+      const unsigned gc = (unsigned)((c->nsegs + bs - 1) / bs);
+      k_weno_z_columns<T, kOrder, NVAR><<<gc, bs, 0, c->stream>>>(src, W, b, c->d_seg_base);
+    } else {
+      k_weno_sweep<T, kOrder, 2, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
+    }
   }
   return launched();
 }

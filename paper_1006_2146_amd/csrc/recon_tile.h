@@ -144,4 +144,89 @@ struct ReconTile {
   }
 };
 
+// The z sweep along column segments: a thread takes the zones (i, j, k) of
+// kZSeg consecutive planes and slides a window of 2M-1 planes down the
+// column, so each source value is read once per segment (plus the 2(M-1)
+// halo planes) instead of once per stencil point.  Same line reconstructions
+// as weno_sweep_zone<.., 2, ..>: the sources are the moments (a, b, 0) with
+// a + b <= M-2, the zone averages entering as differences in double.
+constexpr int kZSeg = 16;
+
+template <class T, int M, int NVAR>
+struct ZColumn {
+  static constexpr int R = M - 1, NW = 2 * R + 1;
+  static constexpr int NSRC = M * (M - 1) / 2;   // sources (a, b) of the z sweep
+
+  // source s -> (a, b) in the order of the sweep kernel's loops
+  __host__ __device__ static constexpr int src_a(int s) {
+    int q = 0;
+    for (int a = 0; a <= M - 2; ++a)
+      for (int b = 0; a + b <= M - 2; ++b) {
+        if (q == s) return a;
+        ++q;
+      }
+    return -1;
+  }
+  __host__ __device__ static constexpr int src_b(int s) {
+    int q = 0;
+    for (int a = 0; a <= M - 2; ++a)
+      for (int b = 0; a + b <= M - 2; ++b) {
+        if (q == s) return b;
+        ++q;
+      }
+    return -1;
+  }
+
+  __device__ static void load(const double* __restrict__ U, const T* __restrict__ W, const Grid& g,
+                              long long z, double (&u)[NVAR], T (&f)[NSRC > 1 ? NSRC - 1 : 1][NVAR]) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) u[v] = U[(long long)v * g.S + z];
+#pragma unroll
+    for (int s = 1; s < NSRC; ++s) {
+      const int src = spatial_mode(src_a(s), src_b(s), 0);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) f[s - 1][v] = W[((long long)(src - 1) * NVAR + v) * g.S + z];
+    }
+  }
+
+  __device__ static void run(const double* __restrict__ U, T* __restrict__ W, const Grid& g, int i,
+                             int j, int k0, int k1) {
+    double wu[NW][NVAR];
+    T wf[NW][NSRC > 1 ? NSRC - 1 : 1][NVAR];
+#pragma unroll
+    for (int q = 0; q < NW - 1; ++q)
+      load(U, W, g, zone_of(i, j, wrap(k0 - R + q, g.nz), g), wu[q], wf[q]);
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+      load(U, W, g, zone_of(i, j, wrap(k + R, g.nz), g), wu[NW - 1], wf[NW - 1]);
+      const long long n = zone_of(i, j, k, g);
+#pragma unroll
+      for (int s = 0; s < NSRC; ++s) {
+        const int a = src_a(s), b = src_b(s);
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) {
+          T d[NW];
+#pragma unroll
+          for (int q = 0; q < NW; ++q)
+            d[q] = s == 0 ? T(wu[q][v] - wu[R][v]) : wf[q][s > 0 ? s - 1 : 0][v];
+          T mo[M];
+          weno1d<T, M>(d, mo);
+#pragma unroll
+          for (int c = 1; c <= M - 1 - a - b; ++c)
+            W[((long long)(spatial_mode(a, b, c) - 1) * NVAR + v) * g.S + n] = mo[c];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NW - 1; ++q) {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) wu[q][v] = wu[q + 1][v];
+#pragma unroll
+        for (int s = 0; s < (NSRC > 1 ? NSRC - 1 : 1); ++s)
+#pragma unroll
+          for (int v = 0; v < NVAR; ++v) wf[q][s][v] = wf[q + 1][s][v];
+      }
+    }
+  }
+};
+
 }  // namespace ader

@@ -256,10 +256,10 @@ def test_config4_ensemble_full_size():
 @pytest.mark.parametrize("precision", [ader.ADER_FP64, ader.ADER_MIXED])
 @pytest.mark.parametrize("order", [3, 4])
 def test_tiled_reconstruction_equals_sweeps(order, precision, system):
-    # the LDS-tiled reconstruction runs the same line reconstructions as the
-    # one-kernel-per-sweep path: whole steps agree to rounding (multiply-adds
-    # may be contracted differently), on ragged problems smaller and larger
-    # than a tile
+    # the LDS-tiled and the z-column reconstructions run the same line
+    # reconstructions as the one-kernel-per-sweep path: whole steps agree to
+    # rounding (multiply-adds may be contracted differently), on ragged
+    # problems smaller and larger than a tile or a column segment
     shapes = [(9, 14, 21), (1, 1, 1), (5, 3, 17), (16, 16, 16), (2, 9, 1)]
     mhd = system == "mhd"
     states = _states(shapes, mhd=mhd)
@@ -267,7 +267,7 @@ def test_tiled_reconstruction_equals_sweeps(order, precision, system):
     if mhd:
         kw.update(gamma=5.0 / 3.0, system=ader.ADER_MHD)
     out = {}
-    for mode in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_TILED):
+    for mode in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS):
         say("recon mode", mode, order, precision, system)
         with ader.BatchSolver(shapes, **kw) as b:
             ader.ader_set_recon(b.ctx, mode)
@@ -278,6 +278,7 @@ def test_tiled_reconstruction_equals_sweeps(order, precision, system):
                 b.step_cfl(0.3)
             out[mode] = [b.get_state(i) for i in range(len(shapes))]
     tol = 1e-14 if precision == ader.ADER_FP64 else 1e-7
-    for a, c in zip(out[ader.ADER_RECON_SWEEPS], out[ader.ADER_RECON_TILED]):
-        for x, y in (zip(a, c) if mhd else [(a, c)]):
-            assert np.abs(x - y).max() <= tol * np.abs(x).max()
+    for other in (ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS):
+        for a, c in zip(out[ader.ADER_RECON_SWEEPS], out[other]):
+            for x, y in (zip(a, c) if mhd else [(a, c)]):
+                assert np.abs(x - y).max() <= tol * np.abs(x).max(), other
