@@ -33,6 +33,7 @@ WORKLOAD = "sedov-modes-128^3"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 78.6}
 PUBLISHED_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
+RECON_NAMES = ["sweeps", "tiled", "columns"]
 LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves",
                 5: "pair", 6: "pair-2waves"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
@@ -152,7 +153,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         finite = bool(torch.isfinite(dU).all().item())
         launch = ader.ader_get_launch(s.ctx)
         layout = LAYOUT_NAMES[ader.ader_get_layout(s.ctx)]
-        recon_mode = ["sweeps", "tiled"][ader.ader_get_recon(s.ctx)]
+        recon_mode = RECON_NAMES[ader.ader_get_recon(s.ctx)]
     finally:
         s.close()
     wall = t1 - t0
@@ -312,7 +313,7 @@ def run_ensemble(ader, torch, steps, warmup):
                          "stage_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in stages.items()},
                          "launch": ader.ader_get_launch(b.ctx),
                          "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(b.ctx)],
-                         "recon_mode": ["sweeps", "tiled"][ader.ader_get_recon(b.ctx)]}
+                         "recon_mode": RECON_NAMES[ader.ader_get_recon(b.ctx)]}
         log("ensemble", name, "%.3e zone-updates/s" % out[name]["zone_updates_per_s"])
     out["mixed_over_fp64"] = out["mixed"]["zone_updates_per_s"] / out["fp64"]["zone_updates_per_s"]
     return out
