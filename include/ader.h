@@ -247,7 +247,7 @@ int ader_get_layout(ader_ctx* ctx, int* layout_out);
  * ADER_RECON_SWEEPS, one launch per sweep direction, ADER_RECON_TILED, one
  * launch doing the x, y and z sweeps of 8 x 8 x 8-zone tiles in LDS (halo
  * M-1 zones), ADER_RECON_COLUMNS, the x and y sweeps as launches and the z
- * sweep by threads that slide a window down 16-plane column segments, or -1
+ * sweep by threads that slide a window down 8-plane column segments, or -1
  * for the default (sweeps).  All run the same line reconstructions (modes
  * equal up to rounding); order 2 (minmod) always runs per zone.
  * ader_autotune also picks it; ader_get_recon returns the mode in use. */

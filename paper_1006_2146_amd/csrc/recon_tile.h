@@ -150,7 +150,7 @@ struct ReconTile {
 // halo planes) instead of once per stencil point.  Same line reconstructions
 // as weno_sweep_zone<.., 2, ..>: the sources are the moments (a, b, 0) with
 // a + b <= M-2, the zone averages entering as differences in double.
-constexpr int kZSeg = 16;
+constexpr int kZSeg = 8;
 
 template <class T, int M, int NVAR>
 struct ZColumn {
@@ -189,16 +189,19 @@ struct ZColumn {
     }
   }
 
+  // The window holds planes k-R .. k+R and one plane ahead (k+R+1), whose
+  // loads are issued before plane k is reconstructed so that their latency
+  // overlaps the arithmetic.
   __device__ static void run(const double* __restrict__ U, T* __restrict__ W, const Grid& g, int i,
                              int j, int k0, int k1) {
-    double wu[NW][NVAR];
-    T wf[NW][NSRC > 1 ? NSRC - 1 : 1][NVAR];
+    double wu[NW + 1][NVAR];
+    T wf[NW + 1][NSRC > 1 ? NSRC - 1 : 1][NVAR];
 #pragma unroll
-    for (int q = 0; q < NW - 1; ++q)
+    for (int q = 0; q < NW; ++q)
       load(U, W, g, zone_of(i, j, wrap(k0 - R + q, g.nz), g), wu[q], wf[q]);
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
-      load(U, W, g, zone_of(i, j, wrap(k + R, g.nz), g), wu[NW - 1], wf[NW - 1]);
+      if (k + 1 < k1) load(U, W, g, zone_of(i, j, wrap(k + R + 1, g.nz), g), wu[NW], wf[NW]);
       const long long n = zone_of(i, j, k, g);
 #pragma unroll
       for (int s = 0; s < NSRC; ++s) {
@@ -217,7 +220,7 @@ struct ZColumn {
         }
       }
 #pragma unroll
-      for (int q = 0; q < NW - 1; ++q) {
+      for (int q = 0; q < NW; ++q) {
 #pragma unroll
         for (int v = 0; v < NVAR; ++v) wu[q][v] = wu[q + 1][v];
 #pragma unroll
