@@ -41,6 +41,8 @@ def load():
         DP = ctypes.POINTER(ctypes.c_double)
         lib.hostemu_step.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, I, D]
         lib.hostemu_step.restype = I
+        lib.hostemu_step_rk.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, D]
+        lib.hostemu_step_rk.restype = I
         lib.hostemu_dt.argtypes = [DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt.restype = D
         lib.hostemu_step_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, I, I, I, I, D]
@@ -64,6 +66,17 @@ def step(U, dt, order, form="modal", riemann="hll", precision="fp64",
     load().hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
                         dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
                         1 if riemann == "linearized" else 0, PRECISION[precision], dt)
+    return out
+
+
+def step_rk(U, dt, order, riemann="hll", precision="fp64", lengths=(1.0, 1.0, 1.0),
+            gamma=1.4):
+    """One SSP-RK step (Euler) of the host build of the RK kernels."""
+    out = np.ascontiguousarray(U, dtype=np.float64).copy()
+    nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
+    load().hostemu_step_rk(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
+                           dx, dy, dz, gamma, order, 1 if riemann == "linearized" else 0,
+                           PRECISION[precision], dt)
     return out
 
 

@@ -53,6 +53,57 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
   for (long long n = 0; n < N; ++n) update_zone(U, F.data(), g, dt, dx, dy, dz, n);
 }
 
+// One SSP-RK step (Sec. II.d) of the Euler equations from the RK kernels'
+// per-zone functions: the stage weights of eq. (18), (19) and (20) are
+// restated here (the host build has no access to the library's table).
+template <class T, bool DEV>
+static void emu_rk_step(double* U, Grid g, double dx, double dy, double dz, double gam,
+                        int order, int riemann, double dt) {
+  struct Row { double a_n, a_c, c_l, a_2, a_3, c_d; int keep; };
+  static const Row rk2[] = {{0, 1, 1, 0, 0, 0, 0}, {0.5, 0.5, 0.5, 0, 0, 0, 0}};
+  static const Row rk3[] = {{0, 1, 1, 0, 0, 0, 0}, {0.75, 0.25, 0.25, 0, 0, 0, 0},
+                            {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 0, 0, 0, 0}};
+  static const Row rk54[] = {
+      {0, 1, 0.39175222700392, 0, 0, 0, 0},
+      {0.44437049406734, 0.55562950593266, 0.36841059262959, 0, 0, 0, 2},
+      {0.62010185138540, 0.37989814861460, 0.25189177424738, 0, 0, 0, 3},
+      {0.17807995410773, 0.82192004589227, 0.54497475021237, 0, 0, 0, 4},
+      {0.00683325884039, 0.34833675773694, 0.22600748319395, 0.51723167208978,
+       0.12759831133288, 0.08460416338212, 0}};
+  const Row* rows = order == 2 ? rk2 : order == 3 ? rk3 : rk54;
+  const int nst = order == 2 ? 2 : order == 3 ? 3 : 5;
+  const long long N = g.N;
+  std::vector<T> W((size_t)19 * 5 * N), PK((size_t)90 * N);
+  std::vector<double> F((size_t)15 * N), Un(U, U + 5 * N), S2(5 * N), S3(5 * N), D3(5 * N);
+  for (int s = 0; s < nst; ++s) {
+    if (order == 2) {
+      for (long long n = 0; n < N; ++n) minmod_zone<T>(U, W.data(), g, n);
+    } else if (order == 3) {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 0>(U, W.data(), g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 1>(U, W.data(), g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 3, 2>(U, W.data(), g, n);
+    } else {
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 0>(U, W.data(), g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 1>(U, W.data(), g, n);
+      for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 2>(U, W.data(), g, n);
+    }
+    for (long long n = 0; n < N; ++n) {
+      if (order == 2) rk_sides_zone<T, 2, DEV>(U, W.data(), PK.data(), g, gam, n);
+      else if (order == 3) rk_sides_zone<T, 3, DEV>(U, W.data(), PK.data(), g, gam, n);
+      else rk_sides_zone<T, 4, DEV>(U, W.data(), PK.data(), g, gam, n);
+    }
+    for (long long n = 0; n < N; ++n) {
+      if (riemann == 0) face_flux_zone<T, 0, DEV>(U, PK.data(), F.data(), g, gam, n);
+      else face_flux_zone<T, 1, DEV>(U, PK.data(), F.data(), g, gam, n);
+    }
+    const Row& r = rows[s];
+    const RkStage st{r.a_n, r.a_c, r.c_l, r.a_2, r.a_3, r.c_d, Un.data(), S2.data(), S3.data(),
+                     D3.data(), r.keep == 2 ? S2.data() : r.keep == 3 ? S3.data() : nullptr,
+                     r.keep == 4 ? D3.data() : nullptr};
+    for (long long n = 0; n < N; ++n) rk_stage_zone(U, F.data(), st, g, dt, dx, dy, dz, n);
+  }
+}
+
 template <class T>
 static void emu_recon(const double* src, T* W, Grid g, int order, int nvar) {
   const long long N = g.N;
@@ -178,6 +229,19 @@ int hostemu_step(double* U, int nx, int ny, int nz, double dx, double dy, double
     emu_step<float, true>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
   else
     emu_step<double, true>(U, g, dx, dy, dz, gam, order, form, riemann, dt);
+  return 0;
+}
+
+// One SSP-RK step of the host build (Euler), in place on U[5][nz][ny][nx].
+int hostemu_step_rk(double* U, int nx, int ny, int nz, double dx, double dy, double dz,
+                    double gam, int order, int riemann, int precision, double dt) {
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
+  if (precision == 0)
+    emu_rk_step<double, false>(U, g, dx, dy, dz, gam, order, riemann, dt);
+  else if (precision == 1)
+    emu_rk_step<float, true>(U, g, dx, dy, dz, gam, order, riemann, dt);
+  else
+    emu_rk_step<double, true>(U, g, dx, dy, dz, gam, order, riemann, dt);
   return 0;
 }
 

@@ -120,3 +120,26 @@ def test_kernel_source_mhd_eigensystem():
                                  du[:, None], axis)[:, 0]
             Dk = hostemu.mhd_dissipation(ul, ur, du, axis, G)
             assert np.abs(Dk - Do).max() <= 1e-12 * np.abs(Do).max()
+
+
+# ------------------------------------------------ SSP-RK (Sec. II.d), Euler --
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp64dev", 1e-12), ("mixed", 1e-7)])
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_kernel_source_rk(order, rs, precision, tol):
+    # the RK side-packet and stage-combination kernels, built for the host,
+    # against the oracle's SSP-RK steps (a smooth ragged mesh, then a blast
+    # where the positivity scaling acts)
+    from oracle import rk as ork
+    for U0, lengths in ((workloads.random_smooth((7, 9, 11), seed=order + 5), (1.0, 0.8, 1.3)),
+                        (workloads.blast((8, 8, 8), p_in=100.0, p_out=0.1, radius=0.25),
+                         (1.0, 1.0, 1.0))):
+        cfg = OracleConfig(order=order, riemann=rs, lengths=lengths)
+        U = U0
+        for it in range(2):
+            dt = hostemu.compute_dt(U, 0.3, lengths)
+            Ue = hostemu.step_rk(U, dt, order, rs, precision=precision, lengths=lengths)
+            err = rel_l1(Ue, ork.step_rk(U, dt, cfg))
+            assert np.all(err <= tol), (it, err)
+            U = Ue
