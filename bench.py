@@ -35,7 +35,7 @@ PUBLISHED_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_PEAK_GBS = 8000.0
 RECON_NAMES = ["sweeps", "tiled", "columns"]
 LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves",
-                5: "pair", 6: "pair-2waves"}
+                5: "pair", 6: "pair-2waves", 7: "pair-2kernels"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
 
 
@@ -278,6 +278,44 @@ def run_schemes(ader, torch, U0, steps, warmup, Um=None, Bm=None):
     return out
 
 
+def run_host_roundtrip(ader, U0, steps):
+    """The same 128^3 mixed HLL run through the host-buffer entry points:
+    ader_set_state from host memory, `steps` CFL steps, ader_get_state back
+    to host memory, all inside the timed region (the PCIe-inclusive rate; the
+    headline value keeps the state resident)."""
+    nz, ny, nx = SHAPE
+    N = nx * ny * nz
+    s = ader.Solver(SHAPE, order=3, riemann=ader.ADER_HLL, precision=ader.ADER_MIXED)
+    try:
+        cfg = TUNE.saved.get("mixed-hll")
+        if cfg:
+            ader.ader_set_launch(s.ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
+            ader.ader_set_layout(s.ctx, cfg["layout"])
+            ader.ader_set_recon(s.ctx, cfg["recon"])
+        s.set_state(U0)
+        s.step_cfl(CFL)
+        s.synchronize()
+        t0 = time.perf_counter()
+        s.set_state(U0)
+        for _ in range(steps):
+            s.step_cfl(CFL)
+        out = s.get_state()
+        t1 = time.perf_counter()
+        t2 = time.perf_counter()
+        s.set_state(U0)
+        s.synchronize()
+        t3 = time.perf_counter()
+        s.get_state()
+        t4 = time.perf_counter()
+    finally:
+        s.close()
+    assert np.isfinite(out).all()
+    return {"steps": steps, "zone_updates_per_s": N * steps / (t1 - t0),
+            "set_state_ms": 1e3 * (t3 - t2), "get_state_ms": 1e3 * (t4 - t3),
+            "note": "set_state from host, %d CFL steps (eager), get_state to host, all timed"
+                    % steps}
+
+
 def run_ensemble(ader, torch, steps, warmup):
     """The batched ensemble: 64 uneven problems, order 3, HLL, mixed
     precision, one persistent launch per stage, graph-replayed, autotuned."""
@@ -509,6 +547,11 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % nbytes)
 
+    roundtrip = None
+    if "mixed-hll" in variants:
+        log("host round trip")
+        roundtrip = run_host_roundtrip(ader, U0, args.steps)
+
     schemes = None
     if not args.no_schemes:
         log("ADER vs SSP-RK")
@@ -582,6 +625,7 @@ def main():
         "ensemble": ensemble,
         "turbulent_mhd": turbulent,
         "ader_vs_ssprk": schemes,
+        "host_roundtrip": roundtrip,
     }
     for prec in ("fp64", "mixed"):
         if prec + "-hll" in variants and prec + "-hll-nodal" in variants:

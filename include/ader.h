@@ -233,13 +233,16 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * compiled to fit two waves per SIMD (Euler, orders 2 and 3 only),
  * ADER_LAYOUT_PAIR, two lanes per zone each holding four of the eight MHD
  * variables and exchanging them for each flux (MHD, orders 3 and 4 only),
- * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD, or -1 for
- * the default of the setting
+ * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD,
+ * ADER_LAYOUT_PAIR_SPLIT, the pair layout in two kernels (the predictor,
+ * then the side packets; the evolutionary modes pass through device memory,
+ * allocated on first use), or -1 for the default of the setting
  * (split for MHD at orders 3-4 and Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,
-       ADER_LAYOUT_ZONE_2W = 4, ADER_LAYOUT_PAIR = 5, ADER_LAYOUT_PAIR2 = 6 };
+       ADER_LAYOUT_ZONE_2W = 4, ADER_LAYOUT_PAIR = 5, ADER_LAYOUT_PAIR2 = 6,
+       ADER_LAYOUT_PAIR_SPLIT = 7 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
 

@@ -54,6 +54,7 @@ struct StageFns {
   int (*predict_zone_2w)(ader_ctx*);  // one lane per zone, registers capped for 2 waves/SIMD
   int (*predict_pair)(ader_ctx*);     // MHD: two lanes per zone
   int (*predict_pair2)(ader_ctx*);    // the same, registers capped for 2 waves/SIMD
+  int (*predict_pair_split)(ader_ctx*);  // the same in two kernels (predictor, sides)
   int (*rk_sides)(ader_ctx*);         // SSP-RK stage: side packets (Euler, modal tables)
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
@@ -96,7 +97,11 @@ struct ader_ctx {
   bool have_dt = false;
   size_t bytes = 0;          // device bytes held: fixed part plus work arrays
   size_t fixed_bytes = 0;
-  size_t work_bytes[5] = {0, 0, 0, 0, 0};   // W, PK, WB, BN, RK as allocated
+  size_t work_bytes[7] = {0, 0, 0, 0, 0, 0, 0};   // W, PK, WB, BN, RK, EM, TH as allocated
+  // MHD pair layout in two kernels: evolutionary modes [NE][8][S] in the
+  // bulk type and the two positivity scaling factors [2][S]
+  void* EM = nullptr;
+  double* TH = nullptr;
   // time stepping (ADER_SCHEME_*); SSP-RK keeps four extra states in RK:
   // the step's starting state, the stage states 2 and 3 and dt L(U^(3))
   int scheme = ADER_SCHEME_ADER;

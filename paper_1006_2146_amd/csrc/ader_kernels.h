@@ -263,16 +263,18 @@ __global__ void __launch_bounds__(256) k_copy_state(const double* __restrict__ s
   });
 }
 
-// pair layout (MHD): two lanes per zone, 32 zones per wave
-template <class T, int ORDER, int FORM, int WAVES, bool EDGES_ALL>
+// pair layout (MHD): two lanes per zone, 32 zones per wave; PHASE as in
+// predict_zone_mhd_pair (0: whole, 1: predictor, 2: side packets)
+template <class T, int ORDER, int FORM, int WAVES, bool EDGES_ALL, int PHASE = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_pair(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, Batch b,
-    const double* __restrict__ dt, double gam) {
+    const double* __restrict__ dt, double gam, T* __restrict__ EM = nullptr,
+    double* __restrict__ TH = nullptr) {
   for_zone_groups<2>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
-    predict_zone_mhd_pair<T, ORDER, FORM, kDeviation<T>, EDGES_ALL>(
+    predict_zone_mhd_pair<T, ORDER, FORM, kDeviation<T>, EDGES_ALL, PHASE>(
         L, U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz,
-        gam, n);
+        gam, n, EM, TH);
   });
 }
 

@@ -96,6 +96,7 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
     case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w != nullptr;
     case ADER_LAYOUT_PAIR: return s->predict_pair != nullptr;
     case ADER_LAYOUT_PAIR2: return s->predict_pair2 != nullptr;
+    case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split != nullptr;
   }
   return false;
 }
@@ -114,6 +115,7 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_ZONE_2W: return s->predict_zone_2w(c);
     case ADER_LAYOUT_PAIR: return s->predict_pair(c);
     case ADER_LAYOUT_PAIR2: return s->predict_pair2(c);
+    case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split(c);
     default: return s->predict(c);
   }
 }
@@ -227,12 +229,15 @@ int ensure_work(ader_ctx* c) {
   const size_t t = c->precision == ADER_FP64 ? sizeof(double) : sizeof(float);
   const size_t ls = c->order == 2 ? 4 : c->order == 3 ? 10 : 20;
   const bool mhd = c->system == ADER_MHD;
-  const size_t need[5] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
+  const size_t ne = c->order == 2 ? 1 : c->order == 3 ? 5 : 15;   // evolutionary modes
+  const bool split = mhd && c->order >= 3 && c->layout == ADER_LAYOUT_PAIR_SPLIT;
+  const size_t need[7] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
                           mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0,
                           c->scheme == ADER_SCHEME_SSPRK ? sizeof(double) * 4 * (mhd ? 8 : 5) * Z
-                                                         : 0};
-  void** buf[5] = {&c->W, &c->PK, &c->WB, &c->BN, (void**)&c->RK};
-  for (int q = 0; q < 5; ++q) {
+                                                         : 0,
+                          split ? t * ne * 8 * Z : 0, split ? sizeof(double) * 2 * Z : 0};
+  void** buf[7] = {&c->W, &c->PK, &c->WB, &c->BN, (void**)&c->RK, &c->EM, (void**)&c->TH};
+  for (int q = 0; q < 7; ++q) {
     if (need[q] <= c->work_bytes[q]) continue;
     if (*buf[q]) {
       // a captured step holds the old address: rebuild it on its next use
@@ -245,14 +250,14 @@ int ensure_work(ader_ctx* c) {
     if (hipMalloc(buf[q], need[q]) != hipSuccess) {
       *buf[q] = nullptr;
       (void)hipGetLastError();
-      c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] +
-                 c->work_bytes[3] + c->work_bytes[4];
+      c->bytes = c->fixed_bytes;
+      for (size_t w : c->work_bytes) c->bytes += w;
       return ADER_ENOMEM;
     }
     c->work_bytes[q] = need[q];
   }
-  c->bytes = c->fixed_bytes + c->work_bytes[0] + c->work_bytes[1] + c->work_bytes[2] +
-             c->work_bytes[3] + c->work_bytes[4];
+  c->bytes = c->fixed_bytes;
+  for (size_t w : c->work_bytes) c->bytes += w;
   return ADER_OK;
 }
 
@@ -371,7 +376,7 @@ void free_buffers(ader_ctx* c) {
   if (c->owns_U && c->U) (void)hipFree(c->U);
   if (c->owns_B && c->B) (void)hipFree(c->B);
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
-                  (void*)c->RK,
+                  (void*)c->RK, c->EM, (void*)c->TH,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs,
                   (void*)c->d_tile_base, (void*)c->d_seg_base})
     if (p) (void)hipFree(p);
@@ -517,7 +522,7 @@ int get_problem(ader_ctx* c, int q, double* U, double* B) {
 // of that stage alone) and keep the fastest.  The state is saved first and
 // restored at the end, so tuning does not advance the solution.
 // ---------------------------------------------------------------------------
-constexpr int kNumLayouts = 7;
+constexpr int kNumLayouts = 8;
 constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
                                        {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
 
@@ -584,6 +589,8 @@ int autotune(ader_ctx* c, int reps) {
       if (cls == kClassPredict) {
         if (!layout_built(c, s, lay)) continue;
         c->layout = lay;
+        rc = ensure_work(c);   // a layout may need buffers of its own
+        if (rc != ADER_OK) break;
       }
       if (cls == kClassRecon) {
         if ((lay == ADER_RECON_TILED || lay == ADER_RECON_COLUMNS) && c->order < 3) continue;
@@ -840,7 +847,8 @@ int ader_set_layout(ader_ctx* c, int layout) {
   if (layout == ADER_LAYOUT_ZONE2 && c->order > 3) return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_ZONE_2W && (c->order > 3 || c->system == ADER_MHD))
     return ADER_EUNSUPPORTED;
-  if ((layout == ADER_LAYOUT_PAIR || layout == ADER_LAYOUT_PAIR2) &&
+  if ((layout == ADER_LAYOUT_PAIR || layout == ADER_LAYOUT_PAIR2 ||
+       layout == ADER_LAYOUT_PAIR_SPLIT) &&
       (c->order < 3 || c->system != ADER_MHD))
     return ADER_EUNSUPPORTED;
   c->layout = layout;

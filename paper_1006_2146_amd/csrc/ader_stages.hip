@@ -137,6 +137,36 @@ int predict_pair(ader_ctx* c) {
   }
 }
 
+// the pair layout in two kernels: the predictor (modes to EM, scaling
+// factors to TH), then the side packets
+int predict_pair_split(ader_ctx* c) {
+  if constexpr (kMhd && kOrder >= 3) {
+    const unsigned g = grid_for(c, kClassPredict, 32);
+    const int bs = c->shape[kClassPredict].block;
+    const T* W = static_cast<const T*>(c->W);
+    T* PK = static_cast<T*>(c->PK);
+    const T* WB = static_cast<const T*>(c->WB);
+    const T* BN = static_cast<const T*>(c->BN);
+    T* EM = static_cast<T*>(c->EM);
+    if (c->riemann == ADER_LINEARIZED) {
+      k_predict_mhd_pair<T, kOrder, kForm, 1, true, 1><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma, EM, c->TH);
+      ADER_TRY(launched());
+      k_predict_mhd_pair<T, kOrder, kForm, 1, true, 2><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma, EM, c->TH);
+    } else {
+      k_predict_mhd_pair<T, kOrder, kForm, 1, false, 1><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma, EM, c->TH);
+      ADER_TRY(launched());
+      k_predict_mhd_pair<T, kOrder, kForm, 1, false, 2><<<g, bs, 0, c->stream>>>(
+          c->U, W, c->B0, WB, BN, PK, c->batch(), c->d_dt, c->gamma, EM, c->TH);
+    }
+    return launched();
+  } else {
+    return ADER_EUNSUPPORTED;
+  }
+}
+
 // SSP-RK stage (Euler): side packets of the spatial polynomial; the tables
 // are those of the modal scheme of the order
 int rk_sides(ader_ctx* c) {
@@ -203,6 +233,7 @@ const StageFns kStages = {recon,
                           (!kMhd && kOrder <= 3) ? predict<true, 2> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair<1> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair<2> : nullptr,
+                          (kMhd && kOrder >= 3) ? predict_pair_split : nullptr,
                           kForm == 0 ? rk_sides : nullptr,
                           flux,
                           update};

@@ -379,13 +379,17 @@ __device__ double theta_facial_pair(const SplitLane& L, const double (&w0)[8],
 
 // The same operations as predict_zone_mhd, in the pair layout.  EDGES_ALL:
 // every variable's edge averages are stored (linearized flux), else only the
-// field component each edge needs.
-template <class T, int ORDER, int FORM, bool DEV, bool EDGES_ALL>
+// field component each edge needs.  PHASE 0 does it all; PHASE 1 stops after
+// the predictor and its positivity scaling, storing the (scaled)
+// evolutionary modes in EM (rows m*8 + v) and the two scaling factors in TH
+// (rows 0: spatial, 1: facial); PHASE 2 reloads them and forms the side
+// packets, so each of the two kernels holds fewer live values.
+template <class T, int ORDER, int FORM, bool DEV, bool EDGES_ALL, int PHASE = 0>
 __device__ __forceinline__ void predict_zone_mhd_pair(
     const SplitLane& L, const double* __restrict__ U, const T* __restrict__ W,
     const double* __restrict__ B0, const T* __restrict__ WB, const T* __restrict__ BN,
     T* __restrict__ PK, const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz,
-    double gam, long long n) {
+    double gam, long long n, T* __restrict__ EM = nullptr, double* __restrict__ TH = nullptr) {
   constexpr int VPL = kPairVars;
   using S = typename SchemeOf<ORDER, FORM, T, VPL>::type;
   constexpr int LS = S::LS, NE = S::NE;
@@ -430,11 +434,16 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
         w[m][1 + c] = rn.row((a - 1) * 3 + c);
       }
   }
+  double th_s = 1.0;
   {
-    PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
-    S::spatial_points_all(w, scan);
-    const double theta =
-        scan.inner.near ? theta_spatial_pair(L, w0, w, S::spatial_phi_all, gam) : 1.0;
+    if constexpr (PHASE == 2) {
+      th_s = TH[n];
+    } else {
+      PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
+      S::spatial_points_all(w, scan);
+      th_s = scan.inner.near ? theta_spatial_pair(L, w0, w, S::spatial_phi_all, gam) : 1.0;
+    }
+    const double theta = th_s;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll
@@ -445,8 +454,22 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
   }
   const PairFlux<Mhd<T>, T, DEV> ph{FluxOf<Mhd<T>, T, DEV>::make(w0, gam), L};
   T e[NE][VPL];
-  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
-  {
+  if constexpr (PHASE == 2) {
+    const double theta = TH[g.S + n];
+    if (theta < 1.0) {
+      const T th = T(theta);
+#pragma unroll
+      for (int m = 1; m < LS; ++m)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) w[m][k] *= th;
+    }
+    RowCursor<const T> re(EM, g.S, n, v0);
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+#pragma unroll
+      for (int k = 0; k < VPL; ++k) e[m][k] = re.row(m * 8 + v0 + k);
+  } else {
+    S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
     PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
     S::facial_points_all(w, e, scan);
     const double theta =
@@ -461,6 +484,18 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
       for (int m = 0; m < NE; ++m)
 #pragma unroll
         for (int k = 0; k < VPL; ++k) e[m][k] *= th;
+    }
+    if constexpr (PHASE == 1) {
+      RowCursor<T> re(EM, g.S, n, v0);
+#pragma unroll
+      for (int m = 0; m < NE; ++m)
+#pragma unroll
+        for (int k = 0; k < VPL; ++k) re.row(m * 8 + v0 + k) = e[m][k];
+      if (L.var == 0) {
+        TH[n] = th_s;
+        TH[g.S + n] = theta;
+      }
+      return;
     }
   }
   auto side = [&](auto side_c) {

@@ -98,7 +98,7 @@ def test_mixed_error_vs_truncation(order, n, rs):
 
 
 MHD_LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT2, ader.ADER_LAYOUT_PAIR,
-               ader.ADER_LAYOUT_PAIR2]
+               ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT]
 
 
 @pytest.mark.parametrize("rs", ["hll", "linearized"])

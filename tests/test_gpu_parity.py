@@ -201,7 +201,7 @@ def test_mhd_linearized_layouts():
     U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=31)
     cfg = OracleConfig(order=3, gamma=G53, riemann="linearized")
     for layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
-                   ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2):
+                   ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT):
         with _mhd_solver((6, 7, 8), 3, "modal", rs="linearized") as s:
             ader.ader_set_layout(s.ctx, layout)
             s.set_state(U0, B0)
@@ -240,7 +240,7 @@ def test_config3_mhd_full_size_sampled():
 
 LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
            ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W, ader.ADER_LAYOUT_PAIR,
-           ader.ADER_LAYOUT_PAIR2]
+           ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT]
 
 
 def _skip_unbuilt(layout, order, mhd=False):
@@ -249,7 +249,8 @@ def _skip_unbuilt(layout, order, mhd=False):
                     "orders 2 and 3")
     if layout == ader.ADER_LAYOUT_ZONE_2W and (order > 3 or mhd):
         pytest.skip("the two-wave one-lane-per-zone instance is built for Euler at orders 2-3")
-    if layout in (ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2) and (order < 3 or not mhd):
+    if layout in (ader.ADER_LAYOUT_PAIR, ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT) \
+            and (order < 3 or not mhd):
         pytest.skip("the pair layout is built for MHD at orders 3-4")
 
 
@@ -302,7 +303,7 @@ def test_parity_layouts_mhd(layout, order):
 def test_layout_errors():
     with _solver((4, 4, 4), 2, "modal", "hll") as s:
         assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_SPLIT) == ader.ADER_EUNSUPPORTED
-        assert ader.load().ader_set_layout(s.ctx, 7) == ader.ADER_EINVAL
+        assert ader.load().ader_set_layout(s.ctx, 9) == ader.ADER_EINVAL
         assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE
         ader.ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE2)
         assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE2
