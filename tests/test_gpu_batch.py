@@ -181,6 +181,34 @@ def test_graph_follows_order_and_precision_changes():
             assert np.array_equal(g.get_state(), e.get_state()), (order, prec)
 
 
+def test_graph_follows_mhd_two_kernel_layout_buffers():
+    # the two-kernel pair layout allocates its mode buffer for the order and
+    # precision in use; order and precision changes grow it under the graph
+    G53 = 5.0 / 3.0
+    shape = (7, 8, 9)
+    U0, B0 = workloads.mhd_random_field(shape, seed=33)
+    stream = torch.cuda.Stream()
+    seq = [(3, ader.ADER_MIXED), (4, ader.ADER_MIXED), (4, ader.ADER_FP64), (3, ader.ADER_FP64)]
+    kw = dict(gamma=G53, system=ader.ADER_MHD, order=3)
+    with ader.Solver(shape, **kw) as e, ader.Solver(shape, stream=stream.cuda_stream, **kw) as g:
+        for s in (e, g):
+            ader.ader_set_layout(s.ctx, ader.ADER_LAYOUT_PAIR_SPLIT)
+            s.set_state(U0, B0)
+        ader.ader_set_graph(g.ctx, True)
+        for order, prec in seq:
+            say("mhd two-kernel layout, order", order, "precision", prec)
+            for s in (e, g):
+                ader.ader_set_order(s.ctx, order)
+                ader.ader_set_precision(s.ctx, prec)
+                assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_PAIR_SPLIT
+            for _ in range(2):
+                e.step_cfl(0.3)
+                g.step_cfl(0.3)
+            g.synchronize()
+            (Ue, Be), (Ug, Bg) = e.get_state(), g.get_state()
+            assert np.array_equal(Ug, Ue) and np.array_equal(Bg, Be), (order, prec)
+
+
 def test_graph_needs_a_stream():
     with ader.Solver((4, 4, 4)) as s:
         assert ader.load().ader_set_graph(s.ctx, 1) == ader.ADER_EUNSUPPORTED
