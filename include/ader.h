@@ -237,7 +237,7 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * ADER_LAYOUT_PAIR_SPLIT, the pair layout in two kernels (the predictor,
  * then the side packets; the evolutionary modes pass through device memory,
  * allocated on first use), or -1 for the default of the setting
- * (split for MHD at orders 3-4 and Euler at order 4).  Results do not
+ * (pair for MHD at orders 3-4, split for Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,

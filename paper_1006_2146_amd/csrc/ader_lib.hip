@@ -82,9 +82,9 @@ int queue_dt(ader_ctx* c, double cfl) {
   return ADER_OK;
 }
 
-// The predictor layout in use: the one set, else lane-split where it keeps
-// the per-lane state small enough to avoid spills (MHD at orders 3 and 4,
-// Euler at order 4), one lane per zone otherwise.
+// The predictor layout in use: the one set, else the layout measured fastest
+// without tuning: two lanes per zone for MHD at orders 3 and 4, one lane per
+// zone and variable for Euler at order 4, one lane per zone otherwise.
 bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
   if (layout == ADER_LAYOUT_ZONE2 && c->system == ADER_MHD && c->riemann == ADER_LINEARIZED)
     return false;
@@ -103,7 +103,8 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
 
 int layout_of(const ader_ctx* c, const StageFns* s) {
   if (c->layout >= 0 && layout_built(c, s, c->layout)) return c->layout;
-  if (s->predict_split && (c->system == ADER_MHD || c->order == 4)) return ADER_LAYOUT_SPLIT;
+  if (s->predict_pair && c->system == ADER_MHD) return ADER_LAYOUT_PAIR;
+  if (s->predict_split && c->order == 4) return ADER_LAYOUT_SPLIT;
   return ADER_LAYOUT_ZONE;
 }
 
