@@ -258,6 +258,125 @@ def _scaled_fluxes(ubar, dt, dx, gamma):
     return fbar, gbar, hbar
 
 
+# ----------------------------------------------------------- source terms --
+# The scaled nodal sources are s = dt S(u) at the nodes of eq. (31), (37),
+# (46).  Their modes follow the flux rules with f, g, h -> s where the paper
+# says so, and eq. (34), (43), (52) for the rest; they enter the evolution
+# equations (30), (36), (45), and dt times the space-time average of the
+# source, eq. (35), (44), (53), enters the update eq. (6).
+
+def source_modes_2(s):
+    """Eq. (34)."""
+    m = {1: (s[1] + s[2] + s[3] + s[4] + s[5] + s[6]) / 6.0}
+    m[5] = s[7] - m[1]
+    return m
+
+
+def source_modes_3(s):
+    """Eq. (40)-(42) with f, g, h -> s, then eq. (43)."""
+    r = flux_modes_3(s, s, s)
+    m = {2: r['f2'], 3: r['g3'], 4: r['h4'], 5: r['f5'], 6: r['g6'], 7: r['h7'],
+         13: r['f13'], 14: r['g14'], 15: r['h15']}
+    m[1] = s[1] + (m[5] + m[6] + m[7]) / 12.0
+    m[11] = 2.0 * (s[14] + s[15] + s[16] + s[17] + s[18] + s[19] - 6.0 * m[1]) / 3.0 - s[20] + s[1]
+    m[12] = s[20] - s[1] - m[11]
+    return m
+
+
+def source_modes_4(s):
+    """Eq. (49)-(51) with f, g, h -> s, then eq. (52)."""
+    r = flux_modes_4(s, s, s)
+    m = {2: r['f2'], 3: r['g3'], 4: r['h4'], 5: r['f5'], 6: r['g6'], 7: r['h7'], 8: r['f8'],
+         9: r['g9'], 10: r['f10'], 24: r['f24'], 25: r['g25'], 26: r['h26'], 27: r['f27'],
+         28: r['g28'], 29: r['h29'], 30: r['f30'], 31: r['g31'], 32: r['h32'], 33: r['f33'],
+         34: r['g34'], 35: r['f35']}
+    m[1] = 0.125 * (s[14] + s[15] + s[16] + s[17] + s[18] + s[19] + s[20] + s[21]) \
+        - (m[5] + m[6] + m[7]) / 6.0
+    m[23] = 4.5 * (s[42] - s[1]) - 13.5 * (s[35] - s[22])
+    m[22] = 2.25 * (s[1] - s[22] - s[35] + s[42]) - 1.5 * m[23]
+    m[21] = s[42] - s[1] - m[22] - m[23] + (m[30] + m[31] + m[32]) / 12.0
+    return m
+
+
+def evolve_source_2(m):
+    """The source terms of eq. (30)."""
+    return [m[1] + 2.0 / 3.0 * m[5]]
+
+
+def evolve_source_3(m):
+    """The source terms of eq. (36), for u_11 .. u_15."""
+    return [m[1] - 0.3 * m[12], 0.5 * m[11] + 0.6 * m[12], m[2] + 2.0 / 3.0 * m[13],
+            m[3] + 2.0 / 3.0 * m[14], m[4] + 2.0 / 3.0 * m[15]]
+
+
+def evolve_source_4(m):
+    """The source terms of eq. (45), for u_21 .. u_35."""
+    return [m[1] + 8.0 / 70.0 * m[23], 0.5 * m[21] - 3.0 / 7.0 * m[23],
+            m[22] / 3.0 + 4.0 / 7.0 * m[23],
+            m[2] - 0.3 * m[27], m[3] - 0.3 * m[28], m[4] - 0.3 * m[29],
+            0.5 * m[24] + 0.6 * m[27], 0.5 * m[25] + 0.6 * m[28], 0.5 * m[26] + 0.6 * m[29],
+            m[5] + 2.0 / 3.0 * m[30], m[6] + 2.0 / 3.0 * m[31], m[7] + 2.0 / 3.0 * m[32],
+            m[8] + 2.0 / 3.0 * m[33], m[9] + 2.0 / 3.0 * m[34], m[10] + 2.0 / 3.0 * m[35]]
+
+
+def source_integral(m, order):
+    """dt times the space-time average of the source: eq. (35), (44), (53)."""
+    if order == 2:
+        return m[1] + 0.5 * m[5]
+    if order == 3:
+        return m[1] + 0.5 * m[11] + m[12] / 3.0
+    return m[1] + 0.5 * m[21] + m[22] / 3.0 + 0.25 * m[23]
+
+
+SOURCE_MODES = {2: source_modes_2, 3: source_modes_3, 4: source_modes_4}
+EVOLVE_SOURCE = {2: evolve_source_2, 3: evolve_source_3, 4: evolve_source_4}
+
+
+def predict_modal_source(what, order, dt, dx, gamma, source_fn, flux_fn=None):
+    """Modal ADER-CG with a non-stiff source S(u) (Sec. IV with the source
+    terms): returns (uhat, dt * S-bar).  Each iteration evaluates the fluxes
+    and the scaled sources dt S at the nodes of the current polynomial; dt
+    S-bar comes from the source modes of the final polynomial (the sources
+    evaluated once more at its nodes, as the flux modes may be rebuilt once
+    the evolutionary modes are final), which keeps it of the design order
+    (with the modes of the last iterate a single iteration at second order
+    would reduce to forward Euler for a pure source)."""
+    ls, L = N_SPATIAL[order], N_SPACETIME[order]
+    uhat = np.zeros((L,) + what.shape[1:])
+    uhat[:ls] = what
+    nodes = NODES_MODAL[order]
+    for _ in range(order - 1):
+        ubar = _one_based([evaluate(uhat, order, x) for x in nodes])
+        if flux_fn is None:
+            fbar, gbar, hbar = _scaled_fluxes(ubar, dt, dx, gamma)
+        else:
+            fbar = _one_based([dt / dx[0] * flux_fn(u, 0) for u in ubar[1:]])
+            gbar = _one_based([dt / dx[1] * flux_fn(u, 1) for u in ubar[1:]])
+            hbar = _one_based([dt / dx[2] * flux_fn(u, 2) for u in ubar[1:]])
+        sb = _one_based([dt * source_fn(u) for u in ubar[1:]])
+        modes = FLUX_MODES[order](fbar, gbar, hbar)
+        sm = SOURCE_MODES[order](sb)
+        evo = EVOLVE[order](modes)
+        src = EVOLVE_SOURCE[order](sm)
+        uhat[ls:] = np.stack([a + b for a, b in zip(evo, src)])
+    ubar = _one_based([evaluate(uhat, order, x) for x in nodes])
+    sm = SOURCE_MODES[order](_one_based([dt * source_fn(u) for u in ubar[1:]]))
+    return uhat, source_integral(sm, order)
+
+
+def gravity_source(g):
+    """S(u) of a uniform gravitational acceleration g = (gx, gy, gz) on the
+    Euler variables: (0, rho g, m . g)."""
+    g = np.asarray(g, dtype=np.float64)
+
+    def source(u):
+        out = np.zeros_like(u)
+        out[1:4] = u[0][None] * g.reshape((3,) + (1,) * (u.ndim - 1))
+        out[4] = u[1] * g[0] + u[2] * g[1] + u[3] * g[2]
+        return out
+    return source
+
+
 def predict_modal(what, order, dt, dx, gamma, flux_fn=None):
     """Modal ADER-CG of Sec. IV.1-IV.3: spatial modes -> all L modes.
 

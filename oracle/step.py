@@ -19,7 +19,8 @@ from .bweno import zone_b_mean, zone_b_modes
 from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
 from .positivity import limit_spatial, limit_spacetime
-from .predictor import predict_modal, predict_nodal_2, predict_nodal_3, predict_nodal_4
+from .predictor import (predict_modal, predict_modal_source, predict_nodal_2, predict_nodal_3,
+                        predict_nodal_4)
 from .riemann import (hll, hll_combine, hll_speeds, linearized_euler, linearized_mhd_combine,
                       mhd_abs_jacobian)
 from .weno import reconstruct
@@ -33,6 +34,7 @@ class OracleConfig:
     gamma: float = 1.4
     lengths: tuple = (1.0, 1.0, 1.0)   # domain (lx, ly, lz)
     zone_size: tuple = None            # (dx, dy, dz); overrides ``lengths``
+    source: object = None              # S(u), a non-stiff source (Euler, modal form)
 
     def spacing(self, shape):
         if self.zone_size is not None:
@@ -188,14 +190,34 @@ def step(U, dt, cfg, B=None):
     """Eq. (6): U^{n+1} = U^n - sum_d dt/dx_d (F_{i+1/2} - F_{i-1/2}).
     With face fields B (MHD) returns (U^{n+1}, B^{n+1}), see step_mhd."""
     if B is not None:
+        if cfg.source is not None:
+            raise NotImplementedError('source terms are built for the Euler equations')
         return step_mhd(U, B, dt, cfg)
     dx = cfg.spacing(U.shape[1:])
-    uhat = predictor(U, dt, cfg)
+    if cfg.source is None:
+        uhat = predictor(U, dt, cfg)
+    else:
+        uhat, dts = predictor_source(U, dt, cfg)
     flows = face_fluxes(uhat, cfg)
     Un = U.copy()
     for d in range(3):
         Un = Un - dt / dx[d] * (_nb(flows[d], d, 1) - flows[d])
+    if cfg.source is not None:
+        Un = Un + dts     # eq. (6): + dt S-bar
     return Un
+
+
+def predictor_source(U, dt, cfg):
+    """The predictor with a source term (modal form, Euler): the space-time
+    polynomial after the positivity safeguard, and dt times the space-time
+    average of the source (eq. 35, 44, 53), taken from the source modes of
+    the last iteration."""
+    if cfg.form != 'modal':
+        raise NotImplementedError('source terms are built for the modal form')
+    dx = cfg.spacing(U.shape[1:])
+    what = limit_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma)
+    uhat, dts = predict_modal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
+    return limit_spacetime(uhat, cfg.order, cfg.form, cfg.gamma), dts
 
 
 def step_block(U, dt, cfg, origin, shape, B=None):
