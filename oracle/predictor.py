@@ -429,6 +429,31 @@ def predict_nodal_2(what, dt, dx, gamma, flux_fn=None):
     return uhat
 
 
+def nodal3_b2_source(s):
+    """The source terms of (B.2), from the scaled sources s_1 .. s_7."""
+    return {
+        11: (-9 * s[1] + 2 * (s[2] + s[3] + s[4] + s[5] + s[6] + s[7])) / 24.0,
+        12: (7 * s[1] - 8 * s[2] - 4 * s[3] + 2 * (s[4] + s[5] + s[6] + s[7])) / 24.0,
+        13: (7 * s[1] + 2 * (s[2] + s[3]) - 8 * s[4] - 4 * s[5] + 2 * (s[6] + s[7])) / 24.0,
+        14: (7 * s[1] + 2 * (s[2] + s[3] + s[4] + s[5]) - 8 * s[6] - 4 * s[7]) / 24.0,
+        15: (-27 * s[1] + 5 * (s[2] + s[3] + s[4] + s[5] + s[6] + s[7])) / 30.0,
+    }
+
+
+def nodal3_b3_source(s):
+    """The source terms of (B.3) at the later nodes, from s_11 .. s_15."""
+    q1 = 0.0
+    q2 = (-4 * s[11] - 3 * s[15]) / 24.0
+    return {11: 0.125 * (4 * s[11] - s[15]) + q1, 12: q2 + 2 * s[12] / 3.0,
+            13: q2 + 2 * s[13] / 3.0, 14: q2 + 2 * s[14] / 3.0,
+            15: 4 * q1 + 0.1 * (8 * s[11] + s[15])}
+
+
+def nodal3_b6(s):
+    """(B.6): dt times the space-time average of the source."""
+    return (-5 * s[1] + s[2] + s[3] + s[4] + s[5] + s[6] + s[7] + 4 * s[11] + s[15]) / 6.0
+
+
 def nodal3_b2(u, f, g, h):
     """(B.2) without source terms: the temporaries q_11 .. q_15 from the
     nodal values u_1 .. u_10 at the tau = 0 nodes and their scaled fluxes
@@ -618,3 +643,112 @@ def predict_nodal_4(what, dt, dx, gamma, flux_fn=None):
     allv[lt] = later
     uhat[ls:] = _apply(C, allv)[ls:]
     return uhat
+
+
+_SOURCE_MAPS = {}
+
+
+def nodal_source_map(order):
+    """The source part of the nodal update of App. A-C: with the source s
+    interpolated on the same nodal basis, the residual u_tau + f_xi + g_eta +
+    h_zeta - s orthogonal to the later nodes' basis functions adds As @ s to
+    the later nodal values (s at every node); and dt times the space-time
+    average of the source is wbar @ s, wbar_j the integral of the j-th basis
+    function over the element (eq. A.7, B.6 and the App. C analogue)."""
+    if order in _SOURCE_MAPS:
+        return _SOURCE_MAPS[order]
+    nodes, t0, lt, Au, Af, Ag, Ah, C = nodal_update_map(order)
+    modes = spacetime_modes(order)
+    g, gw = np.polynomial.legendre.leggauss(5)
+    xs, xw = 0.5 * g, 0.5 * gw
+    ts, tw = 0.5 * (g + 1.0), 0.5 * gw
+    X, Y, Z, T = np.meshgrid(xs, xs, xs, ts, indexing='ij')
+    Wq = np.einsum('i,j,k,l->ijkl', xw, xw, xw, tw).ravel()
+    X, Y, Z, T = X.ravel(), Y.ravel(), Z.ravel(), T.ravel()
+    Phi = np.array([phi(m, X, Y, Z, T) for m in modes])
+    dT = np.array([P(a, X) * P(b, Y) * P(c, Z) * (d * T ** (d - 1) if d > 0 else 0.0 * T)
+                   for (a, b, c, d) in modes])
+    Pq = C.T @ Phi
+    Psi = Pq[lt] * Wq
+    E = Psi @ (C.T @ dT).T
+    M = Psi @ Pq.T
+    As = np.linalg.inv(E[:, lt]) @ M
+    wbar = Pq @ Wq
+    _SOURCE_MAPS[order] = (As, wbar)
+    return As, wbar
+
+
+def predict_nodal_source(what, order, dt, dx, gamma, source_fn):
+    """The nodal ADER-CG of App. A (order 2), B (3) or C (4) with a source
+    S(u): returns (uhat, dt * S-bar).  Orders 2 and 3 take the printed source
+    terms of (A.4) and (B.2)-(B.3); order 4 the source part of the Galerkin
+    map (nodal_source_map).  dt S-bar is (A.7), (B.6) or wbar @ s with the
+    sources of the final nodal values."""
+    fn = lambda u, a: flux(u, a, gamma)  # noqa: E731
+    nodes = NODES_NODAL[order]
+    L = len(nodes)
+    ls = N_SPATIAL[order]
+    uhat = np.zeros((L,) + what.shape[1:])
+    uhat[:ls] = what
+    t0 = [i for i, x in enumerate(nodes) if x[3] == 0]
+    lt = [i for i, x in enumerate(nodes) if x[3] != 0]
+    u = [None] * L
+    for i in t0:
+        u[i] = evaluate(uhat, order, nodes[i])
+    for i in lt:   # start: the spatial polynomial at the later nodes' positions
+        u[i] = evaluate(uhat, order, tuple(nodes[i][:3]) + (0.0,))
+
+    def sc(i, a):
+        return dt / dx[a] * fn(u[i], a)
+
+    def src(i):
+        return dt * source_fn(u[i])
+
+    if order == 2:
+        f1, f2 = sc(0, 0), sc(1, 0)
+        g1, g3 = sc(0, 1), sc(2, 1)
+        h1, h4 = sc(0, 2), sc(3, 2)
+        s1, s5 = src(0), src(4)
+        u[4] = u[0] - 2.0 * (f2 - f1) - 2.0 * (g3 - g1) - 2.0 * (h4 - h1) + s1 / 3.0 + 2.0 * s5 / 3.0
+        uhat[4] = u[4] - u[0]
+        return uhat, 0.5 * (src(0) + src(4))
+    if order == 3:
+        one = lambda vals: [None] + list(vals)  # noqa: E731
+        f = one([sc(i, 0) for i in t0])
+        g = one([sc(i, 1) for i in t0])
+        h = one([sc(i, 2) for i in t0])
+        s0 = one([src(i) for i in t0])
+        q = nodal3_b2(one([u[i] for i in t0]), f, g, h)
+        qs = nodal3_b2_source(s0)
+        q = {k: q[k] + qs[k] for k in q}
+        for _ in range(2):
+            fl = {k: sc(k - 1, 0) for k in (11, 12)}
+            gl = {k: sc(k - 1, 1) for k in (11, 13)}
+            hl = {k: sc(k - 1, 2) for k in (11, 14)}
+            sl = {k: src(k - 1) for k in (11, 12, 13, 14, 15)}
+            later = nodal3_b3(q, fl, gl, hl)
+            ls_ = nodal3_b3_source(sl)
+            for k in later:
+                u[k - 1] = later[k] + ls_[k]
+        uhat[10:] = np.stack(nodal3_b5(one([u[i] for i in t0]), {k: u[k - 1] for k in range(11, 16)}))
+        s_all = one([src(i) for i in range(L)])
+        return uhat, nodal3_b6(s_all)
+    # order 4: the Galerkin map with its source part
+    _, _, _, Au, Af, Ag, Ah, C = nodal_update_map(4)
+    As, wbar = nodal_source_map(4)
+    u0 = np.stack([u[i] for i in t0])
+    fs = [np.stack([sc(i, a) for i in t0]) for a in range(3)]
+    s0 = np.stack([src(i) for i in t0])
+    q = (_apply(Au, u0) + _apply(Af[:, t0], fs[0]) + _apply(Ag[:, t0], fs[1])
+         + _apply(Ah[:, t0], fs[2]) + _apply(As[:, t0], s0))
+    for _ in range(3):
+        fl = [np.stack([sc(i, a) for i in lt]) for a in range(3)]
+        sl = np.stack([src(i) for i in lt])
+        later = (q + _apply(Af[:, lt], fl[0]) + _apply(Ag[:, lt], fl[1]) + _apply(Ah[:, lt], fl[2])
+                 + _apply(As[:, lt], sl))
+        for r, i in enumerate(lt):
+            u[i] = later[r]
+    allv = np.stack(u)
+    uhat[ls:] = _apply(C, allv)[ls:]
+    s_all = np.stack([src(i) for i in range(L)])
+    return uhat, _apply(wbar[None, :], s_all)[0]

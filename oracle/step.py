@@ -20,7 +20,7 @@ from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
 from .positivity import limit_spatial, limit_spacetime
 from .predictor import (predict_modal, predict_modal_source, predict_nodal_2, predict_nodal_3,
-                        predict_nodal_4)
+                        predict_nodal_4, predict_nodal_source)
 from .riemann import (hll, hll_combine, hll_speeds, linearized_euler, linearized_mhd_combine,
                       mhd_abs_jacobian)
 from .weno import reconstruct
@@ -34,7 +34,7 @@ class OracleConfig:
     gamma: float = 1.4
     lengths: tuple = (1.0, 1.0, 1.0)   # domain (lx, ly, lz)
     zone_size: tuple = None            # (dx, dy, dz); overrides ``lengths``
-    source: object = None              # S(u), a non-stiff source (Euler, modal form)
+    source: object = None              # S(u), a non-stiff source (Euler)
 
     def spacing(self, shape):
         if self.zone_size is not None:
@@ -208,15 +208,16 @@ def step(U, dt, cfg, B=None):
 
 
 def predictor_source(U, dt, cfg):
-    """The predictor with a source term (modal form, Euler): the space-time
-    polynomial after the positivity safeguard, and dt times the space-time
-    average of the source (eq. 35, 44, 53), taken from the source modes of
-    the last iteration."""
-    if cfg.form != 'modal':
-        raise NotImplementedError('source terms are built for the modal form')
+    """The predictor with a source term (Euler): the space-time polynomial
+    after the positivity safeguard, and dt times the space-time average of
+    the source (eq. 35, 44, 53; A.7, B.6 in the nodal form), from the
+    sources at the nodes of the final polynomial."""
     dx = cfg.spacing(U.shape[1:])
     what = limit_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma)
-    uhat, dts = predict_modal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
+    if cfg.form == 'nodal':
+        uhat, dts = predict_nodal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
+    else:
+        uhat, dts = predict_modal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
     return limit_spacetime(uhat, cfg.order, cfg.form, cfg.gamma), dts
 
 

@@ -208,7 +208,7 @@ def _read_app_c():
                 continue
             name, d, den, *pairs = line.split()
             coef = {int(k): int(v) for k, v in (p.split(':') for p in pairs)}
-            rows.append((name, 'fgh'.index(d), int(den), coef))
+            rows.append((name, 'fghs'.index(d), int(den), coef))
     return rows
 
 
@@ -217,14 +217,15 @@ def test_nodal_C2_C3_printed_coefficients():
     # paper prints for the temporaries q_21, q_22, q_23 (C.2) and the
     # later-node flux terms of u_21, u_22 (C.3)
     nodes, t0, lt, Au, Af, Ag, Ah, C = pr.nodal_update_map(4)
-    A = (Af, Ag, Ah)
+    As, _ = pr.nodal_source_map(4)
+    A = (Af, Ag, Ah, As)
     rows = _read_app_c()
-    assert len(rows) == 15
+    assert len(rows) == 17
     for name, d, den, coef in rows:
         k = int(name[1:]) - 21          # later node 21 + k
         for node, c in coef.items():
             got = A[d][k, node - 1] * den
-            assert abs(got - c) < 1e-6 * max(1.0, abs(c)), (name, 'fgh'[d], node, got, c)
+            assert abs(got - c) < 1e-6 * max(1.0, abs(c)), (name, 'fghs'[d], node, got, c)
     # the u terms of the temporaries: q_21 = u_1 + ..., q_22 = u_3 + ..., q_23 = u_4 + ...
     for k, j in ((0, 1), (1, 3), (2, 4)):
         ref = np.zeros(len(t0))
@@ -243,6 +244,25 @@ def test_nodal_map_at_third_order_is_B2_B3():
     ref = Au @ np.array(u[1:]) + Af @ np.array(F[1:]) + Ag @ np.array(G[1:]) + Ah @ np.array(H[1:])
     for k in range(11, 16):
         assert abs(got[k] - ref[k - 11]) < 1e-12
+
+
+def test_nodal_source_terms_from_galerkin():
+    # the source part of the same Galerkin construction reproduces the
+    # printed source terms of (A.4), (B.2)-(B.3) and the averages (A.7),
+    # (B.6): the explicit third-order source functions of the oracle against
+    # the map, every source an independent random number
+    As2, w2 = pr.nodal_source_map(2)
+    assert np.allclose(As2[0], [1.0 / 3.0, 0, 0, 0, 2.0 / 3.0], atol=1e-14)
+    assert np.allclose(w2, [0.5, 0, 0, 0, 0.5], atol=1e-14)
+    As3, w3 = pr.nodal_source_map(3)
+    rng = np.random.default_rng(21)
+    s = [None] + list(rng.normal(size=15))
+    q = pr.nodal3_b2_source(s)
+    later = pr.nodal3_b3_source(s)
+    ref = As3 @ np.array(s[1:])
+    for k in range(11, 16):
+        assert abs(q[k] + later[k] - ref[k - 11]) < 1e-13, k
+    assert abs(pr.nodal3_b6(s) - w3 @ np.array(s[1:])) < 1e-13
 
 
 def _linear_flux(adv):

@@ -1,6 +1,6 @@
-"""Pins of the oracle's non-stiff source terms (modal form; Sec. IV source
+"""Pins of the oracle's non-stiff source terms (modal form: Sec. IV source
 modes eq. 34, 43, 52, evolution eq. 30, 36, 45, space-time averages eq. 35,
-44, 53, update eq. 6)."""
+44, 53; nodal form: App. A-C; update eq. 6)."""
 
 import numpy as np
 import pytest
@@ -20,13 +20,17 @@ def _uniform(rho, v, p, shape=(4, 5, 6), gamma=1.4):
     return U
 
 
+FORMS = ["modal", "nodal"]
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_uniform_gravity_is_exact(order):
+def test_uniform_gravity_is_exact(order, form):
     # a uniform state under uniform gravity: v(t) = v + g t, rho and p
     # constant, E gains m.g t + rho |g|^2 t^2 / 2 -- a quadratic in time the
     # scheme reproduces at every order (this pins the tau modes of the
     # sources and the weights of the space-time averages)
-    cfg = OracleConfig(order=order, riemann='hll', source=gravity_source(G))
+    cfg = OracleConfig(order=order, form=form, riemann='hll', source=gravity_source(G))
     rho, v, p = 1.3, np.array([0.2, -0.1, 0.3]), 2.0
     dt = 0.05
     Un = step(_uniform(rho, v, p), dt, cfg)
@@ -35,13 +39,14 @@ def test_uniform_gravity_is_exact(order):
     assert np.abs(Un - ref).max() < 1e-14 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_linear_damping_local_error_order(order):
+def test_linear_damping_local_error_order(order, form):
     # S = -kappa u on a state at rest (uniform fluxes): one step must agree
     # with exp(-kappa dt) to O(dt^(M+1)); a wrong coefficient anywhere in the
     # source modes, the evolution terms or the average lowers the order
     kappa = 1.0
-    cfg = OracleConfig(order=order, riemann='hll', source=lambda u: -kappa * u)
+    cfg = OracleConfig(order=order, form=form, riemann='hll', source=lambda u: -kappa * u)
     errs = []
     for dt in (0.2, 0.1, 0.05):
         U = _uniform(1.0, [0.0, 0.0, 0.0], 1.0, shape=(3, 3, 3))
