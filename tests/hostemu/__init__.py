@@ -42,6 +42,8 @@ def load():
         lib.hostemu_step.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, I, D]
         lib.hostemu_step.restype = I
         lib.hostemu_step_rk.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, D]
+        lib.hostemu_step_rk_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, I, I, I, D]
+        lib.hostemu_step_rk_mhd.restype = I
         lib.hostemu_step_rk.restype = I
         lib.hostemu_dt.argtypes = [DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt.restype = D
@@ -99,6 +101,17 @@ def step_mhd(U, B, dt, order, form="modal", precision="fp64", lengths=(1.0, 1.0,
     load().hostemu_step_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
                             1 if form == "nodal" else 0, 1 if riemann == "linearized" else 0,
                             PRECISION[precision], dt)
+    return Uo, Bo
+
+
+def step_rk_mhd(U, B, dt, order, riemann="hll", precision="fp64", lengths=(1.0, 1.0, 1.0),
+                gamma=5.0 / 3.0):
+    """One SSP-RK step of ideal MHD of the host build of the RK kernels."""
+    Uo = np.ascontiguousarray(U, dtype=np.float64).copy()
+    Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
+    nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
+    load().hostemu_step_rk_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
+                               1 if riemann == "linearized" else 0, PRECISION[precision], dt)
     return Uo, Bo
 
 

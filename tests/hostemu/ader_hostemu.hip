@@ -171,7 +171,79 @@ static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, dou
   for (long long n = 0; n < N; ++n) ct_zone(B, E.data(), g, dt, dx, dy, dz, n);
 }
 
+// One SSP-RK step of ideal MHD from the RK kernels' per-zone functions
+// (stage weights of eq. 18-20 restated as in emu_rk_step).
+template <class T, bool DEV, int RS>
+static void emu_rk_step_mhd(double* U, double* B, Grid g, double dx, double dy, double dz,
+                            double gam, int order, double dt) {
+  constexpr bool ALL = RS == 1;
+  struct Row { double a_n, a_c, c_l, a_2, a_3, c_d; int keep; };
+  static const Row rk2[] = {{0, 1, 1, 0, 0, 0, 0}, {0.5, 0.5, 0.5, 0, 0, 0, 0}};
+  static const Row rk3[] = {{0, 1, 1, 0, 0, 0, 0}, {0.75, 0.25, 0.25, 0, 0, 0, 0},
+                            {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0, 0, 0, 0, 0}};
+  static const Row rk54[] = {
+      {0, 1, 0.39175222700392, 0, 0, 0, 0},
+      {0.44437049406734, 0.55562950593266, 0.36841059262959, 0, 0, 0, 2},
+      {0.62010185138540, 0.37989814861460, 0.25189177424738, 0, 0, 0, 3},
+      {0.17807995410773, 0.82192004589227, 0.54497475021237, 0, 0, 0, 4},
+      {0.00683325884039, 0.34833675773694, 0.22600748319395, 0.51723167208978,
+       0.12759831133288, 0.08460416338212, 0}};
+  const Row* rows = order == 2 ? rk2 : order == 3 ? rk3 : rk54;
+  const int nst = order == 2 ? 2 : order == 3 ? 3 : 5;
+  const long long N = g.N;
+  std::vector<T> W((size_t)19 * 5 * N), WB((size_t)19 * 3 * N), BN((size_t)9 * N),
+      PK((size_t)6 * kMhdSlots * N);
+  std::vector<double> B0((size_t)3 * N), E((size_t)3 * N), F((size_t)15 * N), FE((size_t)12 * N);
+  std::vector<double> Un(U, U + 5 * N), S2(5 * N), S3(5 * N), D3(5 * N);
+  std::vector<double> Bn(B, B + 3 * N), SB2(3 * N), SB3(3 * N), DB3(3 * N);
+  for (int s = 0; s < nst; ++s) {
+    for (long long n = 0; n < N; ++n) {
+      if (order == 2) bface_zone<T, 2>(B, B0.data(), BN.data(), g, n);
+      if (order == 3) bface_zone<T, 3>(B, B0.data(), BN.data(), g, n);
+      if (order == 4) bface_zone<T, 4>(B, B0.data(), BN.data(), g, n);
+    }
+    emu_recon<T>(U, W.data(), g, order, 5);
+    emu_recon<T>(B0.data(), WB.data(), g, order, 3);
+    for (long long n = 0; n < N; ++n) {
+      if (order == 2)
+        predict_zone_mhd<T, 2, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+      else if (order == 3)
+        predict_zone_mhd<T, 3, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+      else
+        predict_zone_mhd<T, 4, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+    }
+    for (long long n = 0; n < N; ++n)
+      face_flux_zone_mhd<T, RS, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
+    for (long long n = 0; n < N; ++n) edge_e_zone(FE.data(), E.data(), g, n);
+    const Row& r = rows[s];
+    const RkStage su{r.a_n, r.a_c, r.c_l, r.a_2, r.a_3, r.c_d, Un.data(), S2.data(), S3.data(),
+                     D3.data(), r.keep == 2 ? S2.data() : r.keep == 3 ? S3.data() : nullptr,
+                     r.keep == 4 ? D3.data() : nullptr};
+    const RkStage sb{r.a_n, r.a_c, r.c_l, r.a_2, r.a_3, r.c_d, Bn.data(), SB2.data(), SB3.data(),
+                     DB3.data(), r.keep == 2 ? SB2.data() : r.keep == 3 ? SB3.data() : nullptr,
+                     r.keep == 4 ? DB3.data() : nullptr};
+    for (long long n = 0; n < N; ++n) rk_stage_zone(U, F.data(), su, g, dt, dx, dy, dz, n);
+    for (long long n = 0; n < N; ++n) rk_stage_field_zone(B, E.data(), sb, g, dt, dx, dy, dz, n);
+  }
+}
+
 extern "C" {
+
+// One SSP-RK step of ideal MHD of the host build, in place on U and B.
+int hostemu_step_rk_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,
+                        double dz, double gam, int order, int riemann, int precision, double dt) {
+  Grid g{nx, ny, nz, (long long)nx * ny * nz, (long long)nx * ny * nz, 0};
+  if (riemann == 0) {
+    if (precision == 0) emu_rk_step_mhd<double, false, 0>(U, B, g, dx, dy, dz, gam, order, dt);
+    else if (precision == 1) emu_rk_step_mhd<float, true, 0>(U, B, g, dx, dy, dz, gam, order, dt);
+    else emu_rk_step_mhd<double, true, 0>(U, B, g, dx, dy, dz, gam, order, dt);
+  } else {
+    if (precision == 0) emu_rk_step_mhd<double, false, 1>(U, B, g, dx, dy, dz, gam, order, dt);
+    else if (precision == 1) emu_rk_step_mhd<float, true, 1>(U, B, g, dx, dy, dz, gam, order, dt);
+    else emu_rk_step_mhd<double, true, 1>(U, B, g, dx, dy, dz, gam, order, dt);
+  }
+  return 0;
+}
 
 // precision: 0 FP64 point form (the FP64 path), 1 FP32 deviation form (the
 // mixed path), 2 FP64 deviation form (checks the deviation algebra alone).

@@ -143,3 +143,25 @@ def test_kernel_source_rk(order, rs, precision, tol):
             err = rel_l1(Ue, ork.step_rk(U, dt, cfg))
             assert np.all(err <= tol), (it, err)
             U = Ue
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp64dev", 1e-12), ("mixed", 1e-6)])
+@pytest.mark.parametrize("rs", ["hll", "linearized"])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_kernel_source_rk_mhd(order, rs, precision, tol):
+    # the MHD RK side packets (the predictor kernel with the predictor
+    # bypassed) and the stage combinations of U and of the face fields,
+    # built for the host, against the oracle's MHD SSP-RK steps
+    from oracle import rk as ork
+    from oracle.bweno import divergence
+    U0, B0 = workloads.mhd_random_field((6, 7, 8), seed=order + 70)
+    cfg = OracleConfig(order=order, gamma=5.0 / 3.0, riemann=rs)
+    U, B = U0, B0
+    for it in range(2):
+        dt = hostemu.compute_dt_mhd(U, B, 0.3)
+        Ue, Be = hostemu.step_rk_mhd(U, B, dt, order, rs, precision=precision)
+        Uo, Bo = ork.step_rk_mhd(U, B, dt, cfg)
+        assert np.all(rel_l1(Ue, Uo) <= tol) and np.all(rel_l1(Be, Bo) <= tol), it
+        dx = cfg.spacing(U.shape[1:])
+        assert np.abs(divergence(Be, dx)).max() <= 1e-12 * np.abs(Be).max() / min(dx)
+        U, B = Ue, Be
