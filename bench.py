@@ -278,6 +278,33 @@ def run_schemes(ader, torch, U0, steps, warmup, Um=None, Bm=None):
     return out
 
 
+def run_density_wave(ader, torch, steps=10):
+    """The 32^3 density wave (rho = 1 + 0.2 sin 2 pi (x + y + z), v = (1, 1, 1),
+    P = 1), second-order nodal predictor with minmod slopes, HLL, FP64, CFL
+    0.4: `steps` graph-replayed steps (after one warm-up)."""
+    from paper_1006_2146_amd import workloads
+    shape = (32, 32, 32)
+    U0 = workloads.density_wave(shape)
+    stream = torch.cuda.Stream()
+    s = ader.Solver(shape, order=2, form=ader.ADER_NODAL, riemann=ader.ADER_HLL,
+                    precision=ader.ADER_FP64, stream=stream.cuda_stream)
+    try:
+        s.set_state(U0)
+        ader.ader_set_graph(s.ctx, True)
+        s.step_cfl(0.4)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step_cfl(0.4)
+        s.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        s.close()
+    return {"workload": "density-wave-32^3, order 2 nodal, minmod, HLL, FP64, CFL 0.4",
+            "steps": steps, "zone_updates_per_s": 32 ** 3 * steps / (t1 - t0),
+            "ms_per_step": 1e3 * (t1 - t0) / steps}
+
+
 def run_host_roundtrip(ader, U0, steps):
     """The same 128^3 mixed HLL run through the host-buffer entry points:
     ader_set_state from host memory, `steps` CFL steps, ader_get_state back
@@ -547,6 +574,9 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % nbytes)
 
+    log("density wave 32^3")
+    small = run_density_wave(ader, torch)
+
     roundtrip = None
     if "mixed-hll" in variants:
         log("host round trip")
@@ -626,6 +656,7 @@ def main():
         "turbulent_mhd": turbulent,
         "ader_vs_ssprk": schemes,
         "host_roundtrip": roundtrip,
+        "density_wave_32": small,
     }
     for prec in ("fp64", "mixed"):
         if prec + "-hll" in variants and prec + "-hll-nodal" in variants:
