@@ -1,5 +1,14 @@
-"""Positivity safeguard for the zone polynomials (a reading: the paper is
-silent on positivity).
+"""Positivity of the zone polynomials: the check of the paper's scheme and
+an optional safeguard (the paper describes no positivity treatment).
+
+Two modes, chosen by ``OracleConfig.positivity``:
+
+* ``'check'`` (the default, the paper's scheme): nothing is changed; the
+  polynomials are evaluated at the check sets below and ``NonPhysical`` is
+  raised if any point has rho <= 0 or P <= 0, since the fluxes and wave
+  speeds there have no meaning.  The step is the paper's step wherever it
+  does not raise.
+* ``'limit'`` (an opt-in added here): the Zhang-Shu scaling described next.
 
 Component-wise WENO of the conserved variables (Sec. II.1, VII) can put
 negative density or pressure at the predictor and facial nodes next to strong
@@ -37,6 +46,12 @@ from .faces import FACE_NODES, zone_point
 from .predictor import NODES_MODAL, NODES_NODAL
 
 EPS_REL = 1.0e-8
+
+MODES = ('check', 'limit')
+
+
+class NonPhysical(ArithmeticError):
+    """A check point of some zone has rho <= 0 or P <= 0 (check mode)."""
 
 
 # 1-based facial nodes with a nonzero weight in the face average
@@ -162,3 +177,62 @@ def limit_spacetime(uhat, order, form, gamma):
     out = uhat.copy()
     out[1:] = out[1:] * theta
     return out
+
+
+def _check(values, gamma, where):
+    """Raise NonPhysical if any of the point states has rho <= 0 or P <= 0
+    (or a non-finite value)."""
+    bad = None
+    for u in values:
+        with np.errstate(divide='ignore', invalid='ignore'):
+            ok = (u[0] > 0.0) & (_pressure_like(u, gamma) > 0.0)
+        b = ~ok
+        bad = b if bad is None else bad | b
+    if bad is not None and bad.any():
+        raise NonPhysical('%s: %d zone(s) with rho <= 0 or P <= 0 at a check point'
+                          % (where, int(bad.sum())))
+
+
+def check_spatial(what, order, form, gamma):
+    """The check mode's test of the spatial polynomial at the spatial check
+    set (before the predictor)."""
+    pts = spatial_check_points(order, form, all_nodes=what.shape[1] == 8)
+    _check([evaluate(_as_spacetime(what, order), order, p) for p in pts], gamma, 'spatial')
+
+
+def check_spacetime(uhat, order, form, gamma):
+    """The check mode's test of the space-time polynomial at the facial
+    check set (after the predictor)."""
+    pts = facial_check_points(order, uhat.shape[1] == 8)
+    _check([evaluate(uhat, order, p) for p in pts], gamma, 'space-time')
+
+
+def safeguard_spatial(what, order, form, gamma, mode):
+    """The spatial polynomial after the positivity handling of ``mode``."""
+    if mode == 'limit':
+        return limit_spatial(what, order, form, gamma)
+    if mode != 'check':
+        raise ValueError('positivity mode %r' % (mode,))
+    check_spatial(what, order, form, gamma)
+    return what
+
+
+def safeguard_spacetime(uhat, order, form, gamma, mode):
+    """The space-time polynomial after the positivity handling of ``mode``."""
+    if mode == 'limit':
+        return limit_spacetime(uhat, order, form, gamma)
+    if mode != 'check':
+        raise ValueError('positivity mode %r' % (mode,))
+    check_spacetime(uhat, order, form, gamma)
+    return uhat
+
+
+def limited_zones(what, uhat, order, form, gamma):
+    """Number of zones the limit mode scales (theta < 1) before and after the
+    predictor, for reporting."""
+    pts = spatial_check_points(order, form, all_nodes=what.shape[1] == 8)
+    th_s = scale_factor(what[0], [evaluate(_as_spacetime(what, order), order, p) for p in pts],
+                        gamma)
+    vals = [evaluate(uhat, order, p) for p in facial_check_points(order, uhat.shape[1] == 8)]
+    th_t = scale_factor(uhat[0], vals, gamma)
+    return int((th_s < 1.0).sum()), int((th_t < 1.0).sum())

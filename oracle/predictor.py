@@ -16,6 +16,8 @@ drops the source terms (S = 0 for every system handled here).
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 """
 
+from fractions import Fraction as F
+
 import numpy as np
 
 from .basis import N_SPATIAL, N_SPACETIME, P, Q, dP, evaluate, phi, spacetime_modes
@@ -364,6 +366,25 @@ def predict_modal_source(what, order, dt, dx, gamma, source_fn, flux_fn=None):
     return uhat, source_integral(sm, order)
 
 
+def source_average(uhat, order, form, dt, source_fn):
+    """dt times the space-time average of the source over a zone whose
+    space-time polynomial is ``uhat``: the sources at the nodes of eq. (31),
+    (37), (46) and the rule eq. (35), (44), (53) in the modal form; in the
+    nodal form the sources at the nodes of (A.1), (B.1), (C.1) and the
+    averages (A.7), (B.6) or the integrals of the nodal basis."""
+    if form == 'modal':
+        ubar = _one_based([evaluate(uhat, order, x) for x in NODES_MODAL[order]])
+        sm = SOURCE_MODES[order](_one_based([dt * source_fn(u) for u in ubar[1:]]))
+        return source_integral(sm, order)
+    s = [dt * source_fn(evaluate(uhat, order, x)) for x in NODES_NODAL[order]]
+    if order == 2:
+        return 0.5 * (s[0] + s[4])
+    if order == 3:
+        return nodal3_b6([None] + s)
+    _, wbar = nodal_source_map(4)
+    return _apply(wbar[None, :], np.stack(s))[0]
+
+
 def gravity_source(g):
     """S(u) of a uniform gravitational acceleration g = (gx, gy, gz) on the
     Euler variables: (0, rho g, m . g)."""
@@ -527,67 +548,152 @@ def nodal3_b5(u, later):
     return [m11, m12, m13, m14, m15]
 
 
-_UPDATE_MAPS = {}
+_EXACT_MAPS = {}
+
+
+# --- exact rational arithmetic on the basis of eq. (9) and (13) -------------
+# A 1D polynomial is a list of Fraction coefficients (constant term first).
+
+_P1D = {0: [F(1)], 1: [F(0), F(1)], 2: [F(-1, 12), F(0), F(1)],
+        3: [F(0), F(-3, 20), F(0), F(1)]}       # eq. (9)
+
+
+def _q1d(d):
+    """Eq. (13): tau^d."""
+    return [F(0)] * d + [F(1)]
+
+
+def _val(p, x):
+    out = F(0)
+    for c in reversed(p):
+        out = out * x + c
+    return out
+
+
+def _der(p):
+    return [k * c for k, c in enumerate(p)][1:] or [F(0)]
+
+
+def _mul(p, q):
+    out = [F(0)] * (len(p) + len(q) - 1)
+    for i, a in enumerate(p):
+        for j, b in enumerate(q):
+            out[i + j] += a * b
+    return out
+
+
+def _int_space(p):
+    """Integral over [-1/2, 1/2]."""
+    return sum(c * (F(1, 2) ** (k + 1) - F(-1, 2) ** (k + 1)) / (k + 1) for k, c in enumerate(p))
+
+
+def _int_time(p):
+    """Integral over [0, 1]."""
+    return sum(c / (k + 1) for k, c in enumerate(p))
+
+
+def _inverse(A):
+    """Exact inverse of a square matrix of Fractions (Gauss-Jordan)."""
+    n = len(A)
+    M = [list(row) + [F(int(i == j)) for j in range(n)] for i, row in enumerate(A)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        inv = 1 / M[c][c]
+        M[c] = [v * inv for v in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [a - f * b for a, b in zip(M[r], M[c])]
+    return [row[n:] for row in M]
+
+
+def _matmul(A, B):
+    Bt = list(zip(*B))
+    return [[sum((a * b for a, b in zip(row, col) if a and b), F(0)) for col in Bt] for row in A]
+
+
+def _transpose(A):
+    return [list(r) for r in zip(*A)]
+
+
+def nodal_maps_exact(order):
+    """The nodal ADER-CG of App. A (order 2), B (3), C (4) in exact rational
+    arithmetic: the solution and the scaled fluxes and sources are
+    interpolated on the Lagrange basis psi_j of the nodes (A.1)/(B.1)/(C.1)
+    (psi_j = sum_m C[m][j] phi_m, C the inverse of the matrix of basis
+    values at the nodes, eq. 9 and 13), and the residual u_tau + f_xi +
+    g_eta + h_zeta - s is orthogonal to the psi of the later (tau > 0)
+    nodes over the space-time element.  That gives the later nodal values
+
+        u_later = Au u_0 + Af f + Ag g + Ah h + As s
+
+    (u_0 the tau = 0 nodal values, f, g, h, s at every node); the tau = 0
+    columns are the temporaries q of (B.2)/(C.2) and the later columns the
+    evolutionary equations (B.3)/(C.3).  wbar_j, the integral of psi_j over
+    the element, weights dt times the space-time average of the source
+    (eq. A.7, B.6, C.6).  Returns a dict of lists of Fractions: nodes, t0,
+    lt, C, Au, Af, Ag, Ah, As, wbar."""
+    if order in _EXACT_MAPS:
+        return _EXACT_MAPS[order]
+    nodes = [tuple(F(c).limit_denominator(12) for c in x) for x in NODES_NODAL[order]]
+    modes = spacetime_modes(order)
+    L = len(modes)
+    basis = [([_P1D[a], _P1D[b], _P1D[c]], _q1d(d)) for (a, b, c, d) in modes]
+    V = [[_val(sp[0], x[0]) * _val(sp[1], x[1]) * _val(sp[2], x[2]) * _val(tq, x[3])
+          for (sp, tq) in basis] for x in nodes]
+    C = _inverse(V)                          # mode m = sum_j C[m][j] u_j
+
+    def gram(deriv):
+        """G[m][n] = integral of phi_m times the `deriv` derivative of phi_n
+        (deriv 0..2 a space axis, 3 time, None none)."""
+        G = [[F(0)] * L for _ in range(L)]
+        for m, (sm, tm) in enumerate(basis):
+            for n, (sn, tn) in enumerate(basis):
+                v = F(1)
+                for ax in range(3):
+                    q = _der(sn[ax]) if deriv == ax else sn[ax]
+                    v *= _int_space(_mul(sm[ax], q))
+                    if v == 0:
+                        break
+                if v != 0:
+                    v *= _int_time(_mul(tm, _der(tn) if deriv == 3 else tn))
+                G[m][n] = v
+        return G
+
+    Ct = _transpose(C)
+    # in the nodal basis: N[i][j] = integral psi_i (d) psi_j
+    nodal = {k: _matmul(_matmul(Ct, gram(k)), C) for k in (0, 1, 2, 3, None)}
+    t0 = [i for i, x in enumerate(nodes) if x[3] == 0]
+    lt = [i for i, x in enumerate(nodes) if x[3] != 0]
+    E = [nodal[3][i] for i in lt]
+    Einv = _inverse([[row[j] for j in lt] for row in E])
+    neg = [[-v for v in row] for row in Einv]
+    Au = _matmul(neg, [[row[j] for j in t0] for row in E])
+    Af, Ag, Ah = (_matmul(neg, [nodal[a][i] for i in lt]) for a in range(3))
+    As = _matmul(Einv, [nodal[None][i] for i in lt])
+    mean = [_int_space(sp[0]) * _int_space(sp[1]) * _int_space(sp[2]) * _int_time(tq)
+            for (sp, tq) in basis]
+    wbar = [sum((C[m][j] * mean[m] for m in range(L)), F(0)) for j in range(L)]
+    out = dict(nodes=nodes, t0=t0, lt=lt, C=C, Au=Au, Af=Af, Ag=Ag, Ah=Ah, As=As, wbar=wbar)
+    _EXACT_MAPS[order] = out
+    return out
+
+
+def _floats(A):
+    return np.array([[float(v) for v in row] for row in A])
 
 
 def nodal_update_map(order):
-    """The nodal update equations of App. B and C in matrix form.
-
-    u and the scaled fluxes f, g, h are interpolated on the nodal basis of
-    the nodes (B.1)/(C.1) (the Lagrange basis of the L space-time modes);
-    the residual u_tau + f_xi + g_eta + h_zeta is required to be orthogonal
-    to the basis functions of the later (tau > 0) nodes over the space-time
-    element, which gives the later nodal values as
-        u_later = Au @ u_0 + Af @ f + Ag @ g + Ah @ h
-    with u_0 the tau = 0 nodal values and f, g, h the fluxes at every node.
-    The tau = 0 columns are the temporaries q of (B.2)/(C.2) and the later
-    columns the evolutionary equations (B.3)/(C.3), whose printed
-    coefficients this reproduces.  Also returned: the node list, the index
-    arrays of the tau = 0 and later nodes, and the inverse Vandermonde
-    matrix C (mode m = sum_j C[m, j] u_j).
-    """
-    if order in _UPDATE_MAPS:
-        return _UPDATE_MAPS[order]
-    nodes = NODES_NODAL[order]
-    modes = spacetime_modes(order)
-    L = len(modes)
-    V = np.array([[float(phi(m, *x)) for m in modes] for x in nodes])
-    C = np.linalg.inv(V)
-    # tensor Gauss-Legendre rule on [-1/2, 1/2]^3 x [0, 1], exact for the
-    # products below (degree <= 7 per axis)
-    g, gw = np.polynomial.legendre.leggauss(5)
-    xs, xw = 0.5 * g, 0.5 * gw
-    ts, tw = 0.5 * (g + 1.0), 0.5 * gw
-    X, Y, Z, T = np.meshgrid(xs, xs, xs, ts, indexing='ij')
-    Wq = np.einsum('i,j,k,l->ijkl', xw, xw, xw, tw).ravel()
-    X, Y, Z, T = X.ravel(), Y.ravel(), Z.ravel(), T.ravel()
-    Phi = np.array([phi(m, X, Y, Z, T) for m in modes])
-    dPhi = []
-    for axis in range(3):
-        rows = []
-        for (a, b, c, d) in modes:
-            e = [a, b, c]
-            fac = [P(e[0], X), P(e[1], Y), P(e[2], Z)]
-            fac[axis] = dP(e[axis], (X, Y, Z)[axis])
-            rows.append(fac[0] * fac[1] * fac[2] * Q(d, T))
-        dPhi.append(np.array(rows))
-    dt_rows = [P(a, X) * P(b, Y) * P(c, Z) * (d * T ** (d - 1) if d > 0 else 0.0 * T)
-               for (a, b, c, d) in modes]
-    dPhi.append(np.array(dt_rows))
-    # nodal basis and its derivatives at the quadrature points
-    Pq = C.T @ Phi
-    dPq = [C.T @ d for d in dPhi]
-    t0 = np.array([i for i, x in enumerate(nodes) if x[3] == 0])
-    lt = np.array([i for i, x in enumerate(nodes) if x[3] != 0])
-    Psi = Pq[lt] * Wq
-    E = Psi @ dPq[3].T
-    D = [Psi @ dPq[a].T for a in range(3)]
-    Einv = np.linalg.inv(E[:, lt])
-    Au = -Einv @ E[:, t0]
-    Af, Ag, Ah = (-Einv @ D[a] for a in range(3))
-    out = (nodes, t0, lt, Au, Af, Ag, Ah, C)
-    _UPDATE_MAPS[order] = out
-    return out
+    """The nodal update equations of App. B and C in matrix form, rounded
+    once from the exact rational maps of nodal_maps_exact:
+        u_later = Au @ u_0 + Af @ f + Ag @ g + Ah @ h.
+    Returns the node list, the index arrays of the tau = 0 and later nodes,
+    Au, Af, Ag, Ah and the inverse Vandermonde matrix C (mode m = sum_j
+    C[m, j] u_j)."""
+    ex = nodal_maps_exact(order)
+    return (NODES_NODAL[order], np.array(ex['t0']), np.array(ex['lt']), _floats(ex['Au']),
+            _floats(ex['Af']), _floats(ex['Ag']), _floats(ex['Ah']), _floats(ex['C']))
 
 
 def _apply(A, x):
@@ -645,37 +751,13 @@ def predict_nodal_4(what, dt, dx, gamma, flux_fn=None):
     return uhat
 
 
-_SOURCE_MAPS = {}
-
-
 def nodal_source_map(order):
-    """The source part of the nodal update of App. A-C: with the source s
-    interpolated on the same nodal basis, the residual u_tau + f_xi + g_eta +
-    h_zeta - s orthogonal to the later nodes' basis functions adds As @ s to
-    the later nodal values (s at every node); and dt times the space-time
-    average of the source is wbar @ s, wbar_j the integral of the j-th basis
-    function over the element (eq. A.7, B.6 and the App. C analogue)."""
-    if order in _SOURCE_MAPS:
-        return _SOURCE_MAPS[order]
-    nodes, t0, lt, Au, Af, Ag, Ah, C = nodal_update_map(order)
-    modes = spacetime_modes(order)
-    g, gw = np.polynomial.legendre.leggauss(5)
-    xs, xw = 0.5 * g, 0.5 * gw
-    ts, tw = 0.5 * (g + 1.0), 0.5 * gw
-    X, Y, Z, T = np.meshgrid(xs, xs, xs, ts, indexing='ij')
-    Wq = np.einsum('i,j,k,l->ijkl', xw, xw, xw, tw).ravel()
-    X, Y, Z, T = X.ravel(), Y.ravel(), Z.ravel(), T.ravel()
-    Phi = np.array([phi(m, X, Y, Z, T) for m in modes])
-    dT = np.array([P(a, X) * P(b, Y) * P(c, Z) * (d * T ** (d - 1) if d > 0 else 0.0 * T)
-                   for (a, b, c, d) in modes])
-    Pq = C.T @ Phi
-    Psi = Pq[lt] * Wq
-    E = Psi @ (C.T @ dT).T
-    M = Psi @ Pq.T
-    As = np.linalg.inv(E[:, lt]) @ M
-    wbar = Pq @ Wq
-    _SOURCE_MAPS[order] = (As, wbar)
-    return As, wbar
+    """The source part of the nodal update of App. A-C (nodal_maps_exact),
+    rounded once: As adds As @ s to the later nodal values (s at every
+    node), and dt times the space-time average of the source is wbar @ s
+    (eq. A.7, B.6, C.6)."""
+    ex = nodal_maps_exact(order)
+    return _floats(ex['As']), np.array([float(v) for v in ex['wbar']])
 
 
 def predict_nodal_source(what, order, dt, dx, gamma, source_fn):

@@ -2,8 +2,8 @@
 operator of the ADER step.
 
 The space-time predictor of Sec. II.2 is bypassed: each stage reconstructs
-the stage state (Sec. II.1, with the positivity safeguard on the spatial
-polynomial), takes the face-side packets of Sec. V / App. D from the spatial
+the stage state (Sec. II.1, with the positivity handling of
+``cfg.positivity`` on the spatial polynomial), takes the face-side packets of Sec. V / App. D from the spatial
 polynomial held constant over the stage (so the App. D face averages become
 face averages at the stage time), solves the Riemann problems (Sec. II.3)
 and forms L(U) = -sum_d (F_{i+1/2} - F_{i-1/2}) / dx_d, the right-hand side
@@ -20,7 +20,7 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 import numpy as np
 
 from .basis import N_SPACETIME, N_SPATIAL
-from .positivity import limit_spatial
+from .positivity import safeguard_spatial
 from .bweno import zone_b_modes
 from .step import _nb, curl_e, face_fluxes, mhd_fluxes
 from .weno import reconstruct
@@ -32,7 +32,7 @@ def spatial_operator(U, cfg):
     """L(U) for the five Euler variables on the periodic mesh."""
     dx = cfg.spacing(U.shape[1:])
     what = reconstruct(U, cfg.order)
-    what = limit_spatial(what, cfg.order, 'modal', cfg.gamma)
+    what = safeguard_spatial(what, cfg.order, 'modal', cfg.gamma, cfg.positivity)
     uhat = np.zeros((N_SPACETIME[cfg.order],) + what.shape[1:])
     uhat[:N_SPATIAL[cfg.order]] = what
     flows = face_fluxes(uhat, cfg)
@@ -49,7 +49,7 @@ def mhd_operator(state, cfg):
     U, B = state
     dx = cfg.spacing(U.shape[1:])
     what = np.concatenate([reconstruct(U, cfg.order), zone_b_modes(B, cfg.order)], axis=1)
-    what = limit_spatial(what, cfg.order, 'modal', cfg.gamma)
+    what = safeguard_spatial(what, cfg.order, 'modal', cfg.gamma, cfg.positivity)
     uhat = np.zeros((N_SPACETIME[cfg.order],) + what.shape[1:])
     uhat[:N_SPATIAL[cfg.order]] = what
     flows, E = mhd_fluxes(uhat, cfg)

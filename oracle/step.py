@@ -18,9 +18,9 @@ import numpy as np
 from .bweno import zone_b_mean, zone_b_modes
 from .faces import face_side_packet, transverse_axes
 from .physics import primitives, fast_speed
-from .positivity import limit_spatial, limit_spacetime
+from .positivity import safeguard_spatial, safeguard_spacetime
 from .predictor import (predict_modal, predict_modal_source, predict_nodal_2, predict_nodal_3,
-                        predict_nodal_4, predict_nodal_source)
+                        predict_nodal_4, predict_nodal_source, source_average)
 from .riemann import (hll, hll_combine, hll_speeds, linearized_euler, linearized_mhd_combine,
                       mhd_abs_jacobian)
 from .weno import reconstruct
@@ -35,6 +35,9 @@ class OracleConfig:
     lengths: tuple = (1.0, 1.0, 1.0)   # domain (lx, ly, lz)
     zone_size: tuple = None            # (dx, dy, dz); overrides ``lengths``
     source: object = None              # S(u), a non-stiff source (Euler)
+    # 'check': the paper's scheme, NonPhysical raised where rho <= 0 or
+    # P <= 0 at a check point; 'limit': the Zhang-Shu scaling (opt-in)
+    positivity: str = 'check'
 
     def spacing(self, shape):
         if self.zone_size is not None:
@@ -69,12 +72,13 @@ def compute_dt(U, cfg, cfl, B=None):
 def predictor(U, dt, cfg, B=None):
     """Spatial reconstruction (for MHD the hydro variables plus the zone
     field of Sec. III) followed by the space-time predictor, each followed by
-    the positivity safeguard."""
+    the positivity handling of ``cfg.positivity`` (the check, or the
+    scaling)."""
     dx = cfg.spacing(U.shape[1:])
     what = reconstruct(U, cfg.order)
     if B is not None:
         what = np.concatenate([what, zone_b_modes(B, cfg.order)], axis=1)
-    what = limit_spatial(what, cfg.order, cfg.form, cfg.gamma)
+    what = safeguard_spatial(what, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
     if cfg.form == 'nodal':
         if cfg.order == 2:
             uhat = predict_nodal_2(what, dt, dx, cfg.gamma)
@@ -84,7 +88,7 @@ def predictor(U, dt, cfg, B=None):
             uhat = predict_nodal_4(what, dt, dx, cfg.gamma)
     else:
         uhat = predict_modal(what, cfg.order, dt, dx, cfg.gamma)
-    return limit_spacetime(uhat, cfg.order, cfg.form, cfg.gamma)
+    return safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
 
 
 def face_fluxes(uhat, cfg):
@@ -209,16 +213,22 @@ def step(U, dt, cfg, B=None):
 
 def predictor_source(U, dt, cfg):
     """The predictor with a source term (Euler): the space-time polynomial
-    after the positivity safeguard, and dt times the space-time average of
+    after the positivity handling, and dt times the space-time average of
     the source (eq. 35, 44, 53; A.7, B.6 in the nodal form), from the
-    sources at the nodes of the final polynomial."""
+    sources at the nodes of the final polynomial -- in the limit mode the
+    scaled one, so the source average and the fluxes see the same
+    polynomial."""
     dx = cfg.spacing(U.shape[1:])
-    what = limit_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma)
+    what = safeguard_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma,
+                             cfg.positivity)
     if cfg.form == 'nodal':
         uhat, dts = predict_nodal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
     else:
         uhat, dts = predict_modal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
-    return limit_spacetime(uhat, cfg.order, cfg.form, cfg.gamma), dts
+    out = safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
+    if cfg.positivity == 'limit':
+        dts = source_average(out, cfg.order, cfg.form, dt, cfg.source)
+    return out, dts
 
 
 def step_block(U, dt, cfg, origin, shape, B=None):
@@ -234,7 +244,8 @@ def step_block(U, dt, cfg, origin, shape, B=None):
     blk = U[:, iz][:, :, iy][:, :, :, ix]
     # the block keeps the zone size of the full mesh
     sub = OracleConfig(order=cfg.order, form=cfg.form, riemann=cfg.riemann,
-                       gamma=cfg.gamma, zone_size=cfg.spacing(U.shape[1:]))
+                       gamma=cfg.gamma, zone_size=cfg.spacing(U.shape[1:]),
+                       source=cfg.source, positivity=cfg.positivity)
     cut = (slice(None), slice(g, g + shape[0]), slice(g, g + shape[1]), slice(g, g + shape[2]))
     with np.errstate(all='ignore'):
         if B is None:

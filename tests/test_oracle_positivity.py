@@ -1,4 +1,5 @@
-"""Pins of the positivity safeguard (a reading; see oracle/positivity.py)."""
+"""Pins of the positivity handling: the check of the paper's scheme (the
+default) and the opt-in scaling safeguard (see oracle/positivity.py)."""
 
 import numpy as np
 import pytest
@@ -68,3 +69,47 @@ def test_limiter_restores_positivity_tightly(order):
             tight = min(rho.min() / eps_r, p.min() / eps_p)
             assert abs(tight - 1.0) < 1e-3
     assert hits > 5
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_check_mode_reports_exactly_nonpositive_points(order):
+    # the check raises where some check point has rho <= 0 or P <= 0 and
+    # returns the polynomial unchanged (the same object) otherwise
+    rng = np.random.default_rng(20 + order)
+    w = _zone_poly(order, rng, 0.01)
+    assert positivity.safeguard_spatial(w, order, 'modal', 1.4, 'check') is w
+    w[:, 1:4] = 0.0     # at rest, so only rho decides
+    vals = _check_values(w, order, 'modal')
+    # move the zone average so that the lowest check point has rho slightly
+    # below / above zero
+    r_min = min(v[0, 0] for v in vals)
+    for shift, raises in ((r_min + 1e-9, True), (r_min - 1e-9, False)):
+        v = w.copy()
+        v[0, 0, 0] -= shift
+        if raises:
+            with pytest.raises(positivity.NonPhysical):
+                positivity.check_spatial(v, order, 'modal', 1.4)
+        else:
+            positivity.check_spatial(v, order, 'modal', 1.4)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_check_mode_pressure(order):
+    # lowering the total energy until the pressure at the worst check point
+    # crosses zero flips the check
+    rng = np.random.default_rng(40 + order)
+    w = _zone_poly(order, rng, 0.01)
+    vals = _check_values(w, order, 'modal')
+    pmin = min(float(primitives(v, 1.4)[2][0]) for v in vals)
+    v = w.copy()
+    v[0, 4, 0] -= pmin / 0.4 * 0.999
+    positivity.check_spatial(v, order, 'modal', 1.4)
+    v[0, 4, 0] -= pmin / 0.4 * 0.002
+    with pytest.raises(positivity.NonPhysical):
+        positivity.check_spatial(v, order, 'modal', 1.4)
+
+
+def test_unknown_mode_rejected():
+    w = _zone_poly(3, np.random.default_rng(0), 0.01)
+    with pytest.raises(ValueError):
+        positivity.safeguard_spatial(w, 3, 'modal', 1.4, 'clip')

@@ -200,37 +200,126 @@ def test_nodal_B5_recovers_the_modes():
     assert np.allclose(got, uhat[10:], rtol=0, atol=1e-13)
 
 
+def _golden(name):
+    with open(os.path.join(os.path.dirname(__file__), 'golden', name)) as fh:
+        return [line.split() for line in fh if line.strip() and not line.startswith('#')]
+
+
 def _read_app_c():
     rows = []
-    with open(os.path.join(os.path.dirname(__file__), 'golden', 'app_c_nodal4.txt')) as fh:
-        for line in fh:
-            if line.startswith('#') or not line.strip():
-                continue
-            name, d, den, *pairs = line.split()
-            coef = {int(k): int(v) for k, v in (p.split(':') for p in pairs)}
-            rows.append((name, 'fghs'.index(d), int(den), coef))
+    for name, d, den, *pairs in _golden('app_c_nodal4.txt'):
+        coef = {int(k): int(v) for k, v in (p.split(':') for p in pairs)}
+        rows.append((name, d, int(den), coef))
     return rows
 
 
 def test_nodal_C2_C3_printed_coefficients():
-    # the Galerkin map behind App. C must reproduce the coefficients the
-    # paper prints for the temporaries q_21, q_22, q_23 (C.2) and the
-    # later-node flux terms of u_21, u_22 (C.3)
-    nodes, t0, lt, Au, Af, Ag, Ah, C = pr.nodal_update_map(4)
-    As, _ = pr.nodal_source_map(4)
-    A = (Af, Ag, Ah, As)
+    # every coefficient the paper prints in (C.2) (temporaries q21 .. q35)
+    # and (C.3) (evolutionary equations u21 .. u35) -- f, g, h, s and the
+    # starting nodal value, unprinted ones being zero -- equals the exact
+    # rational Galerkin map over the nodes (C.1)
+    from fractions import Fraction
+    ex = pr.nodal_maps_exact(4)
+    A = {'f': ex['Af'], 'g': ex['Ag'], 'h': ex['Ah'], 's': ex['As']}
+    t0, lt = ex['t0'], ex['lt']
     rows = _read_app_c()
-    assert len(rows) == 17
+    assert len(rows) == 135
+    covered = set()
     for name, d, den, coef in rows:
         k = int(name[1:]) - 21          # later node 21 + k
-        for node, c in coef.items():
-            got = A[d][k, node - 1] * den
-            assert abs(got - c) < 1e-6 * max(1.0, abs(c)), (name, 'fghs'[d], node, got, c)
-    # the u terms of the temporaries: q_21 = u_1 + ..., q_22 = u_3 + ..., q_23 = u_4 + ...
-    for k, j in ((0, 1), (1, 3), (2, 4)):
-        ref = np.zeros(len(t0))
-        ref[j - 1] = 1.0
-        assert np.allclose(Au[k], ref, rtol=0, atol=1e-12)
+        assert set(coef) <= {j + 1 for j in (t0 if name[0] == 'q' else lt)}, name
+        if d == 'u':
+            for jj, j in enumerate(t0):
+                assert ex['Au'][k][jj] == Fraction(coef.get(j + 1, 0), den), (name, j + 1)
+            covered.add((name, d))
+            continue
+        for j in (t0 if name[0] == 'q' else lt):
+            assert A[d][k][j] == Fraction(coef.get(j + 1, 0), den), (name, d, j + 1)
+        covered.add((name, d))
+    # every row of every map is printed: q (tau = 0 columns) and u (later
+    # columns) for each direction and the source, and the u start of each q
+    for k in range(21, 36):
+        for d in 'fghs':
+            assert ('q%d' % k, d) in covered and ('u%d' % k, d) in covered
+        assert ('q%d' % k, 'u') in covered
+
+
+def test_nodal_C5_printed_modes_from_nodes():
+    # (C.5), the modes 21-35 from the nodal values, against the exact
+    # inverse of the nodal evaluation; the only difference is the misprint
+    # in the u35 line (u_24 printed for u_26)
+    from fractions import Fraction
+    C = pr.nodal_maps_exact(4)['C']
+    diffs = []
+    for name, fac, *pairs in _golden('app_c_c5.txt'):
+        m = int(name[1:]) - 1
+        coef = {int(k): int(v) for k, v in (p.split(':') for p in pairs)}
+        for j in range(35):
+            want = Fraction(fac) * coef.get(j + 1, 0)
+            if C[m][j] != want:
+                diffs.append((m + 1, j + 1, C[m][j], want))
+    assert diffs == [(35, 24, 0, -12), (35, 26, -12, 0)], diffs
+
+
+def test_nodal_C4_printed_nodes_from_modes():
+    # (C.4), the twenty tau = 0 nodal values from the spatial modes through
+    # the temporaries q1-q3 as printed, equals direct evaluation of the
+    # spatial polynomial (eq. 9, 12) at the nodes (C.1), for every mode
+    from fractions import Fraction as F
+    h = F(1, 2)
+
+    def c4(w):
+        w = [None] + w
+        q1 = F(1, 4) * w[2] - F(1, 8) * (w[8] + w[10]) \
+            + (-21 * w[11] + 40 * w[16] + 40 * w[18] + 60 * w[20]) / 960
+        q2 = F(1, 4) * w[3] - F(1, 8) * (w[8] + w[9]) \
+            + (-21 * w[12] + 40 * w[14] + 40 * w[19] + 60 * w[20]) / 960
+        q3 = F(1, 4) * w[4] - F(1, 8) * (w[9] + w[10]) \
+            + (-21 * w[13] + 40 * w[15] + 40 * w[17] + 60 * w[20]) / 960
+        u = {1: w[1] - (w[5] + w[6] + w[7]) / 12}
+        u[3] = u[1] + h * w[2] + F(1, 4) * w[5] + F(1, 20) * w[11] - (w[16] + w[18]) / 24
+        u[4] = 2 * u[1] - u[3] + h * w[5]
+        u[5] = u[1] + h * w[3] + F(1, 4) * w[6] + F(1, 20) * w[12] - (w[14] + w[19]) / 24
+        u[6] = 2 * u[1] - u[5] + h * w[6]
+        u[7] = u[1] + h * w[4] + F(1, 4) * w[7] + F(1, 20) * w[13] - (w[15] + w[17]) / 24
+        u[8] = 2 * u[1] - u[7] + h * w[7]
+        u[9] = u[5] + u[7] - u[1] + F(1, 4) * w[9] + F(1, 8) * (w[17] + w[19])
+        u[11] = u[3] + u[7] - u[1] + F(1, 4) * w[10] + F(1, 8) * (w[15] + w[18])
+        u[13] = u[3] + u[5] - u[1] + F(1, 4) * w[8] + F(1, 8) * (w[14] + w[16])
+        u[10] = 2 * u[7] - u[11] + h * w[5] + F(1, 4) * w[15]
+        u[12] = 2 * u[3] - u[13] + h * w[6] + F(1, 4) * w[16]
+        u[14] = 2 * u[5] - u[9] + h * w[7] + F(1, 4) * w[19]
+        u[2] = u[11] + u[9] - u[7] + F(1, 4) * w[8] + F(1, 8) * (w[14] + w[16] + w[20])
+        u[15] = 2 * u[8] - u[14] - q1 + F(1, 16) * w[5] + h * w[6] \
+            - F(1, 32) * (w[14] + w[15]) - F(1, 4) * w[17]
+        u[17] = 2 * u[4] - u[10] - q2 + F(1, 16) * w[6] + h * w[7] \
+            - F(1, 32) * (w[16] + w[17]) - F(1, 4) * w[18]
+        u[19] = 2 * u[6] - u[12] - q3 + h * w[5] + F(1, 16) * w[7] - F(1, 4) * w[14] \
+            - F(1, 32) * (w[18] + w[19])
+        u[16], u[18], u[20] = u[15] + 2 * q1, u[17] + 2 * q2, u[19] + 2 * q3
+        return u
+
+    def p1(a, x):      # eq. (9) in exact arithmetic
+        return [F(1), x, x * x - F(1, 12), x ** 3 - F(3, 20) * x][a]
+
+    nodes = [tuple(F(c).limit_denominator(12) for c in x) for x in pr.NODES_NODAL_4[:20]]
+    for unit in range(20):
+        w = [F(0)] * 20
+        w[unit] = F(1)
+        u = c4(w)
+        a, b, c = basis.SPATIAL_MODES[unit]
+        for j, x in enumerate(nodes):
+            assert u[j + 1] == p1(a, x[0]) * p1(b, x[1]) * p1(c, x[2]), (unit + 1, j + 1)
+
+
+def test_nodal_C6_printed_source_average():
+    # (C.6): dt S-bar = (15 s1 - 2 (s3 .. s8) - 27 s21 + 6 (s22 .. s27)
+    # + 9 s31 + 3 s35) / 24, the integrals of the nodal basis functions
+    from fractions import Fraction
+    w = pr.nodal_maps_exact(4)['wbar']
+    printed = {1: 15, 3: -2, 4: -2, 5: -2, 6: -2, 7: -2, 8: -2, 21: -27, 22: 6, 23: 6, 24: 6,
+               25: 6, 26: 6, 27: 6, 31: 9, 35: 3}
+    assert w == [Fraction(printed.get(j, 0), 24) for j in range(1, 36)]
 
 
 def test_nodal_map_at_third_order_is_B2_B3():
@@ -296,6 +385,4 @@ def test_predictor_exact_for_linear_advection(order, form):
         tau = p[3] + 0.5
         got = indep.st_value(uhat[:, 0], order, (p[0], p[1], p[2], tau))
         ref = _spatial_value(what[:, 0], order, p[:3] - c * tau)
-        # the fourth-order nodal map is formed in floating point (inverses of
-        # the 35-node Vandermonde and Galerkin matrices), hence the looser bound
-        assert abs(got - ref) < (1e-12 if (order, form) == (4, 'nodal') else 1e-13)
+        assert abs(got - ref) < 1e-13
