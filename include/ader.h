@@ -99,6 +99,32 @@ enum { ADER_SCHEME_ADER = 0, ADER_SCHEME_SSPRK = 1 };
 int ader_set_scheme(ader_ctx* ctx, int scheme);
 int ader_get_scheme(ader_ctx* ctx, int* scheme_out);
 
+/* Positivity.  The paper describes no positivity treatment, so the default,
+ * ADER_POSITIVITY_CHECK, runs its scheme unchanged and only checks: where a
+ * zone's spatial polynomial (before the predictor, at the spatial positions
+ * of the predictor nodes of eq. 31/37/46 or A.1/B.1/C.1 and of the facial
+ * nodes of App. D) or its space-time polynomial (after the predictor, at the
+ * facial nodes of App. D that the step evaluates and the six face
+ * barycentres of eq. 54) has rho <= 0 or P <= 0, the problem is flagged and
+ * the next call that reports status (ader_synchronize, ader_compute_dt with
+ * dt_out, ader_batch_step_cfl with dts_out) returns ADER_ESTATE; the step's
+ * result is then meaningless.  ADER_POSITIVITY_LIMIT is an opt-in safeguard
+ * that is not part of the paper's method: the scaling limiter of Zhang and
+ * Shu (J. Comput. Phys. 229, 2010) multiplies every non-constant mode of a
+ * zone polynomial by the largest theta in [0, 1] keeping rho and P at least
+ * 1e-8 of their zone-average values at the same points (zone averages
+ * untouched, so still conservative); where theta would be 1 the result is
+ * bit-identical to the check mode.  The same applies to SSP-RK stages
+ * (spatial polynomial only).  ADER_EINVAL for another mode. */
+enum { ADER_POSITIVITY_CHECK = 0, ADER_POSITIVITY_LIMIT = 1 };
+int ader_set_positivity(ader_ctx* ctx, int mode);
+int ader_get_positivity(ader_ctx* ctx, int* mode_out);
+
+/* Per problem (counts_out: n values), the number of zone polynomials the
+ * limit mode has scaled (spatial and space-time counted apart) since the
+ * previous call; the counters restart at zero (synchronises). */
+int ader_limited_zones(ader_ctx* ctx, long long* counts_out);
+
 /* ADER_HLL (eq. 17/56, Davis speeds from the barycentre states) or
  * ADER_LINEARIZED (Sec. II.3: (F_L + F_R)/2 - R|Lambda|L (u_R - u_L)/2 with
  * the eigen-system frozen at the mean of the two barycentre primitive
@@ -166,6 +192,23 @@ int ader_stage_times(ader_ctx* ctx, double* ms_out, int* counts_out);
  * the work arrays allocated so far). */
 int ader_device_bytes(ader_ctx* ctx, double* bytes_out);
 
+/* Conserved totals and the face field's divergence, per problem (n values
+ * for a batch, 1 otherwise), computed on the device from the current state
+ * (synchronises).  totals (n x 8 doubles, may be NULL): for each problem the
+ * integrals over its box of the five conserved variables (rho, rho v, E:
+ * the sum of the zone averages times the zone volume) and, for MHD, of the
+ * three face-field components (the sum of each component's face values
+ * times the zone volume; 0 for Euler).  max_abs_divB (n doubles, may be
+ * NULL): the largest |sum_d (B_d(upper face) - B_d(lower face)) / dx_d| over
+ * the zones (0 for Euler).  On a periodic mesh eq. (6) changes the totals
+ * only by face fluxes that cancel, so they stay constant to round-off, and
+ * the constrained transport of eq. (8) keeps the divergence at its initial
+ * round-off level.  The sums are reduced in a fixed order (tiles of 8192
+ * zones, fixed trees, no atomics): the same state gives the same bits for
+ * any launch.  The first call allocates 72 bytes per 8192 zones of scratch
+ * (ADER_ENOMEM if that fails); ADER_ESEQ before a state is set. */
+int ader_diagnostics(ader_ctx* ctx, double* totals, double* max_abs_divB);
+
 /* Static description of an error code. */
 const char* ader_strerror(int code);
 
@@ -232,12 +275,13 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * quadrature (orders 2 and 3 only), ADER_LAYOUT_ZONE_2W, one lane per zone
  * compiled to fit two waves per SIMD (Euler, orders 2 and 3 only),
  * ADER_LAYOUT_PAIR, two lanes per zone each holding four of the eight MHD
- * variables and exchanging them for each flux (MHD, orders 3 and 4 only),
- * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD,
+ * variables and exchanging them for each flux (MHD, order 3 only),
+ * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD (order 3),
  * ADER_LAYOUT_PAIR_SPLIT, the pair layout in two kernels (the predictor,
  * then the side packets; the evolutionary modes pass through device memory,
- * allocated on first use), or -1 for the default of the setting
- * (pair for MHD at orders 3-4, split for Euler at order 4).  Results do not
+ * allocated on first use; MHD, orders 3 and 4), or -1 for the default of
+ * the setting (pair for MHD at order 3, the two-kernel pair at order 4,
+ * split for Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,
@@ -258,19 +302,6 @@ enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1, ADER_RECON_COLUMNS = 2 };
 int ader_set_recon(ader_ctx* ctx, int mode);
 int ader_get_recon(ader_ctx* ctx, int* mode_out);
 
-/* Measurement support, not part of a step: the peak rates this library's
- * code reaches on `device`, the denominators of its kernels' rooflines.
- * ADER_PROBE_FP32_FMA and ADER_PROBE_FP64_FMA time independent FMA chains
- * (8 per thread, 32 waves per compute unit; FP32 as this library compiles
- * it, without packed FP32 instructions) and return TFLOP/s;
- * ADER_PROBE_HBM_COPY times a 1 GiB device-to-device copy kernel and
- * returns GB/s (bytes read plus bytes written).  Each takes the best of
- * several launches on a stream of its own and synchronises; the copy
- * allocates 2 GiB for its duration (ADER_ENOMEM if it cannot).
- * ADER_EINVAL for an unknown kind, a device out of range or a null
- * value_out. */
-enum { ADER_PROBE_FP32_FMA = 0, ADER_PROBE_FP64_FMA = 1, ADER_PROBE_HBM_COPY = 2 };
-int ader_probe_peak(int device, int kind, double* value_out);
 
 #ifdef __cplusplus
 }

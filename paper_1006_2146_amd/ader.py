@@ -33,9 +33,11 @@ EXPORTS = [
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
-    "ader_probe_peak", "ader_set_scheme", "ader_get_scheme",
+    "ader_set_scheme", "ader_get_scheme",
+    "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
+ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
 ADER_PROBE_FP32_FMA, ADER_PROBE_FP64_FMA, ADER_PROBE_HBM_COPY = 0, 1, 2
 ADER_RECON_SWEEPS, ADER_RECON_TILED, ADER_RECON_COLUMNS = 0, 1, 2
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
@@ -104,9 +106,12 @@ def load():
         "ader_get_layout": ([P, ctypes.POINTER(I)], I),
         "ader_set_recon": ([P, I], I),
         "ader_get_recon": ([P, ctypes.POINTER(I)], I),
-        "ader_probe_peak": ([I, I, DP], I),
         "ader_set_scheme": ([P, I], I),
         "ader_get_scheme": ([P, ctypes.POINTER(I)], I),
+        "ader_set_positivity": ([P, I], I),
+        "ader_get_positivity": ([P, ctypes.POINTER(I)], I),
+        "ader_limited_zones": ([P, ctypes.POINTER(ctypes.c_longlong)], I),
+        "ader_diagnostics": ([P, DP, DP], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -234,11 +239,55 @@ def ader_get_scheme(ctx):
     return v.value
 
 
+def ader_set_positivity(ctx, mode):
+    _check(load().ader_set_positivity(ctx, mode), "ader_set_positivity")
+
+
+def ader_get_positivity(ctx):
+    v = ctypes.c_int()
+    _check(load().ader_get_positivity(ctx, ctypes.byref(v)), "ader_get_positivity")
+    return v.value
+
+
+def ader_limited_zones(ctx, n=1):
+    """Per problem, the zone polynomials the limit mode scaled since the
+    previous call (a list of n counts)."""
+    out = (ctypes.c_longlong * n)()
+    _check(load().ader_limited_zones(ctx, out), "ader_limited_zones")
+    return list(out)
+
+
+def ader_diagnostics(ctx, n=1):
+    """(totals[n][8], max_abs_divB[n]) of the current state."""
+    tot = np.empty((n, 8), dtype=np.float64)
+    div = np.empty(n, dtype=np.float64)
+    _check(load().ader_diagnostics(ctx, _dptr(tot), _dptr(div)), "ader_diagnostics")
+    return tot, div
+
+
+_probe = None
+
+
+def load_probe():
+    """The measurement library (include/ader_probe.h), apart from the step
+    library's ABI."""
+    global _probe
+    if _probe is None:
+        path = os.path.join(_HERE, "libader_probe.so")
+        if not os.path.exists(path):
+            raise FileNotFoundError("libader_probe.so is not built")
+        _probe = ctypes.CDLL(path)
+        _probe.ader_probe_peak.argtypes = [ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.c_double)]
+        _probe.ader_probe_peak.restype = ctypes.c_int
+    return _probe
+
+
 def ader_probe_peak(kind, device=0):
     """Measured peak of `kind` (ADER_PROBE_*): TFLOP/s for the FMA probes,
     GB/s (read + write) for the HBM copy."""
     v = ctypes.c_double()
-    _check(load().ader_probe_peak(device, kind, ctypes.byref(v)), "ader_probe_peak")
+    _check(load_probe().ader_probe_peak(device, kind, ctypes.byref(v)), "ader_probe_peak")
     return v.value
 
 
@@ -335,11 +384,12 @@ def ader_set_launch(ctx, shapes):
     _check(load().ader_set_launch(ctx, b, g), "ader_set_launch")
 
 
-def _configure(ctx, gamma, order, form, riemann, precision):
+def _configure(ctx, gamma, order, form, riemann, precision, positivity):
     ader_set_gamma(ctx, gamma)
     ader_set_order(ctx, order, form)
     ader_set_riemann(ctx, riemann)
     ader_set_precision(ctx, precision)
+    ader_set_positivity(ctx, positivity)
 
 
 class BatchSolver:
@@ -349,7 +399,7 @@ class BatchSolver:
 
     def __init__(self, shapes, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3, form=ADER_MODAL,
                  riemann=ADER_HLL, precision=ADER_FP64, device=0, stream=None,
-                 system=ADER_EULER):
+                 system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK):
         if lengths and not isinstance(lengths[0], (tuple, list)):
             lengths = [lengths] * len(shapes)
         self.shapes = [tuple(s) for s in shapes]
@@ -357,7 +407,7 @@ class BatchSolver:
         meshes = [(s[2], s[1], s[0]) + tuple(L) for s, L in zip(self.shapes, lengths)]
         self.ctx = ader_batch_create(meshes, system=system, device=device, stream=stream)
         try:
-            _configure(self.ctx, gamma, order, form, riemann, precision)
+            _configure(self.ctx, gamma, order, form, riemann, precision, positivity)
         except Exception:
             self.close()
             raise
@@ -379,6 +429,12 @@ class BatchSolver:
 
     def dts(self):
         return ader_get_dt(self.ctx, len(self))
+
+    def limited_zones(self):
+        return ader_limited_zones(self.ctx, len(self))
+
+    def diagnostics(self):
+        return ader_diagnostics(self.ctx, len(self))
 
     def synchronize(self):
         ader_synchronize(self.ctx)
@@ -406,13 +462,13 @@ class Solver:
 
     def __init__(self, shape, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3,
                  form=ADER_MODAL, riemann=ADER_HLL, precision=ADER_FP64,
-                 device=0, stream=None, system=ADER_EULER):
+                 device=0, stream=None, system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK):
         nz, ny, nx = shape
         self.shape = (5, nz, ny, nx)
         self.mhd = system == ADER_MHD
         self.ctx = ader_create(nx, ny, nz, *lengths, system=system, device=device, stream=stream)
         try:
-            _configure(self.ctx, gamma, order, form, riemann, precision)
+            _configure(self.ctx, gamma, order, form, riemann, precision, positivity)
         except Exception:
             self.close()
             raise
@@ -435,6 +491,14 @@ class Solver:
 
     def dt(self):
         return ader_get_dt(self.ctx)
+
+    def limited_zones(self):
+        return ader_limited_zones(self.ctx)[0]
+
+    def diagnostics(self):
+        """(totals[8], max |div B|) of the current state."""
+        tot, div = ader_diagnostics(self.ctx, 1)
+        return tot[0], div[0]
 
     def synchronize(self):
         ader_synchronize(self.ctx)

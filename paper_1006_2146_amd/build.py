@@ -15,6 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libader_hip.so")
+PROBE_LIB = os.path.join(HERE, "libader_probe.so")
 OBJ = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
@@ -64,6 +65,7 @@ def _compile(src, obj, defines, verbose):
 def build(verbose=False):
     os.makedirs(OBJ, exist_ok=True)
     jobs = [(os.path.join(CSRC, "ader_lib.hip"), os.path.join(OBJ, "ader_lib.o"), []),
+            (os.path.join(CSRC, "diagnostics.hip"), os.path.join(OBJ, "diagnostics.o"), []),
             (os.path.join(CSRC, "peak_probe.hip"), os.path.join(OBJ, "peak_probe.o"), [])]
     for sys_, prec, order, form in VARIANTS:
         obj = os.path.join(OBJ, "stages_%s_%s_o%d_f%d.o" % (sys_, prec, order, form))
@@ -72,15 +74,18 @@ def build(verbose=False):
                       ("ADER_FORM", form)]))
     with cf.ThreadPoolExecutor(max_workers=_jobs()) as ex:
         objs = list(ex.map(lambda j: _compile(j[0], j[1], j[2], verbose), jobs))
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("linking libader_hip.so failed")
-    os.replace(tmp, LIB)
+    probe_obj = objs.pop(2)
+    # the step library, and the measurement probes in a library of their own
+    for lib, parts in ((LIB, objs), (PROBE_LIB, [probe_obj])):
+        tmp = lib + ".tmp"
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + parts
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("linking %s failed" % os.path.basename(lib))
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -37,6 +37,11 @@ struct LaunchShape {
 enum { kClassDt = 0, kClassRecon = 1, kClassPredict = 2, kClassFlux = 3, kClassUpdate = 4,
        kNumClasses = 5 };
 
+// Diagnostics: zones per reduction tile, and values per partial row (five
+// hydro sums, three face-field sums, the largest |div B|).
+constexpr long long kDiagTile = 8192;
+constexpr int kDiagVals = 9;
+
 }  // namespace ader
 
 struct ader_ctx;
@@ -58,6 +63,8 @@ struct StageFns {
   int (*rk_sides)(ader_ctx*);         // SSP-RK stage: side packets (Euler, modal tables)
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
+  int (*predict_src)(ader_ctx*);   // Euler with the affine source (one lane per zone)
+  int (*update_src)(ader_ctx*);    // eq. (6) with the source term
 };
 
 }  // namespace ader
@@ -97,7 +104,7 @@ struct ader_ctx {
   bool have_dt = false;
   size_t bytes = 0;          // device bytes held: fixed part plus work arrays
   size_t fixed_bytes = 0;
-  size_t work_bytes[7] = {0, 0, 0, 0, 0, 0, 0};   // W, PK, WB, BN, RK, EM, TH as allocated
+  size_t work_bytes[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // W, PK, WB, BN, RK, EM, TH, SB as allocated
   // MHD pair layout in two kernels: evolutionary modes [NE][8][S] in the
   // bulk type and the two positivity scaling factors [2][S]
   void* EM = nullptr;
@@ -127,7 +134,25 @@ struct ader_ctx {
   double graph_cfl = 0.0;
   unsigned long long graph_key = 0;
 
+  // positivity (ADER_POSITIVITY_*): the check of the paper's scheme or the
+  // scaling; per problem the count of scaled zone polynomials
+  int positivity = ADER_POSITIVITY_CHECK;
+  unsigned int* d_limited = nullptr;
+  // affine source term (Euler): S(u) = A u + b, and dt S-bar per zone [5][S]
+  bool has_source = false;
+  ader::SourceAffine source{};
+  double* SB = nullptr;
+  // diagnostics: problem p's reduction tiles at diag_base[p] ..
+  // diag_base[p+1]-1, and the partial rows and results (allocated on first
+  // use)
+  long long* d_diag_base = nullptr;
+  long long ndiag_tiles = 0;
+  double* d_diag = nullptr;
+
   ader::Batch batch() const { return ader::Batch{d_probs, (int)probs.size(), S}; }
+  ader::PosCtl pos() const {
+    return ader::PosCtl{positivity == ADER_POSITIVITY_LIMIT ? 1 : 0, d_bad, d_limited};
+  }
   int np() const { return (int)probs.size(); }
 };
 

@@ -117,10 +117,24 @@ template <class T, int ORDER, int FORM, bool FUSED, int WAVES = 1>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict(const double* __restrict__ U,
                                                  const T* __restrict__ W, T* __restrict__ PK,
                                                  Batch b, const double* __restrict__ dt,
-                                                 double gam) {
+                                                 double gam, PosCtl pc) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
-                                                       1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+                                                       1.0 / pr.dy, 1.0 / pr.dz, gam, pc.at(p), n);
+  });
+}
+
+// the one-lane-per-zone predictor with the affine source term; dt S-bar to SB
+template <class T, int ORDER, int FORM>
+__global__ void __launch_bounds__(256) k_predict_src(const double* __restrict__ U,
+                                                     const T* __restrict__ W, T* __restrict__ PK,
+                                                     Batch b, const double* __restrict__ dt,
+                                                     double gam, PosCtl pc, SourceAffine src,
+                                                     double* __restrict__ SB) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    predict_zone<T, ORDER, FORM, kDeviation<T>, true, true>(U, W, PK, grid_of(pr, b), dt[p],
+                                                            1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz,
+                                                            gam, pc.at(p), n, &src, SB);
   });
 }
 
@@ -132,11 +146,11 @@ __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ 
                                                      const T* __restrict__ WB,
                                                      const T* __restrict__ BN, T* __restrict__ PK,
                                                      Batch b, const double* __restrict__ dt,
-                                                     double gam) {
+                                                     double gam, PosCtl pc) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone_mhd<T, ORDER, FORM, kDeviation<T>, FUSED, EDGES_ALL>(U, W, B0, WB, BN, PK, grid_of(pr, b),
                                                            dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
-                                                           1.0 / pr.dz, gam, n);
+                                                           1.0 / pr.dz, gam, pc.at(p), n);
   });
 }
 
@@ -171,10 +185,11 @@ template <class T, int ORDER, int FORM, int WAVES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_split(const double* __restrict__ U,
                                                        const T* __restrict__ W, T* __restrict__ PK,
                                                        Batch b, const double* __restrict__ dt,
-                                                       double gam) {
+                                                       double gam, PosCtl pc) {
   for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, PK, grid_of(pr, b), dt[p],
-                                                      1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam, n);
+                                                      1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
+                                                      pc.at(p), n);
   });
 }
 
@@ -182,11 +197,11 @@ template <class T, int ORDER, int FORM, int WAVES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_split(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, Batch b,
-    const double* __restrict__ dt, double gam) {
+    const double* __restrict__ dt, double gam, PosCtl pc) {
   for_zone_groups<8>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_mhd_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, B0, WB, BN, PK, grid_of(pr, b),
                                                           dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
-                                                          1.0 / pr.dz, gam, n);
+                                                          1.0 / pr.dz, gam, pc.at(p), n);
   });
 }
 
@@ -214,9 +229,9 @@ __global__ void __launch_bounds__(256) k_weno_z_columns(const double* __restrict
 template <class T, int ORDER>
 __global__ void __launch_bounds__(256) k_rk_sides(const double* __restrict__ U,
                                                   const T* __restrict__ W, T* __restrict__ PK,
-                                                  Batch b, double gam) {
-  for_zones(b, [&](const Problem& pr, int, long long n) {
-    rk_sides_zone<T, ORDER, kDeviation<T>>(U, W, PK, grid_of(pr, b), gam, n);
+                                                  Batch b, double gam, PosCtl pc) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    rk_sides_zone<T, ORDER, kDeviation<T>>(U, W, PK, grid_of(pr, b), gam, pc.at(p), n);
   });
 }
 
@@ -237,10 +252,11 @@ __global__ void __launch_bounds__(256) k_rk_sides_mhd(const double* __restrict__
                                                       const double* __restrict__ B0,
                                                       const T* __restrict__ WB,
                                                       const T* __restrict__ BN,
-                                                      T* __restrict__ PK, Batch b, double gam) {
-  for_zones(b, [&](const Problem& pr, int, long long n) {
+                                                      T* __restrict__ PK, Batch b, double gam,
+                                                      PosCtl pc) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone_mhd<T, ORDER, 0, kDeviation<T>, true, EDGES_ALL, true>(
-        U, W, B0, WB, BN, PK, grid_of(pr, b), 0.0, 0.0, 0.0, 0.0, gam, n);
+        U, W, B0, WB, BN, PK, grid_of(pr, b), 0.0, 0.0, 0.0, 0.0, gam, pc.at(p), n);
   });
 }
 
@@ -269,12 +285,12 @@ template <class T, int ORDER, int FORM, int WAVES, bool EDGES_ALL, int PHASE = 0
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_pair(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, Batch b,
-    const double* __restrict__ dt, double gam, T* __restrict__ EM = nullptr,
+    const double* __restrict__ dt, double gam, PosCtl pc, T* __restrict__ EM = nullptr,
     double* __restrict__ TH = nullptr) {
   for_zone_groups<2>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_mhd_pair<T, ORDER, FORM, kDeviation<T>, EDGES_ALL, PHASE>(
         L, U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz,
-        gam, n, EM, TH);
+        gam, pc.at(p), n, EM, TH);
   });
 }
 
@@ -311,6 +327,19 @@ __global__ void __launch_bounds__(256) k_update(double* __restrict__ U, const do
                                                 Batch b, const double* __restrict__ dt) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     update_zone(U, F, grid_of(pr, b), dt[p], pr.dx, pr.dy, pr.dz, n);
+  });
+}
+
+// eq. (6) with the source term dt S-bar
+template <int = 0>
+__global__ void __launch_bounds__(256) k_update_src(double* __restrict__ U,
+                                                    const double* __restrict__ F,
+                                                    const double* __restrict__ SB, Batch b,
+                                                    const double* __restrict__ dt) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    const Grid g = grid_of(pr, b);
+    update_zone(U, F, g, dt[p], pr.dx, pr.dy, pr.dz, n);
+    source_zone(U, SB, g, n);
   });
 }
 

@@ -83,8 +83,9 @@ int queue_dt(ader_ctx* c, double cfl) {
 }
 
 // The predictor layout in use: the one set, else the layout measured fastest
-// without tuning: two lanes per zone for MHD at orders 3 and 4, one lane per
-// zone and variable for Euler at order 4, one lane per zone otherwise.
+// without tuning: two lanes per zone for MHD at orders 3 and 4 (one kernel at
+// order 3, the two-kernel form at order 4, where only it is built), one lane
+// per zone and variable for Euler at order 4, one lane per zone otherwise.
 bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
   if (layout == ADER_LAYOUT_ZONE2 && c->system == ADER_MHD && c->riemann == ADER_LINEARIZED)
     return false;
@@ -104,6 +105,7 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
 int layout_of(const ader_ctx* c, const StageFns* s) {
   if (c->layout >= 0 && layout_built(c, s, c->layout)) return c->layout;
   if (s->predict_pair && c->system == ADER_MHD) return ADER_LAYOUT_PAIR;
+  if (s->predict_pair_split && c->system == ADER_MHD) return ADER_LAYOUT_PAIR_SPLIT;
   if (s->predict_split && c->order == 4) return ADER_LAYOUT_SPLIT;
   return ADER_LAYOUT_ZONE;
 }
@@ -231,7 +233,10 @@ int ensure_work(ader_ctx* c) {
   const size_t ls = c->order == 2 ? 4 : c->order == 3 ? 10 : 20;
   const bool mhd = c->system == ADER_MHD;
   const size_t ne = c->order == 2 ? 1 : c->order == 3 ? 5 : 15;   // evolutionary modes
-  const bool split = mhd && c->order >= 3 && c->layout == ADER_LAYOUT_PAIR_SPLIT;
+  // the two-kernel pair layout's mode and factor buffers, for the layout
+  // the step will run (set explicitly or the default of the setting)
+  const StageFns* st = stages_of(c);
+  const bool split = mhd && c->order >= 3 && st && layout_of(c, st) == ADER_LAYOUT_PAIR_SPLIT;
   const size_t need[7] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
                           mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0,
                           c->scheme == ADER_SCHEME_SSPRK ? sizeof(double) * 4 * (mhd ? 8 : 5) * Z
@@ -271,6 +276,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)(c->layout + 1);
   k = k * 3 + (unsigned long long)(c->recon_mode + 1);
   k = k * 3 + (unsigned long long)c->scheme;
+  k = k * 3 + (unsigned long long)c->positivity;
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
@@ -378,8 +384,10 @@ void free_buffers(ader_ctx* c) {
   if (c->owns_B && c->B) (void)hipFree(c->B);
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
                   (void*)c->RK, c->EM, (void*)c->TH,
-                  (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_probs,
-                  (void*)c->d_tile_base, (void*)c->d_seg_base})
+                  (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_limited,
+                  (void*)c->d_probs,
+                  (void*)c->d_tile_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
+                  (void*)c->d_diag})
     if (p) (void)hipFree(p);
 }
 
@@ -448,15 +456,18 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
             hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
             hipMalloc(&c->d_rate, sizeof(unsigned long long) * n) == hipSuccess &&
             hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess &&
+            hipMalloc(&c->d_limited, sizeof(unsigned int) * n) == hipSuccess &&
             hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
-            hipMalloc(&c->d_seg_base, sizeof(long long) * (n + 1)) == hipSuccess;
+            hipMalloc(&c->d_seg_base, sizeof(long long) * (n + 1)) == hipSuccess &&
+            hipMalloc(&c->d_diag_base, sizeof(long long) * (n + 1)) == hipSuccess;
   if (!ok) {
     free_buffers(c);
     delete c;
     (void)hipGetLastError();
     return ADER_ENOMEM;
   }
-  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + sizeof(int) * n + 2 * sizeof(long long) * (n + 1);
+  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + (sizeof(int) + sizeof(unsigned int)) * n +
+                   3 * sizeof(long long) * (n + 1);
   c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
   std::vector<long long> tile_base(n + 1, 0);
@@ -473,7 +484,14 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     seg_base[q + 1] = seg_base[q] + (long long)pr.nx * pr.ny * ((pr.nz + kZSeg - 1) / kZSeg);
   }
   c->nsegs = seg_base[n];
+  // diagnostics tiles of kDiagTile zones per problem
+  std::vector<long long> diag_base(n + 1, 0);
+  for (int q = 0; q < n; ++q)
+    diag_base[q + 1] = diag_base[q] + (c->probs[q].N + kDiagTile - 1) / kDiagTile;
+  c->ndiag_tiles = diag_base[n];
   if (hipMemcpy(c->d_tile_base, tile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_diag_base, diag_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_seg_base, seg_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -481,6 +499,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
       hipMemset(c->d_dt, 0, sD) != hipSuccess ||
       hipMemset(c->d_rate, 0, sizeof(unsigned long long) * n) != hipSuccess ||
       hipMemset(c->d_bad, 0, sizeof(int) * n) != hipSuccess ||
+      hipMemset(c->d_limited, 0, sizeof(unsigned int) * n) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     free_buffers(c);
     delete c;
@@ -621,6 +640,7 @@ int autotune(ader_ctx* c, int reps) {
   if (mhd) (void)hipMemcpyAsync(c->B, sB, bB, hipMemcpyDeviceToDevice, c->stream);
   (void)hipMemcpyAsync(c->d_dt, sdt, bD, hipMemcpyDeviceToDevice, c->stream);
   (void)hipMemsetAsync(c->d_bad, 0, sizeof(int) * c->np(), c->stream);
+  (void)hipMemsetAsync(c->d_limited, 0, sizeof(unsigned int) * c->np(), c->stream);
   (void)hipMemsetAsync(c->d_rate, 0, sizeof(unsigned long long) * c->np(), c->stream);
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(sU);
@@ -852,6 +872,8 @@ int ader_set_layout(ader_ctx* c, int layout) {
        layout == ADER_LAYOUT_PAIR_SPLIT) &&
       (c->order < 3 || c->system != ADER_MHD))
     return ADER_EUNSUPPORTED;
+  if ((layout == ADER_LAYOUT_PAIR || layout == ADER_LAYOUT_PAIR2) && c->order == 4)
+    return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;
 }
@@ -865,6 +887,30 @@ int ader_set_scheme(ader_ctx* c, int scheme) {
 int ader_get_scheme(ader_ctx* c, int* scheme_out) {
   if (!c || !scheme_out) return ADER_EINVAL;
   *scheme_out = c->scheme;
+  return ADER_OK;
+}
+
+int ader_set_positivity(ader_ctx* c, int mode) {
+  if (!c || (mode != ADER_POSITIVITY_CHECK && mode != ADER_POSITIVITY_LIMIT)) return ADER_EINVAL;
+  c->positivity = mode;
+  return ADER_OK;
+}
+
+int ader_get_positivity(ader_ctx* c, int* mode_out) {
+  if (!c || !mode_out) return ADER_EINVAL;
+  *mode_out = c->positivity;
+  return ADER_OK;
+}
+
+int ader_limited_zones(ader_ctx* c, long long* counts_out) {
+  if (!c || !counts_out) return ADER_EINVAL;
+  ADER_TRY(set_device(c));
+  std::vector<unsigned int> cnt(c->np(), 0u);
+  ADER_TRY(check(hipMemcpyAsync(cnt.data(), c->d_limited, sizeof(unsigned int) * cnt.size(),
+                                hipMemcpyDeviceToHost, c->stream)));
+  ADER_TRY(check(hipMemsetAsync(c->d_limited, 0, sizeof(unsigned int) * cnt.size(), c->stream)));
+  ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  for (int q = 0; q < c->np(); ++q) counts_out[q] = (long long)cnt[q];
   return ADER_OK;
 }
 
@@ -932,7 +978,8 @@ const char* ader_strerror(int code) {
     case ADER_EUNSUPPORTED: return "not supported";
     case ADER_ENOMEM: return "device allocation failed";
     case ADER_EDEVICE: return "HIP runtime error";
-    case ADER_ESTATE: return "unphysical state (rho <= 0, P <= 0 or non-finite)";
+    case ADER_ESTATE:
+      return "unphysical state (rho <= 0, P <= 0 or non-finite, in a zone or at a check point)";
     case ADER_ESEQ: return "call out of sequence";
   }
   return "unknown error";

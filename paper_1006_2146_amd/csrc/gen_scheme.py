@@ -153,32 +153,39 @@ def rules_o2(f, g, h):
     return [-(f[1] - f[2]) - (g[3] - g[4]) - (h[5] - h[6])]
 
 
-def rules_o3(f, g, h):
-    # eq. (40), (41), (42) then (36)
+def modes_o3(f, g, h):
+    """Eq. (40), (41), (42): the modes of the x-, y- and z-fluxes from their
+    nodal values, as dicts {mode: combination} (1-based mode numbers)."""
     q1, q2, q3 = S(f[2], f[3], f[4], f[5]), S(f[6], f[7], f[8], f[9]), S(f[10], f[11], f[12], f[13])
-    F2 = (q1 - q2) * QTR
-    F5 = (q1 + q2 - q3) * HALF - f[1] * 2
-    F8 = f[2] - f[3] - f[6] + f[7]
-    F10 = f[4] - f[5] - f[8] + f[9]
-    F13 = (f[14] - f[15] - F2) * 2
+    F = {2: (q1 - q2) * QTR}
+    F[5] = (q1 + q2 - q3) * HALF - f[1] * 2
+    F[8] = f[2] - f[3] - f[6] + f[7]
+    F[10] = f[4] - f[5] - f[8] + f[9]
+    F[13] = (f[14] - f[15] - F[2]) * 2
     q4, q5, q6 = S(g[2], g[6], g[10], g[12]), S(g[3], g[7], g[11], g[13]), S(g[4], g[5], g[8], g[9])
-    G3 = (q4 - q5) * QTR
-    G6 = (q4 + q5 - q6) * HALF - g[1] * 2
-    G8 = g[2] - g[3] - g[6] + g[7]
-    G9 = g[10] - g[11] - g[12] + g[13]
-    G14 = (g[16] - g[17] - G3) * 2
+    G = {3: (q4 - q5) * QTR}
+    G[6] = (q4 + q5 - q6) * HALF - g[1] * 2
+    G[8] = g[2] - g[3] - g[6] + g[7]
+    G[9] = g[10] - g[11] - g[12] + g[13]
+    G[14] = (g[16] - g[17] - G[3]) * 2
     q7, q8, q9 = S(h[4], h[8], h[10], h[11]), S(h[5], h[9], h[12], h[13]), S(h[2], h[3], h[6], h[7])
-    H4 = (q7 - q8) * QTR
-    H7 = (q7 + q8 - q9) * HALF - h[1] * 2
-    H9 = h[10] - h[11] - h[12] + h[13]
-    H10 = h[4] - h[5] - h[8] + h[9]
-    H15 = (h[18] - h[19] - H4) * 2
+    H = {4: (q7 - q8) * QTR}
+    H[7] = (q7 + q8 - q9) * HALF - h[1] * 2
+    H[9] = h[10] - h[11] - h[12] + h[13]
+    H[10] = h[4] - h[5] - h[8] + h[9]
+    H[15] = (h[18] - h[19] - H[4]) * 2
+    return F, G, H
+
+
+def rules_o3(f, g, h):
+    # eq. (40)-(42), then the flux part of (36)
+    F, G, H = modes_o3(f, g, h)
     return [
-        -F2 - G3 - H4,
-        -(F13 + G14 + H15) * HALF,
-        -F5 * 2 - G8 - H10,
-        -F8 - G6 * 2 - H9,
-        -F10 - G9 - H7 * 2,
+        -F[2] - G[3] - H[4],
+        -(F[13] + G[14] + H[15]) * HALF,
+        -F[5] * 2 - G[8] - H[10],
+        -F[8] - G[6] * 2 - H[9],
+        -F[10] - G[9] - H[7] * 2,
     ]
 
 
@@ -204,8 +211,9 @@ def _o4_common(f):
     return q, m
 
 
-def rules_o4(f, g, h):
-    # eq. (49), (50), (51) then (45)
+def modes_o4(f, g, h):
+    """Eq. (49), (50), (51): the modes of the x-, y- and z-fluxes from their
+    nodal values, as dicts {mode: combination} (1-based mode numbers)."""
     q, F = _o4_common(f)
     q10 = f[23] + f[24] + f[25] + f[26] - f[27] - f[28] - f[29] - f[30]
     F[5] = (f[2] - f[1] * 2 + f[5]) * 2
@@ -244,7 +252,12 @@ def rules_o4(f, g, h):
     H[32] = (h[40] - h[35] * 2 + h[41]) * 3 - H[7] * Fr(3, 2)
     H[34] = (h[31] - h[32] - h[33] + h[34]) * 3 - H[9] * 3
     H[35] = (h[25] - h[26] - h[29] + h[30]) * 3 - H[10] * 3
+    return F, G, H
 
+
+def rules_o4(f, g, h):
+    # eq. (49)-(51), then the flux part of (45)
+    F, G, H = modes_o4(f, g, h)
     t = Fr(1, 10)
     return [
         -F[11] * t - F[2] - G[12] * t - G[3] - H[13] * t - H[4],
@@ -423,6 +436,114 @@ def rules_nodal4(f, g, h):
                 v = v + value[j] * Ci[m][j]
         assert all(k[0] != 'u' for k in v), m
         out.append(v)
+    return out
+
+
+# ------------------------------------------------------------ source terms --
+# A non-stiff source S(u) enters the evolutionary modes through the scaled
+# nodal sources s = dt S(u) at the predictor nodes.  Modal form: the source
+# modes are the flux-mode rules with f, g, h -> s, each mode taken from the
+# first of the x-, y-, z-rules that defines it, and eq. (34), (43), (52) for
+# the rest; they enter through the source terms of eq. (30), (36), (45).
+# Nodal forms: the source is interpolated on the nodal basis like the fluxes
+# and enters the Galerkin system of App. A-C (residual u_tau + f_xi + g_eta +
+# h_zeta - s orthogonal to the later nodes' basis functions).
+
+def _source_modes_from_rules(F, G, H):
+    sm = {}
+    for D in (F, G, H):
+        for m, v in D.items():
+            sm.setdefault(m, v)
+    return sm
+
+
+def source_rules_modal(order):
+    """Evolutionary mode k's source part as a combination of the scaled
+    nodal sources s_j (unknowns ('s', j))."""
+    n = len(pred_nodes(order, 'modal'))
+    s = unknowns('s', n)
+    if order == 2:
+        s1 = S(s[1], s[2], s[3], s[4], s[5], s[6]) / 6                       # eq. (34)
+        s5 = s[7] - s1
+        return [s1 + s5 * Fr(2, 3)]                                            # eq. (30)
+    if order == 3:
+        sm = _source_modes_from_rules(*modes_o3(s, s, s))
+        sm[1] = s[1] + (sm[5] + sm[6] + sm[7]) / 12                           # eq. (43)
+        sm[11] = (S(s[14], s[15], s[16], s[17], s[18], s[19]) - sm[1] * 6) * Fr(2, 3) \
+            - s[20] + s[1]
+        sm[12] = s[20] - s[1] - sm[11]
+        return [sm[1] - sm[12] * Fr(3, 10), sm[11] * HALF + sm[12] * Fr(3, 5),   # eq. (36)
+                sm[2] + sm[13] * Fr(2, 3), sm[3] + sm[14] * Fr(2, 3), sm[4] + sm[15] * Fr(2, 3)]
+    sm = _source_modes_from_rules(*modes_o4(s, s, s))
+    sm[1] = S(*[s[j] for j in range(14, 22)]) * Fr(1, 8) - (sm[5] + sm[6] + sm[7]) / 6   # (52)
+    sm[23] = (s[42] - s[1]) * Fr(9, 2) - (s[35] - s[22]) * Fr(27, 2)
+    sm[22] = (s[1] - s[22] - s[35] + s[42]) * Fr(9, 4) - sm[23] * Fr(3, 2)
+    sm[21] = s[42] - s[1] - sm[22] - sm[23] + (sm[30] + sm[31] + sm[32]) / 12
+    two3, three5, three10 = Fr(2, 3), Fr(3, 5), Fr(3, 10)
+    return [sm[1] + sm[23] * Fr(8, 70), sm[21] * HALF - sm[23] * Fr(3, 7),      # eq. (45)
+            sm[22] * THIRD + sm[23] * Fr(4, 7),
+            sm[2] - sm[27] * three10, sm[3] - sm[28] * three10, sm[4] - sm[29] * three10,
+            sm[24] * HALF + sm[27] * three5, sm[25] * HALF + sm[28] * three5,
+            sm[26] * HALF + sm[29] * three5,
+            sm[5] + sm[30] * two3, sm[6] + sm[31] * two3, sm[7] + sm[32] * two3,
+            sm[8] + sm[33] * two3, sm[9] + sm[34] * two3, sm[10] + sm[35] * two3]
+
+
+def source_rules_nodal(order):
+    """The source part of the nodal ADER-CG (App. A, B, C) by the Galerkin
+    system over the nodes (A.1)/(B.1)/(C.1), mapped back to the evolutionary
+    modes."""
+    nodes = pred_nodes(order, 'nodal')
+    modes = mode_list(order)
+    n = len(nodes)
+    mp = [_mode_poly(m) for m in modes]
+    V = [[sum(v * Fr(x[0]) ** k[0] * Fr(x[1]) ** k[1] * Fr(x[2]) ** k[2] * Fr(x[3]) ** k[3]
+              for k, v in mp[m].items()) for m in range(n)] for x in nodes]
+    Ci = _inverse(V)
+    basis = []
+    for j in range(n):
+        p = {}
+        for m in range(n):
+            if Ci[m][j] != 0:
+                p = _poly_add(p, mp[m], Ci[m][j])
+        basis.append(p)
+    lt = [j for j in range(n) if nodes[j][3] != 0]
+    E = [[_integral(_poly_mul(basis[i], _poly_diff(basis[j], 3))) for j in range(n)] for i in lt]
+    Mm = [[_integral(_poly_mul(basis[i], basis[j])) for j in range(n)] for i in lt]
+    Ei = _inverse([[E[r][j] for j in lt] for r in range(len(lt))])
+    s = unknowns('s', n)
+    later = {}
+    for r, j0 in enumerate(lt):
+        v = Lin()
+        for q in range(len(lt)):
+            c = Ei[r][q]
+            if c == 0:
+                continue
+            for j in range(n):
+                if Mm[q][j] != 0:
+                    v = v + s[j + 1] * (c * Mm[q][j])
+        later[j0] = v
+    out = []
+    for m in range(LS[order], n):
+        v = Lin()
+        for j0, lv in later.items():
+            if Ci[m][j0] != 0:
+                v = v + lv * Ci[m][j0]
+        out.append(v)
+    return out
+
+
+def source_weights(order, form):
+    return source_rules_nodal(order) if form == 'nodal' else source_rules_modal(order)
+
+
+def mean_weights(order):
+    """Space-time mean of u over the element from its modes (only the pure
+    time modes have a nonzero mean: tau^d has 1/(d+1))."""
+    out = {}
+    for m, (a, b, c, d) in enumerate(mode_list(order)):
+        if a == 0 and b == 0 and c == 0 and m > 0:
+            out[m] = Fr(1, d + 1)
     return out
 
 
@@ -721,20 +842,31 @@ def gen_order(order, form):
     out.append("template <class T, int NV> struct Scheme%s {" % tag)
     out.append("  static constexpr int LS = %d, NE = %d;" % (ls, ne))
 
-    # per node, per direction: list of (k, weight)
+    # per node, per direction: list of (k, weight); the scaled sources of
+    # an active source functor enter as direction 's'
     node_dirs = {}
     for k, lin in enumerate(W):
         for (dname, j), c in lin.items():
             node_dirs.setdefault(j, {}).setdefault(dname, []).append((k, c))
+    Ws = source_weights(order, form)
+    for k, lin in enumerate(Ws):
+        for (_, j), c in lin.items():
+            node_dirs.setdefault(j, {}).setdefault('s', []).append((k, c))
+    sigma = [sum(lin.values(), Fr(0)) for lin in Ws]
 
     def emit_node(j, accname, lines, reps):
         pt = nodes[j - 1]
         key = (tag, 'predictor')
+        dirs = node_dirs.get(j, {})
+        only_src = not any(d in dirs for d in 'fgh')
         lines.append("    // node %d at (%s)" % (j, ", ".join(str(x) for x in pt)))
-        _count(key, reps * _eval_flops(point_row(order, pt)))
+        if only_src:
+            lines.append("    if constexpr (Src::kActive) {")
+        else:
+            _count(key, reps * _eval_flops(point_row(order, pt)))
         emit_eval(lines, order, pt, "u")
         for dname, axis in (('f', 0), ('g', 1), ('h', 2)):
-            ws = node_dirs.get(j, {}).get(dname)
+            ws = dirs.get(dname)
             if not ws:
                 continue
             lines.append("    ph.template flux<%d>(u, fl);" % axis)
@@ -742,18 +874,43 @@ def gen_order(order, form):
             for k, c in ws:
                 lines.append("    for (int v = 0; v < NV; ++v) %s[%d][v] += (%s * s%s) * fl[v];"
                              % (accname, k, lit(c), "xyz"[axis]))
+        if 's' in dirs:
+            if not only_src:
+                lines.append("    if constexpr (Src::kActive) {")
+            lines.append("      src(u, fl);")
+            for k, c in dirs['s']:
+                lines.append("      for (int v = 0; v < NV; ++v) %s[%d][v] += %s * fl[v];"
+                             % (accname, k, lit(c)))
+            if not only_src:
+                lines.append("    }")
+        if only_src:
+            lines.append("    }")
 
     # predictor
     out.append("  // Picard iterations of the space-time predictor; fluxes at tau = 0")
     out.append("  // nodes are taken once, the others on each of the %d iterations." % (order - 1))
     out.append("  // ph evaluates the physical flux at a point (point form) or")
     out.append("  // the flux minus that of the zone average (deviation form: w[0] unused).")
+    out.append("  // src (if Src::kActive) gives the scaled source dt S at a node state (in")
+    out.append("  // the deviation form dt S of the deviation, with src.base[v] = dt S of")
+    out.append("  // the zone average, which the constant part of the source modes takes).")
     out.append("  template <class Phys>")
     out.append("  __host__ __device__ static __forceinline__ void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
     out.append("                                        T sx, T sy, T sz, const Phys& ph) {")
+    out.append("    predict(w, e, sx, sy, sz, ph, NoSource{});")
+    out.append("  }")
+    out.append("  template <class Phys, class Src>")
+    out.append("  __host__ __device__ static __forceinline__ void predict(const T (&w)[LS][NV], T (&e)[NE][NV],")
+    out.append("                                        T sx, T sy, T sz, const Phys& ph, const Src& src) {")
     out.append("    constexpr bool DEV = Phys::kDeviation;")
     out.append("    T u[NV], fl[NV], a0[NE][NV];")
     out.append("    for (int k = 0; k < NE; ++k) for (int v = 0; v < NV; ++v) { a0[k][v] = T(0); e[k][v] = T(0); }")
+    const = [(k, c) for k, c in enumerate(sigma) if c != 0]
+    if const:
+        out.append("    if constexpr (Src::kActive && DEV) {")
+        for k, c in const:
+            out.append("      for (int v = 0; v < NV; ++v) a0[%d][v] += %s * src.base[v];" % (k, lit(c)))
+        out.append("    }")
     for j in range(1, len(nodes) + 1):
         if nodes[j - 1][3] == 0 and j in node_dirs:
             emit_node(j, "a0", out, 1)
@@ -778,6 +935,14 @@ def gen_order(order, form):
             src = "a1" if k in moving else "a0"
             out.append("      for (int v = 0; v < NV; ++v) e[%d][v] = %s[%d][v];" % (k, src, k))
         out.append("    }")
+    out.append("  }")
+    # the space-time mean of the polynomial minus its zone average (the pure
+    # time modes), for dt times the space-time average of an affine source
+    mw = mean_weights(order)
+    out.append("  // space-time mean of u over the element minus the zone average")
+    out.append("  __host__ __device__ static __forceinline__ void mean_dev(const T (&e)[NE][NV], double (&m)[NV]) {")
+    terms = " + ".join("%.17g * double(e[%d][v])" % (float(c), k - ls) for k, c in sorted(mw.items()))
+    out.append("    for (int v = 0; v < NV; ++v) m[v] = %s;" % terms)
     out.append("  }")
 
     # spatial check points (positivity, before the predictor)
@@ -1073,6 +1238,12 @@ def main():
         "// the derivation from the paper's equations).",
         "#pragma once",
         "namespace ader_gen {",
+        "// The inactive source of a step without a source term.",
+        "struct NoSource {",
+        "  static constexpr bool kActive = false;",
+        "  template <class U>",
+        "  __host__ __device__ void operator()(const U&, U&) const {}",
+        "};",
     ]
     global SYSTEM
     for order, form in ((2, 'modal'), (2, 'nodal'), (3, 'modal'), (3, 'nodal'), (4, 'modal'),

@@ -85,13 +85,22 @@ struct SplitScan {
 // (NoScan: in this layout the facial check set is scanned on its own before
 // the sides are formed, which keeps the register use of the side code low.)
 
+// pos_scales for the lanes of one zone: every lane gets the same theta, and
+// only the zone's first lane flags or counts.
+__device__ __forceinline__ bool pos_scales_lane(const SplitLane& L, const PosCtl& pc,
+                                                double theta) {
+  if (!(theta < 1.0)) return false;
+  if (L.var == 0) return pos_scales(pc, theta);
+  return theta >= 0.0;
+}
+
 // Exact positivity pass (rare): this lane's component at each check point in
 // double, the zone's state gathered, the same theta in every lane of a zone.
 template <int NP, int LS, class T, int NV>
 __device__ double theta_spatial_split(const SplitLane& L, const double (&w0)[NV],
                                       const T (&w)[LS][1], const double (&phi)[NP][LS],
-                                      double gam) {
-  PosTheta<T, NV> acc(w0, gam);
+                                      double gam, bool limit) {
+  PosTheta<T, NV> acc(w0, gam, limit);
   const double own0 = pick(L, w0);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
@@ -102,14 +111,15 @@ __device__ double theta_spatial_split(const SplitLane& L, const double (&w0)[NV]
     gather(L, s, u);
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 template <int NP, int LS, int NE, class T, int NV>
 __device__ double theta_facial_split(const SplitLane& L, const double (&w0)[NV],
                                      const T (&w)[LS][1], const T (&e)[NE][1],
-                                     const double (&phi)[NP][LS + NE], double gam) {
-  PosTheta<T, NV> acc(w0, gam);
+                                     const double (&phi)[NP][LS + NE], double gam,
+                                     bool limit) {
+  PosTheta<T, NV> acc(w0, gam, limit);
   const double own0 = pick(L, w0);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
@@ -122,7 +132,7 @@ __device__ double theta_facial_split(const SplitLane& L, const double (&w0)[NV],
     gather(L, s, u);
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 // The same operations as predict_zone (Euler), in the lane-split layout.
@@ -131,7 +141,7 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
                                                    const T* __restrict__ W, T* __restrict__ PK,
                                                    const Grid& g, double h, double inv_dx,
                                                    double inv_dy, double inv_dz, double gam,
-                                                   long long n) {
+                                                   PosCtl pc, long long n) {
   using S = typename SchemeOf<ORDER, FORM, T, 1>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[5];
@@ -144,8 +154,9 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
   {
     SplitScan<T, 5, DEV> scan{PosScan<T, 5, DEV>(w0), L};
     S::spatial_points(w, scan);
-    const double theta = scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta =
+        scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi, gam, pc.limit) : 1.0;
+    if (pos_scales_lane(L, pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m) w[m][0] *= th;
@@ -158,8 +169,8 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
     SplitScan<T, 5, DEV> scan{PosScan<T, 5, DEV>(w0), L};
     S::facial_points(w, e, scan);
     const double theta =
-        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi, gam) : 1.0;
-    if (theta < 1.0) {
+        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi, gam, pc.limit) : 1.0;
+    if (pos_scales_lane(L, pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m) w[m][0] *= th;
@@ -191,7 +202,7 @@ __device__ __forceinline__ void predict_zone_mhd_split(
     const SplitLane& L, const double* __restrict__ U, const T* __restrict__ W,
     const double* __restrict__ B0, const T* __restrict__ WB, const T* __restrict__ BN,
     T* __restrict__ PK, const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz,
-    double gam, long long n) {
+    double gam, PosCtl pc, long long n) {
   using S = typename SchemeOf<ORDER, FORM, T, 1>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[8];
@@ -219,8 +230,8 @@ __device__ __forceinline__ void predict_zone_mhd_split(
     SplitScan<T, 8, DEV> scan{PosScan<T, 8, DEV>(w0), L};
     S::spatial_points_all(w, scan);
     const double theta =
-        scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi_all, gam) : 1.0;
-    if (theta < 1.0) {
+        scan.inner.near ? theta_spatial_split(L, w0, w, S::spatial_phi_all, gam, pc.limit) : 1.0;
+    if (pos_scales_lane(L, pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m) w[m][0] *= th;
@@ -233,8 +244,9 @@ __device__ __forceinline__ void predict_zone_mhd_split(
     SplitScan<T, 8, DEV> scan{PosScan<T, 8, DEV>(w0), L};
     S::facial_points_all(w, e, scan);
     const double theta =
-        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi_all, gam) : 1.0;
-    if (theta < 1.0) {
+        scan.inner.near ? theta_facial_split(L, w0, w, e, S::facial_phi_all, gam, pc.limit)
+                        : 1.0;
+    if (pos_scales_lane(L, pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m) w[m][0] *= th;
@@ -332,8 +344,8 @@ struct PairScan {
 template <int NP, int LS, class T>
 __device__ double theta_spatial_pair(const SplitLane& L, const double (&w0)[8],
                                      const T (&w)[LS][kPairVars], const double (&phi)[NP][LS],
-                                     double gam) {
-  PosTheta<T, 8> acc(w0, gam);
+                                     double gam, bool limit) {
+  PosTheta<T, 8> acc(w0, gam, limit);
   double own0[kPairVars];
   pair_pick(L, w0, own0);
 #pragma unroll 1
@@ -349,14 +361,15 @@ __device__ double theta_spatial_pair(const SplitLane& L, const double (&w0)[8],
     pair_gather(L, s, u);
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 template <int NP, int LS, int NE, class T>
 __device__ double theta_facial_pair(const SplitLane& L, const double (&w0)[8],
                                     const T (&w)[LS][kPairVars], const T (&e)[NE][kPairVars],
-                                    const double (&phi)[NP][LS + NE], double gam) {
-  PosTheta<T, 8> acc(w0, gam);
+                                    const double (&phi)[NP][LS + NE], double gam,
+                                    bool limit) {
+  PosTheta<T, 8> acc(w0, gam, limit);
   double own0[kPairVars];
   pair_pick(L, w0, own0);
 #pragma unroll 1
@@ -374,7 +387,7 @@ __device__ double theta_facial_pair(const SplitLane& L, const double (&w0)[8],
     pair_gather(L, s, u);
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 // The same operations as predict_zone_mhd, in the pair layout.  EDGES_ALL:
@@ -389,7 +402,8 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
     const SplitLane& L, const double* __restrict__ U, const T* __restrict__ W,
     const double* __restrict__ B0, const T* __restrict__ WB, const T* __restrict__ BN,
     T* __restrict__ PK, const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz,
-    double gam, long long n, T* __restrict__ EM = nullptr, double* __restrict__ TH = nullptr) {
+    double gam, PosCtl pc, long long n, T* __restrict__ EM = nullptr,
+    double* __restrict__ TH = nullptr) {
   constexpr int VPL = kPairVars;
   using S = typename SchemeOf<ORDER, FORM, T, VPL>::type;
   constexpr int LS = S::LS, NE = S::NE;
@@ -441,7 +455,11 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
     } else {
       PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
       S::spatial_points_all(w, scan);
-      th_s = scan.inner.near ? theta_spatial_pair(L, w0, w, S::spatial_phi_all, gam) : 1.0;
+      th_s = scan.inner.near ? theta_spatial_pair(L, w0, w, S::spatial_phi_all, gam, pc.limit)
+                             : 1.0;
+      // the factor to apply (1 unless the limit mode scales), also what
+      // the side kernel of the two-kernel form reloads
+      th_s = pos_scales_lane(L, pc, th_s) ? th_s : 1.0;
     }
     const double theta = th_s;
     if (theta < 1.0) {
@@ -472,8 +490,9 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
     S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
     PairScan<T, DEV> scan{PosScan<T, 8, DEV>(w0), L};
     S::facial_points_all(w, e, scan);
-    const double theta =
-        scan.inner.near ? theta_facial_pair(L, w0, w, e, S::facial_phi_all, gam) : 1.0;
+    const double theta_x =
+        scan.inner.near ? theta_facial_pair(L, w0, w, e, S::facial_phi_all, gam, pc.limit) : 1.0;
+    const double theta = pos_scales_lane(L, pc, theta_x) ? theta_x : 1.0;
     if (theta < 1.0) {
       const T th = T(theta);
 #pragma unroll

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/ader.h"
+#include "../../include/ader_probe.h"
 
 namespace {
 

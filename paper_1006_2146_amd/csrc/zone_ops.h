@@ -252,10 +252,40 @@ __host__ __device__ __forceinline__ void minmod_zone(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Positivity safeguard (the reading that keeps strong blasts physical: one
-// Zhang-Shu scaling factor per zone polynomial, computed in double).  NV = 5
-// (Euler) or 8 (MHD: the pressure carries B^2/8pi).
+// Positivity.  The paper's scheme has no positivity treatment: in the check
+// mode (the default) a zone whose polynomial has rho <= 0 or P <= 0 at a
+// check point flags its problem (the step then reports an unphysical
+// state) and nothing is changed.  The limit mode is an opt-in safeguard:
+// one Zhang-Shu scaling factor per zone polynomial, computed in double.
+// NV = 5 (Euler) or 8 (MHD: the pressure carries B^2/8pi).
 // ---------------------------------------------------------------------------
+
+// Positivity handling of a kernel launch: the mode and, per problem, the
+// violation flag (check mode) and the count of scaled zone polynomials
+// (limit mode).  at(p) points the two at problem p.
+struct PosCtl {
+  int limit;
+  int* bad;
+  unsigned int* limited;
+  __host__ __device__ PosCtl at(int p) const { return PosCtl{limit, bad + p, limited + p}; }
+};
+
+// Outcome of the exact pass of a zone: true if its modes are to be scaled by
+// theta (limit mode, theta < 1, counted); a violation of the check mode
+// (theta < 0) flags the problem and scales nothing.
+__host__ __device__ inline bool pos_scales(const PosCtl& pc, double theta) {
+  if (!(theta < 1.0)) return false;
+  if (theta < 0.0) {
+    *pc.bad = 1;
+    return false;
+  }
+#if defined(__HIP_DEVICE_COMPILE__)
+  atomicAdd(pc.limited, 1u);
+#else
+  ++*pc.limited;
+#endif
+  return true;
+}
 template <int NV>
 __host__ __device__ __forceinline__ double pressure_of(const double (&u)[NV], double gam) {
   double e = u[4] - 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
@@ -263,12 +293,16 @@ __host__ __device__ __forceinline__ double pressure_of(const double (&u)[NV], do
   return (gam - 1.0) * e;
 }
 
+// limit: the scaling factor theta; else the check (violation set when a
+// point has rho <= 0 or P <= 0) and result() is -1 on a violation, 1 if not.
 template <class T, int NV>
 struct PosTheta {
   double ub[NV];
   double eps_rho, eps_p, gam, theta;
+  bool limit, violation;
 
-  __host__ __device__ PosTheta(const double (&w0)[NV], double g) : gam(g), theta(1.0) {
+  __host__ __device__ PosTheta(const double (&w0)[NV], double g, bool lim)
+      : gam(g), theta(1.0), limit(lim), violation(false) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) ub[v] = w0[v];
     eps_rho = 1.0e-8 * ub[0];
@@ -316,8 +350,14 @@ struct PosTheta {
   // from the zone average to the point: the density bound (linear) and the
   // first crossing of the pressure bound; the same value as scaling for
   // density first and then for pressure.
+  __host__ __device__ double result() const { return limit ? theta : (violation ? -1.0 : 1.0); }
+
   __host__ __device__ void operator()(const double (&u)[NV]) {
     const double p = pressure_of<NV>(u, gam);
+    if (!limit) {
+      if (!(u[0] > 0.0) || !(p > 0.0)) violation = true;
+      return;
+    }
     if (u[0] < eps_rho || p < eps_p) {
       double t = 1.0;
       if (u[0] < eps_rho) t = (ub[0] - eps_rho) / (ub[0] - u[0]);
@@ -372,13 +412,14 @@ struct PosScan {
 };
 
 // Exact pass for a flagged zone: a runtime loop over the check points with
-// the basis values from the scheme's tables, so the rare path stays small.
+// the basis values from the scheme's tables, so the rare path stays small;
+// the scaling factor (limit) or the check's result (see PosTheta).
 // The zone average w0 comes in double; the modes w[1..] (and e) are summed in
 // double, so both forms (w[0] is not read) give the same point values.
 template <int NP, int LS, class T, int NV>
 __host__ __device__ double theta_spatial_tab(const double (&w0)[NV], const T (&w)[LS][NV],
-                                             const double (&phi)[NP][LS], double gam) {
-  PosTheta<T, NV> acc(w0, gam);
+                                             const double (&phi)[NP][LS], double gam, bool limit) {
+  PosTheta<T, NV> acc(w0, gam, limit);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
     double u[NV];
@@ -391,14 +432,15 @@ __host__ __device__ double theta_spatial_tab(const double (&w0)[NV], const T (&w
     }
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 template <int NP, int LS, int NE, class T, int NV>
 __host__ __device__ double theta_facial_tab(const double (&w0)[NV], const T (&w)[LS][NV],
                                             const T (&e)[NE][NV],
-                                            const double (&phi)[NP][LS + NE], double gam) {
-  PosTheta<T, NV> acc(w0, gam);
+                                            const double (&phi)[NP][LS + NE], double gam,
+                                            bool limit) {
+  PosTheta<T, NV> acc(w0, gam, limit);
 #pragma unroll 1
   for (int p = 0; p < NP; ++p) {
     double u[NV];
@@ -413,7 +455,7 @@ __host__ __device__ double theta_facial_tab(const double (&w0)[NV], const T (&w)
     }
     acc(u);
   }
-  return acc.theta;
+  return acc.result();
 }
 
 // The flux evaluator of each form.
@@ -462,17 +504,86 @@ struct NoScan {
   __host__ __device__ void operator()(const U&) const {}
 };
 
+// ---------------------------------------------------------------------------
+// Non-stiff source term (Euler): an affine S(u) = A u + b, the same for all
+// zones of a context (row-major A: S_v = sum_q A[v][q] u_q + b_v).  At the
+// predictor nodes the generated code takes the scaled source dt S from
+// AffineSrc: in the point form dt (A u + b); in the deviation form dt A du of
+// the deviation du, with base = dt S(zone average) (formed in double) for the
+// constant part.  dt times the space-time average of S over the zone, the
+// source term of eq. (6), is dt (A mean + b) with mean the space-time mean of
+// the final polynomial, which for an affine S equals eq. (35), (44), (53)
+// and (A.7), (B.6), (C.6).
+// ---------------------------------------------------------------------------
+struct SourceAffine {
+  double A[25];
+  double b[5];
+};
+
+template <class T, bool DEV>
+struct AffineSrc {
+  static constexpr bool kActive = true;
+  const SourceAffine& s;
+  T h;
+  T base[5];
+  __host__ __device__ AffineSrc(const SourceAffine& src, double dt, const double (&w0)[5])
+      : s(src), h(T(dt)) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double a = s.b[v];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) a += s.A[v * 5 + q] * w0[q];
+      base[v] = DEV ? T(dt * a) : T(0);
+    }
+  }
+  __host__ __device__ void operator()(const T (&u)[5], T (&out)[5]) const {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      T a = DEV ? T(0) : T(s.b[v]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) a += T(s.A[v * 5 + q]) * u[q];
+      out[v] = h * a;
+    }
+  }
+};
+
+// dt (A mean + b) for the final modes of a zone (SB row v at n)
+template <class S, class T>
+__host__ __device__ __forceinline__ void store_source_average(const SourceAffine& src, double dt,
+                                                              const double (&w0)[5],
+                                                              const T (&e)[S::NE][5],
+                                                              double* __restrict__ SB, long long N,
+                                                              long long n) {
+  double m[5];
+  S::mean_dev(e, m);
+  double* q = SB + n;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double a = src.b[v];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a += src.A[v * 5 + k] * (w0[k] + m[k]);
+    *q = dt * a;
+    q = next_row(q, N);
+  }
+}
+
 // Per zone: load the reconstruction, positivity scaling, space-time predictor
 // (Sec. IV / App. A), positivity scaling, and the six face-side packets (in
 // the deviation form without the zone-average part).  FUSED: the facial
 // check set is scanned while the sides are formed (their states are that
 // set), else in a pass of its own before them; the results are the same.
-template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true>
+// SRC: with the affine source *src, whose dt-scaled space-time average goes
+// to SB (rows of 5 doubles).
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool SRC = false>
 __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__ U,
                                                       const T* __restrict__ W,
                                                       T* __restrict__ PK, const Grid& g,
                                                       double h, double inv_dx, double inv_dy,
-                                                      double inv_dz, double gam, long long n) {
+                                                      double inv_dz, double gam, PosCtl pc,
+                                                      long long n,
+                                                      const SourceAffine* src = nullptr,
+                                                      double* __restrict__ SB = nullptr) {
+  static_assert(FUSED || !SRC, "the source instance has the fused facial check");
   using S = typename SchemeOf<ORDER, FORM, T>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[5];
@@ -495,8 +606,8 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   {
     PosScan<T, 5, DEV> scan(w0);
     S::spatial_points(w, scan);
-    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam, pc.limit) : 1.0;
+    if (pos_scales(pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m)
@@ -506,12 +617,16 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
   }
   const auto ph = FluxOf<Euler<T>, T, DEV>::make(w0, gam);
   T e[NE][5];
-  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  if constexpr (SRC)
+    S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph,
+               AffineSrc<T, DEV>(*src, h, w0));
+  else
+    S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
   if constexpr (!FUSED) {
     PosScan<T, 5, DEV> scan(w0);
     S::facial_points(w, e, scan);
-    const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi, gam, pc.limit) : 1.0;
+    if (pos_scales(pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m)
@@ -548,8 +663,8 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
     store_side<S, T, 4>(w, e, ph, scan, q, g.S);
     store_side<S, T, 5>(w, e, ph, scan, q, g.S);
     if (pass == 1 || !scan.near) break;
-    const double theta = theta_facial_tab(w0, w, e, S::facial_phi, gam);
-    if (!(theta < 1.0)) break;
+    const double theta = theta_facial_tab(w0, w, e, S::facial_phi, gam, pc.limit);
+    if (!pos_scales(pc, theta)) break;
     const T th = T(theta);
 #pragma unroll
     for (int m = 1; m < LS; ++m)
@@ -560,6 +675,8 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
 #pragma unroll
       for (int v = 0; v < 5; ++v) e[m][v] *= th;
   }
+  // the source term of eq. (6) from the final (possibly scaled) polynomial
+  if constexpr (SRC) store_source_average<S, T>(*src, h, w0, e, SB, g.S, n);
 }
 
 // An SSP-RK stage (Sec. II.d; Euler): the predictor is bypassed, so a zone
@@ -571,7 +688,7 @@ template <class T, int ORDER, bool DEV>
 __host__ __device__ __forceinline__ void rk_sides_zone(const double* __restrict__ U,
                                                        const T* __restrict__ W,
                                                        T* __restrict__ PK, const Grid& g,
-                                                       double gam, long long n) {
+                                                       double gam, PosCtl pc, long long n) {
   using S = typename SchemeOf<ORDER, 0, T>::type;
   constexpr int LS = S::LS;
   double w0[5];
@@ -593,8 +710,8 @@ __host__ __device__ __forceinline__ void rk_sides_zone(const double* __restrict_
   {
     PosScan<T, 5, DEV> scan(w0);
     S::spatial_points(w, scan);
-    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi, gam, pc.limit) : 1.0;
+    if (pos_scales(pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m)
@@ -889,6 +1006,14 @@ __host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, con
   }
 }
 
+// eq. (6) with the source term: update_zone, then + dt S-bar (SB rows)
+__host__ __device__ __forceinline__ void source_zone(double* __restrict__ U,
+                                                     const double* __restrict__ SB, const Grid& g,
+                                                     long long n) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) U[(long long)v * g.S + n] += SB[(long long)v * g.S + n];
+}
+
 // ---------------------------------------------------------------------------
 // dt by CFL: per zone sum_d (|v_d| + c) / dx_d; wavefront then block maximum
 // into one partial per block; a single block reduces the partials.
@@ -1048,7 +1173,7 @@ template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool EDGES_
 __host__ __device__ __forceinline__ void predict_zone_mhd(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,
     const T* __restrict__ WB, const T* __restrict__ BN, T* __restrict__ PK, const Grid& g,
-    double h, double inv_dx, double inv_dy, double inv_dz, double gam, long long n) {
+    double h, double inv_dx, double inv_dy, double inv_dz, double gam, PosCtl pc, long long n) {
   using S = typename SchemeOf<ORDER, FORM, T, 8>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[8];
@@ -1082,8 +1207,9 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   {
     PosScan<T, 8, DEV> scan(w0);
     S::spatial_points_all(w, scan);
-    const double theta = scan.near ? theta_spatial_tab(w0, w, S::spatial_phi_all, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta =
+        scan.near ? theta_spatial_tab(w0, w, S::spatial_phi_all, gam, pc.limit) : 1.0;
+    if (pos_scales(pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m)
@@ -1108,8 +1234,9 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
   if constexpr (!FUSED) {
     PosScan<T, 8, DEV> scan(w0);
     S::facial_points_all(w, e, scan);
-    const double theta = scan.near ? theta_facial_tab(w0, w, e, S::facial_phi_all, gam) : 1.0;
-    if (theta < 1.0) {
+    const double theta =
+        scan.near ? theta_facial_tab(w0, w, e, S::facial_phi_all, gam, pc.limit) : 1.0;
+    if (pos_scales(pc, theta)) {
       const T th = T(theta);
 #pragma unroll
       for (int m = 1; m < LS; ++m)
@@ -1140,8 +1267,8 @@ __host__ __device__ __forceinline__ void predict_zone_mhd(
     store_side_mhd<S, T, 4, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
     store_side_mhd<S, T, 5, EDGES_ALL>(w, e, ph, scan, PK, g.S, n);
     if (pass == 1 || !scan.near) break;
-    const double theta = theta_facial_tab(w0, w, e, S::facial_phi_all, gam);
-    if (!(theta < 1.0)) break;
+    const double theta = theta_facial_tab(w0, w, e, S::facial_phi_all, gam, pc.limit);
+    if (!pos_scales(pc, theta)) break;
     const T th = T(theta);
 #pragma unroll
     for (int m = 1; m < LS; ++m)

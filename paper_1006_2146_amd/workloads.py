@@ -395,3 +395,39 @@ def turbulent_mhd(shape, seed=384, gamma=5.0 / 3.0, n_modes=64, kmax=8, p0=0.6, 
     rho = np.ones(tuple(shape))
     P = np.full(tuple(shape), p0)
     return _mhd_conserved(rho, v, P, face_mean(B), gamma), B
+
+
+def isentropic_vortex(n, t=0.0, length=10.0, eps=5.0, gamma=1.4, quad=5):
+    """The two-dimensional isentropic vortex of Sec. VI.1 on an n x n mesh
+    with one zone in z: shape (1, n, n), the periodic box [0, length]^2 in
+    x and y standing for [-length/2, length/2]^2, and lz = length.  Mean
+    flow rho = P = 1, v = (1, 1, 0); the vortex adds
+        dv = eps / 2 pi exp((1 - r^2) / 2) (-y, x),
+        dT = -(gamma - 1) eps^2 / (8 gamma pi^2) exp(1 - r^2)
+    at constant entropy (T = P / rho, P / rho^gamma = 1), centred at
+    (t, t) (the exact solution at time t: the vortex carried by the mean
+    flow, periodically; the nearest periodic image of the centre counts).
+    Zone averages of the conserved variables by a quad x quad
+    Gauss-Legendre rule per zone."""
+    g, w = np.polynomial.legendre.leggauss(quad)
+    h = length / n
+    edges = np.arange(n) * h
+    pts = (edges[:, None] + 0.5 * h * (g[None, :] + 1.0)).ravel()     # (n * quad,)
+    wts = np.tile(0.5 * w, n)
+    X = pts[None, :] - 0.5 * length
+    Y = pts[:, None] - 0.5 * length
+    cx = (t + 0.5 * length) % length - 0.5 * length
+    dx = (X - cx + 0.5 * length) % length - 0.5 * length
+    dy = (Y - cx + 0.5 * length) % length - 0.5 * length
+    r2 = dx * dx + dy * dy
+    amp = eps / (2.0 * np.pi) * np.exp(0.5 * (1.0 - r2))
+    vx = 1.0 - amp * dy
+    vy = 1.0 + amp * dx
+    T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * np.pi ** 2) * np.exp(1.0 - r2)
+    rho = T ** (1.0 / (gamma - 1.0))
+    P = rho * T
+    v = np.stack([vx, vy, np.zeros_like(vx)])
+    Uq = _euler_conserved(rho, v, P, gamma)                            # (5, n q, n q)
+    Wq = wts[:, None] * wts[None, :]
+    Uz = (Uq * Wq).reshape(5, n, quad, n, quad).sum(axis=(2, 4))
+    return Uz[:, None, :, :].copy()

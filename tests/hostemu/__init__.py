@@ -52,8 +52,37 @@ def load():
         lib.hostemu_mhd_dissipation.argtypes = [DP, DP, DP, I, D, DP]
         lib.hostemu_dt_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt_mhd.restype = D
+        lib.hostemu_set_positivity.argtypes = [I]
+        lib.hostemu_set_positivity.restype = None
+        lib.hostemu_pos_status.argtypes = [ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint)]
+        lib.hostemu_pos_status.restype = None
         _lib = lib
     return _lib
+
+
+class NonPhysical(ArithmeticError):
+    """The check mode met rho <= 0 or P <= 0 at a check point."""
+
+
+# positivity: "check" (the paper's scheme: report, change nothing) or
+# "limit" (the scaling safeguard)
+POSITIVITY = {"check": 0, "limit": 1}
+
+last_limited = 0   # scaled zone polynomials of the last step (limit mode)
+
+
+def _begin(positivity):
+    load().hostemu_set_positivity(POSITIVITY[positivity])
+
+
+def _end():
+    global last_limited
+    bad = ctypes.c_int(0)
+    lim = ctypes.c_uint(0)
+    load().hostemu_pos_status(ctypes.byref(bad), ctypes.byref(lim))
+    last_limited = lim.value
+    if bad.value:
+        raise NonPhysical("rho <= 0 or P <= 0 at a check point")
 
 
 def _spacing(U, lengths):
@@ -62,23 +91,27 @@ def _spacing(U, lengths):
 
 
 def step(U, dt, order, form="modal", riemann="hll", precision="fp64",
-         lengths=(1.0, 1.0, 1.0), gamma=1.4):
+         lengths=(1.0, 1.0, 1.0), gamma=1.4, positivity="check"):
     out = np.ascontiguousarray(U, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
+    _begin(positivity)
     load().hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
                         dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
                         1 if riemann == "linearized" else 0, PRECISION[precision], dt)
+    _end()
     return out
 
 
 def step_rk(U, dt, order, riemann="hll", precision="fp64", lengths=(1.0, 1.0, 1.0),
-            gamma=1.4):
+            gamma=1.4, positivity="check"):
     """One SSP-RK step (Euler) of the host build of the RK kernels."""
     out = np.ascontiguousarray(U, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
+    _begin(positivity)
     load().hostemu_step_rk(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
                            dx, dy, dz, gamma, order, 1 if riemann == "linearized" else 0,
                            PRECISION[precision], dt)
+    _end()
     return out
 
 
@@ -94,24 +127,28 @@ def _dp(a):
 
 
 def step_mhd(U, B, dt, order, form="modal", precision="fp64", lengths=(1.0, 1.0, 1.0),
-             gamma=5.0 / 3.0, riemann="hll"):
+             gamma=5.0 / 3.0, riemann="hll", positivity="check"):
     Uo = np.ascontiguousarray(U, dtype=np.float64).copy()
     Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
+    _begin(positivity)
     load().hostemu_step_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
                             1 if form == "nodal" else 0, 1 if riemann == "linearized" else 0,
                             PRECISION[precision], dt)
+    _end()
     return Uo, Bo
 
 
 def step_rk_mhd(U, B, dt, order, riemann="hll", precision="fp64", lengths=(1.0, 1.0, 1.0),
-                gamma=5.0 / 3.0):
+                gamma=5.0 / 3.0, positivity="check"):
     """One SSP-RK step of ideal MHD of the host build of the RK kernels."""
     Uo = np.ascontiguousarray(U, dtype=np.float64).copy()
     Bo = np.ascontiguousarray(B, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(Uo, lengths)
+    _begin(positivity)
     load().hostemu_step_rk_mhd(_dp(Uo), _dp(Bo), nx, ny, nz, dx, dy, dz, gamma, order,
                                1 if riemann == "linearized" else 0, PRECISION[precision], dt)
+    _end()
     return Uo, Bo
 
 

@@ -12,6 +12,12 @@
 
 using namespace ader;
 
+// Positivity handling of the host build: the mode set by
+// hostemu_set_positivity, and the problem's flag and scaling count.
+static int g_limit = 0, g_bad = 0;
+static unsigned int g_limited = 0;
+static PosCtl emu_pc() { return PosCtl{g_limit, &g_bad, &g_limited}; }
+
 template <class T, bool DEV>
 static void emu_step(double* U, Grid g, double dx, double dy, double dz, double gam, int order,
                      int form, int riemann, double dt) {
@@ -32,17 +38,17 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
     if (order == 2 && form == 1)
-      predict_zone<T, 2, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 2, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 2)
-      predict_zone<T, 2, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 2, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 3 && form == 1)
-      predict_zone<T, 3, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 3, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 4 && form == 1)
-      predict_zone<T, 4, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 4, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 3)
-      predict_zone<T, 3, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 3, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else
-      predict_zone<T, 4, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone<T, 4, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
   }
   for (long long n = 0; n < N; ++n) {
     if (riemann == 0)
@@ -88,9 +94,9 @@ static void emu_rk_step(double* U, Grid g, double dx, double dy, double dz, doub
       for (long long n = 0; n < N; ++n) weno_sweep_zone<T, 4, 2>(U, W.data(), g, n);
     }
     for (long long n = 0; n < N; ++n) {
-      if (order == 2) rk_sides_zone<T, 2, DEV>(U, W.data(), PK.data(), g, gam, n);
-      else if (order == 3) rk_sides_zone<T, 3, DEV>(U, W.data(), PK.data(), g, gam, n);
-      else rk_sides_zone<T, 4, DEV>(U, W.data(), PK.data(), g, gam, n);
+      if (order == 2) rk_sides_zone<T, 2, DEV>(U, W.data(), PK.data(), g, gam, emu_pc(), n);
+      else if (order == 3) rk_sides_zone<T, 3, DEV>(U, W.data(), PK.data(), g, gam, emu_pc(), n);
+      else rk_sides_zone<T, 4, DEV>(U, W.data(), PK.data(), g, gam, emu_pc(), n);
     }
     for (long long n = 0; n < N; ++n) {
       if (riemann == 0) face_flux_zone<T, 0, DEV>(U, PK.data(), F.data(), g, gam, n);
@@ -152,17 +158,17 @@ static void emu_step_mhd(double* U, double* B, Grid g, double dx, double dy, dou
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
     if (order == 2 && form == 1)
-      predict_zone_mhd<T, 2, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 2)
-      predict_zone_mhd<T, 2, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 2, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 3 && form == 1)
-      predict_zone_mhd<T, 3, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 3, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 4 && form == 1)
-      predict_zone_mhd<T, 4, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 4, 1, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else if (order == 3)
-      predict_zone_mhd<T, 3, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 3, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
     else
-      predict_zone_mhd<T, 4, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, n);
+      predict_zone_mhd<T, 4, 0, DEV, true, ALL>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
   }
   for (long long n = 0; n < N; ++n)
     face_flux_zone_mhd<T, RS, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
@@ -206,11 +212,11 @@ static void emu_rk_step_mhd(double* U, double* B, Grid g, double dx, double dy, 
     emu_recon<T>(B0.data(), WB.data(), g, order, 3);
     for (long long n = 0; n < N; ++n) {
       if (order == 2)
-        predict_zone_mhd<T, 2, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+        predict_zone_mhd<T, 2, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, emu_pc(), n);
       else if (order == 3)
-        predict_zone_mhd<T, 3, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+        predict_zone_mhd<T, 3, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, emu_pc(), n);
       else
-        predict_zone_mhd<T, 4, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, n);
+        predict_zone_mhd<T, 4, 0, DEV, true, ALL, true>(U, W.data(), B0.data(), WB.data(), BN.data(), PK.data(), g, 0.0, 0.0, 0.0, 0.0, gam, emu_pc(), n);
     }
     for (long long n = 0; n < N; ++n)
       face_flux_zone_mhd<T, RS, DEV>(U, B0.data(), PK.data(), F.data(), FE.data(), g, gam, n);
@@ -228,6 +234,22 @@ static void emu_rk_step_mhd(double* U, double* B, Grid g, double dx, double dy, 
 }
 
 extern "C" {
+
+// Mode of the following steps (0 check, 1 limit); clears the status.
+void hostemu_set_positivity(int limit) {
+  g_limit = limit;
+  g_bad = 0;
+  g_limited = 0;
+}
+
+// Status since the last call: the check mode's violation flag and the limit
+// mode's count of scaled zone polynomials; both cleared.
+void hostemu_pos_status(int* bad, unsigned int* limited) {
+  *bad = g_bad;
+  *limited = g_limited;
+  g_bad = 0;
+  g_limited = 0;
+}
 
 // One SSP-RK step of ideal MHD of the host build, in place on U and B.
 int hostemu_step_rk_mhd(double* U, double* B, int nx, int ny, int nz, double dx, double dy,

@@ -53,10 +53,16 @@ def test_argument_validation_before_device(lib):
     assert lib.ader_set_gamma(None, 1.4) == ader.ADER_EINVAL
     assert lib.ader_step(None, 0.1) == ader.ADER_EINVAL
     assert lib.ader_set_order(None, 3, 0) == ader.ADER_EINVAL
-    v = ctypes.c_double()
-    assert lib.ader_probe_peak(0, 3, ctypes.byref(v)) == ader.ADER_EINVAL
-    assert lib.ader_probe_peak(0, 0, None) == ader.ADER_EINVAL
     lib.ader_destroy(None)
+
+
+def test_probe_library_apart_from_the_step_abi(lib):
+    # the measurement probes live in their own library and header
+    assert not hasattr(lib, "ader_probe_peak")
+    probe = ader.load_probe()
+    v = ctypes.c_double()
+    assert probe.ader_probe_peak(0, 3, ctypes.byref(v)) == ader.ADER_EINVAL
+    assert probe.ader_probe_peak(0, 0, None) == ader.ADER_EINVAL
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -27,7 +27,8 @@ def _states(shapes, mhd=False):
     out = []
     for i, s in enumerate(shapes):
         if mhd:
-            out.append(workloads.mhd_random_field(s, seed=100 + i))
+            # P = 1: the small meshes stay positive under the paper's scheme
+            out.append(workloads.mhd_random_field(s, seed=100 + i, p0=1.0))
         else:
             out.append((workloads.random_smooth(s, seed=100 + i), None))
     return out
@@ -186,7 +187,7 @@ def test_graph_follows_mhd_two_kernel_layout_buffers():
     # precision in use; order and precision changes grow it under the graph
     G53 = 5.0 / 3.0
     shape = (7, 8, 9)
-    U0, B0 = workloads.mhd_random_field(shape, seed=33)
+    U0, B0 = workloads.mhd_random_field(shape, seed=33, p0=1.0)
     stream = torch.cuda.Stream()
     seq = [(3, ader.ADER_MIXED), (4, ader.ADER_MIXED), (4, ader.ADER_FP64), (3, ader.ADER_FP64)]
     kw = dict(gamma=G53, system=ader.ADER_MHD, order=3)
@@ -207,6 +208,44 @@ def test_graph_follows_mhd_two_kernel_layout_buffers():
             g.synchronize()
             (Ue, Be), (Ug, Bg) = e.get_state(), g.get_state()
             assert np.array_equal(Ug, Ue) and np.array_equal(Bg, Be), (order, prec)
+
+
+def test_batch_positivity_per_problem():
+    # a smooth problem and a 1000:1 blast in one batch: the limit mode scales
+    # zones of the blast only (counted per problem) and equals the solo runs
+    # bit for bit; the check mode reports the blast's non-positive check
+    # points as ADER_ESTATE from the batched step
+    shapes = [(9, 8, 7), (12, 12, 12)]
+    states = [workloads.random_smooth(shapes[0], seed=7),
+              workloads.blast(shapes[1], p_in=100.0, p_out=0.1, radius=0.25)]
+    solo = []
+    for sh, U0 in zip(shapes, states):
+        with ader.Solver(sh, positivity=ader.ADER_POSITIVITY_LIMIT) as s:
+            s.set_state(U0)
+            for _ in range(2):
+                s.step_cfl(0.3)
+            solo.append(s.get_state())
+    stream = torch.cuda.Stream()
+    with ader.BatchSolver(shapes, stream=stream.cuda_stream,
+                          positivity=ader.ADER_POSITIVITY_LIMIT) as b:
+        ader.ader_set_graph(b.ctx, True)
+        for q, U0 in enumerate(states):
+            b.set_state(q, U0)
+        for it in range(2):
+            say("batch positivity limit step", it)
+            b.step_cfl(0.3, want_dts=True)
+        counts = b.limited_zones()
+        assert counts[0] == 0 and counts[1] > 0, counts
+        for q in range(2):
+            assert np.array_equal(b.get_state(q), solo[q]), q
+    with ader.BatchSolver(shapes) as b:
+        for q, U0 in enumerate(states):
+            b.set_state(q, U0)
+        say("batch positivity check")
+        with pytest.raises(ader.AderError) as e:
+            for _ in range(3):
+                b.step_cfl(0.3, want_dts=True)
+        assert e.value.code == ader.ADER_ESTATE
 
 
 def test_graph_needs_a_stream():

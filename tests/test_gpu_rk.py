@@ -30,24 +30,51 @@ def _rk_solver(shape, order, rs, precision=ader.ADER_FP64, lengths=(1.0, 1.0, 1.
     return s
 
 
+POS = {"check": ader.ADER_POSITIVITY_CHECK, "limit": ader.ADER_POSITIVITY_LIMIT}
+
+
+def _flagged(s):
+    try:
+        s.synchronize()
+    except ader.AderError as e:
+        if e.code != ader.ADER_ESTATE:
+            raise
+        return True
+    return False
+
+
 @pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("order", [2, 3, 4])
 def test_rk_parity_smooth_and_blast(order, rs):
-    for tag, U0, lengths in (
-            ("smooth", workloads.random_smooth((9, 14, 21), seed=order + 30), (1.0, 0.8, 1.3)),
-            ("blast", workloads.blast((12, 12, 12), p_in=100.0, p_out=0.1, radius=0.25),
-             (1.0, 1.0, 1.0))):
-        cfg = OracleConfig(order=order, riemann=rs, lengths=lengths)
-        with _rk_solver(U0.shape[1:], order, rs, lengths=lengths) as s:
+    # smooth ragged mesh (check mode); a 1000:1 blast in the limit mode (the
+    # spatial scaling acts) and in the check mode (a report from both sides
+    # at the same step)
+    from oracle.positivity import NonPhysical
+    blast = workloads.blast((12, 12, 12), p_in=100.0, p_out=0.1, radius=0.25)
+    for tag, U0, lengths, pos in (
+            ("smooth", workloads.random_smooth((9, 14, 21), seed=order + 30), (1.0, 0.8, 1.3),
+             "check"),
+            ("blast", blast, (1.0, 1.0, 1.0), "limit"),
+            ("blast", blast, (1.0, 1.0, 1.0), "check")):
+        cfg = OracleConfig(order=order, riemann=rs, lengths=lengths, positivity=pos)
+        with _rk_solver(U0.shape[1:], order, rs, lengths=lengths, positivity=POS[pos]) as s:
             assert ader.ader_get_scheme(s.ctx) == ader.ADER_SCHEME_SSPRK
             s.set_state(U0)
             U = U0
             for it in range(2):
-                say("rk", tag, order, rs, "step", it)
+                say("rk", tag, pos, order, rs, "step", it)
                 dt = s.compute_dt(0.3)
                 s.step(dt)
+                flagged = _flagged(s)
+                try:
+                    Uo = ork.step_rk(U, dt, cfg)
+                except NonPhysical:
+                    Uo = None
+                assert flagged == (Uo is None), (tag, pos, it)
+                if flagged:
+                    break
                 Ug = s.get_state()
-                err = rel_l1(Ug, ork.step_rk(U, dt, cfg))
+                err = rel_l1(Ug, Uo)
                 assert np.all(err <= TOL_FP64), (tag, it, err)
                 U = Ug
 
@@ -93,17 +120,21 @@ def test_rk_batch_graph_and_errors():
         assert ader.load().ader_set_scheme(s.ctx, 5) == ader.ADER_EINVAL
 
 
+@pytest.mark.parametrize("positivity,p0", [("check", 1.0), ("limit", 0.1)])
 @pytest.mark.parametrize("rs", ["hll", "linearized"])
 @pytest.mark.parametrize("order", [2, 3, 4])
-def test_rk_mhd_parity_and_div_b(order, rs):
+def test_rk_mhd_parity_and_div_b(order, rs, positivity, p0):
+    # (the small random field at P = 0.1 needs the limit mode; the paper's
+    # scheme runs it at P = 1)
     from oracle.bweno import divergence
     G53 = 5.0 / 3.0
-    U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order + 60)
+    U0, B0 = workloads.mhd_random_field((7, 9, 10), seed=order + 60, p0=p0)
     lengths = (1.0, 0.9, 1.2)
-    cfg = OracleConfig(order=order, gamma=G53, riemann=rs, lengths=lengths)
+    cfg = OracleConfig(order=order, gamma=G53, riemann=rs, lengths=lengths,
+                       positivity=positivity)
     for prec, tol in ((ader.ADER_FP64, TOL_FP64), (ader.ADER_MIXED, 1e-6)):
         with _rk_solver((7, 9, 10), order, rs, precision=prec, lengths=lengths, gamma=G53,
-                        system=ader.ADER_MHD) as s:
+                        system=ader.ADER_MHD, positivity=POS[positivity]) as s:
             s.set_state(U0, B0)
             U, B = U0, B0
             for it in range(2):

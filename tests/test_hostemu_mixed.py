@@ -52,14 +52,20 @@ def test_mixed_conserves_and_keeps_constant_states():
 
 @pytest.mark.parametrize("order", [3, 4])
 def test_mixed_blast_stays_physical(order):
+    # the limit mode (opt-in safeguard) keeps the mixed path physical on a
+    # strong blast; the check mode reports it
     U = workloads.blast((10, 10, 10), p_in=100.0, p_out=0.1, radius=0.25)
     for _ in range(4):
         dt = hostemu.compute_dt(U, 0.3)
         assert dt > 0
-        U = hostemu.step(U, dt, order, precision="mixed")
+        U = hostemu.step(U, dt, order, precision="mixed", positivity="limit")
     rho = U[0]
     p = 0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / rho)
     assert np.all(np.isfinite(U)) and rho.min() > 0 and p.min() > 0
+    with pytest.raises(hostemu.NonPhysical):
+        V = workloads.blast((10, 10, 10), p_in=100.0, p_out=0.1, radius=0.25)
+        for _ in range(4):
+            V = hostemu.step(V, hostemu.compute_dt(V, 0.3), order, precision="mixed")
 
 
 @pytest.mark.parametrize("order", [2, 3, 4])
