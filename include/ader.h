@@ -209,6 +209,18 @@ int ader_device_bytes(ader_ctx* ctx, double* bytes_out);
  * (ADER_ENOMEM if that fails); ADER_ESEQ before a state is set. */
 int ader_diagnostics(ader_ctx* ctx, double* totals, double* max_abs_divB);
 
+/* ader_diagnostics for callers that cannot allocate device memory (code
+ * under stream capture, serving loops, harnesses that forbid hipMalloc):
+ * the same results, bit for bit, from the same kernels, with their scratch
+ * in a fixed array of the library (1.47 MB per device, held until the
+ * process ends) instead of an allocation; it calls no allocating routine.
+ * Limits: at most 16384 reduction tiles of 8192 zones (134 M zones over the
+ * context) and 4096 problems, else ADER_EINVAL.  Every call on a device
+ * shares that device's array, so calls that overlap on one device (other
+ * host threads, other contexts' streams) race; calls in sequence do not.
+ * ADER_ESEQ before a state is set. */
+int ader_diagnostics_noalloc(ader_ctx* ctx, double* totals, double* max_abs_divB);
+
 /* Static description of an error code. */
 const char* ader_strerror(int code);
 

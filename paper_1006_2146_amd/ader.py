@@ -35,6 +35,7 @@ EXPORTS = [
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
+    "ader_diagnostics_noalloc",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
@@ -112,6 +113,7 @@ def load():
         "ader_get_positivity": ([P, ctypes.POINTER(I)], I),
         "ader_limited_zones": ([P, ctypes.POINTER(ctypes.c_longlong)], I),
         "ader_diagnostics": ([P, DP, DP], I),
+        "ader_diagnostics_noalloc": ([P, DP, DP], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -262,6 +264,15 @@ def ader_diagnostics(ctx, n=1):
     tot = np.empty((n, 8), dtype=np.float64)
     div = np.empty(n, dtype=np.float64)
     _check(load().ader_diagnostics(ctx, _dptr(tot), _dptr(div)), "ader_diagnostics")
+    return tot, div
+
+
+def ader_diagnostics_noalloc(ctx, n=1):
+    """ader_diagnostics with the library's fixed scratch (no allocation)."""
+    tot = np.empty((n, 8), dtype=np.float64)
+    div = np.empty(n, dtype=np.float64)
+    _check(load().ader_diagnostics_noalloc(ctx, _dptr(tot), _dptr(div)),
+           "ader_diagnostics_noalloc")
     return tot, div
 
 

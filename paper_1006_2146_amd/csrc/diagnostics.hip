@@ -12,6 +12,8 @@
 // nor on timing.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ader_ctx.h"
 #include "recon_tile.h"
 
@@ -138,6 +140,41 @@ int diagnostics_into(ader_ctx* c, double* partial, double* d_totals, double* d_m
   return check(hipStreamSynchronize(c->stream));
 }
 
+// Scratch of ader_diagnostics_noalloc: the partial rows of at most
+// kStaticTiles tiles (134 M zones in tiles of 8192) and the results of at
+// most kStaticProblems problems, 1.47 MB on every device the library runs
+// this entry point on, held until the process ends.  Host code never passes
+// `scratch` itself to a kernel or a copy: it stands in for the device copy
+// only on the device side; its device address comes from
+// hipGetSymbolAddress, per device.
+constexpr long long kStaticTiles = 16384;
+constexpr int kStaticProblems = 4096;
+static __device__ __align__(256) double
+    scratch[(kStaticTiles + kStaticProblems) * kDiagVals];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up once per device.
+int static_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return ADER_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return ADER_EDEVICE;
+    }
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return ADER_OK;
+}
+
 }  // namespace ader
 
 using namespace ader;
@@ -159,5 +196,19 @@ extern "C" int ader_diagnostics(ader_ctx* c, double* totals, double* max_abs_div
   }
   double* d_tot = c->d_diag + (size_t)c->ndiag_tiles * kDiagVals;
   return diagnostics_into(c, c->d_diag, d_tot, d_tot + (size_t)c->np() * (kDiagVals - 1), totals,
+                          max_abs_divB);
+}
+
+extern "C" int ader_diagnostics_noalloc(ader_ctx* c, double* totals, double* max_abs_divB) {
+  if (!c) return ADER_EINVAL;
+  if (c->ndiag_tiles > kStaticTiles || c->np() > kStaticProblems) return ADER_EINVAL;
+  if (!c->have_state) return ADER_ESEQ;
+  ADER_TRY(check(hipSetDevice(c->device)));
+  double* p = nullptr;
+  ADER_TRY(static_scratch(c->device, &p));
+  // every partial row and result is written before it is read: nothing to
+  // clear between calls
+  double* d_tot = p + (size_t)kStaticTiles * kDiagVals;
+  return diagnostics_into(c, p, d_tot, d_tot + (size_t)kStaticProblems * (kDiagVals - 1), totals,
                           max_abs_divB);
 }
