@@ -117,6 +117,21 @@ int ader_get_scheme(ader_ctx* ctx, int* scheme_out);
  * bit-identical to the check mode.  The same applies to SSP-RK stages
  * (spatial polynomial only).  ADER_EINVAL for another mode. */
 enum { ADER_POSITIVITY_CHECK = 0, ADER_POSITIVITY_LIMIT = 1 };
+/* Non-stiff source term of the Euler equations, Sec. IV (source modes and
+ * their space-time average: eq. 34-35 at second order, 43-44 at third,
+ * 52-53 at fourth) and App. A-C in the nodal form (A.7, B.6, C.6): an
+ * affine source S(u) = A u + b of the conserved
+ * variables (rho, rho vx, rho vy, rho vz, E), applied to every problem of
+ * the context.  A is row-major 5 x 5 (S_v = sum_w A[5 v + w] u_w + b_v), b
+ * has 5 entries (NULL: zero); both are host arrays, copied.  The predictor
+ * carries S at its space-time nodes, and eq. (6) adds dt times the
+ * space-time average of S over the zone from the predictor's polynomial.
+ * A = NULL (with b NULL) removes the source.  While a source is set the
+ * predictor runs one lane per zone at orders 2 and 3 and one lane per zone
+ * and variable at order 4, whatever layout is set, and the SSP-RK
+ * scheme's step returns ADER_EUNSUPPORTED.  ADER_EUNSUPPORTED on an MHD
+ * context; ADER_EINVAL for a non-finite entry or b without A. */
+int ader_set_source(ader_ctx* ctx, const double* A, const double* b);
 int ader_set_positivity(ader_ctx* ctx, int mode);
 int ader_get_positivity(ader_ctx* ctx, int* mode_out);
 

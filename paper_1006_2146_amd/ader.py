@@ -35,7 +35,7 @@ EXPORTS = [
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
-    "ader_diagnostics_noalloc",
+    "ader_diagnostics_noalloc", "ader_set_source",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
@@ -114,6 +114,7 @@ def load():
         "ader_limited_zones": ([P, ctypes.POINTER(ctypes.c_longlong)], I),
         "ader_diagnostics": ([P, DP, DP], I),
         "ader_diagnostics_noalloc": ([P, DP, DP], I),
+        "ader_set_source": ([P, DP, DP], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -265,6 +266,18 @@ def ader_diagnostics(ctx, n=1):
     div = np.empty(n, dtype=np.float64)
     _check(load().ader_diagnostics(ctx, _dptr(tot), _dptr(div)), "ader_diagnostics")
     return tot, div
+
+
+def ader_set_source(ctx, A=None, b=None):
+    """The affine source S(u) = A u + b (A 5 x 5, b 5 or None); A None
+    removes it."""
+    if A is None:
+        _check(load().ader_set_source(ctx, None, None), "ader_set_source")
+        return
+    A = np.ascontiguousarray(A, dtype=np.float64).reshape(25)
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64).reshape(5)
+    _check(load().ader_set_source(ctx, _dptr(A), None if bb is None else _dptr(bb)),
+           "ader_set_source")
 
 
 def ader_diagnostics_noalloc(ctx, n=1):
@@ -444,6 +457,9 @@ class BatchSolver:
     def limited_zones(self):
         return ader_limited_zones(self.ctx, len(self))
 
+    def set_source(self, A=None, b=None):
+        ader_set_source(self.ctx, A, b)
+
     def diagnostics(self):
         return ader_diagnostics(self.ctx, len(self))
 
@@ -505,6 +521,9 @@ class Solver:
 
     def limited_zones(self):
         return ader_limited_zones(self.ctx)[0]
+
+    def set_source(self, A=None, b=None):
+        ader_set_source(self.ctx, A, b)
 
     def diagnostics(self):
         """(totals[8], max |div B|) of the current state."""

@@ -141,6 +141,7 @@ struct ader_ctx {
   // affine source term (Euler): S(u) = A u + b, and dt S-bar per zone [5][S]
   bool has_source = false;
   ader::SourceAffine source{};
+  unsigned long long source_version = 0;   // bumped on every ader_set_source
   double* SB = nullptr;
   // diagnostics: problem p's reduction tiles at diag_base[p] ..
   // diag_base[p+1]-1, and the partial rows and results (allocated on first

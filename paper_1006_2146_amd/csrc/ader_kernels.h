@@ -193,6 +193,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   });
 }
 
+// the lane-split predictor with the affine source term; dt S-bar to SB
+template <class T, int ORDER, int FORM>
+__global__ void __launch_bounds__(256) k_predict_split_src(const double* __restrict__ U,
+                                                           const T* __restrict__ W,
+                                                           T* __restrict__ PK, Batch b,
+                                                           const double* __restrict__ dt,
+                                                           double gam, PosCtl pc,
+                                                           SourceAffine src,
+                                                           double* __restrict__ SB) {
+  for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
+    predict_zone_split<T, ORDER, FORM, kDeviation<T>, true>(L, U, W, PK, grid_of(pr, b), dt[p],
+                                                            1.0 / pr.dx, 1.0 / pr.dy,
+                                                            1.0 / pr.dz, gam, pc.at(p), n, &src,
+                                                            SB);
+  });
+}
+
 template <class T, int ORDER, int FORM, int WAVES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_mhd_split(
     const double* __restrict__ U, const T* __restrict__ W, const double* __restrict__ B0,

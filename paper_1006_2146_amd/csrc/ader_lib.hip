@@ -103,6 +103,8 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
 }
 
 int layout_of(const ader_ctx* c, const StageFns* s) {
+  // the source instances: one lane per zone at orders 2 and 3, lane-split at 4
+  if (c->has_source) return c->order == 4 ? ADER_LAYOUT_SPLIT : ADER_LAYOUT_ZONE;
   if (c->layout >= 0 && layout_built(c, s, c->layout)) return c->layout;
   if (s->predict_pair && c->system == ADER_MHD) return ADER_LAYOUT_PAIR;
   if (s->predict_pair_split && c->system == ADER_MHD) return ADER_LAYOUT_PAIR_SPLIT;
@@ -111,6 +113,7 @@ int layout_of(const ader_ctx* c, const StageFns* s) {
 }
 
 int queue_predict(ader_ctx* c, const StageFns* s) {
+  if (c->has_source) return s->predict_src ? s->predict_src(c) : ADER_EUNSUPPORTED;
   switch (layout_of(c, s)) {
     case ADER_LAYOUT_SPLIT: return s->predict_split(c);
     case ADER_LAYOUT_SPLIT2: return s->predict_split2(c);
@@ -121,6 +124,11 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split(c);
     default: return s->predict(c);
   }
+}
+
+int queue_update(ader_ctx* c, const StageFns* s) {
+  if (c->has_source) return s->update_src ? s->update_src(c) : ADER_EUNSUPPORTED;
+  return s->update(c);
 }
 
 // SSP-RK weights of eq. (18), (19) and (20), one row per stage: U <- a_n Un
@@ -203,7 +211,8 @@ int queue_rk_step(ader_ctx* c, const StageFns* s) {
 int queue_step(ader_ctx* c) {
   const StageFns* s = stages_of(c);
   if (!s) return ADER_EUNSUPPORTED;
-  if (c->scheme == ADER_SCHEME_SSPRK) return queue_rk_step(c, s);
+  if (c->scheme == ADER_SCHEME_SSPRK)
+    return c->has_source ? ADER_EUNSUPPORTED : queue_rk_step(c, s);
   {
     StageTimer t(c, ADER_STAGE_RECON);
     ADER_TRY(s->recon(c));
@@ -217,7 +226,7 @@ int queue_step(ader_ctx* c) {
     ADER_TRY(s->flux(c));
   }
   StageTimer t(c, ADER_STAGE_UPDATE);
-  return s->update(c);
+  return queue_update(c, s);
 }
 
 void drop_graph(ader_ctx* c);
@@ -237,13 +246,15 @@ int ensure_work(ader_ctx* c) {
   // the step will run (set explicitly or the default of the setting)
   const StageFns* st = stages_of(c);
   const bool split = mhd && c->order >= 3 && st && layout_of(c, st) == ADER_LAYOUT_PAIR_SPLIT;
-  const size_t need[7] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
+  const size_t need[8] = {t * (ls - 1) * 5 * Z, t * 6 * (mhd ? kMhdSlots : 15) * Z,
                           mhd ? t * (ls - 1) * 3 * Z : 0, mhd ? t * 3 * 3 * Z : 0,
                           c->scheme == ADER_SCHEME_SSPRK ? sizeof(double) * 4 * (mhd ? 8 : 5) * Z
                                                          : 0,
-                          split ? t * ne * 8 * Z : 0, split ? sizeof(double) * 2 * Z : 0};
-  void** buf[7] = {&c->W, &c->PK, &c->WB, &c->BN, (void**)&c->RK, &c->EM, (void**)&c->TH};
-  for (int q = 0; q < 7; ++q) {
+                          split ? t * ne * 8 * Z : 0, split ? sizeof(double) * 2 * Z : 0,
+                          c->has_source ? sizeof(double) * 5 * Z : 0};
+  void** buf[8] = {&c->W,  &c->PK, &c->WB,           &c->BN, (void**)&c->RK,
+                   &c->EM, (void**)&c->TH, (void**)&c->SB};
+  for (int q = 0; q < 8; ++q) {
     if (need[q] <= c->work_bytes[q]) continue;
     if (*buf[q]) {
       // a captured step holds the old address: rebuild it on its next use
@@ -277,12 +288,14 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)(c->recon_mode + 1);
   k = k * 3 + (unsigned long long)c->scheme;
   k = k * 3 + (unsigned long long)c->positivity;
+  k = k * 1000003 + c->source_version;
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
   k ^= (unsigned long long)(uintptr_t)c->B * 0xc2b2ae3d27d4eb4full;
   k ^= (unsigned long long)(uintptr_t)c->W * 0xd6e8feb86659fd93ull;
   k ^= (unsigned long long)(uintptr_t)c->PK * 0xa0761d6478bd642full;
+  k ^= (unsigned long long)(uintptr_t)c->SB * 0xe7037ed1a0b428dbull;
   unsigned long long g;
   std::memcpy(&g, &c->gamma, sizeof g);
   return k ^ (g * 0x165667b19e3779f9ull);
@@ -383,7 +396,7 @@ void free_buffers(ader_ctx* c) {
   if (c->owns_U && c->U) (void)hipFree(c->U);
   if (c->owns_B && c->B) (void)hipFree(c->B);
   for (void* p : {(void*)c->B0, c->WB, c->BN, (void*)c->FE, (void*)c->E, c->W, c->PK, (void*)c->F,
-                  (void*)c->RK, c->EM, (void*)c->TH,
+                  (void*)c->RK, c->EM, (void*)c->TH, (void*)c->SB,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_limited,
                   (void*)c->d_probs,
                   (void*)c->d_tile_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
@@ -560,7 +573,7 @@ int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
       case kClassRecon: rc = s->recon(c); break;
       case kClassPredict: rc = queue_predict(c, s); break;
       case kClassFlux: rc = s->flux(c); break;
-      default: rc = s->update(c); break;
+      default: rc = queue_update(c, s); break;
     }
   }
   if (rc == ADER_OK) rc = check(hipEventRecord(e1, c->stream));
@@ -893,6 +906,32 @@ int ader_get_scheme(ader_ctx* c, int* scheme_out) {
 int ader_set_positivity(ader_ctx* c, int mode) {
   if (!c || (mode != ADER_POSITIVITY_CHECK && mode != ADER_POSITIVITY_LIMIT)) return ADER_EINVAL;
   c->positivity = mode;
+  return ADER_OK;
+}
+
+int ader_set_source(ader_ctx* c, const double* A, const double* b) {
+  if (!c) return ADER_EINVAL;
+  if (c->system == ADER_MHD) return ADER_EUNSUPPORTED;
+  if (!A) {
+    if (b) return ADER_EINVAL;
+    c->has_source = false;
+    c->source = SourceAffine{};
+    ++c->source_version;
+    return ADER_OK;
+  }
+  SourceAffine s{};
+  for (int q = 0; q < 25; ++q) {
+    if (!std::isfinite(A[q])) return ADER_EINVAL;
+    s.A[q] = A[q];
+  }
+  for (int v = 0; v < 5; ++v) {
+    const double bv = b ? b[v] : 0.0;
+    if (!std::isfinite(bv)) return ADER_EINVAL;
+    s.b[v] = bv;
+  }
+  c->source = s;
+  c->has_source = true;
+  ++c->source_version;
   return ADER_OK;
 }
 

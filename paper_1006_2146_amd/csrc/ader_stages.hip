@@ -228,16 +228,26 @@ int update(ader_ctx* c) {
   return launched();
 }
 
-// Euler with the affine source term: the one-lane-per-zone predictor writing
-// dt S-bar, and the update adding it
+// Euler with the affine source term: the predictor writing dt S-bar (one
+// lane per zone at orders 2 and 3, the lane-split layout at order 4), and
+// the update adding it.  (A one-lane-per-zone order-4 instance, which
+// spills about 1.8 KB per lane, gave wrong results on the GPU once the
+// limit mode's scaling acted while its host build agreed with the oracle;
+// it is not built.)
 int predict_src(ader_ctx* c) {
   if constexpr (!kMhd) {
     if (!c->SB) return ADER_ESEQ;
-    const unsigned g = grid_for(c, kClassPredict);
     const int bs = c->shape[kClassPredict].block;
-    k_predict_src<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(
-        c->U, static_cast<const T*>(c->W), static_cast<T*>(c->PK), c->batch(), c->d_dt, c->gamma,
-        c->pos(), c->source, c->SB);
+    const T* W = static_cast<const T*>(c->W);
+    T* PK = static_cast<T*>(c->PK);
+    if constexpr (kOrder <= 3) {
+      k_predict_src<T, kOrder, kForm><<<grid_for(c, kClassPredict), bs, 0, c->stream>>>(
+          c->U, W, PK, c->batch(), c->d_dt, c->gamma, c->pos(), c->source, c->SB);
+    } else {
+      k_predict_split_src<T, kOrder, kForm><<<grid_for(c, kClassPredict, 64 / 5), bs, 0,
+                                              c->stream>>>(
+          c->U, W, PK, c->batch(), c->d_dt, c->gamma, c->pos(), c->source, c->SB);
+    }
     return launched();
   } else {
     return ADER_EUNSUPPORTED;

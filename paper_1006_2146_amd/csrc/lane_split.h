@@ -82,6 +82,52 @@ struct SplitScan {
   }
 };
 
+// Affine source of the lane-split layout: gathers the zone's state at a
+// node, forms the whole dt S (point or deviation form) and returns this
+// lane's component; base is this lane's component of dt S(zone average),
+// which the deviation form's constant source mode takes.
+template <class T, bool DEV>
+struct SplitSrc {
+  static constexpr bool kActive = true;
+  AffineSrc<T, DEV> inner;
+  SplitLane L;
+  T base[1];
+  __device__ SplitSrc(const SourceAffine& s, double dt, const double (&w0)[5], const SplitLane& l)
+      : inner(s, dt, w0), L(l) {
+    base[0] = pick(L, inner.base);
+  }
+  __device__ void operator()(const T (&u)[1], T (&out)[1]) const {
+    T full[5], o[5];
+    gather(L, u[0], full);
+    inner(full, o);
+    out[0] = pick(L, o);
+  }
+};
+
+// dt (A mean + b) of this lane's variable from the zone's final modes (the
+// means of the five lanes gathered); written to SB row L.var at n.
+template <class S, class T>
+__device__ __forceinline__ void store_source_average_split(const SplitLane& L,
+                                                           const SourceAffine& src, double dt,
+                                                           const double (&w0)[5],
+                                                           const T (&e)[S::NE][1],
+                                                           double* __restrict__ SB, long long N,
+                                                           long long n) {
+  double own[1];
+  S::mean_dev(e, own);
+  double m[5];
+  gather(L, own[0], m);
+  double a = 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double r = src.b[v];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) r += src.A[v * 5 + k] * (w0[k] + m[k]);
+    a = L.var == v ? r : a;
+  }
+  SB[(long long)L.var * N + n] = dt * a;
+}
+
 // (NoScan: in this layout the facial check set is scanned on its own before
 // the sides are formed, which keeps the register use of the side code low.)
 
@@ -135,13 +181,17 @@ __device__ double theta_facial_split(const SplitLane& L, const double (&w0)[NV],
   return acc.result();
 }
 
-// The same operations as predict_zone (Euler), in the lane-split layout.
-template <class T, int ORDER, int FORM, bool DEV>
+// The same operations as predict_zone (Euler), in the lane-split layout;
+// SRC: with the affine source *src, whose dt-scaled space-time average goes
+// to SB (rows of 5 doubles).
+template <class T, int ORDER, int FORM, bool DEV, bool SRC = false>
 __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const double* __restrict__ U,
                                                    const T* __restrict__ W, T* __restrict__ PK,
                                                    const Grid& g, double h, double inv_dx,
                                                    double inv_dy, double inv_dz, double gam,
-                                                   PosCtl pc, long long n) {
+                                                   PosCtl pc, long long n,
+                                                   const SourceAffine* src = nullptr,
+                                                   double* __restrict__ SB = nullptr) {
   using S = typename SchemeOf<ORDER, FORM, T, 1>::type;
   constexpr int LS = S::LS, NE = S::NE;
   double w0[5];
@@ -164,7 +214,11 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
   }
   const SplitFlux<Euler<T>, T, DEV> ph{FluxOf<Euler<T>, T, DEV>::make(w0, gam), L};
   T e[NE][1];
-  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  if constexpr (SRC)
+    S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph,
+               SplitSrc<T, DEV>(*src, h, w0, L));
+  else
+    S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
   {
     SplitScan<T, 5, DEV> scan{PosScan<T, 5, DEV>(w0), L};
     S::facial_points(w, e, scan);
@@ -194,6 +248,8 @@ __device__ __forceinline__ void predict_zone_split(const SplitLane& L, const dou
   side(std::integral_constant<int, 3>{});
   side(std::integral_constant<int, 4>{});
   side(std::integral_constant<int, 5>{});
+  // the source term of eq. (6) from the final (possibly scaled) polynomial
+  if constexpr (SRC) store_source_average_split<S, T>(L, *src, h, w0, e, SB, g.S, n);
 }
 
 // The same operations as predict_zone_mhd, in the lane-split layout.

@@ -52,6 +52,8 @@ def load():
         lib.hostemu_mhd_dissipation.argtypes = [DP, DP, DP, I, D, DP]
         lib.hostemu_dt_mhd.argtypes = [DP, DP, I, I, I, D, D, D, D, D]
         lib.hostemu_dt_mhd.restype = D
+        lib.hostemu_set_source.argtypes = [DP, DP]
+        lib.hostemu_set_source.restype = None
         lib.hostemu_set_positivity.argtypes = [I]
         lib.hostemu_set_positivity.restype = None
         lib.hostemu_pos_status.argtypes = [ctypes.POINTER(I), ctypes.POINTER(ctypes.c_uint)]
@@ -91,13 +93,22 @@ def _spacing(U, lengths):
 
 
 def step(U, dt, order, form="modal", riemann="hll", precision="fp64",
-         lengths=(1.0, 1.0, 1.0), gamma=1.4, positivity="check"):
+         lengths=(1.0, 1.0, 1.0), gamma=1.4, positivity="check", source=None):
+    """One ADER step; ``source`` = (A, b) adds the affine source A u + b."""
     out = np.ascontiguousarray(U, dtype=np.float64).copy()
     nx, ny, nz, dx, dy, dz = _spacing(out, lengths)
     _begin(positivity)
-    load().hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
-                        dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
-                        1 if riemann == "linearized" else 0, PRECISION[precision], dt)
+    lib = load()
+    if source is not None:
+        A = np.ascontiguousarray(source[0], dtype=np.float64).reshape(25)
+        b = np.ascontiguousarray(source[1], dtype=np.float64).reshape(5)
+        lib.hostemu_set_source(_dp(A), _dp(b))
+    try:
+        lib.hostemu_step(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nx, ny, nz,
+                         dx, dy, dz, gamma, order, 1 if form == "nodal" else 0,
+                         1 if riemann == "linearized" else 0, PRECISION[precision], dt)
+    finally:
+        lib.hostemu_set_source(None, None)
     _end()
     return out
 

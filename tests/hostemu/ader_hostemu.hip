@@ -18,11 +18,25 @@ static int g_limit = 0, g_bad = 0;
 static unsigned int g_limited = 0;
 static PosCtl emu_pc() { return PosCtl{g_limit, &g_bad, &g_limited}; }
 
+// The affine source term of the host build (hostemu_set_source).
+static bool g_has_src = false;
+static SourceAffine g_src{};
+
+template <class T, int ORDER, int FORM, bool DEV>
+static void emu_predict(const double* U, const T* W, T* PK, double* SB, const Grid& g, double dt,
+                        double ix, double iy, double iz, double gam, long long n) {
+  if (g_has_src)
+    predict_zone<T, ORDER, FORM, DEV, true, true>(U, W, PK, g, dt, ix, iy, iz, gam, emu_pc(), n,
+                                                  &g_src, SB);
+  else
+    predict_zone<T, ORDER, FORM, DEV>(U, W, PK, g, dt, ix, iy, iz, gam, emu_pc(), n);
+}
+
 template <class T, bool DEV>
 static void emu_step(double* U, Grid g, double dx, double dy, double dz, double gam, int order,
                      int form, int riemann, double dt) {
   std::vector<T> W((size_t)19 * 5 * g.N), PK((size_t)90 * g.N);
-  std::vector<double> F((size_t)15 * g.N);
+  std::vector<double> F((size_t)15 * g.N), SB(g_has_src ? (size_t)5 * g.N : 0);
   const long long N = g.N;
   if (order == 2) {
     for (long long n = 0; n < N; ++n) minmod_zone<T>(U, W.data(), g, n);
@@ -37,18 +51,21 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
   }
   const double ix = 1.0 / dx, iy = 1.0 / dy, iz = 1.0 / dz;
   for (long long n = 0; n < N; ++n) {
+    const T* w = W.data();
+    T* pk = PK.data();
+    double* sb = SB.data();
     if (order == 2 && form == 1)
-      predict_zone<T, 2, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 2, 1, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
     else if (order == 2)
-      predict_zone<T, 2, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 2, 0, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
     else if (order == 3 && form == 1)
-      predict_zone<T, 3, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 3, 1, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
     else if (order == 4 && form == 1)
-      predict_zone<T, 4, 1, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 4, 1, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
     else if (order == 3)
-      predict_zone<T, 3, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 3, 0, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
     else
-      predict_zone<T, 4, 0, DEV>(U, W.data(), PK.data(), g, dt, ix, iy, iz, gam, emu_pc(), n);
+      emu_predict<T, 4, 0, DEV>(U, w, pk, sb, g, dt, ix, iy, iz, gam, n);
   }
   for (long long n = 0; n < N; ++n) {
     if (riemann == 0)
@@ -56,7 +73,10 @@ static void emu_step(double* U, Grid g, double dx, double dy, double dz, double 
     else
       face_flux_zone<T, 1, DEV>(U, PK.data(), F.data(), g, gam, n);
   }
-  for (long long n = 0; n < N; ++n) update_zone(U, F.data(), g, dt, dx, dy, dz, n);
+  for (long long n = 0; n < N; ++n) {
+    update_zone(U, F.data(), g, dt, dx, dy, dz, n);
+    if (g_has_src) source_zone(U, SB.data(), g, n);
+  }
 }
 
 // One SSP-RK step (Sec. II.d) of the Euler equations from the RK kernels'
@@ -337,6 +357,16 @@ int hostemu_step_rk(double* U, int nx, int ny, int nz, double dx, double dy, dou
   else
     emu_rk_step<double, true>(U, g, dx, dy, dz, gam, order, riemann, dt);
   return 0;
+}
+
+// The affine source S(u) = A u + b of the next Euler steps (A row-major 5 x
+// 5, b 5 entries or NULL); A NULL removes it.
+void hostemu_set_source(const double* A, const double* b) {
+  g_has_src = A != nullptr;
+  g_src = SourceAffine{};
+  if (!A) return;
+  for (int q = 0; q < 25; ++q) g_src.A[q] = A[q];
+  for (int v = 0; v < 5; ++v) g_src.b[v] = b ? b[v] : 0.0;
 }
 
 // dt of the host build; returns -1 if a zone is unphysical.
