@@ -43,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per zone-update: the FP64 state read once and
 # written once (Euler 5, MHD 8 variables)
 STATE_BYTES_PER_ZONE = {"euler": 80, "mhd": 128}
-RECON_NAMES = ["sweeps", "tiled", "columns"]
+RECON_NAMES = ["sweeps", "tiled", "columns", "march"]
 LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves",
-                5: "pair", 6: "pair-2waves", 7: "pair-2kernels"}
+                5: "pair", 6: "pair-2waves", 7: "pair-2kernels", 8: "fused-recon"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
 ENSEMBLE_WORKLOAD = ("ensemble-64-uneven: 64 periodic unit-box Euler problems, sides drawn from "
                      "{32,48,64,96} per axis (seed 4096), smooth random modes, gamma 1.4; "
@@ -592,7 +592,9 @@ PREDICT_KERNELS = {("f32", "zone"): "k_predict<float,3,0,true,1>",
                    ("f64", "zone-prescan"): "k_predict<double,3,0,false,1>",
                    ("f64", "zone-2waves"): "k_predict<double,3,0,true,2>",
                    ("f64", "split"): "k_predict_split<double,3,0,1>",
-                   ("f64", "split-2waves"): "k_predict_split<double,3,0,2>"}
+                   ("f64", "split-2waves"): "k_predict_split<double,3,0,2>",
+                   ("f32", "fused-recon"): "k_recon_predict<float,3,0,4>",
+                   ("f64", "fused-recon"): "k_recon_predict<double,3,0,4>"}
 
 
 def roofline_of(run, zones, dtype):
@@ -616,7 +618,10 @@ def roofline_of(run, zones, dtype):
             "traffic_unit": "HBM bytes per launch (PMC FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "flops_per_zone": flops_zone,
             "flops_basis": "order-3 modal predictor (%d) + face quadrature (%d) per zone, as "
-                           "the generated code evaluates them" % (fc["predictor"], fc["faces"]),
+                           "the generated code evaluates them%s" % (
+                               fc["predictor"], fc["faces"],
+                               "; this kernel also reconstructs (WENO in LDS), whose work is "
+                               "not counted" if run["predict_layout"] == "fused-recon" else ""),
             "zones_per_launch": zones, "launch_ms": pred_ms,
             "peak_basis": "published MI355X vector FP32 (packed) / FP64",
             "peak_nonpacked": NONPACKED_TFLOPS[dtype],

@@ -306,14 +306,19 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
  * ADER_LAYOUT_PAIR2, the same compiled for two waves per SIMD (order 3),
  * ADER_LAYOUT_PAIR_SPLIT, the pair layout in two kernels (the predictor,
  * then the side packets; the evolutionary modes pass through device memory,
- * allocated on first use; MHD, orders 3 and 4), or -1 for the default of
+ * allocated on first use; MHD, orders 3 and 4), ADER_LAYOUT_FUSED, the
+ * reconstruction and the one-lane-per-zone predictor in one kernel: a block
+ * reconstructs a tile of 8 x 8 x 4 zones in LDS and predicts its zones
+ * from there, so the reconstructed modes never go through device memory
+ * (Euler, order 3 only; the stage timing then books the reconstruction
+ * under the predictor), or -1 for the default of
  * the setting (pair for MHD at order 3, the two-kernel pair at order 4,
  * split for Euler at order 4).  Results do not
  * depend on the layout beyond rounding order.  ader_autotune also picks it.
  * ader_get_layout returns the layout the current setting uses. */
 enum { ADER_LAYOUT_ZONE = 0, ADER_LAYOUT_SPLIT = 1, ADER_LAYOUT_SPLIT2 = 2, ADER_LAYOUT_ZONE2 = 3,
        ADER_LAYOUT_ZONE_2W = 4, ADER_LAYOUT_PAIR = 5, ADER_LAYOUT_PAIR2 = 6,
-       ADER_LAYOUT_PAIR_SPLIT = 7 };
+       ADER_LAYOUT_PAIR_SPLIT = 7, ADER_LAYOUT_FUSED = 8 };
 int ader_set_layout(ader_ctx* ctx, int layout);
 int ader_get_layout(ader_ctx* ctx, int* layout_out);
 
@@ -321,11 +326,15 @@ int ader_get_layout(ader_ctx* ctx, int* layout_out);
  * ADER_RECON_SWEEPS, one launch per sweep direction, ADER_RECON_TILED, one
  * launch doing the x, y and z sweeps of 8 x 8 x 8-zone tiles in LDS (halo
  * M-1 zones), ADER_RECON_COLUMNS, the x and y sweeps as launches and the z
- * sweep by threads that slide a window down 8-plane column segments, or -1
- * for the default (sweeps).  All run the same line reconstructions (modes
+ * sweep by threads that slide a window down 8-plane column segments,
+ * ADER_RECON_MARCH, one launch in which a block takes one variable of a
+ * 16 x 16-zone column segment of 32 planes and walks it plane by plane (x and y
+ * sweeps of each plane in LDS, the z sweep from a ring of the last 2M-1
+ * planes), so the zone averages are read about once and every mode written
+ * once, or -1 for the default (sweeps).  All run the same line reconstructions (modes
  * equal up to rounding); order 2 (minmod) always runs per zone.
  * ader_autotune also picks it; ader_get_recon returns the mode in use. */
-enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1, ADER_RECON_COLUMNS = 2 };
+enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1, ADER_RECON_COLUMNS = 2, ADER_RECON_MARCH = 3 };
 int ader_set_recon(ader_ctx* ctx, int mode);
 int ader_get_recon(ader_ctx* ctx, int* mode_out);
 

@@ -40,10 +40,10 @@ EXPORTS = [
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
 ADER_PROBE_FP32_FMA, ADER_PROBE_FP64_FMA, ADER_PROBE_HBM_COPY = 0, 1, 2
-ADER_RECON_SWEEPS, ADER_RECON_TILED, ADER_RECON_COLUMNS = 0, 1, 2
+ADER_RECON_SWEEPS, ADER_RECON_TILED, ADER_RECON_COLUMNS, ADER_RECON_MARCH = 0, 1, 2, 3
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
 ADER_LAYOUT_ZONE_2W, ADER_LAYOUT_PAIR, ADER_LAYOUT_PAIR2 = 4, 5, 6
-ADER_LAYOUT_PAIR_SPLIT = 7
+ADER_LAYOUT_PAIR_SPLIT, ADER_LAYOUT_FUSED = 7, 8
 LAUNCH_CLASSES = ["dt", "recon", "predict", "flux", "update"]
 STAGES = ["dt", "recon", "predict", "flux", "update"]
 

@@ -60,6 +60,7 @@ struct StageFns {
   int (*predict_pair)(ader_ctx*);     // MHD: two lanes per zone
   int (*predict_pair2)(ader_ctx*);    // the same, registers capped for 2 waves/SIMD
   int (*predict_pair_split)(ader_ctx*);  // the same in two kernels (predictor, sides)
+  int (*predict_fused)(ader_ctx*);  // reconstruction and predictor in one kernel (Euler, order 3)
   int (*rk_sides)(ader_ctx*);         // SSP-RK stage: side packets (Euler, modal tables)
   int (*flux)(ader_ctx*);     // face (and, MHD, edge) fluxes
   int (*update)(ader_ctx*);   // eq. (6), and eq. (8) for MHD
@@ -121,6 +122,13 @@ struct ader_ctx {
   int recon_mode = -1;
   long long* d_tile_base = nullptr;
   long long ntiles = 0;
+  // tiles of kTile x kTile x kFusedTZ zones of the fused reconstruction+predictor
+  long long* d_ftile_base = nullptr;
+  long long nftiles = 0;
+  // column segments (kMarchTile^2 zones x kMarchSeg planes) of the z-marching
+  // reconstruction
+  long long* d_xytile_base = nullptr;
+  long long nxytiles = 0;
   // z-column segments of the column mode: problem p's at seg_base[p] ..
   long long* d_seg_base = nullptr;
   long long nsegs = 0;

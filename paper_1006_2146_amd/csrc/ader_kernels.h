@@ -95,6 +95,41 @@ __global__ void __launch_bounds__(256) k_recon_tile(const double* __restrict__ U
   }
 }
 
+// z-marching reconstruction: one work item = one variable of kMarchSeg
+// planes of one x-y column of kMarchTile^2 zones (items in the XCD-aware
+// order of k_recon_tile: the item range cut into one region per XCD)
+template <class T, int M, int NVAR>
+__global__ void __launch_bounds__(kMarchTile * kMarchTile) k_recon_march(
+    const double* __restrict__ U, T* __restrict__ W, Batch b,
+    const long long* __restrict__ xy_base) {
+  using RM = ReconMarch<T, M, kMarchTile>;
+  __shared__ double su[RM::kSu];
+  __shared__ T sx[RM::kSx];
+  __shared__ double ring0[RM::kRing0];
+  __shared__ T ringT[RM::kRingT];
+  const long long nitems = xy_base[b.np] * NVAR;
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long lo = nitems * x / nreg, hi = nitems * (x + 1) / nreg;
+  for (long long w = lo + r; w < hi; w += nb) {
+    const long long q = w / NVAR;
+    const int v = (int)(w % NVAR);
+    const int p = problem_of_tile(xy_base, b.np, q);
+    const Problem pr = b.P[p];
+    const Grid g = grid_of(pr, b);
+    const long long lt = q - xy_base[p];
+    const int ntx = (pr.nx + kMarchTile - 1) / kMarchTile;
+    const int nty = (pr.ny + kMarchTile - 1) / kMarchTile;
+    const int i0 = (int)(lt % ntx) * kMarchTile, j0 = (int)((lt / ntx) % nty) * kMarchTile;
+    const int k0 = (int)(lt / ((long long)ntx * nty)) * kMarchSeg;
+    const int k1 = k0 + kMarchSeg < pr.nz ? k0 + kMarchSeg : pr.nz;
+    RM::run(U + (long long)v * b.S, W + (long long)v * b.S, g, NVAR, i0, j0, k0, k1, su, sx,
+            ring0, ringT);
+  }
+}
+
 template <class T, int NVAR>
 __global__ void __launch_bounds__(256) k_minmod(const double* __restrict__ U, T* __restrict__ W,
                                                 Batch b) {
@@ -122,6 +157,46 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
     predict_zone<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
                                                        1.0 / pr.dy, 1.0 / pr.dz, gam, pc.at(p), n);
   });
+}
+
+// Reconstruction and predictor in one kernel (Euler): a block takes tiles of
+// kTile x kTile x TZ zones (tiles in the XCD-aware order of k_recon_tile),
+// reconstructs each on LDS (ReconLds) and then runs the one-lane-per-zone
+// predictor on it, one thread per zone, reading the modes from LDS, so the
+// mode array never goes through HBM.  tile_base indexes these tiles.
+template <class T, int ORDER, int FORM, int TZ>
+__global__ void __launch_bounds__(kTile * kTile * TZ) k_recon_predict(
+    const double* __restrict__ U, T* __restrict__ PK, Batch b,
+    const long long* __restrict__ tile_base, const double* __restrict__ dt, double gam,
+    PosCtl pc) {
+  using RL = ReconLds<T, ORDER, 5, TZ>;
+  __shared__ double su[RL::kSu];
+  __shared__ T sx[RL::kSx];
+  __shared__ T sy[RL::kSy];
+  __shared__ T sw[RL::kSw];
+  const long long ntiles = tile_base[b.np];
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long lo = ntiles * x / nreg, hi = ntiles * (x + 1) / nreg;
+  const int t = threadIdx.x;
+  const int tx = t % kTile, ty = (t / kTile) % kTile, tz = t / (kTile * kTile);
+  for (long long q = lo + r; q < hi; q += nb) {
+    const int p = problem_of_tile(tile_base, b.np, q);
+    const Problem pr = b.P[p];
+    const Grid g = grid_of(pr, b);
+    const long long lt = q - tile_base[p];
+    const int ntx = (pr.nx + kTile - 1) / kTile, nty = (pr.ny + kTile - 1) / kTile;
+    const int i0 = (int)(lt % ntx) * kTile, j0 = (int)((lt / ntx) % nty) * kTile;
+    const int k0 = (int)(lt / ((long long)ntx * nty)) * TZ;
+    RL::run(U, g, i0, j0, k0, su, sx, sy, sw);
+    if (i0 + tx < pr.nx && j0 + ty < pr.ny && k0 + tz < pr.nz)
+      predict_zone_lds<T, ORDER, FORM, kDeviation<T>>(U, sw + t, RL::NZ, PK, g, dt[p],
+                                                      1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
+                                                      pc.at(p), zone_of(i0 + tx, j0 + ty, k0 + tz, g));
+    __syncthreads();   // the next tile overwrites the LDS
+  }
 }
 
 // the one-lane-per-zone predictor with the affine source term; dt S-bar to SB

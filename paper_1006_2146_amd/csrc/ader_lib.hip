@@ -98,6 +98,7 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
     case ADER_LAYOUT_PAIR: return s->predict_pair != nullptr;
     case ADER_LAYOUT_PAIR2: return s->predict_pair2 != nullptr;
     case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split != nullptr;
+    case ADER_LAYOUT_FUSED: return s->predict_fused != nullptr;
   }
   return false;
 }
@@ -122,6 +123,7 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_PAIR: return s->predict_pair(c);
     case ADER_LAYOUT_PAIR2: return s->predict_pair2(c);
     case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split(c);
+    case ADER_LAYOUT_FUSED: return s->predict_fused(c);
     default: return s->predict(c);
   }
 }
@@ -213,7 +215,8 @@ int queue_step(ader_ctx* c) {
   if (!s) return ADER_EUNSUPPORTED;
   if (c->scheme == ADER_SCHEME_SSPRK)
     return c->has_source ? ADER_EUNSUPPORTED : queue_rk_step(c, s);
-  {
+  // the fused layout reconstructs inside its predictor kernel
+  if (layout_of(c, s) != ADER_LAYOUT_FUSED) {
     StageTimer t(c, ADER_STAGE_RECON);
     ADER_TRY(s->recon(c));
   }
@@ -399,7 +402,7 @@ void free_buffers(ader_ctx* c) {
                   (void*)c->RK, c->EM, (void*)c->TH, (void*)c->SB,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_limited,
                   (void*)c->d_probs,
-                  (void*)c->d_tile_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
+                  (void*)c->d_tile_base, (void*)c->d_ftile_base, (void*)c->d_xytile_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
                   (void*)c->d_diag})
     if (p) (void)hipFree(p);
 }
@@ -471,6 +474,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
             hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess &&
             hipMalloc(&c->d_limited, sizeof(unsigned int) * n) == hipSuccess &&
             hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
+            hipMalloc(&c->d_ftile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
+            hipMalloc(&c->d_xytile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_seg_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_diag_base, sizeof(long long) * (n + 1)) == hipSuccess;
   if (!ok) {
@@ -480,7 +485,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     return ADER_ENOMEM;
   }
   c->fixed_bytes = sU + sF + sM + sP + 2 * sD + (sizeof(int) + sizeof(unsigned int)) * n +
-                   3 * sizeof(long long) * (n + 1);
+                   5 * sizeof(long long) * (n + 1);
   c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
   std::vector<long long> tile_base(n + 1, 0);
@@ -490,6 +495,25 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
                                           ((pr.ny + kTile - 1) / kTile) * ((pr.nz + kTile - 1) / kTile);
   }
   c->ntiles = tile_base[n];
+  // tiles of the fused reconstruction+predictor: kTile x kTile x kFusedTZ
+  std::vector<long long> ftile_base(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const Problem& pr = c->probs[q];
+    ftile_base[q + 1] = ftile_base[q] + (long long)((pr.nx + kTile - 1) / kTile) *
+                                            ((pr.ny + kTile - 1) / kTile) *
+                                            ((pr.nz + kFusedTZ - 1) / kFusedTZ);
+  }
+  c->nftiles = ftile_base[n];
+  // segments of kMarchSeg planes of the x-y columns of kMarchTile x kMarchTile
+  // zones of the z-marching reconstruction
+  std::vector<long long> xytile_base(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const Problem& pr = c->probs[q];
+    xytile_base[q + 1] = xytile_base[q] + (long long)((pr.nx + kMarchTile - 1) / kMarchTile) *
+                                              ((pr.ny + kMarchTile - 1) / kMarchTile) *
+                                              ((pr.nz + kMarchSeg - 1) / kMarchSeg);
+  }
+  c->nxytiles = xytile_base[n];
   // z-column segments of kZSeg planes per (i, j) column
   std::vector<long long> seg_base(n + 1, 0);
   for (int q = 0; q < n; ++q) {
@@ -503,6 +527,10 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     diag_base[q + 1] = diag_base[q] + (c->probs[q].N + kDiagTile - 1) / kDiagTile;
   c->ndiag_tiles = diag_base[n];
   if (hipMemcpy(c->d_tile_base, tile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_ftile_base, ftile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_xytile_base, xytile_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_diag_base, diag_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -555,7 +583,7 @@ int get_problem(ader_ctx* c, int q, double* U, double* B) {
 // of that stage alone) and keep the fastest.  The state is saved first and
 // restored at the end, so tuning does not advance the solution.
 // ---------------------------------------------------------------------------
-constexpr int kNumLayouts = 8;
+constexpr int kNumLayouts = 9;
 constexpr LaunchShape kCandidates[] = {{64, 4}, {64, 8}, {64, 16}, {128, 2}, {128, 4}, {128, 8},
                                        {256, 1}, {256, 2}, {256, 4}, {256, 8}, {256, 16}};
 
@@ -610,6 +638,9 @@ int autotune(ader_ctx* c, int reps) {
   // the update changes the state in place: tune it (and dt) last
   const int order_of_classes[kNumClasses] = {kClassRecon, kClassPredict, kClassFlux, kClassDt,
                                              kClassUpdate};
+  // the fused layout's predictor includes the reconstruction: the other
+  // layouts are compared with the tuned reconstruction's time added
+  float recon_ms = 0.f;
   for (int qi = 0; qi < kNumClasses && rc == ADER_OK; ++qi) {
     const int cls = order_of_classes[qi];
     LaunchShape best = c->shape[cls];
@@ -617,7 +648,7 @@ int autotune(ader_ctx* c, int reps) {
     float best_ms = 1e30f;
     // the predictor also tries its layouts, the reconstruction its modes
     int best_recon = c->recon_mode;
-    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 3 : 1;
+    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 4 : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
       if (cls == kClassPredict) {
         if (!layout_built(c, s, lay)) continue;
@@ -626,7 +657,7 @@ int autotune(ader_ctx* c, int reps) {
         if (rc != ADER_OK) break;
       }
       if (cls == kClassRecon) {
-        if ((lay == ADER_RECON_TILED || lay == ADER_RECON_COLUMNS) && c->order < 3) continue;
+        if (lay != ADER_RECON_SWEEPS && c->order < 3) continue;
         c->recon_mode = lay;
       }
       for (const LaunchShape& cand : kCandidates) {
@@ -635,6 +666,7 @@ int autotune(ader_ctx* c, int reps) {
         rc = time_stage(c, cls, s, 1, &ms);  // warm-up
         if (rc == ADER_OK) rc = time_stage(c, cls, s, reps, &ms);
         if (rc != ADER_OK) break;
+        if (cls == kClassPredict && c->layout != ADER_LAYOUT_FUSED) ms += recon_ms;
         if (ms < best_ms) {
           best_ms = ms;
           best = cand;
@@ -646,6 +678,7 @@ int autotune(ader_ctx* c, int reps) {
     c->shape[cls] = best;
     c->layout = best_layout;
     c->recon_mode = best_recon;
+    if (cls == kClassRecon) recon_ms = best_ms;
   }
   c->timing = timing;
   // restore the state, dt and clear the flags the trial steps may have set
@@ -887,6 +920,8 @@ int ader_set_layout(ader_ctx* c, int layout) {
     return ADER_EUNSUPPORTED;
   if ((layout == ADER_LAYOUT_PAIR || layout == ADER_LAYOUT_PAIR2) && c->order == 4)
     return ADER_EUNSUPPORTED;
+  if (layout == ADER_LAYOUT_FUSED && (c->order != 3 || c->system != ADER_EULER))
+    return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;
 }
@@ -955,7 +990,7 @@ int ader_limited_zones(ader_ctx* c, long long* counts_out) {
 
 int ader_set_recon(ader_ctx* c, int mode) {
   if (!c || (mode != -1 && mode != ADER_RECON_SWEEPS && mode != ADER_RECON_TILED &&
-             mode != ADER_RECON_COLUMNS))
+             mode != ADER_RECON_COLUMNS && mode != ADER_RECON_MARCH))
     return ADER_EINVAL;
   c->recon_mode = mode;
   return ADER_OK;

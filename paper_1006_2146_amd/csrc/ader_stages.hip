@@ -34,6 +34,16 @@ int sweeps(ader_ctx* c, const double* src, T* W) {
       k_recon_tile<T, kOrder, NVAR><<<gt, bs, 0, c->stream>>>(src, W, b, c->d_tile_base);
       return launched();
     }
+    if (c->recon_mode == ADER_RECON_MARCH) {
+      // one block per work item up to the tuned blocks per CU; the block
+      // size is the column's kMarchTile^2 zones
+      const long long items = c->nxytiles * NVAR;
+      const long long cap = (long long)c->shape[kClassRecon].blocks_per_cu * c->num_cus;
+      const unsigned gm = (unsigned)(items < cap ? items : cap);
+      k_recon_march<T, kOrder, NVAR><<<gm < 1 ? 1 : gm, kMarchTile * kMarchTile, 0, c->stream>>>(
+          src, W, b, c->d_xytile_base);
+      return launched();
+    }
   }
   if constexpr (kOrder == 2) {
     k_minmod<T, NVAR><<<g, bs, 0, c->stream>>>(src, W, b);
@@ -254,6 +264,22 @@ int predict_src(ader_ctx* c) {
   }
 }
 
+// reconstruction and predictor in one kernel on LDS tiles (Euler, order 3):
+// one block per tile of kTile x kTile x kFusedTZ zones, the block size fixed
+// by the tile, the tuned blocks per CU kept
+int predict_fused(ader_ctx* c) {
+  if constexpr (!kMhd && kOrder == 3) {
+    const long long cap = (long long)c->shape[kClassPredict].blocks_per_cu * c->num_cus;
+    const unsigned g = (unsigned)(c->nftiles < cap ? c->nftiles : cap);
+    k_recon_predict<T, kOrder, kForm, kFusedTZ><<<g < 1 ? 1 : g, kTile * kTile * kFusedTZ, 0,
+                                                  c->stream>>>(
+        c->U, static_cast<T*>(c->PK), c->batch(), c->d_ftile_base, c->d_dt, c->gamma, c->pos());
+    return launched();
+  } else {
+    return ADER_EUNSUPPORTED;
+  }
+}
+
 int update_src(ader_ctx* c) {
   if constexpr (!kMhd) {
     if (!c->SB) return ADER_ESEQ;
@@ -277,6 +303,7 @@ const StageFns kStages = {recon,
                           (kMhd && kOrder == 3) ? predict_pair<1> : nullptr,
                           (kMhd && kOrder == 3) ? predict_pair<2> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair_split : nullptr,
+                          (!kMhd && kOrder == 3) ? predict_fused : nullptr,
                           kForm == 0 ? rk_sides : nullptr,
                           flux,
                           update,

@@ -575,6 +575,12 @@ __host__ __device__ __forceinline__ void store_source_average(const SourceAffine
 // SRC: with the affine source *src, whose dt-scaled space-time average goes
 // to SB (rows of 5 doubles).
 template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool SRC = false>
+__host__ __device__ __forceinline__ void predict_zone_body(
+    const double (&w0)[5], T (&w)[SchemeOf<ORDER, FORM, T>::type::LS][5], T* __restrict__ PK,
+    const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz, double gam, PosCtl pc,
+    long long n, const SourceAffine* src, double* __restrict__ SB);
+
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED = true, bool SRC = false>
 __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__ U,
                                                       const T* __restrict__ W,
                                                       T* __restrict__ PK, const Grid& g,
@@ -583,9 +589,8 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
                                                       long long n,
                                                       const SourceAffine* src = nullptr,
                                                       double* __restrict__ SB = nullptr) {
-  static_assert(FUSED || !SRC, "the source instance has the fused facial check");
   using S = typename SchemeOf<ORDER, FORM, T>::type;
-  constexpr int LS = S::LS, NE = S::NE;
+  constexpr int LS = S::LS;
   double w0[5];
   {
     const double* q = U + n;
@@ -602,7 +607,45 @@ __host__ __device__ __forceinline__ void predict_zone(const double* __restrict__
 #pragma unroll
       for (int v = 0; v < 5; ++v) { w[m][v] = *q; q = next_row(q, g.S); }
   }
+  predict_zone_body<T, ORDER, FORM, DEV, FUSED, SRC>(w0, w, PK, g, h, inv_dx, inv_dy, inv_dz, gam,
+                                                     pc, n, src, SB);
+}
 
+// predict_zone with the zone's modes in LDS (mode m of variable v at
+// sw[((m - 1) 5 + v) nz]), for the kernel that reconstructs in the same
+// launch
+template <class T, int ORDER, int FORM, bool DEV>
+__device__ __forceinline__ void predict_zone_lds(const double* __restrict__ U, const T* sw, int nz,
+                                                 T* __restrict__ PK, const Grid& g, double h,
+                                                 double inv_dx, double inv_dy, double inv_dz,
+                                                 double gam, PosCtl pc, long long n) {
+  using S = typename SchemeOf<ORDER, FORM, T>::type;
+  constexpr int LS = S::LS;
+  double w0[5];
+  {
+    const double* q = U + n;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { w0[v] = *q; q = next_row(q, g.S); }
+  }
+  T w[LS][5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) w[0][v] = DEV ? T(0) : T(w0[v]);
+#pragma unroll
+  for (int m = 1; m < LS; ++m)
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[m][v] = sw[((m - 1) * 5 + v) * nz];
+  predict_zone_body<T, ORDER, FORM, DEV, true, false>(w0, w, PK, g, h, inv_dx, inv_dy, inv_dz,
+                                                      gam, pc, n, nullptr, nullptr);
+}
+
+template <class T, int ORDER, int FORM, bool DEV, bool FUSED, bool SRC>
+__host__ __device__ __forceinline__ void predict_zone_body(
+    const double (&w0)[5], T (&w)[SchemeOf<ORDER, FORM, T>::type::LS][5], T* __restrict__ PK,
+    const Grid& g, double h, double inv_dx, double inv_dy, double inv_dz, double gam, PosCtl pc,
+    long long n, const SourceAffine* src, double* __restrict__ SB) {
+  static_assert(FUSED || !SRC, "the source instance has the fused facial check");
+  using S = typename SchemeOf<ORDER, FORM, T>::type;
+  constexpr int LS = S::LS, NE = S::NE;
   {
     PosScan<T, 5, DEV> scan(w0);
     S::spatial_points(w, scan);

@@ -431,3 +431,55 @@ def isentropic_vortex(n, t=0.0, length=10.0, eps=5.0, gamma=1.4, quad=5):
     Wq = wts[:, None] * wts[None, :]
     Uz = (Uq * Wq).reshape(5, n, quad, n, quad).sum(axis=(2, 4))
     return Uz[:, None, :, :].copy()
+
+
+def magnetized_vortex(n, t=0.0, length=10.0, kappa=1.0, mu=1.0, gamma=5.0 / 3.0, quad=5):
+    """The two-dimensional magnetized isodensity vortex of Sec. VI.2 on an
+    n x n mesh with one zone in z: U of shape (5, 1, n, n) and face fields
+    B of shape (3, 1, n, n), the periodic box [0, length]^2 standing for
+    [-length/2, length/2]^2, lz = length.  Mean flow rho = P = 1, v = (1, 1,
+    0), B = 0; the vortex adds
+        dv = kappa / 2 pi exp((1 - r^2) / 2) (-y, x),
+        dB = mu / 2 pi exp((1 - r^2) / 2) (-y, x),
+        dP = (mu / 2 pi)^2 (1 - r^2) exp(1 - r^2) / 8 pi
+             - (kappa / 2 pi)^2 exp(1 - r^2) / 2
+    (Gaussian units), rho = 1 everywhere, centred at (t, t): the exact
+    solution at time t (nearest periodic image of the centre).  The face
+    fields are exact face averages, the differences of the potential
+    A_z = mu / 2 pi exp((1 - r^2) / 2) at the face's corners divided by the
+    edge length, so their discrete divergence vanishes; the zone averages
+    of rho v and of E = P / (gamma - 1) + rho |v|^2 / 2 + |B|^2 / 8 pi come
+    from a quad x quad Gauss-Legendre rule per zone."""
+    h = length / n
+    cx = (t + 0.5 * length) % length - 0.5 * length
+
+    def rel(c):
+        return (c - 0.5 * length - cx + 0.5 * length) % length - 0.5 * length
+
+    g, w = np.polynomial.legendre.leggauss(quad)
+    edges = np.arange(n) * h
+    pts = (edges[:, None] + 0.5 * h * (g[None, :] + 1.0)).ravel()
+    wts = np.tile(0.5 * w, n)
+    dx = rel(pts)[None, :]
+    dy = rel(pts)[:, None]
+    r2 = dx * dx + dy * dy
+    e1 = np.exp(0.5 * (1.0 - r2))
+    av = kappa / (2.0 * np.pi) * e1
+    ab = mu / (2.0 * np.pi) * e1
+    vx, vy = 1.0 - av * dy, 1.0 + av * dx
+    bx, by = -ab * dy, ab * dx
+    P = (1.0 + (mu / (2.0 * np.pi)) ** 2 * (1.0 - r2) * e1 * e1 / (8.0 * np.pi)
+         - 0.5 * (kappa / (2.0 * np.pi)) ** 2 * e1 * e1)
+    rho = np.ones_like(P)
+    Uq = np.stack([rho, rho * vx, rho * vy, np.zeros_like(rho),
+                   P / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy)
+                   + (bx * bx + by * by) / (2.0 * FOUR_PI)])
+    Wq = wts[:, None] * wts[None, :]
+    U = (Uq * Wq).reshape(5, n, quad, n, quad).sum(axis=(2, 4))[:, None, :, :].copy()
+    # A_z at the corners (x_i, y_j) of the mesh, single-valued on the torus
+    cxs, cys = rel(edges)[None, :], rel(edges)[:, None]
+    Az = mu / (2.0 * np.pi) * np.exp(0.5 * (1.0 - (cxs * cxs + cys * cys)))   # [j][i]
+    B = np.zeros((3, 1, n, n))
+    B[0, 0] = (np.roll(Az, -1, axis=0) - Az) / h       # B_x = dA_z/dy on x-faces
+    B[1, 0] = -(np.roll(Az, -1, axis=1) - Az) / h      # B_y = -dA_z/dx on y-faces
+    return U, B

@@ -323,18 +323,19 @@ def test_config4_ensemble_full_size():
 @pytest.mark.parametrize("precision", [ader.ADER_FP64, ader.ADER_MIXED])
 @pytest.mark.parametrize("order", [3, 4])
 def test_tiled_reconstruction_equals_sweeps(order, precision, system):
-    # the LDS-tiled and the z-column reconstructions run the same line
-    # reconstructions as the one-kernel-per-sweep path: whole steps agree to
-    # rounding (multiply-adds may be contracted differently), on ragged
-    # problems smaller and larger than a tile or a column segment
-    shapes = [(9, 14, 21), (1, 1, 1), (5, 3, 17), (16, 16, 16), (2, 9, 1)]
+    # the LDS-tiled, z-column and z-marching reconstructions run the same
+    # line reconstructions as the one-kernel-per-sweep path: whole steps
+    # agree to rounding (multiply-adds may be contracted differently), on
+    # ragged problems smaller and larger than a tile, a column and a z segment
+    shapes = [(9, 14, 21), (1, 1, 1), (5, 3, 17), (16, 16, 16), (2, 9, 1), (70, 18, 33)]
     mhd = system == "mhd"
     states = _states(shapes, mhd=mhd)
     kw = dict(order=order, precision=precision)
     if mhd:
         kw.update(gamma=5.0 / 3.0, system=ader.ADER_MHD)
     out = {}
-    for mode in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS):
+    for mode in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS,
+                 ader.ADER_RECON_MARCH):
         say("recon mode", mode, order, precision, system)
         with ader.BatchSolver(shapes, **kw) as b:
             ader.ader_set_recon(b.ctx, mode)
@@ -345,7 +346,42 @@ def test_tiled_reconstruction_equals_sweeps(order, precision, system):
                 b.step_cfl(0.3)
             out[mode] = [b.get_state(i) for i in range(len(shapes))]
     tol = 1e-14 if precision == ader.ADER_FP64 else 1e-7
-    for other in (ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS):
+    for other in (ader.ADER_RECON_TILED, ader.ADER_RECON_COLUMNS, ader.ADER_RECON_MARCH):
         for a, c in zip(out[ader.ADER_RECON_SWEEPS], out[other]):
             for x, y in (zip(a, c) if mhd else [(a, c)]):
                 assert np.abs(x - y).max() <= tol * np.abs(x).max(), other
+
+
+@pytest.mark.parametrize("precision", [ader.ADER_FP64, ader.ADER_MIXED])
+@pytest.mark.parametrize("form", [ader.ADER_MODAL, ader.ADER_NODAL])
+def test_fused_reconstruction_predictor(form, precision):
+    # the reconstruction and the predictor in one kernel on LDS tiles of
+    # 8 x 8 x 4 zones: whole steps agree to rounding with the separate
+    # reconstruction and predictor, on ragged problems smaller and larger
+    # than a tile; each problem of the batch equals its solo run bitwise
+    shapes = [(9, 14, 21), (1, 1, 1), (5, 3, 17), (16, 16, 16), (2, 9, 1), (4, 8, 8)]
+    states = _states(shapes)
+    kw = dict(order=3, form=form, precision=precision)
+    out = {}
+    for layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_FUSED):
+        say("fused", layout, form, precision)
+        res, dts, used = _batch_run(shapes, states, 2, layout=layout, **kw)
+        assert used["layout"] == layout
+        out[layout] = (res, dts)
+    tol = 1e-14 if precision == ader.ADER_FP64 else 1e-7
+    for (a, _), (c, _) in zip(out[ader.ADER_LAYOUT_ZONE][0], out[ader.ADER_LAYOUT_FUSED][0]):
+        assert np.abs(a - c).max() <= tol * np.abs(a).max()
+    for i, (s, (U, _)) in enumerate(zip(shapes, states)):
+        (Us, _), sdts = _solo(s, U, None, 2, layout=ader.ADER_LAYOUT_FUSED, **kw)
+        assert np.array_equal(out[ader.ADER_LAYOUT_FUSED][0][i][0], Us), i
+
+
+def test_fused_layout_is_order_3_euler_only():
+    with ader.Solver((4, 4, 4), order=4) as s:
+        with pytest.raises(ader.AderError) as e:
+            ader.ader_set_layout(s.ctx, ader.ADER_LAYOUT_FUSED)
+        assert e.value.code == ader.ADER_EUNSUPPORTED
+    with ader.Solver((4, 4, 4), order=3, system=ader.ADER_MHD, gamma=5.0 / 3.0) as s:
+        with pytest.raises(ader.AderError) as e:
+            ader.ader_set_layout(s.ctx, ader.ADER_LAYOUT_FUSED)
+        assert e.value.code == ader.ADER_EUNSUPPORTED

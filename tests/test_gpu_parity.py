@@ -362,10 +362,12 @@ def test_config3_mhd_full_size_sampled():
 
 LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2,
            ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W, ader.ADER_LAYOUT_PAIR,
-           ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT]
+           ader.ADER_LAYOUT_PAIR2, ader.ADER_LAYOUT_PAIR_SPLIT, ader.ADER_LAYOUT_FUSED]
 
 
 def _skip_unbuilt(layout, order, mhd=False):
+    if layout == ader.ADER_LAYOUT_FUSED and (order != 3 or mhd):
+        pytest.skip("the fused reconstruction+predictor is built for Euler at order 3")
     if layout == ader.ADER_LAYOUT_ZONE2 and order > 3:
         pytest.skip("the one-lane-per-zone instance with its own facial pass is built for "
                     "orders 2 and 3")
