@@ -54,7 +54,16 @@ enum {
   ADER_ESEQ = -6           /* call out of sequence (e.g. step before set_state) */
 };
 
-enum { ADER_EULER = 0, ADER_MHD = 1 };         /* eq. (3) with B = 0; ideal MHD */
+/* ADER_LINADV: linear advection u_t + a . grad u = 0 of the five state
+ * components (independent of each other), a test system on which the
+ * scheme translates any data by exactly one zone per step at |a_x| dt = dx
+ * (a along x): the same reconstruction, predictor and face quadrature with
+ * the linear flux F_d(u) = a_d u, the upwind limit of the HLL flux of
+ * eq. (56) (signal speeds min(a_d, 0), max(a_d, 0)), the update of eq. (6)
+ * and dt = cfl / sum_d |a_d| / dx_d.  FP64 and the ADER scheme only
+ * (ADER_EUNSUPPORTED at the step otherwise); no positivity handling; a is
+ * set by ader_set_advection (default (1, 0, 0)). */
+enum { ADER_EULER = 0, ADER_MHD = 1, ADER_LINADV = 2 };  /* eq. (3) with B = 0; ideal MHD */
 enum { ADER_HLL = 0, ADER_LINEARIZED = 1 };     /* eq. (17)/(56); Sec. II.3 */
 enum { ADER_MODAL = 0, ADER_NODAL = 1 };        /* Sec. IV; App. A, B, C (orders 2, 3, 4) */
 enum { ADER_FP64 = 0, ADER_MIXED = 1 };         /* all-FP64, or FP32 bulk with FP64
@@ -132,6 +141,10 @@ enum { ADER_POSITIVITY_CHECK = 0, ADER_POSITIVITY_LIMIT = 1 };
  * scheme's step returns ADER_EUNSUPPORTED.  ADER_EUNSUPPORTED on an MHD
  * context; ADER_EINVAL for a non-finite entry or b without A. */
 int ader_set_source(ader_ctx* ctx, const double* A, const double* b);
+
+/* Velocity a of an ADER_LINADV context (ADER_EUNSUPPORTED for the other
+ * systems; ADER_EINVAL for a non-finite component or a = 0). */
+int ader_set_advection(ader_ctx* ctx, double ax, double ay, double az);
 int ader_set_positivity(ader_ctx* ctx, int mode);
 int ader_get_positivity(ader_ctx* ctx, int* mode_out);
 

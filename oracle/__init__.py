@@ -23,6 +23,7 @@ predictor -- ADER-CG space-time predictor, modal (Sec. IV) and nodal (App. A, B)
 faces     -- barycentre states and face/edge space-time averages (Sec. V, App. D)
 riemann   -- HLL (eq. 17, 56) and linearized Riemann fluxes at frozen states
 step      -- whole step: dt by CFL, flux-difference update (eq. 6), CT (eq. 8)
+linadv    -- the same step for linear advection of five components (test system)
 
 Parity status: every function is pinned by the ``-m "not gpu"`` tests in
 ``tests/test_oracle_*.py`` except the choices the paper leaves open (WENO

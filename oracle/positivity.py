@@ -179,51 +179,56 @@ def limit_spacetime(uhat, order, form, gamma):
     return out
 
 
-def _check(values, gamma, where):
+def _check(values, gamma, where, mask=None):
     """Raise NonPhysical if any of the point states has rho <= 0 or P <= 0
-    (or a non-finite value)."""
+    (or a non-finite value), in the zones where ``mask`` is set (all zones
+    without one)."""
     bad = None
     for u in values:
         with np.errstate(divide='ignore', invalid='ignore'):
             ok = (u[0] > 0.0) & (_pressure_like(u, gamma) > 0.0)
         b = ~ok
         bad = b if bad is None else bad | b
+    if bad is not None and mask is not None:
+        bad = bad & mask
     if bad is not None and bad.any():
         raise NonPhysical('%s: %d zone(s) with rho <= 0 or P <= 0 at a check point'
                           % (where, int(bad.sum())))
 
 
-def check_spatial(what, order, form, gamma):
+def check_spatial(what, order, form, gamma, mask=None):
     """The check mode's test of the spatial polynomial at the spatial check
     set (before the predictor)."""
     pts = spatial_check_points(order, form, all_nodes=what.shape[1] == 8)
-    _check([evaluate(_as_spacetime(what, order), order, p) for p in pts], gamma, 'spatial')
+    _check([evaluate(_as_spacetime(what, order), order, p) for p in pts], gamma, 'spatial', mask)
 
 
-def check_spacetime(uhat, order, form, gamma):
+def check_spacetime(uhat, order, form, gamma, mask=None):
     """The check mode's test of the space-time polynomial at the facial
     check set (after the predictor)."""
     pts = facial_check_points(order, uhat.shape[1] == 8)
-    _check([evaluate(uhat, order, p) for p in pts], gamma, 'space-time')
+    _check([evaluate(uhat, order, p) for p in pts], gamma, 'space-time', mask)
 
 
-def safeguard_spatial(what, order, form, gamma, mode):
-    """The spatial polynomial after the positivity handling of ``mode``."""
+def safeguard_spatial(what, order, form, gamma, mode, mask=None):
+    """The spatial polynomial after the positivity handling of ``mode``
+    (the check restricted to the zones of ``mask`` if given)."""
     if mode == 'limit':
         return limit_spatial(what, order, form, gamma)
     if mode != 'check':
         raise ValueError('positivity mode %r' % (mode,))
-    check_spatial(what, order, form, gamma)
+    check_spatial(what, order, form, gamma, mask)
     return what
 
 
-def safeguard_spacetime(uhat, order, form, gamma, mode):
-    """The space-time polynomial after the positivity handling of ``mode``."""
+def safeguard_spacetime(uhat, order, form, gamma, mode, mask=None):
+    """The space-time polynomial after the positivity handling of ``mode``
+    (the check restricted to the zones of ``mask`` if given)."""
     if mode == 'limit':
         return limit_spacetime(uhat, order, form, gamma)
     if mode != 'check':
         raise ValueError('positivity mode %r' % (mode,))
-    check_spacetime(uhat, order, form, gamma)
+    check_spacetime(uhat, order, form, gamma, mask)
     return uhat
 
 

@@ -38,6 +38,8 @@ class OracleConfig:
     # 'check': the paper's scheme, NonPhysical raised where rho <= 0 or
     # P <= 0 at a check point; 'limit': the Zhang-Shu scaling (opt-in)
     positivity: str = 'check'
+    # zones (bool, (nz, ny, nx)) the check mode tests; None: all
+    check_mask: object = None
 
     def spacing(self, shape):
         if self.zone_size is not None:
@@ -78,7 +80,7 @@ def predictor(U, dt, cfg, B=None):
     what = reconstruct(U, cfg.order)
     if B is not None:
         what = np.concatenate([what, zone_b_modes(B, cfg.order)], axis=1)
-    what = safeguard_spatial(what, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
+    what = safeguard_spatial(what, cfg.order, cfg.form, cfg.gamma, cfg.positivity, cfg.check_mask)
     if cfg.form == 'nodal':
         if cfg.order == 2:
             uhat = predict_nodal_2(what, dt, dx, cfg.gamma)
@@ -88,7 +90,8 @@ def predictor(U, dt, cfg, B=None):
             uhat = predict_nodal_4(what, dt, dx, cfg.gamma)
     else:
         uhat = predict_modal(what, cfg.order, dt, dx, cfg.gamma)
-    return safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
+    return safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity,
+                               cfg.check_mask)
 
 
 def face_fluxes(uhat, cfg):
@@ -220,12 +223,13 @@ def predictor_source(U, dt, cfg):
     polynomial."""
     dx = cfg.spacing(U.shape[1:])
     what = safeguard_spatial(reconstruct(U, cfg.order), cfg.order, cfg.form, cfg.gamma,
-                             cfg.positivity)
+                             cfg.positivity, cfg.check_mask)
     if cfg.form == 'nodal':
         uhat, dts = predict_nodal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
     else:
         uhat, dts = predict_modal_source(what, cfg.order, dt, dx, cfg.gamma, cfg.source)
-    out = safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity)
+    out = safeguard_spacetime(uhat, cfg.order, cfg.form, cfg.gamma, cfg.positivity,
+                              cfg.check_mask)
     if cfg.positivity == 'limit':
         dts = source_average(out, cfg.order, cfg.form, dt, cfg.source)
     return out, dts

@@ -18,7 +18,7 @@ ADER_EDEVICE = -4
 ADER_ESTATE = -5
 ADER_ESEQ = -6
 
-ADER_EULER, ADER_MHD = 0, 1
+ADER_EULER, ADER_MHD, ADER_LINADV = 0, 1, 2
 ADER_HLL, ADER_LINEARIZED = 0, 1
 ADER_MODAL, ADER_NODAL = 0, 1
 ADER_FP64, ADER_MIXED = 0, 1
@@ -35,7 +35,7 @@ EXPORTS = [
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
-    "ader_diagnostics_noalloc", "ader_set_source",
+    "ader_diagnostics_noalloc", "ader_set_source", "ader_set_advection",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
@@ -115,6 +115,7 @@ def load():
         "ader_diagnostics": ([P, DP, DP], I),
         "ader_diagnostics_noalloc": ([P, DP, DP], I),
         "ader_set_source": ([P, DP, DP], I),
+        "ader_set_advection": ([P, D, D, D], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -266,6 +267,12 @@ def ader_diagnostics(ctx, n=1):
     div = np.empty(n, dtype=np.float64)
     _check(load().ader_diagnostics(ctx, _dptr(tot), _dptr(div)), "ader_diagnostics")
     return tot, div
+
+
+def ader_set_advection(ctx, a):
+    """Velocity (ax, ay, az) of a linear-advection context."""
+    _check(load().ader_set_advection(ctx, float(a[0]), float(a[1]), float(a[2])),
+           "ader_set_advection")
 
 
 def ader_set_source(ctx, A=None, b=None):
@@ -460,6 +467,9 @@ class BatchSolver:
     def set_source(self, A=None, b=None):
         ader_set_source(self.ctx, A, b)
 
+    def set_advection(self, a):
+        ader_set_advection(self.ctx, a)
+
     def diagnostics(self):
         return ader_diagnostics(self.ctx, len(self))
 
@@ -524,6 +534,9 @@ class Solver:
 
     def set_source(self, A=None, b=None):
         ader_set_source(self.ctx, A, b)
+
+    def set_advection(self, a):
+        ader_set_advection(self.ctx, a)
 
     def diagnostics(self):
         """(totals[8], max |div B|) of the current state."""

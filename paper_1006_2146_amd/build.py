@@ -33,6 +33,9 @@ HIPCC_FLAGS = [
 VARIANTS = [(sys_, prec, order, form)
             for sys_ in ("euler", "mhd") for prec in ("fp64", "mixed")
             for order, form in ((2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1))]
+# linear advection (test system): FP64 only
+VARIANTS += [("linadv", "fp64", order, form)
+             for order, form in ((2, 0), (2, 1), (3, 0), (3, 1), (4, 0), (4, 1))]
 
 
 def hipcc():

@@ -146,6 +146,8 @@ struct ader_ctx {
   // scaling; per problem the count of scaled zone polynomials
   int positivity = ADER_POSITIVITY_CHECK;
   unsigned int* d_limited = nullptr;
+  // velocity of the linear-advection test system
+  double adv[3] = {1.0, 0.0, 0.0};
   // affine source term (Euler): S(u) = A u + b, and dt S-bar per zone [5][S]
   bool has_source = false;
   ader::SourceAffine source{};
@@ -197,7 +199,9 @@ inline unsigned grid_for(const ader_ctx* c, int cls, int zones_per_wave = 64) {
   X(mhd, fp64, 2, 0) X(mhd, fp64, 2, 1) X(mhd, fp64, 3, 0) X(mhd, fp64, 3, 1)             \
   X(mhd, fp64, 4, 0) X(mhd, fp64, 4, 1)                                                   \
   X(mhd, mixed, 2, 0) X(mhd, mixed, 2, 1) X(mhd, mixed, 3, 0) X(mhd, mixed, 3, 1)         \
-  X(mhd, mixed, 4, 0) X(mhd, mixed, 4, 1)
+  X(mhd, mixed, 4, 0) X(mhd, mixed, 4, 1)                                                 \
+  X(linadv, fp64, 2, 0) X(linadv, fp64, 2, 1) X(linadv, fp64, 3, 0) X(linadv, fp64, 3, 1) \
+  X(linadv, fp64, 4, 0) X(linadv, fp64, 4, 1)
 #define ADER_STAGES_NAME(sys, prec, order, form) stages_##sys##_##prec##_o##order##_f##form
 #define ADER_DECLARE_STAGES(sys, prec, order, form) \
   const StageFns* ADER_STAGES_NAME(sys, prec, order, form)();

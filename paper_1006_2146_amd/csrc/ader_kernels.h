@@ -199,6 +199,27 @@ __global__ void __launch_bounds__(kTile * kTile * TZ) k_recon_predict(
   }
 }
 
+// linear advection (test system): predictor and face fluxes
+template <class T, int ORDER, int FORM>
+__global__ void __launch_bounds__(256) k_predict_adv(const double* __restrict__ U,
+                                                     const T* __restrict__ W, T* __restrict__ PK,
+                                                     Batch b, const double* __restrict__ dt,
+                                                     double ax, double ay, double az) {
+  for_zones(b, [&](const Problem& pr, int p, long long n) {
+    predict_zone_adv<T, ORDER, FORM>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
+                                     1.0 / pr.dz, ax, ay, az, n);
+  });
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_face_flux_adv(const T* __restrict__ PK,
+                                                       double* __restrict__ F, Batch b, double ax,
+                                                       double ay, double az) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    face_flux_adv_zone<T>(PK, F, grid_of(pr, b), ax, ay, az, n);
+  });
+}
+
 // the one-lane-per-zone predictor with the affine source term; dt S-bar to SB
 template <class T, int ORDER, int FORM>
 __global__ void __launch_bounds__(256) k_predict_src(const double* __restrict__ U,
@@ -526,6 +547,16 @@ __global__ void __launch_bounds__(64) k_dt_final(unsigned long long* __restrict_
   if (!(r > 0.0) || !__builtin_isfinite(r)) bad[p] = 1;
   else if (!bad[p]) dt[p] = cfl / r;
   rate[p] = 0ull;
+}
+
+// dt of linear advection per problem: cfl / sum_d |a_d| / dx_d
+template <int = 0>
+__global__ void __launch_bounds__(64) k_dt_adv(Batch b, double cfl, double ax, double ay,
+                                               double az, double* __restrict__ dt) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.np) return;
+  const Problem pr = b.P[p];
+  dt[p] = cfl / (fabs(ax) / pr.dx + fabs(ay) / pr.dy + fabs(az) / pr.dz);
 }
 
 template <int = 0>

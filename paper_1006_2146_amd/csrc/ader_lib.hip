@@ -37,7 +37,7 @@ int set_device(ader_ctx* c) { return check(hipSetDevice(c->device)); }
 const StageFns* stages_of(const ader_ctx* c) {
   const int form = c->scheme == ADER_SCHEME_SSPRK ? ADER_MODAL : c->form;
 #define ADER_PICK(SY, PR, OR, FM)                                                                \
-  if (c->system == (#SY[0] == 'm' ? ADER_MHD : ADER_EULER) &&                                    \
+  if (c->system == (#SY[0] == 'm' ? ADER_MHD : #SY[0] == 'l' ? ADER_LINADV : ADER_EULER) &&      \
       c->precision == (#PR[0] == 'm' ? ADER_MIXED : ADER_FP64) && c->order == OR && form == FM) \
     return ADER_STAGES_NAME(SY, PR, OR, FM)();
   ADER_VARIANTS(ADER_PICK)
@@ -73,6 +73,13 @@ struct StageTimer {
 
 int queue_dt(ader_ctx* c, double cfl) {
   StageTimer t(c, ADER_STAGE_DT);
+  if (c->system == ADER_LINADV) {
+    k_dt_adv<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->batch(), cfl, c->adv[0], c->adv[1],
+                                                           c->adv[2], c->d_dt);
+    ADER_TRY(launched());
+    c->have_dt = true;
+    return ADER_OK;
+  }
   k_dt<><<<grid_for(c, kClassDt), c->shape[kClassDt].block, 0, c->stream>>>(
       c->U, c->system == ADER_MHD ? c->B : nullptr, c->batch(), c->gamma, c->d_rate, c->d_bad);
   ADER_TRY(launched());
@@ -299,6 +306,11 @@ unsigned long long config_key(const ader_ctx* c) {
   k ^= (unsigned long long)(uintptr_t)c->W * 0xd6e8feb86659fd93ull;
   k ^= (unsigned long long)(uintptr_t)c->PK * 0xa0761d6478bd642full;
   k ^= (unsigned long long)(uintptr_t)c->SB * 0xe7037ed1a0b428dbull;
+  for (int d = 0; d < 3; ++d) {
+    unsigned long long a;
+    std::memcpy(&a, &c->adv[d], sizeof a);
+    k = k * 1099511628211ull ^ a;
+  }
   unsigned long long g;
   std::memcpy(&g, &c->gamma, sizeof g);
   return k ^ (g * 0x165667b19e3779f9ull);
@@ -358,15 +370,16 @@ int read_status(ader_ctx* c) {
 
 // rho > 0, P > 0 and finite values in every zone of one problem stored with
 // stride S at base (MHD: the zone field is the mean of its two face values,
-// as in the CFL rate)
+// as in the CFL rate); for linear advection (physical false) finite values
 bool host_state_ok(const double* U, const double* B, const Problem& pr, long long S,
-                   double gamma) {
+                   double gamma, bool physical = true) {
   for (long long l = 0; l < pr.N; ++l) {
     const long long n = pr.base + l;
     const double r = U[n], mx = U[S + n], my = U[2 * S + n], mz = U[3 * S + n], E = U[4 * S + n];
     if (!(std::isfinite(r) && std::isfinite(mx) && std::isfinite(my) && std::isfinite(mz) &&
           std::isfinite(E)))
       return false;
+    if (!physical) continue;
     if (!(r > 0.0)) return false;
     double b2 = 0.0;
     if (B) {
@@ -417,7 +430,7 @@ bool mesh_ok(const ader_mesh& m) {
 int create(int n, const ader_mesh* meshes, int system, int device, void* stream, ader_ctx** out) {
   if (!meshes || !out || n < 1 || n > (1 << 20)) return ADER_EINVAL;
   *out = nullptr;
-  if (system != ADER_EULER && system != ADER_MHD) return ADER_EINVAL;
+  if (system != ADER_EULER && system != ADER_MHD && system != ADER_LINADV) return ADER_EINVAL;
   long long S = 0;
   for (int q = 0; q < n; ++q) {
     if (!mesh_ok(meshes[q])) return ADER_EINVAL;
@@ -746,7 +759,7 @@ int ader_set_state(ader_ctx* c, const double* U, const double* B) {
   const bool mhd = c->system == ADER_MHD;
   if (mhd != (B != nullptr)) return ADER_EINVAL;
   for (const Problem& pr : c->probs)
-    if (!host_state_ok(U, B, pr, c->S, c->gamma)) return ADER_ESTATE;
+    if (!host_state_ok(U, B, pr, c->S, c->gamma, c->system != ADER_LINADV)) return ADER_ESTATE;
   ADER_TRY(set_device(c));
   ADER_TRY(check(hipMemcpyAsync(c->U, U, sizeof(double) * 5 * (size_t)c->S, hipMemcpyHostToDevice,
                                 c->stream)));
@@ -765,7 +778,7 @@ int ader_batch_set_state(ader_ctx* c, int i, const double* U, const double* B) {
   if (mhd != (B != nullptr)) return ADER_EINVAL;
   Problem lone = c->probs[i];
   lone.base = 0;
-  if (!host_state_ok(U, B, lone, lone.N, c->gamma)) return ADER_ESTATE;
+  if (!host_state_ok(U, B, lone, lone.N, c->gamma, c->system != ADER_LINADV)) return ADER_ESTATE;
   ADER_TRY(set_device(c));
   ADER_TRY(put_problem(c, i, U, B));
   ADER_TRY(check(hipStreamSynchronize(c->stream)));
@@ -944,9 +957,20 @@ int ader_set_positivity(ader_ctx* c, int mode) {
   return ADER_OK;
 }
 
+int ader_set_advection(ader_ctx* c, double ax, double ay, double az) {
+  if (!c) return ADER_EINVAL;
+  if (c->system != ADER_LINADV) return ADER_EUNSUPPORTED;
+  if (!std::isfinite(ax) || !std::isfinite(ay) || !std::isfinite(az)) return ADER_EINVAL;
+  if (ax == 0.0 && ay == 0.0 && az == 0.0) return ADER_EINVAL;
+  c->adv[0] = ax;
+  c->adv[1] = ay;
+  c->adv[2] = az;
+  return ADER_OK;
+}
+
 int ader_set_source(ader_ctx* c, const double* A, const double* b) {
   if (!c) return ADER_EINVAL;
-  if (c->system == ADER_MHD) return ADER_EUNSUPPORTED;
+  if (c->system != ADER_EULER) return ADER_EUNSUPPORTED;
   if (!A) {
     if (b) return ADER_EINVAL;
     c->has_source = false;

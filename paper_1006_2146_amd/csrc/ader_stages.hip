@@ -8,9 +8,10 @@
 
 #define ADER_STR_euler 0
 #define ADER_STR_mhd 1
+#define ADER_STR_linadv 2
 #define ADER_CAT_(a, b) a##b
 #define ADER_CAT(a, b) ADER_CAT_(a, b)
-#define ADER_IS_MHD ADER_CAT(ADER_STR_, ADER_SYS)
+#define ADER_SYS_ID ADER_CAT(ADER_STR_, ADER_SYS)
 #define ADER_PREC_fp64 double
 #define ADER_PREC_mixed float
 
@@ -20,7 +21,8 @@ namespace {
 using T = ADER_CAT(ADER_PREC_, ADER_PREC);
 constexpr int kOrder = ADER_ORDER;
 constexpr int kForm = ADER_FORM;
-constexpr bool kMhd = ADER_IS_MHD == 1;
+constexpr bool kMhd = ADER_SYS_ID == 1;
+constexpr bool kLinadv = ADER_SYS_ID == 2;   // linear advection (test system)
 
 template <int NVAR>
 int sweeps(ader_ctx* c, const double* src, T* W) {
@@ -81,7 +83,10 @@ int predict(ader_ctx* c) {
   const int bs = c->shape[kClassPredict].block;
   const T* W = static_cast<const T*>(c->W);
   T* PK = static_cast<T*>(c->PK);
-  if constexpr (kMhd) {
+  if constexpr (kLinadv) {
+    k_predict_adv<T, kOrder, kForm><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(), c->d_dt,
+                                                             c->adv[0], c->adv[1], c->adv[2]);
+  } else if constexpr (kMhd) {
     if (c->riemann == ADER_LINEARIZED) {
       // the linearized flux needs every variable's edge states (fused instance only)
       if constexpr (FUSED)
@@ -213,7 +218,10 @@ int flux(ader_ctx* c) {
   const unsigned g = grid_for(c, kClassFlux);
   const int bs = c->shape[kClassFlux].block;
   const T* PK = static_cast<const T*>(c->PK);
-  if constexpr (kMhd) {
+  if constexpr (kLinadv) {
+    k_face_flux_adv<T><<<g, bs, 0, c->stream>>>(PK, c->F, c->batch(), c->adv[0], c->adv[1],
+                                                c->adv[2]);
+  } else if constexpr (kMhd) {
     if (c->riemann == ADER_HLL)
       k_face_flux_mhd<T, 0><<<g, bs, 0, c->stream>>>(c->U, c->B0, PK, c->F, c->FE, c->batch(), c->gamma);
     else
@@ -294,21 +302,22 @@ int update_src(ader_ctx* c) {
 // the one-lane-per-zone instances with a separate facial pass, and with two
 // waves per SIMD (Euler), are built where the zone layout is the likely
 // winner (orders 2 and 3)
+// linear advection builds only the one-lane-per-zone predictor
 const StageFns kStages = {recon,
                           predict<true>,
-                          kOrder >= 3 ? predict_split<1> : nullptr,
-                          kOrder >= 3 ? predict_split<2> : nullptr,
-                          kOrder <= 3 ? predict<false> : nullptr,
-                          (!kMhd && kOrder <= 3) ? predict<true, 2> : nullptr,
+                          (kOrder >= 3 && !kLinadv) ? predict_split<1> : nullptr,
+                          (kOrder >= 3 && !kLinadv) ? predict_split<2> : nullptr,
+                          (kOrder <= 3 && !kLinadv) ? predict<false> : nullptr,
+                          (!kMhd && !kLinadv && kOrder <= 3) ? predict<true, 2> : nullptr,
                           (kMhd && kOrder == 3) ? predict_pair<1> : nullptr,
                           (kMhd && kOrder == 3) ? predict_pair<2> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair_split : nullptr,
-                          (!kMhd && kOrder == 3) ? predict_fused : nullptr,
-                          kForm == 0 ? rk_sides : nullptr,
+                          (!kMhd && !kLinadv && kOrder == 3) ? predict_fused : nullptr,
+                          (kForm == 0 && !kLinadv) ? rk_sides : nullptr,
                           flux,
                           update,
-                          kMhd ? nullptr : predict_src,
-                          kMhd ? nullptr : update_src};
+                          (kMhd || kLinadv) ? nullptr : predict_src,
+                          (kMhd || kLinadv) ? nullptr : update_src};
 
 }  // namespace
 

@@ -143,28 +143,57 @@ __host__ __device__ __forceinline__ void weno1d(const T (&d)[2 * M - 1], T (&m)[
     const T is1 = c1[1] * c1[1] + T(13.0 / 3.0) * c1[2] * c1[2];
     const T is2 = c2[1] * c2[1] + T(13.0 / 3.0) * c2[2] * c2[2];
     const T e0 = T(kEps) + is0, e1 = T(kEps) + is1, e2 = T(kEps) + is2;
-    const T a0 = T(1) / (e0 * e0), a1 = T(100) / (e1 * e1), a2 = T(1) / (e2 * e2);
-    const T tot = a0 + a1 + a2;
-    m[1] = (a0 * c0[1] + a1 * c1[1] + a2 * c2[1]) / tot;
-    m[2] = (a0 * c0[2] + a1 * c1[2] + a2 * c2[2]) / tot;
+    const T q0 = e0 * e0, q1 = e1 * e1, q2 = e2 * e2;
+    T a0, a1, a2, inv;
+    if constexpr (sizeof(T) == 4) {
+      // FP32: lambda_s / q_s with hardware reciprocals (1 ulp each)
+      a0 = recip(q0);
+      a1 = T(100) * recip(q1);
+      a2 = recip(q2);
+      inv = recip(a0 + a1 + a2);
+    } else {
+      // FP64: the same weights times q0 q1 q2 (no division), one division
+      // for the normalisation
+      a0 = q1 * q2;
+      a1 = T(100) * (q0 * q2);
+      a2 = q0 * q1;
+      inv = T(1) / (a0 + a1 + a2);
+    }
+    m[1] = (a0 * c0[1] + a1 * c1[1] + a2 * c2[1]) * inv;
+    m[2] = (a0 * c0[2] + a1 * c1[2] + a2 * c2[2]) * inv;
   } else {
     T c[4][4];
     ader_gen::Weno4<T>::cand0(d, c[0]);
     ader_gen::Weno4<T>::cand1(d, c[1]);
     ader_gen::Weno4<T>::cand2(d, c[2]);
     ader_gen::Weno4<T>::cand3(d, c[3]);
-    T a[4];
+    T qq[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const T t = c[s][1] + T(0.1) * c[s][3];
       const T is = t * t + T(13.0 / 3.0) * c[s][2] * c[s][2] + T(781.0 / 20.0) * c[s][3] * c[s][3];
       const T e = T(kEps) + is;
-      a[s] = ((s == 1 || s == 2) ? T(100) : T(1)) / (e * e);
+      qq[s] = e * e;
     }
-    const T tot = a[0] + a[1] + a[2] + a[3];
+    T a[4], inv;
+    if constexpr (sizeof(T) == 4) {
+      // FP32: lambda_s / q_s with hardware reciprocals (1 ulp each)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) a[s] = ((s == 1 || s == 2) ? T(100) : T(1)) * recip(qq[s]);
+      inv = recip(a[0] + a[1] + a[2] + a[3]);
+    } else {
+      // FP64: the same weights times q0 q1 q2 q3 (no division), one division
+      // for the normalisation
+      const T p01 = qq[0] * qq[1], p23 = qq[2] * qq[3];
+      a[0] = qq[1] * p23;
+      a[1] = T(100) * (qq[0] * p23);
+      a[2] = T(100) * (p01 * qq[3]);
+      a[3] = p01 * qq[2];
+      inv = T(1) / (a[0] + a[1] + a[2] + a[3]);
+    }
 #pragma unroll
     for (int q = 1; q < 4; ++q)
-      m[q] = (a[0] * c[0][q] + a[1] * c[1][q] + a[2] * c[2][q] + a[3] * c[3][q]) / tot;
+      m[q] = (a[0] * c[0][q] + a[1] * c[1][q] + a[2] * c[2][q] + a[3] * c[3][q]) * inv;
   }
 }
 
@@ -1025,6 +1054,90 @@ __host__ __device__ __forceinline__ void face_flux_zone(const double* __restrict
   face_flux_axis<T, RS, 0, DEV>(U, PK, F, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam);
   face_flux_axis<T, RS, 1, DEV>(U, PK, F, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam);
   face_flux_axis<T, RS, 2, DEV>(U, PK, F, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), gam);
+}
+
+// ---------------------------------------------------------------------------
+// Linear advection of five components, F_d(u) = a_d u: the test system on
+// which the scheme translates any data exactly at unit Courant number.  The
+// same predictor and face quadrature run with the linear flux (point form,
+// no positivity handling), and the face flux is the upwind limit of the HLL
+// flux of eq. (56), whose signal speeds are min(a_d, 0) and max(a_d, 0).
+// ---------------------------------------------------------------------------
+template <class T>
+struct AdvFlux {
+  static constexpr bool kDeviation = false;
+  static constexpr int comp(int c) { return c; }
+  T a[3];
+  template <int AXIS, int NV>
+  __host__ __device__ inline void flux(const T (&u)[NV], T (&f)[NV]) const {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[v] = a[AXIS] * u[v];
+  }
+};
+
+template <class T, int ORDER, int FORM>
+__host__ __device__ __forceinline__ void predict_zone_adv(const double* __restrict__ U,
+                                                          const T* __restrict__ W,
+                                                          T* __restrict__ PK, const Grid& g,
+                                                          double h, double inv_dx, double inv_dy,
+                                                          double inv_dz, double ax, double ay,
+                                                          double az, long long n) {
+  using S = typename SchemeOf<ORDER, FORM, T>::type;
+  constexpr int LS = S::LS, NE = S::NE;
+  T w[LS][5];
+  {
+    const double* q = U + n;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { w[0][v] = T(*q); q = next_row(q, g.S); }
+  }
+  {
+    const T* q = W + n;
+#pragma unroll
+    for (int m = 1; m < LS; ++m)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) { w[m][v] = *q; q = next_row(q, g.S); }
+  }
+  const AdvFlux<T> ph{{T(ax), T(ay), T(az)}};
+  T e[NE][5];
+  S::predict(w, e, T(h * inv_dx), T(h * inv_dy), T(h * inv_dz), ph);
+  NoScan none;
+  T* q = PK + n;
+  store_side<S, T, 0>(w, e, ph, none, q, g.S);
+  store_side<S, T, 1>(w, e, ph, none, q, g.S);
+  store_side<S, T, 2>(w, e, ph, none, q, g.S);
+  store_side<S, T, 3>(w, e, ph, none, q, g.S);
+  store_side<S, T, 4>(w, e, ph, none, q, g.S);
+  store_side<S, T, 5>(w, e, ph, none, q, g.S);
+}
+
+// Flux at the lower AXIS-face of zone n: the upper side's face-averaged
+// flux of the lower zone nl for a > 0, this zone's lower side's for a < 0.
+template <class T, int AXIS>
+__host__ __device__ __forceinline__ void face_flux_adv_axis(const T* __restrict__ PK,
+                                                            double* __restrict__ F, const Grid& g,
+                                                            long long n, long long nl, double a) {
+  constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;
+  double* qf = F + (long long)(AXIS * 5) * g.S + n;
+  const T* q = a > 0.0 ? PK + (long long)(SL * 15 + 10) * g.S + nl
+                       : PK + (long long)(SR * 15 + 10) * g.S + n;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    *qf = a != 0.0 ? double(*q) : 0.0;
+    qf = next_row(qf, g.S);
+    q = next_row(q, g.S);
+  }
+}
+
+template <class T>
+__host__ __device__ __forceinline__ void face_flux_adv_zone(const T* __restrict__ PK,
+                                                            double* __restrict__ F, const Grid& g,
+                                                            double ax, double ay, double az,
+                                                            long long n) {
+  int i, j, k;
+  zone_ijk(g, n, i, j, k);
+  face_flux_adv_axis<T, 0>(PK, F, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), ax);
+  face_flux_adv_axis<T, 1>(PK, F, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), ay);
+  face_flux_adv_axis<T, 2>(PK, F, g, n, zone_of(i, j, wrap(k - 1, g.nz), g), az);
 }
 
 // eq. (6) in double: U -= dt/dx (F_{i+1/2} - F_{i-1/2}) + ... (y, z)

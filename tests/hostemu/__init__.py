@@ -21,6 +21,34 @@ _lib = None
 PRECISION = {"fp64": 0, "mixed": 1, "fp64dev": 2}
 
 
+# The same source built with the address and undefined-behaviour sanitizers
+# on the host code (there is no device code in this build), for the CPU
+# test that runs the kernel code under them in a child process.
+SAN_LIB = os.path.join(HERE, "libader_hostemu_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(force=False):
+    stale = force or not os.path.exists(SAN_LIB) or any(
+        os.path.getmtime(d) > os.path.getmtime(SAN_LIB) for d in DEPS)
+    if stale:
+        tmp = "%s.tmp%d" % (SAN_LIB, os.getpid())
+        subprocess.run(["hipcc", "-x", "hip", "--offload-host-only", "-O0", "-std=c++17", "-fPIC",
+                        "-shared"] + SAN_FLAGS + ["-o", tmp, SRC], check=True)
+        os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
+def sanitizer_runtime():
+    """The clang address-sanitizer runtime the sanitized build needs preloaded."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(subprocess.check_output(
+        ["bash", "-c", "command -v hipcc"], text=True).strip())), "..", "lib", "llvm", "bin",
+        "clang")
+    res = subprocess.check_output([clang, "-print-resource-dir"], text=True).strip()
+    return os.path.join(res, "lib", "linux", "libclang_rt.asan-x86_64.so")
+
+
 def build(force=False):
     stale = force or not os.path.exists(LIB) or any(
         os.path.getmtime(d) > os.path.getmtime(LIB) for d in DEPS)
@@ -35,8 +63,12 @@ def build(force=False):
 def load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(LIB)
+        # ADER_HOSTEMU_LIB: another build of the same source (the sanitized one)
+        path = os.environ.get("ADER_HOSTEMU_LIB")
+        if not path:
+            path = LIB
+            build()
+        lib = ctypes.CDLL(path)
         D, I = ctypes.c_double, ctypes.c_int
         DP = ctypes.POINTER(ctypes.c_double)
         lib.hostemu_step.argtypes = [DP, I, I, I, D, D, D, D, I, I, I, I, D]
