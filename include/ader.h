@@ -142,6 +142,25 @@ enum { ADER_POSITIVITY_CHECK = 0, ADER_POSITIVITY_LIMIT = 1 };
  * context; ADER_EINVAL for a non-finite entry or b without A. */
 int ader_set_source(ader_ctx* ctx, const double* A, const double* b);
 
+/* Non-periodic faces (Euler; every problem of the context): bc[6] gives the
+ * kinds of the faces x-, x+, y-, y+, z-, z+: ADER_BC_PERIODIC (the default;
+ * both faces of an axis or neither), ADER_BC_OUTFLOW (zero gradient) or
+ * ADER_BC_REFLECT (a wall).  The paper describes no boundary treatment; the
+ * reading here is the usual one of ghost zones: each bounded face gets four
+ * layers of zones outside the problem, filled before every step (and every
+ * dt rule) from the interior zone averages -- outflow the nearest interior
+ * zone, reflect the mirror-image zone with the normal momentum negated --
+ * and the periodic step then runs on the padded mesh, whose periodic wrap
+ * reaches no interior result.  Zones two or more layers out reach no
+ * interior face: their positivity outcomes are neither reported nor
+ * counted.  The caller's arrays keep the interior layout; device memory
+ * grows by the ghost layers.  Must come before the first state is set
+ * (ADER_ESEQ after, or on a context with a bound device state); a bounded
+ * axis needs at least 4 zones (ADER_EINVAL); ADER_EUNSUPPORTED for MHD and
+ * linear advection, and at the step for the SSP-RK scheme. */
+enum { ADER_BC_PERIODIC = 0, ADER_BC_OUTFLOW = 1, ADER_BC_REFLECT = 2 };
+int ader_set_boundary(ader_ctx* ctx, const int* bc);
+
 /* Velocity a of an ADER_LINADV context (ADER_EUNSUPPORTED for the other
  * systems; ADER_EINVAL for a non-finite component or a = 0). */
 int ader_set_advection(ader_ctx* ctx, double ax, double ay, double az);

@@ -19,6 +19,7 @@ ADER_ESTATE = -5
 ADER_ESEQ = -6
 
 ADER_EULER, ADER_MHD, ADER_LINADV = 0, 1, 2
+ADER_BC_PERIODIC, ADER_BC_OUTFLOW, ADER_BC_REFLECT = 0, 1, 2
 ADER_HLL, ADER_LINEARIZED = 0, 1
 ADER_MODAL, ADER_NODAL = 0, 1
 ADER_FP64, ADER_MIXED = 0, 1
@@ -35,7 +36,7 @@ EXPORTS = [
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
-    "ader_diagnostics_noalloc", "ader_set_source", "ader_set_advection",
+    "ader_diagnostics_noalloc", "ader_set_source", "ader_set_advection", "ader_set_boundary",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
@@ -116,6 +117,7 @@ def load():
         "ader_diagnostics_noalloc": ([P, DP, DP], I),
         "ader_set_source": ([P, DP, DP], I),
         "ader_set_advection": ([P, D, D, D], I),
+        "ader_set_boundary": ([P, ctypes.POINTER(I)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +269,13 @@ def ader_diagnostics(ctx, n=1):
     div = np.empty(n, dtype=np.float64)
     _check(load().ader_diagnostics(ctx, _dptr(tot), _dptr(div)), "ader_diagnostics")
     return tot, div
+
+
+def ader_set_boundary(ctx, bc):
+    """Kinds of the faces x-, x+, y-, y+, z-, z+ (ADER_BC_*), before the
+    first state is set."""
+    arr = (ctypes.c_int * 6)(*[int(x) for x in bc])
+    _check(load().ader_set_boundary(ctx, arr), "ader_set_boundary")
 
 
 def ader_set_advection(ctx, a):
@@ -430,7 +439,7 @@ class BatchSolver:
 
     def __init__(self, shapes, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3, form=ADER_MODAL,
                  riemann=ADER_HLL, precision=ADER_FP64, device=0, stream=None,
-                 system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK):
+                 system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK, boundary=None):
         if lengths and not isinstance(lengths[0], (tuple, list)):
             lengths = [lengths] * len(shapes)
         self.shapes = [tuple(s) for s in shapes]
@@ -438,6 +447,8 @@ class BatchSolver:
         meshes = [(s[2], s[1], s[0]) + tuple(L) for s, L in zip(self.shapes, lengths)]
         self.ctx = ader_batch_create(meshes, system=system, device=device, stream=stream)
         try:
+            if boundary is not None:
+                ader_set_boundary(self.ctx, boundary)
             _configure(self.ctx, gamma, order, form, riemann, precision, positivity)
         except Exception:
             self.close()
@@ -499,12 +510,15 @@ class Solver:
 
     def __init__(self, shape, lengths=(1.0, 1.0, 1.0), gamma=1.4, order=3,
                  form=ADER_MODAL, riemann=ADER_HLL, precision=ADER_FP64,
-                 device=0, stream=None, system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK):
+                 device=0, stream=None, system=ADER_EULER, positivity=ADER_POSITIVITY_CHECK,
+                 boundary=None):
         nz, ny, nx = shape
         self.shape = (5, nz, ny, nx)
         self.mhd = system == ADER_MHD
         self.ctx = ader_create(nx, ny, nz, *lengths, system=system, device=device, stream=stream)
         try:
+            if boundary is not None:
+                ader_set_boundary(self.ctx, boundary)
             _configure(self.ctx, gamma, order, form, riemann, precision, positivity)
         except Exception:
             self.close()

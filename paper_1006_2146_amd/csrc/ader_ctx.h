@@ -18,7 +18,23 @@ struct Problem {
   int nx, ny, nz, pad;
   long long N, base;
   double dx, dy, dz;
+  // non-periodic faces: ghost layers before the interior along each axis
+  // (0 on periodic axes; nx, ny, nz then count them), the interior size,
+  // and the kinds of the faces x-, x+, y-, y+, z-, z+ (ADER_BC_*)
+  int gx, gy, gz, ux, uy, uz;
+  int bc[6];
 };
+
+// ghost layers on each non-periodic face (enough for order 4)
+constexpr int kGhost = 4;
+
+// zone (i, j, k) of a padded problem is a ghost zone (diagnostics sum the
+// interior only)
+__host__ __device__ inline bool ghost_zone(const Problem& pr, int i, int j, int k) {
+  return (pr.gx && (i < pr.gx || i >= pr.gx + pr.ux)) ||
+         (pr.gy && (j < pr.gy || j >= pr.gy + pr.uy)) ||
+         (pr.gz && (k < pr.gz || k >= pr.gz + pr.uz));
+}
 
 // Kernel argument: the device problem table and the array stride.
 struct Batch {
@@ -78,6 +94,10 @@ struct ader_ctx {
   std::vector<ader::Problem> probs;
   ader::Problem* d_probs = nullptr;
   long long S = 0;                 // total zones (array stride)
+  // non-periodic faces (ader_set_boundary): some problem has ghost zones;
+  // the caller's arrays hold the interiors only, S_user zones in all
+  bool bounded = false;
+  long long S_user = 0;
   double gamma = 1.4;
   int system = ADER_EULER;
   int order = 3, form = ADER_MODAL, riemann = ADER_HLL, precision = ADER_FP64;
@@ -161,8 +181,10 @@ struct ader_ctx {
   double* d_diag = nullptr;
 
   ader::Batch batch() const { return ader::Batch{d_probs, (int)probs.size(), S}; }
+  // flags and counts of problem p at [p], sink slots of its deep ghost
+  // zones at [np + p]
   ader::PosCtl pos() const {
-    return ader::PosCtl{positivity == ADER_POSITIVITY_LIMIT ? 1 : 0, d_bad, d_limited};
+    return ader::PosCtl{positivity == ADER_POSITIVITY_LIMIT ? 1 : 0, d_bad, d_limited, np()};
   }
   int np() const { return (int)probs.size(); }
 };

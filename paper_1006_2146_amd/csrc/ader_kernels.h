@@ -12,6 +12,44 @@
 
 namespace ader {
 
+// Ghost zones of bounded problems (non-periodic faces; ader_set_boundary).
+// A padded index along an axis of g ghost layers before u interior zones
+// maps to the interior zone whose average it takes: outflow the nearest one,
+// reflect the mirror image (sign negated for the normal momentum).
+__host__ __device__ __forceinline__ int ghost_source(int i, int g, int u, int lo, int hi,
+                                                     double& sign) {
+  if (g == 0) return i;
+  if (i < g) {
+    if (lo == ADER_BC_OUTFLOW) return g;
+    sign = -sign;
+    return 2 * g - 1 - i;
+  }
+  if (i >= g + u) {
+    if (hi == ADER_BC_OUTFLOW) return g + u - 1;
+    sign = -sign;
+    return 2 * (g + u) - 1 - i;
+  }
+  return i;
+}
+
+// A zone two or more layers outside the interior along a bounded axis: its
+// polynomials reach no interior face (a step updates only the interior;
+// the ghosts are filled again before the next), so its positivity outcome
+// goes to the problem's sink slots.
+__device__ __forceinline__ bool deep_ghost(const Problem& pr, long long n) {
+  if (!(pr.gx | pr.gy | pr.gz)) return false;
+  const long long l = n - pr.base;
+  const int i = (int)(l % pr.nx), j = (int)((l / pr.nx) % pr.ny);
+  const int k = (int)(l / ((long long)pr.nx * pr.ny));
+  return (pr.gx && (i < pr.gx - 1 || i > pr.gx + pr.ux)) ||
+         (pr.gy && (j < pr.gy - 1 || j > pr.gy + pr.uy)) ||
+         (pr.gz && (k < pr.gz - 1 || k > pr.gz + pr.uz));
+}
+
+__device__ __forceinline__ PosCtl pos_at(const PosCtl& pc, int p, const Problem& pr, long long n) {
+  return deep_ghost(pr, n) ? pc.sunk(p) : pc.at(p);
+}
+
 // The FP32 (mixed-precision) kernels run the deviation form, the FP64 ones
 // the point form.  Kernels without a natural template parameter take a
 // dummy one, so this header can go into several translation units.
@@ -57,6 +95,27 @@ __device__ __forceinline__ void for_zones(const Batch& b, Body&& body) {
     while (n >= pr.base + pr.N) pr = b.P[++p];
     body(pr, p, n);
   }
+}
+
+// Fills the ghost zones of bounded problems from the interior (ghost_source)
+template <int = 0>
+__global__ void __launch_bounds__(256) k_fill_ghosts(double* __restrict__ U, Batch b) {
+  for_zones(b, [&](const Problem& pr, int, long long n) {
+    if (!(pr.gx | pr.gy | pr.gz)) return;
+    const Grid g = grid_of(pr, b);
+    int i, j, k;
+    zone_ijk(g, n, i, j, k);
+    double s[3] = {1.0, 1.0, 1.0};
+    const int si = ghost_source(i, pr.gx, pr.ux, pr.bc[0], pr.bc[1], s[0]);
+    const int sj = ghost_source(j, pr.gy, pr.uy, pr.bc[2], pr.bc[3], s[1]);
+    const int sk = ghost_source(k, pr.gz, pr.uz, pr.bc[4], pr.bc[5], s[2]);
+    if (si == i && sj == j && sk == k) return;   // an interior zone
+    const long long src = zone_of(si, sj, sk, g);
+    U[n] = U[src];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[(long long)(1 + d) * b.S + n] = s[d] * U[(long long)(1 + d) * b.S + src];
+    U[4 * b.S + n] = U[4 * b.S + src];
+  });
 }
 
 template <class T, int M, int AXIS, int NVAR>
@@ -155,7 +214,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
                                                  double gam, PosCtl pc) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
-                                                       1.0 / pr.dy, 1.0 / pr.dz, gam, pc.at(p), n);
+                                                       1.0 / pr.dy, 1.0 / pr.dz, gam, pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -194,7 +253,8 @@ __global__ void __launch_bounds__(kTile * kTile * TZ) k_recon_predict(
     if (i0 + tx < pr.nx && j0 + ty < pr.ny && k0 + tz < pr.nz)
       predict_zone_lds<T, ORDER, FORM, kDeviation<T>>(U, sw + t, RL::NZ, PK, g, dt[p],
                                                       1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
-                                                      pc.at(p), zone_of(i0 + tx, j0 + ty, k0 + tz, g));
+                                                      pos_at(pc, p, pr, zone_of(i0 + tx, j0 + ty, k0 + tz, g)),
+                                                      zone_of(i0 + tx, j0 + ty, k0 + tz, g));
     __syncthreads();   // the next tile overwrites the LDS
   }
 }
@@ -230,7 +290,7 @@ __global__ void __launch_bounds__(256) k_predict_src(const double* __restrict__ 
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone<T, ORDER, FORM, kDeviation<T>, true, true>(U, W, PK, grid_of(pr, b), dt[p],
                                                             1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz,
-                                                            gam, pc.at(p), n, &src, SB);
+                                                            gam, pos_at(pc, p, pr, n), n, &src, SB);
   });
 }
 
@@ -246,7 +306,7 @@ __global__ void __launch_bounds__(256) k_predict_mhd(const double* __restrict__ 
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone_mhd<T, ORDER, FORM, kDeviation<T>, FUSED, EDGES_ALL>(U, W, B0, WB, BN, PK, grid_of(pr, b),
                                                            dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
-                                                           1.0 / pr.dz, gam, pc.at(p), n);
+                                                           1.0 / pr.dz, gam, pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -285,7 +345,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, PK, grid_of(pr, b), dt[p],
                                                       1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
-                                                      pc.at(p), n);
+                                                      pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -301,7 +361,7 @@ __global__ void __launch_bounds__(256) k_predict_split_src(const double* __restr
   for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_split<T, ORDER, FORM, kDeviation<T>, true>(L, U, W, PK, grid_of(pr, b), dt[p],
                                                             1.0 / pr.dx, 1.0 / pr.dy,
-                                                            1.0 / pr.dz, gam, pc.at(p), n, &src,
+                                                            1.0 / pr.dz, gam, pos_at(pc, p, pr, n), n, &src,
                                                             SB);
   });
 }
@@ -314,7 +374,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   for_zone_groups<8>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_mhd_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, B0, WB, BN, PK, grid_of(pr, b),
                                                           dt[p], 1.0 / pr.dx, 1.0 / pr.dy,
-                                                          1.0 / pr.dz, gam, pc.at(p), n);
+                                                          1.0 / pr.dz, gam, pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -344,7 +404,7 @@ __global__ void __launch_bounds__(256) k_rk_sides(const double* __restrict__ U,
                                                   const T* __restrict__ W, T* __restrict__ PK,
                                                   Batch b, double gam, PosCtl pc) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
-    rk_sides_zone<T, ORDER, kDeviation<T>>(U, W, PK, grid_of(pr, b), gam, pc.at(p), n);
+    rk_sides_zone<T, ORDER, kDeviation<T>>(U, W, PK, grid_of(pr, b), gam, pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -369,7 +429,7 @@ __global__ void __launch_bounds__(256) k_rk_sides_mhd(const double* __restrict__
                                                       PosCtl pc) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
     predict_zone_mhd<T, ORDER, 0, kDeviation<T>, true, EDGES_ALL, true>(
-        U, W, B0, WB, BN, PK, grid_of(pr, b), 0.0, 0.0, 0.0, 0.0, gam, pc.at(p), n);
+        U, W, B0, WB, BN, PK, grid_of(pr, b), 0.0, 0.0, 0.0, 0.0, gam, pos_at(pc, p, pr, n), n);
   });
 }
 
@@ -403,7 +463,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES)
   for_zone_groups<2>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
     predict_zone_mhd_pair<T, ORDER, FORM, kDeviation<T>, EDGES_ALL, PHASE>(
         L, U, W, B0, WB, BN, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz,
-        gam, pc.at(p), n, EM, TH);
+        gam, pos_at(pc, p, pr, n), n, EM, TH);
   });
 }
 

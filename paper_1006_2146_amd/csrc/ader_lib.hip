@@ -71,8 +71,18 @@ struct StageTimer {
   }
 };
 
+// Ghost zones of bounded problems from the current interior (before the dt
+// rule and each step reads them).
+int fill_ghosts(ader_ctx* c) {
+  if (!c->bounded) return ADER_OK;
+  k_fill_ghosts<><<<grid_for(c, kClassUpdate), c->shape[kClassUpdate].block, 0, c->stream>>>(
+      c->U, c->batch());
+  return launched();
+}
+
 int queue_dt(ader_ctx* c, double cfl) {
   StageTimer t(c, ADER_STAGE_DT);
+  ADER_TRY(fill_ghosts(c));
   if (c->system == ADER_LINADV) {
     k_dt_adv<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->batch(), cfl, c->adv[0], c->adv[1],
                                                            c->adv[2], c->d_dt);
@@ -221,7 +231,7 @@ int queue_step(ader_ctx* c) {
   const StageFns* s = stages_of(c);
   if (!s) return ADER_EUNSUPPORTED;
   if (c->scheme == ADER_SCHEME_SSPRK)
-    return c->has_source ? ADER_EUNSUPPORTED : queue_rk_step(c, s);
+    return (c->has_source || c->bounded) ? ADER_EUNSUPPORTED : queue_rk_step(c, s);
   // the fused layout reconstructs inside its predictor kernel
   if (layout_of(c, s) != ADER_LAYOUT_FUSED) {
     StageTimer t(c, ADER_STAGE_RECON);
@@ -445,6 +455,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
   c->system = system;
   c->stream = static_cast<hipStream_t>(stream);
   c->S = S;
+  c->S_user = S;
   long long base = 0;
   for (int q = 0; q < n; ++q) {
     const ader_mesh& m = meshes[q];
@@ -457,6 +468,9 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     pr.dx = m.lx / m.nx;
     pr.dy = m.ly / m.ny;
     pr.dz = m.lz / m.nz;
+    pr.ux = m.nx;
+    pr.uy = m.ny;
+    pr.uz = m.nz;
     base += pr.N;
     c->probs.push_back(pr);
   }
@@ -484,8 +498,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
                       hipMalloc(&c->E, s3) == hipSuccess)) &&
             hipMalloc(&c->d_probs, sP) == hipSuccess && hipMalloc(&c->d_dt, sD) == hipSuccess &&
             hipMalloc(&c->d_rate, sizeof(unsigned long long) * n) == hipSuccess &&
-            hipMalloc(&c->d_bad, sizeof(int) * n) == hipSuccess &&
-            hipMalloc(&c->d_limited, sizeof(unsigned int) * n) == hipSuccess &&
+            hipMalloc(&c->d_bad, sizeof(int) * 2 * n) == hipSuccess &&
+            hipMalloc(&c->d_limited, sizeof(unsigned int) * 2 * n) == hipSuccess &&
             hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_ftile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_xytile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
@@ -497,7 +511,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     (void)hipGetLastError();
     return ADER_ENOMEM;
   }
-  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + (sizeof(int) + sizeof(unsigned int)) * n +
+  c->fixed_bytes = sU + sF + sM + sP + 2 * sD + (sizeof(int) + sizeof(unsigned int)) * 2 * n +
                    5 * sizeof(long long) * (n + 1);
   c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
@@ -552,8 +566,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
       hipMemcpy(c->d_probs, c->probs.data(), sP, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_dt, 0, sD) != hipSuccess ||
       hipMemset(c->d_rate, 0, sizeof(unsigned long long) * n) != hipSuccess ||
-      hipMemset(c->d_bad, 0, sizeof(int) * n) != hipSuccess ||
-      hipMemset(c->d_limited, 0, sizeof(unsigned int) * n) != hipSuccess ||
+      hipMemset(c->d_bad, 0, sizeof(int) * 2 * n) != hipSuccess ||
+      hipMemset(c->d_limited, 0, sizeof(unsigned int) * 2 * n) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     free_buffers(c);
     delete c;
@@ -564,6 +578,38 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
 }
 
 // Copy problem q's host arrays (U[5][N], B[3][N]) into the batch layout.
+// The caller's view of a bounded problem: its interior, at base ub of rows
+// of the caller's stride.
+Problem user_view(const Problem& pr, long long ub) {
+  Problem u = pr;
+  u.nx = pr.ux;
+  u.ny = pr.uy;
+  u.nz = pr.uz;
+  u.N = (long long)pr.ux * pr.uy * pr.uz;
+  u.base = ub;
+  return u;
+}
+
+// interior rows between the caller's layout (rows of stride us, problem at
+// ub) and a padded host copy [5][N] of the problem
+void pack_interior(const Problem& pr, const double* src, long long us, long long ub, double* dst) {
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < pr.uz; ++k)
+      for (int j = 0; j < pr.uy; ++j)
+        std::memcpy(dst + v * pr.N + ((long long)(k + pr.gz) * pr.ny + j + pr.gy) * pr.nx + pr.gx,
+                    src + v * us + ub + ((long long)k * pr.uy + j) * pr.ux,
+                    sizeof(double) * pr.ux);
+}
+
+void unpack_interior(const Problem& pr, const double* src, double* dst, long long us, long long ub) {
+  for (int v = 0; v < 5; ++v)
+    for (int k = 0; k < pr.uz; ++k)
+      for (int j = 0; j < pr.uy; ++j)
+        std::memcpy(dst + v * us + ub + ((long long)k * pr.uy + j) * pr.ux,
+                    src + v * pr.N + ((long long)(k + pr.gz) * pr.ny + j + pr.gy) * pr.nx + pr.gx,
+                    sizeof(double) * pr.ux);
+}
+
 int put_problem(ader_ctx* c, int q, const double* U, const double* B) {
   const Problem& pr = c->probs[q];
   const size_t bytes = sizeof(double) * (size_t)pr.N;
@@ -758,6 +804,27 @@ int ader_set_state(ader_ctx* c, const double* U, const double* B) {
   if (!c || !U) return ADER_EINVAL;
   const bool mhd = c->system == ADER_MHD;
   if (mhd != (B != nullptr)) return ADER_EINVAL;
+  if (c->bounded) {
+    long long ub = 0;
+    for (const Problem& pr : c->probs) {
+      if (!host_state_ok(U, nullptr, user_view(pr, ub), c->S_user, c->gamma)) return ADER_ESTATE;
+      ub += (long long)pr.ux * pr.uy * pr.uz;
+    }
+    ADER_TRY(set_device(c));
+    std::vector<double> hb;
+    ub = 0;
+    for (int q = 0; q < c->np(); ++q) {
+      const Problem& pr = c->probs[q];
+      hb.assign((size_t)5 * pr.N, 0.0);
+      pack_interior(pr, U, c->S_user, ub, hb.data());
+      ADER_TRY(put_problem(c, q, hb.data(), nullptr));
+      ADER_TRY(check(hipStreamSynchronize(c->stream)));
+      ub += (long long)pr.ux * pr.uy * pr.uz;
+    }
+    c->set_flags.assign(c->np(), 1);
+    c->have_state = true;
+    return ADER_OK;
+  }
   for (const Problem& pr : c->probs)
     if (!host_state_ok(U, B, pr, c->S, c->gamma, c->system != ADER_LINADV)) return ADER_ESTATE;
   ADER_TRY(set_device(c));
@@ -778,6 +845,19 @@ int ader_batch_set_state(ader_ctx* c, int i, const double* U, const double* B) {
   if (mhd != (B != nullptr)) return ADER_EINVAL;
   Problem lone = c->probs[i];
   lone.base = 0;
+  if (c->bounded) {
+    const Problem uv = user_view(lone, 0);
+    if (!host_state_ok(U, nullptr, uv, uv.N, c->gamma)) return ADER_ESTATE;
+    ADER_TRY(set_device(c));
+    std::vector<double> hb((size_t)5 * lone.N, 0.0);
+    pack_interior(lone, U, uv.N, 0, hb.data());
+    ADER_TRY(put_problem(c, i, hb.data(), nullptr));
+    ADER_TRY(check(hipStreamSynchronize(c->stream)));
+    c->set_flags[i] = 1;
+    c->have_state = std::all_of(c->set_flags.begin(), c->set_flags.end(),
+                                [](char f) { return f != 0; });
+    return ADER_OK;
+  }
   if (!host_state_ok(U, B, lone, lone.N, c->gamma, c->system != ADER_LINADV)) return ADER_ESTATE;
   ADER_TRY(set_device(c));
   ADER_TRY(put_problem(c, i, U, B));
@@ -789,6 +869,7 @@ int ader_batch_set_state(ader_ctx* c, int i, const double* U, const double* B) {
 
 int ader_bind_device_state(ader_ctx* c, void* dU, void* dB) {
   if (!c || !dU) return ADER_EINVAL;
+  if (c->bounded) return ADER_EUNSUPPORTED;   // the device layout holds ghost zones
   const bool mhd = c->system == ADER_MHD;
   if (mhd != (dB != nullptr)) return ADER_EINVAL;
   if (c->owns_U && c->U) (void)hipFree(c->U);
@@ -808,6 +889,18 @@ int ader_get_state(ader_ctx* c, double* U, double* B) {
   if (!c || !U) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
+  if (c->bounded) {
+    std::vector<double> hb;
+    long long ub = 0;
+    for (int q = 0; q < c->np(); ++q) {
+      const Problem& pr = c->probs[q];
+      hb.resize((size_t)5 * pr.N);
+      ADER_TRY(get_problem(c, q, hb.data(), nullptr));
+      unpack_interior(pr, hb.data(), U, c->S_user, ub);
+      ub += (long long)pr.ux * pr.uy * pr.uz;
+    }
+    return ADER_OK;
+  }
   ADER_TRY(check(hipMemcpyAsync(U, c->U, sizeof(double) * 5 * (size_t)c->S, hipMemcpyDeviceToHost,
                                 c->stream)));
   if (B && c->system == ADER_MHD)
@@ -820,6 +913,13 @@ int ader_batch_get_state(ader_ctx* c, int i, double* U, double* B) {
   if (!c || !U || i < 0 || i >= c->np()) return ADER_EINVAL;
   if (!c->have_state) return ADER_ESEQ;
   ADER_TRY(set_device(c));
+  if (c->bounded) {
+    const Problem& pr = c->probs[i];
+    std::vector<double> hb((size_t)5 * pr.N);
+    ADER_TRY(get_problem(c, i, hb.data(), nullptr));
+    unpack_interior(pr, hb.data(), U, (long long)pr.ux * pr.uy * pr.uz, 0);
+    return ADER_OK;
+  }
   return get_problem(c, i, U, B);
 }
 
@@ -844,6 +944,7 @@ int ader_step(ader_ctx* c, double dt) {
   ADER_TRY(ensure_work(c));
   k_set_dt<><<<(c->np() + 63) / 64, 64, 0, c->stream>>>(c->d_dt, c->np(), dt);
   ADER_TRY(launched());
+  ADER_TRY(fill_ghosts(c));
   c->have_dt = true;
   return queue_step(c);
 }
@@ -965,6 +1066,78 @@ int ader_set_advection(ader_ctx* c, double ax, double ay, double az) {
   c->adv[0] = ax;
   c->adv[1] = ay;
   c->adv[2] = az;
+  return ADER_OK;
+}
+
+int ader_set_boundary(ader_ctx* c, const int* bc) {
+  if (!c || !bc) return ADER_EINVAL;
+  for (int f = 0; f < 6; ++f)
+    if (bc[f] != ADER_BC_PERIODIC && bc[f] != ADER_BC_OUTFLOW && bc[f] != ADER_BC_REFLECT)
+      return ADER_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if ((bc[2 * a] == ADER_BC_PERIODIC) != (bc[2 * a + 1] == ADER_BC_PERIODIC)) return ADER_EINVAL;
+  if (c->system != ADER_EULER) return ADER_EUNSUPPORTED;
+  if (c->bounded || !c->owns_U ||
+      std::any_of(c->set_flags.begin(), c->set_flags.end(), [](char f) { return f != 0; }))
+    return ADER_ESEQ;
+  const bool bnd[3] = {bc[0] != ADER_BC_PERIODIC, bc[2] != ADER_BC_PERIODIC,
+                       bc[4] != ADER_BC_PERIODIC};
+  if (!bnd[0] && !bnd[1] && !bnd[2]) return ADER_OK;
+  // the padded meshes: kGhost layers on each bounded face, the zone size kept
+  std::vector<ader_mesh> meshes;
+  for (const Problem& pr : c->probs) {
+    if ((bnd[0] && pr.ux < kGhost) || (bnd[1] && pr.uy < kGhost) || (bnd[2] && pr.uz < kGhost))
+      return ADER_EINVAL;
+    ader_mesh m;
+    m.nx = pr.ux + (bnd[0] ? 2 * kGhost : 0);
+    m.ny = pr.uy + (bnd[1] ? 2 * kGhost : 0);
+    m.nz = pr.uz + (bnd[2] ? 2 * kGhost : 0);
+    m.lx = pr.dx * m.nx;
+    m.ly = pr.dy * m.ny;
+    m.lz = pr.dz * m.nz;
+    meshes.push_back(m);
+  }
+  ADER_TRY(set_device(c));
+  ADER_TRY(check(hipStreamSynchronize(c->stream)));
+  ader_ctx* t = nullptr;
+  ADER_TRY(create(c->np(), meshes.data(), c->system, c->device, c->stream, &t));
+  for (int q = 0; q < t->np(); ++q) {
+    Problem& pr = t->probs[q];
+    pr.ux = c->probs[q].ux;
+    pr.uy = c->probs[q].uy;
+    pr.uz = c->probs[q].uz;
+    pr.dx = c->probs[q].dx;
+    pr.dy = c->probs[q].dy;
+    pr.dz = c->probs[q].dz;
+    pr.gx = bnd[0] ? kGhost : 0;
+    pr.gy = bnd[1] ? kGhost : 0;
+    pr.gz = bnd[2] ? kGhost : 0;
+    for (int f = 0; f < 6; ++f) pr.bc[f] = bc[f];
+  }
+  if (hipMemcpy(t->d_probs, t->probs.data(), sizeof(Problem) * t->probs.size(),
+                hipMemcpyHostToDevice) != hipSuccess) {
+    ader_destroy(t);
+    return ADER_EDEVICE;
+  }
+  // the settings carry over; the new layout's buffers replace the old ones
+  t->gamma = c->gamma;
+  t->order = c->order;
+  t->form = c->form;
+  t->riemann = c->riemann;
+  t->precision = c->precision;
+  t->positivity = c->positivity;
+  t->layout = c->layout;
+  t->recon_mode = c->recon_mode;
+  t->scheme = c->scheme;
+  t->use_graph = c->use_graph;
+  for (int q = 0; q < kNumClasses; ++q) t->shape[q] = c->shape[q];
+  t->has_source = c->has_source;
+  t->source = c->source;
+  t->source_version = c->source_version;
+  t->bounded = true;
+  t->S_user = c->S_user;
+  std::swap(*c, *t);
+  ader_destroy(t);
   return ADER_OK;
 }
 

@@ -28,6 +28,11 @@ constexpr int kDiagThreads = 256;
 __device__ __forceinline__ void diag_zone(const double* __restrict__ U,
                                           const double* __restrict__ B, const Grid& g,
                                           const Problem& pr, long long n, double (&acc)[kDiagVals]) {
+  if (pr.gx | pr.gy | pr.gz) {   // bounded problem: its interior only
+    int i, j, k;
+    zone_ijk(g, n, i, j, k);
+    if (ghost_zone(pr, i, j, k)) return;
+  }
 #pragma unroll
   for (int v = 0; v < 5; ++v) acc[v] += U[(long long)v * g.S + n];
   if (!B) return;
@@ -108,7 +113,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag_final(const double* __res
   block_tree(s);
   if (threadIdx.x == 0) {
     const Problem pr = b.P[p];
-    const double vol = pr.dx * pr.dy * pr.dz;
+    const double vol = pr.dx * pr.dy * pr.dz;   // (a padded problem keeps the zone size)
 #pragma unroll
     for (int v = 0; v < kDiagVals - 1; ++v) totals[p * (kDiagVals - 1) + v] = s[0][v] * vol;
     maxdiv[p] = s[0][kDiagVals - 1];

@@ -296,7 +296,11 @@ struct PosCtl {
   int limit;
   int* bad;
   unsigned int* limited;
-  __host__ __device__ PosCtl at(int p) const { return PosCtl{limit, bad + p, limited + p}; }
+  int sink;   // offset of the sink slots (outcomes that must not count)
+  __host__ __device__ PosCtl at(int p) const { return PosCtl{limit, bad + p, limited + p, 0}; }
+  __host__ __device__ PosCtl sunk(int p) const {
+    return PosCtl{limit, bad + sink + p, limited + sink + p, 0};
+  }
 };
 
 // Outcome of the exact pass of a zone: true if its modes are to be scaled by
