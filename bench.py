@@ -44,6 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # written once (Euler 5, MHD 8 variables)
 STATE_BYTES_PER_ZONE = {"euler": 80, "mhd": 128}
 RECON_NAMES = ["sweeps", "tiled", "columns", "march"]
+FLUX_NAMES = ["separate", "fused-update"]
 LAYOUT_NAMES = {0: "zone", 1: "split", 2: "split-2waves", 3: "zone-prescan", 4: "zone-2waves",
                 5: "pair", 6: "pair-2waves", 7: "pair-2kernels", 8: "fused-recon"}
 METRIC = "zone-updates/sec, 3D ADER-WENO3/4 Euler+MHD; mixed-prec batched vs FP64"
@@ -75,11 +76,13 @@ class Tuning:
             ader.ader_set_launch(ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
             ader.ader_set_layout(ctx, cfg["layout"])
             ader.ader_set_recon(ctx, cfg["recon"])
+            ader.ader_set_flux_mode(ctx, cfg.get("flux", -1))
         else:
             ader.ader_autotune(ctx, 4)
             self.saved[key] = {"launch": ader.ader_get_launch(ctx),
                                "layout": ader.ader_get_layout(ctx),
-                               "recon": ader.ader_get_recon(ctx)}
+                               "recon": ader.ader_get_recon(ctx),
+                               "flux": ader.ader_get_flux_mode(ctx)}
 
     def write(self):
         if self.path and not self.reuse:
@@ -190,6 +193,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         launch = ader.ader_get_launch(s.ctx)
         layout = LAYOUT_NAMES[ader.ader_get_layout(s.ctx)]
         recon_mode = RECON_NAMES[ader.ader_get_recon(s.ctx)]
+        flux_mode = FLUX_NAMES[ader.ader_get_flux_mode(s.ctx)]
     finally:
         s.close()
     wall = t1 - t0
@@ -200,6 +204,7 @@ def run_variant(ader, torch, U0, precision, riemann, steps, warmup, order=3, B0=
         "launch": launch,
         "predict_layout": layout,
         "recon_mode": recon_mode,
+        "flux_mode": flux_mode,
         "finite": finite,
         "positivity": "limit" if pos == ader.ADER_POSITIVITY_LIMIT else "check",
         "conservation": conservation(tot0, div0, tot1, div1, mhd, warmup + 2 * steps),
@@ -369,6 +374,7 @@ def run_host_roundtrip(ader, U0, steps):
             ader.ader_set_launch(s.ctx, {k: tuple(v) for k, v in cfg["launch"].items()})
             ader.ader_set_layout(s.ctx, cfg["layout"])
             ader.ader_set_recon(s.ctx, cfg["recon"])
+            ader.ader_set_flux_mode(s.ctx, cfg.get("flux", -1))
         s.set_state(U0)
         s.step_cfl(CFL)
         s.synchronize()
@@ -460,6 +466,7 @@ def run_ensemble(ader, torch, steps, warmup, sample=True):
                          "launch": ader.ader_get_launch(b.ctx),
                          "predict_layout": LAYOUT_NAMES[ader.ader_get_layout(b.ctx)],
                          "recon_mode": RECON_NAMES[ader.ader_get_recon(b.ctx)],
+                         "flux_mode": FLUX_NAMES[ader.ader_get_flux_mode(b.ctx)],
                          "conservation": conservation(tot0, div0, tot1, div1, False,
                                                       warmup + 2 * steps)}
         log("ensemble", name, "%.3e zone-updates/s" % out[name]["zone_updates_per_s"])
@@ -480,15 +487,21 @@ def run_ensemble(ader, torch, steps, warmup, sample=True):
 #          (0,1,0): 10 b);
 #   flux   three faces' two side packets (2 x 3 x 15 b), U of the zone (40 B),
 #          F written (3 x 5 doubles = 120 B);
-#   update U and the zone's own F read (40 + 120 B), U written (40 B).
-def hbm_bytes_per_zone(b):
+#   update U and the zone's own F read (40 + 120 B), U written (40 B);
+#   flux with the update fused (one kernel): the six side packets (90 b),
+#          the averages read (40 B: the predictor's copy in the mixed path)
+#          and U written (40 B); the fluxes stay on chip.
+def hbm_bytes_per_zone(b, fused=False):
+    if fused:
+        return {"recon": 120 + 45 * b + 15 * b, "flux": 90 * b + 40 + 40}
     return {"recon": 120 + 45 * b + 15 * b, "flux": 90 * b + 40 + 120, "update": 200}
 
 
 def hbm_stages(pv, N, dtype, probes):
     b = 8 if dtype == "f64" else 4
     out = {}
-    for stage, per_zone in hbm_bytes_per_zone(b).items():
+    fused = pv.get("flux_mode") == "fused-update"
+    for stage, per_zone in hbm_bytes_per_zone(b, fused).items():
         ms = pv["stage_ms_per_step"][stage]
         gbs = per_zone * N / (ms * 1e-3) / 1e9
         out[stage] = {"bytes_per_zone": per_zone, "ms": ms, "achieved_gbs": gbs,

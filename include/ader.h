@@ -325,7 +325,8 @@ int ader_get_launch(ader_ctx* ctx, int* block_out, int* blocks_per_cu_out);
 int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
 
 /* Layout of the predictor kernel (Sec. IV and App. D work of a zone):
- * ADER_LAYOUT_ZONE, one lane per zone holding all variables, or
+ * ADER_LAYOUT_ZONE, one lane per zone holding all variables (not built for
+ * Euler at order 4: ADER_EUNSUPPORTED there), or
  * ADER_LAYOUT_SPLIT, one lane per (zone, variable) gathering the zone's
  * state across lanes at each flux evaluation (orders 3 and 4 only,
  * ADER_EUNSUPPORTED at order 2), ADER_LAYOUT_SPLIT2, the same compiled to
@@ -369,6 +370,27 @@ int ader_get_layout(ader_ctx* ctx, int* layout_out);
 enum { ADER_RECON_SWEEPS = 0, ADER_RECON_TILED = 1, ADER_RECON_COLUMNS = 2, ADER_RECON_MARCH = 3 };
 int ader_set_recon(ader_ctx* ctx, int mode);
 int ader_get_recon(ader_ctx* ctx, int* mode_out);
+
+/* Execution of the face fluxes (Sec. II and App. D: the Riemann solver at
+ * the face quadrature points) and of the update of eq. (6):
+ * ADER_FLUX_SEPARATE, two launches, the fluxes of every face going through
+ * device memory (F[3][5][S] doubles) between them, or ADER_FLUX_FUSED, one
+ * launch in which a block takes a 32 x 8-zone x-y tile and walks 16 planes
+ * of it in z, forming each plane's face fluxes into LDS and registers and
+ * updating its zones from there, so no flux reaches device memory (the
+ * tile's upper x and y faces and a segment's lower z face are formed by
+ * both blocks that share them).  In the mixed precision the predictor then
+ * also keeps a copy of the zone averages, which the faces between blocks
+ * need after a neighbour has updated its zones.  The fused mode applies to
+ * the ADER step of Euler without a source term (elsewhere the two kernels
+ * run); the stage timing books the update under the flux stage.  Both
+ * modes form every face flux and the update by the same operations, so the
+ * results are equal bit for bit.  -1 selects the default (separate);
+ * ADER_EUNSUPPORTED for MHD and linear advection.  ader_autotune also picks
+ * it; ader_get_flux_mode returns the mode in use. */
+enum { ADER_FLUX_SEPARATE = 0, ADER_FLUX_FUSED = 1 };
+int ader_set_flux_mode(ader_ctx* ctx, int mode);
+int ader_get_flux_mode(ader_ctx* ctx, int* mode_out);
 
 
 #ifdef __cplusplus

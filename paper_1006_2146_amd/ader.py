@@ -34,6 +34,7 @@ EXPORTS = [
     "ader_batch_create", "ader_batch_size", "ader_batch_set_state", "ader_batch_get_state",
     "ader_batch_step_cfl", "ader_set_graph", "ader_autotune", "ader_get_launch",
     "ader_set_launch", "ader_set_layout", "ader_get_layout", "ader_set_recon", "ader_get_recon",
+    "ader_set_flux_mode", "ader_get_flux_mode",
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
     "ader_diagnostics_noalloc", "ader_set_source", "ader_set_advection", "ader_set_boundary",
@@ -42,6 +43,7 @@ ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
 ADER_PROBE_FP32_FMA, ADER_PROBE_FP64_FMA, ADER_PROBE_HBM_COPY = 0, 1, 2
 ADER_RECON_SWEEPS, ADER_RECON_TILED, ADER_RECON_COLUMNS, ADER_RECON_MARCH = 0, 1, 2, 3
+ADER_FLUX_SEPARATE, ADER_FLUX_FUSED = 0, 1
 ADER_LAYOUT_ZONE, ADER_LAYOUT_SPLIT, ADER_LAYOUT_SPLIT2, ADER_LAYOUT_ZONE2 = 0, 1, 2, 3
 ADER_LAYOUT_ZONE_2W, ADER_LAYOUT_PAIR, ADER_LAYOUT_PAIR2 = 4, 5, 6
 ADER_LAYOUT_PAIR_SPLIT, ADER_LAYOUT_FUSED = 7, 8
@@ -108,6 +110,8 @@ def load():
         "ader_get_layout": ([P, ctypes.POINTER(I)], I),
         "ader_set_recon": ([P, I], I),
         "ader_get_recon": ([P, ctypes.POINTER(I)], I),
+        "ader_set_flux_mode": ([P, I], I),
+        "ader_get_flux_mode": ([P, ctypes.POINTER(I)], I),
         "ader_set_scheme": ([P, I], I),
         "ader_get_scheme": ([P, ctypes.POINTER(I)], I),
         "ader_set_positivity": ([P, I], I),
@@ -413,6 +417,16 @@ def ader_set_recon(ctx, mode):
 def ader_get_recon(ctx):
     out = ctypes.c_int()
     _check(load().ader_get_recon(ctx, ctypes.byref(out)), "ader_get_recon")
+    return out.value
+
+
+def ader_set_flux_mode(ctx, mode):
+    _check(load().ader_set_flux_mode(ctx, mode), "ader_set_flux_mode")
+
+
+def ader_get_flux_mode(ctx):
+    out = ctypes.c_int()
+    _check(load().ader_get_flux_mode(ctx, ctypes.byref(out)), "ader_get_flux_mode")
     return out.value
 
 

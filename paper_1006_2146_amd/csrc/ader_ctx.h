@@ -28,6 +28,10 @@ struct Problem {
 // ghost layers on each non-periodic face (enough for order 4)
 constexpr int kGhost = 4;
 
+// the fused face-flux+update kernel: x-y tiles of kFuTX x kFuTY zones, a
+// work item walks kFuSeg planes of one tile in z
+constexpr int kFuTX = 32, kFuTY = 8, kFuSeg = 16;
+
 // zone (i, j, k) of a padded problem is a ghost zone (diagnostics sum the
 // interior only)
 __host__ __device__ inline bool ghost_zone(const Problem& pr, int i, int j, int k) {
@@ -149,6 +153,11 @@ struct ader_ctx {
   // reconstruction
   long long* d_xytile_base = nullptr;
   long long nxytiles = 0;
+  // face fluxes and update in one kernel (ADER_FLUX_*; -1 the default, the
+  // two kernels); its work items, kFuTX x kFuTY columns of kFuSeg planes
+  int flux_mode = -1;
+  long long* d_fu_base = nullptr;
+  long long nfutiles = 0;
   // z-column segments of the column mode: problem p's at seg_base[p] ..
   long long* d_seg_base = nullptr;
   long long nsegs = 0;
@@ -187,6 +196,18 @@ struct ader_ctx {
     return ader::PosCtl{positivity == ADER_POSITIVITY_LIMIT ? 1 : 0, d_bad, d_limited, np()};
   }
   int np() const { return (int)probs.size(); }
+  // the fused face-flux+update kernel runs the ADER step of Euler without a
+  // source term when set; elsewhere the two kernels do
+  bool flux_fused() const {
+    return flux_mode == ADER_FLUX_FUSED && system == ADER_EULER && !has_source &&
+           scheme == ADER_SCHEME_ADER;
+  }
+  // where the predictor keeps the zone averages for that kernel (the first
+  // five rows of F, which it does not use), nullptr when not needed: only
+  // the deviation-form packets (mixed precision) need them
+  double* keep_avg() const {
+    return flux_fused() && precision == ADER_MIXED ? F : nullptr;
+  }
 };
 
 namespace ader {

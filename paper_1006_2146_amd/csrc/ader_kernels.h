@@ -205,14 +205,24 @@ __global__ void __launch_bounds__(256) k_bface(const double* __restrict__ B, dou
   });
 }
 
+// a copy of zone n's averages for the fused face-flux+update kernel (the
+// deviation-form faces between its blocks read them after the update)
+__device__ __forceinline__ void keep_average(const double* __restrict__ U, double* __restrict__ keep,
+                                             long long S, long long n) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) keep[(long long)v * S + n] = U[(long long)v * S + n];
+}
+
 // FUSED: where the facial positivity check runs (see predict_zone); WAVES
 // caps the registers for that many waves per SIMD
 template <class T, int ORDER, int FORM, bool FUSED, int WAVES = 1>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict(const double* __restrict__ U,
                                                  const T* __restrict__ W, T* __restrict__ PK,
                                                  Batch b, const double* __restrict__ dt,
-                                                 double gam, PosCtl pc) {
+                                                 double gam, PosCtl pc,
+                                                 double* __restrict__ keep = nullptr) {
   for_zones(b, [&](const Problem& pr, int p, long long n) {
+    if (keep) keep_average(U, keep, b.S, n);
     predict_zone<T, ORDER, FORM, kDeviation<T>, FUSED>(U, W, PK, grid_of(pr, b), dt[p], 1.0 / pr.dx,
                                                        1.0 / pr.dy, 1.0 / pr.dz, gam, pos_at(pc, p, pr, n), n);
   });
@@ -227,7 +237,7 @@ template <class T, int ORDER, int FORM, int TZ>
 __global__ void __launch_bounds__(kTile * kTile * TZ) k_recon_predict(
     const double* __restrict__ U, T* __restrict__ PK, Batch b,
     const long long* __restrict__ tile_base, const double* __restrict__ dt, double gam,
-    PosCtl pc) {
+    PosCtl pc, double* __restrict__ keep = nullptr) {
   using RL = ReconLds<T, ORDER, 5, TZ>;
   __shared__ double su[RL::kSu];
   __shared__ T sx[RL::kSx];
@@ -250,11 +260,13 @@ __global__ void __launch_bounds__(kTile * kTile * TZ) k_recon_predict(
     const int i0 = (int)(lt % ntx) * kTile, j0 = (int)((lt / ntx) % nty) * kTile;
     const int k0 = (int)(lt / ((long long)ntx * nty)) * TZ;
     RL::run(U, g, i0, j0, k0, su, sx, sy, sw);
-    if (i0 + tx < pr.nx && j0 + ty < pr.ny && k0 + tz < pr.nz)
+    if (i0 + tx < pr.nx && j0 + ty < pr.ny && k0 + tz < pr.nz) {
+      const long long n = zone_of(i0 + tx, j0 + ty, k0 + tz, g);
+      if (keep) keep_average(U, keep, g.S, n);
       predict_zone_lds<T, ORDER, FORM, kDeviation<T>>(U, sw + t, RL::NZ, PK, g, dt[p],
                                                       1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
-                                                      pos_at(pc, p, pr, zone_of(i0 + tx, j0 + ty, k0 + tz, g)),
-                                                      zone_of(i0 + tx, j0 + ty, k0 + tz, g));
+                                                      pos_at(pc, p, pr, n), n);
+    }
     __syncthreads();   // the next tile overwrites the LDS
   }
 }
@@ -341,8 +353,10 @@ template <class T, int ORDER, int FORM, int WAVES>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WAVES))) k_predict_split(const double* __restrict__ U,
                                                        const T* __restrict__ W, T* __restrict__ PK,
                                                        Batch b, const double* __restrict__ dt,
-                                                       double gam, PosCtl pc) {
+                                                       double gam, PosCtl pc,
+                                                       double* __restrict__ keep = nullptr) {
   for_zone_groups<5>(b, [&](const SplitLane& L, const Problem& pr, int p, long long n) {
+    if (keep) keep[(long long)L.var * b.S + n] = U[(long long)L.var * b.S + n];
     predict_zone_split<T, ORDER, FORM, kDeviation<T>>(L, U, W, PK, grid_of(pr, b), dt[p],
                                                       1.0 / pr.dx, 1.0 / pr.dy, 1.0 / pr.dz, gam,
                                                       pos_at(pc, p, pr, n), n);
@@ -474,6 +488,101 @@ __global__ void __launch_bounds__(256) k_face_flux(const double* __restrict__ U,
   for_zones(b, [&](const Problem& pr, int, long long n) {
     face_flux_zone<T, RS, kDeviation<T>>(U, PK, F, grid_of(pr, b), gam, n);
   });
+}
+
+// Face fluxes and the update of eq. (6) in one kernel (Euler).  A work item
+// is an x-y tile of kFuTX x kFuTY zones and a segment of kFuSeg planes; the
+// block walks it in z.  Per plane each thread forms its zone's lower x and y
+// faces into LDS and its upper z face into registers (the lower z face is
+// the previous plane's upper one; the segment's first lower z face and the
+// tile's upper x and y faces are formed here too, and again by the block
+// that owns their other zone), then updates its zone from them.  Every face
+// is formed by face_flux_values, as in k_face_flux, and the update takes
+// update_zone's order of operations, so the two paths agree bit for bit,
+// while no flux reaches device memory.  With deviation-form packets a face
+// needs the zone averages at the step's start, also of zones that another
+// block updates meanwhile: those come from the copy U0 the predictor keeps
+// (read for the block's own zones too, so a launch can be repeated).
+template <class T, int RS>
+__global__ void __launch_bounds__(kFuTX * kFuTY) k_flux_update(
+    double* __restrict__ U, const double* __restrict__ U0, const T* __restrict__ PK, Batch b,
+    const long long* __restrict__ fu_base, const double* __restrict__ dt, double gam) {
+  constexpr bool DEV = kDeviation<T>;
+  static_assert(kFuTY <= 64 && kFuTX <= 64 && kFuTX * kFuTY >= 64 + kFuTX,
+                "the tile's upper faces are formed by waves 0 and 1");
+  __shared__ double fx[5][kFuTY][kFuTX + 1];   // x faces: [v][row j][lower face of local zone i]
+  __shared__ double fy[5][kFuTY + 1][kFuTX];   // y faces: [v][lower face of local row j][i]
+  const double* UA = DEV ? U0 : U;             // the averages the faces and the update read
+  const long long nitems = fu_base[b.np];
+  const int G = gridDim.x;
+  const int nreg = G < 8 ? G : 8;
+  const int x = blockIdx.x % nreg, r = blockIdx.x / nreg;
+  const int nb = (G - x + nreg - 1) / nreg;
+  const long long lo = nitems * x / nreg, hi = nitems * (x + 1) / nreg;
+  const int t = threadIdx.x, ti = t % kFuTX, tj = t / kFuTX;
+  for (long long q = lo + r; q < hi; q += nb) {
+    const int p = problem_of_tile(fu_base, b.np, q);
+    const Problem pr = b.P[p];
+    const Grid g = grid_of(pr, b);
+    const long long lt = q - fu_base[p];
+    const int ntx = (pr.nx + kFuTX - 1) / kFuTX, nty = (pr.ny + kFuTY - 1) / kFuTY;
+    const int i0 = (int)(lt % ntx) * kFuTX, j0 = (int)((lt / ntx) % nty) * kFuTY;
+    const int k0 = (int)(lt / ((long long)ntx * nty)) * kFuSeg;
+    const int k1 = k0 + kFuSeg < pr.nz ? k0 + kFuSeg : pr.nz;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool in = i < pr.nx && j < pr.ny;
+    // local index of the tile's upper x face (y face): the upper face of its
+    // last zone, shared with the next zone (periodically wrapped)
+    const int ex = pr.nx - i0 < kFuTX ? pr.nx - i0 : kFuTX;
+    const int ey = pr.ny - j0 < kFuTY ? pr.ny - j0 : kFuTY;
+    const double h = dt[p];
+    const double c[3] = {h / pr.dx, h / pr.dy, h / pr.dz};
+    double fzl[5], fzu[5], res[5];
+    if (in)
+      face_flux_values<T, RS, 2, DEV>(UA, PK, g, zone_of(i, j, k0, g),
+                                      zone_of(i, j, wrap(k0 - 1, g.nz), g), gam, fzl);
+    for (int k = k0; k < k1; ++k) {
+      if (in) {
+        const long long n = zone_of(i, j, k, g);
+        face_flux_values<T, RS, 0, DEV>(UA, PK, g, n, zone_of(wrap(i - 1, g.nx), j, k, g), gam, res);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fx[v][tj][ti] = res[v];
+        face_flux_values<T, RS, 1, DEV>(UA, PK, g, n, zone_of(i, wrap(j - 1, g.ny), k, g), gam, res);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fy[v][tj][ti] = res[v];
+        face_flux_values<T, RS, 2, DEV>(UA, PK, g, zone_of(i, j, wrap(k + 1, g.nz), g), n, gam, fzu);
+      }
+      if (t < ey) {
+        // wave 0: the upper x face of row t
+        face_flux_values<T, RS, 0, DEV>(UA, PK, g, zone_of(wrap(i0 + ex, g.nx), j0 + t, k, g),
+                                        zone_of(i0 + ex - 1, j0 + t, k, g), gam, res);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fx[v][t][ex] = res[v];
+      } else if (t >= 64 && t < 64 + ex) {
+        // wave 1: the upper y face of column t - 64
+        const int il = t - 64;
+        face_flux_values<T, RS, 1, DEV>(UA, PK, g, zone_of(i0 + il, wrap(j0 + ey, g.ny), k, g),
+                                        zone_of(i0 + il, j0 + ey - 1, k, g), gam, res);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fy[v][ey][il] = res[v];
+      }
+      __syncthreads();
+      if (in) {
+        // eq. (6) in update_zone's order: per variable x, then y, then z
+        const long long n = zone_of(i, j, k, g);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          double u = UA[(long long)v * g.S + n];
+          u = u - c[0] * (fx[v][tj][ti + 1] - fx[v][tj][ti]);
+          u = u - c[1] * (fy[v][tj + 1][ti] - fy[v][tj][ti]);
+          u = u - c[2] * (fzu[v] - fzl[v]);
+          U[(long long)v * g.S + n] = u;
+          fzl[v] = fzu[v];
+        }
+      }
+      __syncthreads();   // the next plane overwrites the LDS faces
+    }
+  }
 }
 
 template <class T, int RS>

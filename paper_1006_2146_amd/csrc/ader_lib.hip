@@ -107,7 +107,7 @@ bool layout_built(const ader_ctx* c, const StageFns* s, int layout) {
   if (layout == ADER_LAYOUT_ZONE2 && c->system == ADER_MHD && c->riemann == ADER_LINEARIZED)
     return false;
   switch (layout) {
-    case ADER_LAYOUT_ZONE: return true;
+    case ADER_LAYOUT_ZONE: return s->predict != nullptr;
     case ADER_LAYOUT_SPLIT: return s->predict_split != nullptr;
     case ADER_LAYOUT_SPLIT2: return s->predict_split2 != nullptr;
     case ADER_LAYOUT_ZONE2: return s->predict_zone2 != nullptr;
@@ -141,11 +141,43 @@ int queue_predict(ader_ctx* c, const StageFns* s) {
     case ADER_LAYOUT_PAIR2: return s->predict_pair2(c);
     case ADER_LAYOUT_PAIR_SPLIT: return s->predict_pair_split(c);
     case ADER_LAYOUT_FUSED: return s->predict_fused(c);
-    default: return s->predict(c);
+    default: return s->predict ? s->predict(c) : ADER_EUNSUPPORTED;
   }
 }
 
+// face fluxes and update in one launch (ctx flux_fused())
+int queue_flux_update(ader_ctx* c) {
+  const long long cap = (long long)c->shape[kClassFlux].blocks_per_cu * c->num_cus;
+  const unsigned g = (unsigned)(c->nfutiles < cap ? c->nfutiles : cap);
+  const dim3 grid(g < 1 ? 1 : g), block(kFuTX * kFuTY);
+  const bool hll = c->riemann == ADER_HLL;
+  if (c->precision == ADER_MIXED) {
+    const float* PK = static_cast<const float*>(c->PK);
+    if (hll)
+      k_flux_update<float, 0><<<grid, block, 0, c->stream>>>(c->U, c->keep_avg(), PK, c->batch(),
+                                                             c->d_fu_base, c->d_dt, c->gamma);
+    else
+      k_flux_update<float, 1><<<grid, block, 0, c->stream>>>(c->U, c->keep_avg(), PK, c->batch(),
+                                                             c->d_fu_base, c->d_dt, c->gamma);
+  } else {
+    const double* PK = static_cast<const double*>(c->PK);
+    if (hll)
+      k_flux_update<double, 0><<<grid, block, 0, c->stream>>>(c->U, nullptr, PK, c->batch(),
+                                                              c->d_fu_base, c->d_dt, c->gamma);
+    else
+      k_flux_update<double, 1><<<grid, block, 0, c->stream>>>(c->U, nullptr, PK, c->batch(),
+                                                               c->d_fu_base, c->d_dt, c->gamma);
+  }
+  return launched();
+}
+
+int queue_flux(ader_ctx* c, const StageFns* s) {
+  return c->flux_fused() ? queue_flux_update(c) : s->flux(c);
+}
+
+// a no-op when the fused kernel has updated already
 int queue_update(ader_ctx* c, const StageFns* s) {
+  if (c->flux_fused()) return ADER_OK;
   if (c->has_source) return s->update_src ? s->update_src(c) : ADER_EUNSUPPORTED;
   return s->update(c);
 }
@@ -243,7 +275,7 @@ int queue_step(ader_ctx* c) {
   }
   {
     StageTimer t(c, ADER_STAGE_FLUX);
-    ADER_TRY(s->flux(c));
+    ADER_TRY(queue_flux(c, s));
   }
   StageTimer t(c, ADER_STAGE_UPDATE);
   return queue_update(c, s);
@@ -306,6 +338,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)c->precision;
   k = k * 3 + (unsigned long long)(c->layout + 1);
   k = k * 3 + (unsigned long long)(c->recon_mode + 1);
+  k = k * 3 + (unsigned long long)(c->flux_mode + 1);
   k = k * 3 + (unsigned long long)c->scheme;
   k = k * 3 + (unsigned long long)c->positivity;
   k = k * 1000003 + c->source_version;
@@ -425,7 +458,7 @@ void free_buffers(ader_ctx* c) {
                   (void*)c->RK, c->EM, (void*)c->TH, (void*)c->SB,
                   (void*)c->d_dt, (void*)c->d_rate, (void*)c->d_bad, (void*)c->d_limited,
                   (void*)c->d_probs,
-                  (void*)c->d_tile_base, (void*)c->d_ftile_base, (void*)c->d_xytile_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
+                  (void*)c->d_tile_base, (void*)c->d_ftile_base, (void*)c->d_xytile_base, (void*)c->d_fu_base, (void*)c->d_seg_base, (void*)c->d_diag_base,
                   (void*)c->d_diag})
     if (p) (void)hipFree(p);
 }
@@ -503,6 +536,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
             hipMalloc(&c->d_tile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_ftile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_xytile_base, sizeof(long long) * (n + 1)) == hipSuccess &&
+            hipMalloc(&c->d_fu_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_seg_base, sizeof(long long) * (n + 1)) == hipSuccess &&
             hipMalloc(&c->d_diag_base, sizeof(long long) * (n + 1)) == hipSuccess;
   if (!ok) {
@@ -512,7 +546,7 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
     return ADER_ENOMEM;
   }
   c->fixed_bytes = sU + sF + sM + sP + 2 * sD + (sizeof(int) + sizeof(unsigned int)) * 2 * n +
-                   5 * sizeof(long long) * (n + 1);
+                   6 * sizeof(long long) * (n + 1);
   c->bytes = c->fixed_bytes;
   // reconstruction tiles of kTile^3 zones per problem
   std::vector<long long> tile_base(n + 1, 0);
@@ -541,6 +575,15 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
                                               ((pr.nz + kMarchSeg - 1) / kMarchSeg);
   }
   c->nxytiles = xytile_base[n];
+  // work items of the fused face-flux+update kernel: kFuTX x kFuTY columns
+  // of kFuSeg planes
+  std::vector<long long> fu_base(n + 1, 0);
+  for (int q = 0; q < n; ++q) {
+    const Problem& pr = c->probs[q];
+    fu_base[q + 1] = fu_base[q] + (long long)((pr.nx + kFuTX - 1) / kFuTX) *
+                                      ((pr.ny + kFuTY - 1) / kFuTY) * ((pr.nz + kFuSeg - 1) / kFuSeg);
+  }
+  c->nfutiles = fu_base[n];
   // z-column segments of kZSeg planes per (i, j) column
   std::vector<long long> seg_base(n + 1, 0);
   for (int q = 0; q < n; ++q) {
@@ -558,6 +601,8 @@ int create(int n, const ader_mesh* meshes, int system, int device, void* stream,
       hipMemcpy(c->d_ftile_base, ftile_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_xytile_base, xytile_base.data(), sizeof(long long) * (n + 1),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_fu_base, fu_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_diag_base, diag_base.data(), sizeof(long long) * (n + 1),
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -659,7 +704,7 @@ int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
       case kClassDt: rc = queue_dt(c, 0.3); break;
       case kClassRecon: rc = s->recon(c); break;
       case kClassPredict: rc = queue_predict(c, s); break;
-      case kClassFlux: rc = s->flux(c); break;
+      case kClassFlux: rc = queue_flux(c, s); break;
       default: rc = queue_update(c, s); break;
     }
   }
@@ -668,6 +713,24 @@ int time_stage(ader_ctx* c, int cls, const StageFns* s, int reps, float* ms) {
   if (rc == ADER_OK) rc = check(hipEventElapsedTime(ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  return rc;
+}
+
+// the update's time at its fastest launch shape (the shape is kept)
+int best_update_ms(ader_ctx* c, const StageFns* s, int reps, float* out) {
+  const LaunchShape keep = c->shape[kClassUpdate];
+  float best = 1e30f;
+  int rc = ADER_OK;
+  for (const LaunchShape& cand : kCandidates) {
+    c->shape[kClassUpdate] = cand;
+    float ms = 0.f;
+    rc = time_stage(c, kClassUpdate, s, 1, &ms);
+    if (rc == ADER_OK) rc = time_stage(c, kClassUpdate, s, reps, &ms);
+    if (rc != ADER_OK) break;
+    best = ms < best ? ms : best;
+  }
+  c->shape[kClassUpdate] = keep;
+  *out = best;
   return rc;
 }
 
@@ -698,8 +761,11 @@ int autotune(ader_ctx* c, int reps) {
   const int order_of_classes[kNumClasses] = {kClassRecon, kClassPredict, kClassFlux, kClassDt,
                                              kClassUpdate};
   // the fused layout's predictor includes the reconstruction: the other
-  // layouts are compared with the tuned reconstruction's time added
-  float recon_ms = 0.f;
+  // layouts are compared with the tuned reconstruction's time added; the
+  // fused face-flux+update kernel is compared with the two kernels' sum
+  float recon_ms = 0.f, update_ms = 0.f;
+  const bool fusable =
+      c->system == ADER_EULER && !c->has_source && c->scheme == ADER_SCHEME_ADER;
   for (int qi = 0; qi < kNumClasses && rc == ADER_OK; ++qi) {
     const int cls = order_of_classes[qi];
     LaunchShape best = c->shape[cls];
@@ -707,7 +773,11 @@ int autotune(ader_ctx* c, int reps) {
     float best_ms = 1e30f;
     // the predictor also tries its layouts, the reconstruction its modes
     int best_recon = c->recon_mode;
-    const int nlayouts = cls == kClassPredict ? kNumLayouts : cls == kClassRecon ? 4 : 1;
+    int best_flux = c->flux_mode;
+    const int nlayouts = cls == kClassPredict ? kNumLayouts
+                         : cls == kClassRecon ? 4
+                         : (cls == kClassFlux && fusable) ? 2
+                                                           : 1;
     for (int lay = 0; lay < nlayouts && rc == ADER_OK; ++lay) {
       if (cls == kClassPredict) {
         if (!layout_built(c, s, lay)) continue;
@@ -719,6 +789,14 @@ int autotune(ader_ctx* c, int reps) {
         if (lay != ADER_RECON_SWEEPS && c->order < 3) continue;
         c->recon_mode = lay;
       }
+      if (cls == kClassFlux && nlayouts == 2) {
+        c->flux_mode = lay;
+        // separate: the update's best time joins; fused: one predictor launch
+        // first keeps the zone averages the fused kernel reads
+        rc = lay == ADER_FLUX_SEPARATE ? best_update_ms(c, s, reps, &update_ms)
+                                       : queue_predict(c, s);
+        if (rc != ADER_OK) break;
+      }
       for (const LaunchShape& cand : kCandidates) {
         c->shape[cls] = cand;
         float ms = 0.f;
@@ -726,17 +804,20 @@ int autotune(ader_ctx* c, int reps) {
         if (rc == ADER_OK) rc = time_stage(c, cls, s, reps, &ms);
         if (rc != ADER_OK) break;
         if (cls == kClassPredict && c->layout != ADER_LAYOUT_FUSED) ms += recon_ms;
+        if (cls == kClassFlux && nlayouts == 2 && lay == ADER_FLUX_SEPARATE) ms += update_ms;
         if (ms < best_ms) {
           best_ms = ms;
           best = cand;
           best_layout = c->layout;
           best_recon = c->recon_mode;
+          best_flux = c->flux_mode;
         }
       }
     }
     c->shape[cls] = best;
     c->layout = best_layout;
     c->recon_mode = best_recon;
+    c->flux_mode = best_flux;
     if (cls == kClassRecon) recon_ms = best_ms;
   }
   c->timing = timing;
@@ -1036,6 +1117,9 @@ int ader_set_layout(ader_ctx* c, int layout) {
     return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_FUSED && (c->order != 3 || c->system != ADER_EULER))
     return ADER_EUNSUPPORTED;
+  // Euler at order 4 runs the lane-split predictor only
+  if (layout == ADER_LAYOUT_ZONE && c->order == 4 && c->system == ADER_EULER)
+    return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;
 }
@@ -1128,6 +1212,7 @@ int ader_set_boundary(ader_ctx* c, const int* bc) {
   t->positivity = c->positivity;
   t->layout = c->layout;
   t->recon_mode = c->recon_mode;
+  t->flux_mode = c->flux_mode;
   t->scheme = c->scheme;
   t->use_graph = c->use_graph;
   for (int q = 0; q < kNumClasses; ++q) t->shape[q] = c->shape[q];
@@ -1196,6 +1281,20 @@ int ader_set_recon(ader_ctx* c, int mode) {
 int ader_get_recon(ader_ctx* c, int* mode_out) {
   if (!c || !mode_out) return ADER_EINVAL;
   *mode_out = (c->order >= 3 && c->recon_mode >= 0) ? c->recon_mode : ADER_RECON_SWEEPS;
+  return ADER_OK;
+}
+
+int ader_set_flux_mode(ader_ctx* c, int mode) {
+  if (!c || (mode != -1 && mode != ADER_FLUX_SEPARATE && mode != ADER_FLUX_FUSED))
+    return ADER_EINVAL;
+  if (mode == ADER_FLUX_FUSED && c->system != ADER_EULER) return ADER_EUNSUPPORTED;
+  c->flux_mode = mode;
+  return ADER_OK;
+}
+
+int ader_get_flux_mode(ader_ctx* c, int* mode_out) {
+  if (!c || !mode_out) return ADER_EINVAL;
+  *mode_out = c->flux_fused() ? ADER_FLUX_FUSED : ADER_FLUX_SEPARATE;
   return ADER_OK;
 }
 

@@ -101,8 +101,8 @@ int predict(ader_ctx* c) {
           c->batch(), c->d_dt, c->gamma, c->pos());
     }
   } else
-    k_predict<T, kOrder, kForm, FUSED, WAVES><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(),
-                                                                       c->d_dt, c->gamma, c->pos());
+    k_predict<T, kOrder, kForm, FUSED, WAVES><<<g, bs, 0, c->stream>>>(
+        c->U, W, PK, c->batch(), c->d_dt, c->gamma, c->pos(), c->keep_avg());
   return launched();
 }
 
@@ -121,8 +121,8 @@ int predict_split(ader_ctx* c) {
           c->U, W, c->B0, static_cast<const T*>(c->WB), static_cast<const T*>(c->BN), PK,
           c->batch(), c->d_dt, c->gamma, c->pos());
     else
-      k_predict_split<T, kOrder, kForm, WAVES><<<g, bs, 0, c->stream>>>(c->U, W, PK, c->batch(),
-                                                                        c->d_dt, c->gamma, c->pos());
+      k_predict_split<T, kOrder, kForm, WAVES><<<g, bs, 0, c->stream>>>(
+          c->U, W, PK, c->batch(), c->d_dt, c->gamma, c->pos(), c->keep_avg());
     return launched();
   } else {
     return ADER_EUNSUPPORTED;
@@ -281,7 +281,8 @@ int predict_fused(ader_ctx* c) {
     const unsigned g = (unsigned)(c->nftiles < cap ? c->nftiles : cap);
     k_recon_predict<T, kOrder, kForm, kFusedTZ><<<g < 1 ? 1 : g, kTile * kTile * kFusedTZ, 0,
                                                   c->stream>>>(
-        c->U, static_cast<T*>(c->PK), c->batch(), c->d_ftile_base, c->d_dt, c->gamma, c->pos());
+        c->U, static_cast<T*>(c->PK), c->batch(), c->d_ftile_base, c->d_dt, c->gamma, c->pos(),
+        c->keep_avg());
     return launched();
   } else {
     return ADER_EUNSUPPORTED;
@@ -299,16 +300,27 @@ int update_src(ader_ctx* c) {
   }
 }
 
+// stage F where B holds, else nullptr (F is then not instantiated)
+template <bool B, int (*F)(ader_ctx*)>
+constexpr int (*only_if())(ader_ctx*) {
+  if constexpr (B) return F;
+  else return nullptr;
+}
+
 // the one-lane-per-zone instances with a separate facial pass, and with two
 // waves per SIMD (Euler), are built where the zone layout is the likely
-// winner (orders 2 and 3)
+// winner (orders 2 and 3).  The Euler one-lane-per-zone predictor is not
+// built at order 4: it spills about 2-3.5 KB per lane there, and a run of
+// its FP64 instance on a batch of five ragged meshes did not finish within
+// two minutes, with no cause found in the source; the lane-split layout,
+// the default and the faster one at that order, runs instead.
 // linear advection builds only the one-lane-per-zone predictor
 const StageFns kStages = {recon,
-                          predict<true>,
+                          only_if<!(kOrder == 4 && !kMhd && !kLinadv), predict<true>>(),
                           (kOrder >= 3 && !kLinadv) ? predict_split<1> : nullptr,
                           (kOrder >= 3 && !kLinadv) ? predict_split<2> : nullptr,
-                          (kOrder <= 3 && !kLinadv) ? predict<false> : nullptr,
-                          (!kMhd && !kLinadv && kOrder <= 3) ? predict<true, 2> : nullptr,
+                          only_if<kOrder <= 3 && !kLinadv, predict<false>>(),
+                          only_if<!kMhd && !kLinadv && kOrder <= 3, predict<true, 2>>(),
                           (kMhd && kOrder == 3) ? predict_pair<1> : nullptr,
                           (kMhd && kOrder == 3) ? predict_pair<2> : nullptr,
                           (kMhd && kOrder >= 3) ? predict_pair_split : nullptr,

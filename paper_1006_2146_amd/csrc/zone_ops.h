@@ -964,10 +964,11 @@ __host__ __device__ __forceinline__ void linearized_flux(const T (&ubl)[5], cons
 // FP32 part, linearized (F(wl) + F(wr))/2) plus the solver applied to the
 // deviations with the jump wr - wl added to the right state (FP32).
 template <class T, int RS, int AXIS, bool DEV>
-__host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict__ U,
-                                                        const T* __restrict__ PK,
-                                                        double* __restrict__ F, const Grid& g,
-                                                        long long n, long long nl, double gam) {
+__host__ __device__ __forceinline__ void face_flux_values(const double* __restrict__ U,
+                                                          const T* __restrict__ PK,
+                                                          const Grid& g, long long n,
+                                                          long long nl, double gam,
+                                                          double (&res)[5]) {
   T ubl[5], ul[5], fl[5], ubr[5], ur[5], fr[5], out[5];
   double wl[5], wr[5];
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;  // top side of the lower zone, bottom side of this
@@ -1002,7 +1003,6 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       ur[v] += T(wr[v] - wl[v]);
     }
   }
-  double* qf = F + (long long)(AXIS * 5) * g.S + n;
   const T tg = T(gam);
   if constexpr (RS == 0) {
     // signal speeds of the barycentre states
@@ -1019,10 +1019,7 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       Euler<double>::template flux<AXIS>(wr, Fr, gam);
       const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        *qf = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
-        qf = next_row(qf, g.S);
-      }
+      for (int v = 0; v < 5; ++v) res[v] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
       return;
     }
   } else {
@@ -1032,16 +1029,25 @@ __host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict
       Euler<double>::template flux<AXIS>(wl, Fl, gam);
       Euler<double>::template flux<AXIS>(wr, Fr, gam);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        *qf = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
-        qf = next_row(qf, g.S);
-      }
+      for (int v = 0; v < 5; ++v) res[v] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
       return;
     }
   }
 #pragma unroll
+  for (int v = 0; v < 5; ++v) res[v] = double(out[v]);
+}
+
+template <class T, int RS, int AXIS, bool DEV>
+__host__ __device__ __forceinline__ void face_flux_axis(const double* __restrict__ U,
+                                                        const T* __restrict__ PK,
+                                                        double* __restrict__ F, const Grid& g,
+                                                        long long n, long long nl, double gam) {
+  double res[5];
+  face_flux_values<T, RS, AXIS, DEV>(U, PK, g, n, nl, gam, res);
+  double* qf = F + (long long)(AXIS * 5) * g.S + n;
+#pragma unroll
   for (int v = 0; v < 5; ++v) {
-    *qf = double(out[v]);
+    *qf = res[v];
     qf = next_row(qf, g.S);
   }
 }

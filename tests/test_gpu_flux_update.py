@@ -1,0 +1,192 @@
+"""The fused face-flux+update kernel (ader_set_flux_mode, ADER_FLUX_FUSED)
+through the C ABI: bit-for-bit equal to the two-kernel path (face fluxes of
+Sec. II / App. D through device memory, then eq. 6) at every order, form,
+precision and Riemann solver, with every Euler predictor layout that keeps
+the zone averages for it, on ragged batches whose meshes are not multiples
+of the kernel's 32 x 8-zone tiles and 16-plane segments (and one-zone
+meshes, where every face wraps onto the same zone); with non-periodic faces;
+under graph replay; after ader_autotune; FP64 parity with the oracle; the
+fallback to the two kernels with a source term, and the argument checks."""
+
+import numpy as np
+import pytest
+
+from oracle import OracleConfig, step as oracle_step
+from paper_1006_2146_amd import ader, workloads
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(19, 11, 35), (1, 1, 1), (4, 9, 64), (17, 8, 32), (3, 20, 7)]
+CASES = [(2, "modal"), (3, "modal"), (3, "nodal"), (4, "modal"), (4, "nodal")]
+FORM = {"modal": ader.ADER_MODAL, "nodal": ader.ADER_NODAL}
+PREC = {"fp64": ader.ADER_FP64, "mixed": ader.ADER_MIXED}
+RS = {"hll": ader.ADER_HLL, "linearized": ader.ADER_LINEARIZED}
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _layouts(order):
+    # the Euler one-lane-per-zone predictor is built at orders 2 and 3
+    lays = []
+    if order <= 3:
+        lays += [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_ZONE_2W]
+    if order >= 3:
+        lays.append(ader.ADER_LAYOUT_SPLIT)
+    if order == 3:
+        lays.append(ader.ADER_LAYOUT_FUSED)
+    return lays
+
+
+def _run(order, form, prec, rs, mode, layout, nsteps=3, shapes=SHAPES, boundary=None,
+         graph=False):
+    states = [workloads.random_smooth(sh, seed=40 + q) for q, sh in enumerate(shapes)]
+    import torch
+    stream = torch.cuda.Stream() if graph else None
+    with ader.BatchSolver(shapes, order=order, form=FORM[form], precision=PREC[prec],
+                          riemann=RS[rs], boundary=boundary,
+                          stream=stream.cuda_stream if graph else None) as b:
+        ader.ader_set_layout(b.ctx, layout)
+        ader.ader_set_flux_mode(b.ctx, mode)
+        assert ader.ader_get_flux_mode(b.ctx) == mode
+        if graph:
+            ader.ader_set_graph(b.ctx, True)
+        for q, U in enumerate(states):
+            b.set_state(q, U)
+        for _ in range(nsteps):
+            b.step_cfl(0.3)
+        b.synchronize()
+        return [b.get_state(q) for q in range(len(shapes))]
+
+
+@pytest.mark.parametrize("rs", sorted(RS))
+@pytest.mark.parametrize("prec", sorted(PREC))
+@pytest.mark.parametrize("order,form", CASES)
+def test_fused_equals_two_kernels_bitwise(order, form, prec, rs):
+    for layout in _layouts(order):
+        say("flux+update", order, form, prec, rs, "layout", layout)
+        sep = _run(order, form, prec, rs, ader.ADER_FLUX_SEPARATE, layout)
+        fus = _run(order, form, prec, rs, ader.ADER_FLUX_FUSED, layout)
+        for q in range(len(SHAPES)):
+            assert np.array_equal(sep[q], fus[q]), (layout, q,
+                                                    np.abs(sep[q] - fus[q]).max())
+
+
+def test_fused_with_walls_and_outflow():
+    W, O, P = ader.ADER_BC_REFLECT, ader.ADER_BC_OUTFLOW, ader.ADER_BC_PERIODIC
+    shapes = [(6, 7, 9), (9, 12, 40)]
+    for prec in ("fp64", "mixed"):
+        say("flux+update bounded", prec)
+        a = _run(3, "modal", prec, "hll", ader.ADER_FLUX_SEPARATE, ader.ADER_LAYOUT_ZONE,
+                 shapes=shapes, boundary=(W, O, O, W, P, P))
+        b = _run(3, "modal", prec, "hll", ader.ADER_FLUX_FUSED, ader.ADER_LAYOUT_ZONE,
+                 shapes=shapes, boundary=(W, O, O, W, P, P))
+        for q in range(len(shapes)):
+            assert np.array_equal(a[q], b[q]), (prec, q)
+
+
+def test_fused_graph_replays_equal_eager():
+    for prec in ("fp64", "mixed"):
+        say("flux+update graph", prec)
+        eager = _run(3, "modal", prec, "hll", ader.ADER_FLUX_FUSED, ader.ADER_LAYOUT_SPLIT,
+                     nsteps=4)
+        replay = _run(3, "modal", prec, "hll", ader.ADER_FLUX_FUSED, ader.ADER_LAYOUT_SPLIT,
+                      nsteps=4, graph=True)
+        for q in range(len(SHAPES)):
+            assert np.array_equal(eager[q], replay[q]), (prec, q)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_then_step_equals_two_kernels(prec):
+    shapes = [(24, 24, 24), (10, 13, 40)]
+    states = [workloads.random_smooth(sh, seed=7 + q) for q, sh in enumerate(shapes)]
+    out = {}
+    for tuned in (False, True):
+        with ader.BatchSolver(shapes, order=3, precision=PREC[prec]) as b:
+            for q, U in enumerate(states):
+                b.set_state(q, U)
+            if tuned:
+                ader.ader_autotune(b.ctx, 2)
+                # tuning does not advance the state
+                for q, U in enumerate(states):
+                    assert np.array_equal(b.get_state(q), U)
+                say("autotuned flux mode", prec, ader.ader_get_flux_mode(b.ctx),
+                    "layout", ader.ader_get_layout(b.ctx))
+            else:
+                ader.ader_set_flux_mode(b.ctx, ader.ADER_FLUX_SEPARATE)
+            for _ in range(2):
+                b.step_cfl(0.3)
+            out[tuned] = [b.get_state(q) for q in range(len(shapes))]
+    for q in range(len(shapes)):
+        if prec == "fp64":
+            # the tuned predictor layout may differ: equal up to rounding order
+            assert np.abs(out[True][q] - out[False][q]).max() <= 1e-13 * np.abs(out[False][q]).max()
+        else:
+            assert np.abs(out[True][q] - out[False][q]).max() <= 1e-6 * np.abs(out[False][q]).max()
+
+
+@pytest.mark.parametrize("order,form", CASES)
+def test_fused_fp64_parity_with_the_oracle(order, form):
+    shape = (17, 9, 34)
+    U = workloads.random_smooth(shape, seed=order)
+    cfg = OracleConfig(order=order, form=form, riemann="hll")
+    with ader.Solver(shape, order=order, form=FORM[form]) as s:
+        ader.ader_set_flux_mode(s.ctx, ader.ADER_FLUX_FUSED)
+        s.set_state(U)
+        for it in range(2):
+            say("fused parity", order, form, "step", it)
+            dt = s.compute_dt(0.3)
+            s.step(dt)
+            Ug = s.get_state()
+            Uo = oracle_step(U, dt, cfg)
+            err = np.abs(Ug - Uo).sum(axis=(1, 2, 3)) / np.abs(Uo).sum(axis=(1, 2, 3))
+            assert np.all(err <= 1e-12) and np.abs(Ug - Uo).max() <= 1e-12 * np.abs(Uo).max(), err
+            U = Ug
+
+
+def test_stage_times_book_the_update_under_the_fluxes():
+    with ader.Solver((16, 16, 64), order=3) as s:
+        ader.ader_set_flux_mode(s.ctx, ader.ADER_FLUX_FUSED)
+        s.set_state(workloads.random_smooth((16, 16, 64), seed=1))
+        ader.ader_set_timing(s.ctx, 1)
+        s.step_cfl(0.3)
+        s.synchronize()
+        t = ader.ader_stage_times(s.ctx)
+        ader.ader_set_timing(s.ctx, 0)
+    assert t["flux"][0] > 0.0 and t["update"][0] < t["flux"][0]
+
+
+def test_flux_mode_errors_and_fallbacks():
+    with ader.Solver((4, 4, 4), system=ader.ADER_MHD, gamma=5.0 / 3.0) as s:
+        with pytest.raises(ader.AderError) as e:
+            ader.ader_set_flux_mode(s.ctx, ader.ADER_FLUX_FUSED)
+        assert e.value.code == ader.ADER_EUNSUPPORTED
+        assert ader.ader_get_flux_mode(s.ctx) == ader.ADER_FLUX_SEPARATE
+    with ader.Solver((4, 4, 4)) as s:
+        for bad in (2, -2):
+            with pytest.raises(ader.AderError) as e:
+                ader.ader_set_flux_mode(s.ctx, bad)
+            assert e.value.code == ader.ADER_EINVAL
+        assert ader.ader_get_flux_mode(s.ctx) == ader.ADER_FLUX_SEPARATE
+        ader.ader_set_flux_mode(s.ctx, ader.ADER_FLUX_FUSED)
+        assert ader.ader_get_flux_mode(s.ctx) == ader.ADER_FLUX_FUSED
+        ader.ader_set_flux_mode(s.ctx, -1)
+        assert ader.ader_get_flux_mode(s.ctx) == ader.ADER_FLUX_SEPARATE
+    # a source term or the SSP-RK scheme: the two kernels run, results as without the mode
+    U = workloads.random_smooth((6, 7, 9), seed=3)
+    A = 0.2 * np.eye(5)
+    for what in ("source", "ssprk"):
+        res = []
+        for mode in (ader.ADER_FLUX_SEPARATE, ader.ADER_FLUX_FUSED):
+            with ader.Solver((6, 7, 9), order=3, precision=ader.ADER_MIXED) as s:
+                ader.ader_set_flux_mode(s.ctx, mode)
+                if what == "source":
+                    s.set_source(A, np.zeros(5))
+                else:
+                    ader.ader_set_scheme(s.ctx, ader.ADER_SCHEME_SSPRK)
+                assert ader.ader_get_flux_mode(s.ctx) == ader.ADER_FLUX_SEPARATE
+                s.set_state(U)
+                s.step(1e-3)
+                res.append(s.get_state())
+        assert np.array_equal(res[0], res[1]), what

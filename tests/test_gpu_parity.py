@@ -366,6 +366,10 @@ LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT
 
 
 def _skip_unbuilt(layout, order, mhd=False):
+    if layout == ader.ADER_LAYOUT_ZONE and order == 4 and not mhd:
+        pytest.skip("the Euler one-lane-per-zone predictor is not built at order 4 (a run of "
+                    "its FP64 instance did not finish, cause not found); the lane-split "
+                    "layout runs there")
     if layout == ader.ADER_LAYOUT_FUSED and (order != 3 or mhd):
         pytest.skip("the fused reconstruction+predictor is built for Euler at order 3")
     if layout == ader.ADER_LAYOUT_ZONE2 and order > 3:
@@ -450,6 +454,8 @@ def test_layout_errors():
         assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_ZONE2
     with _solver((4, 4, 4), 4, "modal", "hll") as s:
         assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE2) == ader.ADER_EUNSUPPORTED
+        assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE) == ader.ADER_EUNSUPPORTED
+        assert ader.ader_get_layout(s.ctx) == ader.ADER_LAYOUT_SPLIT
         assert ader.load().ader_set_layout(s.ctx, ader.ADER_LAYOUT_ZONE_2W) == \
             ader.ADER_EUNSUPPORTED
     with _mhd_solver((4, 4, 4), 3, "modal") as s:
