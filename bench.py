@@ -674,6 +674,8 @@ def main():
                     help="skip the FMA and HBM-copy peak probes")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the untimed mixed-vs-FP64 accuracy passes")
+    ap.add_argument("--only-probes", action="store_true",
+                    help="the peak probes and the VALU/MFMA comparison alone (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device-to-device copy (a reference kernel "
                          "of known traffic for hardware byte counters)")
@@ -685,7 +687,7 @@ def main():
 
     # the CPU oracle first, before anything touches the GPU
     baseline = None
-    if not args.no_cpu_baseline and not args.only_ensemble:
+    if not args.no_cpu_baseline and not args.only_ensemble and not args.only_probes:
         log("cpu baseline (oracle, all cores)")
         baseline = cpu_baseline()
         log("cpu baseline", baseline)
@@ -706,7 +708,13 @@ def main():
         probes = {"fp32_fma_tflops": ader.ader_probe_peak(ader.ADER_PROBE_FP32_FMA),
                   "fp64_fma_tflops": ader.ader_probe_peak(ader.ADER_PROBE_FP64_FMA),
                   "hbm_copy_gbs": ader.ader_probe_peak(ader.ADER_PROBE_HBM_COPY)}
+        # VALU against MFMA on the predictor's side-point evaluation (FP32)
+        probes["face_eval_valu_vs_mfma"] = {
+            "order%d" % o: ader.ader_probe_face_eval(o) for o in (3, 4)}
         log("probes", probes)
+        if args.only_probes:
+            print(json.dumps({"peak_probes": probes}))
+            return
 
     if args.copy_calibration:
         nbytes = 256 << 20

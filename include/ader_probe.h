@@ -24,6 +24,24 @@ extern "C" {
 enum { ADER_PROBE_FP32_FMA = 0, ADER_PROBE_FP64_FMA = 1, ADER_PROBE_HBM_COPY = 2 };
 int ader_probe_peak(int device, int kind, double* value_out);
 
+/* VALU against MFMA on one contraction of the predictor: the values of the
+ * space-time polynomial at the side points of the face quadrature (App. D:
+ * per side the barycentre and the face-average nodes; order 3: 42 points
+ * from 15 modes, 390 nonzero entries; order 4: 78 points from 35 modes,
+ * 1584 nonzero entries), for 4 Mi zones x 5 variables in FP32, each zone's
+ * point values reduced to the sum of their squares.  The VALU kernel takes
+ * one lane per zone with the nonzero entries as immediate operands (the
+ * form of the predictor kernels); the MFMA kernel takes 32 zones per wave
+ * through v_mfma_f32_32x32x2f32 with the matrix zero-padded to 32-point
+ * tiles and an even mode count.  out[6] receives: the useful rate (2 x
+ * nonzero entries per zone and variable) of the VALU and of the MFMA
+ * kernel in TFLOP/s, their launch times in ms (best of 5), the MFMA
+ * kernel's dense (padded) rate in TFLOP/s, and the largest relative
+ * difference between the two kernels' per-zone results.  Allocates about
+ * 0.6 GB (order 4) for its duration (ADER_ENOMEM if it cannot); ADER_EINVAL
+ * for an order other than 3 or 4, a device out of range or a null out. */
+int ader_probe_face_eval(int device, int order, double* out);
+
 #ifdef __cplusplus
 }
 #endif

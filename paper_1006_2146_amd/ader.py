@@ -324,6 +324,9 @@ def load_probe():
         _probe.ader_probe_peak.argtypes = [ctypes.c_int, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_double)]
         _probe.ader_probe_peak.restype = ctypes.c_int
+        _probe.ader_probe_face_eval.argtypes = [ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_double)]
+        _probe.ader_probe_face_eval.restype = ctypes.c_int
     return _probe
 
 
@@ -333,6 +336,16 @@ def ader_probe_peak(kind, device=0):
     v = ctypes.c_double()
     _check(load_probe().ader_probe_peak(device, kind, ctypes.byref(v)), "ader_probe_peak")
     return v.value
+
+
+def ader_probe_face_eval(order, device=0):
+    """VALU against MFMA on the side-point evaluation of order 3 or 4
+    (include/ader_probe.h)."""
+    out = (ctypes.c_double * 6)()
+    _check(load_probe().ader_probe_face_eval(device, order, out), "ader_probe_face_eval")
+    keys = ("valu_useful_tflops", "mfma_useful_tflops", "valu_ms", "mfma_ms",
+            "mfma_dense_tflops", "max_rel_diff")
+    return dict(zip(keys, out))
 
 
 def ader_destroy(ctx):

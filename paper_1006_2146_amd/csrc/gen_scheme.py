@@ -1230,6 +1230,51 @@ def gen_weno():
     return out
 
 
+def face_point_rows(order):
+    """Basis values of the space-time modes at the side points the face
+    quadrature evaluates (App. D): per side the barycentre and the
+    face-average nodes, the six sides in the order of SIDES."""
+    fav = face_average_weights(order)
+    fn = face_nodes(order)
+    rows = []
+    for d, s in SIDES:
+        rows.append(point_row(order, side_point(d, s, 0, 0, HALF)))
+        for j in sorted(fav):
+            t1, t2, tau = fn[j - 1]
+            rows.append(point_row(order, side_point(d, s, t1, t2, tau)))
+    return rows
+
+
+def _flit(c):
+    """FP32 literal of a rational."""
+    t = "%.9g" % float(c)
+    return t + ("f" if ("." in t or "e" in t) else ".0f")
+
+
+def gen_face_rows():
+    """generated/face_rows.h: the side-point evaluation matrices of orders 3
+    and 4 as FP32 tables, the operand of the measurement library's VALU
+    against MFMA comparison of that contraction."""
+    out = ["// GENERATED by gen_scheme.py -- do not edit by hand.",
+           "// Side-point evaluation of the space-time polynomial (App. D): row p holds",
+           "// the basis values of the space-time modes at side point p (per side the",
+           "// barycentre, then the face-average nodes; sides -x, +x, -y, +y, -z, +z).",
+           "#pragma once",
+           "namespace ader_gen {"]
+    for order in (3, 4):
+        rows = face_point_rows(order)
+        P, K = len(rows), len(rows[0])
+        nnz = sum(1 for r in rows for c in r if c != 0)
+        out.append("constexpr int kFaceP%d = %d, kFaceK%d = %d, kFaceNnz%d = %d;"
+                   % (order, P, order, K, order, nnz))
+        out.append("constexpr float kFaceRows%d[%d][%d] = {" % (order, P, K))
+        for r in rows:
+            out.append("    {" + ", ".join(_flit(c) for c in r) + "},")
+        out.append("};")
+    out.append("}  // namespace ader_gen")
+    return out
+
+
 def main():
     here = os.path.dirname(os.path.abspath(__file__))
     lines = [
@@ -1258,6 +1303,8 @@ def main():
     os.makedirs(os.path.join(here, "generated"), exist_ok=True)
     with open(os.path.join(here, "generated", "ader_scheme.h"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(here, "generated", "face_rows.h"), "w") as fh:
+        fh.write("\n".join(gen_face_rows()) + "\n")
     counts = {}
     for (tag, part), n in sorted(COUNT.items()):
         counts.setdefault(tag, {})[part] = n

@@ -63,6 +63,10 @@ def test_probe_library_apart_from_the_step_abi(lib):
     v = ctypes.c_double()
     assert probe.ader_probe_peak(0, 3, ctypes.byref(v)) == ader.ADER_EINVAL
     assert probe.ader_probe_peak(0, 0, None) == ader.ADER_EINVAL
+    assert not hasattr(lib, "ader_probe_face_eval")
+    out = (ctypes.c_double * 6)()
+    assert probe.ader_probe_face_eval(0, 2, out) == ader.ADER_EINVAL
+    assert probe.ader_probe_face_eval(0, 3, None) == ader.ADER_EINVAL
 
 
 def test_product_path_has_no_oracle_dependency():
