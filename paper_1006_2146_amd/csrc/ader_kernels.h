@@ -568,6 +568,7 @@ __global__ void __launch_bounds__(kFuTX * kFuTY) k_flux_update(
       }
       __syncthreads();
       if (in) {
+#pragma clang fp contract(on)   // as update_zone: equal bits
         // eq. (6) in update_zone's order: per variable x, then y, then z
         const long long n = zone_of(i, j, k, g);
 #pragma unroll

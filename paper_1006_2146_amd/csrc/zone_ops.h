@@ -903,11 +903,41 @@ __host__ __device__ __forceinline__ void rk_stage_zone(double* __restrict__ U,
 // Riemann fluxes at the faces (Sec. II.3, V): wave structure frozen at the
 // two barycentre states.
 // ---------------------------------------------------------------------------
+// The face solvers contract multiply-adds within each expression only
+// (fp contract on): their rounding then does not depend on the code a kernel
+// inlines them into (which products it shares with other faces), so the
+// fused face-flux+update kernel and the two-kernel path give equal bits.
+//
+// Euler pressure and physical flux along AXIS, as Euler<T>::pressure and
+// Euler<T>::flux, for the face solvers.
+template <class T>
+__host__ __device__ __forceinline__ T face_pressure(const T (&u)[5], T gam) {
+#pragma clang fp contract(on)
+  return (gam - T(1)) * (u[4] - T(0.5) * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0]);
+}
+
+template <int AXIS>
+__host__ __device__ __forceinline__ void face_average_flux(const double (&u)[5], double (&f)[5],
+                                                           double gam) {
+#pragma clang fp contract(on)
+  const double rinv = 1.0 / u[0];
+  const double vn = u[1 + AXIS] * rinv;
+  const double ke = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * rinv;
+  const double p = (gam - 1.0) * (u[4] - ke);
+  f[0] = u[1 + AXIS];
+  f[1] = u[1] * vn;
+  f[2] = u[2] * vn;
+  f[3] = u[3] * vn;
+  f[1 + AXIS] += p;
+  f[4] = (u[4] + p) * vn;
+}
+
 // HLL combination (eq. 17 / 56) with signal speeds lam_l <= 0 <= lam_r.
 template <class T, int NV>
 __host__ __device__ __forceinline__ void hll_combine(T lam_l, T lam_r, const T (&ul)[NV],
                                                      const T (&fl)[NV], const T (&ur)[NV],
                                                      const T (&fr)[NV], T (&out)[NV]) {
+#pragma clang fp contract(on)
   const T inv = T(1) / (lam_r - lam_l);
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -920,11 +950,12 @@ template <class T, int AXIS>
 __host__ __device__ __forceinline__ void linearized_flux(const T (&ubl)[5], const T (&ul)[5], const T (&fl)[5],
                                                 const T (&ubr)[5], const T (&ur)[5], const T (&fr)[5],
                                                 T gam, T (&out)[5]) {
+#pragma clang fp contract(on)
   constexpr int A = 1 + AXIS;
   constexpr int B = AXIS == 0 ? 2 : 1;
   constexpr int C = AXIS == 2 ? 2 : 3;
   const T rl = ubl[0], rr = ubr[0];
-  const T pl = Euler<T>::pressure(ubl, gam), pr = Euler<T>::pressure(ubr, gam);
+  const T pl = face_pressure(ubl, gam), pr = face_pressure(ubr, gam);
   const T rho = T(0.5) * (rl + rr);
   const T vn = T(0.5) * (ubl[A] / rl + ubr[A] / rr);
   const T va = T(0.5) * (ubl[B] / rl + ubr[B] / rr);
@@ -969,6 +1000,7 @@ __host__ __device__ __forceinline__ void face_flux_values(const double* __restri
                                                           const Grid& g, long long n,
                                                           long long nl, double gam,
                                                           double (&res)[5]) {
+#pragma clang fp contract(on)
   T ubl[5], ul[5], fl[5], ubr[5], ur[5], fr[5], out[5];
   double wl[5], wr[5];
   constexpr int SL = 2 * AXIS + 1, SR = 2 * AXIS;  // top side of the lower zone, bottom side of this
@@ -1008,15 +1040,15 @@ __host__ __device__ __forceinline__ void face_flux_values(const double* __restri
     // signal speeds of the barycentre states
     const T il = recip(ubl[0]), ir = recip(ubr[0]);
     const T vl = ubl[1 + AXIS] * il, vr = ubr[1 + AXIS] * ir;
-    const T cl = fsqrt(tg * Euler<T>::pressure(ubl, tg) * il);
-    const T cr = fsqrt(tg * Euler<T>::pressure(ubr, tg) * ir);
+    const T cl = fsqrt(tg * face_pressure(ubl, tg) * il);
+    const T cr = fsqrt(tg * face_pressure(ubr, tg) * ir);
     const T lam_l = fmin(fmin(vl - cl, vr - cr), T(0));
     const T lam_r = fmax(fmax(vl + cl, vr + cr), T(0));
     hll_combine<T, 5>(lam_l, lam_r, ul, fl, ur, fr, out);
     if constexpr (DEV) {
       double Fl[5], Fr[5];
-      Euler<double>::template flux<AXIS>(wl, Fl, gam);
-      Euler<double>::template flux<AXIS>(wr, Fr, gam);
+      face_average_flux<AXIS>(wl, Fl, gam);
+      face_average_flux<AXIS>(wr, Fr, gam);
       const double ll = lam_l, lr = lam_r, inv = 1.0 / (lr - ll);
 #pragma unroll
       for (int v = 0; v < 5; ++v) res[v] = (lr * Fl[v] - ll * Fr[v]) * inv + double(out[v]);
@@ -1026,8 +1058,8 @@ __host__ __device__ __forceinline__ void face_flux_values(const double* __restri
     linearized_flux<T, AXIS>(ubl, ul, fl, ubr, ur, fr, tg, out);
     if constexpr (DEV) {
       double Fl[5], Fr[5];
-      Euler<double>::template flux<AXIS>(wl, Fl, gam);
-      Euler<double>::template flux<AXIS>(wr, Fr, gam);
+      face_average_flux<AXIS>(wl, Fl, gam);
+      face_average_flux<AXIS>(wr, Fr, gam);
 #pragma unroll
       for (int v = 0; v < 5; ++v) res[v] = 0.5 * (Fl[v] + Fr[v]) + double(out[v]);
       return;
@@ -1154,6 +1186,7 @@ __host__ __device__ __forceinline__ void face_flux_adv_zone(const T* __restrict_
 __host__ __device__ __forceinline__ void update_zone(double* __restrict__ U, const double* __restrict__ F,
                                                      const Grid& g, double h, double dx,
                                                      double dy, double dz, long long n) {
+#pragma clang fp contract(on)   // as the fused kernel's update: equal bits
   int i, j, k;
   zone_ijk(g, n, i, j, k);
   const long long up[3] = {zone_of(wrap(i + 1, g.nx), j, k, g), zone_of(i, wrap(j + 1, g.ny), k, g),
