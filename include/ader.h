@@ -326,7 +326,8 @@ int ader_set_launch(ader_ctx* ctx, const int* block, const int* blocks_per_cu);
 
 /* Layout of the predictor kernel (Sec. IV and App. D work of a zone):
  * ADER_LAYOUT_ZONE, one lane per zone holding all variables (not built for
- * Euler at order 4: ADER_EUNSUPPORTED there), or
+ * Euler in FP64 at order 4: ADER_EUNSUPPORTED there, the lane-split layout
+ * runs), or
  * ADER_LAYOUT_SPLIT, one lane per (zone, variable) gathering the zone's
  * state across lanes at each flux evaluation (orders 3 and 4 only,
  * ADER_EUNSUPPORTED at order 2), ADER_LAYOUT_SPLIT2, the same compiled to

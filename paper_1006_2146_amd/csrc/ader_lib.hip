@@ -1117,8 +1117,9 @@ int ader_set_layout(ader_ctx* c, int layout) {
     return ADER_EUNSUPPORTED;
   if (layout == ADER_LAYOUT_FUSED && (c->order != 3 || c->system != ADER_EULER))
     return ADER_EUNSUPPORTED;
-  // Euler at order 4 runs the lane-split predictor only
-  if (layout == ADER_LAYOUT_ZONE && c->order == 4 && c->system == ADER_EULER)
+  // Euler in FP64 at order 4 runs the lane-split predictor only
+  if (layout == ADER_LAYOUT_ZONE && c->order == 4 && c->system == ADER_EULER &&
+      c->precision == ADER_FP64)
     return ADER_EUNSUPPORTED;
   c->layout = layout;
   return ADER_OK;

@@ -310,13 +310,14 @@ constexpr int (*only_if())(ader_ctx*) {
 // the one-lane-per-zone instances with a separate facial pass, and with two
 // waves per SIMD (Euler), are built where the zone layout is the likely
 // winner (orders 2 and 3).  The Euler one-lane-per-zone predictor is not
-// built at order 4: it spills about 2-3.5 KB per lane there, and a run of
-// its FP64 instance on a batch of five ragged meshes did not finish within
-// two minutes, with no cause found in the source; the lane-split layout,
-// the default and the faster one at that order, runs instead.
+// built in FP64 at order 4: it spills about 2.1 KB per lane there, and a
+// run of it on a batch of five ragged meshes did not finish within two
+// minutes, with no cause found in the source (its host build finishes the
+// same steps); the lane-split layout runs instead.
 // linear advection builds only the one-lane-per-zone predictor
+constexpr bool kZoneBuilt = !(kOrder == 4 && !kMhd && !kLinadv && sizeof(T) == 8);
 const StageFns kStages = {recon,
-                          only_if<!(kOrder == 4 && !kMhd && !kLinadv), predict<true>>(),
+                          only_if<kZoneBuilt, predict<true>>(),
                           (kOrder >= 3 && !kLinadv) ? predict_split<1> : nullptr,
                           (kOrder >= 3 && !kLinadv) ? predict_split<2> : nullptr,
                           only_if<kOrder <= 3 && !kLinadv, predict<false>>(),

@@ -50,9 +50,8 @@ def _advance(s, T, cfl=0.3):
 def test_mixed_step_close_to_oracle(order, form, rs, layout):
     if order == 2 and layout in (ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT2):
         pytest.skip("the lane-split layout is built for orders 3 and 4")
-    if order == 4 and layout in (ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_ZONE2,
-                                 ader.ADER_LAYOUT_ZONE_2W):
-        pytest.skip("the Euler one-lane-per-zone instances are built for orders 2 and 3")
+    if order == 4 and layout in (ader.ADER_LAYOUT_ZONE2, ader.ADER_LAYOUT_ZONE_2W):
+        pytest.skip("these one-lane-per-zone instances are built for orders 2 and 3")
     U = workloads.random_smooth((9, 14, 21), seed=order)
     cfg = OracleConfig(order=order, form=form, riemann=rs)
     with _euler(U.shape[1:], order, rs, form=ader.ADER_NODAL if form == "nodal" else ader.ADER_MODAL) as s:

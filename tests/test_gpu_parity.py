@@ -367,9 +367,9 @@ LAYOUTS = [ader.ADER_LAYOUT_ZONE, ader.ADER_LAYOUT_SPLIT, ader.ADER_LAYOUT_SPLIT
 
 def _skip_unbuilt(layout, order, mhd=False):
     if layout == ader.ADER_LAYOUT_ZONE and order == 4 and not mhd:
-        pytest.skip("the Euler one-lane-per-zone predictor is not built at order 4 (a run of "
-                    "its FP64 instance did not finish, cause not found); the lane-split "
-                    "layout runs there")
+        pytest.skip("the Euler one-lane-per-zone predictor is not built in FP64 at order 4 (a "
+                    "run of it did not finish, cause not found); the lane-split layout runs "
+                    "there")
     if layout == ader.ADER_LAYOUT_FUSED and (order != 3 or mhd):
         pytest.skip("the fused reconstruction+predictor is built for Euler at order 3")
     if layout == ader.ADER_LAYOUT_ZONE2 and order > 3:
