@@ -674,6 +674,9 @@ def main():
                     help="skip the FMA and HBM-copy peak probes")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the untimed mixed-vs-FP64 accuracy passes")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the headline ensemble and print the other runs' JSON only "
+                         "(for profiling the 128^3 workloads)")
     ap.add_argument("--only-probes", action="store_true",
                     help="the peak probes and the VALU/MFMA comparison alone (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -725,11 +728,11 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 copies of %d bytes" % nbytes)
 
-    log("batched ensemble (headline)")
-    ensemble = run_ensemble(ader, torch, args.steps, args.warmup,
-                            sample=not args.no_accuracy and not args.only_ensemble)
-    head = ensemble["mixed"]
-    zones = ensemble["zones"]
+    ensemble = None
+    if not args.no_ensemble:
+        log("batched ensemble (headline)")
+        ensemble = run_ensemble(ader, torch, args.steps, args.warmup,
+                                sample=not args.no_accuracy and not args.only_ensemble)
 
     variants, mhd_variants = {}, {}
     small = roundtrip = schemes = turbulent = None
@@ -792,6 +795,13 @@ def main():
             del Um, Bm
             turbulent = run_turbulent(ader, torch, args.turbulent_steps, 1)
 
+    if ensemble is None:
+        TUNE.write()
+        print(json.dumps({"sedov_variants": variants, "mhd_variants": mhd_variants,
+                          "density_wave_32": small}))
+        return
+    head = ensemble["mixed"]
+    zones = ensemble["zones"]
     roofline = roofline_of(head, zones, "f32")
     if probes:
         roofline["peak_measured"] = probes["fp32_fma_tflops"]
