@@ -43,7 +43,7 @@ def _layouts(order, prec):
 
 
 def _run(order, form, prec, rs, mode, layout, nsteps=3, shapes=SHAPES, boundary=None,
-         graph=False):
+         graph=False, recon=None):
     states = [workloads.random_smooth(sh, seed=40 + q) for q, sh in enumerate(shapes)]
     import torch
     stream = torch.cuda.Stream() if graph else None
@@ -51,6 +51,8 @@ def _run(order, form, prec, rs, mode, layout, nsteps=3, shapes=SHAPES, boundary=
                           riemann=RS[rs], boundary=boundary,
                           stream=stream.cuda_stream if graph else None) as b:
         ader.ader_set_layout(b.ctx, layout)
+        if recon is not None:
+            ader.ader_set_recon(b.ctx, recon)
         ader.ader_set_flux_mode(b.ctx, mode)
         assert ader.ader_get_flux_mode(b.ctx) == mode
         if graph:
@@ -74,6 +76,19 @@ def test_fused_equals_two_kernels_bitwise(order, form, prec, rs):
         for q in range(len(SHAPES)):
             assert np.array_equal(sep[q], fus[q]), (layout, q,
                                                     np.abs(sep[q] - fus[q]).max())
+
+
+@pytest.mark.parametrize("order", [3, 4])
+def test_fused_with_the_marching_reconstruction(order):
+    # every reconstruction mode gives the same bits in both flux modes
+    for prec in ("mixed", "fp64"):
+        for recon in (ader.ADER_RECON_SWEEPS, ader.ADER_RECON_MARCH, ader.ADER_RECON_COLUMNS):
+            for layout in _layouts(order, prec):
+                say("flux+update recon", order, prec, recon, "layout", layout)
+                sep = _run(order, "modal", prec, "hll", ader.ADER_FLUX_SEPARATE, layout, recon=recon)
+                fus = _run(order, "modal", prec, "hll", ader.ADER_FLUX_FUSED, layout, recon=recon)
+                for q in range(len(SHAPES)):
+                    assert np.array_equal(sep[q], fus[q]), (recon, layout, q)
 
 
 def test_fused_with_walls_and_outflow():
