@@ -483,3 +483,52 @@ def magnetized_vortex(n, t=0.0, length=10.0, kappa=1.0, mu=1.0, gamma=5.0 / 3.0,
     B[0, 0] = (np.roll(Az, -1, axis=0) - Az) / h       # B_x = dA_z/dy on x-faces
     B[1, 0] = -(np.roll(Az, -1, axis=1) - Az) / h      # B_y = -dA_z/dx on y-faces
     return U, B
+
+
+def field_loop(nx, ny, a0=1e-3, radius=0.3, v=(2.0, 1.0), rho=1.0, p=1.0, gamma=5.0 / 3.0):
+    """A weak magnetic field loop advected by a uniform flow across the
+    periodic box [-1, 1] x [-1/2, 1/2] on nx x ny zones with one zone in z
+    (the field-loop test of Sec. VIII, set up after its cited reference):
+    A_z = a0 (radius - r) inside r < radius, zero outside, so |B| = a0 in
+    the loop; rho, P uniform; v = (2, 1) brings the loop back to its start
+    at t = 1.  Face fields are the differences of A_z at the face's corners
+    divided by the edge length (discrete div B zero); U of shape
+    (5, 1, ny, nx), B of shape (3, 1, ny, nx)."""
+    hx, hy = 2.0 / nx, 1.0 / ny
+    x = -1.0 + np.arange(nx) * hx
+    y = -0.5 + np.arange(ny) * hy
+    r = np.sqrt(x[None, :] ** 2 + y[:, None] ** 2)
+    Az = np.where(r < radius, a0 * (radius - r), 0.0)    # [j][i] at corner (x_i, y_j)
+    B = np.zeros((3, 1, ny, nx))
+    B[0, 0] = (np.roll(Az, -1, axis=0) - Az) / hy       # B_x = dA_z/dy on x-faces
+    B[1, 0] = -(np.roll(Az, -1, axis=1) - Az) / hx      # B_y = -dA_z/dx on y-faces
+    shape = (1, ny, nx)
+    vel = np.stack([np.full(shape, v[0]), np.full(shape, v[1]), np.zeros(shape)])
+    U = _mhd_conserved(np.full(shape, rho), vel, np.full(shape, p), face_mean(B), gamma)
+    return U, B
+
+
+def mhd_rotor(n, b0=5.0, rho_in=10.0, rho_out=1.0, r0=0.1, r1=0.115, omega=20.0, p=1.0,
+              gamma=1.4):
+    """The rotor (Sec. VIII) on the periodic unit square, n x n zones and
+    one in z: a dense disk (r < r0) spinning at omega about the centre in a
+    light medium at rest, with a linear taper of density and angular speed
+    over r0 < r < r1, in the uniform field B = (b0, 0, 0) (b0 = 5 in the
+    Gaussian units of the step, i.e. 5 / sqrt(4 pi) in Heaviside units, as
+    in the usual setup), P = 1.  Point values at the zone centres; U of
+    shape (5, 1, n, n), B of shape (3, 1, n, n)."""
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h - 0.5
+    X, Y = np.meshgrid(c, c)                  # [j][i]
+    r = np.sqrt(X * X + Y * Y)
+    f = np.clip((r1 - r) / (r1 - r0), 0.0, 1.0)
+    dens = rho_out + (rho_in - rho_out) * f
+    # angular speed: omega inside r0, tapered to zero at r1, zero outside
+    w = omega * np.where(r < r0, 1.0, f * r0 / np.maximum(r, 1e-300))
+    vx, vy = -w * Y, w * X
+    shape = (1, n, n)
+    B = np.zeros((3, 1, n, n))
+    B[0] = b0
+    vel = np.stack([vx.reshape(shape), vy.reshape(shape), np.zeros(shape)])
+    U = _mhd_conserved(dens.reshape(shape), vel, np.full(shape, p), face_mean(B), gamma)
+    return U, B
