@@ -144,22 +144,35 @@ int ader_set_source(ader_ctx* ctx, const double* A, const double* b);
 
 /* Non-periodic faces (Euler; every problem of the context): bc[6] gives the
  * kinds of the faces x-, x+, y-, y+, z-, z+: ADER_BC_PERIODIC (the default;
- * both faces of an axis or neither), ADER_BC_OUTFLOW (zero gradient) or
- * ADER_BC_REFLECT (a wall).  The paper describes no boundary treatment; the
+ * both faces of an axis or neither), ADER_BC_OUTFLOW (zero gradient),
+ * ADER_BC_REFLECT (a wall) or ADER_BC_INFLOW (a given state, set with
+ * ader_set_inflow).  The paper describes no boundary treatment; the
  * reading here is the usual one of ghost zones: each bounded face gets four
  * layers of zones outside the problem, filled before every step (and every
  * dt rule) from the interior zone averages -- outflow the nearest interior
  * zone, reflect the mirror-image zone with the normal momentum negated --
- * and the periodic step then runs on the padded mesh, whose periodic wrap
- * reaches no interior result.  Zones two or more layers out reach no
+ * or with the inflow state, and the periodic step then runs on the padded
+ * mesh, whose periodic wrap reaches no interior result.  The axes compose
+ * in the order x, y, z: a zone outside the faces of several axes takes the
+ * rule of the last of them applied to the earlier axes' ghost values (the
+ * inflow state of the last inflow face among them, with the momentum signs
+ * of the reflecting faces after it).  The CFL rule covers the ghost zones
+ * too, so an inflow state's signal speeds enter dt.  Zones two or more layers out reach no
  * interior face: their positivity outcomes are neither reported nor
  * counted.  The caller's arrays keep the interior layout; device memory
  * grows by the ghost layers.  Must come before the first state is set
  * (ADER_ESEQ after, or on a context with a bound device state); a bounded
  * axis needs at least 4 zones (ADER_EINVAL); ADER_EUNSUPPORTED for MHD and
  * linear advection, and at the step for the SSP-RK scheme. */
-enum { ADER_BC_PERIODIC = 0, ADER_BC_OUTFLOW = 1, ADER_BC_REFLECT = 2 };
+enum { ADER_BC_PERIODIC = 0, ADER_BC_OUTFLOW = 1, ADER_BC_REFLECT = 2, ADER_BC_INFLOW = 3 };
 int ader_set_boundary(ader_ctx* ctx, const int* bc);
+
+/* The state of inflow face `face` (0..5: x-, x+, y-, y+, z-, z+; every
+ * problem of the context): state[5] conserved (rho, m_x, m_y, m_z, E), with
+ * rho > 0, P > 0 and finite values (ADER_EINVAL otherwise).  May be set or
+ * changed at any time (a captured step is captured again); a step on a
+ * context with an inflow face whose state was never set returns ADER_ESEQ. */
+int ader_set_inflow(ader_ctx* ctx, int face, const double* state);
 
 /* Velocity a of an ADER_LINADV context (ADER_EUNSUPPORTED for the other
  * systems; ADER_EINVAL for a non-finite component or a = 0). */

@@ -8,8 +8,14 @@ interior zone averages:
   interior zone along the axis;
 * reflect (wall): a ghost zone takes the mirror-image zone's average with
   the momentum component normal to the wall negated;
+* inflow: a ghost zone takes a given state (the face's inflow state).
 
-and the periodic step of ``oracle.step`` then runs on the padded mesh;
+The axes are padded in the order x, y, z, each from the array the previous
+ones padded, so a zone outside two bounded faces (a corner) takes the later
+axis's rule applied to the earlier axis's ghost values (an inflow ghost row
+of y holds the inflow state across the x ghosts too; a reflect ghost row of
+y mirrors the x ghosts, inflow states included).  The periodic step of
+``oracle.step`` then runs on the padded mesh;
 the interior results are the bounded step (with GHOST >= the order, no
 interior result depends on the padded mesh's periodic wrap).  In the check
 mode only the interior and the first ghost layer -- the zones whose
@@ -25,7 +31,7 @@ import numpy as np
 from .step import compute_dt, step
 
 GHOST = 4
-KINDS = ('periodic', 'outflow', 'reflect')
+KINDS = ('periodic', 'outflow', 'reflect', 'inflow')
 
 
 def _source_index(n, lo, hi, g):
@@ -36,12 +42,12 @@ def _source_index(n, lo, hi, g):
     hi_pad = g if hi != 'periodic' else 0
     for p in range(-lo_pad, n + hi_pad):
         if p < 0:
-            if lo == 'outflow':
+            if lo in ('outflow', 'inflow'):     # inflow: overwritten by the caller
                 idx.append(0); sgn.append(1.0)
             else:
                 idx.append(-1 - p); sgn.append(-1.0)
         elif p >= n:
-            if hi == 'outflow':
+            if hi in ('outflow', 'inflow'):
                 idx.append(n - 1); sgn.append(1.0)
             else:
                 idx.append(2 * n - 1 - p); sgn.append(-1.0)
@@ -59,11 +65,17 @@ def _check_kinds(bc):
             raise ValueError('a periodic axis is periodic on both faces')
 
 
-def pad(U, bc, g=GHOST):
+def pad(U, bc, g=GHOST, inflow=None):
     """U padded with ghost zones on the bounded faces; bc[axis] = (lower,
-    upper) kinds for axis 0 (x), 1 (y), 2 (z).  Returns (padded U, offsets
-    (x, y, z) of the interior in the padded mesh)."""
+    upper) kinds for axis 0 (x), 1 (y), 2 (z); inflow[(axis, side)] (side 0
+    lower, 1 upper) the conserved state of each inflow face.  Returns
+    (padded U, offsets (x, y, z) of the interior in the padded mesh)."""
     _check_kinds(bc)
+    inflow = inflow or {}
+    for axis in range(3):
+        for side in range(2):
+            if bc[axis][side] == 'inflow' and (axis, side) not in inflow:
+                raise ValueError('inflow face (%d, %d) without a state' % (axis, side))
     nz, ny, nx = U.shape[1:]
     out = U
     offs = []
@@ -77,6 +89,11 @@ def pad(U, bc, g=GHOST):
         shape[3 - axis] = len(sgn)
         out = out.copy()
         out[1 + axis] = out[1 + axis] * sgn.reshape(shape[1:])
+        for side, sl in ((0, slice(0, off)), (1, slice(off + n, None))):
+            if bc[axis][side] == 'inflow':
+                st = [slice(None)] * 4
+                st[3 - axis] = sl
+                out[tuple(st)] = np.asarray(inflow[(axis, side)], dtype=float).reshape(5, 1, 1, 1)
         offs.append(off)
     return out, tuple(offs)
 
@@ -97,10 +114,10 @@ def check_mask(shape, offs, n):
     return m
 
 
-def step_bc(U, dt, cfg, bc):
+def step_bc(U, dt, cfg, bc, inflow=None):
     """One step of the Euler equations with boundaries bc (see pad)."""
     nz, ny, nx = U.shape[1:]
-    Up, offs = pad(U, bc)
+    Up, offs = pad(U, bc, inflow=inflow)
     cfg_p = replace(cfg, zone_size=cfg.spacing(U.shape[1:]),
                     check_mask=check_mask(Up.shape[1:], offs, (nx, ny, nz)))
     Un = step(Up, dt, cfg_p)
@@ -108,7 +125,11 @@ def step_bc(U, dt, cfg, bc):
     return Un[:, oz:oz + nz, oy:oy + ny, ox:ox + nx].copy()
 
 
-def compute_dt_bc(U, cfg, cfl):
-    """dt of the bounded mesh: the ghost zones copy interior states, so the
-    CFL rule over the interior zones."""
-    return compute_dt(U, cfg, cfl)
+def compute_dt_bc(U, cfg, cfl, bc=None, inflow=None):
+    """dt of the bounded mesh: the CFL rule over the zones the step reads,
+    the interior and the ghost zones; outflow and reflect ghosts copy
+    interior states, so only inflow states can add to the interior's."""
+    if not inflow:
+        return compute_dt(U, cfg, cfl)
+    Up, _ = pad(U, bc, inflow=inflow)
+    return compute_dt(Up, replace(cfg, zone_size=cfg.spacing(U.shape[1:])), cfl)

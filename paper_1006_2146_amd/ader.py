@@ -19,7 +19,7 @@ ADER_ESTATE = -5
 ADER_ESEQ = -6
 
 ADER_EULER, ADER_MHD, ADER_LINADV = 0, 1, 2
-ADER_BC_PERIODIC, ADER_BC_OUTFLOW, ADER_BC_REFLECT = 0, 1, 2
+ADER_BC_PERIODIC, ADER_BC_OUTFLOW, ADER_BC_REFLECT, ADER_BC_INFLOW = 0, 1, 2, 3
 ADER_HLL, ADER_LINEARIZED = 0, 1
 ADER_MODAL, ADER_NODAL = 0, 1
 ADER_FP64, ADER_MIXED = 0, 1
@@ -38,6 +38,7 @@ EXPORTS = [
     "ader_set_scheme", "ader_get_scheme",
     "ader_set_positivity", "ader_get_positivity", "ader_limited_zones", "ader_diagnostics",
     "ader_diagnostics_noalloc", "ader_set_source", "ader_set_advection", "ader_set_boundary",
+    "ader_set_inflow",
 ]
 ADER_SCHEME_ADER, ADER_SCHEME_SSPRK = 0, 1
 ADER_POSITIVITY_CHECK, ADER_POSITIVITY_LIMIT = 0, 1
@@ -122,6 +123,7 @@ def load():
         "ader_set_source": ([P, DP, DP], I),
         "ader_set_advection": ([P, D, D, D], I),
         "ader_set_boundary": ([P, ctypes.POINTER(I)], I),
+        "ader_set_inflow": ([P, I, ctypes.POINTER(ctypes.c_double)], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -280,6 +282,13 @@ def ader_set_boundary(ctx, bc):
     first state is set."""
     arr = (ctypes.c_int * 6)(*[int(x) for x in bc])
     _check(load().ader_set_boundary(ctx, arr), "ader_set_boundary")
+
+
+def ader_set_inflow(ctx, face, state):
+    """Conserved state (5 values) of inflow face `face` (0..5: x-, x+, y-,
+    y+, z-, z+)."""
+    arr = np.ascontiguousarray(state, dtype=np.float64).reshape(5)
+    _check(load().ader_set_inflow(ctx, int(face), _dptr(arr)), "ader_set_inflow")
 
 
 def ader_set_advection(ctx, a):

@@ -28,6 +28,12 @@ struct Problem {
 // ghost layers on each non-periodic face (enough for order 4)
 constexpr int kGhost = 4;
 
+// the states of the six faces' inflow (conserved, [face][v]; faces x-, x+,
+// y-, y+, z-, z+), passed to the ghost fill by value
+struct InflowStates {
+  double v[6][5];
+};
+
 // the fused face-flux+update kernel: x-y tiles of kFuTX x kFuTY zones, a
 // work item walks kFuSeg planes of one tile in z
 constexpr int kFuTX = 32, kFuTY = 8, kFuSeg = 16;
@@ -101,6 +107,10 @@ struct ader_ctx {
   // non-periodic faces (ader_set_boundary): some problem has ghost zones;
   // the caller's arrays hold the interiors only, S_user zones in all
   bool bounded = false;
+  // inflow faces' states (ader_set_inflow); bit f of inflow_set: face f given
+  ader::InflowStates inflow{};
+  unsigned inflow_set = 0;
+  unsigned long long inflow_version = 0;   // bumped on every ader_set_inflow
   long long S_user = 0;
   double gamma = 1.4;
   int system = ADER_EULER;

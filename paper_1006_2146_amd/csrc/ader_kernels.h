@@ -15,22 +15,33 @@ namespace ader {
 // Ghost zones of bounded problems (non-periodic faces; ader_set_boundary).
 // A padded index along an axis of g ghost layers before u interior zones
 // maps to the interior zone whose average it takes: outflow the nearest one,
-// reflect the mirror image (sign negated for the normal momentum).
+// reflect the mirror image (sign negated for the normal momentum); on an
+// inflow face it stays and `inflow` is set to the side (0 lower, 1 upper).
 __host__ __device__ __forceinline__ int ghost_source(int i, int g, int u, int lo, int hi,
-                                                     double& sign) {
+                                                     double& sign, int& inflow) {
+  inflow = -1;
   if (g == 0) return i;
   if (i < g) {
     if (lo == ADER_BC_OUTFLOW) return g;
+    if (lo == ADER_BC_INFLOW) {
+      inflow = 0;
+      return i;
+    }
     sign = -sign;
     return 2 * g - 1 - i;
   }
   if (i >= g + u) {
     if (hi == ADER_BC_OUTFLOW) return g + u - 1;
+    if (hi == ADER_BC_INFLOW) {
+      inflow = 1;
+      return i;
+    }
     sign = -sign;
     return 2 * (g + u) - 1 - i;
   }
   return i;
 }
+
 
 // A zone two or more layers outside the interior along a bounded axis: its
 // polynomials reach no interior face (a step updates only the interior;
@@ -98,23 +109,46 @@ __device__ __forceinline__ void for_zones(const Batch& b, Body&& body) {
 }
 
 // Fills the ghost zones of bounded problems from the interior (ghost_source)
+// or with the inflow states.  The axes compose in the order x, y, z: a zone
+// outside the faces of several axes takes the inflow state of the last of
+// them that is an inflow face, with the momentum signs of the reflecting
+// axes after it, else the interior source with every axis's sign.
 template <int = 0>
-__global__ void __launch_bounds__(256) k_fill_ghosts(double* __restrict__ U, Batch b) {
+__global__ void __launch_bounds__(256) k_fill_ghosts(double* __restrict__ U, Batch b,
+                                                     InflowStates in) {
   for_zones(b, [&](const Problem& pr, int, long long n) {
     if (!(pr.gx | pr.gy | pr.gz)) return;
     const Grid g = grid_of(pr, b);
-    int i, j, k;
-    zone_ijk(g, n, i, j, k);
+    int idx[3];
+    zone_ijk(g, n, idx[0], idx[1], idx[2]);
+    const int gw[3] = {pr.gx, pr.gy, pr.gz}, uw[3] = {pr.ux, pr.uy, pr.uz};
     double s[3] = {1.0, 1.0, 1.0};
-    const int si = ghost_source(i, pr.gx, pr.ux, pr.bc[0], pr.bc[1], s[0]);
-    const int sj = ghost_source(j, pr.gy, pr.uy, pr.bc[2], pr.bc[3], s[1]);
-    const int sk = ghost_source(k, pr.gz, pr.uz, pr.bc[4], pr.bc[5], s[2]);
-    if (si == i && sj == j && sk == k) return;   // an interior zone
-    const long long src = zone_of(si, sj, sk, g);
-    U[n] = U[src];
+    int src[3], face = -1;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) U[(long long)(1 + d) * b.S + n] = s[d] * U[(long long)(1 + d) * b.S + src];
-    U[4 * b.S + n] = U[4 * b.S + src];
+    for (int d = 0; d < 3; ++d) {
+      int side;
+      src[d] = ghost_source(idx[d], gw[d], uw[d], pr.bc[2 * d], pr.bc[2 * d + 1], s[d], side);
+      if (side >= 0) {
+        // the inflow state overrides the axes before this one
+        face = 2 * d + side;
+#pragma unroll
+        for (int e = 0; e <= d; ++e) s[e] = 1.0;
+      }
+    }
+    if (face < 0 && src[0] == idx[0] && src[1] == idx[1] && src[2] == idx[2]) return;   // interior
+    double v[5];
+    if (face >= 0) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[q] = in.v[face][q];
+    } else {
+      const long long from = zone_of(src[0], src[1], src[2], g);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) v[q] = U[(long long)q * b.S + from];
+    }
+    U[n] = v[0];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) U[(long long)(1 + d) * b.S + n] = s[d] * v[1 + d];
+    U[4 * b.S + n] = v[4];
   });
 }
 

@@ -75,8 +75,11 @@ struct StageTimer {
 // rule and each step reads them).
 int fill_ghosts(ader_ctx* c) {
   if (!c->bounded) return ADER_OK;
+  // every inflow face needs its state (the faces are the same for all problems)
+  for (int f = 0; f < 6; ++f)
+    if (c->probs[0].bc[f] == ADER_BC_INFLOW && !((c->inflow_set >> f) & 1u)) return ADER_ESEQ;
   k_fill_ghosts<><<<grid_for(c, kClassUpdate), c->shape[kClassUpdate].block, 0, c->stream>>>(
-      c->U, c->batch());
+      c->U, c->batch(), c->inflow);
   return launched();
 }
 
@@ -342,6 +345,7 @@ unsigned long long config_key(const ader_ctx* c) {
   k = k * 3 + (unsigned long long)c->scheme;
   k = k * 3 + (unsigned long long)c->positivity;
   k = k * 1000003 + c->source_version;
+  k = k * 1000003 + c->inflow_version;
   for (int q = 0; q < kNumClasses; ++q) k = k * 1031 + (unsigned long long)c->shape[q].block * 37 +
                                             (unsigned long long)c->shape[q].blocks_per_cu;
   k ^= (unsigned long long)(uintptr_t)c->U * 0x9e3779b97f4a7c15ull;
@@ -1157,7 +1161,8 @@ int ader_set_advection(ader_ctx* c, double ax, double ay, double az) {
 int ader_set_boundary(ader_ctx* c, const int* bc) {
   if (!c || !bc) return ADER_EINVAL;
   for (int f = 0; f < 6; ++f)
-    if (bc[f] != ADER_BC_PERIODIC && bc[f] != ADER_BC_OUTFLOW && bc[f] != ADER_BC_REFLECT)
+    if (bc[f] != ADER_BC_PERIODIC && bc[f] != ADER_BC_OUTFLOW && bc[f] != ADER_BC_REFLECT &&
+        bc[f] != ADER_BC_INFLOW)
       return ADER_EINVAL;
   for (int a = 0; a < 3; ++a)
     if ((bc[2 * a] == ADER_BC_PERIODIC) != (bc[2 * a + 1] == ADER_BC_PERIODIC)) return ADER_EINVAL;
@@ -1222,8 +1227,26 @@ int ader_set_boundary(ader_ctx* c, const int* bc) {
   t->source_version = c->source_version;
   t->bounded = true;
   t->S_user = c->S_user;
+  t->inflow = c->inflow;
+  t->inflow_set = c->inflow_set;
+  t->inflow_version = c->inflow_version;
   std::swap(*c, *t);
   ader_destroy(t);
+  return ADER_OK;
+}
+
+int ader_set_inflow(ader_ctx* c, int face, const double* state) {
+  if (!c || !state || face < 0 || face >= 6) return ADER_EINVAL;
+  if (c->system != ADER_EULER) return ADER_EUNSUPPORTED;
+  for (int v = 0; v < 5; ++v)
+    if (!std::isfinite(state[v])) return ADER_EINVAL;
+  const double r = state[0];
+  const double p = (c->gamma - 1.0) * (state[4] - 0.5 * (state[1] * state[1] + state[2] * state[2] +
+                                                         state[3] * state[3]) / r);
+  if (!(r > 0.0) || !(p > 0.0)) return ADER_EINVAL;
+  for (int v = 0; v < 5; ++v) c->inflow.v[face][v] = state[v];
+  c->inflow_set |= 1u << face;
+  ++c->inflow_version;
   return ADER_OK;
 }
 

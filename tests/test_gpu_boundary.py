@@ -1,6 +1,7 @@
-"""Non-periodic faces on the GPU (ader_set_boundary): ghost zones filled from
-the interior (outflow: nearest zone; reflect: mirror image, normal momentum
-negated) before each step, the periodic kernels on the padded mesh.  FP64
+"""Non-periodic faces on the GPU (ader_set_boundary, ader_set_inflow): ghost
+zones filled from the interior (outflow: nearest zone; reflect: mirror
+image, normal momentum negated) or with a given state (inflow) before each
+step, the periodic kernels on the padded mesh.  FP64
 parity with the oracle's bounded step for mixed face kinds at orders 2-4 in
 both forms; the mirror-extension identity on the device (walls on [0, L]
 equal the periodic step on [0, 2L] of the mirrored data); a blast against
@@ -18,7 +19,8 @@ from paper_1006_2146_amd import ader, workloads
 pytestmark = pytest.mark.gpu
 
 O, W, PP = ader.ADER_BC_OUTFLOW, ader.ADER_BC_REFLECT, ader.ADER_BC_PERIODIC
-NAME = {O: 'outflow', W: 'reflect', PP: 'periodic'}
+IN = ader.ADER_BC_INFLOW
+NAME = {O: 'outflow', W: 'reflect', PP: 'periodic', IN: 'inflow'}
 CASES = [(2, "modal"), (2, "nodal"), (3, "modal"), (3, "nodal"), (4, "modal"), (4, "nodal")]
 FORM = {"modal": ader.ADER_MODAL, "nodal": ader.ADER_NODAL}
 
@@ -209,3 +211,96 @@ def test_sod_shock_tube_against_the_exact_solution(order, form):
         say("sod", order, form, n, errs[-1])
     assert errs[2] < 0.7 * errs[1] < 0.49 * errs[0]
     assert errs[1] < 5e-3   # measured 2.6e-3 to 4.3e-3 (minmod second order the largest)
+
+
+def _state(rho, v, p, gamma=1.4):
+    return np.array([rho, rho * v[0], rho * v[1], rho * v[2],
+                     p / (gamma - 1.0) + 0.5 * rho * np.dot(v, v)])
+
+
+INFLOW_BCS = [(IN, O, W, IN, PP, PP), (IN, IN, PP, PP, O, W), (W, O, O, O, IN, O)]
+
+
+@pytest.mark.parametrize("bc", range(len(INFLOW_BCS)))
+@pytest.mark.parametrize("order,form", [(2, "modal"), (3, "modal"), (3, "nodal"), (4, "modal")])
+def test_inflow_parity_with_the_oracle(order, form, bc):
+    # inflow faces beside outflow and reflecting ones (corners composed in
+    # the order x, y, z), an inflow state faster than the interior (it sets
+    # dt), FP64 parity per step
+    bc = INFLOW_BCS[bc]
+    shape = (6, 7, 9)
+    lengths = (1.0, 0.8, 1.2)
+    U = workloads.random_smooth(shape, seed=order + 11)
+    states = {0: _state(1.1, (2.5, 0.1, 0.0), 1.0), 1: _state(0.9, (-1.0, 0.0, 0.2), 0.8),
+              3: _state(1.2, (0.3, -1.5, 0.1), 1.1), 4: _state(1.0, (0.0, 0.2, 1.0), 0.9)}
+    inflow = {(f // 2, f % 2): st for f, st in states.items() if bc[f] == IN}
+    cfg = OracleConfig(order=order, form=form, lengths=lengths)
+    kinds = _kinds(bc)
+    with ader.Solver(shape, lengths=lengths, order=order, form=FORM[form], boundary=bc) as s:
+        for f in range(6):
+            if bc[f] == IN:
+                ader.ader_set_inflow(s.ctx, f, states[f])
+        s.set_state(U)
+        for it in range(2):
+            say("inflow", bc, order, form, "step", it)
+            dt = s.compute_dt(0.3)
+            assert abs(dt - compute_dt_bc(U, cfg, 0.3, kinds, inflow)) <= 1e-14 * dt
+            s.step(dt)
+            Ug = s.get_state()
+            Uo = step_bc(U, dt, cfg, kinds, inflow)
+            ok, err = close(Ug, Uo)
+            assert ok, (it, err)
+            U = Ug
+
+
+def test_inflow_state_change_under_graph_replay():
+    # a captured step takes up a new inflow state (captured again): graph
+    # replays equal eager steps, before and after the change
+    import torch
+    shape = (6, 6, 10)
+    bc = (IN, O, PP, PP, PP, PP)
+    U0 = workloads.random_smooth(shape, seed=5)
+    a, b = _state(1.0, (1.5, 0.0, 0.0), 1.0), _state(1.3, (2.0, 0.1, 0.0), 1.2)
+    stream = torch.cuda.Stream()
+    res = {}
+    for graph in (False, True):
+        with ader.Solver(shape, boundary=bc, stream=stream.cuda_stream) as s:
+            if graph:
+                ader.ader_set_graph(s.ctx, True)
+            ader.ader_set_inflow(s.ctx, 0, a)
+            s.set_state(U0)
+            for _ in range(3):
+                s.step_cfl(0.3)
+            ader.ader_set_inflow(s.ctx, 0, b)
+            for _ in range(3):
+                s.step_cfl(0.3)
+            s.synchronize()
+            res[graph] = s.get_state()
+    assert np.array_equal(res[False], res[True])
+
+
+def test_inflow_errors():
+    st = _state(1.0, (1.0, 0.0, 0.0), 1.0)
+    with ader.Solver((4, 4, 4), system=ader.ADER_MHD, gamma=5.0 / 3.0) as s:
+        with pytest.raises(ader.AderError) as e:
+            ader.ader_set_inflow(s.ctx, 0, st)
+        assert e.value.code == ader.ADER_EUNSUPPORTED
+    with ader.Solver((4, 4, 6), boundary=(IN, O, PP, PP, PP, PP)) as s:
+        bad_states = (np.array([-1.0, 0, 0, 0, 1.0]), np.array([1.0, 3.0, 0, 0, 1.0]),
+                      np.array([1.0, np.nan, 0, 0, 2.5]))
+        for bad in bad_states:
+            with pytest.raises(ader.AderError) as e:
+                ader.ader_set_inflow(s.ctx, 0, bad)
+            assert e.value.code == ader.ADER_EINVAL
+        for face in (-1, 6):
+            with pytest.raises(ader.AderError) as e:
+                ader.ader_set_inflow(s.ctx, face, st)
+            assert e.value.code == ader.ADER_EINVAL
+        # an inflow face without its state: no step
+        s.set_state(workloads.random_smooth((4, 4, 6), seed=2))
+        with pytest.raises(ader.AderError) as e:
+            s.step(1e-3)
+        assert e.value.code == ader.ADER_ESEQ
+        ader.ader_set_inflow(s.ctx, 0, st)
+        s.step(1e-3)
+        s.synchronize()

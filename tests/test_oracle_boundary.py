@@ -4,13 +4,16 @@ the padded mesh): the ghost fill itself against a brute-force loop; the
 mirror-extension identity (reflecting walls on [0, L] equal the periodic
 step on [0, 2L] of the mirrored data, bit for bit); outflow faces that see
 a constant state change nothing; conservation of mass and energy between
-walls; the check mode ignores ghost zones that reach no interior face."""
+walls; the check mode ignores ghost zones that reach no interior face;
+inflow faces: the fill with its corner rule against a brute-force loop, a
+uniform flow kept by an inflow of its own state, inflow = outflow while
+the boundary zone is unchanged, the inflow state's speed in dt."""
 
 import numpy as np
 import pytest
 
 from oracle import OracleConfig, step
-from oracle.boundary import GHOST, check_mask, pad, step_bc
+from oracle.boundary import GHOST, check_mask, compute_dt_bc, pad, step_bc
 from paper_1006_2146_amd import workloads
 
 P = ('periodic', 'periodic')
@@ -98,3 +101,93 @@ def test_check_mask_keeps_the_first_ghost_layer():
     assert m[:, 3:7, 3:9].all()
     assert not m[:, :, :3].any() and not m[:, :, 9:].any()
     assert not m[:, :3, :].any() and not m[:, 7:, :].any()
+
+
+def test_ghost_fill_with_inflow_by_brute_force():
+    # axes padded x, then y: a corner zone takes y's rule applied to the
+    # x-padded values (the inflow state mirrored by a reflecting y face, or
+    # a y inflow state over the x ghosts)
+    rng = np.random.default_rng(1)
+    U = rng.uniform(0.5, 1.5, size=(5, 5, 6, 7))
+    sx0 = np.array([1.0, 0.5, 0.2, -0.1, 3.0])
+    sy1 = np.array([0.8, -0.3, 0.4, 0.0, 2.5])
+    bc = (('inflow', 'outflow'), ('reflect', 'inflow'), P)
+    Up, offs = pad(U, bc, inflow={(0, 0): sx0, (1, 1): sy1})
+    assert offs == (GHOST, GHOST, 0)
+    nx, ny = 7, 6
+    X = np.zeros((5, 5, ny, nx + 2 * GHOST))
+    for i in range(nx + 2 * GHOST):
+        x = i - GHOST
+        if x < 0:
+            X[:, :, :, i] = sx0[:, None, None]
+        elif x >= nx:
+            X[:, :, :, i] = U[:, :, :, nx - 1]
+        else:
+            X[:, :, :, i] = U[:, :, :, x]
+    for k in range(Up.shape[1]):
+        for j in range(Up.shape[2]):
+            for i in range(Up.shape[3]):
+                y = j - GHOST
+                if y < 0:
+                    ref = X[:, k, -1 - y, i].copy()
+                    ref[2] = -ref[2]
+                elif y >= ny:
+                    ref = sy1
+                else:
+                    ref = X[:, k, y, i]
+                assert np.array_equal(Up[:, k, j, i], ref), (k, j, i)
+
+
+def _uniform(shape, rho, v, p, gamma=1.4):
+    U = np.zeros((5,) + shape)
+    U[0] = rho
+    for d in range(3):
+        U[1 + d] = rho * v[d]
+    U[4] = p / (gamma - 1.0) + 0.5 * rho * np.dot(v, v)
+    return U
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_inflow_of_the_state_itself_keeps_a_uniform_flow(order):
+    # a supersonic uniform flow entering through x- and leaving through x+
+    U = _uniform((4, 5, 8), 1.0, (2.0, 0.3, 0.0), 1.0)
+    cfg = OracleConfig(order=order, form='modal')
+    bc = (('inflow', 'outflow'), ('outflow', 'outflow'), P)
+    Un = step_bc(U, 1e-3, cfg, bc, inflow={(0, 0): U[:, 0, 0, 0]})
+    assert np.abs(Un - U).max() <= 1e-14 * np.abs(U).max()
+
+
+def test_inflow_equals_outflow_while_the_boundary_zone_is_unchanged():
+    # a shock tube along x: while the first interior zone still holds the
+    # left state, an inflow face of that state and an outflow face fill the
+    # same ghost values, so the steps agree bit for bit
+    nx = 32
+    U = np.zeros((5, 4, 4, nx))
+    left = _uniform((4, 4, nx // 2), 1.0, (0.0, 0.0, 0.0), 1.0)
+    right = _uniform((4, 4, nx // 2), 0.125, (0.0, 0.0, 0.0), 0.1)
+    U[..., :nx // 2], U[..., nx // 2:] = left, right
+    cfg = OracleConfig(order=3, form='modal', lengths=(1.0, 0.125, 0.125))
+    a = b = U
+    for _ in range(2):
+        dt = 0.3 * compute_dt_bc(a, cfg, 1.0)
+        a = step_bc(a, dt, cfg, (('outflow', 'outflow'), P, P))
+        b = step_bc(b, dt, cfg, (('inflow', 'outflow'), P, P), inflow={(0, 0): left[:, 0, 0, 0]})
+    assert np.array_equal(a[:, :, :, 0], left[:, :, :, 0])
+    assert np.array_equal(a, b)
+
+
+def test_inflow_speed_enters_the_dt():
+    U = _uniform((4, 4, 8), 1.0, (0.0, 0.0, 0.0), 1.0)
+    cfg = OracleConfig(order=3, form='modal')
+    bc = (('inflow', 'outflow'), P, P)
+    fast = _uniform((1, 1, 1), 1.0, (5.0, 0.0, 0.0), 1.0)[:, 0, 0, 0]
+    dt_in = compute_dt_bc(U, cfg, 0.3, bc, {(0, 0): fast})
+    assert dt_in < compute_dt_bc(U, cfg, 0.3)
+    assert dt_in == pytest.approx(compute_dt_bc(_uniform((4, 4, 8), 1.0, (5.0, 0.0, 0.0), 1.0),
+                                                cfg, 0.3), rel=1e-14)
+
+
+def test_inflow_needs_its_state():
+    U = _uniform((4, 4, 8), 1.0, (0.0, 0.0, 0.0), 1.0)
+    with pytest.raises(ValueError):
+        pad(U, (('inflow', 'outflow'), P, P))
