@@ -1192,6 +1192,32 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
                 _count((tag, 'faces-mhd'), 2)
         out.append("    }")
     out.append("  }")
+    # the same side packet split in two: the linear part (barycentre, face and
+    # edge averages of u) as code, the nodal part (fluxes at the facial nodes)
+    # as tables a loop walks one node at a time
+    out.append("  // facial nodes per side; side_node_w[j]: node j's weight in the face")
+    out.append("  // average of the flux, then in the edge averages q = 0..3 (as ue/fe)")
+    out.append("  static constexpr int NFACE_NODES = %d;" % nf)
+    out.append("  static constexpr double side_node_w[%d][5] = {" % nf)
+    for j in range(1, nf + 1):
+        ws = [fav.get(j, 0)] + [ew[(which, sg)].get(j, 0) for which in (0, 1) for sg in (-1, 1)]
+        out.append("    {%s}," % ", ".join("%.17g" % float(c) for c in ws))
+    out.append("  };")
+    out.append("  template <int SIDE, class Phys>")
+    out.append("  __host__ __device__ static __forceinline__ void side_linear(const T (&w)[LS][NV], const T (&e)[NE][NV],")
+    out.append("      T (&ub)[NV], T (&ua)[NV], T (&ue)[4]) {")
+    out.append("    constexpr bool DEV = Phys::kDeviation;")
+    for si, (d, s_) in enumerate(SIDES):
+        tr = transverse(d)
+        out.append("    %sif constexpr (SIDE == %d) {" % ("" if si == 0 else "else ", si))
+        emit_eval(out, order, side_point(d, s_, 0, 0, HALF), "ub", indent="      ")
+        row = face_average_u_row(order, d, s_)
+        out.append("      for (int v = 0; v < NV; ++v) ua[v] = %s;" % _value(row, ls))
+        for q in range(4):
+            a = tr[q // 2]
+            out.append("      ue[%d] = %s;" % (q, _value(edge_rows[si][q], ls, "Phys::comp(%d)" % (5 + a))))
+        out.append("    }")
+    out.append("  }")
     # every component's edge averages (the linearized solver's edge problems)
     out.append("  // ue[q][v]: edge average (eq. 57) of variable v on edge q of side SIDE")
     out.append("  template <int SIDE, bool DEV>")

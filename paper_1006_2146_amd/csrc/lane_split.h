@@ -446,6 +446,52 @@ __device__ double theta_facial_pair(const SplitLane& L, const double (&w0)[8],
   return acc.result();
 }
 
+// The fluxes of a side packet at the facial nodes (App. D, with the edge
+// averages of eq. 57), in the pair layout, from the scheme's point tables:
+// one node per iteration of a loop the compiler does not unroll, so beside
+// the modes only that node's state and flux are live.  The side kernel of
+// the two-kernel form takes it in FP64 at order 4, where the straight-line
+// form keeps many nodes' partial sums live and spills 2.7 KB per lane (this
+// loop: 0.2 KB; the kernel 19% faster).  In FP32 the straight-line form does
+// not spill and the tables' FP64 coefficients would need a conversion per
+// lane and use, so FP32 keeps it.
+template <class S, int SIDE, class T, class Phys>
+__device__ __forceinline__ void side_node_fluxes(const T (&w)[S::LS][kPairVars],
+                                                 const T (&e)[S::NE][kPairVars], const Phys& ph,
+                                                 T (&fa)[kPairVars], T (&fe)[4]) {
+  constexpr int NF = S::NFACE_NODES, LS = S::LS, NE = S::NE;
+  constexpr int AX = SIDE / 2;
+  constexpr int C0 = Phys::comp(5 + (AX == 0 ? 1 : 0)), C1 = Phys::comp(5 + (AX == 2 ? 1 : 2));
+#pragma unroll
+  for (int k = 0; k < kPairVars; ++k) fa[k] = T(0);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fe[q] = T(0);
+#pragma unroll 1
+  for (int j = 0; j < NF; ++j) {
+    const double* wt = S::side_node_w[j];
+    if (wt[0] == 0.0 && wt[1] == 0.0 && wt[2] == 0.0 && wt[3] == 0.0 && wt[4] == 0.0) continue;
+    const double* phi = S::facial_phi_all[SIDE * (NF + 1) + j];
+    T u[kPairVars], fl[kPairVars];
+#pragma unroll
+    for (int k = 0; k < kPairVars; ++k) u[k] = w[0][k];
+#pragma unroll
+    for (int m = 1; m < LS; ++m)
+#pragma unroll
+      for (int k = 0; k < kPairVars; ++k) u[k] += T(phi[m]) * w[m][k];
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+#pragma unroll
+      for (int k = 0; k < kPairVars; ++k) u[k] += T(phi[LS + m]) * e[m][k];
+    ph.template flux<AX>(u, fl);
+#pragma unroll
+    for (int k = 0; k < kPairVars; ++k) fa[k] += T(wt[0]) * fl[k];
+    fe[0] += T(wt[1]) * fl[C0];
+    fe[1] += T(wt[2]) * fl[C0];
+    fe[2] += T(wt[3]) * fl[C1];
+    fe[3] += T(wt[4]) * fl[C1];
+  }
+}
+
 // The same operations as predict_zone_mhd, in the pair layout.  EDGES_ALL:
 // every variable's edge averages are stored (linearized flux), else only the
 // field component each edge needs.  PHASE 0 does it all; PHASE 1 stops after
@@ -578,8 +624,13 @@ __device__ __forceinline__ void predict_zone_mhd_pair(
     constexpr int AX = SIDE / 2;
     constexpr int TA0 = AX == 0 ? 1 : 0, TA1 = AX == 2 ? 1 : 2;   // transverse axes
     T ub[VPL], ua[VPL], fa[VPL], ue[4], fe[4];
-    NoScan none;
-    S::template side_edges<SIDE>(w, e, ph, none, ub, ua, fa, ue, fe);
+    if constexpr (PHASE == 2 && ORDER == 4 && std::is_same<T, double>::value) {
+      S::template side_linear<SIDE, PairFlux<Mhd<T>, T, DEV>>(w, e, ub, ua, ue);
+      side_node_fluxes<S, SIDE>(w, e, ph, fa, fe);
+    } else {
+      NoScan none;
+      S::template side_edges<SIDE>(w, e, ph, none, ub, ua, fa, ue, fe);
+    }
     T* base = PK + (long long)SIDE * kMhdSlots * g.S + n;
     RowCursor<T> r(base + (long long)v0 * g.S, g.S, 0);
 #pragma unroll
