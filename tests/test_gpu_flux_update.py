@@ -4,7 +4,8 @@ Sec. II / App. D through device memory, then eq. 6) at every order, form,
 precision and Riemann solver, with every Euler predictor layout that keeps
 the zone averages for it, on ragged batches whose meshes are not multiples
 of the kernel's 32 x 8-zone tiles and 16-plane segments (and one-zone
-meshes, where every face wraps onto the same zone); with non-periodic faces;
+meshes, where every face wraps onto the same zone); with non-periodic faces
+(reflecting, outflow, inflow);
 under graph replay; after ader_autotune; FP64 parity with the oracle; the
 fallback to the two kernels with a source term, and the argument checks."""
 
@@ -102,6 +103,30 @@ def test_fused_with_walls_and_outflow():
                  shapes=shapes, boundary=(W, O, O, W, P, P))
         for q in range(len(shapes)):
             assert np.array_equal(a[q], b[q]), (prec, q)
+
+
+def test_fused_with_inflow_faces():
+    # inflow ghost zones (a given state) beside outflow and reflecting ones
+    IN, O, W = ader.ADER_BC_INFLOW, ader.ADER_BC_OUTFLOW, ader.ADER_BC_REFLECT
+    bc = (IN, O, W, IN, O, W)
+    shape = (6, 9, 40)
+    U = workloads.random_smooth(shape, seed=5)
+    states = {0: (1.1, 1.1 * 2.0, 0.11, 0.0, 1.0 / 0.4 + 0.5 * 1.1 * 4.01),
+              3: (1.2, 0.36, -1.8, 0.12, 1.1 / 0.4 + 0.5 * 1.2 * 2.35)}
+    for prec in ("fp64", "mixed"):
+        res = []
+        for mode in (ader.ADER_FLUX_SEPARATE, ader.ADER_FLUX_FUSED):
+            say("flux+update inflow", prec, mode)
+            with ader.Solver(shape, order=3, precision=PREC[prec], boundary=bc) as s:
+                for f, st in states.items():
+                    ader.ader_set_inflow(s.ctx, f, np.array(st))
+                ader.ader_set_flux_mode(s.ctx, mode)
+                assert ader.ader_get_flux_mode(s.ctx) == mode
+                s.set_state(U)
+                for _ in range(3):
+                    s.step_cfl(0.3)
+                res.append(s.get_state())
+        assert np.array_equal(res[0], res[1]), prec
 
 
 def test_fused_graph_replays_equal_eager():
