@@ -222,7 +222,8 @@ INFLOW_BCS = [(IN, O, W, IN, PP, PP), (IN, IN, PP, PP, O, W), (W, O, O, O, IN, O
 
 
 @pytest.mark.parametrize("bc", range(len(INFLOW_BCS)))
-@pytest.mark.parametrize("order,form", [(2, "modal"), (3, "modal"), (3, "nodal"), (4, "modal")])
+@pytest.mark.parametrize("order,form", [(2, "modal"), (2, "nodal"), (3, "modal"), (3, "nodal"),
+                                        (4, "modal"), (4, "nodal")])
 def test_inflow_parity_with_the_oracle(order, form, bc):
     # inflow faces beside outflow and reflecting ones (corners composed in
     # the order x, y, z), an inflow state faster than the interior (it sets
