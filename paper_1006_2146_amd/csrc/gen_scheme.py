@@ -1203,6 +1203,13 @@ def gen_mhd_parts(order, form, tag, nodes, fnodes):
         ws = [fav.get(j, 0)] + [ew[(which, sg)].get(j, 0) for which in (0, 1) for sg in (-1, 1)]
         out.append("    {%s}," % ", ".join("%.17g" % float(c) for c in ws))
     out.append("  };")
+    # edge averages of every variable (the linearized solver's edge states)
+    # as rows over all modes, per side and edge
+    out.append("  static constexpr double edge_rows_all[6][4][%d] = {" % L)
+    for si in range(len(SIDES)):
+        out.append("    {%s}," % ", ".join(
+            "{%s}" % ", ".join("%.17g" % float(c) for c in edge_rows[si][q]) for q in range(4)))
+    out.append("  };")
     out.append("  template <int SIDE, class Phys>")
     out.append("  __host__ __device__ static __forceinline__ void side_linear(const T (&w)[LS][NV], const T (&e)[NE][NV],")
     out.append("      T (&ub)[NV], T (&ua)[NV], T (&ue)[4]) {")
